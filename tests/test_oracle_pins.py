@@ -1,0 +1,368 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values
+derived by hand (tests/golden), closed forms, brute force on tiny inputs,
+independent solvers (scipy Hungarian, networkx network simplex), LP duality
+certificates, invariances and the approximation theorems.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import pdsynth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ------------------------------------------------------------- exact W1 --
+def test_exact_w1_matches_bruteforce(orc):
+    rng = np.random.default_rng(5)
+    for trial in range(40):
+        na, nb = rng.integers(0, 4, 2)
+        A = pdsynth.exp_pd(int(na), 1000 + trial, mean_pers=0.3)
+        B = pdsynth.exp_pd(int(nb), 2000 + trial, mean_pers=0.3)
+        assert orc.exact_w1(A, B) == pytest.approx(orc.brute_w1(A, B), rel=1e-12, abs=1e-12)
+
+
+def test_exact_w1_closed_forms(orc):
+    p = np.array([[0.25, 1.75]])
+    q = np.array([[0.5, 1.5]])
+    assert orc.exact_w1(p, np.zeros((0, 2))) == 0.75  # (d-b)/2
+    # one point each: min(direct, both to the diagonal)
+    assert orc.exact_w1(p, q) == min(0.25, 0.75 + 0.5)
+    far = np.array([[10.0, 10.5]])
+    assert orc.exact_w1(p, far) == 0.75 + 0.25
+    A = pdsynth.exp_pd(30, 3)
+    assert orc.exact_w1(A, A) == 0.0
+    B = pdsynth.exp_pd(25, 4)
+    assert orc.exact_w1(A, B) == pytest.approx(orc.exact_w1(B, A), rel=1e-14)
+
+
+def test_exact_w1_emd_reduction(orc):
+    # Translating equal-size diagrams far from the diagonal makes every point
+    # cheaper to match than to send to the diagonal, so W1 equals the plain
+    # optimal assignment (EMD) of the two point sets (Sec. 6, conditional
+    # lower bound reduction).
+    from scipy.optimize import linear_sum_assignment
+
+    rng = np.random.default_rng(11)
+    for trial in range(5):
+        P = rng.random((12, 2))
+        Q = rng.random((12, 2))
+        M = 100.0
+        A = np.stack([P[:, 0] - M, P[:, 1] + M], 1)
+        B = np.stack([Q[:, 0] - M, Q[:, 1] + M], 1)
+        C = np.maximum(np.abs(P[:, None, 0] - Q[None, :, 0]), np.abs(P[:, None, 1] - Q[None, :, 1]))
+        r, c = linear_sum_assignment(C)
+        assert orc.exact_w1(A, B) == pytest.approx(C[r, c].sum(), rel=1e-12)
+
+
+def test_exact_w1_net_invariance(orc):
+    A = pdsynth.exp_pd(20, 7)
+    B = pdsynth.exp_pd(18, 8)
+    C = pdsynth.exp_pd(10, 9)
+    assert orc.exact_w1(np.concatenate([A, C]), np.concatenate([B, C])) == pytest.approx(orc.exact_w1(A, B), rel=1e-12)
+
+
+# ------------------------------------------------------------ min-cost flow --
+def _certificate(n, src, dst, cost, supply, flow, pot):
+    bal = np.zeros(n, np.int64)
+    np.add.at(bal, src, flow)
+    np.add.at(bal, dst, -flow)
+    assert np.array_equal(bal, supply), "flow conservation"
+    assert (flow >= 0).all()
+    red = cost - pot[src] + pot[dst]
+    assert (red >= 0).all(), "dual feasibility"
+    assert (red[flow > 0] == 0).all(), "complementary slackness"
+    assert int((cost * flow).sum()) == int((supply * pot).sum()), "strong duality"
+
+
+def test_mcf_against_networkx_and_certificate(orc):
+    import networkx as nx
+
+    rng = np.random.default_rng(3)
+    for trial in range(15):
+        n = int(rng.integers(5, 40))
+        m = int(rng.integers(n, 6 * n))
+        src = rng.integers(0, n, m)
+        dst = rng.integers(0, n, m)
+        keep = src != dst
+        src, dst = src[keep], dst[keep]
+        # a spanning cycle keeps every instance feasible
+        src = np.concatenate([src, np.arange(n)])
+        dst = np.concatenate([dst, (np.arange(n) + 1) % n])
+        cost = rng.integers(0, 50, src.shape[0])
+        supply = rng.integers(-5, 6, n)
+        supply[-1] -= supply.sum()
+        c, flow, pot = orc.mcf(n, src, dst, cost, supply, want_certificate=True)
+        _certificate(n, src, dst, cost, supply, flow, pot)
+        G = nx.MultiDiGraph()
+        for v in range(n):
+            G.add_node(v, demand=-int(supply[v]))
+        for k in range(src.shape[0]):
+            G.add_edge(int(src[k]), int(dst[k]), weight=int(cost[k]))
+        assert c == nx.network_simplex(G)[0]
+
+
+def _g_ab(A, B):
+    """Dense 0-condensed network G(A, B) of Sec. 4.3 with costs doubled
+    (integer diagrams make every doubled cost an integer)."""
+    A = np.asarray(A, np.float64)
+    B = np.asarray(B, np.float64)
+    ua, ca = np.unique(A, axis=0, return_counts=True)
+    ub, cb = np.unique(B, axis=0, return_counts=True)
+    na, nb = ua.shape[0], ub.shape[0]
+    abar, bbar = na + nb, na + nb + 1
+    src, dst, cost = [], [], []
+    for x in range(na):
+        for y in range(nb):
+            src.append(x); dst.append(na + y)
+            cost.append(int(2 * max(abs(ua[x, 0] - ub[y, 0]), abs(ua[x, 1] - ub[y, 1]))))
+        src.append(x); dst.append(abar); cost.append(int(ua[x, 1] - ua[x, 0]))
+    for y in range(nb):
+        src.append(bbar); dst.append(na + y); cost.append(int(ub[y, 1] - ub[y, 0]))
+    src.append(bbar); dst.append(abar); cost.append(0)
+    supply = np.concatenate([ca, -cb, [-ca.sum(), cb.sum()]]).astype(np.int64)
+    return na + nb + 2, np.array(src), np.array(dst), np.array(cost), supply
+
+
+def test_matching_equals_flow(orc):
+    # Prop. (matching <=> flow): the min-cost flow on the 0-condensed network
+    # G(A, B) equals the min-weight perfect matching on Bi(A, B).
+    for seed in range(8):
+        A = pdsynth.integer_pd(25, 100 + seed, hi=8)
+        B = pdsynth.integer_pd(20, 200 + seed, hi=8)
+        n, src, dst, cost, supply = _g_ab(A, B)
+        assert orc.mcf(n, src, dst, cost, supply) == round(2 * orc.exact_w1(A, B))
+
+
+# -------------------------------------------------------------------- RWMD --
+def test_rwmd_golden(orc):
+    g = gold("rwmd_small.json")
+    r = orc.run(np.array(g["A"], float), np.array(g["B"], float), eps=0.1)
+    assert r.LA == g["L_A"] and r.LB == g["L_B"] and r.L == g["L"]
+    w = r.locs["w"]
+    assert list(r.locs["t"][w > 0]) == g["t_A"]
+    assert list(r.locs["t"][w < 0]) == g["t_B"]
+    assert orc.exact_w1(g["A"], g["B"]) == g["exact_w1"]
+
+
+def test_rwmd_single_point_closed_form(orc):
+    r = orc.run(np.array([[0.5, 2.0]]), np.zeros((0, 2)), eps=0.1)
+    assert r.L == 0.75 and r.LB == 0.0
+
+
+def test_rwmd_fixed_point_rounds_down(orc):
+    A = pdsynth.exp_pd(300, 21)
+    B = pdsynth.exp_pd(280, 22)
+    r = orc.run(A, B, eps=0.1, flags=orc.ORC_STOP_AFTER_TREE)
+    w, term = r.locs["w"], r.locs["term"]
+    for side, Lx, F in ((w > 0, r.LA, r.FA), (w < 0, r.LB, r.FB)):
+        exact = sum(Fraction(x) for x in term[side])
+        k = int(side.sum())
+        assert Fraction(Lx) <= exact
+        assert exact - Fraction(Lx) <= Fraction(k + 1, 2 ** F) + exact * Fraction(1, 2 ** 52)
+
+
+def test_rwmd_lower_bound_and_net(orc):
+    for seed in range(30):
+        A = pdsynth.exp_pd(12, 300 + seed, mean_pers=0.2)
+        B = pdsynth.exp_pd(9, 400 + seed, mean_pers=0.2)
+        r = orc.run(A, B, eps=0.1, flags=orc.ORC_STOP_AFTER_TREE)
+        assert r.L <= orc.exact_w1(A, B) + 1e-15
+    # co-located A and B points cancel (W1 depends on the net multiset only)
+    A = pdsynth.exp_pd(40, 1)
+    B = pdsynth.exp_pd(30, 2)
+    C = A[:10]
+    r1 = orc.run(A, B, flags=orc.ORC_STOP_AFTER_TREE)
+    r2 = orc.run(np.concatenate([A, C, C]), np.concatenate([B, C, C]), flags=orc.ORC_STOP_AFTER_TREE)
+    assert r1.L == r2.L and r1.n == r2.n
+
+
+# ------------------------------------------------------------------ params --
+def test_params_golden(orc):
+    g = gold("params.json")
+    for eps, s in g["s_table"].items():
+        assert orc.choose_s(float(eps)) == s
+    c = g["grid_case"]
+    assert orc.grid_exponent(c["eps_c"], c["L"], c["n"]) == c["e"]
+
+
+def test_params_minimal_s(orc):
+    for eps in np.linspace(0.01, 0.9, 40):
+        s = orc.choose_s(eps)
+        ec = 0.1 * eps
+        t = (s + 2) / (s - 2)
+        assert t + (t + 1) * ec <= 1 + eps
+        if s > 3:
+            t1 = (s + 1) / (s - 3)
+            assert t1 + (t1 + 1) * ec > 1 + eps
+
+
+# -------------------------------------------------------------------- grid --
+def test_grid_counts_and_node_drop(orc):
+    A = pdsynth.pareto_pd(3000, 5)
+    B = pdsynth.pareto_pd(2500, 6)
+    r = orc.run(A, B, eps=0.5, flags=orc.ORC_STOP_AFTER_TREE)
+    assert r.cells["cA"].sum() == r.nA and r.cells["cB"].sum() == r.nB
+    # node-drop identity: the cells are exactly the distinct floor cells
+    pts = np.concatenate([r.locs["b"], r.locs["d"]]).reshape(2, -1).T
+    cellset = np.unique(np.floor(np.ldexp(pts, -r.e)).astype(np.int64), axis=0)
+    assert cellset.shape[0] == r.cells["i"].shape[0]
+    assert (r.cells["j"] >= r.cells["i"]).all()
+    assert (np.diff(r.cells["key"].astype(np.float64)) > 0).all()
+
+
+def test_scale_and_translation_invariance(orc):
+    A = pdsynth.integer_pd(60, 1, hi=40) * 2.0 ** -8
+    B = pdsynth.integer_pd(50, 2, hi=40) * 2.0 ** -8
+    r = orc.run(A, B, eps=0.2)
+    for k in (-3, 5):
+        rk = orc.run(A * 2.0 ** k, B * 2.0 ** k, eps=0.2)
+        assert rk.e == r.e + k and rk.W1 == r.W1 * 2.0 ** k and rk.flow == r.flow
+        for f in ("i", "j", "cA", "cB"):
+            assert np.array_equal(rk.cells[f], r.cells[f])
+        assert np.array_equal(rk.pairs["u"], r.pairs["u"]) and np.array_equal(rk.pairs["v"], r.pairs["v"])
+    shift = 37 * 2.0 ** r.e
+    rt = orc.run(A + shift, B + shift, eps=0.2)
+    assert rt.W1 == r.W1 and rt.flow == r.flow
+    for f in ("i", "j", "cA", "cB"):
+        assert np.array_equal(rt.cells[f], r.cells[f])
+
+
+# -------------------------------------------------------------------- tree --
+def test_tree_invariants(orc):
+    A = pdsynth.mixture_pd(700, 3)
+    B = pdsynth.mixture_pd(650, 4)
+    r = orc.run(A, B, eps=0.2, flags=orc.ORC_STOP_AFTER_TREE)
+    N = r.cells["i"].shape[0]
+    nodes, key = r.nodes, r.cells["key"]
+    assert nodes.shape[0] == 2 * N - 1
+    seen = np.zeros(2 * N - 1, np.int64)
+    for k in range(N, 2 * N - 1):
+        lo, hi, l, rr, m = nodes[k, :5]
+        seen[l] += 1
+        seen[rr] += 1
+        assert nodes[l, 0] == lo and nodes[l, 1] == m and nodes[rr, 0] == m + 1 and nodes[rr, 1] == hi
+        x = int(key[lo]) ^ int(key[hi])
+        bit = x.bit_length() - 1
+        assert all(((int(key[q]) >> bit) & 1) == (q > m) for q in range(lo, hi + 1))
+        ii, jj = r.cells["i"][lo:hi + 1], r.cells["j"][lo:hi + 1]
+        assert tuple(nodes[k, 5:9]) == (ii.min(), jj.min(), ii.max(), jj.max())
+        assert nodes[k, 9] == max(ii.max() - ii.min(), jj.max() - jj.min())
+    assert seen[r.root] == 0 and (np.delete(seen, r.root) == 1).all()
+
+
+# -------------------------------------------------------------------- WSPD --
+@pytest.mark.parametrize("s_override", [3, 5, 12, 53])
+def test_wspd_bruteforce_coverage(orc, s_override):
+    for seed in range(3):
+        A = pdsynth.exp_pd(24, 50 + seed, mean_pers=0.3)
+        B = pdsynth.exp_pd(22, 60 + seed, mean_pers=0.3)
+        r = orc.run(A, B, eps=0.2, s_override=s_override, flags=orc.ORC_KEEP_PAIR_NODES | orc.ORC_NO_FLOW)
+        assert r.cells["i"].shape[0] >= 30
+        orc.wspd_coverage(r)
+
+
+@pytest.mark.parametrize("s_override", [4, 9, 28])
+def test_wspd_spanner_stretch(orc, s_override):
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import shortest_path
+
+    A = pdsynth.exp_pd(80, 70, mean_pers=0.2)
+    B = pdsynth.exp_pd(70, 71, mean_pers=0.2)
+    r = orc.run(A, B, eps=0.2, s_override=s_override, flags=orc.ORC_NO_FLOW)
+    N = r.cells["i"].shape[0]
+    u, v, c = r.pairs["u"], r.pairs["v"], r.pairs["c"]
+    G = coo_matrix((c.astype(float), (u, v)), shape=(N, N)).tocsr()
+    D = shortest_path(G, directed=False)
+    ci, cj = r.cells["i"], r.cells["j"]
+    direct = 2 * np.maximum(np.abs(ci[:, None] - ci[None, :]), np.abs(cj[:, None] - cj[None, :]))
+    t = (s_override + 2) / (s_override - 2)
+    off = ~np.eye(N, dtype=bool)
+    assert (D[off] <= t * direct[off] + 1e-9).all()
+    assert (D[off] >= direct[off] - 1e-9).all()
+
+
+# --------------------------------------------------------------- theorems --
+def _dense_gdelta_flow(orc, r):
+    """Min-cost flow on the bipartite condensed network G_delta (A cells and
+    B cells as separate nodes, all A-B arcs), costs in units of g/2."""
+    ci, cj, ca, cb = r.cells["i"], r.cells["j"], r.cells["cA"], r.cells["cB"]
+    ia, ib = np.nonzero(ca)[0], np.nonzero(cb)[0]
+    na, nb = ia.shape[0], ib.shape[0]
+    abar, bbar = na + nb, na + nb + 1
+    X, Y = np.meshgrid(np.arange(na), np.arange(nb), indexing="ij")
+    src = [X.ravel()]
+    dst = [na + Y.ravel()]
+    cost = [2 * np.maximum(np.abs(ci[ia][X] - ci[ib][Y]), np.abs(cj[ia][X] - cj[ib][Y])).ravel()]
+    src += [np.arange(na), np.full(nb, bbar), [bbar]]
+    dst += [np.full(na, abar), na + np.arange(nb), [abar]]
+    cost += [cj[ia] - ci[ia], cj[ib] - ci[ib], [0]]
+    supply = np.concatenate([ca[ia], -cb[ib], [-ca.sum(), cb.sum()]])
+    return orc.mcf(na + nb + 2, np.concatenate(src), np.concatenate(dst), np.concatenate(cost), supply)
+
+
+def test_sparse_network_theorem(orc):
+    # Thm. (WSPD network): f* <= fbar* <= t f* with t the spanner stretch.
+    for seed, s in ((0, 4), (1, 6), (2, 12)):
+        A = pdsynth.exp_pd(70, 500 + seed, mean_pers=0.2)
+        B = pdsynth.exp_pd(60, 600 + seed, mean_pers=0.2)
+        r = orc.run(A, B, eps=0.2, s_override=s)
+        fd = _dense_gdelta_flow(orc, r)
+        t = (s + 2) / (s - 2)
+        assert fd <= r.flow <= t * fd + 1e-9
+
+
+@pytest.mark.parametrize("eps", [0.2, 0.1, 0.05])
+def test_bracket_small(orc, eps):
+    # RWMD <= exact <= W1 <= (1+eps) exact; the paper's value lies within
+    # [(1 - eps_c), (1 + eps)] of exact.
+    for seed in range(12):
+        A = pdsynth.exp_pd(45, 2 * seed)
+        B = pdsynth.exp_pd(40, 2 * seed + 1)
+        r = orc.run(A, B, eps=eps)
+        ex = orc.exact_w1(A, B)
+        assert r.L <= ex <= r.W1 <= (1 + eps) * ex
+        assert (1 - r.eps_c) * ex <= r.W1_paper <= (1 + eps) * ex
+
+
+def test_bracket_config1(orc):
+    for k in range(2):
+        A = pdsynth.exp_pd(400, 2 * k)
+        B = pdsynth.exp_pd(400, 2 * k + 1)
+        r = orc.run(A, B, eps=0.1)
+        ex = orc.exact_w1(A, B)
+        assert r.L <= ex <= r.W1 <= 1.1 * ex
+
+
+def test_symmetry_and_net_invariance(orc):
+    A = pdsynth.exp_pd(60, 31)
+    B = pdsynth.exp_pd(55, 32)
+    r = orc.run(A, B, eps=0.2)
+    rs = orc.run(B, A, eps=0.2)
+    assert rs.W1 == r.W1 and rs.flow == r.flow and rs.L == r.L
+    C = pdsynth.exp_pd(20, 33)
+    rc = orc.run(np.concatenate([A, C]), np.concatenate([C, B]), eps=0.2)
+    assert rc.W1 == r.W1
+    rz = orc.run(A, A.copy(), eps=0.2)
+    assert rz.status == 0 and rz.W1 == 0.0 and rz.n == 0
+
+
+def test_one_sided_and_invalid(orc):
+    A = pdsynth.exp_pd(50, 41)
+    r = orc.run(A, np.zeros((0, 2)), eps=0.1)
+    exact = float(np.sum(0.5 * (A[:, 1] - A[:, 0])))
+    assert r.L <= exact <= r.W1 <= 1.1 * exact
+    assert orc.run(np.array([[1.0, 0.5]]), A).status == -1  # death < birth
+    assert orc.run(np.array([[np.nan, 0.5]]), A).status == -1
+    diag = np.array([[0.3, 0.3], [0.7, 0.7]])
+    assert orc.run(np.concatenate([A, diag]), np.zeros((0, 2))).W1 == r.W1
