@@ -1,0 +1,215 @@
+/*
+ * w1approx: approximate 1-Wasserstein distance between persistence diagrams
+ * on one AMD Instinct MI355X (gfx950), after Dey & Zhang, "Approximating
+ * 1-Wasserstein Distance between Persistence Diagrams by Graph
+ * Sparsification" (Alg. 3, the approximate W1 algorithm).
+ *
+ * The library runs the data-parallel part of the method as HIP kernels:
+ *   a0  0-condensation of A u B into net weighted locations (Sec. 4.3),
+ *   a1  RWMD lower bound L (Alg. 1, Sec. 5.1),
+ *   a2  delta-condensation onto a power-of-two grid (Alg. 2,
+ *       Prop. delta-condensation),
+ *   a3  binary radix tree over Morton-ordered cells (the hierarchy for the
+ *       WSPD, Sec. 5.3 split-tree paragraph),
+ *   a4  s-WSPD pairs (Alg. 4-6),
+ *   a5  the sparse transshipment network: biarcs, diagonal arcs (Alg. 7) and
+ *       supplies,
+ * and then solves the uncapacitated min-cost flow of that network on the host
+ * with an integer network simplex (Sec. 5.4), timed separately.
+ *
+ * Ground metric: L-infinity.  Distance to the diagonal of (b, d): (d - b)/2.
+ * Costs of the network are integers in units of g/2, g = 2^grid_exp.
+ * Guarantee: exact_W1 <= w1 <= (1 + eps) * exact_W1 and
+ *            lower_bound <= exact_W1.
+ *
+ * Conventions for every entry point
+ *   - returns W1_OK (0) or a negative W1_E* code; never aborts, never throws;
+ *   - input point arrays are borrowed for the duration of the call; rows are
+ *     (birth, death) pairs, row-major, FP32 or FP64 as given by `dtype`;
+ *     death == birth rows lie on the diagonal and are ignored; death < birth
+ *     or a non-finite value gives W1_EINVAL;
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Device inputs
+ *     must be ready on that stream.  The call synchronises the stream before
+ *     it returns;
+ *   - a w1_ctx is not thread-safe: use one per host thread.  It keeps its
+ *     device buffers between calls (they only grow);
+ *   - arrays inside a w1_result are allocated by the library and released by
+ *     w1_result_free only.
+ */
+#ifndef W1APPROX_H
+#define W1APPROX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define W1_OK 0
+#define W1_EINVAL (-1)    /* bad argument or invalid diagram point          */
+#define W1_ERANGE (-2)    /* grid extent >= 2^30 cells, or coordinates too   */
+                          /* large for exact integer snapping                */
+#define W1_ENOMEM (-3)    /* device or host allocation failed                */
+#define W1_EHIP (-4)      /* HIP runtime error (see w1_ctx_hip_error)        */
+#define W1_EOVERFLOW (-5) /* internal work list capacity exceeded            */
+#define W1_ENODEV (-6)    /* no usable gfx950 device                         */
+
+/* ---- w1_result.status --------------------------------------------------- */
+#define W1_OPTIMAL 0      /* flow solved to optimality (or not requested)    */
+#define W1_STALLED 1      /* pivot_cap reached: flow_cost is not optimal     */
+
+/* ---- dtypes -------------------------------------------------------------- */
+#define W1_F32 0
+#define W1_F64 1
+
+/* ---- w1_params.flags ------------------------------------------------------ */
+#define W1_INPUT_DEVICE 1u /* w1_pd.xy are device pointers                  */
+#define W1_COUNT_ONLY 2u   /* stop after counting WSPD pairs (no arcs, flow) */
+#define W1_NO_FLOW 4u      /* build the network on the device, skip the flow */
+#define W1_KEEP_NETWORK 8u /* copy the network into the result (host)       */
+#define W1_KEEP_STAGES 16u /* copy stage intermediates into the result      */
+
+typedef struct w1_ctx w1_ctx;
+
+/* One persistence diagram: n rows of (birth, death). */
+typedef struct {
+  const void *xy;
+  int64_t n;
+  int32_t dtype;    /* W1_F32 or W1_F64 */
+  int32_t reserved; /* must be 0 */
+} w1_pd;
+
+typedef struct {
+  double eps;         /* target relative error, 0 < eps <= 1                  */
+  double cond_frac;   /* share kappa of eps spent on grid condensation,        */
+                      /* 0 < kappa < 0.5; 0 selects 0.1                         */
+  int32_t s_override; /* > 2: use this WSPD separation s instead of the one   */
+                      /* derived from eps (the (1+eps) bound then does not     */
+                      /* hold; this is the paper's "sparsity parameter" mode) */
+  uint32_t flags;     /* W1_* flags above                                      */
+  int64_t pivot_cap;  /* network simplex pivot limit, 0 = unlimited            */
+} w1_params;
+
+/* Per-stage timings in milliseconds (t_ms index). */
+#define W1_T_CONDENSE0 0 /* a0 */
+#define W1_T_RWMD 1      /* a1 */
+#define W1_T_GRID 2      /* a2 */
+#define W1_T_TREE 3      /* a3 */
+#define W1_T_WSPD 4      /* a4 */
+#define W1_T_ARCS 5      /* a5 */
+#define W1_T_D2H 6       /* network copy to the host */
+#define W1_T_FLOW 7      /* host min-cost flow */
+
+typedef struct {
+  double w1;          /* (g/2)(F* + n): certified, exact <= w1 <= (1+eps) exact */
+  double w1_paper;    /* (g/2) F*: the paper's value on the condensed network  */
+  double lower_bound; /* RWMD lower bound L (exact fixed-point sum, rounded down) */
+  double grid;        /* g = 2^grid_exp                                          */
+  int32_t grid_exp;
+  int32_t s;          /* WSPD separation used                                    */
+  int32_t status;     /* W1_OPTIMAL / W1_STALLED, or a negative W1_E* for this pair */
+  int32_t flow_solved;/* 1 if w1 / w1_paper / flow_cost come from a flow solve   */
+  int64_t n_points;   /* n = nA + nB after co-located A/B points cancel          */
+  int64_t n_a, n_b;
+  int64_t n_locations;/* distinct (birth, death) locations with net mass != 0    */
+  int64_t n_cells;    /* grid cells = network nodes other than the two diagonal nodes */
+  int64_t n_pairs;    /* WSPD pairs = biarcs                                    */
+  int64_t n_arcs;     /* directed arcs: 2 n_pairs + diagonal arcs (incl. b->a)  */
+  int64_t flow_cost;  /* F* in units of g/2 (-1 if not solved)                 */
+  int64_t pivots;     /* network simplex pivots                                 */
+
+  /* Network (W1_KEEP_NETWORK).  Node ids: cells 0..n_cells-1 in Morton order
+   * of (cell_i, cell_j), the diagonal node of A is n_cells, the diagonal node
+   * of B is n_cells+1.  Pair k is the two arcs pair_u->pair_v and
+   * pair_v->pair_u, both with cost pair_cost (= 2 max(|di|, |dj|)).  Diagonal
+   * arcs: cell->A-diagonal for cells with A mass, B-diagonal->cell for cells
+   * with B mass (cost cell_j - cell_i), and B-diagonal->A-diagonal (cost 0).
+   * supply[v] = out-flow minus in-flow at v. */
+  int32_t *cell_i, *cell_j;   /* n_cells, shifted grid coordinates */
+  int32_t *cell_ca, *cell_cb; /* n_cells, multiplicities from A and from B */
+  int64_t *supply;            /* n_cells + 2 */
+  uint32_t *pair_u, *pair_v;  /* n_pairs */
+  int32_t *pair_cost;         /* n_pairs */
+  uint32_t *diag_src, *diag_dst;
+  int32_t *diag_cost;
+  int64_t n_diag;
+
+  /* Stage intermediates (W1_KEEP_STAGES). */
+  double *loc_b, *loc_d; /* n_locations, sorted by (birth, death) */
+  int32_t *loc_w;        /* net multiplicity: count in A minus count in B */
+  double *loc_t;         /* RWMD: cost of the cheapest arc out of the location */
+  int64_t rwmd_sum_a, rwmd_sum_b;     /* fixed-point sums (int64)        */
+  int32_t rwmd_shift_a, rwmd_shift_b; /* L_x = sum_x * 2^-shift_x       */
+  int32_t *node_lo, *node_hi; /* n_cells-1 internal nodes: cell range    */
+  int32_t *node_left, *node_right; /* child: >= 0 internal node, < 0 leaf ~cell */
+  int32_t *node_box;          /* 4 per node: min_i, min_j, max_i, max_j  */
+
+  double t_ms[8];
+} w1_result;
+
+/* Device-resident network of the last w1_approx on a context (batch entry
+ * k of the last call).  Pointers stay valid until the next call on ctx. */
+typedef struct {
+  int64_t n_cells, n_pairs, n_diag;
+  const int32_t *cell_ij; /* 2 per cell: i, j */
+  const int32_t *cell_ca, *cell_cb;
+  const int64_t *supply;
+  const uint32_t *pair_u, *pair_v;
+  const int32_t *pair_cost;
+  const uint32_t *diag_src, *diag_dst;
+  const int32_t *diag_cost;
+} w1_device_network;
+
+/* Create a context on HIP device `device` (must be gfx950). */
+int w1_ctx_create(int device, w1_ctx **out);
+int w1_ctx_destroy(w1_ctx *ctx);
+/* Last HIP error code seen by the context (hipError_t as int). */
+int w1_ctx_hip_error(const w1_ctx *ctx);
+
+/* Approximate W1 of one pair (Alg. 3).  `out` is filled even on per-pair
+ * errors (status < 0); release it with w1_result_free. */
+int w1_approx(w1_ctx *ctx, const w1_pd *a, const w1_pd *b, const w1_params *params, void *stream,
+              w1_result *out);
+
+/* k pairs (a[i], b[i]) processed together: every stage runs once over all
+ * pairs.  out[i] receives pair i.  All diagrams must share one dtype and
+ * one memory kind (host or device, W1_INPUT_DEVICE). */
+int w1_approx_batch(w1_ctx *ctx, const w1_pd *a, const w1_pd *b, int64_t k, const w1_params *params,
+                    void *stream, w1_result *out);
+
+/* RWMD lower bound L (Alg. 1) of each of k pairs, without the rest. */
+int w1_rwmd(w1_ctx *ctx, const w1_pd *a, const w1_pd *b, int64_t k, uint32_t flags, void *stream,
+            double *L_out);
+
+/* Device pointers to the network of pair k of the last call on ctx
+ * (requires that call to have been made without W1_COUNT_ONLY). */
+int w1_device_network_get(w1_ctx *ctx, int64_t k, w1_device_network *out);
+
+/* Device times (ms, HIP events on the call's stream) of the last call's
+ * WSPD kernels: [0] work-list build (expansion rounds, item sort, chunking),
+ * [1] count pass, [2] emit pass, and the
+ * number of pairs emitted [3].  n is the capacity of ms (>= 4). */
+int w1_ctx_last_kernel_times(const w1_ctx *ctx, double *ms, int n);
+
+/* Host network simplex on any uncapacitated network with non-negative integer
+ * costs (the solver used inside w1_approx).  Arcs src[k] -> dst[k] with cost
+ * cost[k]; supply[v] = out-flow minus in-flow.  flow_out (m) and pot_out
+ * (n_nodes, reduced cost cost + pot[src] - pot[dst] >= 0 at optimum) may be
+ * NULL.  Returns W1_OK, W1_EINVAL (infeasible / bad input) or W1_ENOMEM;
+ * *status_out is W1_OPTIMAL or W1_STALLED. */
+int w1_flow_solve(int64_t n_nodes, int64_t m, const uint32_t *src, const uint32_t *dst, const int32_t *cost,
+                  const int64_t *supply, int64_t pivot_cap, int64_t *cost_out, int64_t *flow_out,
+                  int64_t *pot_out, int64_t *pivots_out, int32_t *status_out);
+
+/* WSPD separation s for eps and kappa (0 selects 0.1): the smallest s with
+ * t + (t + 1) kappa eps <= 1 + eps, t = (s + 2)/(s - 2). */
+int w1_separation_for_eps(double eps, double kappa);
+
+void w1_result_free(w1_result *r);
+const char *w1_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* W1APPROX_H */

@@ -199,20 +199,31 @@ double fixed_point_sum(const std::vector<double>& terms, int64_t* S_out, int* F_
   return std::ldexp(to_double_rz(S), -F);
 }
 
+// The nearest location of the other diagram is found by scanning that
+// diagram in birth order outwards from the query's birth, stopping once the
+// birth gap alone reaches the best cost found (the L-infinity distance is at
+// least the birth gap), so the minimum is exact.
+double cheapest_arc(const std::vector<Loc>& other, double b, double d) {
+  double best = 0.5 * (d - b);  // arc to the diagonal node
+  size_t k = (size_t)(std::lower_bound(other.begin(), other.end(), b,
+                                       [](const Loc& l, double x) { return l.b < x; }) - other.begin());
+  for (size_t r = k; r < other.size() && other[r].b - b < best; ++r)
+    best = std::min(best, std::max(std::fabs(b - other[r].b), std::fabs(d - other[r].d)));
+  for (size_t r = k; r-- > 0 && b - other[r].b < best;)
+    best = std::min(best, std::max(std::fabs(b - other[r].b), std::fabs(d - other[r].d)));
+  return best;
+}
+
 void rwmd(Oracle& o) {
   const size_t m = o.locs.size();
   o.t.assign(m, 0.0);
   o.term.assign(m, 0.0);
+  std::vector<Loc> sideA, sideB;  // locs are sorted by (b, d), so these are too
+  for (const Loc& l : o.locs) (l.w > 0 ? sideA : sideB).push_back(l);
   std::vector<double> termA, termB;
   for (size_t u = 0; u < m; ++u) {
     const Loc& a = o.locs[u];
-    double best = 0.5 * (a.d - a.b);  // arc to the diagonal node
-    for (size_t v = 0; v < m; ++v) {
-      const Loc& q = o.locs[v];
-      if ((a.w > 0) == (q.w > 0)) continue;  // only the other diagram
-      double dist = std::max(std::fabs(a.b - q.b), std::fabs(a.d - q.d));
-      best = std::min(best, dist);
-    }
+    const double best = cheapest_arc(a.w > 0 ? sideB : sideA, a.b, a.d);
     o.t[u] = best;
     o.term[u] = (double)(a.w > 0 ? a.w : -a.w) * best;
     if (a.w > 0) termA.push_back(o.term[u]);

@@ -1,0 +1,236 @@
+// Host min-cost flow of the sparse transshipment network: primal network
+// simplex for uncapacitated networks with integer costs (Sec. 5.4).
+//
+//  * Basis: a spanning tree rooted at an artificial node; the start tree
+//    links every node to the root with an artificial arc of cost larger than
+//    any simple path, oriented so the tree is strongly feasible (zero-flow
+//    tree arcs point away from the root).
+//  * Entering arc: block search pivot rule (the paper's choice): arcs are
+//    scanned cyclically in blocks of about sqrt(m); the most negative reduced
+//    cost of the first block that has one enters.
+//  * Leaving arc: the last blocking arc met when the pivot cycle is traversed
+//    in the direction of the entering arc starting at the apex; this keeps
+//    every basis strongly feasible, so degenerate pivots cannot cycle (this
+//    takes over the job of the paper's random jitter, which it used against
+//    stalling).
+//  * Tree storage: parent, predecessor arc, depth and doubly linked child
+//    lists; after a pivot the detached subtree is re-rooted along the path to
+//    the entering arc and its potentials and depths are shifted by a DFS.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "flow.h"
+
+namespace w1 {
+
+namespace {
+
+struct Simplex {
+  int32_t n = 0, root = 0;
+  int64_t m = 0;
+  std::vector<int32_t> src, dst;
+  std::vector<int64_t> cost, flow;
+  std::vector<uint8_t> in_tree;
+  std::vector<int32_t> parent, pred, depth, first_child, next_sib, prev_sib;
+  std::vector<uint8_t> up;  // pred arc runs node -> parent
+  std::vector<int64_t> pi;
+  std::vector<int32_t> path, stack;
+
+  int64_t rc(int64_t a) const { return cost[a] + pi[src[a]] - pi[dst[a]]; }
+
+  void unlink(int32_t x) {
+    const int32_t p = parent[x];
+    if (prev_sib[x] >= 0) next_sib[prev_sib[x]] = next_sib[x];
+    else first_child[p] = next_sib[x];
+    if (next_sib[x] >= 0) prev_sib[next_sib[x]] = prev_sib[x];
+    next_sib[x] = prev_sib[x] = -1;
+  }
+  void link(int32_t x, int32_t p) {
+    parent[x] = p;
+    prev_sib[x] = -1;
+    next_sib[x] = first_child[p];
+    if (first_child[p] >= 0) prev_sib[first_child[p]] = x;
+    first_child[p] = x;
+  }
+};
+
+}  // namespace
+
+int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint32_t* dst, const int32_t* cost,
+                    const int64_t* supply, int64_t pivot_cap, FlowResult* out) {
+  out->cost = -1;
+  out->pivots = 0;
+  out->status = 0;
+  if (n_nodes < 0 || m < 0 || n_nodes >= (int64_t(1) << 31) - 1) return -1;
+  int64_t total = 0;
+  for (int64_t v = 0; v < n_nodes; ++v) total += supply[v];
+  if (total != 0) return -1;
+  int64_t maxc = 0;
+  for (int64_t a = 0; a < m; ++a) {
+    if (cost[a] < 0 || src[a] >= (uint64_t)n_nodes || dst[a] >= (uint64_t)n_nodes) return -1;
+    maxc = std::max<int64_t>(maxc, cost[a]);
+  }
+  Simplex S;
+  const int32_t n = (int32_t)n_nodes;
+  S.n = n;
+  S.root = n;
+  S.m = m;
+  const int64_t ma = m + n;
+  try {
+    S.src.resize((size_t)ma);
+    S.dst.resize((size_t)ma);
+    S.cost.resize((size_t)ma);
+    S.flow.assign((size_t)ma, 0);
+    S.in_tree.assign((size_t)ma, 0);
+    S.parent.assign((size_t)n + 1, -1);
+    S.pred.assign((size_t)n + 1, -1);
+    S.depth.assign((size_t)n + 1, 0);
+    S.first_child.assign((size_t)n + 1, -1);
+    S.next_sib.assign((size_t)n + 1, -1);
+    S.prev_sib.assign((size_t)n + 1, -1);
+    S.up.assign((size_t)n + 1, 0);
+    S.pi.assign((size_t)n + 1, 0);
+  } catch (...) {
+    return -3;
+  }
+  for (int64_t a = 0; a < m; ++a) {
+    S.src[a] = (int32_t)src[a];
+    S.dst[a] = (int32_t)dst[a];
+    S.cost[a] = cost[a];
+  }
+  const int64_t ART = (maxc + 1) * ((int64_t)n + 1);
+  for (int32_t v = 0; v < n; ++v) {
+    const int64_t a = m + v;
+    S.cost[a] = ART;
+    S.in_tree[a] = 1;
+    if (supply[v] > 0) {
+      S.src[a] = v;
+      S.dst[a] = S.root;
+      S.flow[a] = supply[v];
+      S.up[v] = 1;
+      S.pi[v] = -ART;
+    } else {
+      S.src[a] = S.root;
+      S.dst[a] = v;
+      S.flow[a] = -supply[v];
+      S.up[v] = 0;
+      S.pi[v] = ART;
+    }
+    S.pred[v] = (int32_t)a;
+    S.depth[v] = 1;
+    S.link(v, S.root);
+  }
+
+  const int64_t block = std::max<int64_t>(10, (int64_t)std::sqrt((double)std::max<int64_t>(m, 1)));
+  int64_t next_arc = 0;
+  int64_t pivots = 0;
+  int status = 0;
+  for (;;) {
+    // ---- entering arc: block search
+    int64_t enter = -1, best = 0;
+    if (m > 0) {
+      int64_t a = next_arc;
+      for (int64_t scanned = 0; scanned < m;) {
+        if (!S.in_tree[a]) {
+          const int64_t r = S.rc(a);
+          if (r < best) {
+            best = r;
+            enter = a;
+          }
+        }
+        if (++a == m) a = 0;
+        ++scanned;
+        if (enter >= 0 && scanned % block == 0) break;
+      }
+      next_arc = a;
+    }
+    if (enter < 0) break;
+    if (pivot_cap > 0 && pivots >= pivot_cap) {
+      status = 1;
+      break;
+    }
+    ++pivots;
+    const int32_t k = S.src[enter], l = S.dst[enter];
+    // ---- apex
+    int32_t x = k, y = l;
+    while (S.depth[x] > S.depth[y]) x = S.parent[x];
+    while (S.depth[y] > S.depth[x]) y = S.parent[y];
+    while (x != y) {
+      x = S.parent[x];
+      y = S.parent[y];
+    }
+    const int32_t apex = x;
+    // ---- leaving arc (last blocking arc from the apex along k -> l)
+    const int64_t INF = INT64_MAX;
+    int64_t delta = INF;
+    int32_t leave_node = -1;
+    bool leave_on_k = false;
+    for (int32_t v = k; v != apex; v = S.parent[v])
+      if (S.up[v] && S.flow[S.pred[v]] < delta) {
+        delta = S.flow[S.pred[v]];
+        leave_node = v;
+        leave_on_k = true;
+      }
+    for (int32_t v = l; v != apex; v = S.parent[v])
+      if (!S.up[v] && S.flow[S.pred[v]] <= delta) {
+        delta = S.flow[S.pred[v]];
+        leave_node = v;
+        leave_on_k = false;
+      }
+    if (leave_node < 0) return -1;  // unbounded: impossible with non-negative costs
+    // ---- flow update
+    if (delta > 0) {
+      for (int32_t v = k; v != apex; v = S.parent[v]) S.flow[S.pred[v]] += S.up[v] ? -delta : delta;
+      for (int32_t v = l; v != apex; v = S.parent[v]) S.flow[S.pred[v]] += S.up[v] ? delta : -delta;
+      S.flow[enter] += delta;
+    }
+    // ---- tree update: detach the subtree at leave_node, re-root it at the
+    // entering arc's endpoint inside it, hang it below the other endpoint.
+    const int32_t u_in = leave_on_k ? k : l, v_in = leave_on_k ? l : k;
+    const int64_t leave_arc = S.pred[leave_node];
+    S.path.clear();
+    for (int32_t v = u_in;; v = S.parent[v]) {
+      S.path.push_back(v);
+      if (v == leave_node) break;
+    }
+    for (int32_t v : S.path) S.unlink(v);
+    int32_t new_parent = v_in;
+    int64_t new_pred = enter;
+    for (size_t i = 0; i < S.path.size(); ++i) {
+      const int32_t v = S.path[i];
+      const int64_t old_pred = S.pred[v];
+      S.link(v, new_parent);
+      S.pred[v] = (int32_t)new_pred;
+      S.up[v] = S.src[new_pred] == v ? 1 : 0;
+      new_parent = v;
+      new_pred = old_pred;
+    }
+    S.in_tree[leave_arc] = 0;
+    S.in_tree[enter] = 1;
+    const int64_t dpi = leave_on_k ? -best : best;
+    S.stack.clear();
+    S.stack.push_back(u_in);
+    while (!S.stack.empty()) {
+      const int32_t v = S.stack.back();
+      S.stack.pop_back();
+      S.pi[v] += dpi;
+      S.depth[v] = S.depth[S.parent[v]] + 1;
+      for (int32_t c = S.first_child[v]; c >= 0; c = S.next_sib[c]) S.stack.push_back(c);
+    }
+  }
+  out->pivots = pivots;
+  out->status = status;
+  int64_t c = 0;
+  for (int64_t a = 0; a < m; ++a) c += S.cost[a] * S.flow[a];
+  if (status == 0)
+    for (int32_t v = 0; v < n; ++v)
+      if (S.flow[m + v] != 0) return -1;  // supplies cannot be routed
+  out->cost = c;
+  if (out->flow) std::copy(S.flow.begin(), S.flow.begin() + m, out->flow);
+  if (out->pot) std::copy(S.pi.begin(), S.pi.begin() + n, out->pot);
+  return 0;
+}
+
+}  // namespace w1

@@ -1,0 +1,113 @@
+// Host-side launchers of the stage kernels (internal).
+#pragma once
+
+#include "common.h"
+
+namespace w1 {
+
+// One input segment: the points of diagram `side` (0 = A, 1 = B) of pair
+// `pair`, read from `ptr` and placed at packed index out_off.
+struct SegDesc {
+  const void* ptr;
+  int64_t n;
+  int64_t out_off;
+  int32_t pair;
+  int32_t side;
+};
+
+// a0
+void launch_load(const SegDesc* segs, int nseg, int64_t total, int dtype, double* pb, double* pd, uint32_t* psd,
+                 uint64_t* kw0, uint64_t* kw1, uint64_t* kw2, int32_t* perr, hipStream_t st);
+void launch_group_heads(const uint32_t* perm, const uint64_t* kw2s, const double* pb, const double* pd, int64_t n,
+                        uint32_t* head, hipStream_t st);
+void launch_group_fill(const uint32_t* perm, const uint64_t* kw2s, const uint32_t* head, const uint32_t* gidx,
+                       const double* pb, const double* pd, const uint32_t* psd, int64_t n, double* gb, double* gd,
+                       uint32_t* gpair, int32_t* gw, hipStream_t st);
+void launch_count_total(const uint32_t* head, const uint32_t* scanned, int64_t n, uint64_t* out, hipStream_t st);
+void launch_nonzero_flags(const int32_t* gw, int64_t G, uint32_t* flag, hipStream_t st);
+void launch_loc_fill(const int32_t* gw, const uint32_t* flag, const uint32_t* lidx, const double* gb, const double* gd,
+                     const uint32_t* gpair, int64_t G, double* lb, double* ld, int32_t* lw, uint32_t* lpair,
+                     const PairArrays& P, hipStream_t st);
+// a1
+void launch_loc_bbox(const double* lb, const double* ld, const uint32_t* lpair, int64_t M, const PairArrays& P,
+                     hipStream_t st);
+void launch_bucket_setup(const PairArrays& P, int64_t K, int64_t* nbuckets, hipStream_t st);
+void launch_bucket_count(const double* lb, const double* ld, const int32_t* lw, const uint32_t* lpair, int64_t M,
+                         const PairArrays& P, uint32_t* bincnt, int64_t* lbin, hipStream_t st);
+void launch_bucket_fill(const double* lb, const double* ld, const int64_t* lbin, int64_t M, const uint32_t* binstart,
+                        uint32_t* bincur, double2* ent, hipStream_t st);
+void launch_nn(const double* lb, const double* ld, const int32_t* lw, const uint32_t* lpair, int64_t M,
+               const PairArrays& P, const uint32_t* binstart, const double2* ent, double* lt, double* lterm,
+               hipStream_t st);
+void launch_term_max(const double* lterm, const int32_t* lw, const uint32_t* lpair, int64_t M, const PairArrays& P,
+                     hipStream_t st);
+void launch_rwmd_shift(const PairArrays& P, int64_t K, hipStream_t st);
+void launch_term_sum(const double* lterm, const int32_t* lw, const uint32_t* lpair, int64_t M, const PairArrays& P,
+                     hipStream_t st);
+void launch_params(const PairArrays& P, int64_t K, double eps_c, hipStream_t st);
+// a2
+void launch_snap(const double* lb, const double* ld, const uint32_t* lpair, int64_t M, const PairArrays& P, int64_t* li,
+                 int64_t* lj, hipStream_t st);
+void launch_morton(const int64_t* li, const int64_t* lj, const uint32_t* lpair, int64_t M, const PairArrays& P,
+                   uint64_t* kw0, uint64_t* kw1, hipStream_t st);
+void launch_cell_heads(const uint32_t* perm, const uint64_t* kw1s, const uint64_t* kw0, int64_t M, uint32_t* head,
+                       hipStream_t st);
+void launch_cell_fill(const uint32_t* perm, const uint64_t* kw1s, const uint64_t* kw0, const uint32_t* head,
+                      const uint32_t* cidx, const int64_t* li, const int64_t* lj, const int32_t* lw, int64_t M,
+                      const PairArrays& P, uint64_t* ckey, uint32_t* cpair, int2* cij, int32_t* ca, int32_t* cb,
+                      hipStream_t st);
+// a3
+void launch_karras(const uint32_t* cpair, const uint64_t* ckey, int64_t N, int4* iaux, int32_t* iparent,
+                   int32_t* lparent, hipStream_t st);
+void launch_boxes(const int2* cij, int64_t N, const int4* iaux, const int32_t* iparent, const int32_t* lparent,
+                  uint32_t* visit, int4* ibox, int32_t* iheight, hipStream_t st);
+// a5
+void launch_diag_count(const uint32_t* cpair, const int32_t* ca, const int32_t* cb, int64_t N, uint32_t* dcnt,
+                       hipStream_t st);
+void launch_diag_fill(const uint32_t* cpair, const int2* cij, const int32_t* ca, const int32_t* cb, int64_t N,
+                      const uint32_t* dpos, const PairArrays& P, uint32_t* dsrc, uint32_t* ddst, int32_t* dcost,
+                      int64_t* supply, hipStream_t st);
+
+// a4 ------------------------------------------------------------------------
+// Tree view used by the WSPD traversal.  Node reference r >= 0 is internal
+// node r, r < 0 is the leaf of cell ~r.
+struct TreeView {
+  const int4* ibox;     // internal: min_i, min_j, max_i, max_j
+  const int4* iaux;     // internal: left, right, lo, hi
+  const int32_t* iheight;
+  const int2* cij;      // cell coordinates
+  const uint32_t* cpair;
+  int64_t N;
+};
+
+struct WspdTuning {
+  int stack_depth;  // per-lane DFS stack entries (LDS), items need height sum < this
+  int work_cap;     // items need |U| * |V| <= work_cap to skip the expansion rounds
+  int chunk_items;  // items per chunk of the count / emit passes
+  int blocks_per_cu;
+};
+
+void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st);
+void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st);
+void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s, const WspdTuning& tun,
+                          uint64_t* cnt, hipStream_t st);
+void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const uint64_t* cnt, const uint64_t* pos,
+                         int2* out_items, int64_t out_base, int2* next, hipStream_t st);
+void launch_item_keys(const TreeView& T, const int2* items, int64_t m, uint64_t* keys, hipStream_t st);
+void launch_gather_items(const int2* src, const uint32_t* perm, int2* dst, int64_t m, hipStream_t st);
+void launch_item_pairs(const TreeView& T, const int2* items, int64_t m, int32_t* items_per_pair, hipStream_t st);
+void launch_chunk_heads(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start, int chunk,
+                        uint32_t* head, hipStream_t st);
+void launch_chunk_fill(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start,
+                       const int32_t* items_per_pair, const uint32_t* head, const uint32_t* cid, int chunk,
+                       int32_t* chunk_first, int32_t* chunk_end, int32_t* chunk_pair, hipStream_t st);
+void launch_wspd_pass(bool emit, const TreeView& T, const int2* items, const int32_t* chunk_first,
+                      const int32_t* chunk_end, const int32_t* chunk_pair, int64_t nchunks, const int32_t* xcd_range,
+                      uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
+                      const int64_t* cell_start, uint32_t* pu, uint32_t* pv, int32_t* pc, int32_t* err,
+                      int num_cus, hipStream_t st);
+void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
+                        const int32_t* chunk_first, const int64_t* item_start, int64_t nchunks, uint64_t* npairs,
+                        uint64_t* pair_start, hipStream_t st);
+
+}  // namespace w1

@@ -1,0 +1,1004 @@
+// Host orchestration of the approximate W1 pipeline and the C-ABI entry
+// points declared in include/w1approx.h.
+//
+// Stage order (Alg. 3): a0 0-condensation, a1 RWMD, a2 grid condensation,
+// a3 radix tree, a4 WSPD pairs, a5 diagonal arcs and supplies, then the host
+// network simplex.  A batch of k pairs runs every stage once over all pairs;
+// a single pair is a batch of one.  The host reads back a few counts between
+// stages to size buffers; everything else stays on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/w1approx.h"
+#include "common.h"
+#include "flow.h"
+#include "kernels.h"
+
+namespace w1 {
+
+struct DBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct StageError {
+  int code;
+};
+
+struct Ctx {
+  int device = 0;
+  int num_cus = 256;
+  int hip_err = 0;
+  bool trace = false;
+  hipStream_t st = nullptr;
+  uint64_t* hpin = nullptr;  // pinned host scratch for read-backs
+  WspdTuning tun{32, 4096, 256, 2};
+  std::vector<DBuf*> all;
+  // points
+  DBuf stage, segs, pb, pd, psd, kw0, kw1, kw2, kA, kB, vA, vB, head, idx, scantmp, sorttmp, small;
+  // groups / locations
+  DBuf gb, gd, gpair, gw, lb, ld, lw, lpair, lt, lterm, lbin, li, lj;
+  // rwmd buckets
+  DBuf nbuck, bincnt, binstart, ent;
+  // cells / tree
+  DBuf ckey, cpair, cij, ca, cb, iaux, ibox, iheight, iparent, lparent, visit;
+  // wspd
+  DBuf itemsA, itemsB, itemsI, itemsS, icnt, ipos, ipp, chead, cid, cfirst, cend, cpairs, ccnt, coff, xrange, xctr, err;
+  // network
+  DBuf pu, pv, pc, dcnt, dpos, dsrc, ddst, dcost, supply;
+  // per pair
+  DBuf pairs;
+  PairArrays P{};
+  int64_t K = 0;
+  std::vector<int64_t> h_cell_start, h_ncells, h_pair_start, h_npairs, h_diag_start, h_ndiag, h_supply_base;
+  bool network_valid = false;
+  hipEvent_t ev[8];
+  hipEvent_t kev[4];
+  double kms[4] = {0, 0, 0, 0};
+
+  Ctx() {
+    DBuf* list[] = {&stage, &segs, &pb, &pd, &psd, &kw0, &kw1, &kw2, &kA, &kB, &vA, &vB, &head, &idx, &scantmp, &sorttmp,
+                    &small, &gb, &gd, &gpair, &gw, &lb, &ld, &lw, &lpair, &lt, &lterm, &lbin, &li, &lj, &nbuck,
+                    &bincnt, &binstart, &ent, &ckey, &cpair, &cij, &ca, &cb, &iaux, &ibox, &iheight, &iparent,
+                    &lparent, &visit, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &chead, &cid,
+                    &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &pv, &pc, &dcnt, &dpos,
+                    &dsrc, &ddst, &dcost, &supply, &pairs};
+    all.assign(std::begin(list), std::end(list));
+  }
+};
+
+namespace {
+
+void check(Ctx& c, hipError_t e) {
+  if (e != hipSuccess) {
+    c.hip_err = (int)e;
+    throw StageError{W1_EHIP};
+  }
+}
+
+template <typename T>
+T* need(Ctx& c, DBuf& b, int64_t count) {
+  size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (bytes > b.cap) {
+    if (b.p) {
+      check(c, hipStreamSynchronize(c.st));
+      (void)hipFree(b.p);
+      b.p = nullptr;
+      b.cap = 0;
+    }
+    size_t want = std::max(bytes, b.cap + b.cap / 2);
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        throw StageError{W1_ENOMEM};
+      }
+      want = bytes;
+    }
+    b.cap = want;
+  }
+  return (T*)b.p;
+}
+
+// Grow while keeping the first `keep` elements.
+template <typename T>
+T* grow_keep(Ctx& c, DBuf& b, int64_t count, int64_t keep) {
+  size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+  if (bytes <= b.cap) return (T*)b.p;
+  DBuf nb;
+  T* np = need<T>(c, nb, count * 2);
+  if (keep > 0) check(c, hipMemcpyAsync(np, b.p, (size_t)keep * sizeof(T), hipMemcpyDeviceToDevice, c.st));
+  check(c, hipStreamSynchronize(c.st));
+  if (b.p) (void)hipFree(b.p);
+  b = nb;
+  return np;
+}
+
+template <typename T>
+void readback(Ctx& c, const T* dev, T* host, int64_t count) {
+  if (count <= 0) return;
+  check(c, hipMemcpyAsync(host, dev, (size_t)count * sizeof(T), hipMemcpyDeviceToHost, c.st));
+  check(c, hipStreamSynchronize(c.st));
+}
+
+// Small host -> device copy that completes before returning (the host
+// buffer may be released right after).
+void upload(Ctx& c, void* dev, const void* host, size_t bytes) {
+  if (!bytes) return;
+  check(c, hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c.st));
+  check(c, hipStreamSynchronize(c.st));
+}
+
+uint64_t read_u64(Ctx& c, const void* dev) {
+  check(c, hipMemcpyAsync(c.hpin, dev, 8, hipMemcpyDeviceToHost, c.st));
+  check(c, hipStreamSynchronize(c.st));
+  return c.hpin[0];
+}
+
+inline int clz64(uint64_t x) { return x ? __builtin_clzll(x) : 64; }
+inline int ctz64(uint64_t x) { return x ? __builtin_ctzll(x) : 64; }
+
+// Stable sort of n elements by the words (least significant first); returns
+// the permutation in *perm and the sorted most significant word in *top.
+void sort_words(Ctx& c, const uint64_t* const* words, int nw, int64_t n, uint32_t** perm, uint64_t** top) {
+  uint64_t* kA = need<uint64_t>(c, c.kA, n);
+  uint64_t* kB = need<uint64_t>(c, c.kB, n);
+  uint32_t* vA = need<uint32_t>(c, c.vA, n);
+  uint32_t* vB = need<uint32_t>(c, c.vB, n);
+  void* tmp = need<char>(c, c.sorttmp, (int64_t)radix_tmp_bytes(n));
+  uint64_t* orand = need<uint64_t>(c, c.small, 64) + 8;
+  iota_u32(vA, n, c.st);
+  for (int w = 0; w < nw; ++w) {
+    if (w == 0) check(c, hipMemcpyAsync(kA, words[0], (size_t)n * 8, hipMemcpyDeviceToDevice, c.st));
+    else gather_u64(words[w], vA, kA, n, c.st);
+    key_or_and(kA, n, orand, c.st);
+    readback(c, orand, c.hpin, 2);
+    const uint64_t vary = c.hpin[0] ^ c.hpin[1];
+    if (!vary) continue;
+    const int lo = ctz64(vary), hi = 64 - clz64(vary);
+    if (radix_sort(kA, vA, kB, vB, n, lo, hi, tmp, c.st)) {
+      std::swap(kA, kB);
+      std::swap(vA, vB);
+      std::swap(c.kA, c.kB);
+      std::swap(c.vA, c.vB);
+    }
+  }
+  *perm = vA;
+  *top = kA;
+}
+
+uint32_t* scan_flags(Ctx& c, const uint32_t* flags, int64_t n, DBuf& out) {
+  uint32_t* o = need<uint32_t>(c, out, n);
+  scan_u32(flags, o, n, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(n, 8)), c.st);
+  return o;
+}
+
+uint64_t total_of(Ctx& c, const uint32_t* flags, const uint32_t* scanned, int64_t n) {
+  if (n <= 0) return 0;
+  uint64_t* slot = need<uint64_t>(c, c.small, 64);
+  launch_count_total(flags, scanned, n, slot, c.st);
+  return read_u64(c, slot);
+}
+
+struct Opts {
+  double eps = 0.1, kappa = 0.1;
+  int s = 0;
+  uint32_t flags = 0;
+  int64_t pivot_cap = 0;
+};
+
+int separation(double eps, double kappa) {
+  const double ec = kappa * eps;
+  const double tau = (eps - 2.0 * ec) / (1.0 + ec);
+  int s = (int)std::ceil(2.0 + 4.0 / tau);
+  if (s < 3) s = 3;
+  for (;;) {
+    const double t = (double)(s + 2) / (double)(s - 2);
+    if (t + (t + 1.0) * ec <= 1.0 + eps) break;
+    ++s;
+  }
+  return s;
+}
+
+void setup_pairs(Ctx& c, int64_t K) {
+  // 24 int64-sized arrays and 12 int32-sized arrays per pair
+  const int64_t K8 = ((K + 31) / 32) * 32;
+  char* base = need<char>(c, c.pairs, K8 * 8 * 26 + K8 * 4 * 14);
+  int64_t off = 0;
+  auto take8 = [&](void) { void* p = base + off; off += K8 * 8; return p; };
+  auto take4 = [&](void) { void* p = base + off; off += K8 * 4; return p; };
+  PairArrays& P = c.P;
+  P.nA = (int64_t*)take8(); P.nB = (int64_t*)take8(); P.loc_start = (int64_t*)take8();
+  P.bmax = (uint64_t*)take8(); P.dmax = (uint64_t*)take8(); P.bx0 = (int64_t*)take8(); P.by0 = (int64_t*)take8();
+  P.bbase = (int64_t*)take8(); P.tmaxA = (uint64_t*)take8(); P.tmaxB = (uint64_t*)take8();
+  P.sumA = (uint64_t*)take8(); P.sumB = (uint64_t*)take8(); P.L = (double*)take8();
+  P.cell_start = (int64_t*)take8(); P.item_start = (int64_t*)take8(); P.npairs = (uint64_t*)take8();
+  P.pair_start = (uint64_t*)take8(); P.diag_start = (int64_t*)take8();
+  const int64_t zero8_end = off;
+  P.bmin = (uint64_t*)take8(); P.dmin = (uint64_t*)take8(); P.m0 = (int64_t*)take8();
+  const int64_t ones8_end = off;
+  off += K8 * 8 * 3;  // spare
+  P.err = (int32_t*)take4(); P.locA = (int32_t*)take4(); P.locB = (int32_t*)take4(); P.beh = (int32_t*)take4();
+  P.bnx = (int32_t*)take4(); P.bny = (int32_t*)take4(); P.FA = (int32_t*)take4(); P.FB = (int32_t*)take4();
+  P.e = (int32_t*)take4(); P.ncells = (int32_t*)take4(); P.ndiag = (int32_t*)take4();
+  fill_u64((uint64_t*)base, 0, zero8_end / 8, c.st);
+  fill_u64((uint64_t*)P.bmin, ~0ull, K8 * 2, c.st);
+  fill_u64((uint64_t*)P.m0, (uint64_t)INT64_MAX, K8, c.st);
+  (void)ones8_end;
+  fill_u32((uint32_t*)P.err, 0, K8 * 11, c.st);
+}
+
+struct HostPair {
+  int32_t err, locA, locB, e, ncells, ndiag, FA, FB;
+  int64_t nA, nB, cell_start, diag_start;
+  uint64_t sumA, sumB, npairs, pair_start;
+  double L;
+};
+
+template <typename T>
+std::vector<T> fetch_pairs(Ctx& c, const T* dev, int64_t K) {
+  std::vector<T> h((size_t)K);
+  readback(c, dev, h.data(), K);
+  return h;
+}
+
+void record(Ctx& c, int i) {
+  check(c, hipEventRecord(c.ev[i], c.st));
+  if (c.trace) {
+    static const char* names[] = {"start", "a0 condense0", "a1 rwmd", "a2 grid", "a3 tree", "a4 wspd", "a5 arcs", "end"};
+    check(c, hipStreamSynchronize(c.st));
+    std::fprintf(stderr, "[w1] %s done\n", names[i]);
+    std::fflush(stderr);
+  }
+}
+
+void trace(Ctx& c, const char* what, int64_t v) {
+  if (!c.trace) return;
+  std::fprintf(stderr, "[w1]   %s = %lld\n", what, (long long)v);
+  std::fflush(stderr);
+}
+
+// ------------------------------------------------------------------ pipeline --
+int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStream_t st, w1_result* res,
+        double* L_only) {
+  c.st = st;
+  c.network_valid = false;
+  c.K = K;
+  int dtype = -1;
+  int64_t total = 0;
+  const bool dev_in = (o.flags & W1_INPUT_DEVICE) != 0;
+  for (int64_t p = 0; p < K; ++p) {
+    for (int side = 0; side < 2; ++side) {
+      const w1_pd& d = side ? b[p] : a[p];
+      if (d.n < 0 || (d.n > 0 && !d.xy) || (d.dtype != W1_F32 && d.dtype != W1_F64) || d.reserved != 0) return W1_EINVAL;
+      if (dtype < 0) dtype = d.dtype;
+      if (d.dtype != dtype) return W1_EINVAL;
+      total += d.n;
+    }
+  }
+  if (total >= (int64_t(1) << 31) || K >= (int64_t(1) << 30)) return W1_EINVAL;
+  const int s = o.s > 0 ? o.s : separation(o.eps, o.kappa);
+  const double eps_c = o.kappa * o.eps;
+  for (int i = 0; i < 8; ++i) record(c, i);
+  record(c, 0);
+
+  // ---------------------------------------------------------------- a0 --
+  const size_t esz = dtype == W1_F32 ? 4 : 8;
+  std::vector<SegDesc> segs;
+  segs.reserve((size_t)(2 * K));
+  char* staging = nullptr;
+  if (!dev_in && total > 0) staging = need<char>(c, c.stage, total * 2 * (int64_t)esz);
+  int64_t off = 0;
+  for (int64_t p = 0; p < K; ++p)
+    for (int side = 0; side < 2; ++side) {
+      const w1_pd& d = side ? b[p] : a[p];
+      if (d.n == 0) continue;
+      const void* ptr = d.xy;
+      if (!dev_in) {
+        check(c, hipMemcpyAsync(staging + off * 2 * esz, d.xy, (size_t)d.n * 2 * esz, hipMemcpyHostToDevice, st));
+        ptr = staging + off * 2 * esz;
+      }
+      segs.push_back(SegDesc{ptr, d.n, off, (int32_t)p, side});
+      off += d.n;
+    }
+  setup_pairs(c, K);
+  PairArrays& P = c.P;
+  int64_t M = 0, N = 0;
+  if (total > 0) {
+    SegDesc* dsegs = need<SegDesc>(c, c.segs, (int64_t)segs.size());
+    upload(c, dsegs, segs.data(), segs.size() * sizeof(SegDesc));
+    double* pb = need<double>(c, c.pb, total);
+    double* pd = need<double>(c, c.pd, total);
+    uint32_t* psd = need<uint32_t>(c, c.psd, total);
+    uint64_t* kw0 = need<uint64_t>(c, c.kw0, total);
+    uint64_t* kw1 = need<uint64_t>(c, c.kw1, total);
+    uint64_t* kw2 = need<uint64_t>(c, c.kw2, total);
+    launch_load(dsegs, (int)segs.size(), total, dtype, pb, pd, psd, kw0, kw1, kw2, P.err, st);
+    check(c, hipGetLastError());
+    uint32_t* perm;
+    uint64_t* kw2s;
+    const uint64_t* words[3] = {kw0, kw1, kw2};
+    sort_words(c, words, 3, total, &perm, &kw2s);
+    uint32_t* head = need<uint32_t>(c, c.head, total);
+    launch_group_heads(perm, kw2s, pb, pd, total, head, st);
+    uint32_t* gidx = scan_flags(c, head, total, c.idx);
+    const int64_t G = (int64_t)total_of(c, head, gidx, total);
+    trace(c, "points", total);
+    trace(c, "groups", G);
+    double* gb = need<double>(c, c.gb, G);
+    double* gd = need<double>(c, c.gd, G);
+    uint32_t* gpair = need<uint32_t>(c, c.gpair, G);
+    int32_t* gw = need<int32_t>(c, c.gw, G);
+    fill_u32((uint32_t*)gw, 0, G, st);
+    launch_group_fill(perm, kw2s, head, gidx, pb, pd, psd, total, gb, gd, gpair, gw, st);
+    uint32_t* flag = need<uint32_t>(c, c.head, G);
+    launch_nonzero_flags(gw, G, flag, st);
+    uint32_t* lidx = scan_flags(c, flag, G, c.idx);
+    M = (int64_t)total_of(c, flag, lidx, G);
+    trace(c, "locations", M);
+    double* lb = need<double>(c, c.lb, M);
+    double* ld = need<double>(c, c.ld, M);
+    int32_t* lw = need<int32_t>(c, c.lw, M);
+    uint32_t* lpair = need<uint32_t>(c, c.lpair, M);
+    launch_loc_fill(gw, flag, lidx, gb, gd, gpair, G, lb, ld, lw, lpair, P, st);
+    check(c, hipGetLastError());
+  }
+  record(c, 1);
+
+  // ---------------------------------------------------------------- a1 --
+  if (M > 0) {
+    const double* lb = (const double*)c.lb.p;
+    const double* ld = (const double*)c.ld.p;
+    const int32_t* lw = (const int32_t*)c.lw.p;
+    const uint32_t* lpair = (const uint32_t*)c.lpair.p;
+    launch_loc_bbox(lb, ld, lpair, M, P, st);
+    int64_t* nbk = need<int64_t>(c, c.nbuck, K + 1);
+    launch_bucket_setup(P, K, nbk, st);
+    scan_i64(nbk, P.bbase, K, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(K, 8)), st);
+    int64_t lastb[2];
+    readback(c, P.bbase + (K - 1), &lastb[0], 1);
+    readback(c, nbk + (K - 1), &lastb[1], 1);
+    const int64_t Btot = lastb[0] + lastb[1];
+    trace(c, "rwmd buckets", Btot);
+    const int64_t nbins = 2 * Btot + 1;
+    if (nbins >= (int64_t(1) << 32)) throw StageError{W1_ERANGE};
+    uint32_t* bincnt = need<uint32_t>(c, c.bincnt, nbins);
+    fill_u32(bincnt, 0, nbins, st);
+    int64_t* lbin = need<int64_t>(c, c.lbin, M);
+    launch_bucket_count(lb, ld, lw, lpair, M, P, bincnt, lbin, st);
+    uint32_t* binstart = need<uint32_t>(c, c.binstart, nbins);
+    scan_u32(bincnt, binstart, nbins, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(nbins, 8)), st);
+    fill_u32(bincnt, 0, nbins, st);
+    double2* ent = need<double2>(c, c.ent, M);
+    launch_bucket_fill(lb, ld, lbin, M, binstart, bincnt, ent, st);
+    double* lt = need<double>(c, c.lt, M);
+    double* lterm = need<double>(c, c.lterm, M);
+    launch_nn(lb, ld, lw, lpair, M, P, binstart, ent, lt, lterm, st);
+    launch_term_max(lterm, lw, lpair, M, P, st);
+    launch_rwmd_shift(P, K, st);
+    launch_term_sum(lterm, lw, lpair, M, P, st);
+    launch_params(P, K, eps_c, st);
+    check(c, hipGetLastError());
+  }
+  record(c, 2);
+  if (L_only) {
+    std::vector<double> L = fetch_pairs(c, P.L, K);
+    std::vector<int32_t> er = fetch_pairs(c, P.err, K);
+    for (int64_t p = 0; p < K; ++p) L_only[p] = er[(size_t)p] == -1 ? NAN : L[(size_t)p];
+    return W1_OK;
+  }
+
+  // ---------------------------------------------------------------- a2 --
+  if (M > 0) {
+    const double* lb = (const double*)c.lb.p;
+    const double* ld = (const double*)c.ld.p;
+    const int32_t* lw = (const int32_t*)c.lw.p;
+    const uint32_t* lpair = (const uint32_t*)c.lpair.p;
+    int64_t* li = need<int64_t>(c, c.li, M);
+    int64_t* lj = need<int64_t>(c, c.lj, M);
+    launch_snap(lb, ld, lpair, M, P, li, lj, st);
+    uint64_t* kw0 = need<uint64_t>(c, c.kw0, M);
+    uint64_t* kw1 = need<uint64_t>(c, c.kw1, M);
+    launch_morton(li, lj, lpair, M, P, kw0, kw1, st);
+    uint32_t* perm;
+    uint64_t* kw1s;
+    const uint64_t* words[2] = {kw0, kw1};
+    sort_words(c, words, 2, M, &perm, &kw1s);
+    uint32_t* head = need<uint32_t>(c, c.head, M);
+    launch_cell_heads(perm, kw1s, kw0, M, head, st);
+    uint32_t* cidx = scan_flags(c, head, M, c.idx);
+    N = (int64_t)total_of(c, head, cidx, M);
+    trace(c, "cells", N);
+    uint64_t* ckey = need<uint64_t>(c, c.ckey, N);
+    uint32_t* cpair = need<uint32_t>(c, c.cpair, N);
+    int2* cij = need<int2>(c, c.cij, N);
+    int32_t* ca = need<int32_t>(c, c.ca, N);
+    int32_t* cb = need<int32_t>(c, c.cb, N);
+    fill_u32((uint32_t*)ca, 0, N, st);
+    fill_u32((uint32_t*)cb, 0, N, st);
+    launch_cell_fill(perm, kw1s, kw0, head, cidx, li, lj, lw, M, P, ckey, cpair, cij, ca, cb, st);
+    int64_t* nc64 = need<int64_t>(c, c.nbuck, K + 1);
+    // cell_start = exclusive scan of ncells (int32 -> int64 via host, K is small)
+    std::vector<int32_t> nc = fetch_pairs(c, P.ncells, K);
+    std::vector<int64_t> cs((size_t)K);
+    int64_t acc = 0;
+    for (int64_t p = 0; p < K; ++p) {
+      cs[(size_t)p] = acc;
+      acc += nc[(size_t)p];
+    }
+    upload(c, P.cell_start, cs.data(), (size_t)K * 8);
+    (void)nc64;
+    check(c, hipGetLastError());
+  }
+  record(c, 3);
+
+  // ---------------------------------------------------------------- a3 --
+  TreeView T{};
+  if (N > 0) {
+    T.cij = (const int2*)c.cij.p;
+    T.cpair = (const uint32_t*)c.cpair.p;
+    T.N = N;
+  }
+  if (N >= 2) {
+    int4* iaux = need<int4>(c, c.iaux, N - 1);
+    int4* ibox = need<int4>(c, c.ibox, N - 1);
+    int32_t* ih = need<int32_t>(c, c.iheight, N - 1);
+    int32_t* ipar = need<int32_t>(c, c.iparent, N - 1);
+    int32_t* lpar = need<int32_t>(c, c.lparent, N);
+    uint32_t* visit = need<uint32_t>(c, c.visit, N - 1);
+    fill_u32(visit, 0, N - 1, st);
+    launch_karras((const uint32_t*)c.cpair.p, (const uint64_t*)c.ckey.p, N, iaux, ipar, lpar, st);
+    launch_boxes((const int2*)c.cij.p, N, iaux, ipar, lpar, visit, ibox, ih, st);
+    T.ibox = ibox;
+    T.iaux = iaux;
+    T.iheight = ih;
+    check(c, hipGetLastError());
+  }
+  record(c, 4);
+
+  // ---------------------------------------------------------------- a4 --
+  int64_t Ptot = 0;
+  bool timed = false, emitted = false;
+  int32_t* derr = need<int32_t>(c, c.err, 64);
+  fill_u32((uint32_t*)derr, 0, 1, st);
+  if (N >= 2) {
+    const WspdTuning& tun = c.tun;
+    uint32_t* rflag = need<uint32_t>(c, c.head, N - 1);
+    launch_wspd_roots_flags(T, rflag, st);
+    uint32_t* rpos = scan_flags(c, rflag, N - 1, c.idx);
+    int64_t f = (int64_t)total_of(c, rflag, rpos, N - 1);
+    int2* F = need<int2>(c, c.itemsA, f);
+    launch_wspd_roots_fill(T, rflag, rpos, F, st);
+    int64_t isz = 0;
+    int2* I = need<int2>(c, c.itemsI, std::max<int64_t>(f, 1024));
+    check(c, hipEventRecord(c.kev[0], st));
+    trace(c, "root items", f);
+    for (int round = 0; f > 0; ++round) {
+      if (round > 4 * 64 + 8) throw StageError{W1_EOVERFLOW};  // deeper than two 64-bit key trees
+      uint64_t* cnt = need<uint64_t>(c, c.icnt, f);
+      uint64_t* pos = need<uint64_t>(c, c.ipos, f);
+      launch_wspd_classify(T, F, f, s, tun, cnt, st);
+      scan_u64(cnt, pos, f, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(f, 8)), st);
+      uint64_t lastp = 0, lastc = 0;
+      readback(c, pos + (f - 1), &lastp, 1);
+      readback(c, cnt + (f - 1), &lastc, 1);
+      const uint64_t tot = lastp + lastc;
+      const int64_t kept = (int64_t)(uint32_t)tot, grown = (int64_t)(tot >> 32);
+      I = grow_keep<int2>(c, c.itemsI, isz + kept, isz);
+      int2* Nx = need<int2>(c, c.itemsB, std::max<int64_t>(grown, 1));
+      F = (int2*)c.itemsA.p;
+      launch_wspd_scatter(T, F, f, cnt, pos, I, isz, Nx, st);
+      check(c, hipGetLastError());
+      std::swap(c.itemsA, c.itemsB);
+      F = (int2*)c.itemsA.p;
+      isz += kept;
+      f = grown;
+      trace(c, "  round: kept items", isz);
+      trace(c, "  round: frontier", f);
+    }
+    const int64_t m = isz;
+    if (m > 0) {
+      // sort items by (rep U, rep V): Morton order, pair-major, canonical
+      uint64_t* keys = need<uint64_t>(c, c.kw0, m);
+      launch_item_keys(T, I, m, keys, st);
+      uint32_t* perm;
+      uint64_t* top;
+      const uint64_t* words[1] = {keys};
+      sort_words(c, words, 1, m, &perm, &top);
+      int2* S = need<int2>(c, c.itemsS, m);
+      launch_gather_items(I, perm, S, m, st);
+      int32_t* ipp = need<int32_t>(c, c.ipp, K);
+      fill_u32((uint32_t*)ipp, 0, K, st);
+      launch_item_pairs(T, S, m, ipp, st);
+      timed = true;
+      std::vector<int32_t> hipp = fetch_pairs(c, ipp, K);
+      std::vector<int64_t> ist((size_t)K);
+      int64_t acc = 0;
+      for (int64_t p = 0; p < K; ++p) {
+        ist[(size_t)p] = acc;
+        acc += hipp[(size_t)p];
+      }
+      upload(c, P.item_start, ist.data(), (size_t)K * 8);
+      uint32_t* ch = need<uint32_t>(c, c.chead, m);
+      launch_chunk_heads(T, S, m, P.item_start, tun.chunk_items, ch, st);
+      uint32_t* cidv = scan_flags(c, ch, m, c.cid);
+      const int64_t nch = (int64_t)total_of(c, ch, cidv, m);
+      trace(c, "chunks", nch);
+      int32_t* cf = need<int32_t>(c, c.cfirst, nch);
+      int32_t* ce = need<int32_t>(c, c.cend, nch);
+      int32_t* cp = need<int32_t>(c, c.cpairs, nch);
+      launch_chunk_fill(T, S, m, P.item_start, ipp, ch, cidv, tun.chunk_items, cf, ce, cp, st);
+      int32_t hr[9];
+      for (int x = 0; x <= 8; ++x) hr[x] = (int32_t)((nch * x) / 8);
+      int32_t* xr = need<int32_t>(c, c.xrange, 16);
+      upload(c, xr, hr, sizeof(hr));
+      uint32_t* xc = need<uint32_t>(c, c.xctr, 16);
+      uint64_t* ccnt = need<uint64_t>(c, c.ccnt, nch);
+      uint64_t* coff = need<uint64_t>(c, c.coff, nch);
+      fill_u32(xc, 0, 8, st);
+      check(c, hipEventRecord(c.kev[1], st));
+      launch_wspd_pass(false, T, S, cf, ce, cp, nch, xr, xc, s, tun, ccnt, coff, P.cell_start, nullptr, nullptr,
+                       nullptr, derr, c.num_cus, st);
+      check(c, hipGetLastError());
+      check(c, hipEventRecord(c.kev[2], st));
+      scan_u64(ccnt, coff, nch, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(nch, 8)), st);
+      uint64_t lo = 0, lc = 0;
+      readback(c, coff + (nch - 1), &lo, 1);
+      readback(c, ccnt + (nch - 1), &lc, 1);
+      Ptot = (int64_t)(lo + lc);
+      trace(c, "wspd pairs", Ptot);
+      launch_pair_totals(ccnt, coff, cp, cf, P.item_start, nch, P.npairs, P.pair_start, st);
+      if (!(o.flags & W1_COUNT_ONLY) && Ptot > 0) {
+        uint32_t* pu = need<uint32_t>(c, c.pu, Ptot);
+        uint32_t* pv = need<uint32_t>(c, c.pv, Ptot);
+        int32_t* pc = need<int32_t>(c, c.pc, Ptot);
+        fill_u32(xc, 0, 8, st);
+        check(c, hipEventRecord(c.kev[3], st));
+        launch_wspd_pass(true, T, S, cf, ce, cp, nch, xr, xc, s, tun, ccnt, coff, P.cell_start, pu, pv, pc, derr,
+                         c.num_cus, st);
+        check(c, hipGetLastError());
+        emitted = true;
+      }
+    }
+  }
+  record(c, 5);
+  c.kms[0] = c.kms[1] = c.kms[2] = 0;
+  c.kms[3] = (double)Ptot;
+
+  // ---------------------------------------------------------------- a5 --
+  int64_t Dtot = 0;
+  if (N > 0 && !(o.flags & W1_COUNT_ONLY)) {
+    uint32_t* dc = need<uint32_t>(c, c.dcnt, N);
+    launch_diag_count((const uint32_t*)c.cpair.p, (const int32_t*)c.ca.p, (const int32_t*)c.cb.p, N, dc, st);
+    uint32_t* dp = scan_flags(c, dc, N, c.dpos);
+    Dtot = (int64_t)total_of(c, dc, dp, N);
+    uint32_t* ds = need<uint32_t>(c, c.dsrc, Dtot);
+    uint32_t* dd = need<uint32_t>(c, c.ddst, Dtot);
+    int32_t* dco = need<int32_t>(c, c.dcost, Dtot);
+    int64_t* sup = need<int64_t>(c, c.supply, N + 2 * K);
+    launch_diag_fill((const uint32_t*)c.cpair.p, (const int2*)c.cij.p, (const int32_t*)c.ca.p, (const int32_t*)c.cb.p,
+                     N, dp, P, ds, dd, dco, sup, st);
+    check(c, hipGetLastError());
+  }
+  record(c, 6);
+  check(c, hipStreamSynchronize(st));
+  int32_t herr = 0;
+  readback(c, derr, &herr, 1);
+  if (timed) {
+    float a = 0, b2 = 0, d = 0;
+    (void)hipEventElapsedTime(&a, c.kev[0], c.kev[1]);
+    (void)hipEventElapsedTime(&b2, c.kev[1], c.kev[2]);
+    if (emitted) (void)hipEventElapsedTime(&d, c.kev[3], c.ev[5]);
+    c.kms[0] = a;
+    c.kms[1] = b2;
+    c.kms[2] = d;
+  }
+  if (herr) throw StageError{W1_EOVERFLOW};
+
+  // ------------------------------------------------------------ results --
+  std::vector<int32_t> h_err = fetch_pairs(c, P.err, K), h_locA = fetch_pairs(c, P.locA, K),
+                       h_locB = fetch_pairs(c, P.locB, K), h_e = fetch_pairs(c, P.e, K),
+                       h_nc = fetch_pairs(c, P.ncells, K), h_nd = fetch_pairs(c, P.ndiag, K),
+                       h_FA = fetch_pairs(c, P.FA, K), h_FB = fetch_pairs(c, P.FB, K);
+  std::vector<int64_t> h_nA = fetch_pairs(c, P.nA, K), h_nB = fetch_pairs(c, P.nB, K),
+                       h_cs = fetch_pairs(c, P.cell_start, K), h_ds = fetch_pairs(c, P.diag_start, K);
+  std::vector<uint64_t> h_sA = fetch_pairs(c, P.sumA, K), h_sB = fetch_pairs(c, P.sumB, K),
+                        h_np = fetch_pairs(c, P.npairs, K), h_ps = fetch_pairs(c, P.pair_start, K);
+  std::vector<double> h_L = fetch_pairs(c, P.L, K);
+  float tms[8] = {0};
+  for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&tms[i], c.ev[i], c.ev[i + 1]);
+  c.h_cell_start.assign(h_cs.begin(), h_cs.end());
+  c.h_ncells.assign(h_nc.begin(), h_nc.end());
+  c.h_pair_start.assign(h_ps.begin(), h_ps.end());
+  c.h_npairs.assign(h_np.begin(), h_np.end());
+  c.h_diag_start.assign(h_ds.begin(), h_ds.end());
+  c.h_ndiag.assign(h_nd.begin(), h_nd.end());
+  c.network_valid = !(o.flags & W1_COUNT_ONLY);
+  int64_t loc_off = 0;
+  for (int64_t p = 0; p < K; ++p) {
+    w1_result& r = res[p];
+    std::memset(&r, 0, sizeof(r));
+    r.s = s;
+    r.status = h_err[(size_t)p];
+    r.flow_cost = -1;
+    r.n_a = h_nA[(size_t)p];
+    r.n_b = h_nB[(size_t)p];
+    r.n_points = r.n_a + r.n_b;
+    r.n_locations = (int64_t)h_locA[(size_t)p] + h_locB[(size_t)p];
+    r.lower_bound = h_L[(size_t)p];
+    r.grid_exp = h_e[(size_t)p];
+    r.grid = std::ldexp(1.0, r.grid_exp);
+    r.n_cells = h_nc[(size_t)p];
+    r.n_pairs = (int64_t)h_np[(size_t)p];
+    r.n_diag = (o.flags & W1_COUNT_ONLY) ? 0 : h_nd[(size_t)p];
+    r.n_arcs = 2 * r.n_pairs + r.n_diag;
+    r.rwmd_sum_a = (int64_t)h_sA[(size_t)p];
+    r.rwmd_sum_b = (int64_t)h_sB[(size_t)p];
+    r.rwmd_shift_a = h_FA[(size_t)p];
+    r.rwmd_shift_b = h_FB[(size_t)p];
+    for (int i = 0; i < 6; ++i) r.t_ms[i] = tms[i];
+    if (r.status == 0 && r.n_points == 0) {
+      r.w1 = r.w1_paper = 0.0;
+      r.flow_cost = 0;
+      r.flow_solved = 1;
+    }
+    // stage intermediates
+    if ((o.flags & W1_KEEP_STAGES) && r.status == 0 && r.n_locations > 0) {
+      const int64_t nl = r.n_locations;
+      r.loc_b = (double*)std::malloc((size_t)nl * 8);
+      r.loc_d = (double*)std::malloc((size_t)nl * 8);
+      r.loc_t = (double*)std::malloc((size_t)nl * 8);
+      r.loc_w = (int32_t*)std::malloc((size_t)nl * 4);
+      if (!r.loc_b || !r.loc_d || !r.loc_t || !r.loc_w) throw StageError{W1_ENOMEM};
+      readback(c, (const double*)c.lb.p + loc_off, r.loc_b, nl);
+      readback(c, (const double*)c.ld.p + loc_off, r.loc_d, nl);
+      readback(c, (const double*)c.lt.p + loc_off, r.loc_t, nl);
+      readback(c, (const int32_t*)c.lw.p + loc_off, r.loc_w, nl);
+      if (K == 1 && N >= 2) {
+        const int64_t ni = N - 1;
+        std::vector<int4> aux((size_t)ni), box((size_t)ni);
+        readback(c, (const int4*)c.iaux.p, aux.data(), ni);
+        readback(c, (const int4*)c.ibox.p, box.data(), ni);
+        r.node_lo = (int32_t*)std::malloc((size_t)ni * 4);
+        r.node_hi = (int32_t*)std::malloc((size_t)ni * 4);
+        r.node_left = (int32_t*)std::malloc((size_t)ni * 4);
+        r.node_right = (int32_t*)std::malloc((size_t)ni * 4);
+        r.node_box = (int32_t*)std::malloc((size_t)ni * 16);
+        if (!r.node_lo || !r.node_hi || !r.node_left || !r.node_right || !r.node_box) throw StageError{W1_ENOMEM};
+        for (int64_t q = 0; q < ni; ++q) {
+          r.node_left[q] = aux[(size_t)q].x;
+          r.node_right[q] = aux[(size_t)q].y;
+          r.node_lo[q] = aux[(size_t)q].z;
+          r.node_hi[q] = aux[(size_t)q].w;
+          std::memcpy(r.node_box + 4 * q, &box[(size_t)q], 16);
+        }
+      }
+    }
+    loc_off += (int64_t)h_locA[(size_t)p] + h_locB[(size_t)p];
+  }
+  (void)Ptot;
+  (void)Dtot;
+  return W1_OK;
+}
+
+// Copy one pair's network to the host (arrays owned by the result).
+void copy_network(Ctx& c, int64_t p, w1_result& r) {
+  const int64_t nc = c.h_ncells[(size_t)p], np = c.h_npairs[(size_t)p], nd = c.h_ndiag[(size_t)p];
+  const int64_t cs = c.h_cell_start[(size_t)p], ps = c.h_pair_start[(size_t)p], ds = c.h_diag_start[(size_t)p];
+  r.cell_i = (int32_t*)std::malloc((size_t)std::max<int64_t>(nc, 1) * 4);
+  r.cell_j = (int32_t*)std::malloc((size_t)std::max<int64_t>(nc, 1) * 4);
+  r.cell_ca = (int32_t*)std::malloc((size_t)std::max<int64_t>(nc, 1) * 4);
+  r.cell_cb = (int32_t*)std::malloc((size_t)std::max<int64_t>(nc, 1) * 4);
+  r.supply = (int64_t*)std::malloc((size_t)(nc + 2) * 8);
+  r.pair_u = (uint32_t*)std::malloc((size_t)std::max<int64_t>(np, 1) * 4);
+  r.pair_v = (uint32_t*)std::malloc((size_t)std::max<int64_t>(np, 1) * 4);
+  r.pair_cost = (int32_t*)std::malloc((size_t)std::max<int64_t>(np, 1) * 4);
+  r.diag_src = (uint32_t*)std::malloc((size_t)std::max<int64_t>(nd, 1) * 4);
+  r.diag_dst = (uint32_t*)std::malloc((size_t)std::max<int64_t>(nd, 1) * 4);
+  r.diag_cost = (int32_t*)std::malloc((size_t)std::max<int64_t>(nd, 1) * 4);
+  if (!r.cell_i || !r.cell_j || !r.cell_ca || !r.cell_cb || !r.supply || !r.pair_u || !r.pair_v || !r.pair_cost ||
+      !r.diag_src || !r.diag_dst || !r.diag_cost)
+    throw StageError{W1_ENOMEM};
+  if (nc > 0) {
+    std::vector<int2> ij((size_t)nc);
+    readback(c, (const int2*)c.cij.p + cs, ij.data(), nc);
+    for (int64_t q = 0; q < nc; ++q) {
+      r.cell_i[q] = ij[(size_t)q].x;
+      r.cell_j[q] = ij[(size_t)q].y;
+    }
+    readback(c, (const int32_t*)c.ca.p + cs, r.cell_ca, nc);
+    readback(c, (const int32_t*)c.cb.p + cs, r.cell_cb, nc);
+    readback(c, (const int64_t*)c.supply.p + cs + 2 * p, r.supply, nc + 2);
+  } else {
+    r.supply[0] = r.supply[1] = 0;
+  }
+  if (np > 0) {
+    readback(c, (const uint32_t*)c.pu.p + ps, r.pair_u, np);
+    readback(c, (const uint32_t*)c.pv.p + ps, r.pair_v, np);
+    readback(c, (const int32_t*)c.pc.p + ps, r.pair_cost, np);
+  }
+  if (nd > 0) {
+    readback(c, (const uint32_t*)c.dsrc.p + ds, r.diag_src, nd);
+    readback(c, (const uint32_t*)c.ddst.p + ds, r.diag_dst, nd);
+    readback(c, (const int32_t*)c.dcost.p + ds, r.diag_cost, nd);
+  }
+}
+
+void free_network(w1_result& r) {
+  void* ptrs[] = {r.cell_i, r.cell_j, r.cell_ca, r.cell_cb, r.supply, r.pair_u, r.pair_v, r.pair_cost,
+                  r.diag_src, r.diag_dst, r.diag_cost};
+  for (void* q : ptrs) std::free(q);
+  r.cell_i = r.cell_j = r.cell_ca = r.cell_cb = nullptr;
+  r.supply = nullptr;
+  r.pair_u = r.pair_v = nullptr;
+  r.pair_cost = nullptr;
+  r.diag_src = r.diag_dst = nullptr;
+  r.diag_cost = nullptr;
+}
+
+// Host flow of one pair from its host network copy.
+void solve_flow(w1_result& r, int64_t pivot_cap) {
+  const int64_t nc = r.n_cells, np = r.n_pairs, nd = r.n_diag;
+  const int64_t m = 2 * np + nd;
+  std::vector<uint32_t> src((size_t)m), dst((size_t)m);
+  std::vector<int32_t> cost((size_t)m);
+  for (int64_t k = 0; k < np; ++k) {
+    src[(size_t)(2 * k)] = r.pair_u[k];
+    dst[(size_t)(2 * k)] = r.pair_v[k];
+    src[(size_t)(2 * k + 1)] = r.pair_v[k];
+    dst[(size_t)(2 * k + 1)] = r.pair_u[k];
+    cost[(size_t)(2 * k)] = cost[(size_t)(2 * k + 1)] = r.pair_cost[k];
+  }
+  for (int64_t k = 0; k < nd; ++k) {
+    src[(size_t)(2 * np + k)] = r.diag_src[k];
+    dst[(size_t)(2 * np + k)] = r.diag_dst[k];
+    cost[(size_t)(2 * np + k)] = r.diag_cost[k];
+  }
+  FlowResult fr{};
+  const int rc = network_simplex(nc + 2, m, src.data(), dst.data(), cost.data(), r.supply, pivot_cap, &fr);
+  if (rc != 0) {
+    r.status = rc == -3 ? W1_ENOMEM : W1_EINVAL;
+    return;
+  }
+  r.flow_cost = fr.cost;
+  r.pivots = fr.pivots;
+  r.status = fr.status ? W1_STALLED : W1_OPTIMAL;
+  r.flow_solved = 1;
+  r.w1 = std::ldexp((double)(fr.cost + r.n_points), r.grid_exp - 1);
+  r.w1_paper = std::ldexp((double)fr.cost, r.grid_exp - 1);
+}
+
+int entry(Ctx* c, const w1_pd* a, const w1_pd* b, int64_t K, const w1_params* params, void* stream, w1_result* out,
+          double* L_only) {
+  if (!c || !a || !b || K <= 0 || (!out && !L_only)) return W1_EINVAL;
+  Opts o;
+  if (params) {
+    o.eps = params->eps;
+    o.kappa = params->cond_frac > 0 ? params->cond_frac : 0.1;
+    o.s = params->s_override;
+    o.flags = params->flags;
+    o.pivot_cap = params->pivot_cap;
+    if (params->s_override != 0 && params->s_override < 3) return W1_EINVAL;
+  }
+  if (!(o.eps > 0.0 && o.eps <= 1.0) || !(o.kappa > 0.0 && o.kappa < 0.5)) return W1_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return W1_EHIP;
+  try {
+    int rc = run(*c, a, b, K, o, (hipStream_t)stream, out, L_only);
+    if (rc != W1_OK || L_only) return rc;
+    const bool want_flow = !(o.flags & (W1_COUNT_ONLY | W1_NO_FLOW));
+    const bool keep = (o.flags & W1_KEEP_NETWORK) != 0;
+    if (want_flow || keep) {
+      auto t0 = std::chrono::steady_clock::now();
+      for (int64_t p = 0; p < K; ++p)
+        if (out[p].status == 0 && out[p].n_points > 0) copy_network(*c, p, out[p]);
+      auto t1 = std::chrono::steady_clock::now();
+      double d2h = std::chrono::duration<double, std::milli>(t1 - t0).count();
+      if (want_flow) {
+        unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        unsigned nt = (unsigned)std::min<int64_t>(K, std::min(hw, 16u));
+        std::atomic<int64_t> next{0};
+        auto worker = [&]() {
+          for (;;) {
+            int64_t p = next.fetch_add(1);
+            if (p >= K) break;
+            if (out[p].status == 0 && out[p].n_points > 0) solve_flow(out[p], o.pivot_cap);
+          }
+        };
+        std::vector<std::thread> th;
+        for (unsigned i = 1; i < nt; ++i) th.emplace_back(worker);
+        worker();
+        for (auto& t : th) t.join();
+      }
+      auto t2 = std::chrono::steady_clock::now();
+      double fl = std::chrono::duration<double, std::milli>(t2 - t1).count();
+      for (int64_t p = 0; p < K; ++p) {
+        out[p].t_ms[W1_T_D2H] = d2h;
+        out[p].t_ms[W1_T_FLOW] = fl;
+        if (!keep) free_network(out[p]);
+      }
+    }
+    return W1_OK;
+  } catch (const StageError& e) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    if (out)
+      for (int64_t p = 0; p < K; ++p) {
+        w1_result_free(&out[p]);
+        std::memset(&out[p], 0, sizeof(w1_result));
+        out[p].status = e.code;
+      }
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    return W1_ENOMEM;
+  }
+}
+
+}  // namespace
+}  // namespace w1
+
+// =========================================================================== ABI
+using namespace w1;
+
+struct w1_ctx : Ctx {};
+
+extern "C" {
+
+int w1_ctx_create(int device, w1_ctx** out) {
+  if (!out) return W1_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return W1_ENODEV;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return W1_ENODEV;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return W1_ENODEV;
+  w1_ctx* c = new (std::nothrow) w1_ctx();
+  if (!c) return W1_ENOMEM;
+  c->device = device;
+  c->num_cus = prop.multiProcessorCount;
+  c->trace = std::getenv("W1_TRACE") != nullptr;
+  if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void**)&c->hpin, 4096, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return W1_EHIP;
+  }
+  for (int i = 0; i < 4; ++i)
+    if (hipEventCreate(&c->kev[i]) != hipSuccess) {
+      delete c;
+      return W1_EHIP;
+    }
+  for (int i = 0; i < 8; ++i)
+    if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+      delete c;
+      return W1_EHIP;
+    }
+  if (const char* e = std::getenv("W1_WSPD_TUNING")) {
+    int a, b2, d, f;
+    if (std::sscanf(e, "%d,%d,%d,%d", &a, &b2, &d, &f) == 4 && a >= 4 && a <= 64 && b2 >= 1 && d >= 1 && f >= 1)
+      c->tun = WspdTuning{a, b2, d, f};
+  }
+  *out = c;
+  return W1_OK;
+}
+
+int w1_ctx_destroy(w1_ctx* c) {
+  if (!c) return W1_EINVAL;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (DBuf* b : c->all)
+    if (b->p) (void)hipFree(b->p);
+  for (int i = 0; i < 8; ++i) (void)hipEventDestroy(c->ev[i]);
+  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(c->kev[i]);
+  if (c->hpin) (void)hipHostFree(c->hpin);
+  delete c;
+  return W1_OK;
+}
+
+int w1_ctx_hip_error(const w1_ctx* c) { return c ? c->hip_err : 0; }
+
+int w1_approx(w1_ctx* c, const w1_pd* a, const w1_pd* b, const w1_params* params, void* stream, w1_result* out) {
+  return entry(c, a, b, 1, params, stream, out, nullptr);
+}
+
+int w1_approx_batch(w1_ctx* c, const w1_pd* a, const w1_pd* b, int64_t k, const w1_params* params, void* stream,
+                    w1_result* out) {
+  return entry(c, a, b, k, params, stream, out, nullptr);
+}
+
+int w1_rwmd(w1_ctx* c, const w1_pd* a, const w1_pd* b, int64_t k, uint32_t flags, void* stream, double* L_out) {
+  if (!L_out) return W1_EINVAL;
+  w1_params p{0.1, 0.1, 0, flags, 0};
+  return entry(c, a, b, k, &p, stream, nullptr, L_out);
+}
+
+int w1_device_network_get(w1_ctx* c, int64_t k, w1_device_network* out) {
+  if (!c || !out || k < 0 || k >= c->K || !c->network_valid) return W1_EINVAL;
+  const int64_t cs = c->h_cell_start[(size_t)k], ps = c->h_pair_start[(size_t)k], ds = c->h_diag_start[(size_t)k];
+  out->n_cells = c->h_ncells[(size_t)k];
+  out->n_pairs = c->h_npairs[(size_t)k];
+  out->n_diag = c->h_ndiag[(size_t)k];
+  out->cell_ij = (const int32_t*)c->cij.p + 2 * cs;
+  out->cell_ca = (const int32_t*)c->ca.p + cs;
+  out->cell_cb = (const int32_t*)c->cb.p + cs;
+  out->supply = (const int64_t*)c->supply.p + cs + 2 * k;
+  out->pair_u = (const uint32_t*)c->pu.p + ps;
+  out->pair_v = (const uint32_t*)c->pv.p + ps;
+  out->pair_cost = (const int32_t*)c->pc.p + ps;
+  out->diag_src = (const uint32_t*)c->dsrc.p + ds;
+  out->diag_dst = (const uint32_t*)c->ddst.p + ds;
+  out->diag_cost = (const int32_t*)c->dcost.p + ds;
+  return W1_OK;
+}
+
+int w1_ctx_last_kernel_times(const w1_ctx* c, double* ms, int n) {
+  if (!c || !ms || n < 4) return W1_EINVAL;
+  for (int i = 0; i < 4; ++i) ms[i] = c->kms[i];
+  return W1_OK;
+}
+
+int w1_flow_solve(int64_t n_nodes, int64_t m, const uint32_t* src, const uint32_t* dst, const int32_t* cost,
+                  const int64_t* supply, int64_t pivot_cap, int64_t* cost_out, int64_t* flow_out, int64_t* pot_out,
+                  int64_t* pivots_out, int32_t* status_out) {
+  if (n_nodes < 0 || m < 0 || (m > 0 && (!src || !dst || !cost)) || (n_nodes > 0 && !supply) || !cost_out)
+    return W1_EINVAL;
+  FlowResult fr{};
+  fr.flow = flow_out;
+  fr.pot = pot_out;
+  int rc;
+  try {
+    rc = network_simplex(n_nodes, m, src, dst, cost, supply, pivot_cap, &fr);
+  } catch (const std::bad_alloc&) {
+    return W1_ENOMEM;
+  }
+  if (rc == -3) return W1_ENOMEM;
+  if (rc != 0) return W1_EINVAL;
+  *cost_out = fr.cost;
+  if (pivots_out) *pivots_out = fr.pivots;
+  if (status_out) *status_out = fr.status ? W1_STALLED : W1_OPTIMAL;
+  return W1_OK;
+}
+
+int w1_separation_for_eps(double eps, double kappa) {
+  if (kappa <= 0) kappa = 0.1;
+  if (!(eps > 0.0 && eps <= 1.0) || !(kappa < 0.5)) return W1_EINVAL;
+  return separation(eps, kappa);
+}
+
+void w1_result_free(w1_result* r) {
+  if (!r) return;
+  free_network(*r);
+  void* ptrs[] = {r->loc_b, r->loc_d, r->loc_w, r->loc_t, r->node_lo, r->node_hi, r->node_left, r->node_right,
+                  r->node_box};
+  for (void* q : ptrs) std::free(q);
+  r->loc_b = r->loc_d = r->loc_t = nullptr;
+  r->loc_w = nullptr;
+  r->node_lo = r->node_hi = r->node_left = r->node_right = r->node_box = nullptr;
+}
+
+const char* w1_strerror(int code) {
+  switch (code) {
+    case W1_OK: return "ok";
+    case W1_EINVAL: return "invalid argument or diagram point";
+    case W1_ERANGE: return "grid extent or coordinate range exceeded";
+    case W1_ENOMEM: return "out of memory";
+    case W1_EHIP: return "HIP runtime error";
+    case W1_EOVERFLOW: return "internal work list capacity exceeded";
+    case W1_ENODEV: return "no gfx950 device";
+  }
+  return "unknown error";
+}
+
+}  // extern "C"

@@ -1,0 +1,335 @@
+// s-WSPD of the Morton radix tree (Alg. 4-6: for every internal node w,
+// search the pair (w.left, w.right); output a pair when it is s-well-
+// separated, otherwise split the node with the longer box side, ties
+// splitting the second node).
+//
+// GPU organisation (differs from the paper's one-thread-per-internal-node
+// scheme, whose work per thread ranges from one pair to millions):
+//   1. expansion rounds: the root searches (w.left, w.right) of all internal
+//      nodes form a work list; items whose subtrees are large are expanded
+//      breadth-first, one level per round, until every item is either
+//      separated or small (bounded subtree height sum and size product);
+//      each round is compacted with scans so the item order is deterministic;
+//   2. the final items are sorted by their first representative (Morton
+//      order) and cut into chunks that never straddle two diagram pairs;
+//   3. a persistent count pass and an identical emit pass: each wave takes a
+//      chunk, its 64 lanes run depth-first searches with per-lane LDS
+//      stacks, idle lanes refill from the chunk, and the pairs found in one
+//      step are written contiguously at the wave's cursor (ballot + popcount).
+//      The schedule inside a chunk depends only on the chunk, so both passes
+//      see the same order and the output is deterministic.
+//   Chunks are handed out from eight contiguous ranges, one per XCD
+//   (workgroup b runs on XCD b mod 8), so each XCD's L2 holds a compact part
+//   of the tree; an XCD that runs dry takes chunks from the other ranges.
+#include "common.h"
+#include "kernels.h"
+
+namespace w1 {
+
+namespace {
+
+__device__ inline int4 node_box(const TreeView& T, int32_t r) {
+  if (r >= 0) return T.ibox[r];
+  const int2 c = T.cij[~r];
+  return make_int4(c.x, c.y, c.x, c.y);
+}
+__device__ inline int32_t node_rep(const TreeView& T, int32_t r) { return r >= 0 ? T.iaux[r].z : ~r; }
+__device__ inline int32_t node_height(const TreeView& T, int32_t r) { return r >= 0 ? T.iheight[r] : 0; }
+__device__ inline int64_t node_size(const TreeView& T, int32_t r) {
+  if (r < 0) return 1;
+  const int4 a = T.iaux[r];
+  return (int64_t)a.w - a.z + 1;
+}
+__device__ inline int32_t box_diam(int4 b) { return max(b.z - b.x, b.w - b.y); }
+__device__ inline bool separated(int4 a, int4 b, int s) {
+  const int gi = max(a.x - b.z, b.x - a.z);
+  const int gj = max(a.y - b.w, b.y - a.w);
+  const int dist = max(0, max(gi, gj));
+  return (int64_t)dist >= (int64_t)s * (int64_t)max(box_diam(a), box_diam(b));
+}
+
+__global__ void k_roots_flags(TreeView T, uint32_t* __restrict__ flag) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= T.N - 1) return;
+  const int4 a = T.iaux[w];
+  flag[w] = T.cpair[a.z] == T.cpair[a.w] ? 1u : 0u;
+}
+
+__global__ void k_roots_fill(TreeView T, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos,
+                             int2* __restrict__ items) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= T.N - 1 || !flag[w]) return;
+  const int4 a = T.iaux[w];
+  items[pos[w]] = make_int2(a.x, a.y);
+}
+
+// Item kinds of an expansion round: kept (final or separated) -> low word
+// count 1; expanded -> high word count 2.
+__global__ void k_classify(TreeView T, const int2* __restrict__ items, int64_t f, int s, int stack_depth,
+                           int64_t work_cap, uint64_t* __restrict__ cnt) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= f) return;
+  const int2 it = items[x];
+  const bool small = node_height(T, it.x) + node_height(T, it.y) <= stack_depth - 1 &&
+                     node_size(T, it.x) * node_size(T, it.y) <= work_cap;
+  const bool keep = small || separated(node_box(T, it.x), node_box(T, it.y), s);
+  cnt[x] = keep ? 1ull : (2ull << 32);
+}
+
+__global__ void k_scatter(TreeView T, const int2* __restrict__ items, int64_t f, const uint64_t* __restrict__ cnt,
+                          const uint64_t* __restrict__ pos, int2* __restrict__ out_items, int64_t out_base,
+                          int2* __restrict__ next) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= f) return;
+  const int2 it = items[x];
+  const uint64_t p = pos[x];
+  if (cnt[x] == 1ull) {
+    out_items[out_base + (int64_t)(uint32_t)p] = it;
+    return;
+  }
+  const int64_t q = (int64_t)(p >> 32);
+  const int4 bu = node_box(T, it.x), bv = node_box(T, it.y);
+  if (box_diam(bu) > box_diam(bv)) {
+    const int4 a = T.iaux[it.x];
+    next[q] = make_int2(a.x, it.y);
+    next[q + 1] = make_int2(a.y, it.y);
+  } else {
+    const int4 a = T.iaux[it.y];
+    next[q] = make_int2(it.x, a.x);
+    next[q + 1] = make_int2(it.x, a.y);
+  }
+}
+
+// Canonical item key (rep U, rep V): depends only on the cells, not on node
+// numbering, so a pair's work list -- and hence its output order -- is the
+// same alone or inside a batch.  Keys are unique: two items cannot share
+// both representatives because the WSPD covers every cell pair once.
+__global__ void k_item_keys(TreeView T, const int2* __restrict__ items, int64_t m, uint64_t* __restrict__ keys) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < m)
+    keys[x] = ((uint64_t)(uint32_t)node_rep(T, items[x].x) << 32) | (uint64_t)(uint32_t)node_rep(T, items[x].y);
+}
+
+__global__ void k_gather_items(const int2* __restrict__ src, const uint32_t* __restrict__ perm, int2* __restrict__ dst,
+                               int64_t m) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < m) dst[x] = src[perm[x]];
+}
+
+__global__ void k_item_pairs(TreeView T, const int2* __restrict__ items, int64_t m, int32_t* __restrict__ ipp) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t key = ~0u;
+  int32_t one = 0;
+  if (x < m) {
+    key = T.cpair[node_rep(T, items[x].x)];
+    one = 1;
+  }
+  if (wave_seg_reduce(key, one, [](int32_t a, int32_t b) { return a + b; })) atomicAdd(&ipp[key], one);
+}
+
+__global__ void k_chunk_heads(TreeView T, const int2* __restrict__ items, int64_t m, const int64_t* __restrict__ item_start,
+                              int chunk, uint32_t* __restrict__ head) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= m) return;
+  const uint32_t p = T.cpair[node_rep(T, items[x].x)];
+  head[x] = ((x - item_start[p]) % chunk) == 0 ? 1u : 0u;
+}
+
+__global__ void k_chunk_fill(TreeView T, const int2* __restrict__ items, int64_t m, const int64_t* __restrict__ item_start,
+                             const int32_t* __restrict__ ipp, const uint32_t* __restrict__ head,
+                             const uint32_t* __restrict__ cid, int chunk, int32_t* __restrict__ chunk_first,
+                             int32_t* __restrict__ chunk_end, int32_t* __restrict__ chunk_pair) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= m || !head[x]) return;
+  const uint32_t p = T.cpair[node_rep(T, items[x].x)];
+  const uint32_t c = cid[x];
+  const int64_t pend = item_start[p] + ipp[p];
+  chunk_first[c] = (int32_t)x;
+  chunk_end[c] = (int32_t)(x + chunk < pend ? x + chunk : pend);
+  chunk_pair[c] = (int32_t)p;
+}
+
+template <bool EMIT>
+__global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict__ items,
+                                              const int32_t* __restrict__ chunk_first, const int32_t* __restrict__ chunk_end,
+                                              const int32_t* __restrict__ chunk_pair, const int32_t* __restrict__ xcd_range,
+                                              uint32_t* __restrict__ xcd_ctr, int s, int stack_depth, int64_t step_cap,
+                                              uint64_t* __restrict__ chunk_cnt, const uint64_t* __restrict__ chunk_off,
+                                              const int64_t* __restrict__ cell_start, uint32_t* __restrict__ pu,
+                                              uint32_t* __restrict__ pv, int32_t* __restrict__ pc, int32_t* __restrict__ err) {
+  extern __shared__ int2 s_stack[];
+  const int wave = threadIdx.x / WAVE, lane = lane_id();
+  int2* stk = s_stack + (size_t)wave * stack_depth * WAVE;
+  const uint64_t below = lanes_below();
+  const int xcd = blockIdx.x & 7;
+  // Loop control (chunk index, item cursor, output cursor) is kept in wave-
+  // uniform scalars (readfirstlane) so every loop exit is a uniform branch.
+  for (int probe = 0; probe < 8; ++probe) {
+    const int xr = (xcd + probe) & 7;
+    const int r0 = xcd_range[xr], r1 = xcd_range[xr + 1];
+    for (;;) {
+      // every lane takes part in the fetch (lane 0 adds 1, the others 0), so
+      // there is no lane-divergent region in the chunk loop
+      const uint32_t t = atomicAdd(&xcd_ctr[xr], lane == 0 ? 1u : 0u);
+      const int k = (int)__builtin_amdgcn_readfirstlane(t) + r0;
+      if (k >= r1) break;
+      int next = __builtin_amdgcn_readfirstlane(chunk_first[k]);
+      const int end = __builtin_amdgcn_readfirstlane(chunk_end[k]);
+      const int64_t cs = EMIT ? cell_start[chunk_pair[k]] : 0;
+      const uint64_t obase = EMIT ? chunk_off[k] : 0;
+      uint64_t cursor = 0;
+      bool has = false, ku = false, kv = false;
+      int sp = 0;
+      int32_t U = 0, V = 0;
+      int4 bu = make_int4(0, 0, 0, 0), bv = bu;
+      bool runaway = false, overflow = false;
+      for (int64_t step = 0;; ++step) {
+        if (step > step_cap) {  // beyond any chunk's possible work: give up, report
+          runaway = true;
+          break;
+        }
+        if (!has && sp > 0) {
+          --sp;
+          const int2 q = stk[sp * WAVE + lane];
+          U = q.x;
+          V = q.y;
+          has = true;
+          ku = kv = false;
+        }
+        const uint64_t need = __ballot(!has);
+        const int avail = end - next;
+        if (!has) {
+          const int r = __popcll(need & below);
+          if (r < avail) {
+            const int2 q = items[next + r];
+            U = q.x;
+            V = q.y;
+            has = true;
+            ku = kv = false;
+          }
+        }
+        const int took = __popcll(need);
+        next += took < avail ? took : (avail > 0 ? avail : 0);
+        if (__ballot(has) == 0) break;
+        bool emit = false;
+        if (has) {
+          if (!ku) { bu = node_box(T, U); ku = true; }
+          if (!kv) { bv = node_box(T, V); kv = true; }
+          if (separated(bu, bv, s)) {
+            emit = true;
+          } else {
+            int2 second;
+            if (box_diam(bu) > box_diam(bv)) {
+              const int4 a = T.iaux[U];
+              second = make_int2(a.y, V);
+              U = a.x;
+              ku = false;
+            } else {
+              const int4 a = T.iaux[V];
+              second = make_int2(U, a.y);
+              V = a.x;
+              kv = false;
+            }
+            if (sp < stack_depth) {
+              stk[sp * WAVE + lane] = second;
+              ++sp;
+            } else {
+              overflow = true;
+            }
+          }
+        }
+        const uint64_t em = __ballot(emit);
+        if (EMIT && emit) {
+          const int32_t ru = node_rep(T, U), rv = node_rep(T, V);
+          const int2 cu = T.cij[ru], cv = T.cij[rv];
+          const uint64_t pos = obase + cursor + (uint64_t)__popcll(em & below);
+          pu[pos] = (uint32_t)(ru - cs);
+          pv[pos] = (uint32_t)(rv - cs);
+          pc[pos] = 2 * max(abs(cu.x - cv.x), abs(cu.y - cv.y));
+        }
+        if (emit) has = false;
+        cursor += (uint64_t)__popcll(em);
+      }
+      const bool bad = runaway || __ballot(overflow) != 0;
+      if (bad) atomicOr(err, 1);
+      if (!EMIT) chunk_cnt[k] = cursor;  // same value from every lane
+    }
+  }
+}
+
+__global__ void k_pair_totals(const uint64_t* __restrict__ chunk_cnt, const uint64_t* __restrict__ chunk_off,
+                              const int32_t* __restrict__ chunk_pair, const int32_t* __restrict__ chunk_first,
+                              const int64_t* __restrict__ item_start, int64_t nchunks, uint64_t* __restrict__ npairs,
+                              uint64_t* __restrict__ pair_start) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nchunks) return;
+  const int32_t p = chunk_pair[c];
+  atomicAdd((unsigned long long*)&npairs[p], (unsigned long long)chunk_cnt[c]);
+  if (chunk_first[c] == item_start[p]) pair_start[p] = chunk_off[c];
+}
+
+inline unsigned blocks(int64_t n, int bs = 256) { return (unsigned)(n > 0 ? ceil_div(n, bs) : 1); }
+
+}  // namespace
+
+#define LAUNCH(kern, n, ...) \
+  do { if ((n) > 0) hipLaunchKernelGGL(kern, dim3(blocks(n)), dim3(256), 0, st, __VA_ARGS__); } while (0)
+
+void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st) { LAUNCH(k_roots_flags, T.N - 1, T, flag); }
+void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st) {
+  LAUNCH(k_roots_fill, T.N - 1, T, flag, pos, items);
+}
+void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s, const WspdTuning& tun, uint64_t* cnt,
+                          hipStream_t st) {
+  LAUNCH(k_classify, f, T, items, f, s, tun.stack_depth, (int64_t)tun.work_cap, cnt);
+}
+void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const uint64_t* cnt, const uint64_t* pos,
+                         int2* out_items, int64_t out_base, int2* next, hipStream_t st) {
+  LAUNCH(k_scatter, f, T, items, f, cnt, pos, out_items, out_base, next);
+}
+void launch_item_keys(const TreeView& T, const int2* items, int64_t m, uint64_t* keys, hipStream_t st) {
+  LAUNCH(k_item_keys, m, T, items, m, keys);
+}
+void launch_gather_items(const int2* src, const uint32_t* perm, int2* dst, int64_t m, hipStream_t st) {
+  LAUNCH(k_gather_items, m, src, perm, dst, m);
+}
+void launch_item_pairs(const TreeView& T, const int2* items, int64_t m, int32_t* items_per_pair, hipStream_t st) {
+  LAUNCH(k_item_pairs, m, T, items, m, items_per_pair);
+}
+void launch_chunk_heads(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start, int chunk,
+                        uint32_t* head, hipStream_t st) {
+  LAUNCH(k_chunk_heads, m, T, items, m, item_start, chunk, head);
+}
+void launch_chunk_fill(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start,
+                       const int32_t* items_per_pair, const uint32_t* head, const uint32_t* cid, int chunk,
+                       int32_t* chunk_first, int32_t* chunk_end, int32_t* chunk_pair, hipStream_t st) {
+  LAUNCH(k_chunk_fill, m, T, items, m, item_start, items_per_pair, head, cid, chunk, chunk_first, chunk_end, chunk_pair);
+}
+void launch_wspd_pass(bool emit, const TreeView& T, const int2* items, const int32_t* chunk_first,
+                      const int32_t* chunk_end, const int32_t* chunk_pair, int64_t nchunks, const int32_t* xcd_range,
+                      uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
+                      const int64_t* cell_start, uint32_t* pu, uint32_t* pv, int32_t* pc, int32_t* err,
+                      int num_cus, hipStream_t st) {
+  if (nchunks <= 0) return;
+  int64_t grid = (int64_t)num_cus * tun.blocks_per_cu;
+  grid = ((grid + 7) / 8) * 8;
+  const size_t lds = (size_t)4 * tun.stack_depth * WAVE * sizeof(int2);
+  // A chunk's items each have at most work_cap leaf pairs, hence fewer than
+  // 2 work_cap search steps; every wave step advances at least one lane.
+  const int64_t step_cap = (int64_t)tun.chunk_items * (2 * (int64_t)tun.work_cap + 2) + 1024;
+  if (emit)
+    hipLaunchKernelGGL(k_wspd<true>, dim3((unsigned)grid), dim3(256), lds, st, T, items, chunk_first, chunk_end,
+                       chunk_pair, xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, cell_start, pu, pv, pc,
+                       err);
+  else
+    hipLaunchKernelGGL(k_wspd<false>, dim3((unsigned)grid), dim3(256), lds, st, T, items, chunk_first, chunk_end,
+                       chunk_pair, xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, cell_start, pu, pv, pc,
+                       err);
+}
+void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
+                        const int32_t* chunk_first, const int64_t* item_start, int64_t nchunks, uint64_t* npairs,
+                        uint64_t* pair_start, hipStream_t st) {
+  LAUNCH(k_pair_totals, nchunks, chunk_cnt, chunk_off, chunk_pair, chunk_first, item_start, nchunks, npairs, pair_start);
+}
+
+}  // namespace w1

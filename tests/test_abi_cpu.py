@@ -1,0 +1,106 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and its host parts (parameter choice, network simplex) agree
+with the oracle and with LP optimality conditions.  No GPU needed."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2110_14734_amd as w1
+import pdsynth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "w1approx.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(w1_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = w1.lib()
+    declared = _header_functions()
+    assert len(declared) >= 10
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(w1.EXPORTS) == declared
+
+
+def test_strerror_and_separation(orc):
+    assert w1.strerror(0) == "ok"
+    assert "invalid" in w1.strerror(-1)
+    for eps in (0.2, 0.1, 0.05, 0.01, 0.37):
+        assert w1.separation_for_eps(eps) == orc.choose_s(eps)
+    with pytest.raises(w1.W1Error):
+        w1.separation_for_eps(0.0)
+
+
+def test_context_without_gpu_fails_cleanly():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(w1.W1Error) as e:
+        w1.Context()
+    assert e.value.code == w1.W1_ENODEV
+
+
+def _certificate(n, src, dst, cost, supply, flow, pot):
+    bal = np.zeros(n, np.int64)
+    np.add.at(bal, src.astype(np.int64), flow)
+    np.add.at(bal, dst.astype(np.int64), -flow)
+    assert np.array_equal(bal, supply)
+    assert (flow >= 0).all()
+    red = cost.astype(np.int64) + pot[src] - pot[dst]
+    assert (red >= 0).all()
+    assert (red[flow > 0] == 0).all()
+
+
+def test_network_simplex_random_networks(orc):
+    rng = np.random.default_rng(17)
+    for trial in range(40):
+        n = int(rng.integers(3, 60))
+        m = int(rng.integers(n, 8 * n))
+        src = rng.integers(0, n, m)
+        dst = rng.integers(0, n, m)
+        keep = src != dst
+        src = np.concatenate([src[keep], np.arange(n)])
+        dst = np.concatenate([dst[keep], (np.arange(n) + 1) % n])
+        cost = rng.integers(0, 30, src.shape[0])
+        if trial % 3 == 0:
+            cost[:] = rng.integers(0, 2, src.shape[0])  # many ties: degenerate pivots
+        supply = rng.integers(-6, 7, n)
+        supply[-1] -= supply.sum()
+        c, piv, st, flow, pot = w1.flow_solve(n, src, dst, cost, supply, certificate=True)
+        assert st == w1.W1_OPTIMAL
+        assert c == orc.mcf(n, src, dst, cost, supply)
+        _certificate(n, src, dst, cost, supply, flow, pot)
+
+
+def test_network_simplex_on_oracle_networks(orc):
+    # the sparse transshipment networks the method builds (oracle side)
+    for seed in range(4):
+        A = pdsynth.exp_pd(120, 2 * seed)
+        B = pdsynth.exp_pd(110, 2 * seed + 1)
+        src, dst, cost, sup = orc.network(A, B, eps=0.2)
+        r = orc.run(A, B, eps=0.2)
+        c, piv, st, flow, pot = w1.flow_solve(sup.shape[0], src, dst, cost, sup, certificate=True)
+        assert c == r.flow
+        _certificate(sup.shape[0], src.astype(np.uint32), dst.astype(np.uint32), cost, sup, flow, pot)
+
+
+def test_network_simplex_pivot_cap_and_errors():
+    src = np.array([0, 1, 0], np.uint32)
+    dst = np.array([1, 2, 2], np.uint32)
+    cost = np.array([1, 1, 5], np.int32)
+    sup = np.array([3, 0, -3], np.int64)
+    c, piv, st = w1.flow_solve(3, src, dst, cost, sup)
+    assert c == 6 and st == w1.W1_OPTIMAL
+    c2, piv2, st2 = w1.flow_solve(3, src, dst, cost, sup, pivot_cap=1)
+    assert st2 == w1.W1_STALLED and piv2 == 1
+    with pytest.raises(w1.W1Error):
+        w1.flow_solve(3, src, dst, cost, np.array([3, 0, -2], np.int64))  # unbalanced
+    with pytest.raises(w1.W1Error):
+        w1.flow_solve(3, src[:2], dst[:2], cost[:2], np.array([0, 3, -3], np.int64)[::-1].copy())  # infeasible
