@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c1", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -133,6 +135,14 @@ def main():
             "avg_launch_ms": emit_avg,
         },
     }
+    if args.calib_copy_mb:
+        src = torch.empty(args.calib_copy_mb << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = src.numel()
+        del src, dst
     if not args.no_c1:
         # end to end incl. host network simplex, 400 + 400 points, eps 0.1
         C1a, C1b = pdsynth.exp_pd(400, 0), pdsynth.exp_pd(400, 1)

@@ -72,6 +72,8 @@ void launch_diag_fill(const uint32_t* cpair, const int2* cij, const int32_t* ca,
 // Tree view used by the WSPD traversal.  Node reference r >= 0 is internal
 // node r, r < 0 is the leaf of cell ~r.
 struct TreeView {
+  const int4* inode;    // internal, 3 int4 per node: box; left, right, lo, hi;
+                        // rep_i, rep_j, height, 0 (packed for the traversal)
   const int4* ibox;     // internal: min_i, min_j, max_i, max_j
   const int4* iaux;     // internal: left, right, lo, hi
   const int32_t* iheight;
@@ -87,13 +89,14 @@ struct WspdTuning {
   int blocks_per_cu;
 };
 
+void launch_pack_nodes(const TreeView& T, int4* inode, hipStream_t st);
 void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st);
 void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st);
 void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s, const WspdTuning& tun,
                           uint64_t* cnt, hipStream_t st);
 void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const uint64_t* cnt, const uint64_t* pos,
                          int2* out_items, int64_t out_base, int2* next, hipStream_t st);
-void launch_item_keys(const TreeView& T, const int2* items, int64_t m, uint64_t* keys, hipStream_t st);
+void launch_item_keys(const TreeView& T, const int2* items, int64_t m, bool both, uint64_t* keys, hipStream_t st);
 void launch_gather_items(const int2* src, const uint32_t* perm, int2* dst, int64_t m, hipStream_t st);
 void launch_item_pairs(const TreeView& T, const int2* items, int64_t m, int32_t* items_per_pair, hipStream_t st);
 void launch_chunk_heads(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start, int chunk,

@@ -42,7 +42,7 @@ struct Ctx {
   bool trace = false;
   hipStream_t st = nullptr;
   uint64_t* hpin = nullptr;  // pinned host scratch for read-backs
-  WspdTuning tun{32, 4096, 256, 2};
+  WspdTuning tun{16, 1024, 512, 5};
   std::vector<DBuf*> all;
   // points
   DBuf stage, segs, pb, pd, psd, kw0, kw1, kw2, kA, kB, vA, vB, head, idx, scantmp, sorttmp, small;
@@ -51,7 +51,7 @@ struct Ctx {
   // rwmd buckets
   DBuf nbuck, bincnt, binstart, ent;
   // cells / tree
-  DBuf ckey, cpair, cij, ca, cb, iaux, ibox, iheight, iparent, lparent, visit;
+  DBuf ckey, cpair, cij, ca, cb, iaux, ibox, iheight, iparent, lparent, visit, inode;
   // wspd
   DBuf itemsA, itemsB, itemsI, itemsS, icnt, ipos, ipp, chead, cid, cfirst, cend, cpairs, ccnt, coff, xrange, xctr, err;
   // network
@@ -70,7 +70,7 @@ struct Ctx {
     DBuf* list[] = {&stage, &segs, &pb, &pd, &psd, &kw0, &kw1, &kw2, &kA, &kB, &vA, &vB, &head, &idx, &scantmp, &sorttmp,
                     &small, &gb, &gd, &gpair, &gw, &lb, &ld, &lw, &lpair, &lt, &lterm, &lbin, &li, &lj, &nbuck,
                     &bincnt, &binstart, &ent, &ckey, &cpair, &cij, &ca, &cb, &iaux, &ibox, &iheight, &iparent,
-                    &lparent, &visit, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &chead, &cid,
+                    &lparent, &visit, &inode, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &chead, &cid,
                     &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &pv, &pc, &dcnt, &dpos,
                     &dsrc, &ddst, &dcost, &supply, &pairs};
     all.assign(std::begin(list), std::end(list));
@@ -464,6 +464,9 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     T.ibox = ibox;
     T.iaux = iaux;
     T.iheight = ih;
+    int4* inode = need<int4>(c, c.inode, 3 * (N - 1));
+    launch_pack_nodes(T, inode, st);
+    T.inode = inode;
     check(c, hipGetLastError());
   }
   record(c, 4);
@@ -481,6 +484,18 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     int64_t f = (int64_t)total_of(c, rflag, rpos, N - 1);
     int2* F = need<int2>(c, c.itemsA, f);
     launch_wspd_roots_fill(T, rflag, rpos, F, st);
+    if (f > 1) {  // canonical root order: (rep left, rep right)
+      uint64_t* rkeys = need<uint64_t>(c, c.kw0, f);
+      launch_item_keys(T, F, f, true, rkeys, st);
+      uint32_t* rperm;
+      uint64_t* rtop;
+      const uint64_t* rw[1] = {rkeys};
+      sort_words(c, rw, 1, f, &rperm, &rtop);
+      int2* F2 = need<int2>(c, c.itemsB, f);
+      launch_gather_items(F, rperm, F2, f, st);
+      std::swap(c.itemsA, c.itemsB);
+      F = (int2*)c.itemsA.p;
+    }
     int64_t isz = 0;
     int2* I = need<int2>(c, c.itemsI, std::max<int64_t>(f, 1024));
     check(c, hipEventRecord(c.kev[0], st));
@@ -512,7 +527,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     if (m > 0) {
       // sort items by (rep U, rep V): Morton order, pair-major, canonical
       uint64_t* keys = need<uint64_t>(c, c.kw0, m);
-      launch_item_keys(T, I, m, keys, st);
+      launch_item_keys(T, I, m, false, keys, st);
       uint32_t* perm;
       uint64_t* top;
       const uint64_t* words[1] = {keys};

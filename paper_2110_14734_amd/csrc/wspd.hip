@@ -100,14 +100,18 @@ __global__ void k_scatter(TreeView T, const int2* __restrict__ items, int64_t f,
   }
 }
 
-// Canonical item key (rep U, rep V): depends only on the cells, not on node
-// numbering, so a pair's work list -- and hence its output order -- is the
-// same alone or inside a batch.  Keys are unique: two items cannot share
-// both representatives because the WSPD covers every cell pair once.
-__global__ void k_item_keys(TreeView T, const int2* __restrict__ items, int64_t m, uint64_t* __restrict__ keys) {
+// Item keys.  (rep U, rep V) is canonical -- it depends only on the cells,
+// not on node numbering -- and unique (the WSPD covers every cell pair once);
+// the root search items are put in that order, the expansion rounds keep it,
+// and the final work list is then stably sorted by rep U alone (Morton
+// order, pair-major), so a pair's work list and hence its output order are
+// the same alone or inside a batch.
+__global__ void k_item_keys(TreeView T, const int2* __restrict__ items, int64_t m, int both,
+                            uint64_t* __restrict__ keys) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x < m)
-    keys[x] = ((uint64_t)(uint32_t)node_rep(T, items[x].x) << 32) | (uint64_t)(uint32_t)node_rep(T, items[x].y);
+  if (x >= m) return;
+  const uint64_t u = (uint32_t)node_rep(T, items[x].x);
+  keys[x] = both ? ((u << 32) | (uint64_t)(uint32_t)node_rep(T, items[x].y)) : u;
 }
 
 __global__ void k_gather_items(const int2* __restrict__ src, const uint32_t* __restrict__ perm, int2* __restrict__ dst,
@@ -149,6 +153,65 @@ __global__ void k_chunk_fill(TreeView T, const int2* __restrict__ items, int64_t
   chunk_pair[c] = (int32_t)p;
 }
 
+// Packed node record for the traversal: box, children, representative
+// (first cell in Morton order) and the representative's coordinates.
+struct Rec {
+  int4 box;
+  int left, right;
+  int rep, ri, rj;
+};
+
+__device__ inline Rec load_rec(const TreeView& T, int32_t r) {
+  Rec q;
+  if (r >= 0) {
+    const int4* p = T.inode + 3 * (int64_t)r;
+    const int4 b = p[0], a = p[1], x = p[2];
+    q.box = b;
+    q.left = a.x;
+    q.right = a.y;
+    q.rep = a.z;
+    q.ri = x.x;
+    q.rj = x.y;
+  } else {
+    const int2 c = T.cij[~r];
+    q.box = make_int4(c.x, c.y, c.x, c.y);
+    q.left = q.right = 0;
+    q.rep = ~r;
+    q.ri = c.x;
+    q.rj = c.y;
+  }
+  return q;
+}
+
+__global__ void k_pack_nodes(TreeView T, int4* __restrict__ inode) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= T.N - 1) return;
+  const int4 a = T.iaux[r];
+  const int2 c = T.cij[a.z];
+  inode[3 * r] = T.ibox[r];
+  inode[3 * r + 1] = a;
+  inode[3 * r + 2] = make_int4(c.x, c.y, T.iheight[r], 0);
+}
+
+// One emitted pair of a lane in a step.
+struct Emit {
+  int u, v, c;
+};
+__device__ inline Emit make_emit(const Rec& a, const Rec& b) {
+  return Emit{a.rep, b.rep, 2 * max(abs(a.ri - b.ri), abs(a.rj - b.rj))};
+}
+
+// Count pass (EMIT = false) and emit pass (EMIT = true) of the WSPD search
+// over the chunks of the work list.  Lane state: an item known to be not
+// separated ("current"), or none.  A step splits the current item's node with
+// the longer box side, loads both children and tests both child pairs at
+// once (one dependent memory round trip resolves two recursion nodes);
+// separated child pairs are emitted, a non-separated one becomes current and
+// a second non-separated one is pushed on the lane's LDS stack.  Lanes
+// without work pop their stack or take fresh items from the chunk (fresh
+// items are tested first).  At most two pairs per lane per step, written at
+// the wave cursor in (slot, lane) order, so the order depends only on the
+// chunk.  Loop control lives in wave-uniform scalars.
 template <bool EMIT>
 __global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict__ items,
                                               const int32_t* __restrict__ chunk_first, const int32_t* __restrict__ chunk_end,
@@ -162,8 +225,6 @@ __global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict
   int2* stk = s_stack + (size_t)wave * stack_depth * WAVE;
   const uint64_t below = lanes_below();
   const int xcd = blockIdx.x & 7;
-  // Loop control (chunk index, item cursor, output cursor) is kept in wave-
-  // uniform scalars (readfirstlane) so every loop exit is a uniform branch.
   for (int probe = 0; probe < 8; ++probe) {
     const int xr = (xcd + probe) & 7;
     const int r0 = xcd_range[xr], r1 = xcd_range[xr + 1];
@@ -178,11 +239,10 @@ __global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict
       const int64_t cs = EMIT ? cell_start[chunk_pair[k]] : 0;
       const uint64_t obase = EMIT ? chunk_off[k] : 0;
       uint64_t cursor = 0;
-      bool has = false, ku = false, kv = false;
+      bool has = false, overflow = false, runaway = false;
       int sp = 0;
       int32_t U = 0, V = 0;
-      int4 bu = make_int4(0, 0, 0, 0), bv = bu;
-      bool runaway = false, overflow = false;
+      Rec RU{}, RV{};
       for (int64_t step = 0;; ++step) {
         if (step > step_cap) {  // beyond any chunk's possible work: give up, report
           runaway = true;
@@ -193,43 +253,51 @@ __global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict
           const int2 q = stk[sp * WAVE + lane];
           U = q.x;
           V = q.y;
+          RU = load_rec(T, U);
+          RV = load_rec(T, V);
           has = true;
-          ku = kv = false;
         }
         const uint64_t need = __ballot(!has);
         const int avail = end - next;
+        bool fresh = false;
         if (!has) {
           const int r = __popcll(need & below);
           if (r < avail) {
             const int2 q = items[next + r];
             U = q.x;
             V = q.y;
-            has = true;
-            ku = kv = false;
+            RU = load_rec(T, U);
+            RV = load_rec(T, V);
+            fresh = true;
           }
         }
         const int took = __popcll(need);
         next += took < avail ? took : (avail > 0 ? avail : 0);
-        if (__ballot(has) == 0) break;
-        bool emit = false;
-        if (has) {
-          if (!ku) { bu = node_box(T, U); ku = true; }
-          if (!kv) { bv = node_box(T, V); kv = true; }
-          if (separated(bu, bv, s)) {
-            emit = true;
+        if (__ballot(has || fresh) == 0) break;
+        bool e1 = false, e2 = false;
+        Emit m1{0, 0, 0}, m2{0, 0, 0};
+        if (fresh) {
+          if (separated(RU.box, RV.box, s)) {
+            e1 = true;
+            if (EMIT) m1 = make_emit(RU, RV);
           } else {
-            int2 second;
-            if (box_diam(bu) > box_diam(bv)) {
-              const int4 a = T.iaux[U];
-              second = make_int2(a.y, V);
-              U = a.x;
-              ku = false;
-            } else {
-              const int4 a = T.iaux[V];
-              second = make_int2(U, a.y);
-              V = a.x;
-              kv = false;
-            }
+            has = true;
+          }
+        }
+        if (has) {
+          const bool splitU = box_diam(RU.box) > box_diam(RV.box);
+          const int c1 = splitU ? RU.left : RV.left, c2 = splitU ? RU.right : RV.right;
+          const Rec C1 = load_rec(T, c1), C2 = load_rec(T, c2);
+          const Rec O = splitU ? RV : RU;
+          const bool s1 = separated(C1.box, O.box, s), s2 = separated(C2.box, O.box, s);
+          if (EMIT) {
+            if (s1) m1 = splitU ? make_emit(C1, O) : make_emit(O, C1);
+            if (s2) m2 = splitU ? make_emit(C2, O) : make_emit(O, C2);
+          }
+          e1 = s1;
+          e2 = s2;
+          if (!s1 && !s2) {
+            const int2 second = splitU ? make_int2(c2, V) : make_int2(U, c2);
             if (sp < stack_depth) {
               stk[sp * WAVE + lane] = second;
               ++sp;
@@ -237,18 +305,34 @@ __global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict
               overflow = true;
             }
           }
+          if (!s1) {
+            if (splitU) { U = c1; RU = C1; }
+            else { V = c1; RV = C1; }
+          } else if (!s2) {
+            if (splitU) { U = c2; RU = C2; }
+            else { V = c2; RV = C2; }
+          } else {
+            has = false;
+          }
         }
-        const uint64_t em = __ballot(emit);
-        if (EMIT && emit) {
-          const int32_t ru = node_rep(T, U), rv = node_rep(T, V);
-          const int2 cu = T.cij[ru], cv = T.cij[rv];
-          const uint64_t pos = obase + cursor + (uint64_t)__popcll(em & below);
-          pu[pos] = (uint32_t)(ru - cs);
-          pv[pos] = (uint32_t)(rv - cs);
-          pc[pos] = 2 * max(abs(cu.x - cv.x), abs(cu.y - cv.y));
+        const uint64_t b1 = __ballot(e1), b2 = __ballot(e2);
+        if (EMIT) {
+          // streaming (non-temporal) stores: the output is written once and
+          // must not evict the tree from L2
+          if (e1) {
+            const uint64_t pos = obase + cursor + (uint64_t)__popcll(b1 & below);
+            __builtin_nontemporal_store((uint32_t)(m1.u - cs), pu + pos);
+            __builtin_nontemporal_store((uint32_t)(m1.v - cs), pv + pos);
+            __builtin_nontemporal_store(m1.c, pc + pos);
+          }
+          if (e2) {
+            const uint64_t pos = obase + cursor + (uint64_t)__popcll(b1) + (uint64_t)__popcll(b2 & below);
+            __builtin_nontemporal_store((uint32_t)(m2.u - cs), pu + pos);
+            __builtin_nontemporal_store((uint32_t)(m2.v - cs), pv + pos);
+            __builtin_nontemporal_store(m2.c, pc + pos);
+          }
         }
-        if (emit) has = false;
-        cursor += (uint64_t)__popcll(em);
+        cursor += (uint64_t)(__popcll(b1) + __popcll(b2));
       }
       const bool bad = runaway || __ballot(overflow) != 0;
       if (bad) atomicOr(err, 1);
@@ -275,6 +359,7 @@ inline unsigned blocks(int64_t n, int bs = 256) { return (unsigned)(n > 0 ? ceil
 #define LAUNCH(kern, n, ...) \
   do { if ((n) > 0) hipLaunchKernelGGL(kern, dim3(blocks(n)), dim3(256), 0, st, __VA_ARGS__); } while (0)
 
+void launch_pack_nodes(const TreeView& T, int4* inode, hipStream_t st) { LAUNCH(k_pack_nodes, T.N - 1, T, inode); }
 void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st) { LAUNCH(k_roots_flags, T.N - 1, T, flag); }
 void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st) {
   LAUNCH(k_roots_fill, T.N - 1, T, flag, pos, items);
@@ -287,8 +372,8 @@ void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const 
                          int2* out_items, int64_t out_base, int2* next, hipStream_t st) {
   LAUNCH(k_scatter, f, T, items, f, cnt, pos, out_items, out_base, next);
 }
-void launch_item_keys(const TreeView& T, const int2* items, int64_t m, uint64_t* keys, hipStream_t st) {
-  LAUNCH(k_item_keys, m, T, items, m, keys);
+void launch_item_keys(const TreeView& T, const int2* items, int64_t m, bool both, uint64_t* keys, hipStream_t st) {
+  LAUNCH(k_item_keys, m, T, items, m, both ? 1 : 0, keys);
 }
 void launch_gather_items(const int2* src, const uint32_t* perm, int2* dst, int64_t m, hipStream_t st) {
   LAUNCH(k_gather_items, m, src, perm, dst, m);
@@ -315,7 +400,7 @@ void launch_wspd_pass(bool emit, const TreeView& T, const int2* items, const int
   grid = ((grid + 7) / 8) * 8;
   const size_t lds = (size_t)4 * tun.stack_depth * WAVE * sizeof(int2);
   // A chunk's items each have at most work_cap leaf pairs, hence fewer than
-  // 2 work_cap search steps; every wave step advances at least one lane.
+  // 2 work_cap recursion nodes; every wave step resolves at least one.
   const int64_t step_cap = (int64_t)tun.chunk_items * (2 * (int64_t)tun.work_cap + 2) + 1024;
   if (emit)
     hipLaunchKernelGGL(k_wspd<true>, dim3((unsigned)grid), dim3(256), lds, st, T, items, chunk_first, chunk_end,
