@@ -41,7 +41,107 @@ def parse():
     ap.add_argument("--no-c1", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--no-nn", action="store_true", help="skip the learned form (surrogate + 1-NN)")
+    ap.add_argument("--nn-db", type=int, default=2000, help="1-NN database size")
+    ap.add_argument("--nn-queries", type=int, default=64)
+    ap.add_argument("--embed-db", type=int, default=10_000,
+                    help="diagrams in the embedding (MFMA) workload, sizes log-uniform in [1k, 20k]")
     return ap.parse_args()
+
+
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+EMBED_FLOP_PER_POINT = 2 * (2 * 128 + 128 * 128)  # multiply-adds of phi's two layers, x2
+
+
+def family_db(m, n_fam, seed, lo, hi):
+    import numpy as np
+    import pdsynth
+
+    rng = np.random.default_rng(seed)
+    fams = [pdsynth.family_params(50_000 + seed * 1000 + f) for f in range(n_fam)]
+    sizes = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), m))).astype(int)
+    fid = rng.integers(0, n_fam, m)
+    db = [pdsynth.family_pd(int(sizes[i]), seed * 1_000_000 + i, fams[fid[i]]) for i in range(m)]
+    return db, fams, rng
+
+
+def run_nn(ctx, args):
+    """Learned form: DeepSets surrogate trained on the GPU on W1 labels that
+    the method computes, then 1-NN search with and without it."""
+    import numpy as np
+    import torch
+
+    import paper_2110_14734_amd as w1
+    import pdsynth
+
+    out = {}
+    # (1) embedding throughput on a database of the 1-NN configuration's size
+    t0 = time.perf_counter()
+    big, _, _ = family_db(args.embed_db, 200, 9, 1000, 20_000)
+    gen_s = time.perf_counter() - t0
+    big_dev = [torch.from_numpy(d).cuda() for d in big]
+    sur0 = w1.Surrogate(ctx, seed=1)
+    sur0.embed(big_dev)  # warm-up (also sizes the buffers)
+    ms = []
+    for _ in range(3):
+        sur0.embed(big_dev)
+        ms.append(sur0.last_times()["embed_ms"])
+    lt = sur0.last_times()
+    flops = EMBED_FLOP_PER_POINT * lt["points"]
+    tfl = flops / (min(ms) * 1e-3) / 1e12
+    out["embed"] = {"diagrams": lt["diagrams"], "points": lt["points"], "kernel_ms": min(ms),
+                    "points_per_s": lt["points"] / (min(ms) * 1e-3), "tflops": tfl,
+                    "mfma_util": tfl / MFMA_BF16_PEAK_TFLOPS, "gen_s": gen_s}
+    del big_dev, big
+    sur0.close()
+    torch.cuda.synchronize()
+
+    # (2) 1-NN search on a database whose exact-flow verifications are affordable
+    m, nq = args.nn_db, args.nn_queries
+    db, fams, rng = family_db(m, 100, 3, 50, 500)
+    rand = [(int(i), int(j)) for i, j in rng.integers(0, m, (4 * m, 2)) if i != j]
+    cand = rng.integers(0, m, (m, 16))
+    L = ctx.rwmd([db[i] for i in range(m) for _ in range(16)], [db[j] for j in cand.ravel()]).reshape(m, 16)
+    near = [(i, int(cand[i][np.argsort(L[i])[k]])) for i in range(m) for k in range(2)]
+    pairs = [p for p in rand + near if p[0] != p[1]]
+    t0 = time.perf_counter()
+    labels = []
+    for k in range(0, len(pairs), 512):
+        part = pairs[k:k + 512]
+        labels += [r.w1 for r in ctx.approx_batch([db[i] for i, _ in part], [db[j] for _, j in part], eps=args.eps)]
+    label_s = time.perf_counter() - t0
+    labels = np.array(labels)
+    keep = labels > 0
+    pa = np.array([p[0] for p in pairs])[keep]
+    pb = np.array([p[1] for p in pairs])[keep]
+    sur = w1.Surrogate(ctx, seed=7)
+    t0 = time.perf_counter()
+    losses = sur.train(db, pa, pb, labels[keep], epochs=30, batch_pairs=256, lr=3e-3, seed=5)
+    train_s = time.perf_counter() - t0
+    qs = [pdsynth.family_pd(int(rng.integers(50, 500)), 9_000_000 + i, fams[int(rng.integers(0, 100))])
+          for i in range(nq)]
+    idx = w1.NNIndex(ctx, db, sur)
+    res = {}
+    for mode in ("rwmd", "surrogate"):
+        idx.query(qs[:2], eps=args.eps, mode=mode)  # warm-up
+        t0 = time.perf_counter()
+        r = idx.query(qs, eps=args.eps, mode=mode)
+        dt = time.perf_counter() - t0
+        res[mode] = r
+        out[f"nn_{mode}"] = {"queries_per_s": nq / dt, "verifications_per_query": r.stats["verifications"] / nq,
+                             "rwmd_evals_per_query": r.stats["rwmd_evals"] / nq,
+                             "t_rwmd_ms": r.stats["t_rwmd_ms"], "t_embed_ms": r.stats["t_embed_ms"],
+                             "t_verify_ms": r.stats["t_verify_ms"]}
+    idx.close()
+    out["nn_identical_answers"] = bool(np.array_equal(res["rwmd"].nn, res["surrogate"].nn)
+                                       and np.array_equal(res["rwmd"].w1, res["surrogate"].w1))
+    out["nn_speedup"] = out["nn_surrogate"]["queries_per_s"] / out["nn_rwmd"]["queries_per_s"]
+    out["nn_workload"] = (f"database {m} diagrams (latent-family generator, sizes log-uniform [50, 500]), "
+                          f"{nq} queries, eps={args.eps}; surrogate trained on {int(keep.sum())} W1 labels "
+                          f"from the method ({label_s:.1f} s to label, {train_s:.1f} s to train, "
+                          f"loss {losses[0]:.3f} -> {losses[-1]:.3f})")
+    sur.close()
+    return out
 
 
 def cpu_baseline(A, B, eps):
@@ -154,6 +254,8 @@ def main():
         e2e = (time.perf_counter() - t1) / reps
         out["c1_end_to_end"] = {"pd_pairs_per_s": 1.0 / e2e, "ms": 1e3 * e2e, "w1": g.w1,
                                 "flow_ms": g.t_ms["flow"], "wspd_pairs": g.n_pairs}
+    if not args.no_nn:
+        out["learned"] = run_nn(ctx, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, args.eps)
     ctx.close()

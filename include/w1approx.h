@@ -209,6 +209,132 @@ int w1_separation_for_eps(double eps, double kappa);
 void w1_result_free(w1_result *r);
 const char *w1_strerror(int code);
 
+/* ======================================================================
+ * Learned form: a DeepSets surrogate of W1 and 1-NN search.
+ *
+ * The nearest-neighbour problem (Sec. 6, Problem NN): given database
+ * diagrams A_1..A_m and a query B, find argmin_i W1(B, A_i).  Here W1 is the
+ * certified value `w1` that w1_approx computes at the given eps, and ties go
+ * to the lowest index.  The surrogate only orders the candidates.  Every
+ * answer comes from the method itself.  A candidate is skipped only when
+ * its RWMD lower bound (Alg. 1) exceeds the best W1 found so far, so it
+ * cannot be the answer.  Answers are identical in every search mode.
+ *
+ * Network: phi(x) = ReLU(W2 ReLU(W1 x + b1) + b2), with x = (birth,
+ * death - birth) and shapes 2 -> 128 -> 128.  It is summed over the points
+ * of a diagram (a point of multiplicity k counts k times; diagonal points
+ * are ignored).  Then e = W3 pool + b3 (128 -> 64), and the prediction is
+ * ||e_A - e_B||_2.  W1, b1, W2 and the first hidden layer are BF16 on the
+ * matrix cores with FP32 accumulation; x enters as a two-term BF16
+ * expansion.  b2, pooling and rho are FP32; master parameters are FP32.
+ *
+ * Parameter vector (W1_SURR_NPARAM floats, FP32), in this order:
+ *   W1 [128][2], b1 [128], W2 [128 out][128 in], b2 [128], W3 [64][128], b3 [64]
+ * ====================================================================== */
+#define W1_SURR_NPARAM 25152
+#define W1_SURR_EMB 64
+
+typedef struct w1_surrogate w1_surrogate;
+
+typedef struct {
+  int32_t epochs;      /* passes over the labelled pairs                        */
+  int32_t batch_pairs; /* pairs per Adam step                                   */
+  float lr, beta1, beta2, adam_eps; /* Adam; 0 selects 1e-3, 0.9, 0.999, 1e-8    */
+  uint64_t seed;       /* pair shuffling                                        */
+} w1_train_params;
+
+/* New surrogate on the context's device.  The parameters are drawn from a
+ * counter-based generator seeded by `seed` (uniform fan-in scaling), and the
+ * Adam state starts at zero.  The surrogate is bound to ctx's device; use it
+ * only with contexts on that device. */
+int w1_surrogate_create(w1_ctx *ctx, uint64_t seed, w1_surrogate **out);
+int w1_surrogate_destroy(w1_surrogate *s);
+/* Copy the FP32 master parameters to / from host memory (n = W1_SURR_NPARAM).
+ * set_params resets the Adam state. */
+int w1_surrogate_get_params(const w1_surrogate *s, float *out, int64_t n);
+int w1_surrogate_set_params(w1_surrogate *s, const float *in, int64_t n);
+
+/* Embeddings of k diagrams: emb_out (host) receives k x 64 FP32, row-major.
+ * Diagrams are host arrays, or device arrays with W1_INPUT_DEVICE in flags.
+ * Invalid points (non-finite, death < birth) give W1_EINVAL. */
+int w1_surrogate_embed(w1_ctx *ctx, w1_surrogate *s, const w1_pd *d, int64_t k, uint32_t flags, void *stream,
+                       float *emb_out);
+
+/* Loss and gradient over labelled pairs, without an update.  Pair j joins
+ * diagrams pa[j] and pb[j] (indices into d[0..k)) and has label w[j] > 0.
+ * loss = (1/P) sum_j ((||e_pa - e_pb|| - w_j) / w_j)^2.  grad_out (host,
+ * W1_SURR_NPARAM) gets d loss / d parameters: the BF16 roundings pass
+ * gradients unchanged, and a ReLU at exactly 0 passes none. */
+int w1_surrogate_grad(w1_ctx *ctx, w1_surrogate *s, const w1_pd *d, int64_t k, const int64_t *pa,
+                      const int64_t *pb, const double *w, int64_t npairs, uint32_t flags, void *stream,
+                      double *loss_out, float *grad_out);
+
+/* Train with Adam on labelled pairs, entirely on the device (the forward
+ * and backward kernels of this library).  epoch_loss_out (host, `epochs`
+ * entries, may be NULL) gets the mean pair loss of each epoch as it was
+ * computed during that epoch. */
+int w1_surrogate_train(w1_ctx *ctx, w1_surrogate *s, const w1_pd *d, int64_t k, const int64_t *pa,
+                       const int64_t *pb, const double *w, int64_t npairs, const w1_train_params *tp,
+                       uint32_t flags, void *stream, double *epoch_loss_out);
+
+/* Timings of the surrogate's last embed call: [0] forward kernel ms (HIP
+ * events), [1] points embedded, [2] diagrams embedded.  n >= 3. */
+int w1_surrogate_last_times(const w1_surrogate *s, double *out, int n);
+
+/* ---- 1-NN search ---------------------------------------------------------- */
+typedef struct w1_nn_index w1_nn_index;
+
+/* Search modes.  All return the same answers.
+ *   W1_NN_RWMD        the method without the surrogate: the RWMD bound of
+ *                     every (query, database) pair, then candidates in
+ *                     increasing RWMD order until RWMD > best.
+ *   W1_NN_SURROGATE   verify the seed_k nearest candidates by surrogate
+ *                     distance first; drop every candidate whose dual bound
+ *                     exceeds the best W1 so far; compute RWMD only for the
+ *                     rest, then continue as W1_NN_RWMD on them.  The dual
+ *                     bound is max_c |sum_A f_c - sum_B f_c| over the test
+ *                     functions f_c(x) = max(0, d_diag(x) - c), c = 0 and
+ *                     2^-20 .. 2^11.  Each f_c is 1-Lipschitz in L-infinity
+ *                     and vanishes on the diagonal, so the bound is <= W1
+ *                     (Kantorovich duality).  Its per-diagram sums are FP64,
+ *                     and a margin of 1e-8 (sum_A f_c + sum_B f_c) covers
+ *                     their rounding.
+ *   W1_NN_EXHAUSTIVE  verify every database diagram. */
+#define W1_NN_RWMD 0
+#define W1_NN_SURROGATE 1
+#define W1_NN_EXHAUSTIVE 2
+#define W1_NN_NSTATS 33 /* test functions of the dual bound */
+
+typedef struct {
+  double eps;     /* eps of the method that verifies candidates                 */
+  int32_t mode;   /* W1_NN_*                                                    */
+  int32_t seed_k; /* W1_NN_SURROGATE: candidates verified first, in surrogate  */
+                  /* order (0 selects 1)                                        */
+} w1_nn_params;
+
+typedef struct {
+  int64_t verifications; /* full-method W1 evaluations, all queries          */
+  int64_t rwmd_evals;    /* RWMD bounds computed, all queries                 */
+  int64_t rounds;        /* verification rounds (one candidate per live query) */
+  double t_rwmd_ms;      /* RWMD bounds                                        */
+  double t_embed_ms;     /* query embedding, surrogate distances, dual bounds  */
+  double t_verify_ms;    /* full-method verifications (GPU + host flow)         */
+  double t_total_ms;
+} w1_nn_stats;
+
+/* Index over m database diagrams: a device copy of their points and, when s
+ * is not NULL, their embeddings under s.  The index does not keep s. */
+int w1_nn_build(w1_ctx *ctx, w1_surrogate *s, const w1_pd *db, int64_t m, uint32_t flags, void *stream,
+                w1_nn_index **out);
+int w1_nn_destroy(w1_nn_index *idx);
+/* Nearest database diagram of each of nq queries.  nn_out[q] = index,
+ * w1_out[q] = its certified W1 (may be NULL), verif_out[q] = verifications
+ * spent on query q (may be NULL).  W1_NN_SURROGATE needs the surrogate the
+ * index was built with (s); the other modes ignore s. */
+int w1_nn_query(w1_ctx *ctx, w1_nn_index *idx, w1_surrogate *s, const w1_pd *q, int64_t nq,
+                const w1_nn_params *p, uint32_t flags, void *stream, int64_t *nn_out, double *w1_out,
+                int64_t *verif_out, w1_nn_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

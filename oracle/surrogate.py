@@ -1,0 +1,171 @@
+"""Oracle for the learned form (test infrastructure only): the DeepSets
+surrogate's forward pass and gradient, the dual lower bound, and exhaustive
+1-NN search.  Only the test suite, ``__graft_entry__.smoke()`` and the CPU
+baseline of ``bench.py`` may import it; the GPU library never does.
+
+Network (the 1-NN problem is Problem NN of Sec. 6; the network itself is not
+in the paper, it only orders candidates):
+    x = (birth, death - birth) of each off-diagonal point
+    h1 = ReLU(W1 x + b1)          2 -> 128
+    h2 = ReLU(W2 h1 + b2)         128 -> 128
+    pool = sum of h2 over the points
+    e = W3 pool + b3              128 -> 64,  prediction ||e_A - e_B||_2
+    loss = (1/P) sum_j ((||e_a - e_b|| - w_j) / w_j)^2
+
+``emulate=True`` places the roundings the library's precision contract
+names.  x is first rounded to FP32 and then written as hi + lo, with hi =
+bf16(x) and lo = bf16(x - hi).  W1, b1, W2 and h1 are rounded to BF16.  The
+gradient of dZ2 enters both weight products as bf16(dpool).  Everything else
+is exact FP64.  The roundings pass gradients unchanged (straight-through).
+``emulate=False`` is the plain FP64 network; finite differences pin its
+gradient.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+H, E = 128, 64
+OFF_W1, OFF_B1 = 0, 256
+OFF_W2 = OFF_B1 + H
+OFF_B2 = OFF_W2 + H * H
+OFF_W3 = OFF_B2 + H
+OFF_B3 = OFF_W3 + E * H
+NPARAM = OFF_B3 + E  # 25152
+NSTATS = 33
+
+
+def bf16(x) -> np.ndarray:
+    """Round to the nearest BF16 value (8 significant bits), ties to even."""
+    x = np.asarray(x, np.float64)
+    m, e = np.frexp(x)                    # x = m 2^e, 0.5 <= |m| < 1
+    return np.ldexp(np.rint(np.ldexp(m, 8)), e - 8)
+
+
+def unpack(p) -> dict:
+    """Parameter tensors.  A FP32 vector (the library's master parameters) is
+    widened exactly; a FP64 vector is used as it is."""
+    p = np.asarray(p)
+    if p.dtype != np.float64:
+        p = p.astype(np.float32).astype(np.float64)
+    assert p.shape == (NPARAM,)
+    return dict(W1=p[OFF_W1:OFF_B1].reshape(H, 2), b1=p[OFF_B1:OFF_W2], W2=p[OFF_W2:OFF_B2].reshape(H, H),
+                b2=p[OFF_B2:OFF_W3], W3=p[OFF_W3:OFF_B3].reshape(E, H), b3=p[OFF_B3:NPARAM])
+
+
+def features(A) -> np.ndarray:
+    """(birth, death - birth) of the off-diagonal points, each rounded to
+    FP32 (the difference is taken in FP64 first)."""
+    A = np.asarray(A, np.float64).reshape(-1, 2)
+    if A.size and (not np.isfinite(A).all() or (A[:, 1] < A[:, 0]).any()):
+        raise ValueError("invalid diagram point")
+    A = A[A[:, 1] > A[:, 0]]
+    x = np.stack([A[:, 0], A[:, 1] - A[:, 0]], axis=1) if len(A) else np.zeros((0, 2))
+    return x.astype(np.float32).astype(np.float64)
+
+
+def _weights(P, emulate):
+    if not emulate:
+        return P["W1"], P["b1"], P["W2"]
+    return bf16(P["W1"]), bf16(P["b1"]), bf16(P["W2"])
+
+
+def _inputs(x, emulate):
+    if not emulate:
+        return x
+    hi = bf16(x)
+    return hi + bf16(x - hi)
+
+
+def forward(p, diagrams, emulate=True):
+    """Embeddings (D x 64) and the per-diagram intermediates."""
+    P = unpack(p)
+    W1, b1, W2 = _weights(P, emulate)
+    emb, cache = [], []
+    for A in diagrams:
+        x = _inputs(features(A), emulate)
+        z1 = x @ W1.T + b1
+        h1 = np.maximum(z1, 0.0)
+        if emulate:
+            h1 = bf16(h1)
+        z2 = h1 @ W2.T + P["b2"]
+        h2 = np.maximum(z2, 0.0)
+        pool = h2.sum(axis=0)
+        emb.append(P["W3"] @ pool + P["b3"])
+        cache.append((x, h1, z2, pool))
+    return np.array(emb).reshape(-1, E), cache
+
+
+def loss_grad(p, diagrams, pa, pb, w, emulate=True):
+    """Loss and its gradient with respect to the parameter vector."""
+    P = unpack(p)
+    W1, b1, W2 = _weights(P, emulate)
+    emb, cache = forward(p, diagrams, emulate)
+    pa, pb, w = np.asarray(pa), np.asarray(pb), np.asarray(w, np.float64)
+    nP = len(w)
+    demb = np.zeros_like(emb)
+    loss = 0.0
+    for j in range(nP):
+        diff = emb[pa[j]] - emb[pb[j]]
+        pred = np.sqrt(diff @ diff)
+        rel = (pred - w[j]) / w[j]
+        loss += rel * rel / nP
+        if pred > 0:
+            g = 2.0 * rel / (w[j] * nP) / pred * diff
+            demb[pa[j]] += g
+            demb[pb[j]] -= g
+    grad = np.zeros(NPARAM)
+    gW1, gb1, gW2, gb2 = (np.zeros((H, 2)), np.zeros(H), np.zeros((H, H)), np.zeros(H))
+    gW3 = np.zeros((E, H))
+    gb3 = demb.sum(axis=0)
+    for d, (x, h1, z2, pool) in enumerate(cache):
+        gW3 += np.outer(demb[d], pool)
+        dpool = P["W3"].T @ demb[d]
+        mask2 = z2 > 0.0
+        gb2 += (mask2 * dpool).sum(axis=0)
+        dz2 = mask2 * (bf16(dpool) if emulate else dpool)
+        gW2 += dz2.T @ h1
+        dh1 = dz2 @ W2
+        dz1 = dh1 * (h1 > 0.0)
+        gW1 += dz1.T @ x
+        gb1 += dz1.sum(axis=0)
+    grad[OFF_W1:OFF_B1] = gW1.ravel()
+    grad[OFF_B1:OFF_W2] = gb1
+    grad[OFF_W2:OFF_B2] = gW2.ravel()
+    grad[OFF_B2:OFF_W3] = gb2
+    grad[OFF_W3:OFF_B3] = gW3.ravel()
+    grad[OFF_B3:NPARAM] = gb3
+    return loss, grad
+
+
+# ---------------------------------------------------------------- 1-NN --
+def dual_stats(A) -> np.ndarray:
+    """Sums over the points of f_c(x) = max(0, (d - b)/2 - c) for c = 0 and
+    c = 2^-20 .. 2^11 (33 test functions, each 1-Lipschitz in L-infinity and
+    zero on the diagonal)."""
+    A = np.asarray(A, np.float64).reshape(-1, 2)
+    h = (A[:, 1] - A[:, 0]) * 0.5
+    cs = np.concatenate([[0.0], np.ldexp(1.0, np.arange(-20, 12))])
+    return np.array([np.maximum(0.0, h - c).sum() for c in cs])
+
+
+def dual_bound(A, B) -> float:
+    """max_c |sum_A f_c - sum_B f_c| <= W1(A, B) (Kantorovich duality)."""
+    return float(np.abs(dual_stats(A) - dual_stats(B)).max())
+
+
+def nn_exhaustive(db, queries, eps=0.1):
+    """Problem NN (Sec. 6) by exhaustive search over the oracle's certified
+    W1 at eps; ties go to the lowest index.  Returns (index, W1) per query."""
+    from . import run
+
+    out = []
+    for q in queries:
+        best, bi = np.inf, -1
+        for i, D in enumerate(db):
+            r = run(q, D, eps=eps, fetch=False)
+            if r.status != 0:
+                raise RuntimeError(f"oracle status {r.status}")
+            if r.W1 < best:
+                best, bi = r.W1, i
+        out.append((bi, best))
+    return out

@@ -69,9 +69,33 @@ class _DevNet(ctypes.Structure):
                 ("pair_v", _P), ("pair_cost", _P), ("diag_src", _P), ("diag_dst", _P), ("diag_cost", _P)]
 
 
+class _TrainParams(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch_pairs", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+class _NNParams(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("mode", ctypes.c_int32), ("seed_k", ctypes.c_int32)]
+
+
+class _NNStats(ctypes.Structure):
+    _fields_ = [("verifications", ctypes.c_int64), ("rwmd_evals", ctypes.c_int64), ("rounds", ctypes.c_int64),
+                ("t_rwmd_ms", ctypes.c_double), ("t_embed_ms", ctypes.c_double), ("t_verify_ms", ctypes.c_double),
+                ("t_total_ms", ctypes.c_double)]
+
+
+SURR_NPARAM = 25152
+SURR_EMB = 64
+NN_RWMD, NN_SURROGATE, NN_EXHAUSTIVE = 0, 1, 2
+NN_MODES = {"rwmd": NN_RWMD, "surrogate": NN_SURROGATE, "exhaustive": NN_EXHAUSTIVE}
+
 # Every symbol include/w1approx.h declares.
-EXPORTS = ("w1_ctx_create", "w1_ctx_destroy", "w1_ctx_hip_error", "w1_ctx_last_kernel_times", "w1_approx", "w1_approx_batch", "w1_rwmd",
-           "w1_device_network_get", "w1_flow_solve", "w1_separation_for_eps", "w1_result_free", "w1_strerror")
+EXPORTS = ("w1_ctx_create", "w1_ctx_destroy", "w1_ctx_hip_error", "w1_ctx_last_kernel_times", "w1_approx",
+           "w1_approx_batch", "w1_rwmd", "w1_device_network_get", "w1_flow_solve", "w1_separation_for_eps",
+           "w1_result_free", "w1_strerror", "w1_surrogate_create", "w1_surrogate_destroy",
+           "w1_surrogate_get_params", "w1_surrogate_set_params", "w1_surrogate_embed", "w1_surrogate_grad",
+           "w1_surrogate_train", "w1_surrogate_last_times", "w1_nn_build", "w1_nn_destroy", "w1_nn_query")
 
 _lib = None
 
@@ -109,6 +133,21 @@ def lib():
         L.w1_result_free.restype = None
         L.w1_strerror.argtypes = [i32]
         L.w1_strerror.restype = ctypes.c_char_p
+        f32p, f64p, i64p = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)
+        L.w1_surrogate_create.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp)]
+        L.w1_surrogate_destroy.argtypes = [vp]
+        L.w1_surrogate_get_params.argtypes = [vp, f32p, i64]
+        L.w1_surrogate_set_params.argtypes = [vp, f32p, i64]
+        L.w1_surrogate_embed.argtypes = [vp, vp, ctypes.POINTER(_PD), i64, ctypes.c_uint32, vp, f32p]
+        L.w1_surrogate_grad.argtypes = [vp, vp, ctypes.POINTER(_PD), i64, i64p, i64p, f64p, i64, ctypes.c_uint32, vp,
+                                        f64p, f32p]
+        L.w1_surrogate_train.argtypes = [vp, vp, ctypes.POINTER(_PD), i64, i64p, i64p, f64p, i64,
+                                         ctypes.POINTER(_TrainParams), ctypes.c_uint32, vp, f64p]
+        L.w1_surrogate_last_times.argtypes = [vp, f64p, i32]
+        L.w1_nn_build.argtypes = [vp, vp, ctypes.POINTER(_PD), i64, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
+        L.w1_nn_destroy.argtypes = [vp]
+        L.w1_nn_query.argtypes = [vp, vp, vp, ctypes.POINTER(_PD), i64, ctypes.POINTER(_NNParams), ctypes.c_uint32,
+                                  vp, i64p, f64p, i64p, ctypes.POINTER(_NNStats)]
         _lib = L
     return _lib
 
@@ -346,6 +385,162 @@ class Context:
         if rc != 0:
             raise W1Error(rc, "w1_device_network_get")
         return {f: getattr(d, f) for f, _ in _DevNet._fields_}
+
+
+def _pd_list(ds, keep):
+    """w1_pd array of a list of diagrams (all host or all device)."""
+    k = len(ds)
+    arr = (_PD * k)()
+    devs = set()
+    for i, D in enumerate(ds):
+        arr[i], dv = _pd_of(D, keep)
+        devs.add(dv)
+    if len(devs) > 1:
+        raise ValueError("mix of host and device diagrams")
+    return arr, (devs.pop() if devs else False)
+
+
+def _c(a, dtype):
+    a = np.ascontiguousarray(a, dtype)
+    return a, a.ctypes.data_as(ctypes.POINTER(np.ctypeslib.as_ctypes_type(np.dtype(dtype))))
+
+
+class Surrogate:
+    """DeepSets surrogate of W1 on one GPU (its kernels run in the library)."""
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        h = ctypes.c_void_p()
+        rc = lib().w1_surrogate_create(ctx._h, ctypes.c_uint64(seed), ctypes.byref(h))
+        if rc != 0:
+            raise W1Error(rc, "w1_surrogate_create")
+        self._h, self.ctx = h, ctx
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().w1_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def params(self) -> np.ndarray:
+        out = np.zeros(SURR_NPARAM, np.float32)
+        _, p = _c(out, np.float32)
+        rc = lib().w1_surrogate_get_params(self._h, p, SURR_NPARAM)
+        if rc != 0:
+            raise W1Error(rc, "w1_surrogate_get_params")
+        return out
+
+    @params.setter
+    def params(self, v):
+        a, p = _c(v, np.float32)
+        rc = lib().w1_surrogate_set_params(self._h, p, a.size)
+        if rc != 0:
+            raise W1Error(rc, "w1_surrogate_set_params")
+
+    def embed(self, ds) -> np.ndarray:
+        keep = []
+        arr, dev = _pd_list(ds, keep)
+        out = np.zeros((len(ds), SURR_EMB), np.float32)
+        rc = lib().w1_surrogate_embed(self.ctx._h, self._h, arr, len(ds), INPUT_DEVICE if dev else 0,
+                                      _stream_of(dev), out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        if rc != 0:
+            raise W1Error(rc, "w1_surrogate_embed")
+        return out
+
+    def last_times(self) -> dict:
+        out = (ctypes.c_double * 3)()
+        lib().w1_surrogate_last_times(self._h, out, 3)
+        return {"embed_ms": out[0], "points": int(out[1]), "diagrams": int(out[2])}
+
+    def grad(self, ds, pa, pb, w):
+        """(loss, gradient) over labelled pairs, without an update."""
+        keep = []
+        arr, dev = _pd_list(ds, keep)
+        a, ap = _c(pa, np.int64)
+        b, bp = _c(pb, np.int64)
+        ww, wp = _c(w, np.float64)
+        loss = ctypes.c_double()
+        g = np.zeros(SURR_NPARAM, np.float32)
+        rc = lib().w1_surrogate_grad(self.ctx._h, self._h, arr, len(ds), ap, bp, wp, a.size,
+                                     INPUT_DEVICE if dev else 0, _stream_of(dev), ctypes.byref(loss),
+                                     g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        if rc != 0:
+            raise W1Error(rc, "w1_surrogate_grad")
+        return loss.value, g
+
+    def train(self, ds, pa, pb, w, epochs=10, batch_pairs=256, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8,
+              seed=0) -> np.ndarray:
+        """Adam training on the device; returns the mean loss of each epoch."""
+        keep = []
+        arr, dev = _pd_list(ds, keep)
+        a, ap = _c(pa, np.int64)
+        b, bp = _c(pb, np.int64)
+        ww, wp = _c(w, np.float64)
+        tp = _TrainParams(int(epochs), int(batch_pairs), lr, beta1, beta2, adam_eps, ctypes.c_uint64(seed))
+        losses = np.zeros(max(int(epochs), 1))
+        rc = lib().w1_surrogate_train(self.ctx._h, self._h, arr, len(ds), ap, bp, wp, a.size, ctypes.byref(tp),
+                                      INPUT_DEVICE if dev else 0, _stream_of(dev),
+                                      losses.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if rc != 0:
+            raise W1Error(rc, "w1_surrogate_train")
+        return losses[:int(epochs)]
+
+
+@dataclass
+class NNResult:
+    nn: np.ndarray
+    w1: np.ndarray
+    verifications: np.ndarray
+    stats: dict
+
+
+class NNIndex:
+    """1-NN index over database diagrams (device copy, dual-bound sums and,
+    with a surrogate, embeddings)."""
+
+    def __init__(self, ctx: Context, db, surrogate: Surrogate | None = None):
+        keep = []
+        arr, dev = _pd_list(db, keep)
+        h = ctypes.c_void_p()
+        rc = lib().w1_nn_build(ctx._h, surrogate._h if surrogate else None, arr, len(db),
+                               INPUT_DEVICE if dev else 0, _stream_of(dev), ctypes.byref(h))
+        if rc != 0:
+            raise W1Error(rc, "w1_nn_build")
+        self._h, self.ctx, self.surrogate, self.m = h, ctx, surrogate, len(db)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().w1_nn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self, qs, eps=0.1, mode="surrogate", seed_k=1) -> NNResult:
+        keep = []
+        arr, dev = _pd_list(qs, keep)
+        nq = len(qs)
+        nn = np.zeros(nq, np.int64)
+        w = np.zeros(nq, np.float64)
+        ver = np.zeros(nq, np.int64)
+        st = _NNStats()
+        prm = _NNParams(float(eps), NN_MODES[mode], int(seed_k))
+        sur = self.surrogate._h if (self.surrogate is not None and mode == "surrogate") else None
+        rc = lib().w1_nn_query(self.ctx._h, self._h, sur, arr, nq, ctypes.byref(prm), INPUT_DEVICE if dev else 0,
+                               _stream_of(dev), nn.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                               w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ver.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(st))
+        if rc != 0:
+            raise W1Error(rc, f"w1_nn_query (hip error {lib().w1_ctx_hip_error(self.ctx._h)})")
+        return NNResult(nn, w, ver, {f: getattr(st, f) for f, _ in _NNStats._fields_})
 
 
 def build():

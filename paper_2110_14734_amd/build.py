@@ -19,8 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libw1approx.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["prims.hip", "stages.hip", "wspd.hip", "pipeline.cpp", "flow.cpp"]
-HEADERS = ["common.h", "kernels.h", "flow.h"]
+SOURCES = ["prims.hip", "stages.hip", "wspd.hip", "deepsets.hip", "pipeline.cpp", "surrogate.cpp", "flow.cpp"]
+HEADERS = ["common.h", "kernels.h", "flow.h", "ctx.h", "surrogate.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,0 +1,137 @@
+// Library context: device buffers that persist between calls, the stream of
+// the current call, events, and small helpers shared by the host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/w1approx.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace w1 {
+
+struct DBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct StageError {
+  int code;
+};
+
+struct Ctx {
+  int device = 0;
+  int num_cus = 256;
+  int hip_err = 0;
+  bool trace = false;
+  hipStream_t st = nullptr;
+  uint64_t* hpin = nullptr;  // pinned host scratch for read-backs
+  WspdTuning tun{16, 1024, 512, 5};
+  std::vector<DBuf*> all;
+  // points
+  DBuf stage, segs, pb, pd, psd, kw0, kw1, kw2, kA, kB, vA, vB, head, idx, scantmp, sorttmp, small;
+  // groups / locations
+  DBuf gb, gd, gpair, gw, lb, ld, lw, lpair, lt, lterm, lbin, li, lj;
+  // rwmd buckets
+  DBuf nbuck, bincnt, binstart, ent;
+  // cells / tree
+  DBuf ckey, cpair, cij, ca, cb, iaux, ibox, iheight, iparent, lparent, visit, inode;
+  // wspd
+  DBuf itemsA, itemsB, itemsI, itemsS, icnt, ipos, ipp, chead, cid, cfirst, cend, cpairs, ccnt, coff, xrange, xctr, err;
+  // network
+  DBuf pu, pv, pc, dcnt, dpos, dsrc, ddst, dcost, supply;
+  // per pair
+  DBuf pairs;
+  PairArrays P{};
+  int64_t K = 0;
+  std::vector<int64_t> h_cell_start, h_ncells, h_pair_start, h_npairs, h_diag_start, h_ndiag, h_supply_base;
+  bool network_valid = false;
+  hipEvent_t ev[8];
+  hipEvent_t kev[4];
+  double kms[4] = {0, 0, 0, 0};
+
+  Ctx() {
+    DBuf* list[] = {&stage, &segs, &pb, &pd, &psd, &kw0, &kw1, &kw2, &kA, &kB, &vA, &vB, &head, &idx, &scantmp, &sorttmp,
+                    &small, &gb, &gd, &gpair, &gw, &lb, &ld, &lw, &lpair, &lt, &lterm, &lbin, &li, &lj, &nbuck,
+                    &bincnt, &binstart, &ent, &ckey, &cpair, &cij, &ca, &cb, &iaux, &ibox, &iheight, &iparent,
+                    &lparent, &visit, &inode, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &chead, &cid,
+                    &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &pv, &pc, &dcnt, &dpos,
+                    &dsrc, &ddst, &dcost, &supply, &pairs};
+    all.assign(std::begin(list), std::end(list));
+  }
+};
+
+inline void check(Ctx& c, hipError_t e) {
+  if (e != hipSuccess) {
+    c.hip_err = (int)e;
+    throw StageError{W1_EHIP};
+  }
+}
+
+template <typename T>
+T* need(Ctx& c, DBuf& b, int64_t count) {
+  size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (bytes > b.cap) {
+    if (b.p) {
+      check(c, hipStreamSynchronize(c.st));
+      (void)hipFree(b.p);
+      b.p = nullptr;
+      b.cap = 0;
+    }
+    size_t want = std::max(bytes, b.cap + b.cap / 2);
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        throw StageError{W1_ENOMEM};
+      }
+      want = bytes;
+    }
+    b.cap = want;
+  }
+  return (T*)b.p;
+}
+
+// Grow while keeping the first `keep` elements.
+template <typename T>
+T* grow_keep(Ctx& c, DBuf& b, int64_t count, int64_t keep) {
+  size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+  if (bytes <= b.cap) return (T*)b.p;
+  DBuf nb;
+  T* np = need<T>(c, nb, count * 2);
+  if (keep > 0) check(c, hipMemcpyAsync(np, b.p, (size_t)keep * sizeof(T), hipMemcpyDeviceToDevice, c.st));
+  check(c, hipStreamSynchronize(c.st));
+  if (b.p) (void)hipFree(b.p);
+  b = nb;
+  return np;
+}
+
+template <typename T>
+inline void readback(Ctx& c, const T* dev, T* host, int64_t count) {
+  if (count <= 0) return;
+  check(c, hipMemcpyAsync(host, dev, (size_t)count * sizeof(T), hipMemcpyDeviceToHost, c.st));
+  check(c, hipStreamSynchronize(c.st));
+}
+
+// Small host -> device copy that completes before returning (the host
+// buffer may be released right after).
+inline void upload(Ctx& c, void* dev, const void* host, size_t bytes) {
+  if (!bytes) return;
+  check(c, hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c.st));
+  check(c, hipStreamSynchronize(c.st));
+}
+
+inline uint64_t read_u64(Ctx& c, const void* dev) {
+  check(c, hipMemcpyAsync(c.hpin, dev, 8, hipMemcpyDeviceToHost, c.st));
+  check(c, hipStreamSynchronize(c.st));
+  return c.hpin[0];
+}
+
+}  // namespace w1
+
+struct w1_ctx : w1::Ctx {};

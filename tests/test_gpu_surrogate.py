@@ -1,0 +1,222 @@
+"""GPU parity of the learned form, through the C-ABI.
+
+* forward: library embeddings against the oracle's FP64 network with the
+  library's BF16 rounding points (oracle/surrogate.py, emulate=True);
+* gradient: w1_surrogate_grad against the oracle's gradient;
+* training on the GPU: deterministic and the loss falls;
+* 1-NN: every search mode returns the oracle's exhaustive answer;
+* gain: with a trained surrogate, fewer RWMD evaluations than the plain
+  RWMD-ordered search, with the same answers.
+
+Tolerances (derived from the arithmetic, see the tests): FP32 accumulation
+of at most n + 130 terms per value gives a relative error of at most
+(n + 130) 2^-24 of the magnitude sum; for n <= 3001 that is < 2^-12.  The
+bound used is 2^-11 of the magnitude sum, which leaves room for the rare
+point whose h1 rounds to the other BF16 neighbour.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import surrogate as S
+import pdsynth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def w1():
+    import paper_2110_14734_amd as w1
+
+    return w1
+
+
+@pytest.fixture(scope="module")
+def ctx(w1):
+    c = w1.Context(0)
+    yield c
+    c.close()
+
+
+SIZES = [0, 1, 5, 15, 16, 17, 31, 32, 33, 63, 64, 65, 100, 257, 1000, 3001]
+
+
+def _diagrams(seed=500):
+    ds = []
+    for i, n in enumerate(SIZES):
+        ds.append(pdsynth.mixture_pd(n, seed + i) if n else np.zeros((0, 2), np.float32))
+    ds[4] = np.concatenate([ds[4], np.array([[0.5, 0.5], [0.25, 0.25]], np.float32)])  # diagonal points
+    return ds
+
+
+def _embed_scale(p, ds):
+    """Per-output magnitude sums: sum_u |W3[o,u]| sum_p (|h1| |W2|^T + |b2|)[p,u] + |b3[o]|."""
+    P = S.unpack(p)
+    W2b = S.bf16(P["W2"])
+    _, cache = S.forward(p, ds, emulate=True)
+    out = []
+    for x, h1, z2, pool in cache:
+        mz = (np.abs(h1) @ np.abs(W2b).T + np.abs(P["b2"])).sum(axis=0) if len(x) else np.zeros(128)
+        out.append(np.abs(P["W3"]) @ mz + np.abs(P["b3"]))
+    return np.array(out)
+
+
+def test_forward_parity(w1, ctx):
+    _say("surrogate forward parity")
+    sur = w1.Surrogate(ctx, seed=3)
+    p = sur.params
+    ds = _diagrams()
+    e_gpu = sur.embed(ds)
+    e_orc, _ = S.forward(p, ds, emulate=True)
+    tol = 2.0**-11 * _embed_scale(p, ds)
+    err = np.abs(e_gpu.astype(np.float64) - e_orc)
+    assert np.all(err <= tol), (err / tol).max()
+    # FP64 inputs of the same points give the same embedding
+    ds64 = [d.astype(np.float64) for d in ds]
+    assert np.array_equal(sur.embed(ds64), e_gpu)
+    # repeatable bit for bit
+    assert np.array_equal(sur.embed(ds), e_gpu)
+    # an empty diagram embeds to W3 * 0 + b3
+    assert np.array_equal(e_gpu[0], p[S.OFF_B3:].astype(np.float32))
+
+
+def test_forward_parity_device_inputs(w1, ctx):
+    import torch
+
+    _say("surrogate forward, device inputs")
+    sur = w1.Surrogate(ctx, seed=4)
+    ds = _diagrams(700)
+    e_host = sur.embed(ds)
+    e_dev = sur.embed([torch.from_numpy(np.ascontiguousarray(d)).cuda() for d in ds])
+    assert np.array_equal(e_host, e_dev)
+
+
+def test_gradient_parity(w1, ctx):
+    _say("surrogate gradient parity")
+    sur = w1.Surrogate(ctx, seed=5)
+    rng = np.random.default_rng(6)
+    p = sur.params.copy()
+    p[S.OFF_W3:S.OFF_B3] = rng.uniform(-0.02, 0.02, 64 * 128).astype(np.float32)
+    p[S.OFF_B2:S.OFF_W3] = rng.uniform(-0.05, 0.05, 128).astype(np.float32)
+    sur.params = p
+    ds = [pdsynth.mixture_pd(n, 900 + i) for i, n in enumerate((40, 17, 300, 96, 1, 130, 33, 64))]
+    pa = np.array([0, 1, 2, 3, 4, 5, 6, 0, 2, 7, 7, 3])
+    pb = np.array([1, 2, 3, 4, 5, 6, 7, 7, 5, 1, 2, 0])
+    w = rng.uniform(0.5, 5.0, len(pa))
+    loss_g, g_gpu = sur.grad(ds, pa, pb, w)
+    loss_o, g_orc = S.loss_grad(p, ds, pa, pb, w, emulate=True)
+    assert abs(loss_g - loss_o) <= 1e-4 * abs(loss_o)
+    spans = dict(W1=(S.OFF_W1, S.OFF_B1), b1=(S.OFF_B1, S.OFF_W2), W2=(S.OFF_W2, S.OFF_B2),
+                 b2=(S.OFF_B2, S.OFF_W3), W3=(S.OFF_W3, S.OFF_B3), b3=(S.OFF_B3, S.NPARAM))
+    gscale = np.linalg.norm(g_orc)
+    for name, (lo, hi) in spans.items():
+        a, b = g_gpu[lo:hi].astype(np.float64), g_orc[lo:hi]
+        # b3's exact gradient is zero (it cancels in e_a - e_b): the floor
+        # tied to the whole gradient's size covers tensors near zero
+        err = np.linalg.norm(a - b)
+        assert err <= 1e-3 * np.linalg.norm(b) + 1e-6 * gscale, (name, err, np.linalg.norm(b))
+
+
+def _family_db(m, n_fam, seed, lo=20, hi=120):
+    rng = np.random.default_rng(seed)
+    fams = [pdsynth.family_params(10_000 + seed * 1000 + f) for f in range(n_fam)]
+    sizes = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), m))).astype(int)
+    fid = rng.integers(0, n_fam, m)
+    return [pdsynth.family_pd(int(sizes[i]), seed * 100_000 + i, fams[fid[i]]) for i in range(m)], fams, rng
+
+
+def _labels(ctx, ds, pairs, eps=0.1, chunk=256):
+    out = []
+    for k in range(0, len(pairs), chunk):
+        part = pairs[k:k + chunk]
+        res = ctx.approx_batch([ds[i] for i, _ in part], [ds[j] for _, j in part], eps=eps)
+        out += [r.w1 for r in res]
+    return np.array(out)
+
+
+def test_training_deterministic_and_learns(w1, ctx):
+    _say("surrogate training")
+    ds, _, rng = _family_db(60, 8, 1)
+    pairs = [(int(i), int(j)) for i, j in rng.integers(0, len(ds), (400, 2)) if i != j]
+    w = _labels(ctx, ds, pairs)
+    keep = w > 0
+    pa = np.array([p[0] for p in pairs])[keep]
+    pb = np.array([p[1] for p in pairs])[keep]
+    w = w[keep]
+    runs = []
+    for _ in range(2):
+        sur = w1.Surrogate(ctx, seed=11)
+        losses = sur.train(ds, pa, pb, w, epochs=15, batch_pairs=64, lr=3e-3, seed=2)
+        runs.append((losses, sur.params))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    losses = runs[0][0]
+    assert np.all(np.isfinite(losses)) and losses[-1] < 0.5 * losses[0], losses
+
+
+def test_nn_answers_match_oracle(w1, ctx):
+    _say("1-NN answers vs oracle")
+    ds, fams, rng = _family_db(40, 6, 2, lo=15, hi=60)
+    qs = [pdsynth.family_pd(int(rng.integers(15, 60)), 777_000 + i, fams[i % len(fams)]) for i in range(5)]
+    qs.append(ds[7].copy())  # a database member: W1 = 0 at itself
+    sur = w1.Surrogate(ctx, seed=1)
+    idx = w1.NNIndex(ctx, ds, sur)
+    want = S.nn_exhaustive(ds, qs, eps=0.1)
+    for mode in ("exhaustive", "rwmd", "surrogate"):
+        r = idx.query(qs, eps=0.1, mode=mode)
+        assert [int(v) for v in r.nn] == [wi for wi, _ in want], mode
+        assert [float(v) for v in r.w1] == [wv for _, wv in want], mode
+        if mode == "exhaustive":
+            assert np.all(r.verifications == len(ds))
+        else:
+            assert np.all(r.verifications <= len(ds))
+    assert want[-1] == (7, 0.0)
+    idx.close()
+
+
+def test_nn_gain_with_trained_surrogate(w1, ctx):
+    """What the trained network gains over the method without it: the same
+    answers with fewer RWMD evaluations (the surrogate's first candidate
+    gives an incumbent that the dual bound prunes with)."""
+    _say("1-NN gain with a trained surrogate")
+    ds, fams, rng = _family_db(300, 20, 3, lo=30, hi=150)
+    m = len(ds)
+    rand = [(int(i), int(j)) for i, j in rng.integers(0, m, (3000, 2)) if i != j]
+    cand = rng.integers(0, m, (m, 10))
+    L = ctx.rwmd([ds[i] for i in range(m) for _ in range(10)], [ds[j] for j in cand.ravel()]).reshape(m, 10)
+    near = [(i, int(cand[i][np.argsort(L[i])[k]])) for i in range(m) for k in range(3)]
+    pairs = [p for p in rand + near if p[0] != p[1]]
+    w = _labels(ctx, ds, pairs)
+    keep = w > 0
+    pa = np.array([p[0] for p in pairs])[keep]
+    pb = np.array([p[1] for p in pairs])[keep]
+    sur = w1.Surrogate(ctx, seed=7)
+    losses = sur.train(ds, pa, pb, w[keep], epochs=30, batch_pairs=128, lr=3e-3, seed=5)
+    assert losses[-1] < losses[0]
+    qs = [pdsynth.family_pd(int(rng.integers(30, 150)), 888_000 + i, fams[int(rng.integers(0, 20))])
+          for i in range(24)]
+    idx = w1.NNIndex(ctx, ds, sur)
+    plain = idx.query(qs, eps=0.1, mode="rwmd")
+    learned = idx.query(qs, eps=0.1, mode="surrogate")
+    assert np.array_equal(plain.nn, learned.nn) and np.array_equal(plain.w1, learned.w1)
+    _say(f"plain: {plain.stats}")
+    _say(f"surrogate: {learned.stats}")
+    assert plain.stats["rwmd_evals"] == len(qs) * m
+    assert learned.stats["rwmd_evals"] < 0.8 * plain.stats["rwmd_evals"]
+    assert learned.stats["verifications"] <= plain.stats["verifications"] + len(qs)
+    idx.close()
+
+
+def test_invalid_inputs(w1, ctx):
+    sur = w1.Surrogate(ctx, seed=0)
+    bad = np.array([[0.5, 0.2]], np.float32)
+    with pytest.raises(w1.W1Error) as e:
+        sur.embed([bad])
+    assert e.value.code == w1.W1_EINVAL
+    with pytest.raises(w1.W1Error):
+        sur.grad([pdsynth.exp_pd(5, 1)] * 2, [0], [1], [0.0])  # label must be > 0
+    with pytest.raises(w1.W1Error):
+        w1.NNIndex(ctx, [bad])
