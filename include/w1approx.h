@@ -183,8 +183,31 @@ int w1_rwmd(w1_ctx *ctx, const w1_pd *a, const w1_pd *b, int64_t k, uint32_t fla
             double *L_out);
 
 /* Device pointers to the network of pair k of the last call on ctx
- * (requires that call to have been made without W1_COUNT_ONLY). */
+ * (requires that call to have been made without W1_COUNT_ONLY, and pair k
+ * to be in the call's last launch group, see w1_tuning). */
 int w1_device_network_get(w1_ctx *ctx, int64_t k, w1_device_network *out);
+
+/* Tunables of the WSPD traversal and of batching (Alg. 4-6 run as a
+ * persistent traversal over a work list of node pairs):
+ *   stack_depth    per-lane DFS stack entries in LDS (8..32); work-list items
+ *                  are expanded until the tree heights of their two nodes sum
+ *                  to less than this;
+ *   work_cap       items are expanded until |U| |V| <= work_cap (cells);
+ *   chunk_items    work-list items per chunk of the persistent passes;
+ *   blocks_per_cu  resident blocks per compute unit of those passes (1..16);
+ *   max_points_per_launch  w1_approx_batch runs its pairs in launch groups of
+ *                  consecutive pairs holding at most this many points (a
+ *                  single larger pair forms its own group).  This bounds the
+ *                  device memory of one launch.
+ * Results do not depend on any of these (pairs are emitted in a canonical
+ * order).  set_tuning returns W1_EINVAL for out-of-range values. */
+typedef struct {
+  int32_t stack_depth, work_cap, chunk_items, blocks_per_cu;
+  int64_t max_points_per_launch;
+} w1_tuning;
+
+int w1_ctx_get_tuning(const w1_ctx *ctx, w1_tuning *out);
+int w1_ctx_set_tuning(w1_ctx *ctx, const w1_tuning *t);
 
 /* Device times (ms, HIP events on the call's stream) of the last call's
  * WSPD kernels: [0] work-list build (expansion rounds, item sort, chunking),

@@ -75,6 +75,11 @@ class _TrainParams(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("stack_depth", ctypes.c_int32), ("work_cap", ctypes.c_int32), ("chunk_items", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("max_points_per_launch", ctypes.c_int64)]
+
+
 class _NNParams(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("mode", ctypes.c_int32), ("seed_k", ctypes.c_int32)]
 
@@ -93,6 +98,7 @@ NN_MODES = {"rwmd": NN_RWMD, "surrogate": NN_SURROGATE, "exhaustive": NN_EXHAUST
 # Every symbol include/w1approx.h declares.
 EXPORTS = ("w1_ctx_create", "w1_ctx_destroy", "w1_ctx_hip_error", "w1_ctx_last_kernel_times", "w1_approx",
            "w1_approx_batch", "w1_rwmd", "w1_device_network_get", "w1_flow_solve", "w1_separation_for_eps",
+           "w1_ctx_get_tuning", "w1_ctx_set_tuning",
            "w1_result_free", "w1_strerror", "w1_surrogate_create", "w1_surrogate_destroy",
            "w1_surrogate_get_params", "w1_surrogate_set_params", "w1_surrogate_embed", "w1_surrogate_grad",
            "w1_surrogate_train", "w1_surrogate_last_times", "w1_nn_build", "w1_nn_destroy", "w1_nn_query")
@@ -128,6 +134,8 @@ def lib():
         L.w1_flow_solve.argtypes = [i64, i64, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp, vp, ctypes.POINTER(i64),
                                     ctypes.POINTER(ctypes.c_int32)]
         L.w1_ctx_last_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
+        L.w1_ctx_get_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
+        L.w1_ctx_set_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
         L.w1_separation_for_eps.argtypes = [ctypes.c_double, ctypes.c_double]
         L.w1_result_free.argtypes = [ctypes.POINTER(_Result)]
         L.w1_result_free.restype = None
@@ -369,6 +377,24 @@ class Context:
         if rc != 0:
             raise W1Error(rc, "w1_rwmd")
         return out
+
+    @property
+    def tuning(self) -> dict:
+        """WSPD traversal and batching tunables (see w1_tuning)."""
+        t = _Tuning()
+        rc = lib().w1_ctx_get_tuning(self._h, ctypes.byref(t))
+        if rc != 0:
+            raise W1Error(rc, "w1_ctx_get_tuning")
+        return {f: getattr(t, f) for f, _ in _Tuning._fields_}
+
+    @tuning.setter
+    def tuning(self, v: dict):
+        cur = self.tuning
+        cur.update(v)
+        t = _Tuning(*(int(cur[f]) for f, _ in _Tuning._fields_))
+        rc = lib().w1_ctx_set_tuning(self._h, ctypes.byref(t))
+        if rc != 0:
+            raise W1Error(rc, "w1_ctx_set_tuning")
 
     def kernel_times(self) -> dict:
         """HIP-event times (ms) of the last call's WSPD kernels."""

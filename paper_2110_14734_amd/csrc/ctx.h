@@ -30,6 +30,8 @@ struct Ctx {
   hipStream_t st = nullptr;
   uint64_t* hpin = nullptr;  // pinned host scratch for read-backs
   WspdTuning tun{16, 1024, 512, 5};
+  int64_t max_points = int64_t(1) << 22;  // points per launch group of a batch
+  int64_t K_base = 0;                      // first pair of the last launch group
   std::vector<DBuf*> all;
   // points
   DBuf stage, segs, pb, pd, psd, kw0, kw1, kw2, kA, kB, vA, vB, head, idx, scantmp, sorttmp, small;

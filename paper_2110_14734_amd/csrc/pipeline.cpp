@@ -691,26 +691,44 @@ int entry(Ctx* c, const w1_pd* a, const w1_pd* b, int64_t K, const w1_params* pa
   }
   if (!(o.eps > 0.0 && o.eps <= 1.0) || !(o.kappa > 0.0 && o.kappa < 0.5)) return W1_EINVAL;
   if (hipSetDevice(c->device) != hipSuccess) return W1_EHIP;
+  if (out) std::memset(out, 0, sizeof(w1_result) * (size_t)K);
   try {
-    int rc = run(*c, a, b, K, o, (hipStream_t)stream, out, L_only);
-    if (rc != W1_OK || L_only) return rc;
-    const bool want_flow = !(o.flags & (W1_COUNT_ONLY | W1_NO_FLOW));
-    const bool keep = (o.flags & W1_KEEP_NETWORK) != 0;
-    if (want_flow || keep) {
+    // Launch groups: consecutive pairs whose points fit the per-launch
+    // budget (a single pair may exceed it).  Every stage runs once per group.
+    for (int64_t g0 = 0; g0 < K;) {
+      int64_t g1 = g0, pts = 0;
+      while (g1 < K && (g1 == g0 || pts + a[g1].n + b[g1].n <= c->max_points)) {
+        pts += a[g1].n + b[g1].n;
+        ++g1;
+      }
+      const int64_t Kg = g1 - g0;
+      w1_result* og = out ? out + g0 : nullptr;
+      c->K_base = g0;
+      int rc = run(*c, a + g0, b + g0, Kg, o, (hipStream_t)stream, og, L_only ? L_only + g0 : nullptr);
+      if (rc != W1_OK) {
+        if (out)
+          for (int64_t p = g1; p < K; ++p) out[p].status = rc;
+        return rc;
+      }
+      g0 = g1;
+      if (L_only) continue;
+      const bool want_flow = !(o.flags & (W1_COUNT_ONLY | W1_NO_FLOW));
+      const bool keep = (o.flags & W1_KEEP_NETWORK) != 0;
+      if (!(want_flow || keep)) continue;
       auto t0 = std::chrono::steady_clock::now();
-      for (int64_t p = 0; p < K; ++p)
-        if (out[p].status == 0 && out[p].n_points > 0) copy_network(*c, p, out[p]);
+      for (int64_t p = 0; p < Kg; ++p)
+        if (og[p].status == 0 && og[p].n_points > 0) copy_network(*c, p, og[p]);
       auto t1 = std::chrono::steady_clock::now();
       double d2h = std::chrono::duration<double, std::milli>(t1 - t0).count();
       if (want_flow) {
         unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-        unsigned nt = (unsigned)std::min<int64_t>(K, std::min(hw, 16u));
+        unsigned nt = (unsigned)std::min<int64_t>(Kg, std::min(hw, 16u));
         std::atomic<int64_t> next{0};
         auto worker = [&]() {
           for (;;) {
             int64_t p = next.fetch_add(1);
-            if (p >= K) break;
-            if (out[p].status == 0 && out[p].n_points > 0) solve_flow(out[p], o.pivot_cap);
+            if (p >= Kg) break;
+            if (og[p].status == 0 && og[p].n_points > 0) solve_flow(og[p], o.pivot_cap);
           }
         };
         std::vector<std::thread> th;
@@ -720,10 +738,10 @@ int entry(Ctx* c, const w1_pd* a, const w1_pd* b, int64_t K, const w1_params* pa
       }
       auto t2 = std::chrono::steady_clock::now();
       double fl = std::chrono::duration<double, std::milli>(t2 - t1).count();
-      for (int64_t p = 0; p < K; ++p) {
-        out[p].t_ms[W1_T_D2H] = d2h;
-        out[p].t_ms[W1_T_FLOW] = fl;
-        if (!keep) free_network(out[p]);
+      for (int64_t p = 0; p < Kg; ++p) {
+        og[p].t_ms[W1_T_D2H] = d2h;
+        og[p].t_ms[W1_T_FLOW] = fl;
+        if (!keep) free_network(og[p]);
       }
     }
     return W1_OK;
@@ -781,11 +799,6 @@ int w1_ctx_create(int device, w1_ctx** out) {
       delete c;
       return W1_EHIP;
     }
-  if (const char* e = std::getenv("W1_WSPD_TUNING")) {
-    int a, b2, d, f;
-    if (std::sscanf(e, "%d,%d,%d,%d", &a, &b2, &d, &f) == 4 && a >= 4 && a <= 64 && b2 >= 1 && d >= 1 && f >= 1)
-      c->tun = WspdTuning{a, b2, d, f};
-  }
   *out = c;
   return W1_OK;
 }
@@ -821,7 +834,9 @@ int w1_rwmd(w1_ctx* c, const w1_pd* a, const w1_pd* b, int64_t k, uint32_t flags
 }
 
 int w1_device_network_get(w1_ctx* c, int64_t k, w1_device_network* out) {
-  if (!c || !out || k < 0 || k >= c->K || !c->network_valid) return W1_EINVAL;
+  if (!c || !out || !c->network_valid) return W1_EINVAL;
+  k -= c->K_base;
+  if (k < 0 || k >= c->K) return W1_EINVAL;
   const int64_t cs = c->h_cell_start[(size_t)k], ps = c->h_pair_start[(size_t)k], ds = c->h_diag_start[(size_t)k];
   out->n_cells = c->h_ncells[(size_t)k];
   out->n_pairs = c->h_npairs[(size_t)k];
@@ -836,6 +851,27 @@ int w1_device_network_get(w1_ctx* c, int64_t k, w1_device_network* out) {
   out->diag_src = (const uint32_t*)c->dsrc.p + ds;
   out->diag_dst = (const uint32_t*)c->ddst.p + ds;
   out->diag_cost = (const int32_t*)c->dcost.p + ds;
+  return W1_OK;
+}
+
+int w1_ctx_get_tuning(const w1_ctx* c, w1_tuning* out) {
+  if (!c || !out) return W1_EINVAL;
+  out->stack_depth = c->tun.stack_depth;
+  out->work_cap = c->tun.work_cap;
+  out->chunk_items = c->tun.chunk_items;
+  out->blocks_per_cu = c->tun.blocks_per_cu;
+  out->max_points_per_launch = c->max_points;
+  return W1_OK;
+}
+
+int w1_ctx_set_tuning(w1_ctx* c, const w1_tuning* t) {
+  if (!c || !t) return W1_EINVAL;
+  if (t->stack_depth < 8 || t->stack_depth > 32 || t->work_cap < 1 || t->work_cap > (1 << 20) ||
+      t->chunk_items < 1 || t->chunk_items > (1 << 20) || t->blocks_per_cu < 1 || t->blocks_per_cu > 16 ||
+      t->max_points_per_launch < 1)
+    return W1_EINVAL;
+  c->tun = WspdTuning{t->stack_depth, t->work_cap, t->chunk_items, t->blocks_per_cu};
+  c->max_points = t->max_points_per_launch;
   return W1_OK;
 }
 
