@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--no-nn", action="store_true", help="skip the learned form (surrogate + 1-NN)")
+    ap.add_argument("--no-nn-search", action="store_true",
+                    help="learned form: only the embedding workload (no labels, training or 1-NN search)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--batch-pairs", type=int, default=4096)
     ap.add_argument("--loop-sample", type=int, default=256,
@@ -162,6 +164,8 @@ def run_nn(ctx, args):
     del big_dev, big
     sur0.close()
     torch.cuda.synchronize()
+    if args.no_nn_search:
+        return out
 
     # (2) 1-NN search on a database whose exact-flow verifications are affordable
     m, nq = args.nn_db, args.nn_queries

@@ -155,8 +155,7 @@ typedef struct {
   const int32_t *cell_ij; /* 2 per cell: i, j */
   const int32_t *cell_ca, *cell_cb;
   const int64_t *supply;
-  const uint32_t *pair_u, *pair_v;
-  const int32_t *pair_cost;
+  const uint32_t *pairs; /* 3 per pair: u, v, cost (12-byte records) */
   const uint32_t *diag_src, *diag_dst;
   const int32_t *diag_cost;
 } w1_device_network;

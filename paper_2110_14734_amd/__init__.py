@@ -65,8 +65,8 @@ class _Result(ctypes.Structure):
 
 class _DevNet(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_diag", ctypes.c_int64),
-                ("cell_ij", _P), ("cell_ca", _P), ("cell_cb", _P), ("supply", _P), ("pair_u", _P),
-                ("pair_v", _P), ("pair_cost", _P), ("diag_src", _P), ("diag_dst", _P), ("diag_cost", _P)]
+                ("cell_ij", _P), ("cell_ca", _P), ("cell_cb", _P), ("supply", _P), ("pairs", _P),
+                ("diag_src", _P), ("diag_dst", _P), ("diag_cost", _P)]
 
 
 class _TrainParams(ctypes.Structure):

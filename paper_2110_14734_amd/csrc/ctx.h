@@ -44,7 +44,7 @@ struct Ctx {
   // wspd
   DBuf itemsA, itemsB, itemsI, itemsS, icnt, ipos, ipp, chead, cid, cfirst, cend, cpairs, ccnt, coff, xrange, xctr, err;
   // network
-  DBuf pu, pv, pc, dcnt, dpos, dsrc, ddst, dcost, supply;
+  DBuf pu, dcnt, dpos, dsrc, ddst, dcost, supply;  // pu: 12-byte pair records (u, v, cost)
   // per pair
   DBuf pairs;
   PairArrays P{};
@@ -60,7 +60,7 @@ struct Ctx {
                     &small, &gb, &gd, &gpair, &gw, &lb, &ld, &lw, &lpair, &lt, &lterm, &lbin, &li, &lj, &nbuck,
                     &bincnt, &binstart, &ent, &ckey, &cpair, &cij, &ca, &cb, &iaux, &ibox, &iheight, &iparent,
                     &lparent, &visit, &inode, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &chead, &cid,
-                    &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &pv, &pc, &dcnt, &dpos,
+                    &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &dcnt, &dpos,
                     &dsrc, &ddst, &dcost, &supply, &pairs};
     all.assign(std::begin(list), std::end(list));
   }

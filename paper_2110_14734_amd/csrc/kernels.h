@@ -72,8 +72,8 @@ void launch_diag_fill(const uint32_t* cpair, const int2* cij, const int32_t* ca,
 // Tree view used by the WSPD traversal.  Node reference r >= 0 is internal
 // node r, r < 0 is the leaf of cell ~r.
 struct TreeView {
-  const int4* inode;    // internal, 3 int4 per node: box; left, right, lo, hi;
-                        // rep_i, rep_j, height, 0 (packed for the traversal)
+  const int4* inode;    // traversal records, 2 int4 each: N - 1 internal nodes
+                        // then N cells (see k_pack_nodes)
   const int4* ibox;     // internal: min_i, min_j, max_i, max_j
   const int4* iaux;     // internal: left, right, lo, hi
   const int32_t* iheight;
@@ -89,7 +89,7 @@ struct WspdTuning {
   int blocks_per_cu;
 };
 
-void launch_pack_nodes(const TreeView& T, int4* inode, hipStream_t st);
+void launch_pack_nodes(const TreeView& T, int4* rec, hipStream_t st);
 void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st);
 void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st);
 void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s, const WspdTuning& tun,
@@ -107,8 +107,7 @@ void launch_chunk_fill(const TreeView& T, const int2* items, int64_t m, const in
 void launch_wspd_pass(bool emit, const TreeView& T, const int2* items, const int32_t* chunk_first,
                       const int32_t* chunk_end, const int32_t* chunk_pair, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
-                      const int64_t* cell_start, uint32_t* pu, uint32_t* pv, int32_t* pc, int32_t* err,
-                      int num_cus, hipStream_t st);
+                      const int64_t* cell_start, uint32_t* out, int32_t* err, int num_cus, hipStream_t st);
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         const int32_t* chunk_first, const int64_t* item_start, int64_t nchunks, uint64_t* npairs,
                         uint64_t* pair_start, hipStream_t st);

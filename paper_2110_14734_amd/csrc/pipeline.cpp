@@ -346,7 +346,8 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     T.ibox = ibox;
     T.iaux = iaux;
     T.iheight = ih;
-    int4* inode = need<int4>(c, c.inode, 3 * (N - 1));
+    if (N >= (int64_t(1) << 30)) throw StageError{W1_ERANGE};  // record split field holds 30 bits
+    int4* inode = need<int4>(c, c.inode, 2 * (2 * N - 1));
     launch_pack_nodes(T, inode, st);
     T.inode = inode;
     check(c, hipGetLastError());
@@ -446,8 +447,8 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       uint64_t* coff = need<uint64_t>(c, c.coff, nch);
       fill_u32(xc, 0, 8, st);
       check(c, hipEventRecord(c.kev[1], st));
-      launch_wspd_pass(false, T, S, cf, ce, cp, nch, xr, xc, s, tun, ccnt, coff, P.cell_start, nullptr, nullptr,
-                       nullptr, derr, c.num_cus, st);
+      launch_wspd_pass(false, T, S, cf, ce, cp, nch, xr, xc, s, tun, ccnt, coff, P.cell_start, nullptr, derr,
+                       c.num_cus, st);
       check(c, hipGetLastError());
       check(c, hipEventRecord(c.kev[2], st));
       scan_u64(ccnt, coff, nch, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(nch, 8)), st);
@@ -458,12 +459,10 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       trace(c, "wspd pairs", Ptot);
       launch_pair_totals(ccnt, coff, cp, cf, P.item_start, nch, P.npairs, P.pair_start, st);
       if (!(o.flags & W1_COUNT_ONLY) && Ptot > 0) {
-        uint32_t* pu = need<uint32_t>(c, c.pu, Ptot);
-        uint32_t* pv = need<uint32_t>(c, c.pv, Ptot);
-        int32_t* pc = need<int32_t>(c, c.pc, Ptot);
+        uint32_t* pout = need<uint32_t>(c, c.pu, 3 * Ptot);
         fill_u32(xc, 0, 8, st);
         check(c, hipEventRecord(c.kev[3], st));
-        launch_wspd_pass(true, T, S, cf, ce, cp, nch, xr, xc, s, tun, ccnt, coff, P.cell_start, pu, pv, pc, derr,
+        launch_wspd_pass(true, T, S, cf, ce, cp, nch, xr, xc, s, tun, ccnt, coff, P.cell_start, pout, derr,
                          c.num_cus, st);
         check(c, hipGetLastError());
         emitted = true;
@@ -621,10 +620,18 @@ void copy_network(Ctx& c, int64_t p, w1_result& r) {
   } else {
     r.supply[0] = r.supply[1] = 0;
   }
-  if (np > 0) {
-    readback(c, (const uint32_t*)c.pu.p + ps, r.pair_u, np);
-    readback(c, (const uint32_t*)c.pv.p + ps, r.pair_v, np);
-    readback(c, (const int32_t*)c.pc.p + ps, r.pair_cost, np);
+  if (np > 0) {  // 12-byte device records (u, v, cost) -> three host arrays
+    const int64_t blk = int64_t(1) << 22;
+    std::vector<uint32_t> rec((size_t)(3 * std::min(np, blk)));
+    for (int64_t q0 = 0; q0 < np; q0 += blk) {
+      const int64_t nq = std::min(blk, np - q0);
+      readback(c, (const uint32_t*)c.pu.p + 3 * (ps + q0), rec.data(), 3 * nq);
+      for (int64_t q = 0; q < nq; ++q) {
+        r.pair_u[q0 + q] = rec[(size_t)(3 * q)];
+        r.pair_v[q0 + q] = rec[(size_t)(3 * q + 1)];
+        r.pair_cost[q0 + q] = (int32_t)rec[(size_t)(3 * q + 2)];
+      }
+    }
   }
   if (nd > 0) {
     readback(c, (const uint32_t*)c.dsrc.p + ds, r.diag_src, nd);
@@ -845,9 +852,7 @@ int w1_device_network_get(w1_ctx* c, int64_t k, w1_device_network* out) {
   out->cell_ca = (const int32_t*)c->ca.p + cs;
   out->cell_cb = (const int32_t*)c->cb.p + cs;
   out->supply = (const int64_t*)c->supply.p + cs + 2 * k;
-  out->pair_u = (const uint32_t*)c->pu.p + ps;
-  out->pair_v = (const uint32_t*)c->pv.p + ps;
-  out->pair_cost = (const int32_t*)c->pc.p + ps;
+  out->pairs = (const uint32_t*)c->pu.p + 3 * ps;
   out->diag_src = (const uint32_t*)c->dsrc.p + ds;
   out->diag_dst = (const uint32_t*)c->ddst.p + ds;
   out->diag_cost = (const int32_t*)c->dcost.p + ds;

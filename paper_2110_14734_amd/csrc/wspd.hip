@@ -153,78 +153,89 @@ __global__ void k_chunk_fill(TreeView T, const int2* __restrict__ items, int64_t
   chunk_pair[c] = (int32_t)p;
 }
 
-// Packed node record for the traversal: box, children, representative
-// (first cell in Morton order) and the representative's coordinates.
+// Packed node record for the traversal, 32 bytes, one format for internal
+// nodes and cells: int4 box (min i, min j, max i, max j) and int4 aux =
+// (representative cell, split | left-is-cell << 30 | right-is-cell << 31,
+// representative i, representative j).  Internal node r has split g: its
+// children are g and g + 1 (cells or internal nodes, per the two flags).
+// Record index: internal node r -> r, cell c -> (N - 1) + c.
 struct Rec {
-  int4 box;
-  int left, right;
-  int rep, ri, rj;
+  int4 box, aux;
 };
 
-__device__ inline Rec load_rec(const TreeView& T, int32_t r) {
-  Rec q;
-  if (r >= 0) {
-    const int4* p = T.inode + 3 * (int64_t)r;
-    const int4 b = p[0], a = p[1], x = p[2];
-    q.box = b;
-    q.left = a.x;
-    q.right = a.y;
-    q.rep = a.z;
-    q.ri = x.x;
-    q.rj = x.y;
-  } else {
-    const int2 c = T.cij[~r];
-    q.box = make_int4(c.x, c.y, c.x, c.y);
-    q.left = q.right = 0;
-    q.rep = ~r;
-    q.ri = c.x;
-    q.rj = c.y;
-  }
-  return q;
+__device__ inline Rec load_rec(const int4* __restrict__ R, int32_t r, int32_t nint) {
+  const int64_t i = r >= 0 ? (int64_t)r : (int64_t)nint + ~r;
+  const int4* p = R + 2 * i;
+  return Rec{p[0], p[1]};
+}
+__device__ inline int32_t rec_left(const Rec& q) {
+  const uint32_t f = (uint32_t)q.aux.y;
+  const int32_t g = (int32_t)(f & 0x3fffffffu);
+  return (f >> 30) & 1u ? ~g : g;
+}
+__device__ inline int32_t rec_right(const Rec& q) {
+  const uint32_t f = (uint32_t)q.aux.y;
+  const int32_t g = (int32_t)(f & 0x3fffffffu) + 1;
+  return (f >> 31) ? ~g : g;
 }
 
-__global__ void k_pack_nodes(TreeView T, int4* __restrict__ inode) {
+__global__ void k_pack_nodes(TreeView T, int4* __restrict__ rec) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= T.N - 1) return;
-  const int4 a = T.iaux[r];
-  const int2 c = T.cij[a.z];
-  inode[3 * r] = T.ibox[r];
-  inode[3 * r + 1] = a;
-  inode[3 * r + 2] = make_int4(c.x, c.y, T.iheight[r], 0);
+  const int64_t nint = T.N - 1;
+  if (r >= nint + T.N) return;
+  if (r < nint) {
+    const int4 a = T.iaux[r];  // left, right, lo, hi
+    const int32_t g = a.x >= 0 ? a.x : ~a.x;
+    const uint32_t f = (uint32_t)g | (a.x < 0 ? 1u << 30 : 0u) | (a.y < 0 ? 1u << 31 : 0u);
+    const int2 c = T.cij[a.z];
+    rec[2 * r] = T.ibox[r];
+    rec[2 * r + 1] = make_int4(a.z, (int)f, c.x, c.y);
+  } else {
+    const int32_t cell = (int32_t)(r - nint);
+    const int2 c = T.cij[cell];
+    rec[2 * r] = make_int4(c.x, c.y, c.x, c.y);
+    rec[2 * r + 1] = make_int4(cell, 0, c.x, c.y);
+  }
 }
 
-// One emitted pair of a lane in a step.
-struct Emit {
-  int u, v, c;
-};
-__device__ inline Emit make_emit(const Rec& a, const Rec& b) {
-  return Emit{a.rep, b.rep, 2 * max(abs(a.ri - b.ri), abs(a.rj - b.rj))};
+// Three-word pair record.  The vector type is 16 bytes in size (its store is
+// 12), so records are addressed in 32-bit words, never by u32x3 arithmetic.
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+typedef u32x3 u32x3_w __attribute__((aligned(4)));
+
+// One emitted pair: (rep U - cell base, rep V - cell base, cost).
+__device__ inline u32x3 make_emit(const Rec& a, const Rec& b, int64_t cs) {
+  const int c = 2 * max(abs(a.aux.z - b.aux.z), abs(a.aux.w - b.aux.w));
+  return u32x3{(uint32_t)(a.aux.x - cs), (uint32_t)(b.aux.x - cs), (uint32_t)c};
 }
 
 // Count pass (EMIT = false) and emit pass (EMIT = true) of the WSPD search
-// over the chunks of the work list.  Lane state: an item known to be not
-// separated ("current"), or none.  A step splits the current item's node with
-// the longer box side, loads both children and tests both child pairs at
-// once (one dependent memory round trip resolves two recursion nodes);
-// separated child pairs are emitted, a non-separated one becomes current and
-// a second non-separated one is pushed on the lane's LDS stack.  Lanes
-// without work pop their stack or take fresh items from the chunk (fresh
-// items are tested first).  At most two pairs per lane per step, written at
-// the wave cursor in (slot, lane) order, so the order depends only on the
-// chunk.  Loop control lives in wave-uniform scalars.
+// over the chunks of the work list.  Lane state: a node pair known to be not
+// separated ("current"), or none.  A step first lets every lane without a
+// current pair acquire one (pop its LDS stack, else take a fresh item from
+// the chunk) through a single record-load path; fresh items are tested.  Then
+// each current pair splits the node with the longer box side, loads both
+// children and tests both child pairs (one dependent memory round trip
+// resolves two recursion nodes): separated child pairs are emitted, a
+// non-separated one becomes current and a second one goes on the stack.  At
+// most two pairs per lane per step, written as 12-byte records at the wave
+// cursor in (slot, lane) order, so the order depends only on the chunk.
+// Loop control lives in wave-uniform scalars.
 template <bool EMIT>
 __global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict__ items,
                                               const int32_t* __restrict__ chunk_first, const int32_t* __restrict__ chunk_end,
                                               const int32_t* __restrict__ chunk_pair, const int32_t* __restrict__ xcd_range,
                                               uint32_t* __restrict__ xcd_ctr, int s, int stack_depth, int64_t step_cap,
                                               uint64_t* __restrict__ chunk_cnt, const uint64_t* __restrict__ chunk_off,
-                                              const int64_t* __restrict__ cell_start, uint32_t* __restrict__ pu,
-                                              uint32_t* __restrict__ pv, int32_t* __restrict__ pc, int32_t* __restrict__ err) {
+                                              const int64_t* __restrict__ cell_start, uint32_t* __restrict__ out,
+                                              int32_t* __restrict__ err) {
   extern __shared__ int2 s_stack[];
   const int wave = threadIdx.x / WAVE, lane = lane_id();
   int2* stk = s_stack + (size_t)wave * stack_depth * WAVE;
   const uint64_t below = lanes_below();
   const int xcd = blockIdx.x & 7;
+  const int4* __restrict__ R = T.inode;
+  const int32_t nint = (int32_t)(T.N - 1);
   for (int probe = 0; probe < 8; ++probe) {
     const int xr = (xcd + probe) & 7;
     const int r0 = xcd_range[xr], r1 = xcd_range[xr + 1];
@@ -237,62 +248,65 @@ __global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict
       int next = __builtin_amdgcn_readfirstlane(chunk_first[k]);
       const int end = __builtin_amdgcn_readfirstlane(chunk_end[k]);
       const int64_t cs = EMIT ? cell_start[chunk_pair[k]] : 0;
-      const uint64_t obase = EMIT ? chunk_off[k] : 0;
+      uint32_t* const obase = EMIT ? out + 3 * chunk_off[k] : nullptr;
       uint64_t cursor = 0;
       bool has = false, overflow = false, runaway = false;
       int sp = 0;
-      int32_t U = 0, V = 0;
       Rec RU{}, RV{};
+      int32_t U = 0, V = 0;
       for (int64_t step = 0;; ++step) {
         if (step > step_cap) {  // beyond any chunk's possible work: give up, report
           runaway = true;
           break;
         }
-        if (!has && sp > 0) {
-          --sp;
-          const int2 q = stk[sp * WAVE + lane];
-          U = q.x;
-          V = q.y;
-          RU = load_rec(T, U);
-          RV = load_rec(T, V);
-          has = true;
-        }
-        const uint64_t need = __ballot(!has);
+        // acquire: stack first, then fresh items in lane order
+        const bool want = !has;
+        const uint64_t need = __ballot(want && sp == 0);
         const int avail = end - next;
-        bool fresh = false;
-        if (!has) {
-          const int r = __popcll(need & below);
-          if (r < avail) {
-            const int2 q = items[next + r];
-            U = q.x;
-            V = q.y;
-            RU = load_rec(T, U);
-            RV = load_rec(T, V);
-            fresh = true;
+        bool got = false, fresh = false;
+        int2 q = make_int2(0, 0);
+        if (want) {
+          if (sp > 0) {
+            --sp;
+            q = stk[sp * WAVE + lane];
+            got = true;
+          } else {
+            const int r = __popcll(need & below);
+            if (r < avail) {
+              q = items[next + r];
+              got = fresh = true;
+            }
           }
         }
         const int took = __popcll(need);
         next += took < avail ? took : (avail > 0 ? avail : 0);
-        if (__ballot(has || fresh) == 0) break;
+        if (got) {
+          U = q.x;
+          V = q.y;
+          RU = load_rec(R, U, nint);
+          RV = load_rec(R, V, nint);
+        }
+        if (__ballot(has || got) == 0) break;
         bool e1 = false, e2 = false;
-        Emit m1{0, 0, 0}, m2{0, 0, 0};
-        if (fresh) {
-          if (separated(RU.box, RV.box, s)) {
+        u32x3 m1, m2;
+        if (got) {
+          has = true;
+          if (fresh && separated(RU.box, RV.box, s)) {
             e1 = true;
-            if (EMIT) m1 = make_emit(RU, RV);
-          } else {
-            has = true;
+            has = false;
+            if (EMIT) m1 = make_emit(RU, RV, cs);
           }
         }
         if (has) {
           const bool splitU = box_diam(RU.box) > box_diam(RV.box);
-          const int c1 = splitU ? RU.left : RV.left, c2 = splitU ? RU.right : RV.right;
-          const Rec C1 = load_rec(T, c1), C2 = load_rec(T, c2);
+          const Rec& P = splitU ? RU : RV;
+          const int32_t c1 = rec_left(P), c2 = rec_right(P);
+          const Rec C1 = load_rec(R, c1, nint), C2 = load_rec(R, c2, nint);
           const Rec O = splitU ? RV : RU;
           const bool s1 = separated(C1.box, O.box, s), s2 = separated(C2.box, O.box, s);
           if (EMIT) {
-            if (s1) m1 = splitU ? make_emit(C1, O) : make_emit(O, C1);
-            if (s2) m2 = splitU ? make_emit(C2, O) : make_emit(O, C2);
+            if (s1) m1 = splitU ? make_emit(C1, O, cs) : make_emit(O, C1, cs);
+            if (s2) m2 = splitU ? make_emit(C2, O, cs) : make_emit(O, C2, cs);
           }
           e1 = s1;
           e2 = s2;
@@ -305,32 +319,27 @@ __global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict
               overflow = true;
             }
           }
-          if (!s1) {
-            if (splitU) { U = c1; RU = C1; }
-            else { V = c1; RV = C1; }
-          } else if (!s2) {
-            if (splitU) { U = c2; RU = C2; }
-            else { V = c2; RV = C2; }
+          if (!s1 || !s2) {
+            const int32_t cn = !s1 ? c1 : c2;
+            const Rec& CN = !s1 ? C1 : C2;
+            if (splitU) {
+              U = cn;
+              RU = CN;
+            } else {
+              V = cn;
+              RV = CN;
+            }
           } else {
             has = false;
           }
         }
         const uint64_t b1 = __ballot(e1), b2 = __ballot(e2);
         if (EMIT) {
-          // streaming (non-temporal) stores: the output is written once and
-          // must not evict the tree from L2
-          if (e1) {
-            const uint64_t pos = obase + cursor + (uint64_t)__popcll(b1 & below);
-            __builtin_nontemporal_store((uint32_t)(m1.u - cs), pu + pos);
-            __builtin_nontemporal_store((uint32_t)(m1.v - cs), pv + pos);
-            __builtin_nontemporal_store(m1.c, pc + pos);
-          }
-          if (e2) {
-            const uint64_t pos = obase + cursor + (uint64_t)__popcll(b1) + (uint64_t)__popcll(b2 & below);
-            __builtin_nontemporal_store((uint32_t)(m2.u - cs), pu + pos);
-            __builtin_nontemporal_store((uint32_t)(m2.v - cs), pv + pos);
-            __builtin_nontemporal_store(m2.c, pc + pos);
-          }
+          // streaming (non-temporal) 12-byte stores: the output is written
+          // once and must not evict the tree from L2
+          const int n1 = __popcll(b1);
+          if (e1) __builtin_nontemporal_store(m1, (u32x3_w*)(obase + 3 * (cursor + __popcll(b1 & below))));
+          if (e2) __builtin_nontemporal_store(m2, (u32x3_w*)(obase + 3 * (cursor + n1 + __popcll(b2 & below))));
         }
         cursor += (uint64_t)(__popcll(b1) + __popcll(b2));
       }
@@ -359,7 +368,7 @@ inline unsigned blocks(int64_t n, int bs = 256) { return (unsigned)(n > 0 ? ceil
 #define LAUNCH(kern, n, ...) \
   do { if ((n) > 0) hipLaunchKernelGGL(kern, dim3(blocks(n)), dim3(256), 0, st, __VA_ARGS__); } while (0)
 
-void launch_pack_nodes(const TreeView& T, int4* inode, hipStream_t st) { LAUNCH(k_pack_nodes, T.N - 1, T, inode); }
+void launch_pack_nodes(const TreeView& T, int4* rec, hipStream_t st) { LAUNCH(k_pack_nodes, 2 * T.N - 1, T, rec); }
 void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st) { LAUNCH(k_roots_flags, T.N - 1, T, flag); }
 void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st) {
   LAUNCH(k_roots_fill, T.N - 1, T, flag, pos, items);
@@ -393,8 +402,7 @@ void launch_chunk_fill(const TreeView& T, const int2* items, int64_t m, const in
 void launch_wspd_pass(bool emit, const TreeView& T, const int2* items, const int32_t* chunk_first,
                       const int32_t* chunk_end, const int32_t* chunk_pair, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
-                      const int64_t* cell_start, uint32_t* pu, uint32_t* pv, int32_t* pc, int32_t* err,
-                      int num_cus, hipStream_t st) {
+                      const int64_t* cell_start, uint32_t* out, int32_t* err, int num_cus, hipStream_t st) {
   if (nchunks <= 0) return;
   int64_t grid = (int64_t)num_cus * tun.blocks_per_cu;
   grid = ((grid + 7) / 8) * 8;
@@ -404,12 +412,10 @@ void launch_wspd_pass(bool emit, const TreeView& T, const int2* items, const int
   const int64_t step_cap = (int64_t)tun.chunk_items * (2 * (int64_t)tun.work_cap + 2) + 1024;
   if (emit)
     hipLaunchKernelGGL(k_wspd<true>, dim3((unsigned)grid), dim3(256), lds, st, T, items, chunk_first, chunk_end,
-                       chunk_pair, xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, cell_start, pu, pv, pc,
-                       err);
+                       chunk_pair, xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, cell_start, out, err);
   else
     hipLaunchKernelGGL(k_wspd<false>, dim3((unsigned)grid), dim3(256), lds, st, T, items, chunk_first, chunk_end,
-                       chunk_pair, xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, cell_start, pu, pv, pc,
-                       err);
+                       chunk_pair, xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, cell_start, out, err);
 }
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         const int32_t* chunk_first, const int64_t* item_start, int64_t nchunks, uint64_t* npairs,
