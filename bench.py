@@ -257,12 +257,15 @@ def main():
         ctx.approx(tA, tB, eps=args.eps, flags=flags)
     torch.cuda.synchronize()
     emit_ms, stage = [], {k: 0.0 for k in w1.T_NAMES[:6]}
+    kern = {"worklist_ms": 0.0, "count_ms": 0.0, "emit_ms": 0.0}
     r = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
         r = ctx.approx(tA, tB, eps=args.eps, flags=flags)
         kt = ctx.kernel_times()
         emit_ms.append(kt["emit_ms"])
+        for k in kern:
+            kern[k] += kt[k] / args.steps
         for k in stage:
             stage[k] += r.t_ms[k] / args.steps
     torch.cuda.synchronize()
@@ -294,6 +297,7 @@ def main():
         "pd_pairs_per_s": args.steps / dt,
         "wspd_pairs_per_s": r.n_pairs / (dt / args.steps),
         "stage_ms": {k: round(v, 3) for k, v in stage.items()},
+        "wspd_kernel_ms": {k: round(v, 3) for k, v in kern.items()},
         "roofline": {
             "kernel": "k_wspd<emit> (WSPD pair emission)",
             "bound": "hbm",

@@ -20,6 +20,8 @@ struct PairArrays {
   int32_t* locA;         // number of A locations (net > 0)
   int32_t* locB;         // number of B locations (net < 0)
   int64_t* loc_start;    // first location index
+  int64_t* seg_lo;       // scratch: first index of the pair's run in a pair-major array
+  int64_t* seg_hi;       // scratch: one past its last index (both zeroed before use)
   uint64_t* bmin;        // bounding box of locations, ordered bit patterns
   uint64_t* bmax;
   uint64_t* dmin;

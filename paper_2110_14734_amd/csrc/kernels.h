@@ -56,6 +56,9 @@ void launch_cell_fill(const uint32_t* perm, const uint64_t* kw1s, const uint64_t
                       const uint32_t* cidx, const int64_t* li, const int64_t* lj, const int32_t* lw, int64_t M,
                       const PairArrays& P, uint64_t* ckey, uint32_t* cpair, int2* cij, int32_t* ca, int32_t* cb,
                       hipStream_t st);
+// pair-major runs: bounds of each pair's run, and their lengths
+void launch_run_bounds(const uint32_t* key, int64_t n, int64_t* lo, int64_t* hi, hipStream_t st);
+void launch_bounds_count32(const int64_t* lo, const int64_t* hi, int64_t K, int32_t* out, hipStream_t st);
 // a3
 void launch_karras(const uint32_t* cpair, const uint64_t* ckey, int64_t N, int4* iaux, int32_t* iparent,
                    int32_t* lparent, hipStream_t st);
@@ -98,7 +101,7 @@ void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const 
                          int2* out_items, int64_t out_base, int2* next, hipStream_t st);
 void launch_item_keys(const TreeView& T, const int2* items, int64_t m, bool both, uint64_t* keys, hipStream_t st);
 void launch_gather_items(const int2* src, const uint32_t* perm, int2* dst, int64_t m, hipStream_t st);
-void launch_item_pairs(const TreeView& T, const int2* items, int64_t m, int32_t* items_per_pair, hipStream_t st);
+void launch_item_bounds(const TreeView& T, const int2* items, int64_t m, int64_t* lo, int64_t* hi, hipStream_t st);
 void launch_chunk_heads(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start, int chunk,
                         uint32_t* head, hipStream_t st);
 void launch_chunk_fill(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start,
@@ -109,7 +112,7 @@ void launch_wspd_pass(bool emit, const TreeView& T, const int2* items, const int
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
                       const int64_t* cell_start, uint32_t* out, int32_t* err, int num_cus, hipStream_t st);
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
-                        const int32_t* chunk_first, const int64_t* item_start, int64_t nchunks, uint64_t* npairs,
-                        uint64_t* pair_start, hipStream_t st);
+                        int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,
+                        hipStream_t st);
 
 }  // namespace w1

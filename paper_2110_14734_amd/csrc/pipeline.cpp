@@ -111,7 +111,8 @@ void setup_pairs(Ctx& c, int64_t K) {
   const int64_t zero8_end = off;
   P.bmin = (uint64_t*)take8(); P.dmin = (uint64_t*)take8(); P.m0 = (int64_t*)take8();
   const int64_t ones8_end = off;
-  off += K8 * 8 * 3;  // spare
+  P.seg_lo = (int64_t*)take8(); P.seg_hi = (int64_t*)take8();
+  off += K8 * 8;  // spare
   P.err = (int32_t*)take4(); P.locA = (int32_t*)take4(); P.locB = (int32_t*)take4(); P.beh = (int32_t*)take4();
   P.bnx = (int32_t*)take4(); P.bny = (int32_t*)take4(); P.FA = (int32_t*)take4(); P.FB = (int32_t*)take4();
   P.e = (int32_t*)take4(); P.ncells = (int32_t*)take4(); P.ndiag = (int32_t*)take4();
@@ -311,7 +312,10 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     fill_u32((uint32_t*)ca, 0, N, st);
     fill_u32((uint32_t*)cb, 0, N, st);
     launch_cell_fill(perm, kw1s, kw0, head, cidx, li, lj, lw, M, P, ckey, cpair, cij, ca, cb, st);
-    int64_t* nc64 = need<int64_t>(c, c.nbuck, K + 1);
+    fill_u64((uint64_t*)P.seg_lo, 0, K, st);
+    fill_u64((uint64_t*)P.seg_hi, 0, K, st);
+    launch_run_bounds(cpair, N, P.seg_lo, P.seg_hi, st);
+    launch_bounds_count32(P.seg_lo, P.seg_hi, K, P.ncells, st);
     // cell_start = exclusive scan of ncells (int32 -> int64 via host, K is small)
     std::vector<int32_t> nc = fetch_pairs(c, P.ncells, K);
     std::vector<int64_t> cs((size_t)K);
@@ -321,7 +325,6 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       acc += nc[(size_t)p];
     }
     upload(c, P.cell_start, cs.data(), (size_t)K * 8);
-    (void)nc64;
     check(c, hipGetLastError());
   }
   record(c, 3);
@@ -418,8 +421,10 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       int2* S = need<int2>(c, c.itemsS, m);
       launch_gather_items(I, perm, S, m, st);
       int32_t* ipp = need<int32_t>(c, c.ipp, K);
-      fill_u32((uint32_t*)ipp, 0, K, st);
-      launch_item_pairs(T, S, m, ipp, st);
+      fill_u64((uint64_t*)P.seg_lo, 0, K, st);
+      fill_u64((uint64_t*)P.seg_hi, 0, K, st);
+      launch_item_bounds(T, S, m, P.seg_lo, P.seg_hi, st);
+      launch_bounds_count32(P.seg_lo, P.seg_hi, K, ipp, st);
       timed = true;
       std::vector<int32_t> hipp = fetch_pairs(c, ipp, K);
       std::vector<int64_t> ist((size_t)K);
@@ -457,7 +462,8 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       readback(c, ccnt + (nch - 1), &lc, 1);
       Ptot = (int64_t)(lo + lc);
       trace(c, "wspd pairs", Ptot);
-      launch_pair_totals(ccnt, coff, cp, cf, P.item_start, nch, P.npairs, P.pair_start, st);
+      fill_u64((uint64_t*)P.seg_hi, 0, K, st);
+      launch_pair_totals(ccnt, coff, cp, nch, P.pair_start, (uint64_t*)P.seg_hi, P.npairs, K, st);
       if (!(o.flags & W1_COUNT_ONLY) && Ptot > 0) {
         uint32_t* pout = need<uint32_t>(c, c.pu, 3 * Ptot);
         fill_u32(xc, 0, 8, st);

@@ -474,7 +474,6 @@ __global__ void k_cell_fill(const uint32_t* __restrict__ perm, const uint64_t* _
       ckey[c] = kw0[l];
       cpair[c] = p;
       cij[c] = make_int2((int)(li[l] - P.m0[p]), (int)(lj[l] - P.m0[p]));
-      atomicAdd(&P.ncells[p], 1);
     }
   }
   const uint32_t c0 = c;
@@ -484,6 +483,23 @@ __global__ void k_cell_fill(const uint32_t* __restrict__ perm, const uint64_t* _
     if (a) atomicAdd(&ca[c0], a);
     if (b) atomicAdd(&cb[c0], b);
   }
+}
+
+// Bounds of each pair's run in a pair-major array of pair ids: the first
+// element of a run writes lo[p], the last writes hi[p] (no atomics).
+__global__ void k_run_bounds(const uint32_t* __restrict__ key, int64_t n, int64_t* __restrict__ lo,
+                             int64_t* __restrict__ hi) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const uint32_t p = key[x];
+  if (x == 0 || key[x - 1] != p) lo[p] = x;
+  if (x == n - 1 || key[x + 1] != p) hi[p] = x + 1;
+}
+
+__global__ void k_bounds_count32(const int64_t* __restrict__ lo, const int64_t* __restrict__ hi, int64_t K,
+                                 int32_t* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < K) out[p] = (int32_t)(hi[p] - lo[p]);
 }
 
 // ===================================================================== a3 ==
@@ -682,6 +698,12 @@ void launch_cell_fill(const uint32_t* perm, const uint64_t* kw1s, const uint64_t
                       const PairArrays& P, uint64_t* ckey, uint32_t* cpair, int2* cij, int32_t* ca, int32_t* cb,
                       hipStream_t st) {
   LAUNCH(k_cell_fill, M, perm, kw1s, kw0, head, cidx, li, lj, lw, M, P, ckey, cpair, cij, ca, cb);
+}
+void launch_run_bounds(const uint32_t* key, int64_t n, int64_t* lo, int64_t* hi, hipStream_t st) {
+  LAUNCH(k_run_bounds, n, key, n, lo, hi);
+}
+void launch_bounds_count32(const int64_t* lo, const int64_t* hi, int64_t K, int32_t* out, hipStream_t st) {
+  LAUNCH(k_bounds_count32, K, lo, hi, K, out);
 }
 void launch_karras(const uint32_t* cpair, const uint64_t* ckey, int64_t N, int4* iaux, int32_t* iparent,
                    int32_t* lparent, hipStream_t st) {

@@ -120,15 +120,15 @@ __global__ void k_gather_items(const int2* __restrict__ src, const uint32_t* __r
   if (x < m) dst[x] = src[perm[x]];
 }
 
-__global__ void k_item_pairs(TreeView T, const int2* __restrict__ items, int64_t m, int32_t* __restrict__ ipp) {
+// Bounds of each diagram pair's run of work-list items (items are sorted
+// pair-major): first item writes lo[p], last writes hi[p].
+__global__ void k_item_bounds(TreeView T, const int2* __restrict__ items, int64_t m, int64_t* __restrict__ lo,
+                              int64_t* __restrict__ hi) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t key = ~0u;
-  int32_t one = 0;
-  if (x < m) {
-    key = T.cpair[node_rep(T, items[x].x)];
-    one = 1;
-  }
-  if (wave_seg_reduce(key, one, [](int32_t a, int32_t b) { return a + b; })) atomicAdd(&ipp[key], one);
+  if (x >= m) return;
+  const uint32_t p = T.cpair[node_rep(T, items[x].x)];
+  if (x == 0 || T.cpair[node_rep(T, items[x - 1].x)] != p) lo[p] = x;
+  if (x == m - 1 || T.cpair[node_rep(T, items[x + 1].x)] != p) hi[p] = x + 1;
 }
 
 __global__ void k_chunk_heads(TreeView T, const int2* __restrict__ items, int64_t m, const int64_t* __restrict__ item_start,
@@ -350,15 +350,22 @@ __global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict
   }
 }
 
-__global__ void k_pair_totals(const uint64_t* __restrict__ chunk_cnt, const uint64_t* __restrict__ chunk_off,
-                              const int32_t* __restrict__ chunk_pair, const int32_t* __restrict__ chunk_first,
-                              const int64_t* __restrict__ item_start, int64_t nchunks, uint64_t* __restrict__ npairs,
-                              uint64_t* __restrict__ pair_start) {
+// Per diagram pair: first output position (the first chunk's offset) and
+// pair count (end of its last chunk minus that).  Chunks are pair-major.
+__global__ void k_pair_bounds(const uint64_t* __restrict__ chunk_cnt, const uint64_t* __restrict__ chunk_off,
+                              const int32_t* __restrict__ chunk_pair, int64_t nchunks, uint64_t* __restrict__ pair_start,
+                              uint64_t* __restrict__ pair_end) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nchunks) return;
   const int32_t p = chunk_pair[c];
-  atomicAdd((unsigned long long*)&npairs[p], (unsigned long long)chunk_cnt[c]);
-  if (chunk_first[c] == item_start[p]) pair_start[p] = chunk_off[c];
+  if (c == 0 || chunk_pair[c - 1] != p) pair_start[p] = chunk_off[c];
+  if (c == nchunks - 1 || chunk_pair[c + 1] != p) pair_end[p] = chunk_off[c] + chunk_cnt[c];
+}
+
+__global__ void k_pair_counts(const uint64_t* __restrict__ pair_start, const uint64_t* __restrict__ pair_end, int64_t K,
+                              uint64_t* __restrict__ npairs) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < K) npairs[p] = pair_end[p] > pair_start[p] ? pair_end[p] - pair_start[p] : 0;
 }
 
 inline unsigned blocks(int64_t n, int bs = 256) { return (unsigned)(n > 0 ? ceil_div(n, bs) : 1); }
@@ -387,8 +394,8 @@ void launch_item_keys(const TreeView& T, const int2* items, int64_t m, bool both
 void launch_gather_items(const int2* src, const uint32_t* perm, int2* dst, int64_t m, hipStream_t st) {
   LAUNCH(k_gather_items, m, src, perm, dst, m);
 }
-void launch_item_pairs(const TreeView& T, const int2* items, int64_t m, int32_t* items_per_pair, hipStream_t st) {
-  LAUNCH(k_item_pairs, m, T, items, m, items_per_pair);
+void launch_item_bounds(const TreeView& T, const int2* items, int64_t m, int64_t* lo, int64_t* hi, hipStream_t st) {
+  LAUNCH(k_item_bounds, m, T, items, m, lo, hi);
 }
 void launch_chunk_heads(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start, int chunk,
                         uint32_t* head, hipStream_t st) {
@@ -418,9 +425,10 @@ void launch_wspd_pass(bool emit, const TreeView& T, const int2* items, const int
                        chunk_pair, xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, cell_start, out, err);
 }
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
-                        const int32_t* chunk_first, const int64_t* item_start, int64_t nchunks, uint64_t* npairs,
-                        uint64_t* pair_start, hipStream_t st) {
-  LAUNCH(k_pair_totals, nchunks, chunk_cnt, chunk_off, chunk_pair, chunk_first, item_start, nchunks, npairs, pair_start);
+                        int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,
+                        hipStream_t st) {
+  LAUNCH(k_pair_bounds, nchunks, chunk_cnt, chunk_off, chunk_pair, nchunks, pair_start, pair_end);
+  LAUNCH(k_pair_counts, K, pair_start, pair_end, K, npairs);
 }
 
 }  // namespace w1
