@@ -34,6 +34,13 @@ __device__ inline uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// Hardware FP32 -> BF16 conversion (v_cvt_pk_bf16_f32, round to nearest even,
+// the same rounding as f2bf for finite values).
+__device__ inline __bf16 to_bf16(float f) { return (__bf16)f; }
+// ReLU as an integer max on the bit pattern: negative floats (sign bit set)
+// are negative integers, so max(bits, 0) maps them (and -0) to +0 and keeps
+// positive values; one instruction, no NaN canonicalisation.
+__device__ inline float relu(float v) { return __int_as_float(max(__float_as_int(v), 0)); }
 
 __device__ inline bf16x8 as_bf16x8(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
 
@@ -148,11 +155,13 @@ __global__ void k_ds_prep(const float* __restrict__ P, uint16_t* __restrict__ w1
 // Lane (r = l % 16, g = l / 16) handles point r of the tile and, after
 // layer 2, the 32 units n = 16 nb + 4 g + q.
 template <bool TRAIN>
-__global__ void __launch_bounds__(256) k_ds_embed(const float2* __restrict__ X, const int64_t* __restrict__ dstart,
-                                                  const int32_t* __restrict__ dlist, const float* __restrict__ P,
-                                                  const u16x8* __restrict__ w1op, const u16x8* __restrict__ w2op,
-                                                  float* __restrict__ pool_out, float* __restrict__ emb_out,
-                                                  DsTrainRows tr) {
+__device__ __forceinline__ void embed_body(const float2* __restrict__ X, const int64_t* __restrict__ dstart,
+                                           const int32_t* __restrict__ dlist, const float* __restrict__ P,
+                                           const u16x8* __restrict__ w1op, const u16x8* __restrict__ w2op,
+                                           float* __restrict__ pool_out, float* __restrict__ emb_out,
+                                           const DsTrainRows& tr) {
+  __shared__ bf16x8 s_w1[8 * 64];      // layer-1 operands (4 KiB)
+  __shared__ f32x4 s_b2[8 * 4];        // b2 in accumulator layout: [nb][g] -> units 16 nb + 4 g + q
   __shared__ float s_part[4][DS_H];
   __shared__ float s_pool[DS_H];
   __shared__ int32_t s_cnt[4][DS_H];
@@ -166,68 +175,90 @@ __global__ void __launch_bounds__(256) k_ds_embed(const float2* __restrict__ X, 
   const int64_t nrows = TRAIN ? ((n + 31) & ~int64_t(31)) : n;
   const int64_t ntiles = (nrows + 15) >> 4;
 
-  bf16x8 a1[8], a2[8][4];
-  f32x4 binit[8], acc_pool[8];
-  int cnt[8][4];
-  for (int kb = 0; kb < 8; ++kb) a1[kb] = as_bf16x8(w1op[kb * 64 + lane]);
-  for (int nb = 0; nb < 8; ++nb) {
+  for (int i = threadIdx.x; i < 8 * 64; i += 256) s_w1[i] = as_bf16x8(w1op[i]);
+  bf16x8 a2[8][4];  // layer-2 operands stay in registers for the whole diagram
+  for (int nb = 0; nb < 8; ++nb)
     for (int ks = 0; ks < 4; ++ks) a2[nb][ks] = as_bf16x8(w2op[(nb * 4 + ks) * 64 + lane]);
+  if (threadIdx.x < 32) {
+    const int nb = threadIdx.x >> 2, gg = threadIdx.x & 3;
+    for (int q = 0; q < 4; ++q) s_b2[threadIdx.x][q] = P[DS_OFF_B2 + 16 * nb + 4 * gg + q];
+  }
+  f32x4 acc_pool[8];
+  int cnt[8][4];
+  for (int nb = 0; nb < 8; ++nb)
     for (int q = 0; q < 4; ++q) {
-      binit[nb][q] = P[DS_OFF_B2 + 16 * nb + 4 * g + q];
       acc_pool[nb][q] = 0.f;
       cnt[nb][q] = 0;
     }
-  }
+  __syncthreads();
 
+  // the next tile's point is loaded one iteration ahead (hides its latency)
+  float2 x_next = make_float2(0.f, 0.f);
+  if (wave * 16 + r < n) x_next = X[start + wave * 16 + r];
   for (int64_t t = wave; t < ntiles; t += 4) {
     const int64_t p = t * 16 + r;
     const bool valid = p < n;
-    float2 x = make_float2(0.f, 0.f);
-    if (valid) x = X[start + p];
-    const uint16_t bh = f2bf(x.x), ph = f2bf(x.y);
-    const uint16_t bl = f2bf(x.x - bf2f(bh)), pl = f2bf(x.y - bf2f(ph));
-    u16x8 xb = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (g == 0 && valid) xb = u16x8{bh, bl, ph, pl, (uint16_t)0x3f80, 0, 0, 0};
-    const bf16x8 b1 = as_bf16x8(xb);
+    const float2 x = x_next;
+    const int64_t pn = p + 64;
+    x_next = pn < n ? X[start + pn] : make_float2(0.f, 0.f);
+    const __bf16 bh = to_bf16(x.x), ph = to_bf16(x.y);
+    const __bf16 bl = to_bf16(x.x - (float)bh), pl = to_bf16(x.y - (float)ph);
+    const __bf16 z0 = (__bf16)0.f, one = (__bf16)1.f;
+    bf16x8 b1 = {z0, z0, z0, z0, z0, z0, z0, z0};
+    if (g == 0 && valid) b1 = bf16x8{bh, bl, ph, pl, one, z0, z0, z0};
 
     // layer 1: h1[k][r] for k = 16 kb + 4 g + q
-    u16x8 hb[4];
+    bf16x8 hb[4];
     for (int kb = 0; kb < 8; ++kb) {
-      const f32x4 z = mfma(a1[kb], b1, f32x4{0.f, 0.f, 0.f, 0.f});
-      for (int q = 0; q < 4; ++q) hb[kb >> 1][(kb & 1) * 4 + q] = f2bf(fmaxf(z[q], 0.f));
+      if (kb == 4) __builtin_amdgcn_sched_barrier(0);  // two halves: 16 live accumulators
+      const f32x4 z = mfma(s_w1[kb * 64 + lane], b1, f32x4{0.f, 0.f, 0.f, 0.f});
+      for (int q = 0; q < 4; ++q) hb[kb >> 1][(kb & 1) * 4 + q] = to_bf16(relu(z[q]));
     }
-    // layer 2: z2[n][r] for n = 16 nb + 4 g + q
-    f32x4 z2[8];
-    for (int nb = 0; nb < 8; ++nb) {
-      f32x4 c = binit[nb];
-      for (int ks = 0; ks < 4; ++ks) c = mfma(a2[nb][ks], as_bf16x8(hb[ks]), c);
-      z2[nb] = c;
-    }
-    if (valid) {
-      for (int nb = 0; nb < 8; ++nb)
-        for (int q = 0; q < 4; ++q) acc_pool[nb][q] += fmaxf(z2[nb][q], 0.f);
+    __builtin_amdgcn_sched_barrier(0);
+    // layer 2: z2[n][r] for n = 16 nb + 4 g + q, pooled block by block so
+    // that only one block's accumulators are live
+    // two output blocks per pass: their MFMA chains interleave
+    const bool full = t * 16 + 16 <= n;  // wave-uniform: no per-point mask needed
+    uint32_t bits = 0;
+    for (int nb = 0; nb < 8; nb += 2) {
+      f32x4 c0 = s_b2[nb * 4 + g], c1 = s_b2[(nb + 1) * 4 + g];
+      for (int ks = 0; ks < 4; ++ks) {
+        c0 = mfma(a2[nb][ks], hb[ks], c0);
+        c1 = mfma(a2[nb + 1][ks], hb[ks], c1);
+      }
+      if (full) {
+        for (int q = 0; q < 4; ++q) {
+          acc_pool[nb][q] += relu(c0[q]);
+          acc_pool[nb + 1][q] += relu(c1[q]);
+        }
+      } else {
+        for (int q = 0; q < 4; ++q) {
+          acc_pool[nb][q] += valid ? relu(c0[q]) : 0.f;
+          acc_pool[nb + 1][q] += valid ? relu(c1[q]) : 0.f;
+        }
+      }
+      if constexpr (TRAIN)
+        for (int q = 0; q < 4; ++q) {
+          const bool on0 = valid && c0[q] > 0.f, on1 = valid && c1[q] > 0.f;
+          bits |= ((on0 ? 1u : 0u) << (nb * 4 + q)) | ((on1 ? 1u : 0u) << ((nb + 1) * 4 + q));
+          cnt[nb][q] += on0 ? 1 : 0;
+          cnt[nb + 1][q] += on1 ? 1 : 0;
+        }
     }
     if constexpr (TRAIN) {
       const int64_t row = tr.roff[d] + p;
-      uint32_t bits = 0;
-      for (int nb = 0; nb < 8; ++nb)
-        for (int q = 0; q < 4; ++q) {
-          const bool on = valid && z2[nb][q] > 0.f;
-          bits |= (on ? 1u : 0u) << (nb * 4 + q);
-          cnt[nb][q] += on ? 1 : 0;
-        }
       tr.m2[row * 4 + g] = bits;
       for (int kb = 0; kb < 8; ++kb) {
         const int k0 = 16 * kb + 4 * g;
         const int base = (kb & 1) * 4;
-        const u16x8 hv = hb[kb >> 1];
+        const u16x8 hv = __builtin_bit_cast(u16x8, hb[kb >> 1]);
         uint2 pk;
         pk.x = (uint32_t)hv[base] | ((uint32_t)hv[base + 1] << 16);
         pk.y = (uint32_t)hv[base + 2] | ((uint32_t)hv[base + 3] << 16);
         *(uint2*)(tr.h1 + row * DS_H + k0) = pk;
         for (int q = 0; q < 4; ++q) tr.h1t[(int64_t)(k0 + q) * tr.rows + row] = hv[base + q];
       }
-      if (g == 0) tr.xb[row] = make_float2(bf2f(bh) + bf2f(bl), bf2f(ph) + bf2f(pl));
+      if (g == 0) tr.xb[row] = make_float2((float)bh + (float)bl, (float)ph + (float)pl);
     }
   }
 
@@ -269,6 +300,25 @@ __global__ void __launch_bounds__(256) k_ds_embed(const float2* __restrict__ X, 
     s += __shfl_xor(s, 2);
     if (part == 0) emb_out[oi * DS_E + o] = s + P[DS_OFF_B3 + o];
   }
+}
+
+// Inference: two blocks (eight waves) per CU, the layer-2 operands resident
+// in registers.
+__global__ void __launch_bounds__(256, 2) k_ds_embed_fwd(const float2* __restrict__ X,
+                                                         const int64_t* __restrict__ dstart,
+                                                         const int32_t* __restrict__ dlist, const float* __restrict__ P,
+                                                         const u16x8* __restrict__ w1op, const u16x8* __restrict__ w2op,
+                                                         float* __restrict__ pool_out, float* __restrict__ emb_out) {
+  embed_body<false>(X, dstart, dlist, P, w1op, w2op, pool_out, emb_out, DsTrainRows{});
+}
+
+// Training forward: also writes the per-row tensors the backward pass reads.
+__global__ void __launch_bounds__(256) k_ds_embed_train(const float2* __restrict__ X, const int64_t* __restrict__ dstart,
+                                                        const int32_t* __restrict__ dlist, const float* __restrict__ P,
+                                                        const u16x8* __restrict__ w1op, const u16x8* __restrict__ w2op,
+                                                        float* __restrict__ pool_out, float* __restrict__ emb_out,
+                                                        DsTrainRows tr) {
+  embed_body<true>(X, dstart, dlist, P, w1op, w2op, pool_out, emb_out, tr);
 }
 
 // ------------------------------------------------------------ backward --
@@ -507,11 +557,11 @@ void ds_embed(const float2* X, const int64_t* dstart, const int32_t* dlist, int6
               const DsOperands& op, float* pool, float* emb, const DsTrainRows* train, hipStream_t st) {
   if (D <= 0) return;
   if (train)
-    hipLaunchKernelGGL(k_ds_embed<true>, dim3((unsigned)D), dim3(256), 0, st, X, dstart, dlist, params,
+    hipLaunchKernelGGL(k_ds_embed_train, dim3((unsigned)D), dim3(256), 0, st, X, dstart, dlist, params,
                        (const u16x8*)op.w1op, (const u16x8*)op.w2op, pool, emb, *train);
   else
-    hipLaunchKernelGGL(k_ds_embed<false>, dim3((unsigned)D), dim3(256), 0, st, X, dstart, dlist, params,
-                       (const u16x8*)op.w1op, (const u16x8*)op.w2op, pool, emb, DsTrainRows{});
+    hipLaunchKernelGGL(k_ds_embed_fwd, dim3((unsigned)D), dim3(256), 0, st, X, dstart, dlist, params,
+                       (const u16x8*)op.w1op, (const u16x8*)op.w2op, pool, emb);
 }
 void ds_loss(const float* emb, const int32_t* pa, const int32_t* pb, const double* w, int64_t P, float* gp,
              double* lpart, hipStream_t st) {
