@@ -198,8 +198,10 @@ int w1_device_network_get(w1_ctx *ctx, int64_t k, w1_device_network *out);
  *                  consecutive pairs holding at most this many points (a
  *                  single larger pair forms its own group).  This bounds the
  *                  device memory of one launch.
- * Results do not depend on any of these (pairs are emitted in a canonical
- * order).  set_tuning returns W1_EINVAL for out-of-range values. */
+ * The set of WSPD pairs, every count, the network and W1 do not depend on
+ * these; the order of the pairs within a diagram pair's output does (it is
+ * deterministic for a given tuning).  set_tuning returns W1_EINVAL for
+ * out-of-range values. */
 typedef struct {
   int32_t stack_depth, work_cap, chunk_items, blocks_per_cu;
   int64_t max_points_per_launch;

@@ -248,3 +248,32 @@ def test_full_size_config2(orc, ctx):
     assert np.array_equal(net["cell_ca"], r.cells["cA"]) and np.array_equal(net["cell_cb"], r.cells["cB"])
     assert g.n_pairs == r.n_pairs
     assert _mix(net["pair_u"], net["pair_v"], net["pair_cost"]) == r.checksum
+
+
+def test_tuning_and_launch_groups(orc, ctx):
+    """Other tunings and launch groups of a few points give the same pair
+    sets, counts and W1; invalid tunings are rejected."""
+    import paper_2110_14734_amd as w1
+
+    _say("[gpu] tuning and launch groups")
+    sizes = pdsynth.batch_sizes(12, 5, lo=50, hi=1500)
+    As = [pdsynth.exp_pd(int(sizes[i]), 3000 + 2 * i, dtype=np.float32) for i in range(6)]
+    Bs = [pdsynth.exp_pd(int(sizes[6 + i]), 3001 + 2 * i, dtype=np.float32) for i in range(6)]
+    ref = ctx.approx_batch(As, Bs, eps=0.2, flags=w1.KEEP_NETWORK)
+    t0 = ctx.tuning
+    try:
+        ctx.tuning = dict(stack_depth=12, work_cap=64, chunk_items=16, blocks_per_cu=2,
+                          max_points_per_launch=2000)
+        got = ctx.approx_batch(As, Bs, eps=0.2, flags=w1.KEEP_NETWORK)
+        for a, b in zip(ref, got):
+            assert (a.w1, a.n_pairs, a.n_cells, a.flow_cost) == (b.w1, b.n_pairs, b.n_cells, b.flow_cost)
+            pa = _sorted_pairs(a.network["pair_u"], a.network["pair_v"], a.network["pair_cost"])
+            pb = _sorted_pairs(b.network["pair_u"], b.network["pair_v"], b.network["pair_cost"])
+            assert all(np.array_equal(x, y) for x, y in zip(pa, pb))
+        for bad in (dict(stack_depth=4), dict(stack_depth=40), dict(blocks_per_cu=0), dict(work_cap=0),
+                    dict(max_points_per_launch=0)):
+            with pytest.raises(w1.W1Error):
+                ctx.tuning = dict(t0, **bad)
+    finally:
+        ctx.tuning = t0
+    assert ctx.tuning == t0
