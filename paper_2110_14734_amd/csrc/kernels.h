@@ -24,6 +24,8 @@ void launch_group_fill(const uint32_t* perm, const uint64_t* kw2s, const uint32_
                        const double* pb, const double* pd, const uint32_t* psd, int64_t n, double* gb, double* gd,
                        uint32_t* gpair, int32_t* gw, hipStream_t st);
 void launch_count_total(const uint32_t* head, const uint32_t* scanned, int64_t n, uint64_t* out, hipStream_t st);
+// *out = scanned[n-1] + cnt[n-1] (total of an exclusive scan), 64-bit
+void launch_count_total64(const uint64_t* cnt, const uint64_t* scanned, int64_t n, uint64_t* out, hipStream_t st);
 void launch_nonzero_flags(const int32_t* gw, int64_t G, uint32_t* flag, hipStream_t st);
 void launch_loc_fill(const int32_t* gw, const uint32_t* flag, const uint32_t* lidx, const double* gb, const double* gd,
                      const uint32_t* gpair, int64_t G, double* lb, double* ld, int32_t* lw, uint32_t* lpair,

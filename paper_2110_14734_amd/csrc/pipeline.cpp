@@ -392,10 +392,9 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       uint64_t* pos = need<uint64_t>(c, c.ipos, f);
       launch_wspd_classify(T, F, f, s, tun, cnt, st);
       scan_u64(cnt, pos, f, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(f, 8)), st);
-      uint64_t lastp = 0, lastc = 0;
-      readback(c, pos + (f - 1), &lastp, 1);
-      readback(c, cnt + (f - 1), &lastc, 1);
-      const uint64_t tot = lastp + lastc;
+      uint64_t* slot = need<uint64_t>(c, c.small, 64);
+      launch_count_total64(cnt, pos, f, slot, st);
+      const uint64_t tot = read_u64(c, slot);
       const int64_t kept = (int64_t)(uint32_t)tot, grown = (int64_t)(tot >> 32);
       I = grow_keep<int2>(c, c.itemsI, isz + kept, isz);
       int2* Nx = need<int2>(c, c.itemsB, std::max<int64_t>(grown, 1));
@@ -457,10 +456,9 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       check(c, hipGetLastError());
       check(c, hipEventRecord(c.kev[2], st));
       scan_u64(ccnt, coff, nch, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(nch, 8)), st);
-      uint64_t lo = 0, lc = 0;
-      readback(c, coff + (nch - 1), &lo, 1);
-      readback(c, ccnt + (nch - 1), &lc, 1);
-      Ptot = (int64_t)(lo + lc);
+      uint64_t* slot = need<uint64_t>(c, c.small, 64);
+      launch_count_total64(ccnt, coff, nch, slot, st);
+      Ptot = (int64_t)read_u64(c, slot);
       trace(c, "wspd pairs", Ptot);
       fill_u64((uint64_t*)P.seg_hi, 0, K, st);
       launch_pair_totals(ccnt, coff, cp, nch, P.pair_start, (uint64_t*)P.seg_hi, P.npairs, K, st);

@@ -128,6 +128,11 @@ __global__ void k_count_total(const uint32_t* __restrict__ head, const uint32_t*
   if (threadIdx.x == 0 && blockIdx.x == 0) *out = n > 0 ? (uint64_t)scanned[n - 1] + head[n - 1] : 0;
 }
 
+__global__ void k_count_total64(const uint64_t* __restrict__ cnt, const uint64_t* __restrict__ scanned, int64_t n,
+                                uint64_t* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = n > 0 ? scanned[n - 1] + cnt[n - 1] : 0;
+}
+
 __global__ void k_nonzero_flags(const int32_t* __restrict__ gw, int64_t G, uint32_t* __restrict__ flag) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g < G) flag[g] = gw[g] != 0 ? 1u : 0u;
@@ -639,6 +644,9 @@ void launch_group_fill(const uint32_t* perm, const uint64_t* kw2s, const uint32_
                        const double* pb, const double* pd, const uint32_t* psd, int64_t n, double* gb, double* gd,
                        uint32_t* gpair, int32_t* gw, hipStream_t st) {
   LAUNCH(k_group_fill, n, perm, kw2s, head, gidx, pb, pd, psd, n, gb, gd, gpair, gw);
+}
+void launch_count_total64(const uint64_t* cnt, const uint64_t* scanned, int64_t n, uint64_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_total64, dim3(1), dim3(64), 0, st, cnt, scanned, n, out);
 }
 void launch_count_total(const uint32_t* head, const uint32_t* scanned, int64_t n, uint64_t* out, hipStream_t st) {
   hipLaunchKernelGGL(k_count_total, dim3(1), dim3(64), 0, st, head, scanned, n, out);
