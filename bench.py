@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--no-nn-search", action="store_true",
                     help="learned form: only the embedding workload (no labels, training or 1-NN search)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
+    ap.add_argument("--stress", action="store_true",
+                    help="also count the WSPD of the 2M+2M Pareto stress pair (30%% duplicates) at --stress-eps")
+    ap.add_argument("--stress-eps", type=float, default=0.01)
     ap.add_argument("--batch-pairs", type=int, default=4096)
     ap.add_argument("--loop-sample", type=int, default=256,
                     help="pairs of the batch also run one call each (the per-pair loop)")
@@ -149,6 +152,39 @@ def run_batch(ctx, args):
         "identical_counts": bool(same),
         "tuning": ctx.tuning, "tuning_from_cache": bool(tuned), "gen_s": gen_s,
     }
+
+
+def run_stress(ctx, args):
+    """Stress pair: 2M points per diagram, birth U[0,1), persistence
+    min(Lomax(1.5), 10), 30% exact copies of random rows, FP32.  The WSPD is
+    counted, not stored (~1e12 pairs at eps 0.01), with a large-item tuning
+    (work-list items up to 65,536 cell pairs, 32-entry traversal stacks)."""
+    import torch
+
+    import paper_2110_14734_amd as w1
+    import pdsynth
+
+    A, B = pdsynth.pareto_pd(2_000_000, 0), pdsynth.pareto_pd(2_000_000, 1)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    t0_tuning = ctx.tuning
+    ctx.tuning = dict(stack_depth=32, work_cap=65536, chunk_items=64, blocks_per_cu=2)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.approx(tA, tB, eps=args.stress_eps, flags=w1.COUNT_ONLY)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kt = ctx.kernel_times()
+    except w1.W1Error as e:
+        return {"error": str(e), "eps": args.stress_eps}
+    finally:
+        ctx.tuning = t0_tuning
+    return {"workload": f"2M+2M Pareto(1.5, cap 10) diagrams with 30% exact duplicates, FP32, eps={args.stress_eps}, "
+                        "a0-a4 with WSPD pairs counted",
+            "s": r.s, "grid_exp": r.grid_exp, "n_points_after_cancellation": r.n_points, "cells": r.n_cells,
+            "wspd_pairs": r.n_pairs, "seconds": dt, "wspd_pairs_per_s": r.n_pairs / dt,
+            "stage_ms": {k: round(r.t_ms[k], 3) for k in w1.T_NAMES[:5]},
+            "worklist_ms": kt["worklist_ms"], "count_ms": kt["count_ms"]}
 
 
 def run_nn(ctx, args):
@@ -350,6 +386,8 @@ def main():
                                 "flow_ms": g.t_ms["flow"], "wspd_pairs": g.n_pairs}
     if not args.no_batch:
         out["batched"] = run_batch(ctx, args)
+    if args.stress:
+        out["stress"] = run_stress(ctx, args)
     if not args.no_nn:
         out["learned"] = run_nn(ctx, args)
     if not args.no_cpu_baseline:

@@ -270,6 +270,15 @@ def test_tuning_and_launch_groups(orc, ctx):
             pa = _sorted_pairs(a.network["pair_u"], a.network["pair_v"], a.network["pair_cost"])
             pb = _sorted_pairs(b.network["pair_u"], b.network["pair_v"], b.network["pair_cost"])
             assert all(np.array_equal(x, y) for x, y in zip(pa, pb))
+        # the large-item setting used for counting at large separations
+        ctx.tuning = dict(stack_depth=32, work_cap=65536, chunk_items=64, blocks_per_cu=2,
+                          max_points_per_launch=1 << 22)
+        big = ctx.approx_batch(As, Bs, eps=0.2, flags=w1.COUNT_ONLY)
+        assert [x.n_pairs for x in big] == [x.n_pairs for x in ref]
+        C, D = pdsynth.pareto_pd(20000, 8), pdsynth.pareto_pd(20000, 9)
+        r0 = orc.run(C, D, eps=0.05, flags=orc.ORC_COUNT_ONLY)
+        g0 = ctx.approx(C, D, eps=0.05, flags=w1.COUNT_ONLY)
+        assert (g0.n_pairs, g0.n_cells, g0.n_points) == (r0.n_pairs, len(r0.cells["i"]), r0.n)
         for bad in (dict(stack_depth=4), dict(stack_depth=40), dict(blocks_per_cu=0), dict(work_cap=0),
                     dict(max_points_per_launch=0)):
             with pytest.raises(w1.W1Error):
