@@ -27,9 +27,15 @@ namespace w1 {
 
 namespace {
 
+// Arc record read by the pricing loop: one 12-byte load per arc.
+struct Arc {
+  int32_t src, dst, cost;
+};
+
 struct Simplex {
   int32_t n = 0, root = 0;
   int64_t m = 0;
+  std::vector<Arc> arc;  // the m network arcs
   std::vector<int32_t> src, dst;
   std::vector<int64_t> cost, flow;
   std::vector<uint8_t> in_tree;
@@ -95,10 +101,16 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
   } catch (...) {
     return -3;
   }
+  try {
+    S.arc.resize((size_t)m);
+  } catch (...) {
+    return -3;
+  }
   for (int64_t a = 0; a < m; ++a) {
     S.src[a] = (int32_t)src[a];
     S.dst[a] = (int32_t)dst[a];
     S.cost[a] = cost[a];
+    S.arc[(size_t)a] = Arc{(int32_t)src[a], (int32_t)dst[a], cost[a]};
   }
   const int64_t ART = (maxc + 1) * ((int64_t)n + 1);
   for (int32_t v = 0; v < n; ++v) {
@@ -128,21 +140,26 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
   int64_t pivots = 0;
   int status = 0;
   for (;;) {
-    // ---- entering arc: block search
+    // ---- entering arc: block search.  Tree arcs have reduced cost exactly 0
+    // (integer potentials), so they never enter and need no test.
     int64_t enter = -1, best = 0;
     if (m > 0) {
-      int64_t a = next_arc;
-      for (int64_t scanned = 0; scanned < m;) {
-        if (!S.in_tree[a]) {
-          const int64_t r = S.rc(a);
+      const Arc* A = S.arc.data();
+      const int64_t* pi = S.pi.data();
+      int64_t a = next_arc, scanned = 0;
+      while (scanned < m) {
+        const int64_t len = std::min(block, m - scanned);
+        for (int64_t t = 0; t < len; ++t) {
+          const Arc& e = A[a];
+          const int64_t r = (int64_t)e.cost + pi[e.src] - pi[e.dst];
           if (r < best) {
             best = r;
             enter = a;
           }
+          if (++a == m) a = 0;
         }
-        if (++a == m) a = 0;
-        ++scanned;
-        if (enter >= 0 && scanned % block == 0) break;
+        scanned += len;
+        if (enter >= 0) break;
       }
       next_arc = a;
     }
