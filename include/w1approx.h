@@ -270,7 +270,9 @@ typedef struct {
 /* New surrogate on the context's device.  The parameters are drawn from a
  * counter-based generator seeded by `seed` (uniform fan-in scaling), and the
  * Adam state starts at zero.  The surrogate is bound to ctx's device; use it
- * only with contexts on that device. */
+ * only with contexts on that device.  Like a context, a surrogate (and an
+ * nn index) is not thread-safe: calls that share one must not overlap.
+ * Every call synchronises the stream it is given before it returns. */
 int w1_surrogate_create(w1_ctx *ctx, uint64_t seed, w1_surrogate **out);
 int w1_surrogate_destroy(w1_surrogate *s);
 /* Copy the FP32 master parameters to / from host memory (n = W1_SURR_NPARAM).
