@@ -16,6 +16,8 @@
 // The K order of layer 2 is permuted so that the accumulator layout of
 // layer 1 is already the operand layout of layer 2: no LDS round trip.
 // Every reduction has a fixed order, so results repeat bit for bit.
+#include <type_traits>
+
 #include "../../include/w1approx.h"
 #include "surrogate.h"
 
@@ -195,9 +197,14 @@ __device__ __forceinline__ void embed_body(const float2* __restrict__ X, const i
   // the next tile's point is loaded one iteration ahead (hides its latency)
   float2 x_next = make_float2(0.f, 0.f);
   if (wave * 16 + r < n) x_next = X[start + wave * 16 + r];
-  for (int64_t t = wave; t < ntiles; t += 4) {
+  // One 16-point tile.  MASKED handles a tile that may hold points past the
+  // end (only a diagram's last tile, or any tile when training, which also
+  // writes the padding rows); full tiles take the path without per-lane
+  // tests.
+  auto tile = [&](int64_t t, auto masked_tag) {
+    constexpr bool MASKED = decltype(masked_tag)::value;
     const int64_t p = t * 16 + r;
-    const bool valid = p < n;
+    const bool valid = !MASKED || p < n;
     const float2 x = x_next;
     const int64_t pn = p + 64;
     x_next = pn < n ? X[start + pn] : make_float2(0.f, 0.f);
@@ -215,10 +222,8 @@ __device__ __forceinline__ void embed_body(const float2* __restrict__ X, const i
       for (int q = 0; q < 4; ++q) hb[kb >> 1][(kb & 1) * 4 + q] = to_bf16(relu(z[q]));
     }
     __builtin_amdgcn_sched_barrier(0);
-    // layer 2: z2[n][r] for n = 16 nb + 4 g + q, pooled block by block so
-    // that only one block's accumulators are live
-    // two output blocks per pass: their MFMA chains interleave
-    const bool full = t * 16 + 16 <= n;  // wave-uniform: no per-point mask needed
+    // layer 2: z2[n][r] for n = 16 nb + 4 g + q, pooled two output blocks at
+    // a time (their MFMA chains interleave; few accumulators are live)
     uint32_t bits = 0;
     for (int nb = 0; nb < 8; nb += 2) {
       f32x4 c0 = s_b2[nb * 4 + g], c1 = s_b2[(nb + 1) * 4 + g];
@@ -226,15 +231,13 @@ __device__ __forceinline__ void embed_body(const float2* __restrict__ X, const i
         c0 = mfma(a2[nb][ks], hb[ks], c0);
         c1 = mfma(a2[nb + 1][ks], hb[ks], c1);
       }
-      if (full) {
-        for (int q = 0; q < 4; ++q) {
-          acc_pool[nb][q] += relu(c0[q]);
-          acc_pool[nb + 1][q] += relu(c1[q]);
-        }
-      } else {
-        for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 4; ++q) {
+        if constexpr (MASKED) {
           acc_pool[nb][q] += valid ? relu(c0[q]) : 0.f;
           acc_pool[nb + 1][q] += valid ? relu(c1[q]) : 0.f;
+        } else {
+          acc_pool[nb][q] += relu(c0[q]);
+          acc_pool[nb + 1][q] += relu(c1[q]);
         }
       }
       if constexpr (TRAIN)
@@ -260,6 +263,10 @@ __device__ __forceinline__ void embed_body(const float2* __restrict__ X, const i
       }
       if (g == 0) tr.xb[row] = make_float2((float)bh + (float)bl, (float)ph + (float)pl);
     }
+  };
+  for (int64_t t = wave; t < ntiles; t += 4) {
+    if (!TRAIN && t * 16 + 16 <= n) tile(t, std::false_type{});
+    else tile(t, std::true_type{});
   }
 
   // pool: sum over the 16 points of each lane group (butterfly: every lane
