@@ -104,3 +104,45 @@ def test_network_simplex_pivot_cap_and_errors():
         w1.flow_solve(3, src, dst, cost, np.array([3, 0, -2], np.int64))  # unbalanced
     with pytest.raises(w1.W1Error):
         w1.flow_solve(3, src[:2], dst[:2], cost[:2], np.array([0, 3, -3], np.int64)[::-1].copy())  # infeasible
+
+
+def test_learned_form_entry_points_reject_bad_arguments():
+    """The surrogate, 1-NN and tuning entry points validate their arguments
+    before any device work (null handles, bad sizes, out-of-range values)."""
+    import ctypes
+
+    L = w1.lib()
+    vp = ctypes.c_void_p
+    out = vp()
+    assert L.w1_surrogate_create(None, ctypes.c_uint64(0), ctypes.byref(out)) == w1.W1_EINVAL
+    assert L.w1_surrogate_destroy(None) == w1.W1_EINVAL
+    buf = (ctypes.c_float * w1.SURR_NPARAM)()
+    assert L.w1_surrogate_get_params(None, buf, w1.SURR_NPARAM) == w1.W1_EINVAL
+    assert L.w1_surrogate_set_params(None, buf, w1.SURR_NPARAM) == w1.W1_EINVAL
+    t = (ctypes.c_double * 3)()
+    assert L.w1_surrogate_last_times(None, t, 3) == w1.W1_EINVAL
+    assert L.w1_nn_build(None, None, None, 0, 0, None, ctypes.byref(out)) == w1.W1_EINVAL
+    assert L.w1_nn_destroy(None) == w1.W1_EINVAL
+    prm = w1._NNParams(0.1, w1.NN_RWMD, 0)
+    nn = (ctypes.c_int64 * 1)()
+    assert L.w1_nn_query(None, None, None, None, 1, ctypes.byref(prm), 0, None, nn, None, None,
+                         None) == w1.W1_EINVAL
+    assert L.w1_ctx_set_tuning(None, None) == w1.W1_EINVAL
+    tun = w1._Tuning()
+    assert L.w1_ctx_get_tuning(None, ctypes.byref(tun)) == w1.W1_EINVAL
+    assert L.w1_surrogate_embed(None, None, None, 0, 0, None, None) == w1.W1_EINVAL
+    assert L.w1_surrogate_grad(None, None, None, 0, None, None, None, 0, 0, None, None, None) == w1.W1_EINVAL
+    assert L.w1_surrogate_train(None, None, None, 0, None, None, None, 0, None, 0, None, None) == w1.W1_EINVAL
+
+
+def test_tune_workload_keys():
+    """The autotuner's cache key depends on the workload's size class and mode only."""
+    from paper_2110_14734_amd import tune
+
+    A = [np.zeros((1000, 2))] * 4
+    B = [np.zeros((3000, 2))] * 4
+    k1 = tune.workload_key(A, B, 0.1, True)
+    k2 = tune.workload_key(A, B, 0.1, False)
+    assert k1 != k2 and k1.endswith("count") and k2.endswith("emit")
+    assert k1.startswith("pts2^14/pair2^12/")
+    assert tune.workload_key(A, B, 0.05, True) != k1

@@ -220,3 +220,32 @@ def test_invalid_inputs(w1, ctx):
         sur.grad([pdsynth.exp_pd(5, 1)] * 2, [0], [1], [0.0])  # label must be > 0
     with pytest.raises(w1.W1Error):
         w1.NNIndex(ctx, [bad])
+
+
+def test_nn_edge_cases(w1, ctx):
+    """FP64 database, an empty query, a database member as query, several
+    seed candidates, no queries, and a dtype mismatch."""
+    _say("1-NN edge cases")
+    ds, fams, _ = _family_db(25, 4, 4, lo=10, hi=40)
+    ds64 = [d.astype(np.float64) for d in ds]
+    sur = w1.Surrogate(ctx, seed=2)
+    idx = w1.NNIndex(ctx, ds64, sur)
+    qs = [np.zeros((0, 2)), ds64[3].copy(), pdsynth.family_pd(20, 123, fams[0]).astype(np.float64)]
+    want = S.nn_exhaustive(ds64, qs, eps=0.2)
+    assert want[1] == (3, 0.0)
+    for mode, k in (("rwmd", 1), ("surrogate", 1), ("surrogate", 5), ("surrogate", 100), ("exhaustive", 1)):
+        r = idx.query(qs, eps=0.2, mode=mode, seed_k=k)
+        assert [int(v) for v in r.nn] == [a for a, _ in want], (mode, k)
+        assert [float(v) for v in r.w1] == [b for _, b in want], (mode, k)
+    r = idx.query([], eps=0.2, mode="surrogate")
+    assert r.nn.size == 0 and r.stats["verifications"] == 0
+    with pytest.raises(w1.W1Error):
+        idx.query([ds[0]], eps=0.2)  # FP32 query against an FP64 database
+    with pytest.raises(w1.W1Error):
+        idx.query(qs, eps=0.0)
+    plain = w1.NNIndex(ctx, ds64)  # no surrogate: the surrogate mode is unavailable
+    with pytest.raises(w1.W1Error):
+        plain.query(qs, eps=0.2, mode="surrogate")
+    assert [int(v) for v in plain.query(qs, eps=0.2, mode="rwmd").nn] == [a for a, _ in want]
+    plain.close()
+    idx.close()
