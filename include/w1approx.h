@@ -197,14 +197,20 @@ int w1_device_network_get(w1_ctx *ctx, int64_t k, w1_device_network *out);
  *   max_points_per_launch  w1_approx_batch runs its pairs in launch groups of
  *                  consecutive pairs holding at most this many points (a
  *                  single larger pair forms its own group).  This bounds the
- *                  device memory of one launch.
+ *                  device memory of one launch;
+ *   compact_records 1 (default): when every grid coordinate of a launch group
+ *                  is below 2^28, the count pass reads a split's two child
+ *                  boxes from one 32-byte record of 28-bit fields; 0: from
+ *                  the node's 64-byte split record, as the emit pass always
+ *                  does.
  * The set of WSPD pairs, every count, the network and W1 do not depend on
  * these; the order of the pairs within a diagram pair's output does (it is
- * deterministic for a given tuning).  set_tuning returns W1_EINVAL for
- * out-of-range values. */
+ * deterministic for a given tuning, and compact_records does not change it).
+ * set_tuning returns W1_EINVAL for out-of-range values. */
 typedef struct {
   int32_t stack_depth, work_cap, chunk_items, blocks_per_cu;
   int64_t max_points_per_launch;
+  int32_t compact_records;
 } w1_tuning;
 
 int w1_ctx_get_tuning(const w1_ctx *ctx, w1_tuning *out);

@@ -77,7 +77,8 @@ class _TrainParams(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("stack_depth", ctypes.c_int32), ("work_cap", ctypes.c_int32), ("chunk_items", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("max_points_per_launch", ctypes.c_int64)]
+                ("blocks_per_cu", ctypes.c_int32), ("max_points_per_launch", ctypes.c_int64),
+                ("compact_records", ctypes.c_int32)]
 
 
 class _NNParams(ctypes.Structure):

@@ -77,8 +77,9 @@ void launch_diag_fill(const uint32_t* cpair, const int2* cij, const int32_t* ca,
 // Tree view used by the WSPD traversal.  Node reference r >= 0 is internal
 // node r, r < 0 is the leaf of cell ~r.
 struct TreeView {
-  const int4* inode;    // traversal records, 2 int4 each: N - 1 internal nodes
-                        // then N cells (see k_pack_nodes)
+  const int4* inode;    // traversal records, 2 int4 each, 2N - 1 of them:
+                        // root first, siblings adjacent (see k_pack_nodes)
+  const int4* isplit64; // split records of the internal nodes, 4 int4 each
   const int4* ibox;     // internal: min_i, min_j, max_i, max_j
   const int4* iaux;     // internal: left, right, lo, hi
   const int32_t* iheight;
@@ -92,9 +93,19 @@ struct WspdTuning {
   int work_cap;     // items need |U| * |V| <= work_cap to skip the expansion rounds
   int chunk_items;  // items per chunk of the count / emit passes
   int blocks_per_cu;
+  int compact;      // 1: packed split records when coordinates allow, 0: never
 };
 
-void launch_pack_nodes(const TreeView& T, int4* rec, hipStream_t st);
+// Traversal records (2N - 1 of them) and rmap: node reference -> record
+// (internal node r -> rmap[r], cell c -> rmap[N - 1 + c]) and the 64-byte
+// split records of the internal nodes.
+void launch_pack_nodes(const TreeView& T, const int64_t* cell_start, int4* rec, int32_t* rmap, int4* split64,
+                       hipStream_t st);
+// Packed split records (N - 1 of them, 2 uint4 each); every cell coordinate
+// must be below 2^28.
+void launch_pack_split(const TreeView& T, uint4* out, hipStream_t st);
+// Final work items (node references) -> work entries of the passes.
+void launch_item_prep(const TreeView& T, int2* items, int64_t m, int s, const int32_t* rmap, hipStream_t st);
 void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st);
 void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st);
 void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s, const WspdTuning& tun,
@@ -109,10 +120,13 @@ void launch_chunk_heads(const TreeView& T, const int2* items, int64_t m, const i
 void launch_chunk_fill(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start,
                        const int32_t* items_per_pair, const uint32_t* head, const uint32_t* cid, int chunk,
                        int32_t* chunk_first, int32_t* chunk_end, int32_t* chunk_pair, hipStream_t st);
-void launch_wspd_pass(bool emit, const TreeView& T, const int2* items, const int32_t* chunk_first,
-                      const int32_t* chunk_end, const int32_t* chunk_pair, int64_t nchunks, const int32_t* xcd_range,
+// Count (emit = false) or emit pass; split_recs = packed split records for
+// the count pass, or nullptr to read the 64-byte split records (the emit
+// pass always does).
+void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
+                      const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
-                      const int64_t* cell_start, uint32_t* out, int32_t* err, int num_cus, hipStream_t st);
+                      uint32_t* out, int32_t* err, int num_cus, hipStream_t st);
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,
                         hipStream_t st);

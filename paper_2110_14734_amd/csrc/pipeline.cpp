@@ -331,6 +331,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
 
   // ---------------------------------------------------------------- a3 --
   TreeView T{};
+  const uint4* split = nullptr;
   if (N > 0) {
     T.cij = (const int2*)c.cij.p;
     T.cpair = (const uint32_t*)c.cpair.p;
@@ -349,10 +350,24 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     T.ibox = ibox;
     T.iaux = iaux;
     T.iheight = ih;
-    if (N >= (int64_t(1) << 30)) throw StageError{W1_ERANGE};  // record split field holds 30 bits
-    int4* inode = need<int4>(c, c.inode, 2 * (2 * N - 1));
-    launch_pack_nodes(T, inode, st);
+    if (N >= (int64_t(1) << 30)) throw StageError{W1_ERANGE};  // work entries hold record numbers in 31 bits
+    // one leading pad record: sibling pairs (records 2g + 1, 2g + 2) then
+    // start on 64-byte boundaries and never straddle a cache line
+    int4* inode = need<int4>(c, c.inode, 2 * (2 * N)) + 2;
+    int4* split64 = need<int4>(c, c.isplit64, 4 * (N - 1));
+    launch_pack_nodes(T, P.cell_start, inode, need<int32_t>(c, c.rmap, 2 * N - 1), split64, st);
     T.inode = inode;
+    T.isplit64 = split64;
+    if (c.tun.compact) {  // the root's box bounds every coordinate (all are >= 0)
+      int4 root;
+      readback(c, ibox, &root, 1);
+      if (std::max(root.z, root.w) < (1 << 28)) {
+        uint4* sr = need<uint4>(c, c.isplit, 2 * (N - 1));
+        launch_pack_split(T, sr, st);
+        split = sr;
+      }
+    }
+    trace(c, "packed split records", split ? 1 : 0);
     check(c, hipGetLastError());
   }
   record(c, 4);
@@ -442,6 +457,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       int32_t* ce = need<int32_t>(c, c.cend, nch);
       int32_t* cp = need<int32_t>(c, c.cpairs, nch);
       launch_chunk_fill(T, S, m, P.item_start, ipp, ch, cidv, tun.chunk_items, cf, ce, cp, st);
+      launch_item_prep(T, S, m, s, (const int32_t*)c.rmap.p, st);  // S holds work entries from here on
       int32_t hr[9];
       for (int x = 0; x <= 8; ++x) hr[x] = (int32_t)((nch * x) / 8);
       int32_t* xr = need<int32_t>(c, c.xrange, 16);
@@ -451,7 +467,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       uint64_t* coff = need<uint64_t>(c, c.coff, nch);
       fill_u32(xc, 0, 8, st);
       check(c, hipEventRecord(c.kev[1], st));
-      launch_wspd_pass(false, T, S, cf, ce, cp, nch, xr, xc, s, tun, ccnt, coff, P.cell_start, nullptr, derr,
+      launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr,
                        c.num_cus, st);
       check(c, hipGetLastError());
       check(c, hipEventRecord(c.kev[2], st));
@@ -466,7 +482,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         uint32_t* pout = need<uint32_t>(c, c.pu, 3 * Ptot);
         fill_u32(xc, 0, 8, st);
         check(c, hipEventRecord(c.kev[3], st));
-        launch_wspd_pass(true, T, S, cf, ce, cp, nch, xr, xc, s, tun, ccnt, coff, P.cell_start, pout, derr,
+        launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr,
                          c.num_cus, st);
         check(c, hipGetLastError());
         emitted = true;
@@ -870,6 +886,7 @@ int w1_ctx_get_tuning(const w1_ctx* c, w1_tuning* out) {
   out->chunk_items = c->tun.chunk_items;
   out->blocks_per_cu = c->tun.blocks_per_cu;
   out->max_points_per_launch = c->max_points;
+  out->compact_records = c->tun.compact;
   return W1_OK;
 }
 
@@ -877,9 +894,9 @@ int w1_ctx_set_tuning(w1_ctx* c, const w1_tuning* t) {
   if (!c || !t) return W1_EINVAL;
   if (t->stack_depth < 8 || t->stack_depth > 32 || t->work_cap < 1 || t->work_cap > (1 << 20) ||
       t->chunk_items < 1 || t->chunk_items > (1 << 20) || t->blocks_per_cu < 1 || t->blocks_per_cu > 16 ||
-      t->max_points_per_launch < 1)
+      t->max_points_per_launch < 1 || (t->compact_records != 0 && t->compact_records != 1))
     return W1_EINVAL;
-  c->tun = WspdTuning{t->stack_depth, t->work_cap, t->chunk_items, t->blocks_per_cu};
+  c->tun = WspdTuning{t->stack_depth, t->work_cap, t->chunk_items, t->blocks_per_cu, t->compact_records};
   c->max_points = t->max_points_per_launch;
   return W1_OK;
 }

@@ -153,49 +153,123 @@ __global__ void k_chunk_fill(TreeView T, const int2* __restrict__ items, int64_t
   chunk_pair[c] = (int32_t)p;
 }
 
-// Packed node record for the traversal, 32 bytes, one format for internal
-// nodes and cells: int4 box (min i, min j, max i, max j) and int4 aux =
-// (representative cell, split | left-is-cell << 30 | right-is-cell << 31,
-// representative i, representative j).  Internal node r has split g: its
-// children are g and g + 1 (cells or internal nodes, per the two flags).
-// Record index: internal node r -> r, cell c -> (N - 1) + c.
+// Traversal record, 32 bytes: int4 box (min i, min j, max i, max j) and
+// int4 aux = (child base, local representative, rep i ^ 2^31, rep j ^ 2^31).
+// Siblings are adjacent: record 0 is the root and the children of internal
+// node g are records 2g + 1 (left) and 2g + 2 (right), so one offset locates
+// both; the child base of a cell is -1 (cells are never split: a node pair
+// of two cells is always separated).  The representative is the node's first
+// cell, stored relative to its diagram pair's first cell; its coordinates
+// carry a flipped sign bit so that unsigned order is signed order and the
+// unsigned difference gives |a - b|.
 struct Rec {
   int4 box, aux;
 };
 
-__device__ inline Rec load_rec(const int4* __restrict__ R, int32_t r, int32_t nint) {
-  const int64_t i = r >= 0 ? (int64_t)r : (int64_t)nint + ~r;
-  const int4* p = R + 2 * i;
+__device__ inline Rec rec_at(const int4* __restrict__ R, uint32_t i) {
+  const int4* p = R + 2 * (size_t)i;
   return Rec{p[0], p[1]};
 }
-__device__ inline int32_t rec_left(const Rec& q) {
-  const uint32_t f = (uint32_t)q.aux.y;
-  const int32_t g = (int32_t)(f & 0x3fffffffu);
-  return (f >> 30) & 1u ? ~g : g;
-}
-__device__ inline int32_t rec_right(const Rec& q) {
-  const uint32_t f = (uint32_t)q.aux.y;
-  const int32_t g = (int32_t)(f & 0x3fffffffu) + 1;
-  return (f >> 31) ? ~g : g;
+__device__ inline int64_t ref_index(const TreeView& T, int32_t r) { return r >= 0 ? r : (T.N - 1) + ~r; }
+
+__device__ inline void put_rec(const TreeView& T, const int64_t* __restrict__ cell_start, int4* __restrict__ rec,
+                               int32_t* __restrict__ rmap, int64_t at, int32_t r) {
+  const int32_t rep = node_rep(T, r);
+  const int2 c = T.cij[rep];
+  rec[2 * at] = node_box(T, r);
+  rec[2 * at + 1] = make_int4(r >= 0 ? r : -1, (int)(rep - cell_start[T.cpair[rep]]), (int)((uint32_t)c.x ^ 0x80000000u),
+                              (int)((uint32_t)c.y ^ 0x80000000u));
+  rmap[ref_index(T, r)] = (int32_t)at;
 }
 
-__global__ void k_pack_nodes(TreeView T, int4* __restrict__ rec) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nint = T.N - 1;
-  if (r >= nint + T.N) return;
-  if (r < nint) {
-    const int4 a = T.iaux[r];  // left, right, lo, hi
-    const int32_t g = a.x >= 0 ? a.x : ~a.x;
-    const uint32_t f = (uint32_t)g | (a.x < 0 ? 1u << 30 : 0u) | (a.y < 0 ? 1u << 31 : 0u);
-    const int2 c = T.cij[a.z];
-    rec[2 * r] = T.ibox[r];
-    rec[2 * r + 1] = make_int4(a.z, (int)f, c.x, c.y);
-  } else {
-    const int32_t cell = (int32_t)(r - nint);
-    const int2 c = T.cij[cell];
-    rec[2 * r] = make_int4(c.x, c.y, c.x, c.y);
-    rec[2 * r + 1] = make_int4(cell, 0, c.x, c.y);
+// One thread per internal node g writes the records of its two children
+// (thread 0 also the root's), the map from node reference to record, and
+// g's split record for the passes, 64 bytes: int4 left child box, int4 right
+// child box, int4 (gamma, right child's local representative, its i ^ 2^31,
+// j ^ 2^31), int4 unused.  The children are nodes gamma and gamma + 1; the
+// left child's representative is g's own, which the traversal already holds.
+__global__ void k_pack_nodes(TreeView T, const int64_t* __restrict__ cell_start, int4* __restrict__ rec,
+                             int32_t* __restrict__ rmap, int4* __restrict__ split64) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= T.N - 1) return;
+  const int4 a = T.iaux[g];
+  put_rec(T, cell_start, rec, rmap, 2 * g + 1, a.x);
+  put_rec(T, cell_start, rec, rmap, 2 * g + 2, a.y);
+  if (g == 0) put_rec(T, cell_start, rec, rmap, 0, 0);
+  const int4 r2 = rec[2 * (2 * g + 2) + 1];
+  int4* e = split64 + 4 * g;
+  e[0] = node_box(T, a.x);
+  e[1] = node_box(T, a.y);
+  e[2] = make_int4(a.x >= 0 ? a.x : ~a.x, r2.y, r2.z, r2.w);
+  e[3] = make_int4(0, 0, 0, 0);
+}
+
+// Work entries of the passes (work list and stacks), int2:
+//   x = record of the node to split next (P) | orient << 31,
+//   y = record of the other node (O) | separated << 31,
+// orient = 1 when P is the pair's first node U.  The split rule (longer box
+// side, ties split the second node) is applied when an entry is made; a
+// separated entry (fresh items only) is output as it is, U = P.
+__global__ void k_item_prep(TreeView T, int2* __restrict__ items, int64_t m, int s, const int32_t* __restrict__ rmap) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= m) return;
+  const int2 it = items[x];
+  const int4 bu = node_box(T, it.x), bv = node_box(T, it.y);
+  const int32_t ru = rmap[ref_index(T, it.x)], rv = rmap[ref_index(T, it.y)];
+  int2 e;
+  if (separated(bu, bv, s))
+    e = make_int2(ru | INT32_MIN, rv | INT32_MIN);
+  else if (box_diam(bu) > box_diam(bv))
+    e = make_int2(ru | INT32_MIN, rv);
+  else
+    e = make_int2(rv, ru);
+  items[x] = e;
+}
+
+// Packed split record of internal node g, 32 bytes: the boxes of its two
+// children (left child's min i, min j, max i, max j, then the right child's)
+// as eight 28-bit fields, coordinate k at bits [28k, 28k + 28) of words 0-6,
+// and word 7 = the split index gamma (children are node gamma and gamma + 1).
+// The count pass uses them when every cell coordinate of the launch is below
+// 2^28: a split then reads 32 bytes (two loads) instead of both children's
+// full records, and four split records share a 128-byte cache line.  The
+// emit pass needs the right child's representative as well and reads the
+// 64-byte split records (see k_pack_nodes).
+__global__ void k_pack_split(TreeView T, uint4* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= T.N - 1) return;
+  const int4 a = T.iaux[g];
+  const int4 b1 = node_box(T, a.x), b2 = node_box(T, a.y);
+  const uint32_t v[8] = {(uint32_t)b1.x, (uint32_t)b1.y, (uint32_t)b1.z, (uint32_t)b1.w,
+                         (uint32_t)b2.x, (uint32_t)b2.y, (uint32_t)b2.z, (uint32_t)b2.w};
+  uint32_t d[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int o = 28 * k, w = o >> 5, sh = o & 31;
+    d[w] |= v[k] << sh;
+    if (sh > 4) d[w + 1] |= v[k] >> (32 - sh);
   }
+  d[7] = (uint32_t)(a.x >= 0 ? a.x : ~a.x);
+  out[2 * g] = make_uint4(d[0], d[1], d[2], d[3]);
+  out[2 * g + 1] = make_uint4(d[4], d[5], d[6], d[7]);
+}
+
+__device__ inline void unpack_boxes(uint4 w0, uint4 w1, int4& b1, int4& b2) {
+  const uint32_t M = 0x0fffffffu;
+  b1.x = (int)(w0.x & M);
+  b1.y = (int)(__builtin_amdgcn_alignbit(w0.y, w0.x, 28) & M);
+  b1.z = (int)(__builtin_amdgcn_alignbit(w0.z, w0.y, 24) & M);
+  b1.w = (int)(__builtin_amdgcn_alignbit(w0.w, w0.z, 20) & M);
+  b2.x = (int)(__builtin_amdgcn_alignbit(w1.x, w0.w, 16) & M);
+  b2.y = (int)(__builtin_amdgcn_alignbit(w1.y, w1.x, 12) & M);
+  b2.z = (int)(__builtin_amdgcn_alignbit(w1.z, w1.y, 8) & M);
+  b2.w = (int)(w1.z >> 4);
+}
+
+// Separation with the diameters already known.
+__device__ inline bool separated_d(int4 a, int da, int4 b, int db, int s) {
+  const int dist = max(max(max(a.x - b.z, b.x - a.z), max(a.y - b.w, b.y - a.w)), 0);
+  return (int64_t)dist >= (int64_t)s * (int64_t)max(da, db);
 }
 
 // Three-word pair record.  The vector type is 16 bytes in size (its store is
@@ -203,39 +277,50 @@ __global__ void k_pack_nodes(TreeView T, int4* __restrict__ rec) {
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
 typedef u32x3 u32x3_w __attribute__((aligned(4)));
 
-// One emitted pair: (rep U - cell base, rep V - cell base, cost).
-__device__ inline u32x3 make_emit(const Rec& a, const Rec& b, int64_t cs) {
-  const int c = 2 * max(abs(a.aux.z - b.aux.z), abs(a.aux.w - b.aux.w));
-  return u32x3{(uint32_t)(a.aux.x - cs), (uint32_t)(b.aux.x - cs), (uint32_t)c};
+// Output pair (rep U, rep V, cost) of child / node aux c and the other node's
+// aux o; orient = 1 when c is on the U side.  Cost = 2 * L-infinity distance
+// of the representatives in grid units.
+__device__ inline u32x3 make_emit(int4 c, int4 o, bool orient) {
+  const uint32_t ci = (uint32_t)c.z, oi = (uint32_t)o.z, cj = (uint32_t)c.w, oj = (uint32_t)o.w;
+  const uint32_t di = ci > oi ? ci - oi : oi - ci, dj = cj > oj ? cj - oj : oj - cj;
+  return u32x3{(uint32_t)(orient ? c.y : o.y), (uint32_t)(orient ? o.y : c.y), 2u * max(di, dj)};
+}
+
+// Lanes below this one whose bit is set in m, plus add.
+__device__ inline uint32_t lanes_set_below(uint64_t m, uint32_t add) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, add));
 }
 
 // Count pass (EMIT = false) and emit pass (EMIT = true) of the WSPD search
 // over the chunks of the work list.  Lane state: a node pair known to be not
-// separated ("current"), or none.  A step first lets every lane without a
-// current pair acquire one (pop its LDS stack, else take a fresh item from
-// the chunk) through a single record-load path; fresh items are tested.  Then
-// each current pair splits the node with the longer box side, loads both
-// children and tests both child pairs (one dependent memory round trip
-// resolves two recursion nodes): separated child pairs are emitted, a
-// non-separated one becomes current and a second one goes on the stack.  At
-// most two pairs per lane per step, written as 12-byte records at the wave
-// cursor in (slot, lane) order, so the order depends only on the chunk.
-// Loop control lives in wave-uniform scalars.
-template <bool EMIT>
-__global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict__ items,
+// separated, held as (P, O, orient): the aux of P, the node to split (its
+// child base, and its representative, which is also its left child's), and
+// O's record.  A split of P reads P's 64-byte split record (three loads,
+// one cache line); COMPACT (count pass only) reads P's packed 32-byte split
+// record instead (two loads).  Both hold the same boxes and child bases, so
+// the counts are the same.  A step first lets every lane without a pair acquire an
+// entry (pop its LDS stack, else take a fresh item from the chunk); a
+// separated fresh item is output at once.  Then each lane with a pair loads
+// both children of P (adjacent records), tests both child pairs against O
+// (one dependent memory round trip resolves two recursion nodes): separated
+// child pairs are output, the first non-separated one becomes the lane's pair
+// and a second one goes on the stack.  At most two pairs per lane per step,
+// written as 12-byte records at the wave cursor in (slot, lane) order, so the
+// order depends only on the chunk.  Loop control lives in wave-uniform
+// scalars.
+template <bool EMIT, bool COMPACT>
+__global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const int4* __restrict__ E,
+                                              const uint4* __restrict__ SR, const int2* __restrict__ items,
                                               const int32_t* __restrict__ chunk_first, const int32_t* __restrict__ chunk_end,
-                                              const int32_t* __restrict__ chunk_pair, const int32_t* __restrict__ xcd_range,
-                                              uint32_t* __restrict__ xcd_ctr, int s, int stack_depth, int64_t step_cap,
-                                              uint64_t* __restrict__ chunk_cnt, const uint64_t* __restrict__ chunk_off,
-                                              const int64_t* __restrict__ cell_start, uint32_t* __restrict__ out,
+                                              const int32_t* __restrict__ xcd_range, uint32_t* __restrict__ xcd_ctr, int s,
+                                              int stack_depth, int64_t step_cap, uint64_t* __restrict__ chunk_cnt,
+                                              const uint64_t* __restrict__ chunk_off, uint32_t* __restrict__ out,
                                               int32_t* __restrict__ err) {
+  static_assert(!(EMIT && COMPACT), "packed split records carry no representatives");
   extern __shared__ int2 s_stack[];
   const int wave = threadIdx.x / WAVE, lane = lane_id();
-  int2* stk = s_stack + (size_t)wave * stack_depth * WAVE;
-  const uint64_t below = lanes_below();
+  int2* stk = s_stack + (size_t)wave * stack_depth * WAVE + lane;  // entry e at stk[e * WAVE]
   const int xcd = blockIdx.x & 7;
-  const int4* __restrict__ R = T.inode;
-  const int32_t nint = (int32_t)(T.N - 1);
   for (int probe = 0; probe < 8; ++probe) {
     const int xr = (xcd + probe) & 7;
     const int r0 = xcd_range[xr], r1 = xcd_range[xr + 1];
@@ -247,13 +332,11 @@ __global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict
       if (k >= r1) break;
       int next = __builtin_amdgcn_readfirstlane(chunk_first[k]);
       const int end = __builtin_amdgcn_readfirstlane(chunk_end[k]);
-      const int64_t cs = EMIT ? cell_start[chunk_pair[k]] : 0;
-      uint32_t* const obase = EMIT ? out + 3 * chunk_off[k] : nullptr;
+      uint32_t* obase = EMIT ? out + 3 * chunk_off[k] : nullptr;
       uint64_t cursor = 0;
-      bool has = false, overflow = false, runaway = false;
-      int sp = 0;
-      Rec RU{}, RV{};
-      int32_t U = 0, V = 0;
+      bool has = false, overflow = false, runaway = false, orient = false;
+      int sp = 0, oid = 0, od = 0;
+      int4 ob = make_int4(0, 0, 0, 0), oa = ob, pa = ob;
       for (int64_t step = 0;; ++step) {
         if (step > step_cap) {  // beyond any chunk's possible work: give up, report
           runaway = true;
@@ -263,85 +346,109 @@ __global__ void __launch_bounds__(256) k_wspd(TreeView T, const int2* __restrict
         const bool want = !has;
         const uint64_t need = __ballot(want && sp == 0);
         const int avail = end - next;
-        bool got = false, fresh = false;
+        bool got = false;
         int2 q = make_int2(0, 0);
         if (want) {
           if (sp > 0) {
             --sp;
-            q = stk[sp * WAVE + lane];
+            q = stk[sp * WAVE];
             got = true;
           } else {
-            const int r = __popcll(need & below);
+            const int r = (int)lanes_set_below(need, 0u);
             if (r < avail) {
               q = items[next + r];
-              got = fresh = true;
+              got = true;
             }
           }
         }
         const int took = __popcll(need);
         next += took < avail ? took : (avail > 0 ? avail : 0);
         if (got) {
-          U = q.x;
-          V = q.y;
-          RU = load_rec(R, U, nint);
-          RV = load_rec(R, V, nint);
+          oid = q.y & 0x7fffffff;
+          const Rec O = rec_at(R, (uint32_t)oid);
+          pa = R[2 * (size_t)(uint32_t)(q.x & 0x7fffffff) + 1];
+          ob = O.box;
+          oa = O.aux;
+          orient = q.x < 0;
         }
         if (__ballot(has || got) == 0) break;
         bool e1 = false, e2 = false;
         u32x3 m1, m2;
         if (got) {
-          has = true;
-          if (fresh && separated(RU.box, RV.box, s)) {
+          if (q.y < 0) {
             e1 = true;
-            has = false;
-            if (EMIT) m1 = make_emit(RU, RV, cs);
+            if (EMIT) m1 = make_emit(pa, oa, orient);
+          } else {
+            has = true;
+            od = box_diam(ob);
           }
         }
         if (has) {
-          const bool splitU = box_diam(RU.box) > box_diam(RV.box);
-          const Rec& P = splitU ? RU : RV;
-          const int32_t c1 = rec_left(P), c2 = rec_right(P);
-          const Rec C1 = load_rec(R, c1, nint), C2 = load_rec(R, c2, nint);
-          const Rec O = splitU ? RV : RU;
-          const bool s1 = separated(C1.box, O.box, s), s2 = separated(C2.box, O.box, s);
+          const uint32_t c1 = 2 * (uint32_t)pa.x + 1;
+          Rec C1, C2;
+          if (COMPACT) {
+            const uint4* ps = SR + 2 * (size_t)(uint32_t)pa.x;
+            const uint4 w0 = ps[0], w1 = ps[1];
+            unpack_boxes(w0, w1, C1.box, C2.box);
+            const int gamma = (int)w1.w;
+            C1.aux = make_int4(gamma, 0, 0, 0);
+            C2.aux = make_int4(gamma + 1, 0, 0, 0);
+          } else {
+            const int4* pe = E + 4 * (size_t)(uint32_t)pa.x;
+            C1.box = pe[0];
+            C2.box = pe[1];
+            const int4 x = pe[2];
+            C1.aux = make_int4(x.x, pa.y, pa.z, pa.w);  // the left child shares P's representative
+            C2.aux = make_int4(x.x + 1, x.y, x.z, x.w);
+          }
+          const int d1 = box_diam(C1.box), d2 = box_diam(C2.box);
+          const bool s1 = separated_d(C1.box, d1, ob, od, s), s2 = separated_d(C2.box, d2, ob, od, s);
           if (EMIT) {
-            if (s1) m1 = splitU ? make_emit(C1, O, cs) : make_emit(O, C1, cs);
-            if (s2) m2 = splitU ? make_emit(C2, O, cs) : make_emit(O, C2, cs);
+            m1 = make_emit(C1.aux, oa, orient);
+            m2 = make_emit(C2.aux, oa, orient);
           }
           e1 = s1;
           e2 = s2;
-          if (!s1 && !s2) {
-            const int2 second = splitU ? make_int2(c2, V) : make_int2(U, c2);
+          if (!s1 && !s2) {  // (C2, O) goes on the stack, split rule applied
+            const bool split2 = orient ? d2 > od : d2 >= od;
+            const int c2 = (int)(c1 + 1);
+            const int2 e = split2 ? make_int2(c2 | (orient ? INT32_MIN : 0), oid)
+                                  : make_int2(oid | (orient ? 0 : INT32_MIN), c2);
             if (sp < stack_depth) {
-              stk[sp * WAVE + lane] = second;
+              stk[sp * WAVE] = e;
               ++sp;
             } else {
               overflow = true;
             }
           }
-          if (!s1 || !s2) {
-            const int32_t cn = !s1 ? c1 : c2;
-            const Rec& CN = !s1 ? C1 : C2;
-            if (splitU) {
-              U = cn;
-              RU = CN;
-            } else {
-              V = cn;
-              RV = CN;
+          if (!s1 || !s2) {  // the lane's next pair: (first non-separated child, O)
+            const bool first = !s1;
+            const int dn = first ? d1 : d2;
+            const int4 na = first ? C1.aux : C2.aux;
+            if (orient ? dn > od : dn >= od) {
+              pa = na;
+            } else {  // O is split next; the child takes O's place
+              pa = oa;
+              ob = first ? C1.box : C2.box;
+              oa = na;
+              oid = (int)(first ? c1 : c1 + 1);
+              od = dn;
+              orient = !orient;
             }
           } else {
             has = false;
           }
         }
         const uint64_t b1 = __ballot(e1), b2 = __ballot(e2);
+        const uint32_t n1 = (uint32_t)__popcll(b1), n2 = (uint32_t)__popcll(b2);
         if (EMIT) {
           // streaming (non-temporal) 12-byte stores: the output is written
           // once and must not evict the tree from L2
-          const int n1 = __popcll(b1);
-          if (e1) __builtin_nontemporal_store(m1, (u32x3_w*)(obase + 3 * (cursor + __popcll(b1 & below))));
-          if (e2) __builtin_nontemporal_store(m2, (u32x3_w*)(obase + 3 * (cursor + n1 + __popcll(b2 & below))));
+          if (e1) __builtin_nontemporal_store(m1, (u32x3_w*)(obase + 3 * lanes_set_below(b1, 0u)));
+          if (e2) __builtin_nontemporal_store(m2, (u32x3_w*)(obase + 3 * lanes_set_below(b2, n1)));
+          obase += 3 * (n1 + n2);
         }
-        cursor += (uint64_t)(__popcll(b1) + __popcll(b2));
+        cursor += n1 + n2;
       }
       const bool bad = runaway || __ballot(overflow) != 0;
       if (bad) atomicOr(err, 1);
@@ -375,7 +482,14 @@ inline unsigned blocks(int64_t n, int bs = 256) { return (unsigned)(n > 0 ? ceil
 #define LAUNCH(kern, n, ...) \
   do { if ((n) > 0) hipLaunchKernelGGL(kern, dim3(blocks(n)), dim3(256), 0, st, __VA_ARGS__); } while (0)
 
-void launch_pack_nodes(const TreeView& T, int4* rec, hipStream_t st) { LAUNCH(k_pack_nodes, 2 * T.N - 1, T, rec); }
+void launch_pack_nodes(const TreeView& T, const int64_t* cell_start, int4* rec, int32_t* rmap, int4* split64,
+                       hipStream_t st) {
+  LAUNCH(k_pack_nodes, T.N - 1, T, cell_start, rec, rmap, split64);
+}
+void launch_pack_split(const TreeView& T, uint4* out, hipStream_t st) { LAUNCH(k_pack_split, T.N - 1, T, out); }
+void launch_item_prep(const TreeView& T, int2* items, int64_t m, int s, const int32_t* rmap, hipStream_t st) {
+  LAUNCH(k_item_prep, m, T, items, m, s, rmap);
+}
 void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st) { LAUNCH(k_roots_flags, T.N - 1, T, flag); }
 void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st) {
   LAUNCH(k_roots_fill, T.N - 1, T, flag, pos, items);
@@ -406,10 +520,10 @@ void launch_chunk_fill(const TreeView& T, const int2* items, int64_t m, const in
                        int32_t* chunk_first, int32_t* chunk_end, int32_t* chunk_pair, hipStream_t st) {
   LAUNCH(k_chunk_fill, m, T, items, m, item_start, items_per_pair, head, cid, chunk, chunk_first, chunk_end, chunk_pair);
 }
-void launch_wspd_pass(bool emit, const TreeView& T, const int2* items, const int32_t* chunk_first,
-                      const int32_t* chunk_end, const int32_t* chunk_pair, int64_t nchunks, const int32_t* xcd_range,
+void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
+                      const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
-                      const int64_t* cell_start, uint32_t* out, int32_t* err, int num_cus, hipStream_t st) {
+                      uint32_t* out, int32_t* err, int num_cus, hipStream_t st) {
   if (nchunks <= 0) return;
   int64_t grid = (int64_t)num_cus * tun.blocks_per_cu;
   grid = ((grid + 7) / 8) * 8;
@@ -417,12 +531,12 @@ void launch_wspd_pass(bool emit, const TreeView& T, const int2* items, const int
   // A chunk's items each have at most work_cap leaf pairs, hence fewer than
   // 2 work_cap recursion nodes; every wave step resolves at least one.
   const int64_t step_cap = (int64_t)tun.chunk_items * (2 * (int64_t)tun.work_cap + 2) + 1024;
-  if (emit)
-    hipLaunchKernelGGL(k_wspd<true>, dim3((unsigned)grid), dim3(256), lds, st, T, items, chunk_first, chunk_end,
-                       chunk_pair, xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, cell_start, out, err);
-  else
-    hipLaunchKernelGGL(k_wspd<false>, dim3((unsigned)grid), dim3(256), lds, st, T, items, chunk_first, chunk_end,
-                       chunk_pair, xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, cell_start, out, err);
+  // the emit pass always reads the 64-byte split records (the packed ones
+  // serve the count pass)
+  auto k = emit ? k_wspd<true, false> : (split_recs ? k_wspd<false, true> : k_wspd<false, false>);
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds, st, T.inode, T.isplit64, split_recs, items, chunk_first,
+                     chunk_end,
+                     xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, out, err);
 }
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,

@@ -280,9 +280,45 @@ def test_tuning_and_launch_groups(orc, ctx):
         g0 = ctx.approx(C, D, eps=0.05, flags=w1.COUNT_ONLY)
         assert (g0.n_pairs, g0.n_cells, g0.n_points) == (r0.n_pairs, len(r0.cells["i"]), r0.n)
         for bad in (dict(stack_depth=4), dict(stack_depth=40), dict(blocks_per_cu=0), dict(work_cap=0),
-                    dict(max_points_per_launch=0)):
+                    dict(max_points_per_launch=0), dict(compact_records=2), dict(compact_records=-1)):
             with pytest.raises(w1.W1Error):
                 ctx.tuning = dict(t0, **bad)
     finally:
         ctx.tuning = t0
     assert ctx.tuning == t0
+
+
+def test_compact_records_and_wide_extent(orc, ctx):
+    """The packed split records (28-bit child boxes) and the full child
+    records give the same pairs in the same order; a pair whose grid extent
+    exceeds 2^28 cells, where the packed records cannot be used, still
+    matches the oracle stage by stage."""
+    import paper_2110_14734_amd as w1
+
+    _say("[gpu] compact and full traversal records")
+    sizes = pdsynth.batch_sizes(8, 7, lo=100, hi=3000)
+    As = [pdsynth.mixture_pd(int(sizes[i]), 4000 + 2 * i) for i in range(4)]
+    Bs = [pdsynth.mixture_pd(int(sizes[4 + i]), 4001 + 2 * i) for i in range(4)]
+    t0 = ctx.tuning
+    assert t0["compact_records"] == 1
+    try:
+        ref = ctx.approx_batch(As, Bs, eps=0.1, flags=w1.KEEP_NETWORK)
+        ctx.tuning = dict(t0, compact_records=0)
+        full = ctx.approx_batch(As, Bs, eps=0.1, flags=w1.KEEP_NETWORK)
+        for a, b in zip(ref, full):
+            assert (a.w1, a.n_pairs, a.flow_cost) == (b.w1, b.n_pairs, b.flow_cost)
+            for key in ("pair_u", "pair_v", "pair_cost"):
+                assert np.array_equal(a.network[key], b.network[key])
+    finally:
+        ctx.tuning = t0
+    # a cluster near the origin and two points near 19000: the grid is
+    # 2^-15, so cell coordinates reach about 6.2e8 > 2^28
+    rng = np.random.default_rng(5)
+    b0 = rng.uniform(0.0, 1.0, 40)
+    A = np.concatenate([np.stack([b0, b0 + rng.uniform(0.5, 1.0, 40)], 1), [[19000.0, 19001.0], [19003.0, 19005.0]]])
+    B = A.copy()
+    B[:, 1] += rng.uniform(0.0, 0.01, len(B))
+    g = ctx.approx(A, B, eps=0.1)
+    extent = (B[:, 1].max() - A[:, 0].min()) / g.grid
+    assert 2.0**28 < extent < 2.0**30, (g.grid_exp, extent)
+    compare(orc, ctx, A, B, eps=0.1)
