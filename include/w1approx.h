@@ -201,8 +201,8 @@ int w1_device_network_get(w1_ctx *ctx, int64_t k, w1_device_network *out);
  *   compact_records 1 (default): when every grid coordinate of a launch group
  *                  is below 2^28, the count pass reads a split's two child
  *                  boxes from one 32-byte record of 28-bit fields; 0: from
- *                  the node's 64-byte split record, as the emit pass always
- *                  does.
+ *                  the children's full 32-byte records, as the emit pass
+ *                  always does.
  * The set of WSPD pairs, every count, the network and W1 do not depend on
  * these; the order of the pairs within a diagram pair's output does (it is
  * deterministic for a given tuning, and compact_records does not change it).

@@ -79,7 +79,6 @@ void launch_diag_fill(const uint32_t* cpair, const int2* cij, const int32_t* ca,
 struct TreeView {
   const int4* inode;    // traversal records, 2 int4 each, 2N - 1 of them:
                         // root first, siblings adjacent (see k_pack_nodes)
-  const int4* isplit64; // split records of the internal nodes, 4 int4 each
   const int4* ibox;     // internal: min_i, min_j, max_i, max_j
   const int4* iaux;     // internal: left, right, lo, hi
   const int32_t* iheight;
@@ -97,10 +96,8 @@ struct WspdTuning {
 };
 
 // Traversal records (2N - 1 of them) and rmap: node reference -> record
-// (internal node r -> rmap[r], cell c -> rmap[N - 1 + c]) and the 64-byte
-// split records of the internal nodes.
-void launch_pack_nodes(const TreeView& T, const int64_t* cell_start, int4* rec, int32_t* rmap, int4* split64,
-                       hipStream_t st);
+// (internal node r -> rmap[r], cell c -> rmap[N - 1 + c]).
+void launch_pack_nodes(const TreeView& T, const int64_t* cell_start, int4* rec, int32_t* rmap, hipStream_t st);
 // Packed split records (N - 1 of them, 2 uint4 each); every cell coordinate
 // must be below 2^28.
 void launch_pack_split(const TreeView& T, uint4* out, hipStream_t st);
@@ -121,8 +118,8 @@ void launch_chunk_fill(const TreeView& T, const int2* items, int64_t m, const in
                        const int32_t* items_per_pair, const uint32_t* head, const uint32_t* cid, int chunk,
                        int32_t* chunk_first, int32_t* chunk_end, int32_t* chunk_pair, hipStream_t st);
 // Count (emit = false) or emit pass; split_recs = packed split records for
-// the count pass, or nullptr to read the 64-byte split records (the emit
-// pass always does).
+// the count pass, or nullptr to read the children's records (the emit pass
+// always does).
 void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,

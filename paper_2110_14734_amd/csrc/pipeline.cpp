@@ -354,10 +354,8 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     // one leading pad record: sibling pairs (records 2g + 1, 2g + 2) then
     // start on 64-byte boundaries and never straddle a cache line
     int4* inode = need<int4>(c, c.inode, 2 * (2 * N)) + 2;
-    int4* split64 = need<int4>(c, c.isplit64, 4 * (N - 1));
-    launch_pack_nodes(T, P.cell_start, inode, need<int32_t>(c, c.rmap, 2 * N - 1), split64, st);
+    launch_pack_nodes(T, P.cell_start, inode, need<int32_t>(c, c.rmap, 2 * N - 1), st);
     T.inode = inode;
-    T.isplit64 = split64;
     if (c.tun.compact) {  // the root's box bounds every coordinate (all are >= 0)
       int4 root;
       readback(c, ibox, &root, 1);

@@ -183,25 +183,15 @@ __device__ inline void put_rec(const TreeView& T, const int64_t* __restrict__ ce
 }
 
 // One thread per internal node g writes the records of its two children
-// (thread 0 also the root's), the map from node reference to record, and
-// g's split record for the passes, 64 bytes: int4 left child box, int4 right
-// child box, int4 (gamma, right child's local representative, its i ^ 2^31,
-// j ^ 2^31), int4 unused.  The children are nodes gamma and gamma + 1; the
-// left child's representative is g's own, which the traversal already holds.
+// (thread 0 also the root's) and the map from node reference to record.
 __global__ void k_pack_nodes(TreeView T, const int64_t* __restrict__ cell_start, int4* __restrict__ rec,
-                             int32_t* __restrict__ rmap, int4* __restrict__ split64) {
+                             int32_t* __restrict__ rmap) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= T.N - 1) return;
   const int4 a = T.iaux[g];
   put_rec(T, cell_start, rec, rmap, 2 * g + 1, a.x);
   put_rec(T, cell_start, rec, rmap, 2 * g + 2, a.y);
   if (g == 0) put_rec(T, cell_start, rec, rmap, 0, 0);
-  const int4 r2 = rec[2 * (2 * g + 2) + 1];
-  int4* e = split64 + 4 * g;
-  e[0] = node_box(T, a.x);
-  e[1] = node_box(T, a.y);
-  e[2] = make_int4(a.x >= 0 ? a.x : ~a.x, r2.y, r2.z, r2.w);
-  e[3] = make_int4(0, 0, 0, 0);
 }
 
 // Work entries of the passes (work list and stacks), int2:
@@ -233,8 +223,8 @@ __global__ void k_item_prep(TreeView T, int2* __restrict__ items, int64_t m, int
 // The count pass uses them when every cell coordinate of the launch is below
 // 2^28: a split then reads 32 bytes (two loads) instead of both children's
 // full records, and four split records share a 128-byte cache line.  The
-// emit pass needs the right child's representative as well and reads the
-// 64-byte split records (see k_pack_nodes).
+// emit pass needs the children's representatives as well and reads their
+// full records (one aligned 64-byte pair).
 __global__ void k_pack_split(TreeView T, uint4* __restrict__ out) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= T.N - 1) return;
@@ -295,10 +285,10 @@ __device__ inline uint32_t lanes_set_below(uint64_t m, uint32_t add) {
 // over the chunks of the work list.  Lane state: a node pair known to be not
 // separated, held as (P, O, orient): the aux of P, the node to split (its
 // child base, and its representative, which is also its left child's), and
-// O's record.  A split of P reads P's 64-byte split record (three loads,
-// one cache line); COMPACT (count pass only) reads P's packed 32-byte split
-// record instead (two loads).  Both hold the same boxes and child bases, so
-// the counts are the same.  A step first lets every lane without a pair acquire an
+// O's record.  A split of P reads both children's records (one aligned
+// 64-byte pair, four loads); COMPACT (count pass only) reads P's packed
+// 32-byte split record instead (two loads).  Both hold the same boxes and
+// child bases, so the counts are the same.  A step first lets every lane without a pair acquire an
 // entry (pop its LDS stack, else take a fresh item from the chunk); a
 // separated fresh item is output at once.  Then each lane with a pair loads
 // both children of P (adjacent records), tests both child pairs against O
@@ -309,8 +299,8 @@ __device__ inline uint32_t lanes_set_below(uint64_t m, uint32_t add) {
 // order depends only on the chunk.  Loop control lives in wave-uniform
 // scalars.
 template <bool EMIT, bool COMPACT>
-__global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const int4* __restrict__ E,
-                                              const uint4* __restrict__ SR, const int2* __restrict__ items,
+__global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const uint4* __restrict__ SR,
+                                              const int2* __restrict__ items,
                                               const int32_t* __restrict__ chunk_first, const int32_t* __restrict__ chunk_end,
                                               const int32_t* __restrict__ xcd_range, uint32_t* __restrict__ xcd_ctr, int s,
                                               int stack_depth, int64_t step_cap, uint64_t* __restrict__ chunk_cnt,
@@ -394,12 +384,9 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
             C1.aux = make_int4(gamma, 0, 0, 0);
             C2.aux = make_int4(gamma + 1, 0, 0, 0);
           } else {
-            const int4* pe = E + 4 * (size_t)(uint32_t)pa.x;
-            C1.box = pe[0];
-            C2.box = pe[1];
-            const int4 x = pe[2];
-            C1.aux = make_int4(x.x, pa.y, pa.z, pa.w);  // the left child shares P's representative
-            C2.aux = make_int4(x.x + 1, x.y, x.z, x.w);
+            const int4* pc = R + 2 * (size_t)c1;  // both children: 64 contiguous, aligned bytes
+            C1 = Rec{pc[0], pc[1]};
+            C2 = Rec{pc[2], pc[3]};
           }
           const int d1 = box_diam(C1.box), d2 = box_diam(C2.box);
           const bool s1 = separated_d(C1.box, d1, ob, od, s), s2 = separated_d(C2.box, d2, ob, od, s);
@@ -482,9 +469,8 @@ inline unsigned blocks(int64_t n, int bs = 256) { return (unsigned)(n > 0 ? ceil
 #define LAUNCH(kern, n, ...) \
   do { if ((n) > 0) hipLaunchKernelGGL(kern, dim3(blocks(n)), dim3(256), 0, st, __VA_ARGS__); } while (0)
 
-void launch_pack_nodes(const TreeView& T, const int64_t* cell_start, int4* rec, int32_t* rmap, int4* split64,
-                       hipStream_t st) {
-  LAUNCH(k_pack_nodes, T.N - 1, T, cell_start, rec, rmap, split64);
+void launch_pack_nodes(const TreeView& T, const int64_t* cell_start, int4* rec, int32_t* rmap, hipStream_t st) {
+  LAUNCH(k_pack_nodes, T.N - 1, T, cell_start, rec, rmap);
 }
 void launch_pack_split(const TreeView& T, uint4* out, hipStream_t st) { LAUNCH(k_pack_split, T.N - 1, T, out); }
 void launch_item_prep(const TreeView& T, int2* items, int64_t m, int s, const int32_t* rmap, hipStream_t st) {
@@ -531,11 +517,10 @@ void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, con
   // A chunk's items each have at most work_cap leaf pairs, hence fewer than
   // 2 work_cap recursion nodes; every wave step resolves at least one.
   const int64_t step_cap = (int64_t)tun.chunk_items * (2 * (int64_t)tun.work_cap + 2) + 1024;
-  // the emit pass always reads the 64-byte split records (the packed ones
-  // serve the count pass)
+  // the emit pass always reads the children's records (the packed split
+  // records serve the count pass)
   auto k = emit ? k_wspd<true, false> : (split_recs ? k_wspd<false, true> : k_wspd<false, false>);
-  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds, st, T.inode, T.isplit64, split_recs, items, chunk_first,
-                     chunk_end,
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds, st, T.inode, split_recs, items, chunk_first, chunk_end,
                      xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, out, err);
 }
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
