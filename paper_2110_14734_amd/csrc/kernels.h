@@ -63,9 +63,12 @@ void launch_run_bounds(const uint32_t* key, int64_t n, int64_t* lo, int64_t* hi,
 void launch_bounds_count32(const int64_t* lo, const int64_t* hi, int64_t K, int32_t* out, hipStream_t st);
 // a3
 void launch_karras(const uint32_t* cpair, const uint64_t* ckey, int64_t N, int4* iaux, int32_t* iparent,
-                   int32_t* lparent, hipStream_t st);
-void launch_boxes(const int2* cij, int64_t N, const int4* iaux, const int32_t* iparent, const int32_t* lparent,
-                  uint32_t* visit, int4* ibox, int32_t* iheight, hipStream_t st);
+                   hipStream_t st);
+// Depth of each internal node (maxd: the largest; zero it first), then the
+// tight boxes and heights one depth level per launch, deepest first.
+void launch_node_depth(const int32_t* iparent, int64_t N, int32_t* depth, int32_t* maxd, hipStream_t st);
+void launch_level_boxes(const int2* cij, int64_t N, const int4* iaux, const int32_t* depth, int d, int4* ibox,
+                        int32_t* iheight, hipStream_t st);
 // a5
 void launch_diag_count(const uint32_t* cpair, const int32_t* ca, const int32_t* cb, int64_t N, uint32_t* dcnt,
                        hipStream_t st);

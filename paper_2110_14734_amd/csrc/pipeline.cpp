@@ -342,11 +342,15 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     int4* ibox = need<int4>(c, c.ibox, N - 1);
     int32_t* ih = need<int32_t>(c, c.iheight, N - 1);
     int32_t* ipar = need<int32_t>(c, c.iparent, N - 1);
-    int32_t* lpar = need<int32_t>(c, c.lparent, N);
-    uint32_t* visit = need<uint32_t>(c, c.visit, N - 1);
-    fill_u32(visit, 0, N - 1, st);
-    launch_karras((const uint32_t*)c.cpair.p, (const uint64_t*)c.ckey.p, N, iaux, ipar, lpar, st);
-    launch_boxes((const int2*)c.cij.p, N, iaux, ipar, lpar, visit, ibox, ih, st);
+    int32_t* depth = (int32_t*)need<uint32_t>(c, c.visit, N - 1);
+    launch_karras((const uint32_t*)c.cpair.p, (const uint64_t*)c.ckey.p, N, iaux, ipar, st);
+    int32_t* dmax_d = (int32_t*)need<uint64_t>(c, c.small, 64);
+    fill_u32((uint32_t*)dmax_d, 0, 1, st);
+    launch_node_depth(ipar, N, depth, dmax_d, st);
+    int32_t dmax = 0;
+    readback(c, dmax_d, &dmax, 1);
+    if (dmax >= N - 1) throw StageError{W1_EOVERFLOW};  // a parent chain longer than the tree
+    for (int d = dmax; d >= 0; --d) launch_level_boxes((const int2*)c.cij.p, N, iaux, depth, d, ibox, ih, st);
     T.ibox = ibox;
     T.iaux = iaux;
     T.iheight = ih;

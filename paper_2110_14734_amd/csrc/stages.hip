@@ -520,7 +520,7 @@ __device__ inline int delta_pk(const uint32_t* __restrict__ cpair, const uint64_
 // with one end at i; the other end and the split are found by binary search
 // on the common-prefix length.
 __global__ void k_karras(const uint32_t* __restrict__ cpair, const uint64_t* __restrict__ ckey, int64_t N,
-                         int4* __restrict__ iaux, int32_t* __restrict__ iparent, int32_t* __restrict__ lparent) {
+                         int4* __restrict__ iaux, int32_t* __restrict__ iparent) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N - 1) return;
   const int dn = delta_pk(cpair, ckey, N, i, i + 1), dp = delta_pk(cpair, ckey, N, i, i - 1);
@@ -543,49 +543,51 @@ __global__ void k_karras(const uint32_t* __restrict__ cpair, const uint64_t* __r
   const int32_t left = (lo == gamma) ? (int32_t)~gamma : (int32_t)gamma;
   const int32_t right = (hi == gamma + 1) ? (int32_t)~(gamma + 1) : (int32_t)(gamma + 1);
   iaux[i] = make_int4(left, right, (int)lo, (int)hi);
-  if (left < 0) lparent[gamma] = (int32_t)i;
-  else iparent[gamma] = (int32_t)i;
-  if (right < 0) lparent[gamma + 1] = (int32_t)i;
-  else iparent[gamma + 1] = (int32_t)i;
+  if (left >= 0) iparent[gamma] = (int32_t)i;
+  if (right >= 0) iparent[gamma + 1] = (int32_t)i;
   if (i == 0) iparent[0] = -1;
 }
 
-__device__ inline int ld_coherent(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Depth of every internal node (the root has depth 0), by climbing the
+// parent links; read-only, so no thread waits for another.  maxd receives
+// the largest depth.
+__global__ void k_node_depth(const int32_t* __restrict__ iparent, int64_t N, int32_t* __restrict__ depth,
+                             int32_t* __restrict__ maxd) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int d = 0;
+  if (g < N - 1) {
+    for (int32_t p = iparent[g]; p >= 0 && d < N; p = iparent[p]) ++d;  // d < N: stop on a malformed chain
+    depth[g] = d;
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) d = max(d, __shfl_xor(d, o));
+  if (lane_id() == 0) atomicMax(maxd, d);
 }
 
-// Bottom-up tight boxes and heights: the second child to arrive at a node
-// computes it (the first one stops), so each node is computed exactly once.
-__global__ void k_boxes(const int2* __restrict__ cij, int64_t N, const int4* __restrict__ iaux,
-                        const int32_t* __restrict__ iparent, const int32_t* __restrict__ lparent, uint32_t* __restrict__ visit,
-                        int4* ibox, int32_t* iheight) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N || N < 2) return;
-  int32_t node = lparent[c];
-  for (int64_t guard = 0; node >= 0; ++guard) {
-    if (guard > N) return;  // a parent chain longer than the tree: malformed input, stop
-    __threadfence();
-    if (atomicAdd(&visit[node], 1u) == 0) return;
-    __threadfence();
-    const int4 a = iaux[node];
-    int4 bx[2];
-    int hh[2];
-    const int32_t ch[2] = {a.x, a.y};
-    for (int q = 0; q < 2; ++q) {
-      if (ch[q] < 0) {
-        const int2 v = cij[~ch[q]];
-        bx[q] = make_int4(v.x, v.y, v.x, v.y);
-        hh[q] = 0;
-      } else {
-        const int* bp = (const int*)&ibox[ch[q]];
-        bx[q] = make_int4(ld_coherent(bp), ld_coherent(bp + 1), ld_coherent(bp + 2), ld_coherent(bp + 3));
-        hh[q] = ld_coherent(&iheight[ch[q]]);
-      }
+// Bottom-up tight boxes and heights, one depth level per launch: the nodes
+// at depth d combine their children (cells, or nodes of depth d + 1 that the
+// previous launch computed).  Launch boundaries order the levels, so no
+// fences or counters are needed.
+__global__ void k_level_boxes(const int2* __restrict__ cij, int64_t N, const int4* __restrict__ iaux,
+                              const int32_t* __restrict__ depth, int d, int4* __restrict__ ibox,
+                              int32_t* __restrict__ iheight) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N - 1 || depth[g] != d) return;
+  const int4 a = iaux[g];
+  int4 bx[2];
+  int hh[2];
+  const int32_t ch[2] = {a.x, a.y};
+  for (int q = 0; q < 2; ++q) {
+    if (ch[q] < 0) {
+      const int2 v = cij[~ch[q]];
+      bx[q] = make_int4(v.x, v.y, v.x, v.y);
+      hh[q] = 0;
+    } else {
+      bx[q] = ibox[ch[q]];
+      hh[q] = iheight[ch[q]];
     }
-    ibox[node] = make_int4(min(bx[0].x, bx[1].x), min(bx[0].y, bx[1].y), max(bx[0].z, bx[1].z), max(bx[0].w, bx[1].w));
-    iheight[node] = 1 + max(hh[0], hh[1]);
-    node = iparent[node];
   }
+  ibox[g] = make_int4(min(bx[0].x, bx[1].x), min(bx[0].y, bx[1].y), max(bx[0].z, bx[1].z), max(bx[0].w, bx[1].w));
+  iheight[g] = 1 + max(hh[0], hh[1]);
 }
 
 // ===================================================================== a5 ==
@@ -714,12 +716,15 @@ void launch_bounds_count32(const int64_t* lo, const int64_t* hi, int64_t K, int3
   LAUNCH(k_bounds_count32, K, lo, hi, K, out);
 }
 void launch_karras(const uint32_t* cpair, const uint64_t* ckey, int64_t N, int4* iaux, int32_t* iparent,
-                   int32_t* lparent, hipStream_t st) {
-  LAUNCH(k_karras, N - 1, cpair, ckey, N, iaux, iparent, lparent);
+                   hipStream_t st) {
+  LAUNCH(k_karras, N - 1, cpair, ckey, N, iaux, iparent);
 }
-void launch_boxes(const int2* cij, int64_t N, const int4* iaux, const int32_t* iparent, const int32_t* lparent,
-                  uint32_t* visit, int4* ibox, int32_t* iheight, hipStream_t st) {
-  if (N >= 2) LAUNCH(k_boxes, N, cij, N, iaux, iparent, lparent, visit, ibox, iheight);
+void launch_node_depth(const int32_t* iparent, int64_t N, int32_t* depth, int32_t* maxd, hipStream_t st) {
+  if (N >= 2) LAUNCH(k_node_depth, N - 1, iparent, N, depth, maxd);
+}
+void launch_level_boxes(const int2* cij, int64_t N, const int4* iaux, const int32_t* depth, int d, int4* ibox,
+                        int32_t* iheight, hipStream_t st) {
+  if (N >= 2) LAUNCH(k_level_boxes, N - 1, cij, N, iaux, depth, d, ibox, iheight);
 }
 void launch_diag_count(const uint32_t* cpair, const int32_t* ca, const int32_t* cb, int64_t N, uint32_t* dcnt,
                        hipStream_t st) {
