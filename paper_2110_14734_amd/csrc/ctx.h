@@ -38,7 +38,7 @@ struct Ctx {
   // groups / locations
   DBuf gb, gd, gpair, gw, lb, ld, lw, lpair, lt, lterm, lbin, li, lj;
   // rwmd buckets
-  DBuf nbuck, bincnt, binstart, ent;
+  DBuf nbuck, bincnt, binstart, ent, entl;
   // cells / tree
   DBuf ckey, cpair, cij, ca, cb, iaux, ibox, iheight, iparent, visit, inode, rmap, isplit;
   // wspd
@@ -58,7 +58,7 @@ struct Ctx {
   Ctx() {
     DBuf* list[] = {&stage, &segs, &pb, &pd, &psd, &kw0, &kw1, &kw2, &kA, &kB, &vA, &vB, &head, &idx, &scantmp, &sorttmp,
                     &small, &gb, &gd, &gpair, &gw, &lb, &ld, &lw, &lpair, &lt, &lterm, &lbin, &li, &lj, &nbuck,
-                    &bincnt, &binstart, &ent, &ckey, &cpair, &cij, &ca, &cb, &iaux, &ibox, &iheight, &iparent,
+                    &bincnt, &binstart, &ent, &entl, &ckey, &cpair, &cij, &ca, &cb, &iaux, &ibox, &iheight, &iparent,
                     &visit, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &chead, &cid,
                     &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &dcnt, &dpos,
                     &dsrc, &ddst, &dcost, &supply, &pairs};

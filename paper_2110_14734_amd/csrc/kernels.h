@@ -37,10 +37,12 @@ void launch_bucket_setup(const PairArrays& P, int64_t K, int64_t* nbuckets, hipS
 void launch_bucket_count(const double* lb, const double* ld, const int32_t* lw, const uint32_t* lpair, int64_t M,
                          const PairArrays& P, uint32_t* bincnt, int64_t* lbin, hipStream_t st);
 void launch_bucket_fill(const double* lb, const double* ld, const int64_t* lbin, int64_t M, const uint32_t* binstart,
-                        uint32_t* bincur, double2* ent, hipStream_t st);
+                        uint32_t* bincur, double2* ent, uint32_t* entl, hipStream_t st);
+// RWMD nearest neighbours: every location starts at its diagonal cost, then
+// one wave per bin (nbins = 2 * buckets + 1 bounds) searches the other side.
 void launch_nn(const double* lb, const double* ld, const int32_t* lw, const uint32_t* lpair, int64_t M,
-               const PairArrays& P, const uint32_t* binstart, const double2* ent, double* lt, double* lterm,
-               hipStream_t st);
+               const PairArrays& P, const uint32_t* binstart, const double2* ent, const uint32_t* entl, int64_t nbins,
+               double* lt, double* lterm, hipStream_t st);
 void launch_term_max(const double* lterm, const int32_t* lw, const uint32_t* lpair, int64_t M, const PairArrays& P,
                      hipStream_t st);
 void launch_rwmd_shift(const PairArrays& P, int64_t K, hipStream_t st);

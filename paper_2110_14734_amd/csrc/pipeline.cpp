@@ -256,7 +256,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     const int64_t Btot = lastb[0] + lastb[1];
     trace(c, "rwmd buckets", Btot);
     const int64_t nbins = 2 * Btot + 1;
-    if (nbins >= (int64_t(1) << 32)) throw StageError{W1_ERANGE};
+    if (nbins >= (int64_t(1) << 31)) throw StageError{W1_ERANGE};  // one workgroup per bin in the NN search
     uint32_t* bincnt = need<uint32_t>(c, c.bincnt, nbins);
     fill_u32(bincnt, 0, nbins, st);
     int64_t* lbin = need<int64_t>(c, c.lbin, M);
@@ -265,10 +265,11 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     scan_u32(bincnt, binstart, nbins, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(nbins, 8)), st);
     fill_u32(bincnt, 0, nbins, st);
     double2* ent = need<double2>(c, c.ent, M);
-    launch_bucket_fill(lb, ld, lbin, M, binstart, bincnt, ent, st);
+    uint32_t* entl = need<uint32_t>(c, c.entl, M);
+    launch_bucket_fill(lb, ld, lbin, M, binstart, bincnt, ent, entl, st);
     double* lt = need<double>(c, c.lt, M);
     double* lterm = need<double>(c, c.lterm, M);
-    launch_nn(lb, ld, lw, lpair, M, P, binstart, ent, lt, lterm, st);
+    launch_nn(lb, ld, lw, lpair, M, P, binstart, ent, entl, nbins, lt, lterm, st);
     launch_term_max(lterm, lw, lpair, M, P, st);
     launch_rwmd_shift(P, K, st);
     launch_term_sum(lterm, lw, lpair, M, P, st);

@@ -255,13 +255,14 @@ __global__ void k_bucket_count(const double* __restrict__ lb, const double* __re
 
 __global__ void k_bucket_fill(const double* __restrict__ lb, const double* __restrict__ ld, const int64_t* __restrict__ lbin,
                               int64_t M, const uint32_t* __restrict__ binstart, uint32_t* __restrict__ bincur,
-                              double2* __restrict__ ent) {
+                              double2* __restrict__ ent, uint32_t* __restrict__ entl) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= M) return;
   const int64_t bin = lbin[l];
   if (bin < 0) return;
   const uint32_t pos = binstart[bin] + atomicAdd(&bincur[bin], 1u);
   ent[pos] = make_double2(lb[l], ld[l]);
+  entl[pos] = (uint32_t)l;
 }
 
 // Nearest location of the other diagram in L-infinity, capped by the cost
@@ -269,59 +270,119 @@ __global__ void k_bucket_fill(const double* __restrict__ lb, const double* __res
 // bucket; a location in ring r is at least (r - 1) h away (bucket indices are
 // exact floors of power-of-two scalings), so after ring r nothing closer
 // than r h remains and the search stops once best <= r h.
-__global__ void __launch_bounds__(256) k_nn(const double* __restrict__ lb, const double* __restrict__ ld,
-                                            const int32_t* __restrict__ lw, const uint32_t* __restrict__ lpair, int64_t M,
-                                            PairArrays P, const uint32_t* __restrict__ binstart,
-                                            const double2* __restrict__ ent, double* __restrict__ lt,
-                                            double* __restrict__ lterm) {
+struct RingSearch {
+  const uint32_t* binstart;
+  const double2* ent;
+  int64_t base, nx, ny;
+  int opp;
+  __device__ void visit(int64_t x, int64_t y, double b, double d, double& best) const {
+    const int64_t bin = 2 * (base + y * nx + x) + opp;
+    const uint32_t e0 = binstart[bin], e1 = binstart[bin + 1];
+    for (uint32_t e = e0; e < e1; ++e) {
+      const double2 q = ent[e];
+      double dist = fabs(b - q.x);
+      const double dy = fabs(d - q.y);
+      if (dy > dist) dist = dy;
+      if (dist < best) best = dist;
+    }
+  }
+  // rings r0, r0 + 1, ... until certified or past the grid
+  __device__ void run(int64_t ix, int64_t iy, int64_t r0, int64_t rmax, double h, double b, double d, double& best) const {
+    for (int64_t r = r0;; ++r) {
+      if (r == 0) {
+        visit(ix, iy, b, d, best);
+      } else {
+        const int64_t x0 = ix - r < 0 ? 0 : ix - r, x1 = ix + r > nx - 1 ? nx - 1 : ix + r;
+        const int64_t y0 = iy - r + 1 < 0 ? 0 : iy - r + 1, y1 = iy + r - 1 > ny - 1 ? ny - 1 : iy + r - 1;
+        if (iy - r >= 0)
+          for (int64_t x = x0; x <= x1; ++x) visit(x, iy - r, b, d, best);
+        if (iy + r < ny)
+          for (int64_t x = x0; x <= x1; ++x) visit(x, iy + r, b, d, best);
+        if (ix - r >= 0)
+          for (int64_t y = y0; y <= y1; ++y) visit(ix - r, y, b, d, best);
+        if (ix + r < nx)
+          for (int64_t y = y0; y <= y1; ++y) visit(ix + r, y, b, d, best);
+      }
+      if (best <= (double)r * h || r >= rmax) break;
+    }
+  }
+};
+
+// Every location starts at its cost to the diagonal (locations of a pair
+// with an error keep it).
+__global__ void k_nn_init(const double* __restrict__ lb, const double* __restrict__ ld, const int32_t* __restrict__ lw,
+                          int64_t M, double* __restrict__ lt, double* __restrict__ lterm) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= M) return;
-  const uint32_t p = lpair[l];
-  const double b = lb[l], d = ld[l];
+  const double best = 0.5 * (ld[l] - lb[l]);
   const int32_t w = lw[l];
-  double best = 0.5 * (d - b);
-  if (!P.err[p]) {
-    int64_t ix, iy;
-    bucket_of(P, p, b, d, &ix, &iy);
-    const int64_t nx = P.bnx[p], ny = P.bny[p];
-    const int64_t base = P.bbase[p];
-    const int opp = w > 0 ? 1 : 0;
-    const double h = ldexp(1.0, P.beh[p]);
-    int64_t rmax = ix;
-    if (nx - 1 - ix > rmax) rmax = nx - 1 - ix;
-    if (iy > rmax) rmax = iy;
-    if (ny - 1 - iy > rmax) rmax = ny - 1 - iy;
-    auto visit = [&](int64_t x, int64_t y) {
-      const int64_t bin = 2 * (base + y * nx + x) + opp;
-      const uint32_t e0 = binstart[bin], e1 = binstart[bin + 1];
-      for (uint32_t e = e0; e < e1; ++e) {
-        const double2 q = ent[e];
+  lt[l] = best;
+  lterm[l] = (double)(w > 0 ? w : -w) * best;
+}
+
+// One wave per bucket side: the other diagram's locations in the 3x3 block
+// of buckets around it (rings 0 and 1) are staged in LDS once and scanned by
+// every query of the bucket.  Every location closer than h lies in that
+// block, so a query whose best is <= h is done; the others continue with
+// ring 2 onwards.  A block with more candidates than fit runs the ring
+// search from ring 0.  The minimum is over the same locations as the plain
+// ring search, so the result is identical.
+constexpr int kNnCand = 1024;
+
+__global__ void __launch_bounds__(64) k_nn_bins(const int32_t* __restrict__ lw, const uint32_t* __restrict__ lpair,
+                                                PairArrays P, const uint32_t* __restrict__ binstart,
+                                                const double2* __restrict__ ent, const uint32_t* __restrict__ entl,
+                                                double* __restrict__ lt, double* __restrict__ lterm) {
+  __shared__ double2 cand[kNnCand];
+  const int64_t qb = blockIdx.x;
+  const uint32_t e0 = binstart[qb], e1 = binstart[qb + 1];
+  if (e0 == e1) return;
+  const int lane = lane_id();
+  const uint32_t p = lpair[entl[e0]];  // every location of a bin belongs to one pair
+  RingSearch rs{binstart, ent, P.bbase[p], P.bnx[p], P.bny[p], (int)(qb & 1) ^ 1};
+  const int64_t cell = (qb >> 1) - rs.base;
+  const int64_t ix = cell % rs.nx, iy = cell / rs.nx;
+  int nc = 0;
+  bool spill = false;
+  for (int64_t y = iy - 1; y <= iy + 1; ++y)
+    for (int64_t x = ix - 1; x <= ix + 1; ++x) {
+      if (x < 0 || y < 0 || x >= rs.nx || y >= rs.ny) continue;
+      const int64_t bin = 2 * (rs.base + y * rs.nx + x) + rs.opp;
+      const uint32_t s0 = binstart[bin], cnt = binstart[bin + 1] - s0;
+      if (nc + (int)cnt > kNnCand) {
+        spill = true;
+        continue;
+      }
+      for (uint32_t t = lane; t < cnt; t += WAVE) cand[nc + t] = ent[s0 + t];
+      nc += (int)cnt;
+    }
+  __syncthreads();
+  const double h = ldexp(1.0, P.beh[p]);
+  int64_t rmax = ix;
+  if (rs.nx - 1 - ix > rmax) rmax = rs.nx - 1 - ix;
+  if (iy > rmax) rmax = iy;
+  if (rs.ny - 1 - iy > rmax) rmax = rs.ny - 1 - iy;
+  for (uint32_t e = e0 + lane; e < e1; e += WAVE) {
+    const double2 me = ent[e];
+    const double b = me.x, d = me.y;
+    double best = 0.5 * (d - b);
+    if (spill) {
+      rs.run(ix, iy, 0, rmax, h, b, d, best);
+    } else {
+      for (int c = 0; c < nc; ++c) {
+        const double2 q = cand[c];
         double dist = fabs(b - q.x);
         const double dy = fabs(d - q.y);
         if (dy > dist) dist = dy;
         if (dist < best) best = dist;
       }
-    };
-    for (int64_t r = 0;; ++r) {
-      if (r == 0) {
-        visit(ix, iy);
-      } else {
-        const int64_t x0 = ix - r < 0 ? 0 : ix - r, x1 = ix + r > nx - 1 ? nx - 1 : ix + r;
-        const int64_t y0 = iy - r + 1 < 0 ? 0 : iy - r + 1, y1 = iy + r - 1 > ny - 1 ? ny - 1 : iy + r - 1;
-        if (iy - r >= 0)
-          for (int64_t x = x0; x <= x1; ++x) visit(x, iy - r);
-        if (iy + r < ny)
-          for (int64_t x = x0; x <= x1; ++x) visit(x, iy + r);
-        if (ix - r >= 0)
-          for (int64_t y = y0; y <= y1; ++y) visit(ix - r, y);
-        if (ix + r < nx)
-          for (int64_t y = y0; y <= y1; ++y) visit(ix + r, y);
-      }
-      if (best <= (double)r * h || r >= rmax) break;
+      if (!(best <= h) && rmax >= 2) rs.run(ix, iy, 2, rmax, h, b, d, best);
     }
+    const uint32_t l = entl[e];
+    const int32_t w = lw[l];
+    lt[l] = best;
+    lterm[l] = (double)(w > 0 ? w : -w) * best;
   }
-  lt[l] = best;
-  lterm[l] = (double)(w > 0 ? w : -w) * best;
 }
 
 __global__ void k_term_max(const double* __restrict__ lterm, const int32_t* __restrict__ lw, const uint32_t* __restrict__ lpair,
@@ -673,13 +734,16 @@ void launch_bucket_count(const double* lb, const double* ld, const int32_t* lw, 
   LAUNCH(k_bucket_count, M, lb, ld, lw, lpair, M, P, bincnt, lbin);
 }
 void launch_bucket_fill(const double* lb, const double* ld, const int64_t* lbin, int64_t M, const uint32_t* binstart,
-                        uint32_t* bincur, double2* ent, hipStream_t st) {
-  LAUNCH(k_bucket_fill, M, lb, ld, lbin, M, binstart, bincur, ent);
+                        uint32_t* bincur, double2* ent, uint32_t* entl, hipStream_t st) {
+  LAUNCH(k_bucket_fill, M, lb, ld, lbin, M, binstart, bincur, ent, entl);
 }
 void launch_nn(const double* lb, const double* ld, const int32_t* lw, const uint32_t* lpair, int64_t M,
-               const PairArrays& P, const uint32_t* binstart, const double2* ent, double* lt, double* lterm,
-               hipStream_t st) {
-  LAUNCH(k_nn, M, lb, ld, lw, lpair, M, P, binstart, ent, lt, lterm);
+               const PairArrays& P, const uint32_t* binstart, const double2* ent, const uint32_t* entl, int64_t nbins,
+               double* lt, double* lterm, hipStream_t st) {
+  LAUNCH(k_nn_init, M, lb, ld, lw, M, lt, lterm);
+  if (nbins > 1)
+    hipLaunchKernelGGL(k_nn_bins, dim3((unsigned)(nbins - 1)), dim3(WAVE), 0, st, lw, lpair, P, binstart, ent, entl, lt,
+                       lterm);
 }
 void launch_term_max(const double* lterm, const int32_t* lw, const uint32_t* lpair, int64_t M, const PairArrays& P,
                      hipStream_t st) {
