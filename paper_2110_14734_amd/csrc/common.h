@@ -93,6 +93,28 @@ __device__ inline bool wave_seg_reduce(uint32_t key, T& v, Op op) {
   return tail && key != ~0u;
 }
 
+// True when every thread of the block holds the same valid key (call once
+// per kernel, from every thread).  Such a block is one run: after
+// wave_seg_reduce the last lane of each wave holds its wave's total, and
+// block_total combines them, so one atomic per block replaces one per wave.
+__device__ inline bool block_single_key(uint32_t key) {
+  __shared__ uint32_t s_k0;
+  if (threadIdx.x == 0) s_k0 = key;
+  __syncthreads();
+  const uint32_t k0 = s_k0;
+  return __syncthreads_and(key == k0 && k0 != ~0u) != 0;
+}
+
+template <typename T, typename Op>
+__device__ inline T block_total(T v, Op op) {  // 256-thread blocks, after wave_seg_reduce of one run
+  __shared__ T s[4];
+  if (lane_id() == WAVE - 1) s[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  const T r = op(op(s[0], s[1]), op(s[2], s[3]));
+  __syncthreads();
+  return r;
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ------------------------------------------------------------- primitives --
@@ -103,7 +125,10 @@ void scan_u64(const uint64_t* in, uint64_t* out, int64_t n, void* tmp, hipStream
 void scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t st);
 
 // OR and AND of n keys into out[0], out[1] (device).
-void key_or_and(const uint64_t* keys, int64_t n, uint64_t* out, hipStream_t st);
+// out[0] = OR, out[1] = AND of the n keys (0 and ~0 for n = 0); part holds
+// 2 kOrAndBlocks words of scratch.
+constexpr int kOrAndBlocks = 1024;
+void key_or_and(const uint64_t* keys, int64_t n, uint64_t* out, uint64_t* part, hipStream_t st);
 
 // Stable LSD radix sort of (key, value) by bits [bit_lo, bit_hi), 8-bit
 // digits.  Buffers k0/v0 hold the input; k1/v1 are scratch of equal size.

@@ -34,7 +34,7 @@ struct Ctx {
   int64_t K_base = 0;                      // first pair of the last launch group
   std::vector<DBuf*> all;
   // points
-  DBuf stage, segs, pb, pd, psd, kw0, kw1, kw2, kA, kB, vA, vB, head, idx, scantmp, sorttmp, small;
+  DBuf stage, orpart, segs, pb, pd, psd, kw0, kw1, kw2, kA, kB, vA, vB, head, idx, scantmp, sorttmp, small;
   // groups / locations
   DBuf gb, gd, gpair, gw, lb, ld, lw, lpair, lt, lterm, lbin, li, lj;
   // rwmd buckets
@@ -56,7 +56,7 @@ struct Ctx {
   double kms[4] = {0, 0, 0, 0};
 
   Ctx() {
-    DBuf* list[] = {&stage, &segs, &pb, &pd, &psd, &kw0, &kw1, &kw2, &kA, &kB, &vA, &vB, &head, &idx, &scantmp, &sorttmp,
+    DBuf* list[] = {&stage, &orpart, &segs, &pb, &pd, &psd, &kw0, &kw1, &kw2, &kA, &kB, &vA, &vB, &head, &idx, &scantmp, &sorttmp,
                     &small, &gb, &gd, &gpair, &gw, &lb, &ld, &lw, &lpair, &lt, &lterm, &lbin, &li, &lj, &nbuck,
                     &bincnt, &binstart, &ent, &entl, &ckey, &cpair, &cij, &ca, &cb, &iaux, &ibox, &iheight, &iparent,
                     &visit, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &chead, &cid,

@@ -45,7 +45,7 @@ void sort_words(Ctx& c, const uint64_t* const* words, int nw, int64_t n, uint32_
   for (int w = 0; w < nw; ++w) {
     if (w == 0) check(c, hipMemcpyAsync(kA, words[0], (size_t)n * 8, hipMemcpyDeviceToDevice, c.st));
     else gather_u64(words[w], vA, kA, n, c.st);
-    key_or_and(kA, n, orand, c.st);
+    key_or_and(kA, n, orand, need<uint64_t>(c, c.orpart, 2 * kOrAndBlocks), c.st);
     readback(c, orand, c.hpin, 2);
     const uint64_t vary = c.hpin[0] ^ c.hpin[1];
     if (!vary) continue;

@@ -171,10 +171,14 @@ __global__ void __launch_bounds__(RB) k_radix_scatter(const uint64_t* __restrict
   }
 }
 
-__global__ void k_or_and(const uint64_t* __restrict__ keys, int64_t n, unsigned long long* out) {
+// OR and AND of all keys in two launches without atomics: per-block
+// partials, then one block combines them.
+__global__ void __launch_bounds__(256) k_or_and_part(const uint64_t* __restrict__ keys, int64_t n,
+                                                     uint64_t* __restrict__ part) {
+  __shared__ uint64_t s_o[4], s_a[4];
   uint64_t o = 0, a = ~0ull;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-    uint64_t k = keys[x];
+    const uint64_t k = keys[x];
     o |= k;
     a &= k;
   }
@@ -182,9 +186,39 @@ __global__ void k_or_and(const uint64_t* __restrict__ keys, int64_t n, unsigned 
     o |= __shfl_xor(o, d);
     a &= __shfl_xor(a, d);
   }
+  const int w = threadIdx.x / WAVE;
   if (lane_id() == 0) {
-    atomicOr(&out[0], (unsigned long long)o);
-    atomicAnd(&out[1], (unsigned long long)a);
+    s_o[w] = o;
+    s_a[w] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s_o[0] | s_o[1] | s_o[2] | s_o[3];
+    part[2 * blockIdx.x + 1] = s_a[0] & s_a[1] & s_a[2] & s_a[3];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_or_and_final(const uint64_t* __restrict__ part, int nparts,
+                                                      uint64_t* __restrict__ out) {
+  __shared__ uint64_t s_o[4], s_a[4];
+  uint64_t o = 0, a = ~0ull;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+    o |= part[2 * b];
+    a &= part[2 * b + 1];
+  }
+  for (int d = WAVE / 2; d > 0; d >>= 1) {
+    o |= __shfl_xor(o, d);
+    a &= __shfl_xor(a, d);
+  }
+  const int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    s_o[w] = o;
+    s_a[w] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = s_o[0] | s_o[1] | s_o[2] | s_o[3];
+    out[1] = s_a[0] & s_a[1] & s_a[2] & s_a[3];
   }
 }
 
@@ -228,11 +262,10 @@ void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* tmp, hipStream
 void scan_u64(const uint64_t* in, uint64_t* out, int64_t n, void* tmp, hipStream_t st) { scan_impl<uint64_t>(in, out, n, tmp, st); }
 void scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t st) { scan_impl<int64_t>(in, out, n, tmp, st); }
 
-void key_or_and(const uint64_t* keys, int64_t n, uint64_t* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill<uint64_t>, dim3(1), dim3(64), 0, st, out, (uint64_t)0, (int64_t)1);
-  hipLaunchKernelGGL(k_fill<uint64_t>, dim3(1), dim3(64), 0, st, out + 1, ~(uint64_t)0, (int64_t)1);
-  if (n > 0) hipLaunchKernelGGL(k_or_and, dim3(grid_for(n, 256) > 1024 ? 1024 : grid_for(n, 256)), dim3(256), 0, st, keys, n,
-                                (unsigned long long*)out);
+void key_or_and(const uint64_t* keys, int64_t n, uint64_t* out, uint64_t* part, hipStream_t st) {
+  const unsigned g = n > 0 ? (grid_for(n, 256) > kOrAndBlocks ? (unsigned)kOrAndBlocks : grid_for(n, 256)) : 0;
+  if (g > 0) hipLaunchKernelGGL(k_or_and_part, dim3(g), dim3(256), 0, st, keys, n, part);
+  hipLaunchKernelGGL(k_or_and_final, dim3(1), dim3(256), 0, st, part, (int)g, out);
 }
 
 size_t radix_tmp_bytes(int64_t n) {

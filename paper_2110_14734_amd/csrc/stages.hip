@@ -158,10 +158,18 @@ __global__ void k_loc_fill(const int32_t* __restrict__ gw, const uint32_t* __res
     else { nb = -(int64_t)w; cb = 1; }
   }
   const uint32_t k0 = key;
+  const bool one = block_single_key(k0);
   bool t = wave_seg_reduce(k0, na, op_add<int64_t>);
   wave_seg_reduce(k0, nb, op_add<int64_t>);
   wave_seg_reduce(k0, ca, op_add<int32_t>);
   wave_seg_reduce(k0, cb, op_add<int32_t>);
+  if (one) {
+    na = block_total(na, op_add<int64_t>);
+    nb = block_total(nb, op_add<int64_t>);
+    ca = block_total(ca, op_add<int32_t>);
+    cb = block_total(cb, op_add<int32_t>);
+    t = threadIdx.x == 0;
+  }
   if (t) {
     if (na) atomicAdd((unsigned long long*)&P.nA[k0], (unsigned long long)na);
     if (nb) atomicAdd((unsigned long long*)&P.nB[k0], (unsigned long long)nb);
@@ -181,10 +189,18 @@ __global__ void k_loc_bbox(const double* __restrict__ lb, const double* __restri
     b0 = b1 = ordered_bits(dbl_bits(lb[l]));
     d0 = d1 = ordered_bits(dbl_bits(ld[l]));
   }
+  const bool one = block_single_key(key);
   bool t = wave_seg_reduce(key, b0, u64min);
   wave_seg_reduce(key, b1, u64max);
   wave_seg_reduce(key, d0, u64min);
   wave_seg_reduce(key, d1, u64max);
+  if (one) {
+    b0 = block_total(b0, u64min);
+    b1 = block_total(b1, u64max);
+    d0 = block_total(d0, u64min);
+    d1 = block_total(d1, u64max);
+    t = threadIdx.x == 0;
+  }
   if (t) {
     atomicMin((unsigned long long*)&P.bmin[key], (unsigned long long)b0);
     atomicMax((unsigned long long*)&P.bmax[key], (unsigned long long)b1);
@@ -396,8 +412,14 @@ __global__ void k_term_max(const double* __restrict__ lterm, const int32_t* __re
     if (lw[l] > 0) a = bits;
     else b = bits;
   }
+  const bool one = block_single_key(key);
   bool t = wave_seg_reduce(key, a, u64max);
   wave_seg_reduce(key, b, u64max);
+  if (one) {
+    a = block_total(a, u64max);
+    b = block_total(b, u64max);
+    t = threadIdx.x == 0;
+  }
   if (t) {
     if (a) atomicMax((unsigned long long*)&P.tmaxA[key], (unsigned long long)a);
     if (b) atomicMax((unsigned long long*)&P.tmaxB[key], (unsigned long long)b);
@@ -431,8 +453,14 @@ __global__ void k_term_sum(const double* __restrict__ lterm, const int32_t* __re
     if (isA) a = q;
     else b = q;
   }
+  const bool one = block_single_key(key);
   bool t = wave_seg_reduce(key, a, op_add<uint64_t>);
   wave_seg_reduce(key, b, op_add<uint64_t>);
+  if (one) {
+    a = block_total(a, op_add<uint64_t>);
+    b = block_total(b, op_add<uint64_t>);
+    t = threadIdx.x == 0;
+  }
   if (t) {
     if (a) atomicAdd((unsigned long long*)&P.sumA[key], (unsigned long long)a);
     if (b) atomicAdd((unsigned long long*)&P.sumB[key], (unsigned long long)b);
@@ -485,8 +513,14 @@ __global__ void k_snap(const double* __restrict__ lb, const double* __restrict__
       }
     }
   }
-  if (wave_seg_reduce(key, I, [](int64_t a, int64_t b) { return a < b ? a : b; }))
-    atomicMin((long long*)&P.m0[key], (long long)I);
+  const auto imin = [](int64_t a, int64_t b) { return a < b ? a : b; };
+  const bool one = block_single_key(key);
+  bool t = wave_seg_reduce(key, I, imin);
+  if (one) {
+    I = block_total(I, imin);
+    t = threadIdx.x == 0;
+  }
+  if (t) atomicMin((long long*)&P.m0[key], (long long)I);
 }
 
 __global__ void k_morton(const int64_t* __restrict__ li, const int64_t* __restrict__ lj, const uint32_t* __restrict__ lpair,
@@ -621,7 +655,8 @@ __global__ void k_node_depth(const int32_t* __restrict__ iparent, int64_t N, int
     depth[g] = d;
   }
   for (int o = WAVE / 2; o > 0; o >>= 1) d = max(d, __shfl_xor(d, o));
-  if (lane_id() == 0) atomicMax(maxd, d);
+  d = block_total(d, [](int a, int b) { return a > b ? a : b; });  // every lane holds its wave's max
+  if (threadIdx.x == 0) atomicMax(maxd, d);
 }
 
 // Bottom-up tight boxes and heights, one depth level per launch: the nodes
