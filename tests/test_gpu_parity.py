@@ -322,3 +322,22 @@ def test_compact_records_and_wide_extent(orc, ctx):
     extent = (B[:, 1].max() - A[:, 0].min()) / g.grid
     assert 2.0**28 < extent < 2.0**30, (g.grid_exp, extent)
     compare(orc, ctx, A, B, eps=0.1)
+
+
+def test_rwmd_dense_cluster(orc, ctx):
+    """A cluster far denser than the RWMD bucket grid assumes: the 3x3 block
+    of buckets around it holds thousands of candidates, more than the LDS
+    stage takes, so its queries run the full ring search; every stage still
+    matches the oracle."""
+    _say("[gpu] RWMD dense cluster")
+    rng = np.random.default_rng(21)
+
+    def cluster(n, seed_shift):
+        b = 0.5 + 0.005 * rng.random(n)
+        d = 0.6 + 0.005 * rng.random(n)
+        out = np.array([[0.0, 1.0], [0.9, 1.0], [0.1 + 0.01 * seed_shift, 0.7]])
+        return np.concatenate([np.stack([b, d], 1), out])
+
+    A, B = cluster(3000, 0), cluster(3000, 1)
+    g, _ = compare(orc, ctx, A, B, eps=0.2, flow=False)
+    assert g.n_locations > 6000
