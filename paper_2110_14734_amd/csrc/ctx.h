@@ -40,7 +40,7 @@ struct Ctx {
   // rwmd buckets
   DBuf nbuck, bincnt, binstart, ent, entl;
   // cells / tree
-  DBuf ckey, cpair, cij, ca, cb, iaux, ibox, iheight, iparent, visit, inode, rmap, isplit;
+  DBuf ckey, cpair, cij, ca, cb, iaux, ibox, iheight, iparent, ndepth, inode, rmap, isplit;
   // wspd
   DBuf itemsA, itemsB, itemsI, itemsS, icnt, ipos, ipp, chead, cid, cfirst, cend, cpairs, ccnt, coff, xrange, xctr, err;
   // network
@@ -59,7 +59,7 @@ struct Ctx {
     DBuf* list[] = {&stage, &orpart, &segs, &pb, &pd, &psd, &kw0, &kw1, &kw2, &kA, &kB, &vA, &vB, &head, &idx, &scantmp, &sorttmp,
                     &small, &gb, &gd, &gpair, &gw, &lb, &ld, &lw, &lpair, &lt, &lterm, &lbin, &li, &lj, &nbuck,
                     &bincnt, &binstart, &ent, &entl, &ckey, &cpair, &cij, &ca, &cb, &iaux, &ibox, &iheight, &iparent,
-                    &visit, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &chead, &cid,
+                    &ndepth, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &chead, &cid,
                     &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &dcnt, &dpos,
                     &dsrc, &ddst, &dcost, &supply, &pairs};
     all.assign(std::begin(list), std::end(list));

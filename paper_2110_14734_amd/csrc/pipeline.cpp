@@ -343,7 +343,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     int4* ibox = need<int4>(c, c.ibox, N - 1);
     int32_t* ih = need<int32_t>(c, c.iheight, N - 1);
     int32_t* ipar = need<int32_t>(c, c.iparent, N - 1);
-    int32_t* depth = (int32_t*)need<uint32_t>(c, c.visit, N - 1);
+    int32_t* depth = need<int32_t>(c, c.ndepth, N - 1);
     launch_karras((const uint32_t*)c.cpair.p, (const uint64_t*)c.ckey.p, N, iaux, ipar, st);
     int32_t* dmax_d = (int32_t*)need<uint64_t>(c, c.small, 64);
     fill_u32((uint32_t*)dmax_d, 0, 1, st);
