@@ -107,7 +107,8 @@ void launch_pack_nodes(const TreeView& T, const int64_t* cell_start, int4* rec, 
 // must be below 2^28.
 void launch_pack_split(const TreeView& T, uint4* out, hipStream_t st);
 // Final work items (node references) -> work entries of the passes.
-void launch_item_prep(const TreeView& T, int2* items, int64_t m, int s, const int32_t* rmap, hipStream_t st);
+void launch_item_prep(const TreeView& T, const int2* items, const uint32_t* perm, int64_t m, int s, const int32_t* rmap,
+                      int2* out, hipStream_t st);
 void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st);
 void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st);
 void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s, const WspdTuning& tun,
@@ -116,12 +117,13 @@ void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const 
                          int2* out_items, int64_t out_base, int2* next, hipStream_t st);
 void launch_item_keys(const TreeView& T, const int2* items, int64_t m, bool both, uint64_t* keys, hipStream_t st);
 void launch_gather_items(const int2* src, const uint32_t* perm, int2* dst, int64_t m, hipStream_t st);
-void launch_item_bounds(const TreeView& T, const int2* items, int64_t m, int64_t* lo, int64_t* hi, hipStream_t st);
-void launch_chunk_heads(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start, int chunk,
-                        uint32_t* head, hipStream_t st);
-void launch_chunk_fill(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start,
-                       const int32_t* items_per_pair, const uint32_t* head, const uint32_t* cid, int chunk,
-                       int32_t* chunk_first, int32_t* chunk_end, int32_t* chunk_pair, hipStream_t st);
+// Per-pair item runs of the sorted work list (keys: first representative
+// cells), and the chunks from the per-pair item counts: cstart[p] = first
+// chunk of pair p (K + 1 values, cstart[K] = nch).
+void launch_item_bounds(const uint32_t* cpair, const uint64_t* keys, int64_t m, int64_t* lo, int64_t* hi,
+                        hipStream_t st);
+void launch_chunks(const int32_t* cstart, int64_t K, const int64_t* item_start, const int32_t* ipp, int64_t nch,
+                   int chunk, int32_t* chunk_first, int32_t* chunk_end, int32_t* chunk_pair, hipStream_t st);
 // Count (emit = false) or emit pass; split_recs = packed split records for
 // the count pass, or nullptr to read the children's records (the emit pass
 // always does).

@@ -435,32 +435,34 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       uint64_t* top;
       const uint64_t* words[1] = {keys};
       sort_words(c, words, 1, m, &perm, &top);
-      int2* S = need<int2>(c, c.itemsS, m);
-      launch_gather_items(I, perm, S, m, st);
       int32_t* ipp = need<int32_t>(c, c.ipp, K);
       fill_u64((uint64_t*)P.seg_lo, 0, K, st);
       fill_u64((uint64_t*)P.seg_hi, 0, K, st);
-      launch_item_bounds(T, S, m, P.seg_lo, P.seg_hi, st);
+      launch_item_bounds(T.cpair, top, m, P.seg_lo, P.seg_hi, st);
       launch_bounds_count32(P.seg_lo, P.seg_hi, K, ipp, st);
+      int2* S = need<int2>(c, c.itemsS, m);  // work entries in sorted order
+      launch_item_prep(T, I, perm, m, s, (const int32_t*)c.rmap.p, S, st);
       timed = true;
       std::vector<int32_t> hipp = fetch_pairs(c, ipp, K);
       std::vector<int64_t> ist((size_t)K);
-      int64_t acc = 0;
+      std::vector<int32_t> cst((size_t)K + 1);
+      int64_t acc = 0, nch = 0;
       for (int64_t p = 0; p < K; ++p) {
         ist[(size_t)p] = acc;
+        cst[(size_t)p] = (int32_t)nch;
         acc += hipp[(size_t)p];
+        nch += (hipp[(size_t)p] + tun.chunk_items - 1) / tun.chunk_items;
       }
+      cst[(size_t)K] = (int32_t)nch;
+      if (nch >= (int64_t(1) << 31)) throw StageError{W1_EOVERFLOW};
       upload(c, P.item_start, ist.data(), (size_t)K * 8);
-      uint32_t* ch = need<uint32_t>(c, c.chead, m);
-      launch_chunk_heads(T, S, m, P.item_start, tun.chunk_items, ch, st);
-      uint32_t* cidv = scan_flags(c, ch, m, c.cid);
-      const int64_t nch = (int64_t)total_of(c, ch, cidv, m);
+      int32_t* cstd = need<int32_t>(c, c.cid, K + 1);
+      upload(c, cstd, cst.data(), (size_t)(K + 1) * 4);
       trace(c, "chunks", nch);
       int32_t* cf = need<int32_t>(c, c.cfirst, nch);
       int32_t* ce = need<int32_t>(c, c.cend, nch);
       int32_t* cp = need<int32_t>(c, c.cpairs, nch);
-      launch_chunk_fill(T, S, m, P.item_start, ipp, ch, cidv, tun.chunk_items, cf, ce, cp, st);
-      launch_item_prep(T, S, m, s, (const int32_t*)c.rmap.p, st);  // S holds work entries from here on
+      launch_chunks(cstd, K, P.item_start, ipp, nch, tun.chunk_items, cf, ce, cp, st);
       int32_t hr[9];
       for (int x = 0; x <= 8; ++x) hr[x] = (int32_t)((nch * x) / 8);
       int32_t* xr = need<int32_t>(c, c.xrange, 16);

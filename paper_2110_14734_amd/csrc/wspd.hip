@@ -120,37 +120,36 @@ __global__ void k_gather_items(const int2* __restrict__ src, const uint32_t* __r
   if (x < m) dst[x] = src[perm[x]];
 }
 
-// Bounds of each diagram pair's run of work-list items (items are sorted
-// pair-major): first item writes lo[p], last writes hi[p].
-__global__ void k_item_bounds(TreeView T, const int2* __restrict__ items, int64_t m, int64_t* __restrict__ lo,
-                              int64_t* __restrict__ hi) {
+// Bounds of each diagram pair's run of work-list items, from the sorted
+// keys (the first representative's cell, pair-major): first item writes
+// lo[p], last writes hi[p].
+__global__ void k_item_bounds(const uint32_t* __restrict__ cpair, const uint64_t* __restrict__ keys, int64_t m,
+                              int64_t* __restrict__ lo, int64_t* __restrict__ hi) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= m) return;
-  const uint32_t p = T.cpair[node_rep(T, items[x].x)];
-  if (x == 0 || T.cpair[node_rep(T, items[x - 1].x)] != p) lo[p] = x;
-  if (x == m - 1 || T.cpair[node_rep(T, items[x + 1].x)] != p) hi[p] = x + 1;
+  const uint32_t p = cpair[(uint32_t)keys[x]];
+  if (x == 0 || cpair[(uint32_t)keys[x - 1]] != p) lo[p] = x;
+  if (x == m - 1 || cpair[(uint32_t)keys[x + 1]] != p) hi[p] = x + 1;
 }
 
-__global__ void k_chunk_heads(TreeView T, const int2* __restrict__ items, int64_t m, const int64_t* __restrict__ item_start,
-                              int chunk, uint32_t* __restrict__ head) {
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= m) return;
-  const uint32_t p = T.cpair[node_rep(T, items[x].x)];
-  head[x] = ((x - item_start[p]) % chunk) == 0 ? 1u : 0u;
-}
-
-__global__ void k_chunk_fill(TreeView T, const int2* __restrict__ items, int64_t m, const int64_t* __restrict__ item_start,
-                             const int32_t* __restrict__ ipp, const uint32_t* __restrict__ head,
-                             const uint32_t* __restrict__ cid, int chunk, int32_t* __restrict__ chunk_first,
-                             int32_t* __restrict__ chunk_end, int32_t* __restrict__ chunk_pair) {
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= m || !head[x]) return;
-  const uint32_t p = T.cpair[node_rep(T, items[x].x)];
-  const uint32_t c = cid[x];
-  const int64_t pend = item_start[p] + ipp[p];
+// Chunk c of the work list: pair p is the last one with cstart[p] <= c (a
+// pair's items are cut into ceil(items / chunk) chunks, in item order).
+__global__ void k_chunks(const int32_t* __restrict__ cstart, int64_t K, const int64_t* __restrict__ item_start,
+                         const int32_t* __restrict__ ipp, int64_t nch, int chunk, int32_t* __restrict__ chunk_first,
+                         int32_t* __restrict__ chunk_end, int32_t* __restrict__ chunk_pair) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nch) return;
+  int64_t a = 0, b = K;  // cstart[a] <= c < cstart[b]
+  while (b - a > 1) {
+    const int64_t h = (a + b) / 2;
+    if (cstart[h] <= c) a = h;
+    else b = h;
+  }
+  const int64_t x = item_start[a] + (c - cstart[a]) * (int64_t)chunk;
+  const int64_t pend = item_start[a] + ipp[a];
   chunk_first[c] = (int32_t)x;
   chunk_end[c] = (int32_t)(x + chunk < pend ? x + chunk : pend);
-  chunk_pair[c] = (int32_t)p;
+  chunk_pair[c] = (int32_t)a;
 }
 
 // Traversal record, 32 bytes: int4 box (min i, min j, max i, max j) and
@@ -200,10 +199,12 @@ __global__ void k_pack_nodes(TreeView T, const int64_t* __restrict__ cell_start,
 // orient = 1 when P is the pair's first node U.  The split rule (longer box
 // side, ties split the second node) is applied when an entry is made; a
 // separated entry (fresh items only) is output as it is, U = P.
-__global__ void k_item_prep(TreeView T, int2* __restrict__ items, int64_t m, int s, const int32_t* __restrict__ rmap) {
+// Gathers the sorted work list (items[perm[x]]) and writes the entries.
+__global__ void k_item_prep(TreeView T, const int2* __restrict__ items, const uint32_t* __restrict__ perm, int64_t m,
+                            int s, const int32_t* __restrict__ rmap, int2* __restrict__ out) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= m) return;
-  const int2 it = items[x];
+  const int2 it = items[perm[x]];
   const int4 bu = node_box(T, it.x), bv = node_box(T, it.y);
   const int32_t ru = rmap[ref_index(T, it.x)], rv = rmap[ref_index(T, it.y)];
   int2 e;
@@ -213,7 +214,7 @@ __global__ void k_item_prep(TreeView T, int2* __restrict__ items, int64_t m, int
     e = make_int2(ru | INT32_MIN, rv);
   else
     e = make_int2(rv, ru);
-  items[x] = e;
+  out[x] = e;
 }
 
 // Packed split record of internal node g, 32 bytes: the boxes of its two
@@ -473,8 +474,9 @@ void launch_pack_nodes(const TreeView& T, const int64_t* cell_start, int4* rec, 
   LAUNCH(k_pack_nodes, T.N - 1, T, cell_start, rec, rmap);
 }
 void launch_pack_split(const TreeView& T, uint4* out, hipStream_t st) { LAUNCH(k_pack_split, T.N - 1, T, out); }
-void launch_item_prep(const TreeView& T, int2* items, int64_t m, int s, const int32_t* rmap, hipStream_t st) {
-  LAUNCH(k_item_prep, m, T, items, m, s, rmap);
+void launch_item_prep(const TreeView& T, const int2* items, const uint32_t* perm, int64_t m, int s, const int32_t* rmap,
+                      int2* out, hipStream_t st) {
+  LAUNCH(k_item_prep, m, T, items, perm, m, s, rmap, out);
 }
 void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st) { LAUNCH(k_roots_flags, T.N - 1, T, flag); }
 void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st) {
@@ -494,17 +496,13 @@ void launch_item_keys(const TreeView& T, const int2* items, int64_t m, bool both
 void launch_gather_items(const int2* src, const uint32_t* perm, int2* dst, int64_t m, hipStream_t st) {
   LAUNCH(k_gather_items, m, src, perm, dst, m);
 }
-void launch_item_bounds(const TreeView& T, const int2* items, int64_t m, int64_t* lo, int64_t* hi, hipStream_t st) {
-  LAUNCH(k_item_bounds, m, T, items, m, lo, hi);
+void launch_item_bounds(const uint32_t* cpair, const uint64_t* keys, int64_t m, int64_t* lo, int64_t* hi,
+                        hipStream_t st) {
+  LAUNCH(k_item_bounds, m, cpair, keys, m, lo, hi);
 }
-void launch_chunk_heads(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start, int chunk,
-                        uint32_t* head, hipStream_t st) {
-  LAUNCH(k_chunk_heads, m, T, items, m, item_start, chunk, head);
-}
-void launch_chunk_fill(const TreeView& T, const int2* items, int64_t m, const int64_t* item_start,
-                       const int32_t* items_per_pair, const uint32_t* head, const uint32_t* cid, int chunk,
-                       int32_t* chunk_first, int32_t* chunk_end, int32_t* chunk_pair, hipStream_t st) {
-  LAUNCH(k_chunk_fill, m, T, items, m, item_start, items_per_pair, head, cid, chunk, chunk_first, chunk_end, chunk_pair);
+void launch_chunks(const int32_t* cstart, int64_t K, const int64_t* item_start, const int32_t* ipp, int64_t nch,
+                   int chunk, int32_t* chunk_first, int32_t* chunk_end, int32_t* chunk_pair, hipStream_t st) {
+  LAUNCH(k_chunks, nch, cstart, K, item_start, ipp, nch, chunk, chunk_first, chunk_end, chunk_pair);
 }
 void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
