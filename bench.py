@@ -34,7 +34,7 @@ PAIR_BYTES = 12  # one WSPD pair in the network: u32 u, u32 v, i32 cost
 # (each scaled by the 1 GiB copy calibration).  Valid only for the kernel
 # source they were measured on: reported only while its hash prefix matches.
 EMIT_TRAFFIC_BYTES = 26.38e9
-EMIT_TRAFFIC_SRC = ("paper_2110_14734_amd/csrc/wspd.hip", "cac8e65854dd2c08")
+EMIT_TRAFFIC_SRC = ("paper_2110_14734_amd/csrc/wspd.hip", "fdf1f05a928203e3")
 
 
 def measured_traffic(n_points, eps):
