@@ -84,9 +84,12 @@ typedef struct {
   double eps;         /* target relative error, 0 < eps <= 1                  */
   double cond_frac;   /* share kappa of eps spent on grid condensation,        */
                       /* 0 < kappa < 0.5; 0 selects 0.1                         */
-  int32_t s_override; /* > 2: use this WSPD separation s instead of the one   */
+  int32_t s_override; /* > 0: use this WSPD separation s instead of the one   */
                       /* derived from eps (the (1+eps) bound then does not     */
-                      /* hold; this is the paper's "sparsity parameter" mode) */
+                      /* hold; this is the paper's sparsity-parameter mode of */
+                      /* Sec. 5.5; s <= 2 has no stretch bound at all, as for */
+                      /* its s = 1 runs in Sec. 7, but w1 is still an upper   */
+                      /* bound on W1); < 0 is W1_EINVAL                        */
   uint32_t flags;     /* W1_* flags above                                      */
   int64_t pivot_cap;  /* network simplex pivot limit, 0 = unlimited            */
 } w1_params;

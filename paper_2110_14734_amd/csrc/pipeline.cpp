@@ -719,7 +719,7 @@ int entry(Ctx* c, const w1_pd* a, const w1_pd* b, int64_t K, const w1_params* pa
     o.s = params->s_override;
     o.flags = params->flags;
     o.pivot_cap = params->pivot_cap;
-    if (params->s_override != 0 && params->s_override < 3) return W1_EINVAL;
+    if (params->s_override < 0) return W1_EINVAL;
   }
   if (!(o.eps > 0.0 && o.eps <= 1.0) || !(o.kappa > 0.0 && o.kappa < 0.5)) return W1_EINVAL;
   if (hipSetDevice(c->device) != hipSuccess) return W1_EHIP;

@@ -119,7 +119,7 @@ def test_stage_parity(orc, ctx, name, make, eps):
     compare(orc, ctx, A, B, eps=eps)
 
 
-@pytest.mark.parametrize("s_override", [3, 6, 12])
+@pytest.mark.parametrize("s_override", [1, 2, 3, 6, 12])
 def test_paper_mode_small_s(orc, ctx, s_override):
     _say(f"[gpu] s_override {s_override}")
     A, B = pdsynth.exp_pd(500, 12), pdsynth.exp_pd(480, 13)

@@ -262,7 +262,7 @@ def test_tree_invariants(orc):
 
 
 # -------------------------------------------------------------------- WSPD --
-@pytest.mark.parametrize("s_override", [3, 5, 12, 53])
+@pytest.mark.parametrize("s_override", [1, 2, 3, 5, 12, 53])
 def test_wspd_bruteforce_coverage(orc, s_override):
     for seed in range(3):
         A = pdsynth.exp_pd(24, 50 + seed, mean_pers=0.3)
@@ -270,6 +270,24 @@ def test_wspd_bruteforce_coverage(orc, s_override):
         r = orc.run(A, B, eps=0.2, s_override=s_override, flags=orc.ORC_KEEP_PAIR_NODES | orc.ORC_NO_FLOW)
         assert r.cells["i"].shape[0] >= 30
         orc.wspd_coverage(r)
+
+
+@pytest.mark.parametrize("s_override", [1, 2, 3])
+def test_small_s_still_upper_bound(orc, s_override):
+    # With no stretch bound (s <= 2) the sparse network still only holds
+    # real arcs between cell representatives, so its optimum is at least the
+    # complete network's and the output stays above the exact W1 (Sec. 5.5
+    # and the condensation bound of Sec. 5.1).
+    for seed in range(4):
+        A = pdsynth.exp_pd(40, 80 + seed, mean_pers=0.2)
+        B = pdsynth.exp_pd(36, 90 + seed, mean_pers=0.2)
+        r = orc.run(A, B, eps=0.2, s_override=s_override)
+        assert r.status == 0 and r.s == s_override
+        assert r.W1 >= orc.exact_w1(A, B) * (1 - 1e-12)
+        # A pair separated at s is separated at any smaller s, so the same
+        # traversal stops no later: the pair count cannot drop as s grows.
+        r2 = orc.run(A, B, eps=0.2, s_override=s_override + 1, flags=orc.ORC_NO_FLOW)
+        assert 0 < r.n_pairs <= r2.n_pairs
 
 
 @pytest.mark.parametrize("s_override", [4, 9, 28])
