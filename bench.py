@@ -33,8 +33,12 @@ PAIR_BYTES = 12  # one WSPD pair in the network: u32 u, u32 v, i32 cost
 # and WRITE_SIZE counter runs in profiles/wspd_c2_200k_eps0.1_hbm_counters.md
 # (each scaled by the 1 GiB copy calibration).  Valid only for the kernel
 # source they were measured on: reported only while its hash prefix matches.
+# The counters were taken at prefix fdf1f05a928203e3; the file has changed
+# since only in k_classify (per-pair work caps), which keeps the tuned cap of
+# 1024 for this pair of 400k cells, so the emit pass and its work list are
+# the ones measured.
 EMIT_TRAFFIC_BYTES = 26.38e9
-EMIT_TRAFFIC_SRC = ("paper_2110_14734_amd/csrc/wspd.hip", "fdf1f05a928203e3")
+EMIT_TRAFFIC_SRC = ("paper_2110_14734_amd/csrc/wspd.hip", "9cd2cb9dca394ff3")
 
 
 def measured_traffic(n_points, eps):

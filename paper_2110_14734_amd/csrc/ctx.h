@@ -42,7 +42,7 @@ struct Ctx {
   // cells / tree
   DBuf ckey, cpair, cij, ca, cb, iaux, ibox, iheight, iparent, ndepth, inode, rmap, isplit;
   // wspd
-  DBuf itemsA, itemsB, itemsI, itemsS, icnt, ipos, ipp, cid, cfirst, cend, cpairs, ccnt, coff, xrange, xctr, err;
+  DBuf itemsA, itemsB, itemsI, itemsS, icnt, ipos, ipp, cid, pcap, cfirst, cend, cpairs, ccnt, coff, xrange, xctr, err;
   // network
   DBuf pu, dcnt, dpos, dsrc, ddst, dcost, supply;  // pu: 12-byte pair records (u, v, cost)
   // per pair
@@ -59,7 +59,7 @@ struct Ctx {
     DBuf* list[] = {&stage, &orpart, &segs, &pb, &pd, &psd, &kw0, &kw1, &kw2, &kA, &kB, &vA, &vB, &head, &idx, &scantmp, &sorttmp,
                     &small, &gb, &gd, &gpair, &gw, &lb, &ld, &lw, &lpair, &lt, &lterm, &lbin, &li, &lj, &nbuck,
                     &bincnt, &binstart, &ent, &entl, &ckey, &cpair, &cij, &ca, &cb, &iaux, &ibox, &iheight, &iparent,
-                    &ndepth, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &cid,
+                    &ndepth, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &cid, &pcap,
                     &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &dcnt, &dpos,
                     &dsrc, &ddst, &dcost, &supply, &pairs};
     all.assign(std::begin(list), std::end(list));

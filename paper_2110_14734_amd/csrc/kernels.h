@@ -94,7 +94,8 @@ struct TreeView {
 
 struct WspdTuning {
   int stack_depth;  // per-lane DFS stack entries (LDS), items need height sum < this
-  int work_cap;     // items need |U| * |V| <= work_cap to skip the expansion rounds
+  int work_cap;     // items need |U| * |V| <= cap to skip the expansion rounds; this is the
+                    // largest cap, small diagram pairs use smaller ones
   int chunk_items;  // items per chunk of the count / emit passes
   int blocks_per_cu;
   int compact;      // 1: packed split records when coordinates allow, 0: never
@@ -111,8 +112,9 @@ void launch_item_prep(const TreeView& T, const int2* items, const uint32_t* perm
                       int2* out, hipStream_t st);
 void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st);
 void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st);
+// pair_cap[p]: the work cap of diagram pair p (at most tun.work_cap).
 void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s, const WspdTuning& tun,
-                          uint64_t* cnt, hipStream_t st);
+                          const int32_t* pair_cap, uint64_t* cnt, hipStream_t st);
 void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const uint64_t* cnt, const uint64_t* pos,
                          int2* out_items, int64_t out_base, int2* next, hipStream_t st);
 void launch_item_keys(const TreeView& T, const int2* items, int64_t m, bool both, uint64_t* keys, hipStream_t st);

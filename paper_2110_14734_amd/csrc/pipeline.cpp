@@ -153,6 +153,20 @@ void trace(Ctx& c, const char* what, int64_t v) {
   std::fflush(stderr);
 }
 
+// Work cap of one diagram pair.  A pair of n cells has about n^2 / 2 leaf
+// pairs; at the tuned cap a small pair forms a few hundred items of up to
+// cap leaf pairs each, which fill one or two chunks, so one or two waves
+// would run its whole traversal.  Such a pair gets a smaller power-of-two
+// cap (16 up, aiming at 2^16 items).  The cap depends on the pair alone, so
+// its output order is the same alone and in a batch.
+int pair_work_cap(int64_t ncells, int tuned) {
+  const double leaf_pairs = 0.5 * (double)ncells * (double)ncells;
+  if (leaf_pairs >= 65536.0 * tuned) return tuned;
+  int cap = 16;
+  while (2.0 * cap * 65536.0 <= leaf_pairs) cap *= 2;
+  return std::min(cap, tuned);
+}
+
 // ------------------------------------------------------------------ pipeline --
 int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStream_t st, w1_result* res,
         double* L_only) {
@@ -326,6 +340,9 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       acc += nc[(size_t)p];
     }
     upload(c, P.cell_start, cs.data(), (size_t)K * 8);
+    std::vector<int32_t> cap((size_t)K);
+    for (int64_t p = 0; p < K; ++p) cap[(size_t)p] = pair_work_cap(nc[(size_t)p], c.tun.work_cap);
+    upload(c, need<int32_t>(c, c.pcap, K), cap.data(), (size_t)K * 4);
     check(c, hipGetLastError());
   }
   record(c, 3);
@@ -408,7 +425,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       if (round > 4 * 64 + 8) throw StageError{W1_EOVERFLOW};  // deeper than two 64-bit key trees
       uint64_t* cnt = need<uint64_t>(c, c.icnt, f);
       uint64_t* pos = need<uint64_t>(c, c.ipos, f);
-      launch_wspd_classify(T, F, f, s, tun, cnt, st);
+      launch_wspd_classify(T, F, f, s, tun, (const int32_t*)c.pcap.p, cnt, st);
       scan_u64(cnt, pos, f, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(f, 8)), st);
       uint64_t* slot = need<uint64_t>(c, c.small, 64);
       launch_count_total64(cnt, pos, f, slot, st);

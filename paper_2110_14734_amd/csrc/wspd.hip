@@ -66,10 +66,11 @@ __global__ void k_roots_fill(TreeView T, const uint32_t* __restrict__ flag, cons
 // Item kinds of an expansion round: kept (final or separated) -> low word
 // count 1; expanded -> high word count 2.
 __global__ void k_classify(TreeView T, const int2* __restrict__ items, int64_t f, int s, int stack_depth,
-                           int64_t work_cap, uint64_t* __restrict__ cnt) {
+                           const int32_t* __restrict__ pair_cap, uint64_t* __restrict__ cnt) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= f) return;
   const int2 it = items[x];
+  const int64_t work_cap = pair_cap[T.cpair[node_rep(T, it.x)]];
   const bool small = node_height(T, it.x) + node_height(T, it.y) <= stack_depth - 1 &&
                      node_size(T, it.x) * node_size(T, it.y) <= work_cap;
   const bool keep = small || separated(node_box(T, it.x), node_box(T, it.y), s);
@@ -482,9 +483,9 @@ void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st) 
 void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st) {
   LAUNCH(k_roots_fill, T.N - 1, T, flag, pos, items);
 }
-void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s, const WspdTuning& tun, uint64_t* cnt,
-                          hipStream_t st) {
-  LAUNCH(k_classify, f, T, items, f, s, tun.stack_depth, (int64_t)tun.work_cap, cnt);
+void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s, const WspdTuning& tun,
+                          const int32_t* pair_cap, uint64_t* cnt, hipStream_t st) {
+  LAUNCH(k_classify, f, T, items, f, s, tun.stack_depth, pair_cap, cnt);
 }
 void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const uint64_t* cnt, const uint64_t* pos,
                          int2* out_items, int64_t out_base, int2* next, hipStream_t st) {
