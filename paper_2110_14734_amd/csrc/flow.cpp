@@ -23,6 +23,10 @@
 //  * Tree storage: parent, predecessor arc, depth and doubly linked child
 //    lists; after a pivot the detached subtree is re-rooted along the path to
 //    the entering arc and its potentials and depths are shifted by a DFS.
+//  * Flow: without capacities every non-tree arc carries zero flow, so the
+//    flow is kept per node, on its predecessor arc.  The pivot's cycle walk
+//    then touches node arrays only, not the m-arc arrays; arc flows are
+//    formed once at the end.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -56,14 +60,11 @@ struct Simplex {
   int32_t n = 0, root = 0;
   int64_t m = 0;
   std::vector<int32_t> src, dst;
-  std::vector<int64_t> cost, flow;
-  std::vector<uint8_t> in_tree;
+  std::vector<int64_t> tflow;  // flow on pred[v], per node
   std::vector<int32_t> parent, pred, depth, first_child, next_sib, prev_sib;
   std::vector<uint8_t> up;  // pred arc runs node -> parent
   std::vector<int64_t> pi;
   std::vector<int32_t> path, stack;
-
-  int64_t rc(int64_t a) const { return cost[a] + pi[src[a]] - pi[dst[a]]; }
 
   void unlink(int32_t x) {
     const int32_t p = parent[x];
@@ -106,9 +107,7 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
   try {
     S.src.resize((size_t)ma);
     S.dst.resize((size_t)ma);
-    S.cost.resize((size_t)ma);
-    S.flow.assign((size_t)ma, 0);
-    S.in_tree.assign((size_t)ma, 0);
+    S.tflow.assign((size_t)n + 1, 0);
     S.parent.assign((size_t)n + 1, -1);
     S.pred.assign((size_t)n + 1, -1);
     S.depth.assign((size_t)n + 1, 0);
@@ -123,23 +122,20 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
   for (int64_t a = 0; a < m; ++a) {
     S.src[a] = (int32_t)src[a];
     S.dst[a] = (int32_t)dst[a];
-    S.cost[a] = cost[a];
   }
   const int64_t ART = (maxc + 1) * ((int64_t)n + 1);
   for (int32_t v = 0; v < n; ++v) {
     const int64_t a = m + v;
-    S.cost[a] = ART;
-    S.in_tree[a] = 1;
     if (supply[v] > 0) {
       S.src[a] = v;
       S.dst[a] = S.root;
-      S.flow[a] = supply[v];
+      S.tflow[v] = supply[v];
       S.up[v] = 1;
       S.pi[v] = -ART;
     } else {
       S.src[a] = S.root;
       S.dst[a] = v;
-      S.flow[a] = -supply[v];
+      S.tflow[v] = -supply[v];
       S.up[v] = 0;
       S.pi[v] = ART;
     }
@@ -198,47 +194,48 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
     int32_t leave_node = -1;
     bool leave_on_k = false;
     for (int32_t v = k; v != apex; v = S.parent[v])
-      if (S.up[v] && S.flow[S.pred[v]] < delta) {
-        delta = S.flow[S.pred[v]];
+      if (S.up[v] && S.tflow[v] < delta) {
+        delta = S.tflow[v];
         leave_node = v;
         leave_on_k = true;
       }
     for (int32_t v = l; v != apex; v = S.parent[v])
-      if (!S.up[v] && S.flow[S.pred[v]] <= delta) {
-        delta = S.flow[S.pred[v]];
+      if (!S.up[v] && S.tflow[v] <= delta) {
+        delta = S.tflow[v];
         leave_node = v;
         leave_on_k = false;
       }
     if (leave_node < 0) return -1;  // unbounded: impossible with non-negative costs
     // ---- flow update
     if (delta > 0) {
-      for (int32_t v = k; v != apex; v = S.parent[v]) S.flow[S.pred[v]] += S.up[v] ? -delta : delta;
-      for (int32_t v = l; v != apex; v = S.parent[v]) S.flow[S.pred[v]] += S.up[v] ? delta : -delta;
-      S.flow[enter] += delta;
+      for (int32_t v = k; v != apex; v = S.parent[v]) S.tflow[v] += S.up[v] ? -delta : delta;
+      for (int32_t v = l; v != apex; v = S.parent[v]) S.tflow[v] += S.up[v] ? delta : -delta;
     }
     // ---- tree update: detach the subtree at leave_node, re-root it at the
     // entering arc's endpoint inside it, hang it below the other endpoint.
     const int32_t u_in = leave_on_k ? k : l, v_in = leave_on_k ? l : k;
-    const int64_t leave_arc = S.pred[leave_node];
     S.path.clear();
     for (int32_t v = u_in;; v = S.parent[v]) {
       S.path.push_back(v);
       if (v == leave_node) break;
     }
     for (int32_t v : S.path) S.unlink(v);
+    // Each path node takes over its predecessor's tree arc and that arc's
+    // flow; the first takes the entering arc, which now carries delta, and
+    // the leaving arc (flow 0) drops out.
     int32_t new_parent = v_in;
-    int64_t new_pred = enter;
+    int64_t new_pred = enter, new_flow = delta;
     for (size_t i = 0; i < S.path.size(); ++i) {
       const int32_t v = S.path[i];
-      const int64_t old_pred = S.pred[v];
+      const int64_t old_pred = S.pred[v], old_flow = S.tflow[v];
       S.link(v, new_parent);
       S.pred[v] = (int32_t)new_pred;
+      S.tflow[v] = new_flow;
       S.up[v] = S.src[new_pred] == v ? 1 : 0;
       new_parent = v;
       new_pred = old_pred;
+      new_flow = old_flow;
     }
-    S.in_tree[leave_arc] = 0;
-    S.in_tree[enter] = 1;
     const int64_t dpi = leave_on_k ? -best : best;
     S.stack.clear();
     S.stack.push_back(u_in);
@@ -253,12 +250,17 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
   out->pivots = pivots;
   out->status = status;
   int64_t c = 0;
-  for (int64_t a = 0; a < m; ++a) c += S.cost[a] * S.flow[a];
-  if (status == 0)
-    for (int32_t v = 0; v < n; ++v)
-      if (S.flow[m + v] != 0) return -1;  // supplies cannot be routed
+  for (int32_t v = 0; v < n; ++v) {
+    const int64_t a = S.pred[v];
+    if (a < m) c += (int64_t)cost[a] * S.tflow[v];
+    else if (status == 0 && S.tflow[v] != 0) return -1;  // supplies cannot be routed
+  }
   out->cost = c;
-  if (out->flow) std::copy(S.flow.begin(), S.flow.begin() + m, out->flow);
+  if (out->flow) {
+    std::fill(out->flow, out->flow + m, int64_t(0));
+    for (int32_t v = 0; v < n; ++v)
+      if (S.pred[v] < m) out->flow[S.pred[v]] = S.tflow[v];
+  }
   if (out->pot) std::copy(S.pi.begin(), S.pi.begin() + n, out->pot);
   return 0;
 }
