@@ -59,7 +59,11 @@ void price_run(const int32_t* t, const int32_t* h, const int32_t* c, const int64
 struct Simplex {
   int32_t n = 0, root = 0;
   int64_t m = 0;
-  std::vector<int32_t> src, dst;
+  // Network arcs 0..m-1 are read in place from the caller's arrays; the
+  // artificial arc m + v joins v and the root, leaving v when art_out[v].
+  const int32_t *src = nullptr, *dst = nullptr;
+  std::vector<uint8_t> art_out;
+  int32_t tail(int64_t a) const { return a < m ? src[a] : (art_out[a - m] ? (int32_t)(a - m) : root); }
   std::vector<int64_t> tflow;  // flow on pred[v], per node
   std::vector<int32_t> parent, pred, depth, first_child, next_sib, prev_sib;
   std::vector<uint8_t> up;  // pred arc runs node -> parent
@@ -103,10 +107,12 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
   S.n = n;
   S.root = n;
   S.m = m;
-  const int64_t ma = m + n;
+  // Node indices are below 2^31 - 1 (checked above), so the unsigned arc
+  // ends read as int32 unchanged.
+  S.src = reinterpret_cast<const int32_t*>(src);
+  S.dst = reinterpret_cast<const int32_t*>(dst);
   try {
-    S.src.resize((size_t)ma);
-    S.dst.resize((size_t)ma);
+    S.art_out.assign((size_t)n, 0);
     S.tflow.assign((size_t)n + 1, 0);
     S.parent.assign((size_t)n + 1, -1);
     S.pred.assign((size_t)n + 1, -1);
@@ -119,22 +125,15 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
   } catch (...) {
     return -3;
   }
-  for (int64_t a = 0; a < m; ++a) {
-    S.src[a] = (int32_t)src[a];
-    S.dst[a] = (int32_t)dst[a];
-  }
   const int64_t ART = (maxc + 1) * ((int64_t)n + 1);
   for (int32_t v = 0; v < n; ++v) {
     const int64_t a = m + v;
     if (supply[v] > 0) {
-      S.src[a] = v;
-      S.dst[a] = S.root;
+      S.art_out[v] = 1;
       S.tflow[v] = supply[v];
       S.up[v] = 1;
       S.pi[v] = -ART;
     } else {
-      S.src[a] = S.root;
-      S.dst[a] = v;
       S.tflow[v] = -supply[v];
       S.up[v] = 0;
       S.pi[v] = ART;
@@ -160,9 +159,9 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
         // the wrap comes first in scan order, so it wins ties.
         const int64_t len = std::min(block, m - scanned);
         const int64_t end1 = std::min(m, a + len);
-        price_run(S.src.data(), S.dst.data(), cost, pi, a, end1, &best, &enter);
+        price_run(S.src, S.dst, cost, pi, a, end1, &best, &enter);
         if (a + len > m) {
-          price_run(S.src.data(), S.dst.data(), cost, pi, 0, a + len - m, &best, &enter);
+          price_run(S.src, S.dst, cost, pi, 0, a + len - m, &best, &enter);
           a = a + len - m;
         } else {
           a = end1 == m ? 0 : end1;
@@ -231,7 +230,7 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
       S.link(v, new_parent);
       S.pred[v] = (int32_t)new_pred;
       S.tflow[v] = new_flow;
-      S.up[v] = S.src[new_pred] == v ? 1 : 0;
+      S.up[v] = S.tail(new_pred) == v ? 1 : 0;
       new_parent = v;
       new_pred = old_pred;
       new_flow = old_flow;
