@@ -293,8 +293,8 @@ def cpu_baseline(A, B, eps):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(f"bench.py measures one GPU only: this build runs the method on a single MI355X "
-              f"(got --gpus {args.gpus}); multi-GPU sharding is described in DESIGN.md, not run.",
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the method runs on a single "
+              f"MI355X; sharding across GPUs is designed but not built.",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
