@@ -91,6 +91,19 @@ def test_network_simplex_on_oracle_networks(orc):
         _certificate(sup.shape[0], src.astype(np.uint32), dst.astype(np.uint32), cost, sup, flow, pot)
 
 
+def test_network_simplex_full_size_network(orc):
+    # the 400 + 400 point network at eps 0.1 (about 400k arcs, blocks that
+    # wrap past the last arc, tens of thousands of pivots)
+    A, B = pdsynth.exp_pd(400, 0), pdsynth.exp_pd(400, 1)
+    src, dst, cost, sup = orc.network(A, B, eps=0.1)
+    assert src.shape[0] > 300_000
+    r = orc.run(A, B, eps=0.1)
+    c, piv, st, flow, pot = w1.flow_solve(sup.shape[0], src, dst, cost, sup, certificate=True)
+    assert st == w1.W1_OPTIMAL and piv > 1000
+    assert c == r.flow
+    _certificate(sup.shape[0], src.astype(np.uint32), dst.astype(np.uint32), cost, sup, flow, pot)
+
+
 def test_network_simplex_pivot_cap_and_errors():
     src = np.array([0, 1, 0], np.uint32)
     dst = np.array([1, 2, 2], np.uint32)
