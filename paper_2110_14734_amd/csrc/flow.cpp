@@ -22,7 +22,8 @@
 //    branches on every improvement.
 //  * Tree storage: parent, predecessor arc, depth and doubly linked child
 //    lists; after a pivot the detached subtree is re-rooted along the path to
-//    the entering arc and its potentials and depths are shifted by a DFS.
+//    the entering arc and its potentials and depths are shifted by a
+//    preorder walk of the child lists (no stack).
 //  * Flow: without capacities every non-tree arc carries zero flow, so the
 //    flow is kept per node, on its predecessor arc.  The pivot's cycle walk
 //    then touches node arrays only, not the m-arc arrays; arc flows are
@@ -68,7 +69,7 @@ struct Simplex {
   std::vector<int32_t> parent, pred, depth, first_child, next_sib, prev_sib;
   std::vector<uint8_t> up;  // pred arc runs node -> parent
   std::vector<int64_t> pi;
-  std::vector<int32_t> path, stack;
+  std::vector<int32_t> path;
 
   void unlink(int32_t x) {
     const int32_t p = parent[x];
@@ -236,14 +237,16 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
       new_flow = old_flow;
     }
     const int64_t dpi = leave_on_k ? -best : best;
-    S.stack.clear();
-    S.stack.push_back(u_in);
-    while (!S.stack.empty()) {
-      const int32_t v = S.stack.back();
-      S.stack.pop_back();
+    for (int32_t v = u_in;;) {
       S.pi[v] += dpi;
       S.depth[v] = S.depth[S.parent[v]] + 1;
-      for (int32_t c = S.first_child[v]; c >= 0; c = S.next_sib[c]) S.stack.push_back(c);
+      if (S.first_child[v] >= 0) {
+        v = S.first_child[v];
+        continue;
+      }
+      while (v != u_in && S.next_sib[v] < 0) v = S.parent[v];
+      if (v == u_in) break;
+      v = S.next_sib[v];
     }
   }
   out->pivots = pivots;
