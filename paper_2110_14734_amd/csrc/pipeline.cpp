@@ -154,11 +154,11 @@ void trace(Ctx& c, const char* what, int64_t v) {
 }
 
 // Work cap of one diagram pair.  A pair of n cells has about n^2 / 2 leaf
-// pairs; at the tuned cap a small pair forms a few hundred items of up to
-// cap leaf pairs each, which fill one or two chunks, so one or two waves
-// would run its whole traversal.  Such a pair gets a smaller power-of-two
-// cap (16 up, aiming at 2^16 items).  The cap depends on the pair alone, so
-// its output order is the same alone and in a batch.
+// pairs; at the tuned cap a small pair forms a few thousand items of up to
+// cap leaf pairs each, which fill only a handful of chunks, so a handful of
+// waves would run its whole traversal.  Such a pair gets a smaller
+// power-of-two cap (16 up, aiming at 2^16 items).  The cap depends on the
+// pair alone, so its output order is the same alone and in a batch.
 int pair_work_cap(int64_t ncells, int tuned) {
   const double leaf_pairs = 0.5 * (double)ncells * (double)ncells;
   if (leaf_pairs >= 65536.0 * tuned) return tuned;
