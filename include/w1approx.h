@@ -195,9 +195,9 @@ int w1_device_network_get(w1_ctx *ctx, int64_t k, w1_device_network *out);
  *                  are expanded until the tree heights of their two nodes sum
  *                  to less than this;
  *   work_cap       items are expanded until |U| |V| <= work_cap (cells).
- *                  A pair of n cells with n^2 / 2 < 2^16 work_cap uses a
+ *                  A pair of n cells with n^2 / 2 < 2^14 work_cap uses a
  *                  smaller cap: the largest power of two c >= 16 with
- *                  2^16 c <= n^2 / 2, else 16 (smaller items spread a small
+ *                  2^14 c <= n^2 / 2, else 16 (smaller items spread a small
  *                  pair's traversal over more waves);
  *   chunk_items    work-list items per chunk of the persistent passes;
  *   blocks_per_cu  resident blocks per compute unit of those passes (1..16);

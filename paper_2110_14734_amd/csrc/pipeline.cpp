@@ -156,14 +156,15 @@ void trace(Ctx& c, const char* what, int64_t v) {
 // Work cap of one diagram pair.  A pair of n cells has about n^2 / 2 leaf
 // pairs; at the tuned cap a small pair forms a few thousand items of up to
 // cap leaf pairs each, which fill only a handful of chunks, so a handful of
-// waves would run its whole traversal.  Such a pair gets a smaller
-// power-of-two cap (16 up, aiming at 2^16 items).  The cap depends on the
-// pair alone, so its output order is the same alone and in a batch.
+// waves would run its whole traversal.  Such a pair (n^2 / 2 below 2^14
+// times the tuned cap) gets the largest power of two c >= 16 with
+// 2^14 c <= n^2 / 2, else 16.  The cap depends on the pair alone, so its
+// output order is the same alone and in a batch.
 int pair_work_cap(int64_t ncells, int tuned) {
   const double leaf_pairs = 0.5 * (double)ncells * (double)ncells;
-  if (leaf_pairs >= 65536.0 * tuned) return tuned;
+  if (leaf_pairs >= 16384.0 * tuned) return tuned;
   int cap = 16;
-  while (2.0 * cap * 65536.0 <= leaf_pairs) cap *= 2;
+  while (2.0 * cap * 16384.0 <= leaf_pairs) cap *= 2;
   return std::min(cap, tuned);
 }
 
