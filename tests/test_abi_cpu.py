@@ -117,6 +117,13 @@ def test_network_simplex_pivot_cap_and_errors():
         w1.flow_solve(3, src, dst, cost, np.array([3, 0, -2], np.int64))  # unbalanced
     with pytest.raises(w1.W1Error):
         w1.flow_solve(3, src[:2], dst[:2], cost[:2], np.array([0, 3, -3], np.int64)[::-1].copy())  # infeasible
+    with pytest.raises(w1.W1Error):
+        w1.flow_solve(3, src, dst, np.array([1, -1, 5], np.int32), sup)  # negative cost
+    with pytest.raises(w1.W1Error):
+        w1.flow_solve(3, src, np.array([1, 3, 2], np.uint32), cost, sup)  # node out of range
+    # no arcs: only an all-zero supply is feasible
+    c3, piv3, st3 = w1.flow_solve(2, src[:0], dst[:0], cost[:0], np.zeros(2, np.int64))
+    assert c3 == 0 and piv3 == 0 and st3 == w1.W1_OPTIMAL
 
 
 def test_learned_form_entry_points_reject_bad_arguments():
