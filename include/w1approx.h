@@ -57,7 +57,11 @@ extern "C" {
 
 /* ---- w1_result.status --------------------------------------------------- */
 #define W1_OPTIMAL 0      /* flow solved to optimality (or not requested)    */
-#define W1_STALLED 1      /* pivot_cap reached: flow_cost is not optimal     */
+#define W1_STALLED 1      /* pivot_cap reached: the flow is not optimal.  If */
+                          /* it meets every supply, flow_cost is its cost    */
+                          /* and w1 >= exact W1 still holds (without the     */
+                          /* (1 + eps) bound); otherwise flow_solved = 0,    */
+                          /* flow_cost = -1 and w1 = w1_paper = NaN          */
 
 /* ---- dtypes -------------------------------------------------------------- */
 #define W1_F32 0
@@ -234,7 +238,10 @@ int w1_ctx_last_kernel_times(const w1_ctx *ctx, double *ms, int n);
  * cost[k]; supply[v] = out-flow minus in-flow.  flow_out (m) and pot_out
  * (n_nodes, reduced cost cost + pot[src] - pot[dst] >= 0 at optimum) may be
  * NULL.  Returns W1_OK, W1_EINVAL (infeasible / bad input) or W1_ENOMEM;
- * *status_out is W1_OPTIMAL or W1_STALLED. */
+ * *status_out is W1_OPTIMAL or W1_STALLED.  After a stall *cost_out is the
+ * cost of the flow reached if that flow meets every supply, else -1.  Arc
+ * numbers are 64-bit inside the solver: m is limited by memory only; node
+ * numbers must be below 2^31 - 1. */
 int w1_flow_solve(int64_t n_nodes, int64_t m, const uint32_t *src, const uint32_t *dst, const int32_t *cost,
                   const int64_t *supply, int64_t pivot_cap, int64_t *cost_out, int64_t *flow_out,
                   int64_t *pot_out, int64_t *pivots_out, int32_t *status_out);

@@ -16,10 +16,14 @@
 //    every basis strongly feasible, so degenerate pivots cannot cycle (this
 //    takes over the job of the paper's random jitter, which it used against
 //    stalling).
-//  * Pricing reads the arcs as three int32 arrays (tail, head, cost) over
-//    runs that do not wrap past the last arc, with branch-free running
-//    minima: about 1.4x faster than a scan that tests for the wrap and
-//    branches on every improvement.
+//  * Arcs come as a CSR network (row_ptr, col, cost): the arcs of a row
+//    share their tail, so pricing reads one potential per row and one per
+//    arc, over runs that do not wrap past the last arc, with branch-free
+//    running minima.  The tail of a single arc (a tree arc after a pivot)
+//    is found by binary search in row_ptr.
+//  * Arc numbers are int64 throughout (network arcs 0..m-1, the artificial
+//    arc of node v is m + v), so m is limited by memory only; node numbers
+//    are int32.
 //  * Tree storage: parent, predecessor arc, depth and doubly linked child
 //    lists; after a pivot the detached subtree is re-rooted along the path to
 //    the entering arc and its potentials and depths are shifted by a
@@ -39,18 +43,18 @@ namespace w1 {
 
 namespace {
 
-// Most negative reduced cost c[b] + pi[t[b]] - pi[h[b]] over arcs b in
-// [a, end) that is below *best; on success *best and *enter take the value
-// and the first arc that reaches it.  Two running minima (even and odd
-// offsets) halve the dependent chain; they merge by value, then by the
-// earlier arc, so the pick is the one of a single scan.
-void price_run(const int32_t* t, const int32_t* h, const int32_t* c, const int64_t* pi, int64_t a,
-               int64_t end, int64_t* best, int64_t* enter) {
+// Most negative reduced cost c[b] + pit - pi[h[b]] over arcs b in [a, end)
+// of one row (tail potential pit) that is below *best; on success *best and
+// *enter take the value and the first arc that reaches it.  Two running
+// minima (even and odd offsets) halve the dependent chain; they merge by
+// value, then by the earlier arc, so the pick is the one of a single scan.
+void price_run(const int32_t* h, const int32_t* c, const int64_t* pi, int64_t pit, int64_t a, int64_t end,
+               int64_t* best, int64_t* enter) {
   int64_t sv = *best, si = -1, sv1 = *best, si1 = -1;
   int64_t b = a;
   for (; b + 2 <= end; b += 2) {
-    const int64_t r0 = (int64_t)c[b] + pi[t[b]] - pi[h[b]];
-    const int64_t r1 = (int64_t)c[b + 1] + pi[t[b + 1]] - pi[h[b + 1]];
+    const int64_t r0 = (int64_t)c[b] + pit - pi[h[b]];
+    const int64_t r1 = (int64_t)c[b + 1] + pit - pi[h[b + 1]];
     const bool l0 = r0 < sv, l1 = r1 < sv1;
     sv = l0 ? r0 : sv;
     si = l0 ? b : si;
@@ -62,7 +66,7 @@ void price_run(const int32_t* t, const int32_t* h, const int32_t* c, const int64
     si = si1;
   }
   for (; b < end; ++b) {
-    const int64_t r = (int64_t)c[b] + pi[t[b]] - pi[h[b]];
+    const int64_t r = (int64_t)c[b] + pit - pi[h[b]];
     const bool lt = r < sv;
     sv = lt ? r : sv;
     si = lt ? b : si;
@@ -73,16 +77,34 @@ void price_run(const int32_t* t, const int32_t* h, const int32_t* c, const int64
   }
 }
 
+// Row of arc a: the last r with row_ptr[r] <= a (a < row_ptr[n]).
+int32_t row_of(const int64_t* row_ptr, int32_t n, int64_t a) {
+  return (int32_t)(std::upper_bound(row_ptr, row_ptr + n + 1, a) - row_ptr) - 1;
+}
+
+// Prices the arcs [a, end) row by row, starting in row *r (which holds a).
+void price_range(const int64_t* row_ptr, const int32_t* h, const int32_t* c, const int64_t* pi, int32_t* r,
+                 int64_t a, int64_t end, int64_t* best, int64_t* enter) {
+  while (a < end) {
+    while (row_ptr[*r + 1] <= a) ++*r;
+    const int64_t e = std::min(end, row_ptr[*r + 1]);
+    price_run(h, c, pi, pi[*r], a, e, best, enter);
+    a = e;
+  }
+}
+
 struct Simplex {
   int32_t n = 0, root = 0;
   int64_t m = 0;
-  // Network arcs 0..m-1 are read in place from the caller's arrays; the
+  // Network arcs 0..m-1 are read in place from the caller's CSR arrays; the
   // artificial arc m + v joins v and the root, leaving v when art_out[v].
-  const int32_t *src = nullptr, *dst = nullptr;
+  const int64_t* row_ptr = nullptr;
+  const int32_t* col = nullptr;
   std::vector<uint8_t> art_out;
-  int32_t tail(int64_t a) const { return a < m ? src[a] : (art_out[a - m] ? (int32_t)(a - m) : root); }
+  int32_t tail(int64_t a) const { return a < m ? row_of(row_ptr, n, a) : (art_out[a - m] ? (int32_t)(a - m) : root); }
   std::vector<int64_t> tflow;  // flow on pred[v], per node
-  std::vector<int32_t> parent, pred, depth, first_child, next_sib, prev_sib;
+  std::vector<int64_t> pred;   // tree arc joining v to its parent
+  std::vector<int32_t> parent, depth, first_child, next_sib, prev_sib;
   std::vector<uint8_t> up;  // pred arc runs node -> parent
   std::vector<int64_t> pi;
   std::vector<int32_t> path;
@@ -105,29 +127,35 @@ struct Simplex {
 
 }  // namespace
 
-int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint32_t* dst, const int32_t* cost,
+int network_simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int32_t* cost,
                     const int64_t* supply, int64_t pivot_cap, FlowResult* out) {
   out->cost = -1;
   out->pivots = 0;
   out->status = 0;
-  if (n_nodes < 0 || m < 0 || n_nodes >= (int64_t(1) << 31) - 1) return -1;
+  out->feasible = 0;
+  if (n_nodes < 0 || n_nodes >= (int64_t(1) << 31) - 1 || !row_ptr || (n_nodes > 0 && !supply)) return -1;
+  const int32_t n = (int32_t)n_nodes;
+  if (row_ptr[0] != 0) return -1;
+  for (int32_t v = 0; v < n; ++v)
+    if (row_ptr[v + 1] < row_ptr[v]) return -1;
+  const int64_t m = row_ptr[n];
+  if (m > 0 && (!col || !cost)) return -1;
   int64_t total = 0;
-  for (int64_t v = 0; v < n_nodes; ++v) total += supply[v];
+  for (int32_t v = 0; v < n; ++v) total += supply[v];
   if (total != 0) return -1;
   int64_t maxc = 0;
   for (int64_t a = 0; a < m; ++a) {
-    if (cost[a] < 0 || src[a] >= (uint64_t)n_nodes || dst[a] >= (uint64_t)n_nodes) return -1;
+    if (cost[a] < 0 || col[a] >= (uint64_t)n_nodes) return -1;
     maxc = std::max<int64_t>(maxc, cost[a]);
   }
   Simplex S;
-  const int32_t n = (int32_t)n_nodes;
   S.n = n;
   S.root = n;
   S.m = m;
+  S.row_ptr = row_ptr;
   // Node indices are below 2^31 - 1 (checked above), so the unsigned arc
-  // ends read as int32 unchanged.
-  S.src = reinterpret_cast<const int32_t*>(src);
-  S.dst = reinterpret_cast<const int32_t*>(dst);
+  // heads read as int32 unchanged.
+  S.col = reinterpret_cast<const int32_t*>(col);
   try {
     S.art_out.assign((size_t)n, 0);
     S.tflow.assign((size_t)n + 1, 0);
@@ -144,7 +172,6 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
   }
   const int64_t ART = (maxc + 1) * ((int64_t)n + 1);
   for (int32_t v = 0; v < n; ++v) {
-    const int64_t a = m + v;
     if (supply[v] > 0) {
       S.art_out[v] = 1;
       S.tflow[v] = supply[v];
@@ -155,38 +182,47 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
       S.up[v] = 0;
       S.pi[v] = ART;
     }
-    S.pred[v] = (int32_t)a;
+    S.pred[v] = m + v;
     S.depth[v] = 1;
     S.link(v, S.root);
   }
 
   const int64_t block = std::max<int64_t>(10, (int64_t)(0.25 * std::sqrt((double)std::max<int64_t>(m, 1))));
   int64_t next_arc = 0;
+  int32_t next_row = 0;  // row holding next_arc
   int64_t pivots = 0;
   int status = 0;
   for (;;) {
     // ---- entering arc: block search.  Tree arcs have reduced cost exactly 0
     // (integer potentials), so they never enter and need no test.
     int64_t enter = -1, best = 0;
+    int32_t k = -1;
     if (m > 0) {
       const int64_t* pi = S.pi.data();
       int64_t a = next_arc, scanned = 0;
+      int32_t r = next_row;
       while (scanned < m) {
         // One block, split where it wraps past the last arc; the part before
         // the wrap comes first in scan order, so it wins ties.
         const int64_t len = std::min(block, m - scanned);
         const int64_t end1 = std::min(m, a + len);
-        price_run(S.src, S.dst, cost, pi, a, end1, &best, &enter);
+        price_range(row_ptr, S.col, cost, pi, &r, a, end1, &best, &enter);
         if (a + len > m) {
-          price_run(S.src, S.dst, cost, pi, 0, a + len - m, &best, &enter);
+          r = 0;
+          price_range(row_ptr, S.col, cost, pi, &r, 0, a + len - m, &best, &enter);
           a = a + len - m;
         } else {
-          a = end1 == m ? 0 : end1;
+          a = end1;
+          if (a == m) {
+            a = 0;
+            r = 0;
+          }
         }
         scanned += len;
         if (enter >= 0) break;
       }
       next_arc = a;
+      next_row = r;
     }
     if (enter < 0) break;
     if (pivot_cap > 0 && pivots >= pivot_cap) {
@@ -194,7 +230,8 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
       break;
     }
     ++pivots;
-    const int32_t k = S.src[enter], l = S.dst[enter];
+    k = row_of(row_ptr, n, enter);
+    const int32_t l = S.col[enter];
     // ---- apex
     int32_t x = k, y = l;
     while (S.depth[x] > S.depth[y]) x = S.parent[x];
@@ -238,16 +275,17 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
     for (int32_t v : S.path) S.unlink(v);
     // Each path node takes over its predecessor's tree arc and that arc's
     // flow; the first takes the entering arc, which now carries delta, and
-    // the leaving arc (flow 0) drops out.
+    // the leaving arc (flow 0) drops out.  The first node's tail test uses
+    // the entering arc's known tail.
     int32_t new_parent = v_in;
     int64_t new_pred = enter, new_flow = delta;
     for (size_t i = 0; i < S.path.size(); ++i) {
       const int32_t v = S.path[i];
       const int64_t old_pred = S.pred[v], old_flow = S.tflow[v];
       S.link(v, new_parent);
-      S.pred[v] = (int32_t)new_pred;
+      S.pred[v] = new_pred;
       S.tflow[v] = new_flow;
-      S.up[v] = S.tail(new_pred) == v ? 1 : 0;
+      S.up[v] = (i == 0 ? k : S.tail(new_pred)) == v ? 1 : 0;
       new_parent = v;
       new_pred = old_pred;
       new_flow = old_flow;
@@ -267,13 +305,19 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
   }
   out->pivots = pivots;
   out->status = status;
+  // Flow cost over the network arcs.  A stalled solve may leave supply on
+  // artificial arcs: its network flow is then not feasible, and no cost is
+  // reported for it (feasible = 0, cost = -1).
   int64_t c = 0;
+  bool feasible = true;
   for (int32_t v = 0; v < n; ++v) {
     const int64_t a = S.pred[v];
     if (a < m) c += (int64_t)cost[a] * S.tflow[v];
-    else if (status == 0 && S.tflow[v] != 0) return -1;  // supplies cannot be routed
+    else if (S.tflow[v] != 0) feasible = false;
   }
-  out->cost = c;
+  if (!feasible && status == 0) return -1;  // supplies cannot be routed
+  out->feasible = feasible ? 1 : 0;
+  out->cost = feasible ? c : -1;
   if (out->flow) {
     std::fill(out->flow, out->flow + m, int64_t(0));
     for (int32_t v = 0; v < n; ++v)
@@ -281,6 +325,48 @@ int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint3
   }
   if (out->pot) std::copy(S.pi.begin(), S.pi.begin() + n, out->pot);
   return 0;
+}
+
+int network_simplex_arcs(int64_t n_nodes, int64_t m, const uint32_t* src, const uint32_t* dst, const int32_t* cost,
+                         const int64_t* supply, int64_t pivot_cap, FlowResult* out) {
+  out->cost = -1;
+  out->pivots = 0;
+  out->status = 0;
+  out->feasible = 0;
+  if (n_nodes < 0 || m < 0 || n_nodes >= (int64_t(1) << 31) - 1) return -1;
+  if (m > 0 && (!src || !dst || !cost)) return -1;
+  for (int64_t a = 0; a < m; ++a)
+    if (src[a] >= (uint64_t)n_nodes || dst[a] >= (uint64_t)n_nodes) return -1;
+  // Arcs in CSR order (stable counting sort by tail); flows map back.
+  std::vector<int64_t> row_ptr, perm;
+  std::vector<uint32_t> col;
+  std::vector<int32_t> cst;
+  std::vector<int64_t> flow_csr;
+  try {
+    row_ptr.assign((size_t)n_nodes + 1, 0);
+    for (int64_t a = 0; a < m; ++a) ++row_ptr[(size_t)src[a] + 1];
+    for (int64_t v = 0; v < n_nodes; ++v) row_ptr[(size_t)v + 1] += row_ptr[(size_t)v];
+    perm.resize((size_t)m);
+    col.resize((size_t)m);
+    cst.resize((size_t)m);
+    std::vector<int64_t> fill(row_ptr.begin(), row_ptr.end() - 1);
+    for (int64_t a = 0; a < m; ++a) {
+      const int64_t q = fill[src[a]]++;
+      perm[(size_t)q] = a;
+      col[(size_t)q] = dst[a];
+      cst[(size_t)q] = cost[a];
+    }
+    if (out->flow) flow_csr.resize((size_t)m);
+  } catch (...) {
+    return -3;
+  }
+  int64_t* user_flow = out->flow;
+  out->flow = user_flow ? flow_csr.data() : nullptr;
+  const int rc = network_simplex(n_nodes, row_ptr.data(), col.data(), cst.data(), supply, pivot_cap, out);
+  out->flow = user_flow;
+  if (rc == 0 && user_flow)
+    for (int64_t q = 0; q < m; ++q) user_flow[perm[(size_t)q]] = flow_csr[(size_t)q];
+  return rc;
 }
 
 }  // namespace w1

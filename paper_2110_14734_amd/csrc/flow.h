@@ -6,15 +6,22 @@
 namespace w1 {
 
 struct FlowResult {
-  int64_t cost;
+  int64_t cost;     // flow cost, -1 when no feasible flow was reached
   int64_t pivots;
   int status;       // 0 optimal, 1 pivot cap reached
+  int feasible;     // 1 when the returned flow meets every supply
   int64_t* flow;    // optional, m entries
   int64_t* pot;     // optional, n entries
 };
 
+// Network in CSR form: the arcs of node v are row_ptr[v] .. row_ptr[v+1]-1,
+// with heads col[] and costs cost[]; m = row_ptr[n_nodes].
 // Returns 0, -1 (infeasible / invalid) or -3 (out of memory).
-int network_simplex(int64_t n_nodes, int64_t m, const uint32_t* src, const uint32_t* dst, const int32_t* cost,
+int network_simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int32_t* cost,
                     const int64_t* supply, int64_t pivot_cap, FlowResult* out);
+
+// The same for an arc list (src, dst, cost); flow entries follow the list.
+int network_simplex_arcs(int64_t n_nodes, int64_t m, const uint32_t* src, const uint32_t* dst, const int32_t* cost,
+                         const int64_t* supply, int64_t pivot_cap, FlowResult* out);
 
 }  // namespace w1

@@ -24,6 +24,7 @@
 #include "ctx.h"
 #include "flow.h"
 #include "kernels.h"
+#include "limits.h"
 
 namespace w1 {
 
@@ -424,6 +425,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     trace(c, "root items", f);
     for (int round = 0; f > 0; ++round) {
       if (round > 4 * 64 + 8) throw StageError{W1_EOVERFLOW};  // deeper than two 64-bit key trees
+      if (!worklist_round_fits(f)) throw StageError{W1_EOVERFLOW};
       uint64_t* cnt = need<uint64_t>(c, c.icnt, f);
       uint64_t* pos = need<uint64_t>(c, c.ipos, f);
       launch_wspd_classify(T, F, f, s, tun, (const int32_t*)c.pcap.p, cnt, st);
@@ -432,6 +434,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       launch_count_total64(cnt, pos, f, slot, st);
       const uint64_t tot = read_u64(c, slot);
       const int64_t kept = (int64_t)(uint32_t)tot, grown = (int64_t)(tot >> 32);
+      if (!worklist_items_fit(isz + kept)) throw StageError{W1_EOVERFLOW};
       I = grow_keep<int2>(c, c.itemsI, isz + kept, isz);
       int2* Nx = need<int2>(c, c.itemsB, std::max<int64_t>(grown, 1));
       F = (int2*)c.itemsA.p;
@@ -472,7 +475,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         nch += (hipp[(size_t)p] + tun.chunk_items - 1) / tun.chunk_items;
       }
       cst[(size_t)K] = (int32_t)nch;
-      if (nch >= (int64_t(1) << 31)) throw StageError{W1_EOVERFLOW};
+      if (!worklist_chunks_fit(nch)) throw StageError{W1_EOVERFLOW};
       upload(c, P.item_start, ist.data(), (size_t)K * 8);
       int32_t* cstd = need<int32_t>(c, c.cid, K + 1);
       upload(c, cstd, cst.data(), (size_t)(K + 1) * 4);
@@ -695,6 +698,26 @@ void free_network(w1_result& r) {
   r.diag_cost = nullptr;
 }
 
+// Flow outcome into the result.  An optimal flow gives the certified w1.  A
+// stalled solve (pivot cap) whose flow meets every supply still gives an
+// upper bound (any feasible flow costs at least the optimum), but not the
+// (1 + eps) guarantee; one that left supply on artificial arcs gives no
+// value at all (w1 = w1_paper = NaN, flow_cost = -1, flow_solved = 0).
+void finish_flow(w1_result& r, const FlowResult& fr) {
+  r.pivots = fr.pivots;
+  r.status = fr.status ? W1_STALLED : W1_OPTIMAL;
+  if (!fr.feasible) {
+    r.flow_cost = -1;
+    r.flow_solved = 0;
+    r.w1 = r.w1_paper = NAN;
+    return;
+  }
+  r.flow_cost = fr.cost;
+  r.flow_solved = 1;
+  r.w1 = std::ldexp((double)(fr.cost + r.n_points), r.grid_exp - 1);
+  r.w1_paper = std::ldexp((double)fr.cost, r.grid_exp - 1);
+}
+
 // Host flow of one pair from its host network copy.
 void solve_flow(w1_result& r, int64_t pivot_cap) {
   const int64_t nc = r.n_cells, np = r.n_pairs, nd = r.n_diag;
@@ -714,17 +737,12 @@ void solve_flow(w1_result& r, int64_t pivot_cap) {
     cost[(size_t)(2 * np + k)] = r.diag_cost[k];
   }
   FlowResult fr{};
-  const int rc = network_simplex(nc + 2, m, src.data(), dst.data(), cost.data(), r.supply, pivot_cap, &fr);
+  const int rc = network_simplex_arcs(nc + 2, m, src.data(), dst.data(), cost.data(), r.supply, pivot_cap, &fr);
   if (rc != 0) {
     r.status = rc == -3 ? W1_ENOMEM : W1_EINVAL;
     return;
   }
-  r.flow_cost = fr.cost;
-  r.pivots = fr.pivots;
-  r.status = fr.status ? W1_STALLED : W1_OPTIMAL;
-  r.flow_solved = 1;
-  r.w1 = std::ldexp((double)(fr.cost + r.n_points), r.grid_exp - 1);
-  r.w1_paper = std::ldexp((double)fr.cost, r.grid_exp - 1);
+  finish_flow(r, fr);
 }
 
 int entry(Ctx* c, const w1_pd* a, const w1_pd* b, int64_t K, const w1_params* params, void* stream, w1_result* out,
@@ -940,13 +958,13 @@ int w1_flow_solve(int64_t n_nodes, int64_t m, const uint32_t* src, const uint32_
   fr.pot = pot_out;
   int rc;
   try {
-    rc = network_simplex(n_nodes, m, src, dst, cost, supply, pivot_cap, &fr);
+    rc = network_simplex_arcs(n_nodes, m, src, dst, cost, supply, pivot_cap, &fr);
   } catch (const std::bad_alloc&) {
     return W1_ENOMEM;
   }
   if (rc == -3) return W1_ENOMEM;
   if (rc != 0) return W1_EINVAL;
-  *cost_out = fr.cost;
+  *cost_out = fr.cost;  // -1 after a stall that left supply unrouted
   if (pivots_out) *pivots_out = fr.pivots;
   if (status_out) *status_out = fr.status ? W1_STALLED : W1_OPTIMAL;
   return W1_OK;

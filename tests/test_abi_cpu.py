@@ -112,7 +112,11 @@ def test_network_simplex_pivot_cap_and_errors():
     c, piv, st = w1.flow_solve(3, src, dst, cost, sup)
     assert c == 6 and st == w1.W1_OPTIMAL
     c2, piv2, st2 = w1.flow_solve(3, src, dst, cost, sup, pivot_cap=1)
-    assert st2 == w1.W1_STALLED and piv2 == 1
+    # after one pivot the 3 units still sit on artificial arcs: no flow that
+    # meets the supplies has been reached, so no cost is reported
+    assert st2 == w1.W1_STALLED and piv2 == 1 and c2 == -1
+    c4, piv4, st4 = w1.flow_solve(3, src, dst, cost, sup, pivot_cap=2)
+    assert (c4, piv4, st4) == (6, 2, w1.W1_OPTIMAL)
     with pytest.raises(w1.W1Error):
         w1.flow_solve(3, src, dst, cost, np.array([3, 0, -2], np.int64))  # unbalanced
     with pytest.raises(w1.W1Error):
@@ -124,6 +128,37 @@ def test_network_simplex_pivot_cap_and_errors():
     # no arcs: only an all-zero supply is feasible
     c3, piv3, st3 = w1.flow_solve(2, src[:0], dst[:0], cost[:0], np.zeros(2, np.int64))
     assert c3 == 0 and piv3 == 0 and st3 == w1.W1_OPTIMAL
+
+
+def test_network_simplex_stalled_flows():
+    """A solve stopped by the pivot cap reports a cost only for a flow that
+    meets every supply; that flow is then a certified upper bound."""
+    rng = np.random.default_rng(5)
+    feasible_stalls = 0
+    for trial in range(12):
+        n = 40
+        src = rng.integers(0, n, 300)
+        dst = rng.integers(0, n, 300)
+        keep = src != dst
+        src = np.concatenate([src[keep], np.arange(n)]).astype(np.uint32)
+        dst = np.concatenate([dst[keep], (np.arange(n) + 1) % n]).astype(np.uint32)
+        cost = rng.integers(0, 50, src.shape[0]).astype(np.int32)
+        supply = rng.integers(-5, 6, n)
+        supply[-1] -= supply.sum()
+        opt, piv, st = w1.flow_solve(n, src, dst, cost, supply)
+        assert st == w1.W1_OPTIMAL
+        for cap in range(1, piv):
+            c, p, s, flow, pot = w1.flow_solve(n, src, dst, cost, supply, pivot_cap=cap, certificate=True)
+            assert s == w1.W1_STALLED and p == cap
+            if c == -1:
+                continue
+            feasible_stalls += 1
+            bal = np.zeros(n, np.int64)
+            np.add.at(bal, src.astype(np.int64), flow)
+            np.add.at(bal, dst.astype(np.int64), -flow)
+            assert np.array_equal(bal, supply) and (flow >= 0).all()
+            assert c == int((cost.astype(np.int64) * flow).sum()) and c >= opt
+    assert feasible_stalls > 0
 
 
 def test_learned_form_entry_points_reject_bad_arguments():
