@@ -6,6 +6,8 @@ or calls it, and it shares no code with the GPU library.
 
 Contents
 * ``run``            the plain pipeline (oracle.cpp) through ctypes.
+* ``network``, ``csr`` its sparse transshipment network as an arc list, and
+                     as (tail, head)-sorted compressed sparse rows.
 * ``mcf``            exact min-cost flow (successive shortest paths).
 * ``exact_w1``       exact W1 by Hungarian matching on the diagonal-augmented
                      bipartite graph Bi(A, B) (Sec. 4.3), L-infinity metric.
@@ -71,6 +73,8 @@ def lib():
         L.orc_pairs.argtypes = [vp] * 6
         L.orc_network.argtypes = [vp] * 5
         L.orc_network.restype = i64
+        L.orc_csr.argtypes = [vp] * 4
+        L.orc_csr.restype = i64
         L.orc_mcf.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp]
         L.orc_mcf.restype = i64
         L.orc_choose_s.argtypes = [f64, f64]
@@ -190,6 +194,33 @@ def network(A, B, eps=0.1, kappa=0.1, s_override=0):
         sup = np.zeros(N + 2, np.int64)
         L_.orc_network(h, _ptr(src), _ptr(dst), _ptr(cost), _ptr(sup))
         return src, dst, cost, sup
+    finally:
+        L_.orc_free(h)
+
+
+def csr(A, B, eps=0.1, kappa=0.1, s_override=0):
+    """The oracle's network in compressed sparse row form (O8): arcs sorted by
+    (tail, head).  Returns dict(row_ptr, col, cost, supply, n_cells)."""
+    L_ = lib()
+    A64, B64 = _as_f64(A), _as_f64(B)
+    h = L_.orc_new()
+    try:
+        st = L_.orc_run(h, _ptr(A64), A64.shape[0], _ptr(B64), B64.shape[0], float(eps), float(kappa),
+                        int(s_override), ORC_NO_FLOW, 0.0)
+        if st != 0:
+            raise RuntimeError(f"oracle status {st}")
+        N = int(L_.orc_i64(h, _K["NCELLS"]))
+        if int(L_.orc_i64(h, _K["N"])) == 0:
+            z = np.zeros(0, np.int64)
+            return dict(row_ptr=np.zeros(3, np.int64), col=z, cost=z, supply=np.zeros(2, np.int64), n_cells=0)
+        m = int(L_.orc_csr(h, None, None, None))
+        rp = np.zeros(N + 3, np.int64)
+        col, cost = np.zeros(m, np.int64), np.zeros(m, np.int64)
+        L_.orc_csr(h, _ptr(rp), _ptr(col), _ptr(cost))
+        sup = np.zeros(N + 2, np.int64)
+        src_, dst_, c_ = (np.zeros(m, np.int64) for _ in range(3))
+        L_.orc_network(h, _ptr(src_), _ptr(dst_), _ptr(c_), _ptr(sup))
+        return dict(row_ptr=rp, col=col, cost=cost, supply=sup, n_cells=N)
     finally:
         L_.orc_free(h)
 

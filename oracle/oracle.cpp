@@ -26,7 +26,10 @@
 //   O6  binary radix (compressed quad) tree with tight boxes (Sec. 5.3,
 //       split-tree paragraph)
 //   O7  s-WSPD by the descendant-pair recursion            (Alg. 5 / Alg. 6)
-//   O8  biarcs + diagonal arcs + supplies                   (Sec. 5.3, Alg. 7)
+//   O8  biarcs + diagonal arcs + supplies, and the network in
+//       (tail, head)-sorted compressed sparse row form     (Sec. 5.3, Alg. 7,
+//                                                           Appendix, network
+//                                                           representation)
 //   O9  exact min-cost flow (successive shortest paths)     (Def. transshipment)
 //   O10 W1 = (g/2)(F* + n), W1_paper = (g/2) F*
 #include <algorithm>
@@ -553,6 +556,27 @@ void network(const Oracle& o, std::vector<Arc>* arcs, std::vector<int64_t>* supp
   (*supply)[(size_t)(N + 1)] = o.nB;
 }
 
+// Compressed sparse row form of the same network (O8, Appendix
+// "Representing the Transshipment Network"): the arcs sorted by tail, ties by
+// head, so the arcs of node v are row_ptr[v] .. row_ptr[v+1]-1.  A plain
+// std::sort of the arc list, then the row pointers from the tails.  The arc
+// pairs are distinct (a repeated (tail, head) would mean a cell pair covered
+// by two WSPD pairs), so the sorted order is unique.  Pins: sortedness and
+// distinct arcs, the arc-count identity, costs recomputed from the cells,
+// equality with the unsorted arc list as a multiset.
+void csr(const Oracle& o, std::vector<int64_t>* row_ptr, std::vector<Arc>* arcs) {
+  std::vector<int64_t> supply;
+  network(o, arcs, &supply);
+  std::sort(arcs->begin(), arcs->end(), [](const Arc& x, const Arc& y) {
+    if (x.u != y.u) return x.u < y.u;
+    return x.v < y.v;
+  });
+  const int64_t nn = (int64_t)o.cells.size() + 2;
+  row_ptr->assign((size_t)(nn + 1), 0);
+  for (const Arc& a : *arcs) ++(*row_ptr)[(size_t)(a.u + 1)];
+  for (int64_t v = 0; v < nn; ++v) (*row_ptr)[(size_t)(v + 1)] += (*row_ptr)[(size_t)v];
+}
+
 }  // namespace
 
 // ===================================================================== ABI ==
@@ -713,6 +737,23 @@ int64_t orc_network(void* p, int64_t* src, int64_t* dst, int64_t* cost, int64_t*
       cost[k] = arcs[k].c;
     }
     for (size_t k = 0; k < sup.size(); ++k) supply[k] = sup[k];
+  }
+  return (int64_t)arcs.size();
+}
+
+// Network in CSR form (n_cells + 3 row pointers, arcs sorted by (tail,
+// head)): returns the arc count when called with null buffers.
+int64_t orc_csr(void* p, int64_t* row_ptr, int64_t* col, int64_t* cost) {
+  Oracle& o = *(Oracle*)p;
+  std::vector<int64_t> rp;
+  std::vector<Arc> arcs;
+  csr(o, &rp, &arcs);
+  if (row_ptr) {
+    for (size_t k = 0; k < rp.size(); ++k) row_ptr[k] = rp[k];
+    for (size_t k = 0; k < arcs.size(); ++k) {
+      col[k] = arcs[k].v;
+      cost[k] = arcs[k].c;
+    }
   }
   return (int64_t)arcs.size();
 }

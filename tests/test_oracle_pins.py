@@ -187,6 +187,43 @@ def test_rwmd_lower_bound_and_net(orc):
     assert r1.L == r2.L and r1.n == r2.n
 
 
+def _brute_nn_t(b, d, w):
+    """RWMD per-location cost by exhaustive search: the cheapest arc out of
+    each location is to the nearest location of the other diagram (all of
+    them, O(n^2)) or to the diagonal, (d - b)/2 (Alg. 1 with the diagonal
+    arc of the text)."""
+    t = 0.5 * (d - b)
+    for side in (w > 0, w < 0):
+        other = ~side & (w != 0)
+        if not other.any():
+            continue
+        D = np.maximum(np.abs(b[side, None] - b[None, other]), np.abs(d[side, None] - d[None, other]))
+        t[side] = np.minimum(D.min(axis=1), t[side])
+    return t
+
+
+@pytest.mark.parametrize("case", ["mixture", "integer_ties", "dense_cluster"])
+def test_rwmd_nearest_neighbour_bruteforce(orc, case):
+    # The oracle's nearest-neighbour search is a pruned sweep in birth order;
+    # an exhaustive O(n^2) scan must give bit-identical costs: every entry is
+    # the same IEEE max/abs/halving of the same FP64 inputs.
+    if case == "mixture":
+        A, B = pdsynth.mixture_pd(2500, 31), pdsynth.mixture_pd(2200, 32)
+    elif case == "integer_ties":  # many equidistant candidates and diagonal ties
+        A, B = pdsynth.integer_pd(1800, 33, hi=60), pdsynth.integer_pd(1700, 34, hi=60)
+    else:  # thousands of points in a tiny box next to a sparse background
+        rng = np.random.default_rng(35)
+        cl = lambda n: np.stack([0.5 + 1e-6 * rng.random(n), 0.7 + 1e-6 * rng.random(n)], axis=1)
+        A = np.concatenate([cl(1500), pdsynth.exp_pd(300, 36)])
+        B = np.concatenate([cl(1400), pdsynth.exp_pd(250, 37)])
+    r = orc.run(A, B, eps=0.1, flags=orc.ORC_STOP_AFTER_TREE)
+    b, d, w = r.locs["b"], r.locs["d"], r.locs["w"]
+    assert (w > 0).sum() > 100 and (w < 0).sum() > 100
+    t = _brute_nn_t(b, d, w)
+    assert np.array_equal(r.locs["t"], t)
+    assert np.array_equal(r.locs["term"], np.abs(w) * t)
+
+
 # ------------------------------------------------------------------ params --
 def test_params_golden(orc):
     g = gold("params.json")
@@ -270,6 +307,73 @@ def test_wspd_bruteforce_coverage(orc, s_override):
         r = orc.run(A, B, eps=0.2, s_override=s_override, flags=orc.ORC_KEEP_PAIR_NODES | orc.ORC_NO_FLOW)
         assert r.cells["i"].shape[0] >= 30
         orc.wspd_coverage(r)
+
+
+def _check_csr(orc, r, net):
+    """Checks of the network in compressed sparse row form against the cells
+    and the WSPD pairs of the same run (Sec. 5.3 network, Alg. 7 diagonal
+    arcs, Appendix network representation)."""
+    N = r.cells["i"].shape[0]
+    rp, col, cost = net["row_ptr"], net["col"], net["cost"]
+    ci, cj, cA, cB = r.cells["i"], r.cells["j"], r.cells["cA"], r.cells["cB"]
+    assert net["n_cells"] == N and rp.shape == (N + 3,)
+    assert rp[0] == 0 and (np.diff(rp) >= 0).all() and rp[-1] == col.size == cost.size
+    tail = np.repeat(np.arange(N + 2), np.diff(rp))
+    # sorted by (tail, head) with no repeated arc
+    key = tail * (N + 2) + col
+    assert (np.diff(key) > 0).all()
+    # arc-count identity: both directions of each pair, one diagonal arc per
+    # A cell and per B cell, and the B-diagonal -> A-diagonal arc
+    assert col.size == 2 * r.n_pairs + (cA > 0).sum() + (cB > 0).sum() + 1
+    # cell-cell arcs are exactly the two orientations of the WSPD pairs, with
+    # cost 2 max(|di|, |dj|) in units of g/2 recomputed from the cells
+    cc = (tail < N) & (col < N)
+    pairs = set(zip(r.pairs["u"].tolist(), r.pairs["v"].tolist()))
+    assert set(zip(tail[cc].tolist(), col[cc].tolist())) == pairs | {(v, u) for u, v in pairs}
+    assert cc.sum() == 2 * len(pairs)
+    t, h = tail[cc], col[cc]
+    assert (cost[cc] == 2 * np.maximum(np.abs(ci[t] - ci[h]), np.abs(cj[t] - cj[h]))).all()
+    # diagonal arcs by membership; cost = distance to the diagonal, j - i
+    toA = (tail < N) & (col == N)
+    assert np.array_equal(tail[toA], np.flatnonzero(cA > 0))
+    assert (cost[toA] == cj[tail[toA]] - ci[tail[toA]]).all()
+    assert rp[N + 1] == rp[N]  # the A-diagonal node sends nothing
+    bb = col[rp[N + 1]:rp[N + 2]]
+    assert np.array_equal(bb, np.append(np.flatnonzero(cB > 0), N))
+    assert (cost[rp[N + 1]:rp[N + 2] - 1] == cj[bb[:-1]] - ci[bb[:-1]]).all() and cost[rp[N + 2] - 1] == 0
+    assert np.array_equal(net["supply"], np.concatenate([cA - cB, [-r.nA, r.nB]]))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_csr_network(orc, seed):
+    # small: the pairs themselves are pinned by brute-force coverage
+    A = pdsynth.exp_pd(24, 500 + seed, mean_pers=0.3)
+    B = pdsynth.exp_pd(22, 600 + seed, mean_pers=0.3)
+    r = orc.run(A, B, eps=0.2, flags=orc.ORC_KEEP_PAIR_NODES | orc.ORC_NO_FLOW)
+    orc.wspd_coverage(r)
+    _check_csr(orc, r, orc.csr(A, B, eps=0.2))
+    # medium, FP32 mixture with overlapping A/B cells
+    A, B = pdsynth.mixture_pd(900, 700 + seed), pdsynth.mixture_pd(800, 710 + seed)
+    r = orc.run(A, B, eps=0.1, flags=orc.ORC_NO_FLOW)
+    _check_csr(orc, r, orc.csr(A, B, eps=0.1))
+    # the sorted network has the optimum of the arc list it sorts
+    A, B = pdsynth.exp_pd(150, 720 + seed), pdsynth.exp_pd(140, 730 + seed)
+    net = orc.csr(A, B, eps=0.1)
+    rp = net["row_ptr"]
+    tail = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    full = orc.run(A, B, eps=0.1)
+    assert orc.mcf(rp.size - 1, tail, net["col"], net["cost"], net["supply"]) == full.flow
+
+
+def test_csr_network_edges(orc):
+    # identical diagrams: nothing to ship
+    A = pdsynth.exp_pd(30, 1)
+    net = orc.csr(A, A.copy(), eps=0.1)
+    assert net["n_cells"] == 0 and net["col"].size == 0 and list(net["row_ptr"]) == [0, 0, 0]
+    # one point against nothing: one cell, its A-diagonal arc and B->A
+    net = orc.csr(np.array([[0.25, 1.75]]), np.zeros((0, 2)), eps=0.1)
+    assert list(net["row_ptr"]) == [0, 1, 1, 2]
+    assert list(net["col"]) == [1, 1] and net["cost"][1] == 0
 
 
 @pytest.mark.parametrize("s_override", [1, 2, 3])
