@@ -27,28 +27,38 @@ if ROOT not in sys.path:
 
 METRIC = "PD pairs/sec (approx W1 at eps) + sparsify pts/s & HBM GB/s frac; 1-NN q/s"
 HBM_PEAK_GBS = 8000.0
-PAIR_BYTES = 12  # one WSPD pair in the network: u32 u, u32 v, i32 cost
+# Algorithmic HBM bytes of the WSPD and network kernels, per WSPD pair (both
+# arcs of a pair) and per cell:
+#   emit          writes the 12-byte pair record (u32 u, u32 v, i32 cost);
+#   bucket_hist   reads the record;
+#   bucket_scatter reads the record, writes two 4-byte bucket entries;
+#   row_hist      reads the two entries;
+#   row_scatter   reads the two entries, writes two 4-byte row heads;
+#   row_sort      reads the two heads, writes two (u32 head, i32 cost) arcs
+#                 of the final rows and an int64 row pointer per cell.
+# The final network alone is 16 B per pair and 8 B per cell.
+KERNEL_BYTES = {"emit_ms": (12, 0), "bucket_hist_ms": (12, 0), "bucket_scatter_ms": (20, 0),
+                "row_hist_ms": (8, 0), "row_scatter_ms": (16, 0), "row_sort_ms": (24, 8)}
+NETWORK_BYTES = (16, 8)
+KERNEL_NAMES = {"emit_ms": "k_wspd<emit> (WSPD pair records)", "bucket_hist_ms": "k_bucket_hist",
+                "bucket_scatter_ms": "k_bucket_scatter", "row_hist_ms": "k_row_hist",
+                "row_scatter_ms": "k_row_scatter", "row_sort_ms": "k_row_sort (sorted rows, costs)"}
 
-# HBM bytes per launch of the emit pass on this workload, from the FETCH_SIZE
-# and WRITE_SIZE counter runs in profiles/wspd_c2_200k_eps0.1_hbm_counters.md
-# (each scaled by the 1 GiB copy calibration).  Valid only for the kernel
-# source they were measured on: reported only while its hash prefix matches.
-# The counters were taken at prefix fdf1f05a928203e3; the file has changed
-# since only in k_classify (per-pair work caps), which keeps the tuned cap of
-# 1024 for this pair of 400k cells, so the emit pass and its work list are
-# the ones measured.
-EMIT_TRAFFIC_BYTES = 26.38e9
-EMIT_TRAFFIC_SRC = ("paper_2110_14734_amd/csrc/wspd.hip", "9cd2cb9dca394ff3")
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE and WRITE_SIZE
+# counter runs on the benchmark workload (each scaled by a copy-kernel
+# calibration), valid only for the kernel source they were measured on:
+# {kernel key: (source file, sha256 prefix of that file, bytes per launch)}.
+MEASURED_TRAFFIC = {}
 
 
-def measured_traffic(n_points, eps):
+def measured_traffic(key, n_points, eps):
     import hashlib
 
-    path, prefix = EMIT_TRAFFIC_SRC
+    if key not in MEASURED_TRAFFIC or n_points != 400_000 or eps != 0.1:
+        return None
+    path, prefix, nbytes = MEASURED_TRAFFIC[key]
     h = hashlib.sha256(open(os.path.join(ROOT, path), "rb").read()).hexdigest()
-    if h.startswith(prefix) and n_points == 400_000 and eps == 0.1:
-        return EMIT_TRAFFIC_BYTES
-    return None
+    return nbytes if h.startswith(prefix) else None
 
 
 def parse():
@@ -272,22 +282,56 @@ def run_nn(ctx, args):
     return out
 
 
+def _cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(A, B, eps):
-    """The CPU oracle as it stands, single thread: the same workload through
-    0-condensation, RWMD, grid, tree and the WSPD recursion, with WSPD pairs
-    counted rather than stored (the full pair list does not fit in host RAM
-    as the oracle stores it)."""
+    """The CPU oracle as it stands, single thread, on the same workload:
+    0-condensation, RWMD, grid, tree and the WSPD recursion with pairs
+    counted rather than stored (the oracle would need ~44 GB for the pair
+    list), each stage timed on its own (the oracle's own stage split: O1 with
+    O0, O2 RWMD, O3-O6 grid and tree, O7 WSPD).  The flow O9 is timed
+    separately on the 400 + 400-point workload.  The oracle's network O8 is
+    not timed here."""
     import oracle
+    import pdsynth
 
     oracle.build()
     t0 = time.perf_counter()
     r = oracle.run(A, B, eps=eps, flags=oracle.ORC_COUNT_ONLY, fetch=False)
     dt = time.perf_counter() - t0
+    # the stages up to the tree alone, then the RWMD alone given L
+    t1 = time.perf_counter()
+    oracle.run(A, B, eps=eps, flags=oracle.ORC_STOP_AFTER_TREE, fetch=False)
+    t_tree = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    oracle.run(A, B, eps=eps, flags=oracle.ORC_STOP_AFTER_TREE | oracle.ORC_SKIP_RWMD, given_L=r.L, fetch=False)
+    t_norwmd = time.perf_counter() - t1
+    C1a, C1b = pdsynth.exp_pd(400, 0), pdsynth.exp_pd(400, 1)
+    t1 = time.perf_counter()
+    oracle.run(C1a, C1b, eps=0.1, flags=oracle.ORC_NO_FLOW, fetch=False)
+    t_c1_nf = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    oracle.run(C1a, C1b, eps=0.1, fetch=False)
+    t_c1 = time.perf_counter() - t1
     n = A.shape[0] + B.shape[0]
     return {"value": n / dt, "unit": "pts/s", "cores": 1, "kind": "oracle",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
             "sample": f"the full {A.shape[0]}+{B.shape[0]}-point pair at eps={eps}, single thread, "
-                      f"stages a0-a4 with WSPD pairs counted not stored ({r.n_pairs} pairs), {dt:.1f} s",
-            "seconds": dt, "pairs": r.n_pairs}
+                      f"stages O0-O7 with WSPD pairs counted not stored ({r.n_pairs} pairs), {dt:.1f} s",
+            "seconds": dt, "pairs": r.n_pairs,
+            "stage_s": {"O0-O2 condense + RWMD": round(t_tree - t_norwmd, 3),
+                        "O3-O6 grid + tree": round(t_norwmd, 3),
+                        "O7 WSPD (count)": round(dt - t_tree, 3)},
+            "c1_flow_s": {"what": "400+400-point pair at eps 0.1: O9 successive-shortest-path flow alone",
+                          "seconds": round(t_c1 - t_c1_nf, 3)}}
 
 
 def main():
@@ -313,14 +357,13 @@ def main():
     for _ in range(args.warmup):
         ctx.approx(tA, tB, eps=args.eps, flags=flags)
     torch.cuda.synchronize()
-    emit_ms, stage = [], {k: 0.0 for k in w1.T_NAMES[:6]}
-    kern = {"worklist_ms": 0.0, "count_ms": 0.0, "emit_ms": 0.0}
+    stage = {k: 0.0 for k in w1.T_NAMES[:6]}
+    kern = {k: 0.0 for k in w1.Context.KERNEL_TIMES if k != "pairs"}
     r = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
         r = ctx.approx(tA, tB, eps=args.eps, flags=flags)
         kt = ctx.kernel_times()
-        emit_ms.append(kt["emit_ms"])
         for k in kern:
             kern[k] += kt[k] / args.steps
         for k in stage:
@@ -329,8 +372,18 @@ def main():
     dt = time.perf_counter() - t0
     ms_step = 1e3 * dt / args.steps
     n = A.shape[0] + B.shape[0]
-    emit_avg = sum(emit_ms) / len(emit_ms)
-    achieved = PAIR_BYTES * r.n_pairs / (emit_avg * 1e-3) / 1e9
+    P, N = r.n_pairs, r.n_cells
+    kernels = {}
+    for k, (bp, bn) in KERNEL_BYTES.items():
+        nbytes = bp * P + bn * N
+        ach = nbytes / (kern[k] * 1e-3) / 1e9 if kern[k] > 0 else 0.0
+        kernels[k] = {"kernel": KERNEL_NAMES[k], "avg_launch_ms": round(kern[k], 4), "algorithmic_bytes": nbytes,
+                      "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)}
+    dom = max(KERNEL_BYTES, key=lambda k: kern[k])
+    traffic = measured_traffic(dom, n, args.eps)
+    d = kernels[dom]
+    net_bytes = NETWORK_BYTES[0] * P + NETWORK_BYTES[1] * N
+    a45_ms = stage["wspd"] + stage["arcs"]
     out = {
         "metric": METRIC,
         "value": n / (dt / args.steps),
@@ -347,26 +400,32 @@ def main():
         "config": {
             "workload": f"plain method at scale: two {args.n}-point FP32 persistence diagrams "
                         f"(80% persistence LogNormal(-4,1), 20% U[0.1,1], birth U[0,1)), eps={args.eps}, "
-                        f"GPU sparsification a0-a5 (host flow excluded)",
-            "n_points": n, "eps": args.eps, "s": r.s, "grid_exp": r.grid_exp, "cells": r.n_cells,
-            "wspd_pairs": r.n_pairs, "arcs": r.n_arcs,
+                        f"GPU sparsification a0-a5 incl. the (tail, head)-sorted CSR network (host flow excluded)",
+            "n_points": n, "eps": args.eps, "s": r.s, "grid_exp": r.grid_exp, "cells": N,
+            "wspd_pairs": P, "network_arcs": r.n_arcs,
         },
         "pd_pairs_per_s": args.steps / dt,
-        "wspd_pairs_per_s": r.n_pairs / (dt / args.steps),
+        "wspd_pairs_per_s": P / (dt / args.steps),
         "stage_ms": {k: round(v, 3) for k, v in stage.items()},
         "wspd_kernel_ms": {k: round(v, 3) for k, v in kern.items()},
         "roofline": {
-            "kernel": "k_wspd<emit> (WSPD pair emission)",
+            "kernel": d["kernel"],
             "bound": "hbm",
-            "achieved": achieved,
+            "achieved": d["achieved_GBs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(n, args.eps),
-            "traffic_ratio": (measured_traffic(n, args.eps) / (PAIR_BYTES * r.n_pairs)
-                              if measured_traffic(n, args.eps) else None),
-            "algorithmic_bytes_per_launch": PAIR_BYTES * r.n_pairs,
-            "avg_launch_ms": emit_avg,
+            "frac": d["frac"],
+            "traffic": traffic,
+            "traffic_ratio": (traffic / d["algorithmic_bytes"]) if traffic else None,
+            "algorithmic_bytes_per_launch": d["algorithmic_bytes"],
+            "avg_launch_ms": d["avg_launch_ms"],
+        },
+        "kernels": kernels,
+        "network_roofline": {
+            "what": "a4+a5 stage time against the final network's bytes (16 B per WSPD pair, 8 B per cell)",
+            "bytes": net_bytes, "ms": round(a45_ms, 3),
+            "achieved_GBs": round(net_bytes / (a45_ms * 1e-3) / 1e9, 1),
+            "frac": round(net_bytes / (a45_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         },
     }
     if args.calib_copy_mb:

@@ -13,7 +13,8 @@
  *       WSPD, Sec. 5.3 split-tree paragraph),
  *   a4  s-WSPD pairs (Alg. 4-6),
  *   a5  the sparse transshipment network: biarcs, diagonal arcs (Alg. 7) and
- *       supplies,
+ *       supplies, as compressed sparse rows with the arcs sorted by tail,
+ *       then head (Appendix, representation of the transshipment network),
  * and then solves the uncapacitated min-cost flow of that network on the host
  * with an integer network simplex (Sec. 5.4), timed separately.
  *
@@ -48,8 +49,11 @@ extern "C" {
 /* ---- return codes ------------------------------------------------------ */
 #define W1_OK 0
 #define W1_EINVAL (-1)    /* bad argument or invalid diagram point          */
-#define W1_ERANGE (-2)    /* grid extent >= 2^30 cells, or coordinates too   */
-                          /* large for exact integer snapping                */
+#define W1_ERANGE (-2)    /* grid extent >= 2^30 cells, coordinates too      */
+                          /* large for exact integer snapping, or a network  */
+                          /* too large for its row form: more than 2^22      */
+                          /* cells in one launch group, or bucket and head   */
+                          /* bits above 32 (above 2^21 cells in one pair)    */
 #define W1_ENOMEM (-3)    /* device or host allocation failed                */
 #define W1_EHIP (-4)      /* HIP runtime error (see w1_ctx_hip_error)        */
 #define W1_EOVERFLOW (-5) /* internal work list capacity exceeded            */
@@ -122,25 +126,31 @@ typedef struct {
   int64_t n_locations;/* distinct (birth, death) locations with net mass != 0    */
   int64_t n_cells;    /* grid cells = network nodes other than the two diagonal nodes */
   int64_t n_pairs;    /* WSPD pairs = biarcs                                    */
-  int64_t n_arcs;     /* directed arcs: 2 n_pairs + diagonal arcs (incl. b->a)  */
+  int64_t n_arcs;     /* directed arcs: 2 n_pairs + n_diag (0 with COUNT_ONLY) */
   int64_t flow_cost;  /* F* in units of g/2 (-1 if not solved)                 */
   int64_t pivots;     /* network simplex pivots                                 */
 
-  /* Network (W1_KEEP_NETWORK).  Node ids: cells 0..n_cells-1 in Morton order
-   * of (cell_i, cell_j), the diagonal node of A is n_cells, the diagonal node
-   * of B is n_cells+1.  Pair k is the two arcs pair_u->pair_v and
-   * pair_v->pair_u, both with cost pair_cost (= 2 max(|di|, |dj|)).  Diagonal
-   * arcs: cell->A-diagonal for cells with A mass, B-diagonal->cell for cells
-   * with B mass (cost cell_j - cell_i), and B-diagonal->A-diagonal (cost 0).
-   * supply[v] = out-flow minus in-flow at v. */
+  /* Network (W1_KEEP_NETWORK), built on the device in compressed sparse row
+   * form.  Node ids: cells 0..n_cells-1 in Morton order of (cell_i, cell_j),
+   * the diagonal node of A is n_cells, the diagonal node of B is n_cells+1.
+   * The arcs of node v are row_ptr[v] .. row_ptr[v+1]-1 (row_ptr has
+   * n_cells + 3 entries, row_ptr[0] = 0, row_ptr[n_cells + 2] = n_arcs),
+   * with heads col[] in strictly increasing order and costs cost[] in units
+   * of g/2:
+   *   cell -> cell: both orientations of every WSPD pair, cost
+   *                 2 max(|di|, |dj|) of the two cells;
+   *   cell -> A-diagonal: for cells with A mass, cost cell_j - cell_i;
+   *   B-diagonal -> cell: for cells with B mass, cost cell_j - cell_i;
+   *   B-diagonal -> A-diagonal: cost 0 (the A-diagonal row is empty).
+   * supply[v] = out-flow minus in-flow at v: cell_ca - cell_cb for a cell,
+   * -n_a for the A-diagonal node, n_b for the B-diagonal node. */
   int32_t *cell_i, *cell_j;   /* n_cells, shifted grid coordinates */
   int32_t *cell_ca, *cell_cb; /* n_cells, multiplicities from A and from B */
   int64_t *supply;            /* n_cells + 2 */
-  uint32_t *pair_u, *pair_v;  /* n_pairs */
-  int32_t *pair_cost;         /* n_pairs */
-  uint32_t *diag_src, *diag_dst;
-  int32_t *diag_cost;
-  int64_t n_diag;
+  int64_t *row_ptr;           /* n_cells + 3 */
+  uint32_t *col;              /* n_arcs: head of each arc */
+  int32_t *cost;              /* n_arcs */
+  int64_t n_diag;             /* arcs at a diagonal node: #A cells + #B cells + 1 */
 
   /* Stage intermediates (W1_KEEP_STAGES). */
   double *loc_b, *loc_d; /* n_locations, sorted by (birth, death) */
@@ -156,15 +166,18 @@ typedef struct {
 } w1_result;
 
 /* Device-resident network of the last w1_approx on a context (batch entry
- * k of the last call).  Pointers stay valid until the next call on ctx. */
+ * k of the last call), in the layout of the w1_result network above: the
+ * rows of pair k with row_ptr local to it (row_ptr[0] = 0), col / cost
+ * pointing at its first arc.  Pointers stay valid until the next call on
+ * ctx. */
 typedef struct {
-  int64_t n_cells, n_pairs, n_diag;
+  int64_t n_cells, n_pairs, n_arcs;
   const int32_t *cell_ij; /* 2 per cell: i, j */
   const int32_t *cell_ca, *cell_cb;
-  const int64_t *supply;
-  const uint32_t *pairs; /* 3 per pair: u, v, cost (12-byte records) */
-  const uint32_t *diag_src, *diag_dst;
-  const int32_t *diag_cost;
+  const int64_t *supply;  /* n_cells + 2 */
+  const int64_t *row_ptr; /* n_cells + 3 */
+  const uint32_t *col;    /* n_arcs */
+  const int32_t *cost;    /* n_arcs */
 } w1_device_network;
 
 /* Create a context on HIP device `device` (must be gfx950). */
@@ -228,9 +241,12 @@ int w1_ctx_get_tuning(const w1_ctx *ctx, w1_tuning *out);
 int w1_ctx_set_tuning(w1_ctx *ctx, const w1_tuning *t);
 
 /* Device times (ms, HIP events on the call's stream) of the last call's
- * WSPD kernels: [0] work-list build (expansion rounds, item sort, chunking),
- * [1] count pass, [2] emit pass, and the
- * number of pairs emitted [3].  n is the capacity of ms (>= 4). */
+ * WSPD and network kernels: [0] work-list build (expansion rounds, item
+ * sort, chunking), [1] count pass, [2] emit pass, [3] the number of pairs
+ * emitted; then the passes that sort the network into rows: [4] bucket
+ * histogram, [5] bucket scatter, [6] row histogram, [7] row scatter (with
+ * the degree scan before it), [8] row sort (with the diagonal rows and
+ * row pointers).  n is the capacity of ms (>= 4); entries beyond 8 are 0. */
 int w1_ctx_last_kernel_times(const w1_ctx *ctx, double *ms, int n);
 
 /* Host network simplex on any uncapacitated network with non-negative integer

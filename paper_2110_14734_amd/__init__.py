@@ -53,8 +53,7 @@ class _Result(ctypes.Structure):
         ("n_cells", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_arcs", ctypes.c_int64),
         ("flow_cost", ctypes.c_int64), ("pivots", ctypes.c_int64),
         ("cell_i", _P), ("cell_j", _P), ("cell_ca", _P), ("cell_cb", _P), ("supply", _P),
-        ("pair_u", _P), ("pair_v", _P), ("pair_cost", _P), ("diag_src", _P), ("diag_dst", _P),
-        ("diag_cost", _P), ("n_diag", ctypes.c_int64),
+        ("row_ptr", _P), ("col", _P), ("cost", _P), ("n_diag", ctypes.c_int64),
         ("loc_b", _P), ("loc_d", _P), ("loc_w", _P), ("loc_t", _P),
         ("rwmd_sum_a", ctypes.c_int64), ("rwmd_sum_b", ctypes.c_int64),
         ("rwmd_shift_a", ctypes.c_int32), ("rwmd_shift_b", ctypes.c_int32),
@@ -64,9 +63,9 @@ class _Result(ctypes.Structure):
 
 
 class _DevNet(ctypes.Structure):
-    _fields_ = [("n_cells", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_diag", ctypes.c_int64),
-                ("cell_ij", _P), ("cell_ca", _P), ("cell_cb", _P), ("supply", _P), ("pairs", _P),
-                ("diag_src", _P), ("diag_dst", _P), ("diag_cost", _P)]
+    _fields_ = [("n_cells", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_arcs", ctypes.c_int64),
+                ("cell_ij", _P), ("cell_ca", _P), ("cell_cb", _P), ("supply", _P), ("row_ptr", _P),
+                ("col", _P), ("cost", _P)]
 
 
 class _TrainParams(ctypes.Structure):
@@ -230,15 +229,13 @@ def _convert(r: _Result) -> Result:
         grid_exp=r.grid_exp, s=r.s, flow_solved=bool(r.flow_solved), n_points=r.n_points, n_a=r.n_a,
         n_b=r.n_b, n_locations=r.n_locations, n_cells=r.n_cells, n_pairs=r.n_pairs, n_arcs=r.n_arcs,
         flow_cost=r.flow_cost, pivots=r.pivots, t_ms={k: r.t_ms[i] for i, k in enumerate(T_NAMES)})
-    if r.pair_u or r.cell_i:
+    if r.row_ptr:
         nc = r.n_cells
         out.network = dict(
             cell_i=_arr(r.cell_i, nc, np.int32), cell_j=_arr(r.cell_j, nc, np.int32),
             cell_ca=_arr(r.cell_ca, nc, np.int32), cell_cb=_arr(r.cell_cb, nc, np.int32),
-            supply=_arr(r.supply, nc + 2, np.int64), pair_u=_arr(r.pair_u, r.n_pairs, np.uint32),
-            pair_v=_arr(r.pair_v, r.n_pairs, np.uint32), pair_cost=_arr(r.pair_cost, r.n_pairs, np.int32),
-            diag_src=_arr(r.diag_src, r.n_diag, np.uint32), diag_dst=_arr(r.diag_dst, r.n_diag, np.uint32),
-            diag_cost=_arr(r.diag_cost, r.n_diag, np.int32))
+            supply=_arr(r.supply, nc + 2, np.int64), row_ptr=_arr(r.row_ptr, nc + 3, np.int64),
+            col=_arr(r.col, r.n_arcs, np.uint32), cost=_arr(r.cost, r.n_arcs, np.int32))
     if r.loc_b:
         nl = r.n_locations
         out.stages = dict(loc_b=_arr(r.loc_b, nl, np.float64), loc_d=_arr(r.loc_d, nl, np.float64),
@@ -397,13 +394,19 @@ class Context:
         if rc != 0:
             raise W1Error(rc, "w1_ctx_set_tuning")
 
+    KERNEL_TIMES = ("worklist_ms", "count_ms", "emit_ms", "pairs", "bucket_hist_ms", "bucket_scatter_ms",
+                    "row_hist_ms", "row_scatter_ms", "row_sort_ms")
+
     def kernel_times(self) -> dict:
-        """HIP-event times (ms) of the last call's WSPD kernels."""
-        out = (ctypes.c_double * 4)()
-        rc = lib().w1_ctx_last_kernel_times(self._h, out, 4)
+        """HIP-event times (ms) of the last call's WSPD and network kernels."""
+        n = len(self.KERNEL_TIMES)
+        out = (ctypes.c_double * n)()
+        rc = lib().w1_ctx_last_kernel_times(self._h, out, n)
         if rc != 0:
             raise W1Error(rc, "w1_ctx_last_kernel_times")
-        return {"worklist_ms": out[0], "count_ms": out[1], "emit_ms": out[2], "pairs": int(out[3])}
+        d = {k: out[i] for i, k in enumerate(self.KERNEL_TIMES)}
+        d["pairs"] = int(d["pairs"])
+        return d
 
     def device_network(self, k: int = 0) -> dict:
         """Sizes and raw device pointers of pair k's network from the last call."""

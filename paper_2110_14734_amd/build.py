@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libw1approx.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["prims.hip", "stages.hip", "wspd.hip", "deepsets.hip", "pipeline.cpp", "surrogate.cpp", "flow.cpp"]
+SOURCES = ["prims.hip", "stages.hip", "wspd.hip", "csr.hip", "deepsets.hip", "pipeline.cpp", "surrogate.cpp", "flow.cpp"]
 HEADERS = ["common.h", "kernels.h", "flow.h", "ctx.h", "surrogate.h", "limits.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -46,8 +46,6 @@ struct PairArrays {
   int64_t* item_start;   // first WSPD work item of the pair
   uint64_t* npairs;      // WSPD pairs of the pair
   uint64_t* pair_start;  // first output pair of the pair
-  int64_t* diag_start;   // first diagonal arc of the pair
-  int32_t* ndiag;
 };
 
 // ---------------------------------------------------------------- helpers --

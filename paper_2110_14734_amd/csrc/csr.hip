@@ -1,0 +1,528 @@
+// a5: the sparse transshipment network in compressed sparse row form.
+//
+// The network simplex reads the network as a static CSR graph: the arcs
+// sorted by tail, ties by head (Appendix, network representation).  The
+// paper sorts its arc list with a parallel merge sort; here the sort is a
+// two-level partition followed by a per-row bitmap sort, which moves each
+// arc a fixed number of times and never sorts more than one row at once:
+//
+//   1. bucket histogram: each arc u -> v of a WSPD pair record (both
+//      orientations) counts towards the bucket of its tail, a bucket being
+//      2^RB consecutive global cells;
+//   2. bucket scatter: arcs are written bucket-major as 32-bit entries
+//      (tail within the bucket << DB | head), staged in LDS so each block
+//      writes one contiguous run per bucket;
+//   3. row histogram, per bucket: the out-degree of every cell;
+//   4. row scatter, per bucket: each row's heads are written to the row's
+//      final place (order within the row still arbitrary);
+//   5. row sort: one block per row sets one bit per head in an LDS bitmap
+//      over the pair's cells and reads the bits back in order, writing the
+//      heads and their costs (2 max(|di|, |dj|) from the cell coordinates)
+//      and the row's arc to the A-diagonal node;
+//   6. the B-diagonal node's row: its arcs to the cells with B mass, in cell
+//      order, then to the A-diagonal node; and the supplies.
+//
+// Heads are distinct within a row (a repeated arc would mean a cell pair
+// covered by two WSPD pairs), so the bitmap loses nothing and the result is
+// the unique sorted order, independent of the arbitrary orders before it.
+//
+// Row numbering: the rows of diagram pair p are cell_start[p] + 2p + r for
+// r in [0, n_p + 2): its cells, then its A-diagonal node (no out-arcs), then
+// its B-diagonal node -- the layout of the supply array.  Heads are local
+// node ids of the pair (cells 0..n_p-1, A-diagonal n_p, B-diagonal n_p + 1).
+#include "common.h"
+#include "kernels.h"
+
+namespace w1 {
+
+namespace {
+
+constexpr int CB = 512;        // threads per block of the partition passes
+constexpr int PPT = 8;         // pair records per thread in the bucket passes
+constexpr int PTILE = CB * PPT;
+constexpr int SORT_B = 256;    // threads per block of the row sort
+constexpr int WIN_WORDS = (1 << 14) - 8;  // bitmap window (LDS stays within 64 KiB)
+
+// Last p in [0, K) with rstart[p] <= x (the pair holding record x: pairs
+// without records share their start with the next pair, which wins).
+__device__ inline int64_t pair_of(const uint64_t* __restrict__ rstart, int64_t K, uint64_t x) {
+  int64_t lo = 0, hi = K;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (rstart[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Diagram pair of every record of a tile: the pair of the first and of the
+// last record, found once per block; records in between search only that
+// range (almost always one pair).
+struct TilePairs {
+  int64_t p0, p1;
+};
+__device__ inline TilePairs tile_pairs(const uint64_t* rstart, int64_t K, uint64_t x0, uint64_t x1) {
+  __shared__ int64_t s_p[2];
+  if (threadIdx.x == 0) {
+    s_p[0] = pair_of(rstart, K, x0);
+    s_p[1] = pair_of(rstart, K, x1 - 1);
+  }
+  __syncthreads();
+  return TilePairs{s_p[0], s_p[1]};
+}
+__device__ inline int64_t record_pair(const TilePairs& tp, const uint64_t* rstart, uint64_t x) {
+  if (tp.p0 == tp.p1) return tp.p0;
+  int64_t lo = tp.p0, hi = tp.p1 + 1;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (rstart[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Exclusive scan of n LDS counters in place (block of CB threads, each
+// owning a contiguous run); returns nothing, s_tmp needs CB / WAVE slots.
+__device__ inline void lds_excl_scan(uint32_t* cnt, int n, uint32_t* s_tmp) {
+  const int per = (n + CB - 1) / CB;
+  const int a = threadIdx.x * per, b = min(n, a + per);
+  uint32_t sum = 0;
+  for (int i = a; i < b; ++i) sum += cnt[i];
+  // wave inclusive scan of the run sums
+  const int lane = lane_id(), wave = threadIdx.x / WAVE;
+  uint32_t inc = sum;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint32_t o = __shfl_up(inc, d);
+    if (lane >= d) inc += o;
+  }
+  if (lane == WAVE - 1) s_tmp[wave] = inc;
+  __syncthreads();
+  uint32_t pre = inc - sum;
+  for (int w = 0; w < wave; ++w) pre += s_tmp[w];
+  for (int i = a; i < b; ++i) {
+    const uint32_t c = cnt[i];
+    cnt[i] = pre;
+    pre += c;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------- 1. bucket hist --
+// Arcs of pair records [x0, x1): tail cell (global) and entry.
+__device__ inline void record_arcs(const uint32_t* __restrict__ rec, uint64_t x, int64_t cs, int RB, int DB,
+                                   uint32_t& b0, uint32_t& e0, uint32_t& b1, uint32_t& e1) {
+  const uint32_t u = rec[3 * x], v = rec[3 * x + 1];
+  const uint64_t gu = (uint64_t)cs + u, gv = (uint64_t)cs + v;
+  const uint32_t m = (1u << RB) - 1u;
+  b0 = (uint32_t)(gu >> RB);
+  e0 = (((uint32_t)gu & m) << DB) | v;
+  b1 = (uint32_t)(gv >> RB);
+  e1 = (((uint32_t)gv & m) << DB) | u;
+}
+
+__global__ void __launch_bounds__(CB) k_bucket_hist(const uint32_t* __restrict__ rec, uint64_t P,
+                                                    const uint64_t* __restrict__ rstart, int64_t K,
+                                                    const int64_t* __restrict__ cell_start, int RB, int DB, int NB,
+                                                    unsigned long long* __restrict__ bcnt) {
+  extern __shared__ uint32_t s_hist[];
+  const uint64_t x0 = (uint64_t)blockIdx.x * PTILE, x1 = min(P, x0 + PTILE);
+  for (int b = threadIdx.x; b < NB; b += CB) s_hist[b] = 0;
+  const TilePairs tp = tile_pairs(rstart, K, x0, x1);  // (includes a barrier)
+  for (int k = 0; k < PPT; ++k) {
+    const uint64_t x = x0 + (uint64_t)k * CB + threadIdx.x;
+    if (x >= x1) break;
+    const int64_t cs = cell_start[record_pair(tp, rstart, x)];
+    uint32_t b0, e0, b1, e1;
+    record_arcs(rec, x, cs, RB, DB, b0, e0, b1, e1);
+    atomicAdd(&s_hist[b0], 1u);
+    atomicAdd(&s_hist[b1], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < NB; b += CB)
+    if (s_hist[b]) atomicAdd(&bcnt[b], (unsigned long long)s_hist[b]);
+}
+
+// ------------------------------------------------------- 2. bucket scatter --
+__global__ void __launch_bounds__(CB) k_bucket_scatter(const uint32_t* __restrict__ rec, uint64_t P,
+                                                       const uint64_t* __restrict__ rstart, int64_t K,
+                                                       const int64_t* __restrict__ cell_start, int RB, int DB, int NB,
+                                                       const uint64_t* __restrict__ bstart,
+                                                       unsigned long long* __restrict__ bcur,
+                                                       uint32_t* __restrict__ out) {
+  extern __shared__ uint32_t s_mem[];
+  uint32_t* s_cnt = s_mem;                         // NB: counts, then prefixes
+  int64_t* s_gofs = (int64_t*)(s_mem + ((NB + 1) & ~1));  // NB: global base - prefix
+  uint32_t* s_ent = (uint32_t*)(s_gofs + NB);      // 2 PTILE staged entries
+  uint16_t* s_bkt = (uint16_t*)(s_ent + 2 * PTILE);  // 2 PTILE bucket ids
+  __shared__ uint32_t s_tmp[CB / WAVE];
+  const uint64_t x0 = (uint64_t)blockIdx.x * PTILE, x1 = min(P, x0 + PTILE);
+  for (int b = threadIdx.x; b < NB; b += CB) s_cnt[b] = 0;
+  const TilePairs tp = tile_pairs(rstart, K, x0, x1);
+  uint32_t eb[2 * PPT], ee[2 * PPT], er[2 * PPT];
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const uint64_t x = x0 + (uint64_t)k * CB + threadIdx.x;
+    if (x < x1) {
+      const int64_t cs = cell_start[record_pair(tp, rstart, x)];
+      record_arcs(rec, x, cs, RB, DB, eb[2 * k], ee[2 * k], eb[2 * k + 1], ee[2 * k + 1]);
+      er[2 * k] = atomicAdd(&s_cnt[eb[2 * k]], 1u);
+      er[2 * k + 1] = atomicAdd(&s_cnt[eb[2 * k + 1]], 1u);
+      n = 2 * k + 2;
+    }
+  }
+  __syncthreads();
+  // reserve each bucket's run in the global bucket, then turn counts into
+  // block-local prefixes
+  for (int b = threadIdx.x; b < NB; b += CB) {
+    const uint32_t c = s_cnt[b];
+    s_gofs[b] = c ? (int64_t)(bstart[b] + atomicAdd(&bcur[b], (unsigned long long)c)) : 0;
+  }
+  __syncthreads();
+  lds_excl_scan(s_cnt, NB, s_tmp);
+  for (int b = threadIdx.x; b < NB; b += CB) s_gofs[b] -= (int64_t)s_cnt[b];
+#pragma unroll
+  for (int k = 0; k < 2 * PPT; ++k) {
+    if (k < n) {
+      const uint32_t pos = s_cnt[eb[k]] + er[k];
+      s_ent[pos] = ee[k];
+      s_bkt[pos] = (uint16_t)eb[k];
+    }
+  }
+  __syncthreads();
+  const uint32_t tot = (uint32_t)(2 * (x1 - x0));
+  for (uint32_t i = threadIdx.x; i < tot; i += CB) out[s_gofs[s_bkt[i]] + (int64_t)i] = s_ent[i];
+}
+
+// ------------------------------------------------------ 3. / 4. row passes --
+// Tile t of the bucket-major entries: bucket b = last with tfirst[b] <= t.
+struct BTile {
+  int64_t b, a, e;  // bucket, entry range [a, e)
+};
+__device__ inline BTile bucket_tile(const int64_t* __restrict__ tfirst, int NB, const uint64_t* __restrict__ bstart,
+                                    int64_t t, int etile) {
+  __shared__ int64_t s_t[3];
+  if (threadIdx.x == 0) {
+    int64_t lo = 0, hi = NB;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (tfirst[mid] <= t) lo = mid;
+      else hi = mid;
+    }
+    const int64_t a = (int64_t)bstart[lo] + (t - tfirst[lo]) * etile;
+    s_t[0] = lo;
+    s_t[1] = a;
+    s_t[2] = min((int64_t)bstart[lo + 1], a + etile);
+  }
+  __syncthreads();
+  return BTile{s_t[0], s_t[1], s_t[2]};
+}
+
+__global__ void __launch_bounds__(CB) k_row_hist(const uint32_t* __restrict__ ent, const int64_t* __restrict__ tfirst,
+                                                 int NB, const uint64_t* __restrict__ bstart, int RB, int DB,
+                                                 int64_t N, int etile, uint32_t* __restrict__ rowcnt) {
+  extern __shared__ uint32_t s_hist[];
+  const int R = 1 << RB;
+  for (int r = threadIdx.x; r < R; r += CB) s_hist[r] = 0;
+  const BTile bt = bucket_tile(tfirst, NB, bstart, blockIdx.x, etile);
+  for (int64_t i = bt.a + threadIdx.x; i < bt.e; i += CB) atomicAdd(&s_hist[ent[i] >> DB], 1u);
+  __syncthreads();
+  const int64_t g0 = bt.b << RB;
+  for (int r = threadIdx.x; r < R; r += CB)
+    if (s_hist[r] && g0 + r < N) atomicAdd(&rowcnt[g0 + r], s_hist[r]);
+}
+
+// EPT entries per thread: the tile of CB * EPT entries and the 2^RB row
+// counters share the LDS (EPT = 16 up to 2^10 rows per bucket).
+template <int EPT>
+__global__ void __launch_bounds__(CB) k_row_scatter(const uint32_t* __restrict__ ent, const int64_t* __restrict__ tfirst,
+                                                    int NB, const uint64_t* __restrict__ bstart, int RB, int DB,
+                                                    int64_t N, const uint32_t* __restrict__ cpair,
+                                                    const uint64_t* __restrict__ off, uint32_t* __restrict__ rowcur,
+                                                    uint32_t* __restrict__ heads) {
+  extern __shared__ uint32_t s_mem[];
+  const int R = 1 << RB;
+  uint32_t* s_cnt = s_mem;
+  int64_t* s_gofs = (int64_t*)(s_mem + R);
+  uint32_t* s_ent = (uint32_t*)(s_gofs + R);
+  uint16_t* s_row = (uint16_t*)(s_ent + CB * EPT);
+  __shared__ uint32_t s_tmp[CB / WAVE];
+  for (int r = threadIdx.x; r < R; r += CB) s_cnt[r] = 0;
+  const BTile bt = bucket_tile(tfirst, NB, bstart, blockIdx.x, CB * EPT);
+  uint32_t ev[EPT], rk[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int64_t i = bt.a + (int64_t)k * CB + threadIdx.x;
+    if (i < bt.e) {
+      ev[k] = ent[i];
+      rk[k] = atomicAdd(&s_cnt[ev[k] >> DB], 1u);
+    }
+  }
+  __syncthreads();
+  const int64_t g0 = bt.b << RB;
+  for (int r = threadIdx.x; r < R; r += CB) {
+    const uint32_t c = s_cnt[r];
+    int64_t base = 0;
+    if (c) {
+      const int64_t g = g0 + r;
+      base = (int64_t)off[g + 2 * (int64_t)cpair[g]] + (int64_t)atomicAdd(&rowcur[g], c);
+    }
+    s_gofs[r] = base;
+  }
+  __syncthreads();
+  lds_excl_scan(s_cnt, R, s_tmp);
+  for (int r = threadIdx.x; r < R; r += CB) s_gofs[r] -= (int64_t)s_cnt[r];
+  const uint32_t hmask = (1u << DB) - 1u;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int64_t i = bt.a + (int64_t)k * CB + threadIdx.x;
+    if (i < bt.e) {
+      const uint32_t r = ev[k] >> DB;
+      const uint32_t pos = s_cnt[r] + rk[k];
+      s_ent[pos] = ev[k] & hmask;
+      s_row[pos] = (uint16_t)r;
+    }
+  }
+  __syncthreads();
+  const int tot = (int)(bt.e - bt.a);
+  for (int i = threadIdx.x; i < tot; i += CB) heads[s_gofs[s_row[i]] + i] = s_ent[i];
+}
+
+// ------------------------------------------------------------ 5. row sort --
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// One block per cell row g.  heads: the row's heads in arbitrary order
+// (rowcnt[g] of them at off[row]); col / cost: the sorted row.
+__global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict__ cpair,
+                                                     const int64_t* __restrict__ cell_start,
+                                                     const int32_t* __restrict__ ncells, const int2* __restrict__ cij,
+                                                     const int32_t* __restrict__ ca, const uint32_t* __restrict__ rowcnt,
+                                                     const uint64_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ heads, uint32_t* __restrict__ col,
+                                                     int32_t* __restrict__ cost) {
+  __shared__ uint32_t s_bm[WIN_WORDS];
+  __shared__ uint32_t s_wtot[SORT_B / WAVE];
+  const int64_t g = blockIdx.x;
+  const uint32_t p = cpair[g];
+  const int64_t cs = cell_start[p];
+  const uint32_t np = (uint32_t)ncells[p];
+  const int64_t start = (int64_t)off[g + 2 * (int64_t)p];
+  const uint32_t cnt = rowcnt[g];
+  const int2 me = cij[g];
+  const int lane = lane_id(), wave = threadIdx.x / WAVE;
+  uint32_t written = 0;  // heads written by earlier windows (block-uniform)
+  if (cnt > 0) {
+    for (uint32_t w0 = 0; w0 < np; w0 += 32u * WIN_WORDS) {
+      const uint32_t nbits = min(np - w0, 32u * WIN_WORDS);
+      const int nw = (int)((nbits + 31) / 32);
+      for (int i = threadIdx.x; i < nw; i += SORT_B) s_bm[i] = 0;
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < cnt; i += SORT_B) {
+        const uint32_t d = heads[start + i] - w0;
+        if (d < nbits) atomicOr(&s_bm[d >> 5], 1u << (d & 31));
+      }
+      __syncthreads();
+      // each wave owns a contiguous quarter of the words (64-word chunks)
+      const int q = (((nw + 3) / 4) + WAVE - 1) / WAVE * WAVE;
+      const int wa = min(nw, wave * q), wb = min(nw, wa + q);
+      uint32_t mine = 0;
+      for (int i = wa + lane; i < wb; i += WAVE) mine += __popc(s_bm[i]);
+      for (int d = WAVE / 2; d > 0; d >>= 1) mine += __shfl_xor(mine, d);
+      if (lane == 0) s_wtot[wave] = mine;
+      __syncthreads();
+      uint32_t base = written, all = 0;
+      for (int v = 0; v < SORT_B / WAVE; ++v) {
+        if (v < wave) base += s_wtot[v];
+        all += s_wtot[v];
+      }
+      for (int c = wa; c < wb; c += WAVE) {
+        const int i = c + lane;
+        uint32_t bits = i < wb ? s_bm[i] : 0u;
+        const uint32_t pc = (uint32_t)__popc(bits);
+        const uint32_t inc = wave_incl_scan_u32(pc);
+        int64_t k = start + (int64_t)(base + inc - pc);
+        while (bits) {
+          const int bit = __ffs(bits) - 1;
+          bits &= bits - 1;
+          const uint32_t d = w0 + (uint32_t)i * 32u + (uint32_t)bit;
+          const int2 o = cij[cs + d];
+          const int32_t di = abs(me.x - o.x), dj = abs(me.y - o.y);
+          col[k] = d;
+          cost[k] = 2 * max(di, dj);
+          ++k;
+        }
+        base += __shfl(inc, WAVE - 1);
+      }
+      written += all;
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0 && ca[g] > 0) {  // arc to the A-diagonal node, last in the row
+    col[start + cnt] = np;
+    cost[start + cnt] = me.y - me.x;
+  }
+}
+
+// ----------------------------------------------------- degrees and diagonal --
+// Out-degree of every row: a cell has its WSPD arcs plus one arc to the
+// A-diagonal node when it holds A mass; the A-diagonal node has none; the
+// B-diagonal node has one arc per cell with B mass plus one to the
+// A-diagonal node.  bpos: exclusive scan of (cb > 0) over all cells.
+__global__ void k_row_deg(const uint32_t* __restrict__ cpair, const int64_t* __restrict__ cell_start,
+                          const int32_t* __restrict__ ncells, const int32_t* __restrict__ ca,
+                          const int32_t* __restrict__ cb, const uint32_t* __restrict__ rowcnt,
+                          const uint32_t* __restrict__ bpos, int64_t N, uint64_t* __restrict__ deg) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const uint32_t p = cpair[g];
+  const int64_t cs = cell_start[p];
+  const int64_t row = g + 2 * (int64_t)p;
+  deg[row] = (uint64_t)rowcnt[g] + (ca[g] > 0 ? 1u : 0u);
+  if (g - cs == ncells[p] - 1) {
+    deg[row + 1] = 0;
+    deg[row + 2] = (uint64_t)(bpos[g] + (cb[g] > 0 ? 1u : 0u) - bpos[cs]) + 1u;
+  }
+}
+
+__global__ void k_bflags(const int32_t* __restrict__ cb, int64_t N, uint32_t* __restrict__ flag) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < N) flag[g] = cb[g] > 0 ? 1u : 0u;
+}
+
+// The B-diagonal row and the supplies (cell: A mass minus B mass; A-diagonal
+// node: minus the A mass; B-diagonal node: the B mass).
+__global__ void k_bdiag_rows(const uint32_t* __restrict__ cpair, const int64_t* __restrict__ cell_start,
+                             const int32_t* __restrict__ ncells, const int2* __restrict__ cij,
+                             const int32_t* __restrict__ ca, const int32_t* __restrict__ cb,
+                             const uint32_t* __restrict__ bpos, const uint64_t* __restrict__ off, PairArrays P,
+                             int64_t N, uint32_t* __restrict__ col, int32_t* __restrict__ cost,
+                             int64_t* __restrict__ supply) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const uint32_t p = cpair[g];
+  const int64_t cs = cell_start[p];
+  const uint32_t np = (uint32_t)ncells[p];
+  const uint32_t local = (uint32_t)(g - cs);
+  const int64_t rb = cs + 2 * (int64_t)p + np + 1;  // the B-diagonal row
+  const int64_t at = (int64_t)off[rb] + (bpos[g] - bpos[cs]);
+  const int2 v = cij[g];
+  if (cb[g] > 0) {
+    col[at] = local;
+    cost[at] = v.y - v.x;
+  }
+  const int64_t sb = cs + 2 * (int64_t)p;
+  supply[sb + local] = (int64_t)ca[g] - (int64_t)cb[g];
+  if (local == np - 1) {
+    const int64_t last = at + (cb[g] > 0 ? 1 : 0);
+    col[last] = np;
+    cost[last] = 0;
+    supply[sb + np] = -P.nA[p];
+    supply[sb + np + 1] = P.nB[p];
+  }
+}
+
+// Row pointers local to each diagram pair: the n_p + 3 pointers of pair p
+// start at cell_start[p] + 3p and count from its first arc.
+__global__ void k_local_rowptr(const uint32_t* __restrict__ cpair, const int64_t* __restrict__ cell_start,
+                               const int32_t* __restrict__ ncells, const uint64_t* __restrict__ off, int64_t N,
+                               int64_t* __restrict__ rp) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const uint32_t p = cpair[g];
+  const int64_t cs = cell_start[p];
+  const int64_t r0 = cs + 2 * (int64_t)p, local = g - cs;
+  const int64_t base = (int64_t)off[r0];
+  int64_t* out = rp + cs + 3 * (int64_t)p;
+  out[local] = (int64_t)off[r0 + local] - base;
+  if (local == ncells[p] - 1)
+    for (int r = 1; r <= 3; ++r) out[local + r] = (int64_t)off[r0 + local + r] - base;
+}
+
+__global__ void k_pair_arcs(const int64_t* __restrict__ cell_start, const uint64_t* __restrict__ off, int64_t K,
+                            int64_t nrows, uint64_t* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < K) out[p] = off[cell_start[p] + 2 * p];
+  else if (p == K) out[K] = off[nrows];
+}
+
+inline unsigned blocks(int64_t n, int bs = 256) { return (unsigned)(n > 0 ? ceil_div(n, bs) : 1); }
+
+}  // namespace
+
+size_t csr_bucket_scatter_lds(int NB) {
+  return (size_t)((NB + 1) & ~1) * 4 + (size_t)NB * 8 + (size_t)2 * PTILE * (4 + 2);
+}
+int csr_entries_per_thread(int RB) { return RB <= 10 ? 16 : (RB == 11 ? 8 : 4); }
+size_t csr_row_scatter_lds(int RB) {
+  return (size_t)(1 << RB) * 12 + (size_t)CB * csr_entries_per_thread(RB) * (4 + 2);
+}
+int64_t csr_entry_tile(int RB) { return (int64_t)CB * csr_entries_per_thread(RB); }
+
+void launch_csr_bucket_hist(const uint32_t* rec, uint64_t P, const uint64_t* rstart, int64_t K,
+                            const int64_t* cell_start, int RB, int DB, int NB, uint64_t* bcnt, hipStream_t st) {
+  if (P == 0) return;
+  hipLaunchKernelGGL(k_bucket_hist, dim3((unsigned)ceil_div((int64_t)P, PTILE)), dim3(CB), (size_t)NB * 4, st, rec, P,
+                     rstart, K, cell_start, RB, DB, NB, (unsigned long long*)bcnt);
+}
+void launch_csr_bucket_scatter(const uint32_t* rec, uint64_t P, const uint64_t* rstart, int64_t K,
+                               const int64_t* cell_start, int RB, int DB, int NB, const uint64_t* bstart,
+                               uint64_t* bcur, uint32_t* out, hipStream_t st) {
+  if (P == 0) return;
+  hipLaunchKernelGGL(k_bucket_scatter, dim3((unsigned)ceil_div((int64_t)P, PTILE)), dim3(CB),
+                     csr_bucket_scatter_lds(NB), st, rec, P, rstart, K, cell_start, RB, DB, NB, bstart,
+                     (unsigned long long*)bcur, out);
+}
+void launch_csr_row_hist(const uint32_t* ent, const int64_t* tfirst, int64_t ntiles, int NB, const uint64_t* bstart,
+                         int RB, int DB, int64_t N, uint32_t* rowcnt, hipStream_t st) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_row_hist, dim3((unsigned)ntiles), dim3(CB), (size_t)(1 << RB) * 4, st, ent, tfirst, NB, bstart,
+                     RB, DB, N, (int)csr_entry_tile(RB), rowcnt);
+}
+void launch_csr_row_scatter(const uint32_t* ent, const int64_t* tfirst, int64_t ntiles, int NB,
+                            const uint64_t* bstart, int RB, int DB, int64_t N, const uint32_t* cpair,
+                            const uint64_t* off, uint32_t* rowcur, uint32_t* heads, hipStream_t st) {
+  if (ntiles <= 0) return;
+  const int ept = csr_entries_per_thread(RB);
+  auto k = ept == 16 ? k_row_scatter<16> : (ept == 8 ? k_row_scatter<8> : k_row_scatter<4>);
+  hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(CB), csr_row_scatter_lds(RB), st, ent, tfirst, NB, bstart, RB, DB,
+                     N, cpair, off, rowcur, heads);
+}
+void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
+                         const int32_t* ca, const uint32_t* rowcnt, const uint64_t* off, const uint32_t* heads,
+                         int64_t N, uint32_t* col, int32_t* cost, hipStream_t st) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_row_sort, dim3((unsigned)N), dim3(SORT_B), 0, st, cpair, cell_start, ncells, cij, ca, rowcnt,
+                     off, heads, col, cost);
+}
+#define LAUNCH(kern, n, ...) \
+  do { if ((n) > 0) hipLaunchKernelGGL(kern, dim3(blocks(n)), dim3(256), 0, st, __VA_ARGS__); } while (0)
+void launch_csr_bflags(const int32_t* cb, int64_t N, uint32_t* flag, hipStream_t st) { LAUNCH(k_bflags, N, cb, N, flag); }
+void launch_csr_row_deg(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int32_t* ca,
+                        const int32_t* cb, const uint32_t* rowcnt, const uint32_t* bpos, int64_t N, uint64_t* deg,
+                        hipStream_t st) {
+  LAUNCH(k_row_deg, N, cpair, cell_start, ncells, ca, cb, rowcnt, bpos, N, deg);
+}
+void launch_csr_bdiag(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
+                      const int32_t* ca, const int32_t* cb, const uint32_t* bpos, const uint64_t* off,
+                      const PairArrays& P, int64_t N, uint32_t* col, int32_t* cost, int64_t* supply, hipStream_t st) {
+  LAUNCH(k_bdiag_rows, N, cpair, cell_start, ncells, cij, ca, cb, bpos, off, P, N, col, cost, supply);
+}
+void launch_csr_local_rowptr(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells,
+                             const uint64_t* off, int64_t N, int64_t* rp, hipStream_t st) {
+  LAUNCH(k_local_rowptr, N, cpair, cell_start, ncells, off, N, rp);
+}
+void launch_csr_pair_arcs(const int64_t* cell_start, const uint64_t* off, int64_t K, int64_t nrows, uint64_t* out,
+                          hipStream_t st) {
+  LAUNCH(k_pair_arcs, K + 1, cell_start, off, K, nrows, out);
+}
+
+}  // namespace w1

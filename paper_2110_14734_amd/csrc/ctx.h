@@ -22,6 +22,11 @@ struct StageError {
   int code;
 };
 
+// w1_ctx_last_kernel_times: work list, count pass, emit pass, pairs emitted,
+// then the network passes: bucket histogram, bucket scatter, row histogram,
+// row scatter (with the degree scan), row sort (with the diagonal rows).
+constexpr int kNumKernelTimes = 9;
+
 struct Ctx {
   int device = 0;
   int num_cus = 256;
@@ -43,25 +48,28 @@ struct Ctx {
   DBuf ckey, cpair, cij, ca, cb, iaux, ibox, iheight, iparent, ndepth, inode, rmap, isplit;
   // wspd
   DBuf itemsA, itemsB, itemsI, itemsS, icnt, ipos, ipp, cid, pcap, cfirst, cend, cpairs, ccnt, coff, xrange, xctr, err;
-  // network
-  DBuf pu, dcnt, dpos, dsrc, ddst, dcost, supply;  // pu: 12-byte pair records (u, v, cost)
+  // network: pu holds the 12-byte WSPD pair records (u, v, cost) and later
+  // the unsorted row heads; l1 the bucket-major arc entries and later the
+  // sorted heads (col); costb the arc costs; rp the per-pair row pointers
+  DBuf pu, l1, costb, rp, supply, rstart, bcnt, bstart, tfirst, bcur, rowcnt, rowcur, bflag, bpos, deg, off, parc;
   // per pair
   DBuf pairs;
   PairArrays P{};
   int64_t K = 0;
-  std::vector<int64_t> h_cell_start, h_ncells, h_pair_start, h_npairs, h_diag_start, h_ndiag, h_supply_base;
+  std::vector<int64_t> h_cell_start, h_ncells, h_npairs, h_arc_start, h_narcs;
   bool network_valid = false;
   hipEvent_t ev[8];
-  hipEvent_t kev[4];
-  double kms[4] = {0, 0, 0, 0};
+  hipEvent_t kev[11];  // WSPD work list, count, emit; network passes
+  double kms[kNumKernelTimes] = {0};
 
   Ctx() {
     DBuf* list[] = {&stage, &orpart, &segs, &pb, &pd, &psd, &kw0, &kw1, &kw2, &kA, &kB, &vA, &vB, &head, &idx, &scantmp, &sorttmp,
                     &small, &gb, &gd, &gpair, &gw, &lb, &ld, &lw, &lpair, &lt, &lterm, &lbin, &li, &lj, &nbuck,
                     &bincnt, &binstart, &ent, &entl, &ckey, &cpair, &cij, &ca, &cb, &iaux, &ibox, &iheight, &iparent,
                     &ndepth, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &cid, &pcap,
-                    &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &dcnt, &dpos,
-                    &dsrc, &ddst, &dcost, &supply, &pairs};
+                    &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &l1, &costb, &rp,
+                    &supply, &rstart, &bcnt, &bstart, &tfirst, &bcur, &rowcnt, &rowcur, &bflag, &bpos, &deg, &off,
+                    &parc, &pairs};
     all.assign(std::begin(list), std::end(list));
   }
 };

@@ -71,12 +71,39 @@ void launch_karras(const uint32_t* cpair, const uint64_t* ckey, int64_t N, int4*
 void launch_node_depth(const int32_t* iparent, int64_t N, int32_t* depth, int32_t* maxd, hipStream_t st);
 void launch_level_boxes(const int2* cij, int64_t N, const int4* iaux, const int32_t* depth, int d, int4* ibox,
                         int32_t* iheight, hipStream_t st);
-// a5
-void launch_diag_count(const uint32_t* cpair, const int32_t* ca, const int32_t* cb, int64_t N, uint32_t* dcnt,
-                       hipStream_t st);
-void launch_diag_fill(const uint32_t* cpair, const int2* cij, const int32_t* ca, const int32_t* cb, int64_t N,
-                      const uint32_t* dpos, const PairArrays& P, uint32_t* dsrc, uint32_t* ddst, int32_t* dcost,
-                      int64_t* supply, hipStream_t st);
+
+// a5: the network in compressed sparse row form (csr.hip).  Geometry
+// (csr_geometry in limits.h): a bucket is 2^RB consecutive cells, heads take
+// DB bits, RB + DB <= 32, at most 1024 buckets.
+size_t csr_bucket_scatter_lds(int NB);
+size_t csr_row_scatter_lds(int RB);
+int64_t csr_entry_tile(int RB);  // entries per tile of the row passes
+void launch_csr_bucket_hist(const uint32_t* rec, uint64_t P, const uint64_t* rstart, int64_t K,
+                            const int64_t* cell_start, int RB, int DB, int NB, uint64_t* bcnt, hipStream_t st);
+void launch_csr_bucket_scatter(const uint32_t* rec, uint64_t P, const uint64_t* rstart, int64_t K,
+                               const int64_t* cell_start, int RB, int DB, int NB, const uint64_t* bstart,
+                               uint64_t* bcur, uint32_t* out, hipStream_t st);
+void launch_csr_row_hist(const uint32_t* ent, const int64_t* tfirst, int64_t ntiles, int NB, const uint64_t* bstart,
+                         int RB, int DB, int64_t N, uint32_t* rowcnt, hipStream_t st);
+void launch_csr_bflags(const int32_t* cb, int64_t N, uint32_t* flag, hipStream_t st);
+void launch_csr_row_deg(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int32_t* ca,
+                        const int32_t* cb, const uint32_t* rowcnt, const uint32_t* bpos, int64_t N, uint64_t* deg,
+                        hipStream_t st);
+void launch_csr_row_scatter(const uint32_t* ent, const int64_t* tfirst, int64_t ntiles, int NB,
+                            const uint64_t* bstart, int RB, int DB, int64_t N, const uint32_t* cpair,
+                            const uint64_t* off, uint32_t* rowcur, uint32_t* heads, hipStream_t st);
+void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
+                         const int32_t* ca, const uint32_t* rowcnt, const uint64_t* off, const uint32_t* heads,
+                         int64_t N, uint32_t* col, int32_t* cost, hipStream_t st);
+void launch_csr_bdiag(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
+                      const int32_t* ca, const int32_t* cb, const uint32_t* bpos, const uint64_t* off,
+                      const PairArrays& P, int64_t N, uint32_t* col, int32_t* cost, int64_t* supply, hipStream_t st);
+void launch_csr_local_rowptr(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells,
+                             const uint64_t* off, int64_t N, int64_t* rp, hipStream_t st);
+// out[p] = off[cell_start[p] + 2p] for p < K, out[K] = off[nrows]: each pair's
+// first arc and the arc total.
+void launch_csr_pair_arcs(const int64_t* cell_start, const uint64_t* off, int64_t K, int64_t nrows, uint64_t* out,
+                          hipStream_t st);
 
 // a4 ------------------------------------------------------------------------
 // Tree view used by the WSPD traversal.  Node reference r >= 0 is internal

@@ -108,7 +108,7 @@ void setup_pairs(Ctx& c, int64_t K) {
   P.bbase = (int64_t*)take8(); P.tmaxA = (uint64_t*)take8(); P.tmaxB = (uint64_t*)take8();
   P.sumA = (uint64_t*)take8(); P.sumB = (uint64_t*)take8(); P.L = (double*)take8();
   P.cell_start = (int64_t*)take8(); P.item_start = (int64_t*)take8(); P.npairs = (uint64_t*)take8();
-  P.pair_start = (uint64_t*)take8(); P.diag_start = (int64_t*)take8();
+  P.pair_start = (uint64_t*)take8(); off += K8 * 8;  // spare
   const int64_t zero8_end = off;
   P.bmin = (uint64_t*)take8(); P.dmin = (uint64_t*)take8(); P.m0 = (int64_t*)take8();
   const int64_t ones8_end = off;
@@ -116,20 +116,13 @@ void setup_pairs(Ctx& c, int64_t K) {
   off += K8 * 8;  // spare
   P.err = (int32_t*)take4(); P.locA = (int32_t*)take4(); P.locB = (int32_t*)take4(); P.beh = (int32_t*)take4();
   P.bnx = (int32_t*)take4(); P.bny = (int32_t*)take4(); P.FA = (int32_t*)take4(); P.FB = (int32_t*)take4();
-  P.e = (int32_t*)take4(); P.ncells = (int32_t*)take4(); P.ndiag = (int32_t*)take4();
+  P.e = (int32_t*)take4(); P.ncells = (int32_t*)take4(); off += K8 * 4;  // spare
   fill_u64((uint64_t*)base, 0, zero8_end / 8, c.st);
   fill_u64((uint64_t*)P.bmin, ~0ull, K8 * 2, c.st);
   fill_u64((uint64_t*)P.m0, (uint64_t)INT64_MAX, K8, c.st);
   (void)ones8_end;
   fill_u32((uint32_t*)P.err, 0, K8 * 11, c.st);
 }
-
-struct HostPair {
-  int32_t err, locA, locB, e, ncells, ndiag, FA, FB;
-  int64_t nA, nB, cell_start, diag_start;
-  uint64_t sumA, sumB, npairs, pair_start;
-  double L;
-};
 
 template <typename T>
 std::vector<T> fetch_pairs(Ctx& c, const T* dev, int64_t K) {
@@ -301,6 +294,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
   }
 
   // ---------------------------------------------------------------- a2 --
+  int64_t maxnp = 0;  // most cells of one diagram pair
   if (M > 0) {
     const double* lb = (const double*)c.lb.p;
     const double* ld = (const double*)c.ld.p;
@@ -340,6 +334,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     for (int64_t p = 0; p < K; ++p) {
       cs[(size_t)p] = acc;
       acc += nc[(size_t)p];
+      maxnp = std::max<int64_t>(maxnp, nc[(size_t)p]);
     }
     upload(c, P.cell_start, cs.data(), (size_t)K * 8);
     std::vector<int32_t> cap((size_t)K);
@@ -505,7 +500,10 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       fill_u64((uint64_t*)P.seg_hi, 0, K, st);
       launch_pair_totals(ccnt, coff, cp, nch, P.pair_start, (uint64_t*)P.seg_hi, P.npairs, K, st);
       if (!(o.flags & W1_COUNT_ONLY) && Ptot > 0) {
-        uint32_t* pout = need<uint32_t>(c, c.pu, 3 * Ptot);
+        // the records' buffer later holds the rows' unsorted heads, which
+        // are placed by final arc number (2 Ptot WSPD arcs plus at most
+        // 2 N + K diagonal arcs)
+        uint32_t* pout = need<uint32_t>(c, c.pu, std::max<int64_t>(3 * Ptot, 2 * Ptot + 2 * N + K));
         fill_u32(xc, 0, 8, st);
         check(c, hipEventRecord(c.kev[3], st));
         launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr,
@@ -516,23 +514,106 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     }
   }
   record(c, 5);
-  c.kms[0] = c.kms[1] = c.kms[2] = 0;
+  for (double& x : c.kms) x = 0;
   c.kms[3] = (double)Ptot;
 
   // ---------------------------------------------------------------- a5 --
-  int64_t Dtot = 0;
+  // The network in compressed sparse row form, sorted by (tail, head)
+  // (Appendix, network representation); see csr.hip for the passes.
+  bool csr_timed = false;
+  int64_t Mtot = 0;
+  std::vector<uint64_t> h_parc;  // first arc of each pair, then the total
   if (N > 0 && !(o.flags & W1_COUNT_ONLY)) {
-    uint32_t* dc = need<uint32_t>(c, c.dcnt, N);
-    launch_diag_count((const uint32_t*)c.cpair.p, (const int32_t*)c.ca.p, (const int32_t*)c.cb.p, N, dc, st);
-    uint32_t* dp = scan_flags(c, dc, N, c.dpos);
-    Dtot = (int64_t)total_of(c, dc, dp, N);
-    uint32_t* ds = need<uint32_t>(c, c.dsrc, Dtot);
-    uint32_t* dd = need<uint32_t>(c, c.ddst, Dtot);
-    int32_t* dco = need<int32_t>(c, c.dcost, Dtot);
-    int64_t* sup = need<int64_t>(c, c.supply, N + 2 * K);
-    launch_diag_fill((const uint32_t*)c.cpair.p, (const int2*)c.cij.p, (const int32_t*)c.ca.p, (const int32_t*)c.cb.p,
-                     N, dp, P, ds, dd, dco, sup, st);
+    const uint32_t* cp = (const uint32_t*)c.cpair.p;
+    const int2* cij = (const int2*)c.cij.p;
+    const int32_t* ca = (const int32_t*)c.ca.p;
+    const int32_t* cb = (const int32_t*)c.cb.p;
+    const int32_t* ncl = P.ncells;
+    const CsrGeometry geo = csr_geometry(N, maxnp);
+    if (!geo.ok) throw StageError{W1_ERANGE};
+    const int RB = geo.RB, DB = geo.DB;
+    const int64_t NB = geo.NB;
+    trace(c, "csr bucket rows (log2)", RB);
+    trace(c, "csr head bits", DB);
+    const int64_t NR = N + 2 * K;  // rows: cells plus two diagonal nodes per pair
+    uint32_t* heads = (uint32_t*)c.pu.p;
+    uint32_t* col = need<uint32_t>(c, c.l1, 2 * Ptot + 2 * N + K);
+    uint32_t* rowcnt = need<uint32_t>(c, c.rowcnt, N);
+    fill_u32(rowcnt, 0, N, st);
+    int64_t* sup = need<int64_t>(c, c.supply, NR);
+    int64_t ntiles = 0;
+    const uint64_t* bstart = nullptr;
+    const int64_t* tfirst = nullptr;
+    if (Ptot > 0) {
+      uint64_t* rstart = need<uint64_t>(c, c.rstart, K);
+      scan_u64(P.npairs, rstart, K, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(K, 8)), st);
+      uint64_t* bcnt = need<uint64_t>(c, c.bcnt, NB);
+      fill_u64(bcnt, 0, NB, st);
+      csr_timed = true;
+      check(c, hipEventRecord(c.kev[4], st));
+      launch_csr_bucket_hist((const uint32_t*)c.pu.p, (uint64_t)Ptot, rstart, K, P.cell_start, RB, DB, (int)NB, bcnt,
+                             st);
+      check(c, hipEventRecord(c.kev[5], st));
+      // bucket starts and the tiles of the row passes (host: NB is small)
+      std::vector<uint64_t> hb((size_t)NB);
+      readback(c, bcnt, hb.data(), NB);
+      const int64_t et = csr_entry_tile(RB);
+      std::vector<uint64_t> hbs((size_t)NB + 1);
+      std::vector<int64_t> htf((size_t)NB + 1);
+      uint64_t acc = 0;
+      for (int64_t b = 0; b < NB; ++b) {
+        hbs[(size_t)b] = acc;
+        htf[(size_t)b] = ntiles;
+        acc += hb[(size_t)b];
+        ntiles += ceil_div((int64_t)hb[(size_t)b], et);
+      }
+      hbs[(size_t)NB] = acc;
+      htf[(size_t)NB] = ntiles;
+      if (acc != 2 * (uint64_t)Ptot || ntiles >= (int64_t(1) << 31)) throw StageError{W1_EOVERFLOW};
+      uint64_t* dbs = need<uint64_t>(c, c.bstart, NB + 1);
+      int64_t* dtf = need<int64_t>(c, c.tfirst, NB + 1);
+      upload(c, dbs, hbs.data(), (size_t)(NB + 1) * 8);
+      upload(c, dtf, htf.data(), (size_t)(NB + 1) * 8);
+      bstart = dbs;
+      tfirst = dtf;
+      uint64_t* bcur = need<uint64_t>(c, c.bcur, NB);
+      fill_u64(bcur, 0, NB, st);
+      check(c, hipEventRecord(c.kev[6], st));
+      launch_csr_bucket_scatter((const uint32_t*)c.pu.p, (uint64_t)Ptot, rstart, K, P.cell_start, RB, DB, (int)NB,
+                                bstart, bcur, col, st);
+      check(c, hipEventRecord(c.kev[7], st));
+      launch_csr_row_hist(col, tfirst, ntiles, (int)NB, bstart, RB, DB, N, rowcnt, st);
+      check(c, hipEventRecord(c.kev[8], st));
+    }
+    // degrees, row offsets
+    uint32_t* bflag = need<uint32_t>(c, c.bflag, N);
+    launch_csr_bflags(cb, N, bflag, st);
+    uint32_t* bpos = scan_flags(c, bflag, N, c.bpos);
+    uint64_t* deg = need<uint64_t>(c, c.deg, NR + 1);
+    fill_u64(deg, 0, NR + 1, st);
+    launch_csr_row_deg(cp, P.cell_start, ncl, ca, cb, rowcnt, bpos, N, deg, st);
+    uint64_t* off = need<uint64_t>(c, c.off, NR + 1);
+    scan_u64(deg, off, NR + 1, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(NR + 1, 8)), st);
+    if (Ptot > 0) {
+      uint32_t* rowcur = need<uint32_t>(c, c.rowcur, N);
+      fill_u32(rowcur, 0, N, st);
+      launch_csr_row_scatter(col, tfirst, ntiles, (int)NB, bstart, RB, DB, N, cp, off, rowcur, heads, st);
+      check(c, hipEventRecord(c.kev[9], st));
+    }
+    int32_t* cost = need<int32_t>(c, c.costb, 2 * Ptot + 2 * N + K);
+    launch_csr_row_sort(cp, P.cell_start, ncl, cij, ca, rowcnt, off, heads, N, col, cost, st);
+    launch_csr_bdiag(cp, P.cell_start, ncl, cij, ca, cb, bpos, off, P, N, col, cost, sup, st);
+    int64_t* rp = need<int64_t>(c, c.rp, N + 3 * K);
+    fill_u64((uint64_t*)rp, 0, N + 3 * K, st);
+    launch_csr_local_rowptr(cp, P.cell_start, ncl, off, N, rp, st);
+    uint64_t* parc = need<uint64_t>(c, c.parc, K + 1);
+    launch_csr_pair_arcs(P.cell_start, off, K, NR, parc, st);
+    check(c, hipEventRecord(c.kev[10], st));
     check(c, hipGetLastError());
+    h_parc.resize((size_t)K + 1);
+    readback(c, parc, h_parc.data(), K + 1);
+    Mtot = (int64_t)h_parc[(size_t)K];
+    trace(c, "network arcs", Mtot);
   }
   record(c, 6);
   check(c, hipStreamSynchronize(st));
@@ -547,26 +628,39 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     c.kms[1] = b2;
     c.kms[2] = d;
   }
+  if (csr_timed) {
+    float t[5] = {0, 0, 0, 0, 0};
+    (void)hipEventElapsedTime(&t[0], c.kev[4], c.kev[5]);
+    (void)hipEventElapsedTime(&t[1], c.kev[6], c.kev[7]);
+    (void)hipEventElapsedTime(&t[2], c.kev[7], c.kev[8]);
+    (void)hipEventElapsedTime(&t[3], c.kev[8], c.kev[9]);
+    (void)hipEventElapsedTime(&t[4], c.kev[9], c.kev[10]);
+    for (int i = 0; i < 5; ++i) c.kms[4 + i] = t[i];
+  }
   if (herr) throw StageError{W1_EOVERFLOW};
 
   // ------------------------------------------------------------ results --
   std::vector<int32_t> h_err = fetch_pairs(c, P.err, K), h_locA = fetch_pairs(c, P.locA, K),
                        h_locB = fetch_pairs(c, P.locB, K), h_e = fetch_pairs(c, P.e, K),
-                       h_nc = fetch_pairs(c, P.ncells, K), h_nd = fetch_pairs(c, P.ndiag, K),
-                       h_FA = fetch_pairs(c, P.FA, K), h_FB = fetch_pairs(c, P.FB, K);
+                       h_nc = fetch_pairs(c, P.ncells, K), h_FA = fetch_pairs(c, P.FA, K),
+                       h_FB = fetch_pairs(c, P.FB, K);
   std::vector<int64_t> h_nA = fetch_pairs(c, P.nA, K), h_nB = fetch_pairs(c, P.nB, K),
-                       h_cs = fetch_pairs(c, P.cell_start, K), h_ds = fetch_pairs(c, P.diag_start, K);
+                       h_cs = fetch_pairs(c, P.cell_start, K);
   std::vector<uint64_t> h_sA = fetch_pairs(c, P.sumA, K), h_sB = fetch_pairs(c, P.sumB, K),
-                        h_np = fetch_pairs(c, P.npairs, K), h_ps = fetch_pairs(c, P.pair_start, K);
+                        h_np = fetch_pairs(c, P.npairs, K);
   std::vector<double> h_L = fetch_pairs(c, P.L, K);
   float tms[8] = {0};
   for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&tms[i], c.ev[i], c.ev[i + 1]);
   c.h_cell_start.assign(h_cs.begin(), h_cs.end());
   c.h_ncells.assign(h_nc.begin(), h_nc.end());
-  c.h_pair_start.assign(h_ps.begin(), h_ps.end());
   c.h_npairs.assign(h_np.begin(), h_np.end());
-  c.h_diag_start.assign(h_ds.begin(), h_ds.end());
-  c.h_ndiag.assign(h_nd.begin(), h_nd.end());
+  c.h_arc_start.assign((size_t)K, 0);
+  c.h_narcs.assign((size_t)K, 0);
+  if (!h_parc.empty())
+    for (int64_t p = 0; p < K; ++p) {
+      c.h_arc_start[(size_t)p] = (int64_t)h_parc[(size_t)p];
+      c.h_narcs[(size_t)p] = (int64_t)(h_parc[(size_t)p + 1] - h_parc[(size_t)p]);
+    }
   c.network_valid = !(o.flags & W1_COUNT_ONLY);
   int64_t loc_off = 0;
   for (int64_t p = 0; p < K; ++p) {
@@ -584,8 +678,8 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     r.grid = std::ldexp(1.0, r.grid_exp);
     r.n_cells = h_nc[(size_t)p];
     r.n_pairs = (int64_t)h_np[(size_t)p];
-    r.n_diag = (o.flags & W1_COUNT_ONLY) ? 0 : h_nd[(size_t)p];
-    r.n_arcs = 2 * r.n_pairs + r.n_diag;
+    r.n_arcs = c.h_narcs[(size_t)p];
+    r.n_diag = r.n_arcs > 0 ? r.n_arcs - 2 * r.n_pairs : 0;
     r.rwmd_sum_a = (int64_t)h_sA[(size_t)p];
     r.rwmd_sum_b = (int64_t)h_sB[(size_t)p];
     r.rwmd_shift_a = h_FA[(size_t)p];
@@ -630,28 +724,25 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     }
     loc_off += (int64_t)h_locA[(size_t)p] + h_locB[(size_t)p];
   }
-  (void)Ptot;
-  (void)Dtot;
+  (void)Mtot;
   return W1_OK;
 }
 
-// Copy one pair's network to the host (arrays owned by the result).
+// Copy one pair's network to the host (arrays owned by the result): cells,
+// supplies and the sorted rows (row pointers local to the pair, local node
+// ids as heads).
 void copy_network(Ctx& c, int64_t p, w1_result& r) {
-  const int64_t nc = c.h_ncells[(size_t)p], np = c.h_npairs[(size_t)p], nd = c.h_ndiag[(size_t)p];
-  const int64_t cs = c.h_cell_start[(size_t)p], ps = c.h_pair_start[(size_t)p], ds = c.h_diag_start[(size_t)p];
+  const int64_t nc = c.h_ncells[(size_t)p], m = c.h_narcs[(size_t)p];
+  const int64_t cs = c.h_cell_start[(size_t)p], as = c.h_arc_start[(size_t)p];
   r.cell_i = (int32_t*)std::malloc((size_t)std::max<int64_t>(nc, 1) * 4);
   r.cell_j = (int32_t*)std::malloc((size_t)std::max<int64_t>(nc, 1) * 4);
   r.cell_ca = (int32_t*)std::malloc((size_t)std::max<int64_t>(nc, 1) * 4);
   r.cell_cb = (int32_t*)std::malloc((size_t)std::max<int64_t>(nc, 1) * 4);
   r.supply = (int64_t*)std::malloc((size_t)(nc + 2) * 8);
-  r.pair_u = (uint32_t*)std::malloc((size_t)std::max<int64_t>(np, 1) * 4);
-  r.pair_v = (uint32_t*)std::malloc((size_t)std::max<int64_t>(np, 1) * 4);
-  r.pair_cost = (int32_t*)std::malloc((size_t)std::max<int64_t>(np, 1) * 4);
-  r.diag_src = (uint32_t*)std::malloc((size_t)std::max<int64_t>(nd, 1) * 4);
-  r.diag_dst = (uint32_t*)std::malloc((size_t)std::max<int64_t>(nd, 1) * 4);
-  r.diag_cost = (int32_t*)std::malloc((size_t)std::max<int64_t>(nd, 1) * 4);
-  if (!r.cell_i || !r.cell_j || !r.cell_ca || !r.cell_cb || !r.supply || !r.pair_u || !r.pair_v || !r.pair_cost ||
-      !r.diag_src || !r.diag_dst || !r.diag_cost)
+  r.row_ptr = (int64_t*)std::malloc((size_t)(nc + 3) * 8);
+  r.col = (uint32_t*)std::malloc((size_t)std::max<int64_t>(m, 1) * 4);
+  r.cost = (int32_t*)std::malloc((size_t)std::max<int64_t>(m, 1) * 4);
+  if (!r.cell_i || !r.cell_j || !r.cell_ca || !r.cell_cb || !r.supply || !r.row_ptr || !r.col || !r.cost)
     throw StageError{W1_ENOMEM};
   if (nc > 0) {
     std::vector<int2> ij((size_t)nc);
@@ -663,39 +754,25 @@ void copy_network(Ctx& c, int64_t p, w1_result& r) {
     readback(c, (const int32_t*)c.ca.p + cs, r.cell_ca, nc);
     readback(c, (const int32_t*)c.cb.p + cs, r.cell_cb, nc);
     readback(c, (const int64_t*)c.supply.p + cs + 2 * p, r.supply, nc + 2);
+    readback(c, (const int64_t*)c.rp.p + cs + 3 * p, r.row_ptr, nc + 3);
   } else {
     r.supply[0] = r.supply[1] = 0;
+    r.row_ptr[0] = r.row_ptr[1] = r.row_ptr[2] = 0;
   }
-  if (np > 0) {  // 12-byte device records (u, v, cost) -> three host arrays
-    const int64_t blk = int64_t(1) << 22;
-    std::vector<uint32_t> rec((size_t)(3 * std::min(np, blk)));
-    for (int64_t q0 = 0; q0 < np; q0 += blk) {
-      const int64_t nq = std::min(blk, np - q0);
-      readback(c, (const uint32_t*)c.pu.p + 3 * (ps + q0), rec.data(), 3 * nq);
-      for (int64_t q = 0; q < nq; ++q) {
-        r.pair_u[q0 + q] = rec[(size_t)(3 * q)];
-        r.pair_v[q0 + q] = rec[(size_t)(3 * q + 1)];
-        r.pair_cost[q0 + q] = (int32_t)rec[(size_t)(3 * q + 2)];
-      }
-    }
-  }
-  if (nd > 0) {
-    readback(c, (const uint32_t*)c.dsrc.p + ds, r.diag_src, nd);
-    readback(c, (const uint32_t*)c.ddst.p + ds, r.diag_dst, nd);
-    readback(c, (const int32_t*)c.dcost.p + ds, r.diag_cost, nd);
+  if (m > 0) {
+    readback(c, (const uint32_t*)c.l1.p + as, r.col, m);
+    readback(c, (const int32_t*)c.costb.p + as, r.cost, m);
   }
 }
 
 void free_network(w1_result& r) {
-  void* ptrs[] = {r.cell_i, r.cell_j, r.cell_ca, r.cell_cb, r.supply, r.pair_u, r.pair_v, r.pair_cost,
-                  r.diag_src, r.diag_dst, r.diag_cost};
+  void* ptrs[] = {r.cell_i, r.cell_j, r.cell_ca, r.cell_cb, r.supply, r.row_ptr, r.col, r.cost};
   for (void* q : ptrs) std::free(q);
   r.cell_i = r.cell_j = r.cell_ca = r.cell_cb = nullptr;
   r.supply = nullptr;
-  r.pair_u = r.pair_v = nullptr;
-  r.pair_cost = nullptr;
-  r.diag_src = r.diag_dst = nullptr;
-  r.diag_cost = nullptr;
+  r.row_ptr = nullptr;
+  r.col = nullptr;
+  r.cost = nullptr;
 }
 
 // Flow outcome into the result.  An optimal flow gives the certified w1.  A
@@ -718,26 +795,11 @@ void finish_flow(w1_result& r, const FlowResult& fr) {
   r.w1_paper = std::ldexp((double)fr.cost, r.grid_exp - 1);
 }
 
-// Host flow of one pair from its host network copy.
+// Host flow of one pair from its host network copy (the sorted rows are
+// the solver's own input form).
 void solve_flow(w1_result& r, int64_t pivot_cap) {
-  const int64_t nc = r.n_cells, np = r.n_pairs, nd = r.n_diag;
-  const int64_t m = 2 * np + nd;
-  std::vector<uint32_t> src((size_t)m), dst((size_t)m);
-  std::vector<int32_t> cost((size_t)m);
-  for (int64_t k = 0; k < np; ++k) {
-    src[(size_t)(2 * k)] = r.pair_u[k];
-    dst[(size_t)(2 * k)] = r.pair_v[k];
-    src[(size_t)(2 * k + 1)] = r.pair_v[k];
-    dst[(size_t)(2 * k + 1)] = r.pair_u[k];
-    cost[(size_t)(2 * k)] = cost[(size_t)(2 * k + 1)] = r.pair_cost[k];
-  }
-  for (int64_t k = 0; k < nd; ++k) {
-    src[(size_t)(2 * np + k)] = r.diag_src[k];
-    dst[(size_t)(2 * np + k)] = r.diag_dst[k];
-    cost[(size_t)(2 * np + k)] = r.diag_cost[k];
-  }
   FlowResult fr{};
-  const int rc = network_simplex_arcs(nc + 2, m, src.data(), dst.data(), cost.data(), r.supply, pivot_cap, &fr);
+  const int rc = network_simplex(r.n_cells + 2, r.row_ptr, r.col, r.cost, r.supply, pivot_cap, &fr);
   if (rc != 0) {
     r.status = rc == -3 ? W1_ENOMEM : W1_EINVAL;
     return;
@@ -857,7 +919,7 @@ int w1_ctx_create(int device, w1_ctx** out) {
     delete c;
     return W1_EHIP;
   }
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 11; ++i)
     if (hipEventCreate(&c->kev[i]) != hipSuccess) {
       delete c;
       return W1_EHIP;
@@ -878,7 +940,7 @@ int w1_ctx_destroy(w1_ctx* c) {
   for (DBuf* b : c->all)
     if (b->p) (void)hipFree(b->p);
   for (int i = 0; i < 8; ++i) (void)hipEventDestroy(c->ev[i]);
-  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(c->kev[i]);
+  for (int i = 0; i < 11; ++i) (void)hipEventDestroy(c->kev[i]);
   if (c->hpin) (void)hipHostFree(c->hpin);
   delete c;
   return W1_OK;
@@ -905,18 +967,17 @@ int w1_device_network_get(w1_ctx* c, int64_t k, w1_device_network* out) {
   if (!c || !out || !c->network_valid) return W1_EINVAL;
   k -= c->K_base;
   if (k < 0 || k >= c->K) return W1_EINVAL;
-  const int64_t cs = c->h_cell_start[(size_t)k], ps = c->h_pair_start[(size_t)k], ds = c->h_diag_start[(size_t)k];
+  const int64_t cs = c->h_cell_start[(size_t)k], as = c->h_arc_start[(size_t)k];
   out->n_cells = c->h_ncells[(size_t)k];
   out->n_pairs = c->h_npairs[(size_t)k];
-  out->n_diag = c->h_ndiag[(size_t)k];
+  out->n_arcs = c->h_narcs[(size_t)k];
   out->cell_ij = (const int32_t*)c->cij.p + 2 * cs;
   out->cell_ca = (const int32_t*)c->ca.p + cs;
   out->cell_cb = (const int32_t*)c->cb.p + cs;
   out->supply = (const int64_t*)c->supply.p + cs + 2 * k;
-  out->pairs = (const uint32_t*)c->pu.p + 3 * ps;
-  out->diag_src = (const uint32_t*)c->dsrc.p + ds;
-  out->diag_dst = (const uint32_t*)c->ddst.p + ds;
-  out->diag_cost = (const int32_t*)c->dcost.p + ds;
+  out->row_ptr = (const int64_t*)c->rp.p + cs + 3 * k;
+  out->col = (const uint32_t*)c->l1.p + as;
+  out->cost = (const int32_t*)c->costb.p + as;
   return W1_OK;
 }
 
@@ -944,7 +1005,7 @@ int w1_ctx_set_tuning(w1_ctx* c, const w1_tuning* t) {
 
 int w1_ctx_last_kernel_times(const w1_ctx* c, double* ms, int n) {
   if (!c || !ms || n < 4) return W1_EINVAL;
-  for (int i = 0; i < 4; ++i) ms[i] = c->kms[i];
+  for (int i = 0; i < n; ++i) ms[i] = i < kNumKernelTimes ? c->kms[i] : 0.0;
   return W1_OK;
 }
 

@@ -686,42 +686,6 @@ __global__ void k_level_boxes(const int2* __restrict__ cij, int64_t N, const int
   iheight[g] = 1 + max(hh[0], hh[1]);
 }
 
-// ===================================================================== a5 ==
-__global__ void k_diag_count(const uint32_t* __restrict__ cpair, const int32_t* __restrict__ ca,
-                             const int32_t* __restrict__ cb, int64_t N, uint32_t* __restrict__ dcnt) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
-  const bool last = (c == N - 1) || cpair[c + 1] != cpair[c];
-  dcnt[c] = (ca[c] > 0 ? 1u : 0u) + (cb[c] > 0 ? 1u : 0u) + (last ? 1u : 0u);
-}
-
-__global__ void k_diag_fill(const uint32_t* __restrict__ cpair, const int2* __restrict__ cij, const int32_t* __restrict__ ca,
-                            const int32_t* __restrict__ cb, int64_t N, const uint32_t* __restrict__ dpos, PairArrays P,
-                            uint32_t* __restrict__ dsrc, uint32_t* __restrict__ ddst, int32_t* __restrict__ dcost,
-                            int64_t* __restrict__ supply) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
-  const uint32_t p = cpair[c];
-  const int64_t cs = P.cell_start[p];
-  const uint32_t np = (uint32_t)P.ncells[p];
-  const uint32_t local = (uint32_t)(c - cs);
-  const bool last = (c == N - 1) || cpair[c + 1] != p;
-  const int2 v = cij[c];
-  const int32_t dd = v.y - v.x;
-  uint32_t q = dpos[c];
-  if (c == cs) P.diag_start[p] = q;
-  if (ca[c] > 0) { dsrc[q] = local; ddst[q] = np; dcost[q] = dd; ++q; }
-  if (cb[c] > 0) { dsrc[q] = np + 1; ddst[q] = local; dcost[q] = dd; ++q; }
-  const int64_t nb = cs + 2 * (int64_t)p;
-  supply[nb + local] = (int64_t)ca[c] - (int64_t)cb[c];
-  if (last) {
-    dsrc[q] = np + 1; ddst[q] = np; dcost[q] = 0; ++q;
-    P.ndiag[p] = (int32_t)(q - dpos[cs]);
-    supply[nb + np] = -P.nA[p];
-    supply[nb + np + 1] = P.nB[p];
-  }
-}
-
 inline unsigned blocks(int64_t n, int bs = 256) { return (unsigned)(n > 0 ? ceil_div(n, bs) : 1); }
 
 }  // namespace
@@ -825,14 +789,4 @@ void launch_level_boxes(const int2* cij, int64_t N, const int4* iaux, const int3
                         int32_t* iheight, hipStream_t st) {
   if (N >= 2) LAUNCH(k_level_boxes, N - 1, cij, N, iaux, depth, d, ibox, iheight);
 }
-void launch_diag_count(const uint32_t* cpair, const int32_t* ca, const int32_t* cb, int64_t N, uint32_t* dcnt,
-                       hipStream_t st) {
-  LAUNCH(k_diag_count, N, cpair, ca, cb, N, dcnt);
-}
-void launch_diag_fill(const uint32_t* cpair, const int2* cij, const int32_t* ca, const int32_t* cb, int64_t N,
-                      const uint32_t* dpos, const PairArrays& P, uint32_t* dsrc, uint32_t* ddst, int32_t* dcost,
-                      int64_t* supply, hipStream_t st) {
-  LAUNCH(k_diag_fill, N, cpair, cij, ca, cb, N, dpos, P, dsrc, ddst, dcost, supply);
-}
-
 }  // namespace w1

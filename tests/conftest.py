@@ -19,3 +19,20 @@ def orc():
 
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def csr_checker(tmp_path_factory):
+    """The network row checker of tests/native/csr_check.cpp (g++, OpenMP):
+    test infrastructure, no GPU code."""
+    import ctypes
+    import subprocess
+
+    so = str(tmp_path_factory.mktemp("csr_check") / "csr_check.so")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", so,
+                           os.path.join(ROOT, "tests", "native", "csr_check.cpp")])
+    L = ctypes.CDLL(so)
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    L.csr_check_rows.argtypes = [i64, i64, i64, vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.csr_check_rows.restype = i64
+    return L

@@ -26,14 +26,6 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _sorted_pairs(u, v, c):
-    u = np.asarray(u, np.int64)
-    v = np.asarray(v, np.int64)
-    c = np.asarray(c, np.int64)
-    o = np.lexsort((v, u))
-    return u[o], v[o], c[o]
-
-
 def _oracle_tree(r):
     N = r.cells["i"].shape[0]
     nodes = r.nodes[N:]
@@ -48,6 +40,21 @@ def _gpu_tree(g):
     split = np.where(left >= 0, hi[np.maximum(left, 0)], ~left)
     key = np.lexsort((hi, lo))
     return lo[key], hi[key], split[key], st["node_box"].astype(np.int64)[key]
+
+
+def check_csr(net, o):
+    """The library's network rows equal the oracle's sorted rows exactly."""
+    assert np.array_equal(net["row_ptr"], o["row_ptr"])
+    assert np.array_equal(net["col"].astype(np.int64), o["col"])
+    assert np.array_equal(net["cost"].astype(np.int64), o["cost"])
+    assert np.array_equal(net["supply"], o["supply"])
+
+
+NET_KEYS = ("cell_i", "cell_j", "cell_ca", "cell_cb", "supply", "row_ptr", "col", "cost")
+
+
+def same_network(a, b):
+    return all(np.array_equal(a.network.get(f, np.zeros(0)), b.network.get(f, np.zeros(0))) for f in NET_KEYS)
 
 
 def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True):
@@ -81,20 +88,10 @@ def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True):
     if tree and g.n_cells >= 2:
         for x, y in zip(_gpu_tree(g), _oracle_tree(r)):
             assert np.array_equal(x, y)
-    # a4: WSPD pairs (u, v, cost) as a set
+    # a4 + a5: the WSPD pairs and the network, compared as the sorted rows
+    # element by element (no host-side sorting of the library's output)
     assert g.n_pairs == r.n_pairs
-    gu, gv, gc = _sorted_pairs(net["pair_u"], net["pair_v"], net["pair_cost"])
-    ou, ov, oc = _sorted_pairs(r.pairs["u"], r.pairs["v"], r.pairs["c"])
-    assert np.array_equal(gu, ou) and np.array_equal(gv, ov) and np.array_equal(gc, oc)
-    # a5: diagonal arcs and supplies
-    src, dst, cost, sup = orc.network(A, B, eps=eps, s_override=s_override)
-    nd = src.shape[0] - 2 * r.n_pairs
-    d_o = _sorted_pairs(src[2 * r.n_pairs:], dst[2 * r.n_pairs:], cost[2 * r.n_pairs:])
-    d_g = _sorted_pairs(net["diag_src"], net["diag_dst"], net["diag_cost"])
-    assert net["diag_src"].shape[0] == nd
-    for x, y in zip(d_g, d_o):
-        assert np.array_equal(x, y)
-    assert np.array_equal(net["supply"], sup)
+    check_csr(net, orc.csr(A, B, eps=eps, s_override=s_override))
     # flow and W1
     if flow:
         assert g.flow_cost == r.flow
@@ -181,8 +178,9 @@ def test_batch_equals_single_and_oracle(orc, ctx):
         for x in (batch[i], single):
             assert x.w1 == r.W1 and x.flow_cost == (r.flow if r.n else 0) and x.n_pairs == r.n_pairs
             assert x.lower_bound == r.L
-        for f in ("pair_u", "pair_v", "pair_cost", "diag_src", "diag_dst", "supply", "cell_i", "cell_j"):
-            assert np.array_equal(batch[i].network.get(f, np.zeros(0)), single.network.get(f, np.zeros(0))), f
+        assert same_network(batch[i], single)
+        if r.n:
+            check_csr(batch[i].network, orc.csr(As[i], Bs[i], eps=0.2))
 
 
 def test_determinism_and_count_only(ctx):
@@ -192,8 +190,7 @@ def test_determinism_and_count_only(ctx):
     A, B = pdsynth.mixture_pd(20000, 20), pdsynth.mixture_pd(19000, 21)
     g1 = ctx.approx(A, B, eps=0.2, flags=w1.KEEP_NETWORK | w1.NO_FLOW)
     g2 = ctx.approx(A, B, eps=0.2, flags=w1.KEEP_NETWORK | w1.NO_FLOW)
-    for f in ("pair_u", "pair_v", "pair_cost", "diag_src", "supply"):
-        assert np.array_equal(g1.network[f], g2.network[f]), f
+    assert same_network(g1, g2)
     g3 = ctx.approx(A, B, eps=0.2, flags=w1.COUNT_ONLY)
     assert g3.n_pairs == g1.n_pairs and g3.lower_bound == g1.lower_bound
 
@@ -216,38 +213,114 @@ def test_device_inputs_and_stream(orc, ctx):
     assert g_dev.w1 == g_host.w1 and g_dev.flow_cost == g_host.flow_cost
     r = orc.run(A, B, eps=0.2, flags=orc.ORC_NO_FLOW)
     assert g_dev.lower_bound == r.L and g_dev.n_pairs == r.n_pairs
-    gu, gv, gc = _sorted_pairs(g_dev.network["pair_u"], g_dev.network["pair_v"], g_dev.network["pair_cost"])
-    ou, ov, oc = _sorted_pairs(r.pairs["u"], r.pairs["v"], r.pairs["c"])
-    assert np.array_equal(gu, ou) and np.array_equal(gv, ov) and np.array_equal(gc, oc)
+    check_csr(g_dev.network, orc.csr(A, B, eps=0.2))
     assert g_host.lower_bound <= g_host.w1
 
 
-def _mix(u, v, c):
-    u = u.astype(np.uint64)
-    v = v.astype(np.uint64)
-    c = c.astype(np.int64).astype(np.uint64)
-    with np.errstate(over="ignore"):
-        x = ((u + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15) + (v + np.uint64(1))) * np.uint64(0xC2B2AE3D27D4EB4F) + c
-        x = x * np.uint64(0x165667B19E3779F9)
-        return int(x.sum(dtype=np.uint64)), int((x * x).sum(dtype=np.uint64))
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def test_full_size_config2(orc, ctx):
-    """200k + 200k FP32 points (mixture), eps 0.2: every cell, L, the pair
-    count and an order-independent checksum of all 6.8e8 pairs."""
+def _digest(a, dtype):
+    import hashlib
+
+    dt = np.dtype(dtype)
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=dt).astype(dt.newbyteorder("<")).tobytes()).hexdigest()
+
+
+def _hip_runtime():
+    """The HIP runtime already mapped into this process (the one the library
+    and torch share), for plain device-to-host copies."""
+    import ctypes
+
+    paths = sorted({ln.split()[-1] for ln in open("/proc/self/maps") if "libamdhip64" in ln})
+    assert len(paths) == 1, paths
+    h = ctypes.CDLL(paths[0])
+    h.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    return h
+
+
+def _d2h(hip, ptr, n, dtype, out=None):
+    out = np.empty(n, dtype) if out is None else out[:n]
+    if n:
+        assert hip.hipMemcpy(out.ctypes.data, ptr, out.nbytes, 2) == 0  # hipMemcpyDeviceToHost
+    return out
+
+
+def check_device_network(ctx, k, chk, n_pairs, checker, chunk_arcs=1 << 28):
+    """Checks pair k's device-resident network row block by row block: heads
+    strictly increasing, costs recomputed from the cells, diagonal rows by
+    membership, and both orientations of the cell arcs against the oracle's
+    pair count and pair checksum."""
+    import ctypes
+
+    d = ctx.device_network(k)
+    n, m = d["n_cells"], d["n_arcs"]
+    hip, L = _hip_runtime(), checker
+    rp = _d2h(hip, d["row_ptr"], n + 3, np.int64)
+    ij = _d2h(hip, d["cell_ij"], 2 * n, np.int32).reshape(-1, 2)
+    ci, cj = np.ascontiguousarray(ij[:, 0]), np.ascontiguousarray(ij[:, 1])
+    ca, cb = _d2h(hip, d["cell_ca"], n, np.int32), _d2h(hip, d["cell_cb"], n, np.int32)
+    assert rp[0] == 0 and rp[-1] == m and (np.diff(rp) >= 0).all()
+    col_buf = np.empty(min(m, chunk_arcs + n + 2), np.uint32)
+    cost_buf = np.empty_like(col_buf, dtype=np.int32)
+    sums = np.zeros(4, np.uint64)
+    counts = np.zeros(2, np.int64)
+    first = ctypes.c_int64(-1)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    r0 = 0
+    while r0 < n + 2:
+        r1 = int(np.searchsorted(rp, rp[r0] + chunk_arcs, side="right")) - 1
+        r1 = min(max(r1, r0 + 1), n + 2)
+        a0, a1 = int(rp[r0]), int(rp[r1])
+        assert a1 - a0 <= col_buf.shape[0]
+        col = _d2h(hip, d["col"] + 4 * a0, a1 - a0, np.uint32, col_buf)
+        cost = _d2h(hip, d["cost"] + 4 * a0, a1 - a0, np.int32, cost_buf)
+        bad = L.csr_check_rows(n, r0, r1, p(rp), a0, a1 - a0, p(col), p(cost), p(ci), p(cj), p(ca), p(cb),
+                               p(sums), p(counts), ctypes.byref(first))
+        assert bad == 0, f"{bad} bad rows in [{r0}, {r1}), first {first.value}"
+        r0 = r1
+    assert counts[0] == n_pairs and counts[1] == n_pairs
+    assert (int(sums[0]), int(sums[1])) == tuple(chk) and (int(sums[2]), int(sums[3])) == tuple(chk)
+    return m
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.05])
+def test_full_size_config2(ctx, csr_checker, eps):
+    """200k + 200k FP32 points (mixture) at the benchmark's eps 0.1 and at
+    0.05, checked against the oracle's stored results (written by
+    tests/golden/make_full_size.py, which calls only the oracle): every
+    location and its RWMD cost, L and its fixed-point sums, every cell, the
+    pair count, and the device-built network row by row -- sorted heads,
+    costs from the cells, diagonal rows, and both orientations of the cell
+    arcs against the oracle's pair checksum."""
+    import json
+
     import paper_2110_14734_amd as w1
 
-    _say("[gpu] full-size mixture 200k+200k eps 0.2")
+    with open(os.path.join(GOLD, "c2_full.json")) as f:
+        gold = json.load(f)["eps"][str(eps)]
+    _say(f"[gpu] full-size mixture 200k+200k eps {eps}")
     A, B = pdsynth.mixture_pd(200_000, 0), pdsynth.mixture_pd(200_000, 1)
-    r = orc.run(A, B, eps=0.2, flags=orc.ORC_COUNT_ONLY)
-    g = ctx.approx(A, B, eps=0.2, flags=w1.KEEP_NETWORK | w1.KEEP_STAGES | w1.NO_FLOW)
-    assert g.lower_bound == r.L and g.grid_exp == r.e
-    assert np.array_equal(g.stages["loc_t"], r.locs["t"])
-    net = g.network
-    assert np.array_equal(net["cell_i"], r.cells["i"]) and np.array_equal(net["cell_j"], r.cells["j"])
-    assert np.array_equal(net["cell_ca"], r.cells["cA"]) and np.array_equal(net["cell_cb"], r.cells["cB"])
-    assert g.n_pairs == r.n_pairs
-    assert _mix(net["pair_u"], net["pair_v"], net["pair_cost"]) == r.checksum
+    g = ctx.approx(A, B, eps=eps, flags=w1.KEEP_STAGES | w1.NO_FLOW)
+    assert (g.n_a, g.n_b, g.n_points, g.s, g.grid_exp) == (gold["nA"], gold["nB"], gold["n"], gold["s"], gold["e"])
+    assert g.lower_bound == float.fromhex(gold["L"])
+    st = g.stages
+    assert (st["rwmd_sum_a"], st["rwmd_sum_b"], st["rwmd_shift_a"], st["rwmd_shift_b"]) == (
+        gold["SA"], gold["SB"], gold["FA"], gold["FB"])
+    h = gold["sha256"]
+    assert g.n_locations == gold["n_locations"]
+    for key, dt in (("loc_b", np.float64), ("loc_d", np.float64), ("loc_w", np.int64), ("loc_t", np.float64)):
+        assert _digest(st[key], dt) == h[key], key
+    assert g.n_cells == gold["n_cells"] and g.n_pairs == gold["n_pairs"]
+    d = ctx.device_network(0)
+    hip = _hip_runtime()
+    ij = _d2h(hip, d["cell_ij"], 2 * g.n_cells, np.int32).reshape(-1, 2)
+    assert _digest(ij[:, 0], np.int64) == h["cell_i"] and _digest(ij[:, 1], np.int64) == h["cell_j"]
+    assert _digest(_d2h(hip, d["cell_ca"], g.n_cells, np.int32), np.int64) == h["cell_ca"]
+    assert _digest(_d2h(hip, d["cell_cb"], g.n_cells, np.int32), np.int64) == h["cell_cb"]
+    _say(f"[gpu]   network: {g.n_arcs} arcs, checking rows")
+    m = check_device_network(ctx, 0, gold["checksum"], gold["n_pairs"], csr_checker)
+    assert m == g.n_arcs
 
 
 def test_tuning_and_launch_groups(orc, ctx):
@@ -267,9 +340,7 @@ def test_tuning_and_launch_groups(orc, ctx):
         got = ctx.approx_batch(As, Bs, eps=0.2, flags=w1.KEEP_NETWORK)
         for a, b in zip(ref, got):
             assert (a.w1, a.n_pairs, a.n_cells, a.flow_cost) == (b.w1, b.n_pairs, b.n_cells, b.flow_cost)
-            pa = _sorted_pairs(a.network["pair_u"], a.network["pair_v"], a.network["pair_cost"])
-            pb = _sorted_pairs(b.network["pair_u"], b.network["pair_v"], b.network["pair_cost"])
-            assert all(np.array_equal(x, y) for x, y in zip(pa, pb))
+            assert same_network(a, b)
         # the large-item setting used for counting at large separations
         ctx.tuning = dict(stack_depth=32, work_cap=65536, chunk_items=64, blocks_per_cu=2,
                           max_points_per_launch=1 << 22)
@@ -290,9 +361,9 @@ def test_tuning_and_launch_groups(orc, ctx):
 
 def test_compact_records_and_wide_extent(orc, ctx):
     """The packed split records (28-bit child boxes) and the full child
-    records give the same pairs in the same order; a pair whose grid extent
-    exceeds 2^28 cells, where the packed records cannot be used, still
-    matches the oracle stage by stage."""
+    records give the same network; a pair whose grid extent exceeds 2^28
+    cells, where the packed records cannot be used, still matches the oracle
+    stage by stage."""
     import paper_2110_14734_amd as w1
 
     _say("[gpu] compact and full traversal records")
@@ -307,8 +378,7 @@ def test_compact_records_and_wide_extent(orc, ctx):
         full = ctx.approx_batch(As, Bs, eps=0.1, flags=w1.KEEP_NETWORK)
         for a, b in zip(ref, full):
             assert (a.w1, a.n_pairs, a.flow_cost) == (b.w1, b.n_pairs, b.flow_cost)
-            for key in ("pair_u", "pair_v", "pair_cost"):
-                assert np.array_equal(a.network[key], b.network[key])
+            assert same_network(a, b)
     finally:
         ctx.tuning = t0
     # a cluster near the origin and two points near 19000: the grid is
