@@ -33,6 +33,7 @@ ORC_COUNT_ONLY = 2
 ORC_NO_FLOW = 4
 ORC_KEEP_PAIR_NODES = 8
 ORC_SKIP_RWMD = 16
+ORC_PRUNE = 32
 
 _K = dict(STATUS=0, NA=1, NB=2, N=3, NLOC=4, S=5, E=6, M0=7, NCELLS=8, NNODES=9, ROOT=10,
           NPAIRS=11, FLOW=12, SA=13, SB=14, FA=15, FB=16, CHK1=17, CHK2=18)
@@ -178,14 +179,15 @@ def run(A, B, eps: float = 0.1, kappa: float = 0.1, s_override: int = 0, flags: 
         L_.orc_free(h)
 
 
-def network(A, B, eps=0.1, kappa=0.1, s_override=0):
-    """Sparse transshipment network of the oracle: (src, dst, cost, supply, result)."""
+def network(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False):
+    """Sparse transshipment network of the oracle: (src, dst, cost, supply).
+    prune: leave out the diagonal-dominated WSPD pairs (O7')."""
     L_ = lib()
     A64, B64 = _as_f64(A), _as_f64(B)
     h = L_.orc_new()
     try:
         st = L_.orc_run(h, _ptr(A64), A64.shape[0], _ptr(B64), B64.shape[0], float(eps), float(kappa),
-                        int(s_override), ORC_NO_FLOW, 0.0)
+                        int(s_override), ORC_NO_FLOW | (ORC_PRUNE if prune else 0), 0.0)
         if st != 0:
             raise RuntimeError(f"oracle status {st}")
         m = int(L_.orc_network(h, None, None, None, None))
@@ -198,15 +200,16 @@ def network(A, B, eps=0.1, kappa=0.1, s_override=0):
         L_.orc_free(h)
 
 
-def csr(A, B, eps=0.1, kappa=0.1, s_override=0):
+def csr(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False):
     """The oracle's network in compressed sparse row form (O8): arcs sorted by
-    (tail, head).  Returns dict(row_ptr, col, cost, supply, n_cells)."""
+    (tail, head).  Returns dict(row_ptr, col, cost, supply, n_cells).
+    prune: leave out the diagonal-dominated WSPD pairs (O7')."""
     L_ = lib()
     A64, B64 = _as_f64(A), _as_f64(B)
     h = L_.orc_new()
     try:
         st = L_.orc_run(h, _ptr(A64), A64.shape[0], _ptr(B64), B64.shape[0], float(eps), float(kappa),
-                        int(s_override), ORC_NO_FLOW, 0.0)
+                        int(s_override), ORC_NO_FLOW | (ORC_PRUNE if prune else 0), 0.0)
         if st != 0:
             raise RuntimeError(f"oracle status {st}")
         N = int(L_.orc_i64(h, _K["NCELLS"]))

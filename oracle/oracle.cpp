@@ -90,6 +90,7 @@ struct Oracle {
   // O7
   bool count_only = false;
   bool keep_nodes = false;
+  bool prune = false;       // diagonal-dominance pruning (O7')
   int64_t n_pairs = 0;
   uint64_t chk1 = 0, chk2 = 0;
   std::vector<int64_t> pu, pv, pc, pnu, pnv;
@@ -396,9 +397,36 @@ void emit(Oracle& o, int64_t U, int64_t V) {
   }
 }
 
+// O7' (optional, not in the paper): diagonal-dominance pruning.  Costs are
+// in units of g/2: a cell's arc to the diagonal costs j - i, a WSPD arc
+// between cells p and q costs 2 max(|di|, |dj|) >= 2 dist(U, V) for p in U,
+// q in V, and j - i <= maxj - mini over a box.  When
+//   2 dist(U, V) >= (U.maxj - U.mini) + (V.maxj - V.mini)
+// every arc the pair (U, V) or any of its descendant pairs would add costs at
+// least the two representatives' diagonal costs together, c(p,q) >= dd(p) +
+// dd(q).  Such arcs can be left out without changing the optimal flow cost
+// F*: take an optimal flow, decompose it into paths, and send every path that
+// uses such an arc from its source cell straight to the A-diagonal node and
+// from the B-diagonal node straight to its sink cell (lowering the flow on the
+// zero-cost B->A diagonal arc by as much, which carries at least the total
+// cell-to-cell flow).  The diagonal cost is 1-Lipschitz along cell arcs
+// (|d(j-i)| <= 2 max(|di|,|dj|)), so neither replacement costs more.  The
+// test is monotone (children have smaller boxes and larger gaps), so the
+// whole recursion below a dominated pair is skipped, and the pairs kept are
+// exactly the s-WSPD pairs whose own boxes are not dominated.
+// Pins: F* equal with and without pruning over many seeds; the pruned pair
+// set equals the unpruned one filtered by the box test.
+bool dominated(const Node& a, const Node& b) {
+  int64_t gi = std::max(a.mini - b.maxi, b.mini - a.maxi);
+  int64_t gj = std::max(a.minj - b.maxj, b.minj - a.maxj);
+  int64_t dist = std::max<int64_t>(0, std::max(gi, gj));
+  return 2 * dist >= (a.maxj - a.mini) + (b.maxj - b.mini);
+}
+
 void visit(Oracle& o, int64_t U, int64_t V) {
   const Node& a = o.nodes[U];
   const Node& b = o.nodes[V];
+  if (o.prune && dominated(a, b)) return;
   int64_t gi = std::max(a.mini - b.maxi, b.mini - a.maxi);
   int64_t gj = std::max(a.minj - b.maxj, b.minj - a.maxj);
   int64_t dist = std::max<int64_t>(0, std::max(gi, gj));
@@ -588,6 +616,7 @@ enum {
   ORC_NO_FLOW = 4,
   ORC_KEEP_PAIR_NODES = 8,
   ORC_SKIP_RWMD = 16,   // take L from the caller (for timing later stages alone)
+  ORC_PRUNE = 32,       // diagonal-dominance pruning of the WSPD pairs (O7')
 };
 
 void* orc_new(void) { return new Oracle(); }
@@ -600,6 +629,7 @@ int orc_run(void* p, const double* A, int64_t nA, const double* B, int64_t nB, d
   if (!(eps > 0.0 && eps <= 1.0) || !(kappa > 0.0 && kappa < 0.5) || nA < 0 || nB < 0) return o.status = ORC_EINVAL;
   o.count_only = (flags & ORC_COUNT_ONLY) != 0;
   o.keep_nodes = (flags & ORC_KEEP_PAIR_NODES) != 0;
+  o.prune = (flags & ORC_PRUNE) != 0;
   int st = condense0(o, A, nA, B, nB);
   if (st) return o.status = st;
   o.eps = eps;

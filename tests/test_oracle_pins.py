@@ -488,3 +488,74 @@ def test_one_sided_and_invalid(orc):
     assert orc.run(np.array([[np.nan, 0.5]]), A).status == -1
     diag = np.array([[0.3, 0.3], [0.7, 0.7]])
     assert orc.run(np.concatenate([A, diag]), np.zeros((0, 2))).W1 == r.W1
+
+
+# ------------------------------------------------- diagonal-dominance pruning --
+def _dominated(nodes, U, V):
+    """Box test of O7': 2 dist(U, V) >= (U.maxj - U.mini) + (V.maxj - V.mini),
+    all in grid cells (node rows: lo, hi, left, right, split, mini, minj,
+    maxi, maxj, diam)."""
+    a, b = nodes[U], nodes[V]
+    gi = max(a[5] - b[7], b[5] - a[7])
+    gj = max(a[6] - b[8], b[6] - a[8])
+    dist = max(0, gi, gj)
+    return 2 * dist >= (a[8] - a[5]) + (b[8] - b[5])
+
+
+@pytest.mark.parametrize("kind", ["exp", "mixture", "pareto", "integer", "one_sided"])
+def test_prune_keeps_optimum(orc, kind):
+    # Leaving out the diagonal-dominated pairs never changes F* (the rerouting
+    # argument of O7'), so W1 and W1_paper are identical; the network shrinks.
+    for seed in range(6):
+        if kind == "exp":
+            A, B = pdsynth.exp_pd(60 + 7 * seed, 900 + seed), pdsynth.exp_pd(50 + 5 * seed, 950 + seed)
+        elif kind == "mixture":
+            A, B = pdsynth.mixture_pd(300, 910 + seed), pdsynth.mixture_pd(280, 960 + seed)
+        elif kind == "pareto":
+            A, B = pdsynth.pareto_pd(200, 920 + seed), pdsynth.pareto_pd(220, 970 + seed)
+        elif kind == "integer":
+            A, B = pdsynth.integer_pd(40, 930 + seed), pdsynth.integer_pd(35, 980 + seed)
+        else:
+            A, B = pdsynth.exp_pd(70, 940 + seed), np.zeros((0, 2))
+        for eps, s in ((0.1, 0), (0.2, 0), (0.2, 3)):
+            full = orc.run(A, B, eps=eps, s_override=s, fetch=False)
+            pr = orc.run(A, B, eps=eps, s_override=s, flags=orc.ORC_PRUNE, fetch=False)
+            assert full.status == 0 and pr.status == 0
+            assert pr.flow == full.flow and pr.W1 == full.W1 and pr.W1_paper == full.W1_paper
+            assert pr.n_pairs <= full.n_pairs
+
+
+def test_prune_pair_set_is_filtered_wspd(orc):
+    # The recursion below a dominated pair is cut, and the test is monotone,
+    # so the pruned pairs are exactly the s-WSPD pairs whose own boxes pass.
+    for seed in range(4):
+        A = pdsynth.exp_pd(90, 990 + seed, mean_pers=0.15)
+        B = pdsynth.exp_pd(80, 995 + seed, mean_pers=0.15)
+        fl = orc.ORC_KEEP_PAIR_NODES | orc.ORC_NO_FLOW
+        full = orc.run(A, B, eps=0.2, flags=fl)
+        pr = orc.run(A, B, eps=0.2, flags=fl | orc.ORC_PRUNE)
+        keep = [k for k in range(full.n_pairs)
+                if not _dominated(full.nodes, full.pairs["nu"][k], full.pairs["nv"][k])]
+        want = sorted(zip(full.pairs["u"][keep].tolist(), full.pairs["v"][keep].tolist(),
+                          full.pairs["c"][keep].tolist()))
+        got = sorted(zip(pr.pairs["u"].tolist(), pr.pairs["v"].tolist(), pr.pairs["c"].tolist()))
+        assert got == want and 0 < len(got) < full.n_pairs
+        # every arc left out costs at least its two diagonal arcs together
+        ci, cj = full.cells["i"], full.cells["j"]
+        drop = np.setdiff1d(np.arange(full.n_pairs), keep)
+        u, v, c = full.pairs["u"][drop], full.pairs["v"][drop], full.pairs["c"][drop]
+        assert (c >= (cj[u] - ci[u]) + (cj[v] - ci[v])).all()
+
+
+def test_prune_closed_forms(orc):
+    # One point each, far apart relative to their persistence: the optimum
+    # sends both to the diagonal, the only WSPD pair is dominated and left
+    # out, and W1 is unchanged.  Close together: the pair stays.
+    p = np.array([[0.0, 0.25]])
+    for q, kept in ((np.array([[4.0, 4.5]]), 0), (np.array([[0.01, 0.27]]), 1)):
+        full = orc.run(p, q, eps=0.1)
+        pr = orc.run(p, q, eps=0.1, flags=orc.ORC_PRUNE)
+        assert full.n_pairs == 1 and pr.n_pairs == kept
+        assert pr.W1 == full.W1
+        ex = orc.exact_w1(p, q)
+        assert full.L <= ex <= pr.W1 <= 1.1 * ex
