@@ -77,6 +77,19 @@ extern "C" {
 #define W1_NO_FLOW 4u      /* build the network on the device, skip the flow */
 #define W1_KEEP_NETWORK 8u /* copy the network into the result (host)       */
 #define W1_KEEP_STAGES 16u /* copy stage intermediates into the result      */
+#define W1_PRUNE 32u       /* leave out diagonal-dominated WSPD pairs: a    */
+                           /* node pair U, V whose box gap (in grid cells)  */
+                           /* is at least half of (U.maxj - U.mini) +       */
+                           /* (V.maxj - V.mini), with everything below it   */
+                           /* in the WSPD recursion.  Each such arc costs   */
+                           /* at least its two ends' diagonal arcs, so the  */
+                           /* optimal flow cost F*, w1 and w1_paper are     */
+                           /* unchanged and the network is smaller (not in  */
+                           /* the paper; follows from the matching costs of */
+                           /* Sec. 4.3: the distance to the diagonal is     */
+                           /* 1-Lipschitz, and the zero-cost diagonal arc   */
+                           /* carries at least the cell-to-cell flow).      */
+                           /* n_pairs then counts the pairs kept.           */
 
 typedef struct w1_ctx w1_ctx;
 

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libw1approx.so")
 W1_OK, W1_EINVAL, W1_ERANGE, W1_ENOMEM, W1_EHIP, W1_EOVERFLOW, W1_ENODEV = 0, -1, -2, -3, -4, -5, -6
 W1_OPTIMAL, W1_STALLED = 0, 1
 W1_F32, W1_F64 = 0, 1
-INPUT_DEVICE, COUNT_ONLY, NO_FLOW, KEEP_NETWORK, KEEP_STAGES = 1, 2, 4, 8, 16
+INPUT_DEVICE, COUNT_ONLY, NO_FLOW, KEEP_NETWORK, KEEP_STAGES, PRUNE = 1, 2, 4, 8, 16, 32
 T_NAMES = ("condense0", "rwmd", "grid", "tree", "wspd", "arcs", "d2h", "flow")
 
 

@@ -182,6 +182,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
   }
   if (total >= (int64_t(1) << 31) || K >= (int64_t(1) << 30)) return W1_EINVAL;
   const int s = o.s > 0 ? o.s : separation(o.eps, o.kappa);
+  const bool prune = (o.flags & W1_PRUNE) != 0;
   const double eps_c = o.kappa * o.eps;
   for (int i = 0; i < 8; ++i) record(c, i);
   record(c, 0);
@@ -423,7 +424,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       if (!worklist_round_fits(f)) throw StageError{W1_EOVERFLOW};
       uint64_t* cnt = need<uint64_t>(c, c.icnt, f);
       uint64_t* pos = need<uint64_t>(c, c.ipos, f);
-      launch_wspd_classify(T, F, f, s, tun, (const int32_t*)c.pcap.p, cnt, st);
+      launch_wspd_classify(T, F, f, s, tun, (const int32_t*)c.pcap.p, prune, cnt, st);
       scan_u64(cnt, pos, f, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(f, 8)), st);
       uint64_t* slot = need<uint64_t>(c, c.small, 64);
       launch_count_total64(cnt, pos, f, slot, st);
@@ -488,7 +489,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       uint64_t* coff = need<uint64_t>(c, c.coff, nch);
       fill_u32(xc, 0, 8, st);
       check(c, hipEventRecord(c.kev[1], st));
-      launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr,
+      launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr, prune,
                        c.num_cus, st);
       check(c, hipGetLastError());
       check(c, hipEventRecord(c.kev[2], st));
@@ -506,7 +507,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         uint32_t* pout = need<uint32_t>(c, c.pu, std::max<int64_t>(3 * Ptot, 2 * Ptot + 2 * N + K));
         fill_u32(xc, 0, 8, st);
         check(c, hipEventRecord(c.kev[3], st));
-        launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr,
+        launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr, prune,
                          c.num_cus, st);
         check(c, hipGetLastError());
         emitted = true;

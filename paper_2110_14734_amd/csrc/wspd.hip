@@ -47,6 +47,25 @@ __device__ inline bool separated(int4 a, int4 b, int s) {
   const int dist = max(0, max(gi, gj));
   return (int64_t)dist >= (int64_t)s * (int64_t)max(box_diam(a), box_diam(b));
 }
+// Diagonal dominance of a node pair (optional pruning, not in the paper).
+// Costs in units of g/2: an arc between cells p and q costs 2 max(|di|,|dj|)
+// >= 2 dist(box U, box V), and a cell's arc to the diagonal costs j - i <=
+// max j - min i of its box.  When 2 dist >= (U.maxj - U.mini) + (V.maxj -
+// V.mini), every arc of the pair or of any pair below it in the recursion
+// costs at least its two ends' diagonal arcs together, and leaving all of
+// them out keeps the optimal flow cost: a flow path through such an arc can
+// go from its source cell to the A-diagonal node and from the B-diagonal
+// node to its sink cell instead (the distance to the diagonal is 1-Lipschitz
+// along cell arcs), taking the flow off the zero-cost B->A diagonal arc.
+// The test only gets truer further down (larger gaps, smaller boxes), so the
+// recursion below a dominated pair is skipped.  Coordinates are below 2^30,
+// so the sums fit in 32 unsigned bits.
+__device__ inline bool dominated(int4 a, int4 b) {
+  const int gi = max(a.x - b.z, b.x - a.z);
+  const int gj = max(a.y - b.w, b.y - a.w);
+  const uint32_t dist = (uint32_t)max(0, max(gi, gj));
+  return 2u * dist >= (uint32_t)(a.w - a.x) + (uint32_t)(b.w - b.x);
+}
 
 __global__ void k_roots_flags(TreeView T, uint32_t* __restrict__ flag) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,16 +83,22 @@ __global__ void k_roots_fill(TreeView T, const uint32_t* __restrict__ flag, cons
 }
 
 // Item kinds of an expansion round: kept (final or separated) -> low word
-// count 1; expanded -> high word count 2.
+// count 1; expanded -> high word count 2; dropped (diagonal-dominated, with
+// pruning on) -> 0.
 __global__ void k_classify(TreeView T, const int2* __restrict__ items, int64_t f, int s, int stack_depth,
-                           const int32_t* __restrict__ pair_cap, uint64_t* __restrict__ cnt) {
+                           const int32_t* __restrict__ pair_cap, int prune, uint64_t* __restrict__ cnt) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= f) return;
   const int2 it = items[x];
+  const int4 bu = node_box(T, it.x), bv = node_box(T, it.y);
+  if (prune && dominated(bu, bv)) {
+    cnt[x] = 0;
+    return;
+  }
   const int64_t work_cap = pair_cap[T.cpair[node_rep(T, it.x)]];
   const bool small = node_height(T, it.x) + node_height(T, it.y) <= stack_depth - 1 &&
                      node_size(T, it.x) * node_size(T, it.y) <= work_cap;
-  const bool keep = small || separated(node_box(T, it.x), node_box(T, it.y), s);
+  const bool keep = small || separated(bu, bv, s);
   cnt[x] = keep ? 1ull : (2ull << 32);
 }
 
@@ -84,6 +109,7 @@ __global__ void k_scatter(TreeView T, const int2* __restrict__ items, int64_t f,
   if (x >= f) return;
   const int2 it = items[x];
   const uint64_t p = pos[x];
+  if (cnt[x] == 0) return;  // dropped
   if (cnt[x] == 1ull) {
     out_items[out_base + (int64_t)(uint32_t)p] = it;
     return;
@@ -300,7 +326,7 @@ __device__ inline uint32_t lanes_set_below(uint64_t m, uint32_t add) {
 // written as 12-byte records at the wave cursor in (slot, lane) order, so the
 // order depends only on the chunk.  Loop control lives in wave-uniform
 // scalars.
-template <bool EMIT, bool COMPACT>
+template <bool EMIT, bool COMPACT, bool PRUNE>
 __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const uint4* __restrict__ SR,
                                               const int2* __restrict__ items,
                                               const int32_t* __restrict__ chunk_first, const int32_t* __restrict__ chunk_end,
@@ -396,9 +422,13 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
             m1 = make_emit(C1.aux, oa, orient);
             m2 = make_emit(C2.aux, oa, orient);
           }
-          e1 = s1;
-          e2 = s2;
-          if (!s1 && !s2) {  // (C2, O) goes on the stack, split rule applied
+          // a child pair is done when separated (output unless dominated) or
+          // dominated (pruning: no output, nothing below it)
+          const bool x1 = PRUNE && dominated(C1.box, ob), x2 = PRUNE && dominated(C2.box, ob);
+          e1 = s1 && !x1;
+          e2 = s2 && !x2;
+          const bool r1 = s1 || x1, r2 = s2 || x2;
+          if (!r1 && !r2) {  // (C2, O) goes on the stack, split rule applied
             const bool split2 = orient ? d2 > od : d2 >= od;
             const int c2 = (int)(c1 + 1);
             const int2 e = split2 ? make_int2(c2 | (orient ? INT32_MIN : 0), oid)
@@ -410,8 +440,8 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
               overflow = true;
             }
           }
-          if (!s1 || !s2) {  // the lane's next pair: (first non-separated child, O)
-            const bool first = !s1;
+          if (!r1 || !r2) {  // the lane's next pair: (first child not done, O)
+            const bool first = !r1;
             const int dn = first ? d1 : d2;
             const int4 na = first ? C1.aux : C2.aux;
             if (orient ? dn > od : dn >= od) {
@@ -484,8 +514,8 @@ void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint3
   LAUNCH(k_roots_fill, T.N - 1, T, flag, pos, items);
 }
 void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s, const WspdTuning& tun,
-                          const int32_t* pair_cap, uint64_t* cnt, hipStream_t st) {
-  LAUNCH(k_classify, f, T, items, f, s, tun.stack_depth, pair_cap, cnt);
+                          const int32_t* pair_cap, bool prune, uint64_t* cnt, hipStream_t st) {
+  LAUNCH(k_classify, f, T, items, f, s, tun.stack_depth, pair_cap, prune ? 1 : 0, cnt);
 }
 void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const uint64_t* cnt, const uint64_t* pos,
                          int2* out_items, int64_t out_base, int2* next, hipStream_t st) {
@@ -508,7 +538,7 @@ void launch_chunks(const int32_t* cstart, int64_t K, const int64_t* item_start, 
 void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
-                      uint32_t* out, int32_t* err, int num_cus, hipStream_t st) {
+                      uint32_t* out, int32_t* err, bool prune, int num_cus, hipStream_t st) {
   if (nchunks <= 0) return;
   int64_t grid = (int64_t)num_cus * tun.blocks_per_cu;
   grid = ((grid + 7) / 8) * 8;
@@ -518,7 +548,9 @@ void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, con
   const int64_t step_cap = (int64_t)tun.chunk_items * (2 * (int64_t)tun.work_cap + 2) + 1024;
   // the emit pass always reads the children's records (the packed split
   // records serve the count pass)
-  auto k = emit ? k_wspd<true, false> : (split_recs ? k_wspd<false, true> : k_wspd<false, false>);
+  auto k = prune ? (emit ? k_wspd<true, false, true> : (split_recs ? k_wspd<false, true, true> : k_wspd<false, false, true>))
+                 : (emit ? k_wspd<true, false, false>
+                         : (split_recs ? k_wspd<false, true, false> : k_wspd<false, false, false>));
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds, st, T.inode, split_recs, items, chunk_first, chunk_end,
                      xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, out, err);
 }

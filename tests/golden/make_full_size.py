@@ -1,7 +1,8 @@
 """Writes c2_full.json: the CPU oracle's results on the 200k + 200k-point
 mixture pair (diagram A seed 0, diagram B seed 1, FP32; 80% persistence
 LogNormal(-4, 1), 20% U[0.1, 1]) at eps 0.2, 0.1 and 0.05, for the
-full-size GPU parity test.  It calls only oracle/ (count-only runs: the WSPD
+full-size GPU parity test, without and with diagonal-dominance pruning.  It
+calls only oracle/ (count-only runs: the WSPD
 pair set enters through the oracle's order-independent pair checksum), so
 the stored values never come from the GPU library.  Per-location and
 per-cell arrays are stored as SHA-256 digests of their little-endian bytes
@@ -54,6 +55,12 @@ def main():
             },
             "oracle_seconds": round(time.time() - t0, 1),
         }
+        # the same pair with diagonal-dominance pruning (O7'): pairs kept
+        t0 = time.time()
+        rp = oracle.run(A, B, eps=eps, flags=oracle.ORC_COUNT_ONLY | oracle.ORC_PRUNE, fetch=False)
+        assert rp.status == 0
+        out["eps"][str(eps)]["pruned"] = {"n_pairs": rp.n_pairs, "checksum": [rp.checksum[0], rp.checksum[1]],
+                                          "oracle_seconds": round(time.time() - t0, 1)}
         print(eps, out["eps"][str(eps)]["n_pairs"], out["eps"][str(eps)]["oracle_seconds"], flush=True)
     with open(os.path.join(HERE, "c2_full.json"), "w") as f:
         json.dump(out, f, indent=1)

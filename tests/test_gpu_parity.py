@@ -57,12 +57,13 @@ def same_network(a, b):
     return all(np.array_equal(a.network.get(f, np.zeros(0)), b.network.get(f, np.zeros(0))) for f in NET_KEYS)
 
 
-def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True):
+def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True, prune=False):
     import paper_2110_14734_amd as w1
 
-    flags = w1.KEEP_NETWORK | w1.KEEP_STAGES | (0 if flow else w1.NO_FLOW)
+    flags = w1.KEEP_NETWORK | w1.KEEP_STAGES | (0 if flow else w1.NO_FLOW) | (w1.PRUNE if prune else 0)
     g = ctx.approx(A, B, eps=eps, s_override=s_override, flags=flags)
-    r = orc.run(A, B, eps=eps, s_override=s_override, flags=0 if flow else orc.ORC_NO_FLOW)
+    oflags = (0 if flow else orc.ORC_NO_FLOW) | (orc.ORC_PRUNE if prune else 0)
+    r = orc.run(A, B, eps=eps, s_override=s_override, flags=oflags)
     assert r.status == 0 and g.status == 0
     # a0: net 0-condensation
     assert (g.n_a, g.n_b, g.n_points) == (r.nA, r.nB, r.n)
@@ -91,7 +92,7 @@ def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True):
     # a4 + a5: the WSPD pairs and the network, compared as the sorted rows
     # element by element (no host-side sorting of the library's output)
     assert g.n_pairs == r.n_pairs
-    check_csr(net, orc.csr(A, B, eps=eps, s_override=s_override))
+    check_csr(net, orc.csr(A, B, eps=eps, s_override=s_override, prune=prune))
     # flow and W1
     if flow:
         assert g.flow_cost == r.flow
@@ -114,6 +115,40 @@ def test_stage_parity(orc, ctx, name, make, eps):
     _say(f"[gpu] stage parity {name}")
     A, B = make()
     compare(orc, ctx, A, B, eps=eps)
+
+
+@pytest.mark.parametrize("name,make,eps", CASES, ids=[c[0] for c in CASES])
+def test_prune_parity(orc, ctx, name, make, eps):
+    """Diagonal-dominance pruning: the kept pairs and the network equal the
+    oracle's pruned network row for row, and F* (hence W1) equals the
+    unpruned optimum."""
+    _say(f"[gpu] prune parity {name}")
+    A, B = make()
+    g, r = compare(orc, ctx, A, B, eps=eps, prune=True)
+    full = ctx.approx(A, B, eps=eps)
+    assert g.flow_cost == full.flow_cost and g.w1 == full.w1 and g.n_pairs <= full.n_pairs
+
+
+def test_prune_batch_and_count_only(orc, ctx):
+    """Pruning in the batched form: every pair's network equals the oracle's
+    pruned rows, the count-only pass counts the same kept pairs, and the
+    optimum equals the unpruned batch's."""
+    _say("[gpu] prune batch")
+    import paper_2110_14734_amd as w1
+
+    sizes = pdsynth.batch_sizes(16, 31, lo=20, hi=2500)
+    As = [pdsynth.mixture_pd(int(sizes[i]), 5000 + 2 * i) for i in range(8)]
+    Bs = [pdsynth.mixture_pd(int(sizes[8 + i]), 5001 + 2 * i) for i in range(8)]
+    As[2] = np.zeros((0, 2), np.float32)
+    pr = ctx.approx_batch(As, Bs, eps=0.1, flags=w1.KEEP_NETWORK | w1.PRUNE)
+    full = ctx.approx_batch(As, Bs, eps=0.1)
+    cnt = ctx.approx_batch(As, Bs, eps=0.1, flags=w1.COUNT_ONLY | w1.PRUNE)
+    for i in range(8):
+        r = orc.run(As[i], Bs[i], eps=0.1, flags=orc.ORC_PRUNE | orc.ORC_NO_FLOW)
+        assert pr[i].n_pairs == r.n_pairs == cnt[i].n_pairs
+        assert pr[i].flow_cost == full[i].flow_cost and pr[i].w1 == full[i].w1
+        if r.n:
+            check_csr(pr[i].network, orc.csr(As[i], Bs[i], eps=0.1, prune=True))
 
 
 @pytest.mark.parametrize("s_override", [1, 2, 3, 6, 12])
@@ -284,24 +319,26 @@ def check_device_network(ctx, k, chk, n_pairs, checker, chunk_arcs=1 << 28):
     return m
 
 
-@pytest.mark.parametrize("eps", [0.1, 0.05])
-def test_full_size_config2(ctx, csr_checker, eps):
+@pytest.mark.parametrize("eps,prune", [(0.1, False), (0.05, False), (0.1, True)])
+def test_full_size_config2(ctx, csr_checker, eps, prune):
     """200k + 200k FP32 points (mixture) at the benchmark's eps 0.1 and at
     0.05, checked against the oracle's stored results (written by
     tests/golden/make_full_size.py, which calls only the oracle): every
     location and its RWMD cost, L and its fixed-point sums, every cell, the
     pair count, and the device-built network row by row -- sorted heads,
     costs from the cells, diagonal rows, and both orientations of the cell
-    arcs against the oracle's pair checksum."""
+    arcs against the oracle's pair checksum.  With pruning, the kept pairs
+    against the oracle's pruned count and checksum."""
     import json
 
     import paper_2110_14734_amd as w1
 
     with open(os.path.join(GOLD, "c2_full.json")) as f:
         gold = json.load(f)["eps"][str(eps)]
-    _say(f"[gpu] full-size mixture 200k+200k eps {eps}")
+    _say(f"[gpu] full-size mixture 200k+200k eps {eps} prune {prune}")
     A, B = pdsynth.mixture_pd(200_000, 0), pdsynth.mixture_pd(200_000, 1)
-    g = ctx.approx(A, B, eps=eps, flags=w1.KEEP_STAGES | w1.NO_FLOW)
+    g = ctx.approx(A, B, eps=eps, flags=w1.KEEP_STAGES | w1.NO_FLOW | (w1.PRUNE if prune else 0))
+    pairs = gold["pruned"] if prune else gold
     assert (g.n_a, g.n_b, g.n_points, g.s, g.grid_exp) == (gold["nA"], gold["nB"], gold["n"], gold["s"], gold["e"])
     assert g.lower_bound == float.fromhex(gold["L"])
     st = g.stages
@@ -311,7 +348,7 @@ def test_full_size_config2(ctx, csr_checker, eps):
     assert g.n_locations == gold["n_locations"]
     for key, dt in (("loc_b", np.float64), ("loc_d", np.float64), ("loc_w", np.int64), ("loc_t", np.float64)):
         assert _digest(st[key], dt) == h[key], key
-    assert g.n_cells == gold["n_cells"] and g.n_pairs == gold["n_pairs"]
+    assert g.n_cells == gold["n_cells"] and g.n_pairs == pairs["n_pairs"]
     d = ctx.device_network(0)
     hip = _hip_runtime()
     ij = _d2h(hip, d["cell_ij"], 2 * g.n_cells, np.int32).reshape(-1, 2)
@@ -319,7 +356,7 @@ def test_full_size_config2(ctx, csr_checker, eps):
     assert _digest(_d2h(hip, d["cell_ca"], g.n_cells, np.int32), np.int64) == h["cell_ca"]
     assert _digest(_d2h(hip, d["cell_cb"], g.n_cells, np.int32), np.int64) == h["cell_cb"]
     _say(f"[gpu]   network: {g.n_arcs} arcs, checking rows")
-    m = check_device_network(ctx, 0, gold["checksum"], gold["n_pairs"], csr_checker)
+    m = check_device_network(ctx, 0, pairs["checksum"], pairs["n_pairs"], csr_checker)
     assert m == g.n_arcs
 
 
