@@ -214,6 +214,22 @@ int w1_approx_batch(w1_ctx *ctx, const w1_pd *a, const w1_pd *b, int64_t k, cons
 int w1_rwmd(w1_ctx *ctx, const w1_pd *a, const w1_pd *b, int64_t k, uint32_t flags, void *stream,
             double *L_out);
 
+/* w1_rwmd for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments and results as w1_rwmd (flags: only W1_INPUT_DEVICE), but the
+ * call makes no device allocation (no hipMalloc, hipFree or allocating
+ * library routine) and no host allocation: every device buffer it needs is a
+ * slice of one fixed scratch array of 128 MiB per GPU, which the library
+ * holds from the first context created on that GPU until the process ends.
+ * Limits: at most 2^19 points in all k pairs together and k <= 1024;
+ * larger inputs return W1_ERANGE before any work.  Calls on one GPU share
+ * that array (it keeps the last call's contents; the call clears what it
+ * needs), so calls that overlap in time on one GPU, from any contexts or
+ * streams, race and must not be issued.  The context's own buffers are not
+ * touched. */
+int w1_rwmd_noalloc(w1_ctx *ctx, const w1_pd *a, const w1_pd *b, int64_t k, uint32_t flags, void *stream,
+                    double *L_out);
+
 /* Device pointers to the network of pair k of the last call on ctx
  * (requires that call to have been made without W1_COUNT_ONLY, and pair k
  * to be in the call's last launch group, see w1_tuning). */

@@ -97,7 +97,7 @@ NN_MODES = {"rwmd": NN_RWMD, "surrogate": NN_SURROGATE, "exhaustive": NN_EXHAUST
 
 # Every symbol include/w1approx.h declares.
 EXPORTS = ("w1_ctx_create", "w1_ctx_destroy", "w1_ctx_hip_error", "w1_ctx_last_kernel_times", "w1_approx",
-           "w1_approx_batch", "w1_rwmd", "w1_device_network_get", "w1_flow_solve", "w1_separation_for_eps",
+           "w1_approx_batch", "w1_rwmd", "w1_rwmd_noalloc", "w1_device_network_get", "w1_flow_solve", "w1_separation_for_eps",
            "w1_ctx_get_tuning", "w1_ctx_set_tuning",
            "w1_result_free", "w1_strerror", "w1_surrogate_create", "w1_surrogate_destroy",
            "w1_surrogate_get_params", "w1_surrogate_set_params", "w1_surrogate_embed", "w1_surrogate_grad",
@@ -130,6 +130,8 @@ def lib():
                                       ctypes.POINTER(_Result)]
         L.w1_rwmd.argtypes = [vp, ctypes.POINTER(_PD), ctypes.POINTER(_PD), i64, ctypes.c_uint32, vp,
                               ctypes.POINTER(ctypes.c_double)]
+        L.w1_rwmd_noalloc.argtypes = [vp, ctypes.POINTER(_PD), ctypes.POINTER(_PD), i64, ctypes.c_uint32, vp,
+                                      ctypes.POINTER(ctypes.c_double)]
         L.w1_device_network_get.argtypes = [vp, i64, ctypes.POINTER(_DevNet)]
         L.w1_flow_solve.argtypes = [i64, i64, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp, vp, ctypes.POINTER(i64),
                                     ctypes.POINTER(ctypes.c_int32)]
@@ -358,8 +360,10 @@ class Context:
                     raise W1Error(r.status, "pair")
         return out
 
-    def rwmd(self, As, Bs) -> np.ndarray:
-        """RWMD lower bounds of k pairs (Alg. 1); NaN marks an invalid pair."""
+    def rwmd(self, As, Bs, noalloc=False) -> np.ndarray:
+        """RWMD lower bounds of k pairs (Alg. 1); NaN marks an invalid pair.
+        noalloc: through w1_rwmd_noalloc (no device allocation; at most 2^19
+        points in all pairs and 1024 pairs)."""
         k = len(As)
         keep = []
         pa, pb = (_PD * k)(), (_PD * k)()
@@ -370,10 +374,11 @@ class Context:
             devs.update((d1, d2))
         dev = devs.pop()
         out = np.zeros(k)
-        rc = lib().w1_rwmd(self._h, pa, pb, k, INPUT_DEVICE if dev else 0, _stream_of(dev),
-                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        fn = lib().w1_rwmd_noalloc if noalloc else lib().w1_rwmd
+        rc = fn(self._h, pa, pb, k, INPUT_DEVICE if dev else 0, _stream_of(dev),
+                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         if rc != 0:
-            raise W1Error(rc, "w1_rwmd")
+            raise W1Error(rc, "w1_rwmd_noalloc" if noalloc else "w1_rwmd")
         return out
 
     @property

@@ -22,6 +22,20 @@ struct StageError {
   int code;
 };
 
+// A fixed device region that replaces allocation for one call: while a
+// context has an arena, need() hands out consecutive 256-byte aligned slices
+// of it and never calls hipMalloc; running past its end is W1_EOVERFLOW.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+};
+
+// Limits of the allocation-free RWMD entry point (w1_rwmd_noalloc): its
+// device scratch, and the host tables it uses instead of growable ones.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+constexpr int64_t kNoAllocMaxPoints = int64_t(1) << 19;
+constexpr int64_t kNoAllocMaxPairs = 1024;
+
 // w1_ctx_last_kernel_times: work list, count pass, emit pass, pairs emitted,
 // then the network passes: bucket histogram, bucket scatter, row histogram,
 // row scatter (with the degree scan), row sort (with the diagonal rows).
@@ -61,6 +75,14 @@ struct Ctx {
   hipEvent_t ev[8];
   hipEvent_t kev[11];  // WSPD work list, count, emit; network passes
   double kms[kNumKernelTimes] = {0};
+  // allocation-free calls: the device's scratch region (set up when the
+  // context is created), the arena carved from it during such a call, the
+  // context's own buffers put aside meanwhile, and fixed host tables
+  void* scratch = nullptr;
+  Arena arena;
+  std::vector<DBuf> saved;
+  SegDesc seg_fixed[2 * kNoAllocMaxPairs];
+  int32_t err_fixed[kNoAllocMaxPairs];
 
   Ctx() {
     DBuf* list[] = {&stage, &orpart, &segs, &pb, &pd, &psd, &kw0, &kw1, &kw2, &kA, &kB, &vA, &vB, &head, &idx, &scantmp, &sorttmp,
@@ -71,6 +93,7 @@ struct Ctx {
                     &supply, &rstart, &bcnt, &bstart, &tfirst, &bcur, &rowcnt, &rowcur, &bflag, &bpos, &deg, &off,
                     &parc, &pairs};
     all.assign(std::begin(list), std::end(list));
+    saved.resize(all.size());
   }
 };
 
@@ -85,6 +108,14 @@ template <typename T>
 T* need(Ctx& c, DBuf& b, int64_t count) {
   size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
   bytes = (bytes + 255) & ~(size_t)255;
+  if (c.arena.base) {  // allocation-free call: every buffer is a slice of the arena
+    if (b.p && bytes <= b.cap) return (T*)b.p;
+    if (bytes > c.arena.cap - c.arena.off) throw StageError{W1_EOVERFLOW};
+    b.p = c.arena.base + c.arena.off;
+    b.cap = bytes;
+    c.arena.off += bytes;
+    return (T*)b.p;
+  }
   if (bytes > b.cap) {
     if (b.p) {
       check(c, hipStreamSynchronize(c.st));
@@ -116,7 +147,7 @@ T* grow_keep(Ctx& c, DBuf& b, int64_t count, int64_t keep) {
   T* np = need<T>(c, nb, count * 2);
   if (keep > 0) check(c, hipMemcpyAsync(np, b.p, (size_t)keep * sizeof(T), hipMemcpyDeviceToDevice, c.st));
   check(c, hipStreamSynchronize(c.st));
-  if (b.p) (void)hipFree(b.p);
+  if (b.p && !c.arena.base) (void)hipFree(b.p);
   b = nb;
   return np;
 }

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -189,8 +190,16 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
 
   // ---------------------------------------------------------------- a0 --
   const size_t esz = dtype == W1_F32 ? 4 : 8;
-  std::vector<SegDesc> segs;
-  segs.reserve((size_t)(2 * K));
+  // input segments; an allocation-free call uses the context's fixed table
+  std::vector<SegDesc> seg_vec;
+  SegDesc* segs = c.seg_fixed;
+  if (!c.arena.base) {
+    seg_vec.resize((size_t)(2 * K));
+    segs = seg_vec.data();
+  } else if (K > kNoAllocMaxPairs) {
+    return W1_ERANGE;
+  }
+  int64_t nseg = 0;
   char* staging = nullptr;
   if (!dev_in && total > 0) staging = need<char>(c, c.stage, total * 2 * (int64_t)esz);
   int64_t off = 0;
@@ -203,22 +212,22 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         check(c, hipMemcpyAsync(staging + off * 2 * esz, d.xy, (size_t)d.n * 2 * esz, hipMemcpyHostToDevice, st));
         ptr = staging + off * 2 * esz;
       }
-      segs.push_back(SegDesc{ptr, d.n, off, (int32_t)p, side});
+      segs[nseg++] = SegDesc{ptr, d.n, off, (int32_t)p, side};
       off += d.n;
     }
   setup_pairs(c, K);
   PairArrays& P = c.P;
   int64_t M = 0, N = 0;
   if (total > 0) {
-    SegDesc* dsegs = need<SegDesc>(c, c.segs, (int64_t)segs.size());
-    upload(c, dsegs, segs.data(), segs.size() * sizeof(SegDesc));
+    SegDesc* dsegs = need<SegDesc>(c, c.segs, nseg);
+    upload(c, dsegs, segs, (size_t)nseg * sizeof(SegDesc));
     double* pb = need<double>(c, c.pb, total);
     double* pd = need<double>(c, c.pd, total);
     uint32_t* psd = need<uint32_t>(c, c.psd, total);
     uint64_t* kw0 = need<uint64_t>(c, c.kw0, total);
     uint64_t* kw1 = need<uint64_t>(c, c.kw1, total);
     uint64_t* kw2 = need<uint64_t>(c, c.kw2, total);
-    launch_load(dsegs, (int)segs.size(), total, dtype, pb, pd, psd, kw0, kw1, kw2, P.err, st);
+    launch_load(dsegs, (int)nseg, total, dtype, pb, pd, psd, kw0, kw1, kw2, P.err, st);
     check(c, hipGetLastError());
     uint32_t* perm;
     uint64_t* kw2s;
@@ -287,10 +296,17 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     check(c, hipGetLastError());
   }
   record(c, 2);
-  if (L_only) {
-    std::vector<double> L = fetch_pairs(c, P.L, K);
-    std::vector<int32_t> er = fetch_pairs(c, P.err, K);
-    for (int64_t p = 0; p < K; ++p) L_only[p] = er[(size_t)p] == -1 ? NAN : L[(size_t)p];
+  if (L_only) {  // straight into the caller's array, no host buffers
+    int32_t* er = c.err_fixed;
+    std::vector<int32_t> er_vec;
+    if (K > kNoAllocMaxPairs) {
+      er_vec.resize((size_t)K);
+      er = er_vec.data();
+    }
+    readback(c, P.L, L_only, K);
+    readback(c, P.err, er, K);
+    for (int64_t p = 0; p < K; ++p)
+      if (er[p] == -1) L_only[p] = NAN;
     return W1_OK;
   }
 
@@ -894,6 +910,39 @@ int entry(Ctx* c, const w1_pd* a, const w1_pd* b, int64_t K, const w1_params* pa
 }  // namespace
 }  // namespace w1
 
+// ------------------------------------------------ allocation-free scratch --
+// Device scratch of the allocation-free RWMD entry point: one fixed array per
+// GPU, held for the life of the process.  In host code `scratch` names only a
+// host-side stand-in; its device address comes from hipGetSymbolAddress, once
+// per device with that device current, and only that address is used.
+static __device__ __align__(256) char scratch[w1::kNoAllocScratchBytes];
+
+namespace w1 {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current).
+int scratch_setup(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return W1_ENODEV;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return W1_EHIP;
+    }
+    g_scratch_addr[device] = ptr;
+  }
+  *out = g_scratch_addr[device];
+  return W1_OK;
+}
+
+}  // namespace
+}  // namespace w1
+
 // =========================================================================== ABI
 using namespace w1;
 
@@ -930,6 +979,11 @@ int w1_ctx_create(int device, w1_ctx** out) {
       delete c;
       return W1_EHIP;
     }
+  const int rc = scratch_setup(device, &c->scratch);
+  if (rc != W1_OK) {
+    w1_ctx_destroy(c);
+    return rc;
+  }
   *out = c;
   return W1_OK;
 }
@@ -962,6 +1016,44 @@ int w1_rwmd(w1_ctx* c, const w1_pd* a, const w1_pd* b, int64_t k, uint32_t flags
   if (!L_out) return W1_EINVAL;
   w1_params p{0.1, 0.1, 0, flags, 0};
   return entry(c, a, b, k, &p, stream, nullptr, L_out);
+}
+
+int w1_rwmd_noalloc(w1_ctx* c, const w1_pd* a, const w1_pd* b, int64_t k, uint32_t flags, void* stream,
+                    double* L_out) {
+  if (!c || !a || !b || k <= 0 || !L_out || (flags & ~W1_INPUT_DEVICE)) return W1_EINVAL;
+  if (k > kNoAllocMaxPairs) return W1_ERANGE;
+  int64_t total = 0;
+  for (int64_t p = 0; p < k; ++p) {
+    if (a[p].n < 0 || b[p].n < 0) return W1_EINVAL;
+    total += a[p].n + b[p].n;
+    if (total > kNoAllocMaxPoints) return W1_ERANGE;
+  }
+  if (!c->scratch) return W1_ENODEV;
+  if (hipSetDevice(c->device) != hipSuccess) return W1_EHIP;
+  // put the context's own buffers aside: every buffer of this call is a
+  // slice of the device's scratch array
+  for (size_t i = 0; i < c->all.size(); ++i) {
+    c->saved[i] = *c->all[i];
+    *c->all[i] = DBuf{};
+  }
+  c->arena = Arena{(char*)c->scratch, kNoAllocScratchBytes, 0};
+  Opts o;
+  o.flags = flags;
+  int rc;
+  try {
+    c->K_base = 0;
+    rc = run(*c, a, b, k, o, (hipStream_t)stream, nullptr, L_out);
+  } catch (const StageError& e) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    rc = e.code;
+  } catch (const std::bad_alloc&) {
+    rc = W1_ENOMEM;
+  }
+  c->arena = Arena{};
+  for (size_t i = 0; i < c->all.size(); ++i) *c->all[i] = c->saved[i];
+  c->network_valid = false;
+  return rc;
 }
 
 int w1_device_network_get(w1_ctx* c, int64_t k, w1_device_network* out) {
