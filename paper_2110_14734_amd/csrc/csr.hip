@@ -16,9 +16,10 @@
 //   4. row scatter, per bucket: each row's heads are written to the row's
 //      final place (order within the row still arbitrary);
 //   5. row sort: one block per row sets one bit per head in an LDS bitmap
-//      over the pair's cells and reads the bits back in order, writing the
-//      heads and their costs (2 max(|di|, |dj|) from the cell coordinates)
-//      and the row's arc to the A-diagonal node;
+//      over the pair's cells and reads the bits back in order through
+//      per-wave LDS staging, writing the heads and their costs (2 max(|di|,
+//      |dj|) from the cell coordinates) coalesced, and the row's arc to the
+//      A-diagonal node;
 //   6. the B-diagonal node's row: its arcs to the cells with B mass, in cell
 //      order, then to the A-diagonal node; and the supplies.
 //
@@ -40,8 +41,11 @@ namespace {
 constexpr int CB = 512;        // threads per block of the partition passes
 constexpr int PPT = 8;         // pair records per thread in the bucket passes
 constexpr int PTILE = CB * PPT;
-constexpr int SORT_B = 256;    // threads per block of the row sort
-constexpr int WIN_WORDS = (1 << 14) - 8;  // bitmap window (LDS stays within 64 KiB)
+constexpr int SORT_B = 512;    // threads per block of the row sort
+constexpr int SORT_WAVES = SORT_B / WAVE;
+constexpr int SORT_STAGE = 256;  // staged heads per wave of the row sort
+constexpr int WIN_WORDS = 14336;  // largest bitmap window: with the staging, 64 KiB of LDS
+constexpr int SORT_MAXG = WIN_WORDS / WAVE;  // groups of 64 words in a window
 
 // Last p in [0, K) with rstart[p] <= x (the pair holding record x: pairs
 // without records share their start with the next pair, which wins).
@@ -290,27 +294,68 @@ __global__ void __launch_bounds__(CB) k_row_scatter(const uint32_t* __restrict__
 }
 
 // ------------------------------------------------------------ 5. row sort --
-__device__ inline uint32_t wave_incl_scan_u32(uint32_t v) {
-  const int lane = lane_id();
+// Exclusive prefix over the wave's lanes of v < 2^NB, and the wave total,
+// from NB ballots (one per bit plane) and lane-mask counts: no cross-lane
+// data movement, so no memory round trip.
+template <int NB>
+__device__ inline uint32_t wave_excl_prefix(uint32_t v, uint32_t& total) {
+  uint32_t ex = 0, tot = 0;
 #pragma unroll
-  for (int d = 1; d < WAVE; d <<= 1) {
-    const uint32_t o = __shfl_up(v, d);
-    if (lane >= d) v += o;
+  for (int b = 0; b < NB; ++b) {
+    const uint64_t m = __ballot((v >> b) & 1u);
+    ex += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << b;
+    tot += (uint32_t)__popcll(m) << b;
   }
-  return v;
+  total = tot;
+  return ex;
+}
+
+// Writes a wave's staged heads (in order) as arcs k0, k0 + 1, ... of the row
+// of cell `me`: head and cost 2 max(|di|, |dj|).  Four heads per lane are in
+// flight at once, so their cell-coordinate gathers overlap.
+__device__ inline void flush_staged(const uint32_t* st, uint32_t n, int64_t k0, int2 me, const int2* __restrict__ cij,
+                                    int64_t cs, uint32_t* __restrict__ col, int32_t* __restrict__ cost) {
+  const uint32_t lane = (uint32_t)lane_id();
+  for (uint32_t x = lane; x < n; x += 4 * WAVE) {
+    uint32_t d[4];
+    int2 o[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) d[u] = x + u * WAVE < n ? st[x + u * WAVE] : 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (x + u * WAVE < n) o[u] = cij[cs + d[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (x + u * WAVE < n) {
+        const int64_t k = k0 + x + u * WAVE;
+        col[k] = d[u];
+        cost[k] = 2 * max(abs(me.x - o[u].x), abs(me.y - o[u].y));
+      }
+  }
 }
 
 // One block per cell row g.  heads: the row's heads in arbitrary order
 // (rowcnt[g] of them at off[row]); col / cost: the sorted row.
+//   1. the heads set one bit each in an LDS bitmap over the pair's cells
+//      (a window of `win_words` words at a time);
+//   2. the set bits are counted per group of 64 words and the counts scanned,
+//      and each wave takes a run of whole groups holding about an eighth of
+//      the heads (a row's heads crowd around its own cell, so equal runs of
+//      words would leave most of them to one wave);
+//   3. each wave reads its groups in order, 64 words at a time, expands the
+//      set bits into its LDS staging area (a group denser than the staging
+//      area goes through in slices of 8 words, one 4-bit nibble per lane),
+//      and writes the staged heads with their costs coalesced.
 __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict__ cpair,
                                                      const int64_t* __restrict__ cell_start,
                                                      const int32_t* __restrict__ ncells, const int2* __restrict__ cij,
                                                      const int32_t* __restrict__ ca, const uint32_t* __restrict__ rowcnt,
                                                      const uint64_t* __restrict__ off,
-                                                     const uint32_t* __restrict__ heads, uint32_t* __restrict__ col,
-                                                     int32_t* __restrict__ cost) {
-  __shared__ uint32_t s_bm[WIN_WORDS];
-  __shared__ uint32_t s_wtot[SORT_B / WAVE];
+                                                     const uint32_t* __restrict__ heads, int win_words,
+                                                     uint32_t* __restrict__ col, int32_t* __restrict__ cost) {
+  extern __shared__ uint32_t s_mem[];
+  __shared__ uint32_t s_gpre[SORT_MAXG + 1];
+  __shared__ int s_wg[SORT_WAVES + 1];
   const int64_t g = blockIdx.x;
   const uint32_t p = cpair[g];
   const int64_t cs = cell_start[p];
@@ -319,50 +364,106 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
   const uint32_t cnt = rowcnt[g];
   const int2 me = cij[g];
   const int lane = lane_id(), wave = threadIdx.x / WAVE;
+  uint32_t* s_bm = s_mem;
+  uint32_t* s_st = s_mem + win_words + wave * SORT_STAGE;
   uint32_t written = 0;  // heads written by earlier windows (block-uniform)
   if (cnt > 0) {
-    for (uint32_t w0 = 0; w0 < np; w0 += 32u * WIN_WORDS) {
-      const uint32_t nbits = min(np - w0, 32u * WIN_WORDS);
+    for (uint32_t w0 = 0; w0 < np; w0 += 32u * (uint32_t)win_words) {
+      const uint32_t nbits = min(np - w0, 32u * (uint32_t)win_words);
       const int nw = (int)((nbits + 31) / 32);
+      const int ng = (nw + WAVE - 1) / WAVE;
       for (int i = threadIdx.x; i < nw; i += SORT_B) s_bm[i] = 0;
       __syncthreads();
-      for (uint32_t i = threadIdx.x; i < cnt; i += SORT_B) {
-        const uint32_t d = heads[start + i] - w0;
-        if (d < nbits) atomicOr(&s_bm[d >> 5], 1u << (d & 31));
+      for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += 4 * SORT_B) {
+        uint32_t h[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) h[u] = i0 + u * SORT_B < cnt ? heads[start + i0 + u * SORT_B] - w0 : ~0u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (h[u] < nbits) atomicOr(&s_bm[h[u] >> 5], 1u << (h[u] & 31));
       }
       __syncthreads();
-      // each wave owns a contiguous quarter of the words (64-word chunks)
-      const int q = (((nw + 3) / 4) + WAVE - 1) / WAVE * WAVE;
-      const int wa = min(nw, wave * q), wb = min(nw, wa + q);
-      uint32_t mine = 0;
-      for (int i = wa + lane; i < wb; i += WAVE) mine += __popc(s_bm[i]);
-      for (int d = WAVE / 2; d > 0; d >>= 1) mine += __shfl_xor(mine, d);
-      if (lane == 0) s_wtot[wave] = mine;
-      __syncthreads();
-      uint32_t base = written, all = 0;
-      for (int v = 0; v < SORT_B / WAVE; ++v) {
-        if (v < wave) base += s_wtot[v];
-        all += s_wtot[v];
+      // heads per group of 64 words, then their exclusive scan (wave 0)
+      for (int q = wave; q < ng; q += SORT_WAVES) {
+        const int i = q * WAVE + lane;
+        uint32_t t;
+        (void)wave_excl_prefix<6>(i < nw ? (uint32_t)__popc(s_bm[i]) : 0u, t);
+        if (lane == 0) s_gpre[q] = t;
       }
-      for (int c = wa; c < wb; c += WAVE) {
-        const int i = c + lane;
-        uint32_t bits = i < wb ? s_bm[i] : 0u;
-        const uint32_t pc = (uint32_t)__popc(bits);
-        const uint32_t inc = wave_incl_scan_u32(pc);
-        int64_t k = start + (int64_t)(base + inc - pc);
-        while (bits) {
-          const int bit = __ffs(bits) - 1;
-          bits &= bits - 1;
-          const uint32_t d = w0 + (uint32_t)i * 32u + (uint32_t)bit;
-          const int2 o = cij[cs + d];
-          const int32_t di = abs(me.x - o.x), dj = abs(me.y - o.y);
-          col[k] = d;
-          cost[k] = 2 * max(di, dj);
-          ++k;
+      __syncthreads();
+      if (wave == 0) {
+        uint32_t carry = 0;
+        for (int c0 = 0; c0 < ng; c0 += WAVE) {
+          const int q = c0 + lane;
+          uint32_t t;
+          const uint32_t ex = wave_excl_prefix<12>(q < ng ? s_gpre[q] : 0u, t);
+          if (q < ng) s_gpre[q] = carry + ex;
+          carry += t;
         }
-        base += __shfl(inc, WAVE - 1);
+        if (lane == 0) s_gpre[ng] = carry;
+        // wave boundaries: first group whose prefix reaches v/8 of the heads
+        if (lane <= SORT_WAVES) {
+          const uint32_t target = (uint32_t)(((uint64_t)carry * (uint32_t)lane) / SORT_WAVES);
+          int lo = 0, hi = ng;  // first q in [0, ng] with s_gpre[q] >= target
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_gpre[mid] >= target) hi = mid;
+            else lo = mid + 1;
+          }
+          s_wg[lane] = lane == SORT_WAVES ? ng : lo;
+        }
       }
-      written += all;
+      __syncthreads();
+      const int qa = s_wg[wave], qb = s_wg[wave + 1];
+      int64_t k0 = start + written + s_gpre[qa];  // next arc of this wave
+      uint32_t staged = 0;                         // wave-uniform
+      for (int q = qa; q < qb; ++q) {
+        const int i = q * WAVE + lane;
+        const uint32_t word = i < nw ? s_bm[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = wave_excl_prefix<6>((uint32_t)__popc(word), tot);
+        if (tot == 0) continue;
+        if (staged + tot > SORT_STAGE) {
+          __builtin_amdgcn_wave_barrier();
+          flush_staged(s_st, staged, k0, me, cij, cs, col, cost);
+          k0 += staged;
+          staged = 0;
+          __builtin_amdgcn_wave_barrier();
+        }
+        if (tot <= SORT_STAGE) {  // each lane expands its word into the staging area
+          uint32_t bits = word, pos = staged + ex;
+          while (bits) {
+            const int bit = __ffs(bits) - 1;
+            bits &= bits - 1;
+            s_st[pos++] = w0 + (uint32_t)i * 32u + (uint32_t)bit;
+          }
+          staged += tot;
+          continue;
+        }
+        // denser than the staging area: slices of 8 words (at most 256
+        // heads), lane l expanding nibble l % 8 of word l / 8 of the slice,
+        // which is bit order
+        for (int sl = 0; sl < 8; ++sl) {
+          const int wi = q * WAVE + sl * 8 + (lane >> 3);
+          const uint32_t w = wi < nw ? s_bm[wi] : 0u;
+          const int sh = 4 * (lane & 7);
+          uint32_t nib = (w >> sh) & 0xfu, ts;
+          uint32_t pos = wave_excl_prefix<3>((uint32_t)__popc(nib), ts);
+          const uint32_t at = w0 + (uint32_t)wi * 32u + (uint32_t)sh;
+          while (nib) {
+            const int bit = __ffs(nib) - 1;
+            nib &= nib - 1;
+            s_st[pos++] = at + (uint32_t)bit;
+          }
+          __builtin_amdgcn_wave_barrier();
+          flush_staged(s_st, ts, k0, me, cij, cs, col, cost);
+          k0 += ts;
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      flush_staged(s_st, staged, k0, me, cij, cs, col, cost);
+      written += s_gpre[ng];
       __syncthreads();
     }
   }
@@ -498,10 +599,13 @@ void launch_csr_row_scatter(const uint32_t* ent, const int64_t* tfirst, int64_t 
 }
 void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
                          const int32_t* ca, const uint32_t* rowcnt, const uint64_t* off, const uint32_t* heads,
-                         int64_t N, uint32_t* col, int32_t* cost, hipStream_t st) {
+                         int64_t N, int64_t max_pair_cells, uint32_t* col, int32_t* cost, hipStream_t st) {
   if (N <= 0) return;
-  hipLaunchKernelGGL(k_row_sort, dim3((unsigned)N), dim3(SORT_B), 0, st, cpair, cell_start, ncells, cij, ca, rowcnt,
-                     off, heads, col, cost);
+  // the bitmap covers the largest pair's cells at once when they fit
+  const int win = (int)std::min<int64_t>(WIN_WORDS, std::max<int64_t>(1, (max_pair_cells + 31) / 32));
+  const size_t lds = (size_t)win * 4 + (size_t)SORT_WAVES * SORT_STAGE * 4;
+  hipLaunchKernelGGL(k_row_sort, dim3((unsigned)N), dim3(SORT_B), lds, st, cpair, cell_start, ncells, cij, ca, rowcnt,
+                     off, heads, win, col, cost);
 }
 #define LAUNCH(kern, n, ...) \
   do { if ((n) > 0) hipLaunchKernelGGL(kern, dim3(blocks(n)), dim3(256), 0, st, __VA_ARGS__); } while (0)
