@@ -310,6 +310,19 @@ __device__ inline uint32_t wave_excl_prefix(uint32_t v, uint32_t& total) {
   return ex;
 }
 
+// Exclusive prefix of small counts: one ballot per unit of the largest
+// count (sum over j of the lanes below with v > j), cheaper than bit planes
+// when the counts are mostly 0 or 1.
+__device__ inline uint32_t wave_excl_prefix_small(uint32_t v) {
+  uint32_t ex = 0;
+  for (uint32_t j = 0;; ++j) {
+    const uint64_t m = __ballot(v > j);
+    if (m == 0) break;
+    ex += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  }
+  return ex;
+}
+
 // Writes a wave's staged heads (in order) as arcs k0, k0 + 1, ... of the row
 // of cell `me`: head and cost 2 max(|di|, |dj|).  Four heads per lane are in
 // flight at once, so their cell-coordinate gathers overlap.
@@ -334,64 +347,62 @@ __device__ inline void flush_staged(const uint32_t* st, uint32_t n, int64_t k0, 
   }
 }
 
-// One block per cell row g.  heads: the row's heads in arbitrary order
-// (rowcnt[g] of them at off[row]); col / cost: the sorted row.
-//   1. the heads set one bit each in an LDS bitmap over the pair's cells
-//      (a window of `win_words` words at a time);
-//   2. the set bits are counted per group of 64 words and the counts scanned,
-//      and each wave takes a run of whole groups holding about an eighth of
-//      the heads (a row's heads crowd around its own cell, so equal runs of
-//      words would leave most of them to one wave);
-//   3. each wave reads its groups in order, 64 words at a time, expands the
-//      set bits into its LDS staging area (a group denser than the staging
-//      area goes through in slices of 8 words, one 4-bit nibble per lane),
-//      and writes the staged heads with their costs coalesced.
+// Persistent blocks, each sorting rows g = blockIdx.x, + gridDim.x, ...
+// heads: a row's heads in arbitrary order (rowcnt[g] of them at off[row]);
+// col / cost: the sorted row.  Per row (and per window of `win_words`
+// bitmap words over the pair's cells):
+//   1. each head sets its bit in an LDS bitmap and counts towards its group
+//      of 64 words;
+//   2. the group counts are scanned, and each wave takes a run of whole
+//      groups holding about an eighth of the heads (a row's heads crowd
+//      around its own cell, so equal runs of words would leave most of them
+//      to one wave);
+//   3. each wave reads its non-empty groups in order (clearing the words
+//      behind it, so the bitmap is zero again for the next row), expands
+//      the set bits into its LDS staging area (a group denser than the
+//      staging area goes through in slices of 8 words, one 4-bit nibble per
+//      lane), and writes the staged heads with their costs coalesced.
 __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict__ cpair,
                                                      const int64_t* __restrict__ cell_start,
                                                      const int32_t* __restrict__ ncells, const int2* __restrict__ cij,
                                                      const int32_t* __restrict__ ca, const uint32_t* __restrict__ rowcnt,
                                                      const uint64_t* __restrict__ off,
-                                                     const uint32_t* __restrict__ heads, int win_words,
+                                                     const uint32_t* __restrict__ heads, int64_t N, int win_words,
                                                      uint32_t* __restrict__ col, int32_t* __restrict__ cost) {
   extern __shared__ uint32_t s_mem[];
   __shared__ uint32_t s_gpre[SORT_MAXG + 1];
   __shared__ int s_wg[SORT_WAVES + 1];
-  const int64_t g = blockIdx.x;
-  const uint32_t p = cpair[g];
-  const int64_t cs = cell_start[p];
-  const uint32_t np = (uint32_t)ncells[p];
-  const int64_t start = (int64_t)off[g + 2 * (int64_t)p];
-  const uint32_t cnt = rowcnt[g];
-  const int2 me = cij[g];
   const int lane = lane_id(), wave = threadIdx.x / WAVE;
   uint32_t* s_bm = s_mem;
   uint32_t* s_st = s_mem + win_words + wave * SORT_STAGE;
-  uint32_t written = 0;  // heads written by earlier windows (block-uniform)
-  if (cnt > 0) {
-    for (uint32_t w0 = 0; w0 < np; w0 += 32u * (uint32_t)win_words) {
+  for (int i = threadIdx.x; i < win_words; i += SORT_B) s_bm[i] = 0;
+  for (int64_t g = blockIdx.x; g < N; g += gridDim.x) {
+    const uint32_t p = cpair[g];
+    const int64_t cs = cell_start[p];
+    const uint32_t np = (uint32_t)ncells[p];
+    const int64_t start = (int64_t)off[g + 2 * (int64_t)p];
+    const uint32_t cnt = rowcnt[g];
+    const int2 me = cij[g];
+    uint32_t written = 0;  // heads written by earlier windows (block-uniform)
+    for (uint32_t w0 = 0; cnt > 0 && w0 < np; w0 += 32u * (uint32_t)win_words) {
       const uint32_t nbits = min(np - w0, 32u * (uint32_t)win_words);
       const int nw = (int)((nbits + 31) / 32);
       const int ng = (nw + WAVE - 1) / WAVE;
-      for (int i = threadIdx.x; i < nw; i += SORT_B) s_bm[i] = 0;
-      __syncthreads();
+      for (int q = threadIdx.x; q <= ng; q += SORT_B) s_gpre[q] = 0;
+      __syncthreads();  // also orders the previous row's last reads before this row's bits
       for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += 4 * SORT_B) {
         uint32_t h[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) h[u] = i0 + u * SORT_B < cnt ? heads[start + i0 + u * SORT_B] - w0 : ~0u;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (h[u] < nbits) atomicOr(&s_bm[h[u] >> 5], 1u << (h[u] & 31));
+          if (h[u] < nbits) {
+            atomicOr(&s_bm[h[u] >> 5], 1u << (h[u] & 31));
+            atomicAdd(&s_gpre[h[u] >> 11], 1u);
+          }
       }
       __syncthreads();
-      // heads per group of 64 words, then their exclusive scan (wave 0)
-      for (int q = wave; q < ng; q += SORT_WAVES) {
-        const int i = q * WAVE + lane;
-        uint32_t t;
-        (void)wave_excl_prefix<6>(i < nw ? (uint32_t)__popc(s_bm[i]) : 0u, t);
-        if (lane == 0) s_gpre[q] = t;
-      }
-      __syncthreads();
-      if (wave == 0) {
+      if (wave == 0) {  // exclusive scan of the group counts, then the wave runs
         uint32_t carry = 0;
         for (int c0 = 0; c0 < ng; c0 += WAVE) {
           const int q = c0 + lane;
@@ -401,10 +412,9 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
           carry += t;
         }
         if (lane == 0) s_gpre[ng] = carry;
-        // wave boundaries: first group whose prefix reaches v/8 of the heads
-        if (lane <= SORT_WAVES) {
+        if (lane <= SORT_WAVES) {  // first group whose prefix reaches lane/8 of the heads
           const uint32_t target = (uint32_t)(((uint64_t)carry * (uint32_t)lane) / SORT_WAVES);
-          int lo = 0, hi = ng;  // first q in [0, ng] with s_gpre[q] >= target
+          int lo = 0, hi = ng;
           while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if (s_gpre[mid] >= target) hi = mid;
@@ -418,11 +428,10 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
       int64_t k0 = start + written + s_gpre[qa];  // next arc of this wave
       uint32_t staged = 0;                         // wave-uniform
       for (int q = qa; q < qb; ++q) {
+        const uint32_t tot = s_gpre[q + 1] - s_gpre[q];
+        if (tot == 0) continue;
         const int i = q * WAVE + lane;
         const uint32_t word = i < nw ? s_bm[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = wave_excl_prefix<6>((uint32_t)__popc(word), tot);
-        if (tot == 0) continue;
         if (staged + tot > SORT_STAGE) {
           __builtin_amdgcn_wave_barrier();
           flush_staged(s_st, staged, k0, me, cij, cs, col, cost);
@@ -431,45 +440,45 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
           __builtin_amdgcn_wave_barrier();
         }
         if (tot <= SORT_STAGE) {  // each lane expands its word into the staging area
-          uint32_t bits = word, pos = staged + ex;
+          uint32_t bits = word, pos = staged + wave_excl_prefix_small((uint32_t)__popc(word));
           while (bits) {
             const int bit = __ffs(bits) - 1;
             bits &= bits - 1;
             s_st[pos++] = w0 + (uint32_t)i * 32u + (uint32_t)bit;
           }
           staged += tot;
-          continue;
-        }
-        // denser than the staging area: slices of 8 words (at most 256
-        // heads), lane l expanding nibble l % 8 of word l / 8 of the slice,
-        // which is bit order
-        for (int sl = 0; sl < 8; ++sl) {
-          const int wi = q * WAVE + sl * 8 + (lane >> 3);
-          const uint32_t w = wi < nw ? s_bm[wi] : 0u;
-          const int sh = 4 * (lane & 7);
-          uint32_t nib = (w >> sh) & 0xfu, ts;
-          uint32_t pos = wave_excl_prefix<3>((uint32_t)__popc(nib), ts);
-          const uint32_t at = w0 + (uint32_t)wi * 32u + (uint32_t)sh;
-          while (nib) {
-            const int bit = __ffs(nib) - 1;
-            nib &= nib - 1;
-            s_st[pos++] = at + (uint32_t)bit;
+        } else {
+          // denser than the staging area: slices of 8 words (at most 256
+          // heads), lane l expanding nibble l % 8 of word l / 8 of the slice,
+          // which is bit order
+          for (int sl = 0; sl < 8; ++sl) {
+            const uint32_t w = __shfl(word, sl * 8 + (lane >> 3));
+            const int sh = 4 * (lane & 7);
+            uint32_t nib = (w >> sh) & 0xfu, ts;
+            uint32_t pos = wave_excl_prefix<3>((uint32_t)__popc(nib), ts);
+            const uint32_t at = w0 + (uint32_t)(q * WAVE + sl * 8 + (lane >> 3)) * 32u + (uint32_t)sh;
+            while (nib) {
+              const int bit = __ffs(nib) - 1;
+              nib &= nib - 1;
+              s_st[pos++] = at + (uint32_t)bit;
+            }
+            __builtin_amdgcn_wave_barrier();
+            flush_staged(s_st, ts, k0, me, cij, cs, col, cost);
+            k0 += ts;
+            __builtin_amdgcn_wave_barrier();
           }
-          __builtin_amdgcn_wave_barrier();
-          flush_staged(s_st, ts, k0, me, cij, cs, col, cost);
-          k0 += ts;
-          __builtin_amdgcn_wave_barrier();
         }
+        if (i < nw) s_bm[i] = 0;  // zero again for the next row
       }
       __builtin_amdgcn_wave_barrier();
       flush_staged(s_st, staged, k0, me, cij, cs, col, cost);
       written += s_gpre[ng];
       __syncthreads();
     }
-  }
-  if (threadIdx.x == 0 && ca[g] > 0) {  // arc to the A-diagonal node, last in the row
-    col[start + cnt] = np;
-    cost[start + cnt] = me.y - me.x;
+    if (threadIdx.x == 0 && ca[g] > 0) {  // arc to the A-diagonal node, last in the row
+      col[start + cnt] = np;
+      cost[start + cnt] = me.y - me.x;
+    }
   }
 }
 
@@ -599,13 +608,16 @@ void launch_csr_row_scatter(const uint32_t* ent, const int64_t* tfirst, int64_t 
 }
 void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
                          const int32_t* ca, const uint32_t* rowcnt, const uint64_t* off, const uint32_t* heads,
-                         int64_t N, int64_t max_pair_cells, uint32_t* col, int32_t* cost, hipStream_t st) {
+                         int64_t N, int64_t max_pair_cells, int num_cus, uint32_t* col, int32_t* cost,
+                         hipStream_t st) {
   if (N <= 0) return;
   // the bitmap covers the largest pair's cells at once when they fit
   const int win = (int)std::min<int64_t>(WIN_WORDS, std::max<int64_t>(1, (max_pair_cells + 31) / 32));
   const size_t lds = (size_t)win * 4 + (size_t)SORT_WAVES * SORT_STAGE * 4;
-  hipLaunchKernelGGL(k_row_sort, dim3((unsigned)N), dim3(SORT_B), lds, st, cpair, cell_start, ncells, cij, ca, rowcnt,
-                     off, heads, win, col, cost);
+  // persistent: two blocks per compute unit fit beside each other's LDS
+  const int64_t grid = std::min<int64_t>(N, (int64_t)num_cus * 2);
+  hipLaunchKernelGGL(k_row_sort, dim3((unsigned)grid), dim3(SORT_B), lds, st, cpair, cell_start, ncells, cij, ca,
+                     rowcnt, off, heads, N, win, col, cost);
 }
 #define LAUNCH(kern, n, ...) \
   do { if ((n) > 0) hipLaunchKernelGGL(kern, dim3(blocks(n)), dim3(256), 0, st, __VA_ARGS__); } while (0)

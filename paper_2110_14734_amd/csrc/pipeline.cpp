@@ -618,7 +618,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       check(c, hipEventRecord(c.kev[9], st));
     }
     int32_t* cost = need<int32_t>(c, c.costb, 2 * Ptot + 2 * N + K);
-    launch_csr_row_sort(cp, P.cell_start, ncl, cij, ca, rowcnt, off, heads, N, maxnp, col, cost, st);
+    launch_csr_row_sort(cp, P.cell_start, ncl, cij, ca, rowcnt, off, heads, N, maxnp, c.num_cus, col, cost, st);
     launch_csr_bdiag(cp, P.cell_start, ncl, cij, ca, cb, bpos, off, P, N, col, cost, sup, st);
     int64_t* rp = need<int64_t>(c, c.rp, N + 3 * K);
     fill_u64((uint64_t*)rp, 0, N + 3 * K, st);
