@@ -29,18 +29,18 @@ METRIC = "PD pairs/sec (approx W1 at eps) + sparsify pts/s & HBM GB/s frac; 1-NN
 HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes of the WSPD and network kernels, per WSPD pair (both
 # arcs of a pair) and per cell:
-#   emit          writes the 12-byte pair record (u32 u, u32 v, i32 cost);
-#   bucket_hist   reads the record;
+#   emit          writes the 12-byte pair record (u32 u, u32 v, i32 cost) and
+#                 counts both arcs per tail bucket in LDS;
 #   bucket_scatter reads the record, writes two 4-byte bucket entries;
 #   row_hist      reads the two entries;
 #   row_scatter   reads the two entries, writes two 4-byte row heads;
 #   row_sort      reads the two heads, writes two (u32 head, i32 cost) arcs
 #                 of the final rows and an int64 row pointer per cell.
 # The final network alone is 16 B per pair and 8 B per cell.
-KERNEL_BYTES = {"emit_ms": (12, 0), "bucket_hist_ms": (12, 0), "bucket_scatter_ms": (20, 0),
+KERNEL_BYTES = {"emit_ms": (12, 0), "bucket_scatter_ms": (20, 0),
                 "row_hist_ms": (8, 0), "row_scatter_ms": (16, 0), "row_sort_ms": (24, 8)}
 NETWORK_BYTES = (16, 8)
-KERNEL_NAMES = {"emit_ms": "k_wspd<emit> (WSPD pair records)", "bucket_hist_ms": "k_bucket_hist",
+KERNEL_NAMES = {"emit_ms": "k_wspd<emit> (WSPD pair records)",
                 "bucket_scatter_ms": "k_bucket_scatter", "row_hist_ms": "k_row_hist",
                 "row_scatter_ms": "k_row_scatter", "row_sort_ms": "k_row_sort (sorted rows, costs)"}
 
@@ -358,7 +358,7 @@ def main():
         ctx.approx(tA, tB, eps=args.eps, flags=flags)
     torch.cuda.synchronize()
     stage = {k: 0.0 for k in w1.T_NAMES[:6]}
-    kern = {k: 0.0 for k in w1.Context.KERNEL_TIMES if k != "pairs"}
+    kern = {k: 0.0 for k in w1.Context.KERNEL_TIMES if k not in ("pairs", "unused_ms")}
     r = None
     t0 = time.perf_counter()
     for _ in range(args.steps):

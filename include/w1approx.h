@@ -271,11 +271,12 @@ int w1_ctx_set_tuning(w1_ctx *ctx, const w1_tuning *t);
 
 /* Device times (ms, HIP events on the call's stream) of the last call's
  * WSPD and network kernels: [0] work-list build (expansion rounds, item
- * sort, chunking), [1] count pass, [2] emit pass, [3] the number of pairs
- * emitted; then the passes that sort the network into rows: [4] bucket
- * histogram, [5] bucket scatter, [6] row histogram, [7] row scatter (with
- * the degree scan before it), [8] row sort (with the diagonal rows and
- * row pointers).  n is the capacity of ms (>= 4); entries beyond 8 are 0. */
+ * sort, chunking), [1] count pass, [2] emit pass (which also takes the
+ * network's bucket histogram), [3] the number of pairs emitted; then the
+ * passes that sort the network into rows: [4] 0 (no separate histogram
+ * pass), [5] bucket scatter, [6] row histogram, [7] row scatter (with the
+ * degree scan before it), [8] row sort (with the diagonal rows and row
+ * pointers).  n is the capacity of ms (>= 4); entries beyond 8 are 0. */
 int w1_ctx_last_kernel_times(const w1_ctx *ctx, double *ms, int n);
 
 /* Host network simplex on any uncapacitated network with non-negative integer

@@ -399,7 +399,7 @@ class Context:
         if rc != 0:
             raise W1Error(rc, "w1_ctx_set_tuning")
 
-    KERNEL_TIMES = ("worklist_ms", "count_ms", "emit_ms", "pairs", "bucket_hist_ms", "bucket_scatter_ms",
+    KERNEL_TIMES = ("worklist_ms", "count_ms", "emit_ms", "pairs", "unused_ms", "bucket_scatter_ms",
                     "row_hist_ms", "row_scatter_ms", "row_sort_ms")
 
     def kernel_times(self) -> dict:

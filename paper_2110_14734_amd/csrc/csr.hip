@@ -8,7 +8,8 @@
 //
 //   1. bucket histogram: each arc u -> v of a WSPD pair record (both
 //      orientations) counts towards the bucket of its tail, a bucket being
-//      2^RB consecutive global cells;
+//      2^RB consecutive global cells (taken by the WSPD emit pass as it
+//      writes the records);
 //   2. bucket scatter: arcs are written bucket-major as 32-bit entries
 //      (tail within the bucket << DB | head), staged in LDS so each block
 //      writes one contiguous run per bucket;
@@ -46,6 +47,7 @@ constexpr int SORT_WAVES = SORT_B / WAVE;
 constexpr int SORT_STAGE = 256;  // staged heads per wave of the row sort
 constexpr int WIN_WORDS = 14336;  // largest bitmap window: with the staging, 64 KiB of LDS
 constexpr int SORT_MAXG = WIN_WORDS / WAVE;  // groups of 64 words in a window
+constexpr int SORT_FILL = 4;                 // head loads per thread in flight in the row sort
 
 // Last p in [0, K) with rstart[p] <= x (the pair holding record x: pairs
 // without records share their start with the next pair, which wins).
@@ -112,7 +114,7 @@ __device__ inline void lds_excl_scan(uint32_t* cnt, int n, uint32_t* s_tmp) {
   __syncthreads();
 }
 
-// ---------------------------------------------------------- 1. bucket hist --
+// ------------------------------------------------------ arcs of a record --
 // Arcs of pair records [x0, x1): tail cell (global) and entry.
 __device__ inline void record_arcs(const uint32_t* __restrict__ rec, uint64_t x, int64_t cs, int RB, int DB,
                                    uint32_t& b0, uint32_t& e0, uint32_t& b1, uint32_t& e1) {
@@ -123,28 +125,6 @@ __device__ inline void record_arcs(const uint32_t* __restrict__ rec, uint64_t x,
   e0 = (((uint32_t)gu & m) << DB) | v;
   b1 = (uint32_t)(gv >> RB);
   e1 = (((uint32_t)gv & m) << DB) | u;
-}
-
-__global__ void __launch_bounds__(CB) k_bucket_hist(const uint32_t* __restrict__ rec, uint64_t P,
-                                                    const uint64_t* __restrict__ rstart, int64_t K,
-                                                    const int64_t* __restrict__ cell_start, int RB, int DB, int NB,
-                                                    unsigned long long* __restrict__ bcnt) {
-  extern __shared__ uint32_t s_hist[];
-  const uint64_t x0 = (uint64_t)blockIdx.x * PTILE, x1 = min(P, x0 + PTILE);
-  for (int b = threadIdx.x; b < NB; b += CB) s_hist[b] = 0;
-  const TilePairs tp = tile_pairs(rstart, K, x0, x1);  // (includes a barrier)
-  for (int k = 0; k < PPT; ++k) {
-    const uint64_t x = x0 + (uint64_t)k * CB + threadIdx.x;
-    if (x >= x1) break;
-    const int64_t cs = cell_start[record_pair(tp, rstart, x)];
-    uint32_t b0, e0, b1, e1;
-    record_arcs(rec, x, cs, RB, DB, b0, e0, b1, e1);
-    atomicAdd(&s_hist[b0], 1u);
-    atomicAdd(&s_hist[b1], 1u);
-  }
-  __syncthreads();
-  for (int b = threadIdx.x; b < NB; b += CB)
-    if (s_hist[b]) atomicAdd(&bcnt[b], (unsigned long long)s_hist[b]);
 }
 
 // ------------------------------------------------------- 2. bucket scatter --
@@ -390,12 +370,13 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
       const int ng = (nw + WAVE - 1) / WAVE;
       for (int q = threadIdx.x; q <= ng; q += SORT_B) s_gpre[q] = 0;
       __syncthreads();  // also orders the previous row's last reads before this row's bits
-      for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += 4 * SORT_B) {
-        uint32_t h[4];
+      for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += SORT_FILL * SORT_B) {
+        uint32_t h[SORT_FILL];  // all loads in flight before the first bit is set
 #pragma unroll
-        for (int u = 0; u < 4; ++u) h[u] = i0 + u * SORT_B < cnt ? heads[start + i0 + u * SORT_B] - w0 : ~0u;
+        for (int u = 0; u < SORT_FILL; ++u)
+          h[u] = i0 + u * SORT_B < cnt ? heads[start + i0 + u * SORT_B] - w0 : ~0u;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < SORT_FILL; ++u)
           if (h[u] < nbits) {
             atomicOr(&s_bm[h[u] >> 5], 1u << (h[u] & 31));
             atomicAdd(&s_gpre[h[u] >> 11], 1u);
@@ -577,12 +558,6 @@ size_t csr_row_scatter_lds(int RB) {
 }
 int64_t csr_entry_tile(int RB) { return (int64_t)CB * csr_entries_per_thread(RB); }
 
-void launch_csr_bucket_hist(const uint32_t* rec, uint64_t P, const uint64_t* rstart, int64_t K,
-                            const int64_t* cell_start, int RB, int DB, int NB, uint64_t* bcnt, hipStream_t st) {
-  if (P == 0) return;
-  hipLaunchKernelGGL(k_bucket_hist, dim3((unsigned)ceil_div((int64_t)P, PTILE)), dim3(CB), (size_t)NB * 4, st, rec, P,
-                     rstart, K, cell_start, RB, DB, NB, (unsigned long long*)bcnt);
-}
 void launch_csr_bucket_scatter(const uint32_t* rec, uint64_t P, const uint64_t* rstart, int64_t K,
                                const int64_t* cell_start, int RB, int DB, int NB, const uint64_t* bstart,
                                uint64_t* bcur, uint32_t* out, hipStream_t st) {

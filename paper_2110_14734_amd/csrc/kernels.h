@@ -78,8 +78,6 @@ void launch_level_boxes(const int2* cij, int64_t N, const int4* iaux, const int3
 size_t csr_bucket_scatter_lds(int NB);
 size_t csr_row_scatter_lds(int RB);
 int64_t csr_entry_tile(int RB);  // entries per tile of the row passes
-void launch_csr_bucket_hist(const uint32_t* rec, uint64_t P, const uint64_t* rstart, int64_t K,
-                            const int64_t* cell_start, int RB, int DB, int NB, uint64_t* bcnt, hipStream_t st);
 void launch_csr_bucket_scatter(const uint32_t* rec, uint64_t P, const uint64_t* rstart, int64_t K,
                                const int64_t* cell_start, int RB, int DB, int NB, const uint64_t* bstart,
                                uint64_t* bcur, uint32_t* out, hipStream_t st);
@@ -118,6 +116,17 @@ struct TreeView {
   const int2* cij;      // cell coordinates
   const uint32_t* cpair;
   int64_t N;
+};
+
+// Tail-bucket histogram of the network's arcs, taken by the emit pass:
+// bucket of a global cell c = c >> RB, NB buckets (NB = 0: none).  Records
+// hold cells local to their diagram pair, whose first cell is
+// cell_start[chunk_pair[chunk]].
+struct BucketHist {
+  const int32_t* chunk_pair = nullptr;
+  const int64_t* cell_start = nullptr;
+  int RB = 0, NB = 0;
+  uint64_t* count = nullptr;
 };
 
 struct WspdTuning {
@@ -160,7 +169,8 @@ void launch_chunks(const int32_t* cstart, int64_t K, const int64_t* item_start, 
 void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
-                      uint32_t* out, int32_t* err, bool prune, int num_cus, hipStream_t st);
+                      uint32_t* out, int32_t* err, bool prune, const BucketHist& bh, int num_cus,
+                      hipStream_t st);
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,
                         hipStream_t st);

@@ -506,7 +506,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       fill_u32(xc, 0, 8, st);
       check(c, hipEventRecord(c.kev[1], st));
       launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr, prune,
-                       c.num_cus, st);
+                       BucketHist{}, c.num_cus, st);
       check(c, hipGetLastError());
       check(c, hipEventRecord(c.kev[2], st));
       scan_u64(ccnt, coff, nch, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(nch, 8)), st);
@@ -521,9 +521,21 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         // are placed by final arc number (2 Ptot WSPD arcs plus at most
         // 2 N + K diagonal arcs)
         uint32_t* pout = need<uint32_t>(c, c.pu, std::max<int64_t>(3 * Ptot, 2 * Ptot + 2 * N + K));
+        // the emit pass also counts the arcs per tail bucket of the
+        // network's row partition (a5)
+        const CsrGeometry geo = csr_geometry(N, maxnp);
+        if (!geo.ok) throw StageError{W1_ERANGE};
+        uint64_t* bcnt = need<uint64_t>(c, c.bcnt, geo.NB);
+        fill_u64(bcnt, 0, geo.NB, st);
+        BucketHist bh;
+        bh.chunk_pair = cp;
+        bh.cell_start = P.cell_start;
+        bh.RB = geo.RB;
+        bh.NB = (int)geo.NB;
+        bh.count = bcnt;
         fill_u32(xc, 0, 8, st);
         check(c, hipEventRecord(c.kev[3], st));
-        launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr, prune,
+        launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr, prune, bh,
                          c.num_cus, st);
         check(c, hipGetLastError());
         emitted = true;
@@ -564,12 +576,9 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     if (Ptot > 0) {
       uint64_t* rstart = need<uint64_t>(c, c.rstart, K);
       scan_u64(P.npairs, rstart, K, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(K, 8)), st);
-      uint64_t* bcnt = need<uint64_t>(c, c.bcnt, NB);
-      fill_u64(bcnt, 0, NB, st);
+      const uint64_t* bcnt = (const uint64_t*)c.bcnt.p;  // taken by the emit pass
       csr_timed = true;
       check(c, hipEventRecord(c.kev[4], st));
-      launch_csr_bucket_hist((const uint32_t*)c.pu.p, (uint64_t)Ptot, rstart, K, P.cell_start, RB, DB, (int)NB, bcnt,
-                             st);
       check(c, hipEventRecord(c.kev[5], st));
       // bucket starts and the tiles of the row passes (host: NB is small)
       std::vector<uint64_t> hb((size_t)NB);

@@ -333,11 +333,18 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
                                               const int32_t* __restrict__ xcd_range, uint32_t* __restrict__ xcd_ctr, int s,
                                               int stack_depth, int64_t step_cap, uint64_t* __restrict__ chunk_cnt,
                                               const uint64_t* __restrict__ chunk_off, uint32_t* __restrict__ out,
-                                              int32_t* __restrict__ err) {
+                                              int32_t* __restrict__ err, BucketHist bh) {
   static_assert(!(EMIT && COMPACT), "packed split records carry no representatives");
   extern __shared__ int2 s_stack[];
   const int wave = threadIdx.x / WAVE, lane = lane_id();
   int2* stk = s_stack + (size_t)wave * stack_depth * WAVE + lane;  // entry e at stk[e * WAVE]
+  // emit pass: arcs per tail bucket of the network's row partition (both
+  // orientations of every pair), counted in LDS and added up at the end
+  uint32_t* s_hist = (uint32_t*)(s_stack + (size_t)4 * stack_depth * WAVE);
+  if (EMIT) {
+    for (int b = threadIdx.x; b < bh.NB; b += blockDim.x) s_hist[b] = 0;
+    __syncthreads();
+  }
   const int xcd = blockIdx.x & 7;
   for (int probe = 0; probe < 8; ++probe) {
     const int xr = (xcd + probe) & 7;
@@ -351,6 +358,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       int next = __builtin_amdgcn_readfirstlane(chunk_first[k]);
       const int end = __builtin_amdgcn_readfirstlane(chunk_end[k]);
       uint32_t* obase = EMIT ? out + 3 * chunk_off[k] : nullptr;
+      const uint64_t cs = EMIT && bh.NB > 0 ? (uint64_t)bh.cell_start[bh.chunk_pair[k]] : 0;
       uint64_t cursor = 0;
       bool has = false, overflow = false, runaway = false, orient = false;
       int sp = 0, oid = 0, od = 0;
@@ -466,6 +474,16 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
           if (e1) __builtin_nontemporal_store(m1, (u32x3_w*)(obase + 3 * lanes_set_below(b1, 0u)));
           if (e2) __builtin_nontemporal_store(m2, (u32x3_w*)(obase + 3 * lanes_set_below(b2, n1)));
           obase += 3 * (n1 + n2);
+          if (bh.NB > 0) {
+            if (e1) {
+              atomicAdd(&s_hist[(uint32_t)((cs + m1.x) >> bh.RB)], 1u);
+              atomicAdd(&s_hist[(uint32_t)((cs + m1.y) >> bh.RB)], 1u);
+            }
+            if (e2) {
+              atomicAdd(&s_hist[(uint32_t)((cs + m2.x) >> bh.RB)], 1u);
+              atomicAdd(&s_hist[(uint32_t)((cs + m2.y) >> bh.RB)], 1u);
+            }
+          }
         }
         cursor += n1 + n2;
       }
@@ -473,6 +491,11 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       if (bad) atomicOr(err, 1);
       if (!EMIT) chunk_cnt[k] = cursor;  // same value from every lane
     }
+  }
+  if (EMIT && bh.NB > 0) {
+    __syncthreads();
+    for (int b = threadIdx.x; b < bh.NB; b += blockDim.x)
+      if (s_hist[b]) atomicAdd((unsigned long long*)&bh.count[b], (unsigned long long)s_hist[b]);
   }
 }
 
@@ -538,11 +561,11 @@ void launch_chunks(const int32_t* cstart, int64_t K, const int64_t* item_start, 
 void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
-                      uint32_t* out, int32_t* err, bool prune, int num_cus, hipStream_t st) {
+                      uint32_t* out, int32_t* err, bool prune, const BucketHist& bh, int num_cus, hipStream_t st) {
   if (nchunks <= 0) return;
   int64_t grid = (int64_t)num_cus * tun.blocks_per_cu;
   grid = ((grid + 7) / 8) * 8;
-  const size_t lds = (size_t)4 * tun.stack_depth * WAVE * sizeof(int2);
+  const size_t lds = (size_t)4 * tun.stack_depth * WAVE * sizeof(int2) + (emit ? (size_t)bh.NB * 4 : 0);
   // A chunk's items each have at most work_cap leaf pairs, hence fewer than
   // 2 work_cap recursion nodes; every wave step resolves at least one.
   const int64_t step_cap = (int64_t)tun.chunk_items * (2 * (int64_t)tun.work_cap + 2) + 1024;
@@ -552,7 +575,8 @@ void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, con
                  : (emit ? k_wspd<true, false, false>
                          : (split_recs ? k_wspd<false, true, false> : k_wspd<false, false, false>));
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds, st, T.inode, split_recs, items, chunk_first, chunk_end,
-                     xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, out, err);
+                     xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, out, err,
+                     emit ? bh : BucketHist{});
 }
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,
