@@ -44,8 +44,8 @@ constexpr int PPT = 8;         // pair records per thread in the bucket passes
 constexpr int PTILE = CB * PPT;
 constexpr int SORT_B = 512;    // threads per block of the row sort
 constexpr int SORT_WAVES = SORT_B / WAVE;
-constexpr int SORT_STAGE = 256;  // staged heads per wave of the row sort
-constexpr int WIN_WORDS = 14336;  // largest bitmap window: with the staging, 64 KiB of LDS
+constexpr int SORT_STAGE = 512;  // staged heads per wave of the row sort
+constexpr int WIN_WORDS = 24576;  // largest bitmap window (96 KiB; with the staging 112 KiB of LDS)
 constexpr int SORT_MAXG = WIN_WORDS / WAVE;  // groups of 64 words in a window
 constexpr int SORT_FILL = 4;                 // head loads per thread in flight in the row sort
 
@@ -589,8 +589,9 @@ void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const
   // the bitmap covers the largest pair's cells at once when they fit
   const int win = (int)std::min<int64_t>(WIN_WORDS, std::max<int64_t>(1, (max_pair_cells + 31) / 32));
   const size_t lds = (size_t)win * 4 + (size_t)SORT_WAVES * SORT_STAGE * 4;
-  // persistent: two blocks per compute unit fit beside each other's LDS
-  const int64_t grid = std::min<int64_t>(N, (int64_t)num_cus * 2);
+  // persistent: two blocks per compute unit when their LDS fits (a bitmap
+  // of up to 50 KiB, i.e. pairs of up to 400k cells), else one
+  const int64_t grid = std::min<int64_t>(N, (int64_t)num_cus * (lds <= 80 * 1024 ? 2 : 1));
   hipLaunchKernelGGL(k_row_sort, dim3((unsigned)grid), dim3(SORT_B), lds, st, cpair, cell_start, ncells, cij, ca,
                      rowcnt, off, heads, N, win, col, cost);
 }

@@ -187,13 +187,43 @@ def test_edge_cases(orc, ctx):
     assert ctx.approx_batch([nan], [A], check=False)[0].status == w1.W1_EINVAL
 
 
-def test_bracket_against_exact(orc, ctx):
-    _say("[gpu] bracket vs Hungarian")
-    for k in range(10):
-        A, B = pdsynth.exp_pd(400, 2 * k), pdsynth.exp_pd(400, 2 * k + 1)
-        g = ctx.approx(A, B, eps=0.1)
-        ex = orc.exact_w1(A, B)
-        assert g.lower_bound <= ex <= g.w1 <= 1.1 * ex
+def _exact_gold():
+    import json
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "exact_w1.json")) as f:
+        return json.load(f)
+
+
+def test_bracket_against_exact(ctx):
+    """RWMD <= exact W1 <= w1 <= (1 + eps) exact W1 on 100 pairs of 400 + 400
+    points at eps 0.1, end to end (host flow included); exact W1 by Hungarian
+    matching, stored by tests/golden/make_exact_brackets.py (oracle only)."""
+    _say("[gpu] bracket vs Hungarian, 100 pairs of 400+400 points")
+    ex = [float.fromhex(x) for x in _exact_gold()["c1"]["w1"]]
+    As = [pdsynth.exp_pd(400, 2 * k) for k in range(len(ex))]
+    Bs = [pdsynth.exp_pd(400, 2 * k + 1) for k in range(len(ex))]
+    res = ctx.approx_batch(As, Bs, eps=0.1)
+    for k, (g, e) in enumerate(zip(res, ex)):
+        assert g.status == 0 and g.flow_solved == 1, k
+        assert g.lower_bound <= e <= g.w1 <= 1.1 * e, (k, g.lower_bound, e, g.w1)
+        assert (1 - 0.01) * e <= g.w1_paper <= 1.1 * e, k
+
+
+def test_bracket_batched_small_pairs(ctx):
+    """The same bracket on every pair of the batched workload (4096 pairs,
+    100 to 50k points per diagram, FP32) with n_A + n_B <= 3000: 1081 pairs,
+    solved end to end in one batch call at eps 0.1."""
+    _say("[gpu] bracket vs Hungarian, batched workload pairs with n_A + n_B <= 3000")
+    gold = _exact_gold()["c3_small"]
+    idx, ex = gold["index"], [float.fromhex(x) for x in gold["w1"]]
+    sizes = pdsynth.batch_sizes(2 * 4096, 3)
+    na, nb = sizes[0::2], sizes[1::2]
+    As = [pdsynth.exp_pd(int(na[i]), 10 + 2 * i, dtype=np.float32) for i in idx]
+    Bs = [pdsynth.exp_pd(int(nb[i]), 11 + 2 * i, dtype=np.float32) for i in idx]
+    res = ctx.approx_batch(As, Bs, eps=0.1)
+    for i, g, e in zip(idx, res, ex):
+        assert g.status == 0 and g.flow_solved == 1, i
+        assert g.lower_bound <= e <= g.w1 <= 1.1 * e, (i, g.lower_bound, e, g.w1)
 
 
 def test_batch_equals_single_and_oracle(orc, ctx):
