@@ -76,8 +76,9 @@ def parse():
     ap.add_argument("--no-nn-search", action="store_true",
                     help="learned form: only the embedding workload (no labels, training or 1-NN search)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
-    ap.add_argument("--stress", action="store_true",
-                    help="also count the WSPD of the 2M+2M Pareto stress pair (30%% duplicates) at --stress-eps")
+    ap.add_argument("--no-stress", action="store_true",
+                    help="skip the 2M+2M Pareto stress pair (30%% duplicates): WSPD count at --stress-eps and "
+                         "the emission of one arena fill of pair records")
     ap.add_argument("--stress-eps", type=float, default=0.01)
     ap.add_argument("--batch-pairs", type=int, default=4096)
     ap.add_argument("--loop-sample", type=int, default=256,
@@ -153,6 +154,24 @@ def run_batch(ctx, args):
     t_loop = time.perf_counter() - t0
     same = all(x.n_pairs == y.n_pairs and x.n_cells == y.n_cells for x, y in zip(rs_batch, rs_loop))
     same = same and all(res[i].n_pairs == rs_loop[j].n_pairs for j, i in enumerate(sample))
+    # every pair record of the batch written once, streamed through a
+    # recycled arena, with per-pair record checksums
+    t_cur = ctx.tuning
+    ctx.tuning = dict(t_cur, stream_arena_pairs=1 << 30, stream_max_rounds=0)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rst = ctx.approx_batch(dA, dB, eps=args.eps, flags=flags)
+        torch.cuda.synchronize()
+        t_stream = time.perf_counter() - t0
+    finally:
+        ctx.tuning = t_cur
+    streamed = sum(r.n_pairs_streamed for r in rst)
+    stream = {"what": "the same batch with every WSPD pair record emitted through a 2^30-record arena that each "
+                      "run of chunks overwrites, with per-pair record checksums",
+              "seconds": t_stream, "pd_pairs_per_s": K / t_stream, "pairs_written": streamed,
+              "all_written": bool(streamed == wspd and all(r.n_pairs_streamed == r.n_pairs for r in rst)),
+              "record_GBs": 12 * streamed / t_stream / 1e9}
     return {
         "workload": f"{K} pairs, points per diagram log-uniform in [100, 50k] (birth U[0,1), persistence "
                     f"Exponential(mean 0.05), FP32), eps={args.eps}, a0-a4 with WSPD pairs counted",
@@ -165,6 +184,7 @@ def run_batch(ctx, args):
         "batch_over_loop": t_loop / t_sb,
         "identical_counts": bool(same),
         "tuning": ctx.tuning, "tuning_from_cache": bool(tuned), "gen_s": gen_s,
+        "streamed": stream,
     }
 
 
@@ -181,7 +201,9 @@ def run_stress(ctx, args):
     A, B = pdsynth.pareto_pd(2_000_000, 0), pdsynth.pareto_pd(2_000_000, 1)
     tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
     t0_tuning = ctx.tuning
-    ctx.tuning = dict(stack_depth=32, work_cap=65536, chunk_items=64, blocks_per_cu=2)
+    arena = 1 << 33  # pair records per arena fill (103 GB)
+    ctx.tuning = dict(t0_tuning, stack_depth=32, work_cap=65536, chunk_items=64, blocks_per_cu=2,
+                      stream_arena_pairs=arena, stream_max_rounds=1)
     try:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -193,12 +215,19 @@ def run_stress(ctx, args):
         return {"error": str(e), "eps": args.stress_eps}
     finally:
         ctx.tuning = t0_tuning
+    em_ms = kt["stream_emit_ms"]
+    em_bytes = 12 * r.n_pairs_streamed
     return {"workload": f"2M+2M Pareto(1.5, cap 10) diagrams with 30% exact duplicates, FP32, eps={args.stress_eps}, "
-                        "a0-a4 with WSPD pairs counted",
+                        "a0-a4 with every WSPD pair counted, then the first arena fill of pair records emitted",
             "s": r.s, "grid_exp": r.grid_exp, "n_points_after_cancellation": r.n_points, "cells": r.n_cells,
             "wspd_pairs": r.n_pairs, "seconds": dt, "wspd_pairs_per_s": r.n_pairs / dt,
             "stage_ms": {k: round(r.t_ms[k], 3) for k in w1.T_NAMES[:5]},
-            "worklist_ms": kt["worklist_ms"], "count_ms": kt["count_ms"]}
+            "worklist_ms": kt["worklist_ms"], "count_ms": kt["count_ms"],
+            "emission": {"what": "k_wspd<emit> over the longest prefix of work-list chunks whose pair records "
+                                 "fit one arena fill (12 B per record)",
+                         "pairs": r.n_pairs_streamed, "arena_pairs": arena, "ms": round(em_ms, 3),
+                         "achieved_GBs": round(em_bytes / (em_ms * 1e-3) / 1e9, 1) if em_ms > 0 else None,
+                         "frac": round(em_bytes / (em_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if em_ms > 0 else None}}
 
 
 def run_nn(ctx, args):
@@ -296,10 +325,9 @@ def cpu_baseline(A, B, eps):
     """The CPU oracle as it stands, single thread, on the same workload:
     0-condensation, RWMD, grid, tree and the WSPD recursion with pairs
     counted rather than stored (the oracle would need ~44 GB for the pair
-    list), each stage timed on its own (the oracle's own stage split: O1 with
-    O0, O2 RWMD, O3-O6 grid and tree, O7 WSPD).  The flow O9 is timed
-    separately on the 400 + 400-point workload.  The oracle's network O8 is
-    not timed here."""
+    list), each step timed on its own by the oracle's own timers.  The
+    network O8 and the flow O9 are timed separately on the 400 + 400-point
+    workload (end to end there)."""
     import oracle
     import pdsynth
 
@@ -307,31 +335,21 @@ def cpu_baseline(A, B, eps):
     t0 = time.perf_counter()
     r = oracle.run(A, B, eps=eps, flags=oracle.ORC_COUNT_ONLY, fetch=False)
     dt = time.perf_counter() - t0
-    # the stages up to the tree alone, then the RWMD alone given L
-    t1 = time.perf_counter()
-    oracle.run(A, B, eps=eps, flags=oracle.ORC_STOP_AFTER_TREE, fetch=False)
-    t_tree = time.perf_counter() - t1
-    t1 = time.perf_counter()
-    oracle.run(A, B, eps=eps, flags=oracle.ORC_STOP_AFTER_TREE | oracle.ORC_SKIP_RWMD, given_L=r.L, fetch=False)
-    t_norwmd = time.perf_counter() - t1
     C1a, C1b = pdsynth.exp_pd(400, 0), pdsynth.exp_pd(400, 1)
     t1 = time.perf_counter()
-    oracle.run(C1a, C1b, eps=0.1, flags=oracle.ORC_NO_FLOW, fetch=False)
-    t_c1_nf = time.perf_counter() - t1
-    t1 = time.perf_counter()
-    oracle.run(C1a, C1b, eps=0.1, fetch=False)
+    c1 = oracle.run(C1a, C1b, eps=0.1, fetch=False)
     t_c1 = time.perf_counter() - t1
     n = A.shape[0] + B.shape[0]
+    steps = {k: round(v, 4) for k, v in r.stage_s.items() if k not in ("O8 network", "O9 flow")}
     return {"value": n / dt, "unit": "pts/s", "cores": 1, "kind": "oracle",
             "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
             "sample": f"the full {A.shape[0]}+{B.shape[0]}-point pair at eps={eps}, single thread, "
-                      f"stages O0-O7 with WSPD pairs counted not stored ({r.n_pairs} pairs), {dt:.1f} s",
-            "seconds": dt, "pairs": r.n_pairs,
-            "stage_s": {"O0-O2 condense + RWMD": round(t_tree - t_norwmd, 3),
-                        "O3-O6 grid + tree": round(t_norwmd, 3),
-                        "O7 WSPD (count)": round(dt - t_tree, 3)},
-            "c1_flow_s": {"what": "400+400-point pair at eps 0.1: O9 successive-shortest-path flow alone",
-                          "seconds": round(t_c1 - t_c1_nf, 3)}}
+                      f"steps O0-O7 with WSPD pairs counted not stored ({r.n_pairs} pairs), {dt:.1f} s",
+            "seconds": dt, "pairs": r.n_pairs, "stage_s": steps,
+            "c1": {"what": "400+400-point pair at eps 0.1, end to end on one thread (exact W1 by "
+                           "successive shortest paths)",
+                   "pd_pairs_per_s": 1.0 / t_c1,
+                   "stage_s": {k: round(v, 4) for k, v in c1.stage_s.items()}}}
 
 
 def main():
@@ -358,7 +376,7 @@ def main():
         ctx.approx(tA, tB, eps=args.eps, flags=flags)
     torch.cuda.synchronize()
     stage = {k: 0.0 for k in w1.T_NAMES[:6]}
-    kern = {k: 0.0 for k in w1.Context.KERNEL_TIMES if k not in ("pairs", "unused_ms")}
+    kern = {k: 0.0 for k in w1.Context.KERNEL_TIMES if k not in ("pairs", "stream_emit_ms")}
     r = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -428,6 +446,17 @@ def main():
             "frac": round(net_bytes / (a45_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         },
     }
+    # the same step with the diagonal-dominated pairs left out (W1_PRUNE)
+    ctx.approx(tA, tB, eps=args.eps, flags=flags | w1.PRUNE)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        rp = ctx.approx(tA, tB, eps=args.eps, flags=flags | w1.PRUNE)
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t1) / args.steps
+    out["pruned_step"] = {"what": "the same step with diagonal-dominated WSPD pairs left out (F* unchanged)",
+                          "ms_per_step": 1e3 * tp, "points_per_s": n / tp, "wspd_pairs": rp.n_pairs,
+                          "network_arcs": rp.n_arcs}
     if args.calib_copy_mb:
         src = torch.empty(args.calib_copy_mb << 20, dtype=torch.uint8, device="cuda").fill_(1)
         dst = torch.empty_like(src)
@@ -445,11 +474,19 @@ def main():
         for _ in range(reps):
             g = ctx.approx(C1a, C1b, eps=0.1)
         e2e = (time.perf_counter() - t1) / reps
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            gp = ctx.approx(C1a, C1b, eps=0.1, flags=w1.PRUNE)
+        e2p = (time.perf_counter() - t1) / reps
         out["c1_end_to_end"] = {"pd_pairs_per_s": 1.0 / e2e, "ms": 1e3 * e2e, "w1": g.w1,
-                                "flow_ms": g.t_ms["flow"], "wspd_pairs": g.n_pairs}
+                                "flow_ms": g.t_ms["flow"], "wspd_pairs": g.n_pairs,
+                                "pruned": {"what": "diagonal-dominated WSPD pairs left out (same F* and W1)",
+                                           "pd_pairs_per_s": 1.0 / e2p, "ms": 1e3 * e2p, "w1": gp.w1,
+                                           "flow_ms": gp.t_ms["flow"], "wspd_pairs": gp.n_pairs,
+                                           "same_w1": bool(gp.w1 == g.w1)}}
     if not args.no_batch:
         out["batched"] = run_batch(ctx, args)
-    if args.stress:
+    if not args.no_stress:
         out["stress"] = run_stress(ctx, args)
     if not args.no_nn:
         out["learned"] = run_nn(ctx, args)

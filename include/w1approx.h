@@ -142,6 +142,17 @@ typedef struct {
   int64_t n_arcs;     /* directed arcs: 2 n_pairs + n_diag (0 with COUNT_ONLY) */
   int64_t flow_cost;  /* F* in units of g/2 (-1 if not solved)                 */
   int64_t pivots;     /* network simplex pivots                                 */
+  /* Streamed emission (W1_COUNT_ONLY with w1_tuning.stream_arena_pairs > 0):
+   * the pairs written through the arena, and an order-independent checksum
+   * of them (test bookkeeping): with h(u, v, c) = (((u + 1) K1 + (v + 1)) K2
+   * + c) K3 mod 2^64 over the pair records (u = representative of the
+   * pair's first node, v of its second, c the cost, local cell ids),
+   * K1 = 0x9E3779B97F4A7C15, K2 = 0xC2B2AE3D27D4EB4F,
+   * K3 = 0x165667B19E3779F9: pair_checksum = (sum h, sum h^2) mod 2^64.
+   * The checksum covers all of the pair's n_pairs when n_pairs_streamed
+   * equals n_pairs. */
+  int64_t n_pairs_streamed;
+  uint64_t pair_checksum[2];
 
   /* Network (W1_KEEP_NETWORK), built on the device in compressed sparse row
    * form.  Node ids: cells 0..n_cells-1 in Morton order of (cell_i, cell_j),
@@ -259,11 +270,26 @@ int w1_device_network_get(w1_ctx *ctx, int64_t k, w1_device_network *out);
  * The set of WSPD pairs, every count, the network and W1 do not depend on
  * these; the order of the pairs within a diagram pair's output does (it is
  * deterministic for a given tuning, and compact_records does not change it).
+ * stream_arena_pairs and stream_max_rounds (see w1_tuning) only apply to
+ * W1_COUNT_ONLY calls: the WSPD pairs are then written, in runs that reuse
+ * one arena, without building the network -- emission measured at sizes
+ * whose pair list does not fit in memory.
  * set_tuning returns W1_EINVAL for out-of-range values. */
 typedef struct {
   int32_t stack_depth, work_cap, chunk_items, blocks_per_cu;
   int64_t max_points_per_launch;
   int32_t compact_records;
+  int32_t stream_max_rounds;  /* streamed emission: at most this many arena */
+                              /* fills (0 = until every pair is written)    */
+  int64_t stream_arena_pairs; /* streamed emission: with W1_COUNT_ONLY and  */
+                              /* a value > 0, the emit pass also runs, over */
+                              /* consecutive runs of work-list chunks whose */
+                              /* pairs fit this many 12-byte records, each  */
+                              /* run overwriting the one device arena; the  */
+                              /* result then carries n_pairs_streamed and   */
+                              /* pair_checksum, and kernel time [4] the     */
+                              /* emit time.  A chunk larger than the arena  */
+                              /* gives W1_EOVERFLOW.  0 = off               */
 } w1_tuning;
 
 int w1_ctx_get_tuning(const w1_ctx *ctx, w1_tuning *out);
@@ -272,11 +298,12 @@ int w1_ctx_set_tuning(w1_ctx *ctx, const w1_tuning *t);
 /* Device times (ms, HIP events on the call's stream) of the last call's
  * WSPD and network kernels: [0] work-list build (expansion rounds, item
  * sort, chunking), [1] count pass, [2] emit pass (which also takes the
- * network's bucket histogram), [3] the number of pairs emitted; then the
- * passes that sort the network into rows: [4] 0 (no separate histogram
- * pass), [5] bucket scatter, [6] row histogram, [7] row scatter (with the
- * degree scan before it), [8] row sort (with the diagonal rows and row
- * pointers).  n is the capacity of ms (>= 4); entries beyond 8 are 0. */
+ * network's bucket histogram), [3] the number of pairs emitted; [4] the
+ * streamed emission's emit passes, all arena fills together (0 unless
+ * streaming); then the passes that sort the network into rows: [5] bucket
+ * scatter, [6] row histogram, [7] row scatter (with the degree scan before
+ * it), [8] row sort (with the diagonal rows and row pointers).  n is the
+ * capacity of ms (>= 4); entries beyond 8 are 0. */
 int w1_ctx_last_kernel_times(const w1_ctx *ctx, double *ms, int n);
 
 /* Host network simplex on any uncapacitated network with non-negative integer

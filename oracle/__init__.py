@@ -35,6 +35,8 @@ ORC_KEEP_PAIR_NODES = 8
 ORC_SKIP_RWMD = 16
 ORC_PRUNE = 32
 
+STAGE_NAMES = ("O0-O1 condense", "O2 RWMD", "O3-O5 grid + Morton", "O6 tree", "O7 WSPD", "O8 network",
+               "O9 flow")
 _K = dict(STATUS=0, NA=1, NB=2, N=3, NLOC=4, S=5, E=6, M0=7, NCELLS=8, NNODES=9, ROOT=10,
           NPAIRS=11, FLOW=12, SA=13, SB=14, FA=15, FB=16, CHK1=17, CHK2=18)
 _D = dict(L=0, LA=1, LB=2, W1=3, W1P=4, G=5, EPSC=6)
@@ -78,6 +80,8 @@ def lib():
         L.orc_csr.restype = i64
         L.orc_mcf.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp]
         L.orc_mcf.restype = i64
+        L.orc_stage_seconds.argtypes = [vp, vp]
+        L.orc_stage_seconds.restype = None
         L.orc_choose_s.argtypes = [f64, f64]
         L.orc_choose_s.restype = ip
         L.orc_grid_exponent.argtypes = [f64, f64, i64]
@@ -125,6 +129,7 @@ class Result:
     nodes: np.ndarray | None = None
     root: int = -1
     pairs: dict = field(default_factory=dict)
+    stage_s: dict = field(default_factory=dict)
 
 
 def run(A, B, eps: float = 0.1, kappa: float = 0.1, s_override: int = 0, flags: int = 0,
@@ -147,6 +152,9 @@ def run(A, B, eps: float = 0.1, kappa: float = 0.1, s_override: int = 0, flags: 
         r.W1, r.W1_paper, r.flow, r.n_pairs = gd("W1"), gd("W1P"), gi("FLOW"), gi("NPAIRS")
         r.checksum = (gi("CHK1") & (2**64 - 1), gi("CHK2") & (2**64 - 1))
         r.root = gi("ROOT")
+        st = np.zeros(7)
+        L_.orc_stage_seconds(h, _ptr(st))
+        r.stage_s = dict(zip(STAGE_NAMES, st.tolist()))
         if not fetch:
             return r
         m = gi("NLOC")

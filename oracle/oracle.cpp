@@ -33,6 +33,7 @@
 //   O9  exact min-cost flow (successive shortest paths)     (Def. transshipment)
 //   O10 W1 = (g/2)(F* + n), W1_paper = (g/2) F*
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -97,7 +98,18 @@ struct Oracle {
   // O9/O10
   int64_t flow_cost = -1;
   double W1 = 0, W1_paper = 0;
+  // wall time of each step (seconds; bookkeeping for the CPU baseline, not
+  // part of the method): O0+O1, O2, O3+O4+O5, O6, O7, O8, O9
+  double stage_s[7] = {0, 0, 0, 0, 0, 0, 0};
 };
+
+// Seconds since t0, and t0 moved to now (stage timing bookkeeping).
+double lap(std::chrono::steady_clock::time_point& t0) {
+  auto t1 = std::chrono::steady_clock::now();
+  double d = std::chrono::duration<double>(t1 - t0).count();
+  t0 = t1;
+  return d;
+}
 
 // ---------------------------------------------------------------- helpers --
 
@@ -630,7 +642,9 @@ int orc_run(void* p, const double* A, int64_t nA, const double* B, int64_t nB, d
   o.count_only = (flags & ORC_COUNT_ONLY) != 0;
   o.keep_nodes = (flags & ORC_KEEP_PAIR_NODES) != 0;
   o.prune = (flags & ORC_PRUNE) != 0;
+  auto t0 = std::chrono::steady_clock::now();
   int st = condense0(o, A, nA, B, nB);
+  o.stage_s[0] = lap(t0);
   if (st) return o.status = st;
   o.eps = eps;
   o.eps_c = kappa * eps;
@@ -644,19 +658,25 @@ int orc_run(void* p, const double* A, int64_t nA, const double* B, int64_t nB, d
   } else {
     rwmd(o);
   }
+  o.stage_s[1] = lap(t0);
   if (!(o.L > 0.0)) return o.status = ORC_ERANGE;
   o.e = grid_exponent(o.eps_c, o.L, o.n);
   st = grid_condense(o);
+  o.stage_s[2] = lap(t0);
   if (st) return o.status = st;
   tree(o);
+  o.stage_s[3] = lap(t0);
   if (flags & ORC_STOP_AFTER_TREE) return o.status = ORC_OK;
   wspd(o);
+  o.stage_s[4] = lap(t0);
   if (o.count_only || (flags & ORC_NO_FLOW)) return o.status = ORC_OK;
   std::vector<Arc> arcs;
   std::vector<int64_t> supply;
   network(o, &arcs, &supply);
+  o.stage_s[5] = lap(t0);
   int fst = 0;
   o.flow_cost = ssp((int64_t)o.cells.size() + 2, arcs, supply, nullptr, nullptr, &fst);
+  o.stage_s[6] = lap(t0);
   if (fst) return o.status = fst;
   o.W1 = std::ldexp((double)(o.flow_cost + o.n), o.e - 1);
   o.W1_paper = std::ldexp((double)o.flow_cost, o.e - 1);
@@ -707,6 +727,12 @@ double orc_f64(void* p, int key) {
     case D_EPSC: return o.eps_c;
   }
   return 0.0;
+}
+
+// Wall time of each step of the last run: O0+O1, O2, O3-O5, O6, O7, O8, O9.
+void orc_stage_seconds(void* p, double* out7) {
+  Oracle& o = *(Oracle*)p;
+  for (int k = 0; k < 7; ++k) out7[k] = o.stage_s[k];
 }
 
 // Arrays (caller allocates with the sizes above) ------------------------------

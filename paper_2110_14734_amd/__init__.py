@@ -52,6 +52,7 @@ class _Result(ctypes.Structure):
         ("n_a", ctypes.c_int64), ("n_b", ctypes.c_int64), ("n_locations", ctypes.c_int64),
         ("n_cells", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_arcs", ctypes.c_int64),
         ("flow_cost", ctypes.c_int64), ("pivots", ctypes.c_int64),
+        ("n_pairs_streamed", ctypes.c_int64), ("pair_checksum", ctypes.c_uint64 * 2),
         ("cell_i", _P), ("cell_j", _P), ("cell_ca", _P), ("cell_cb", _P), ("supply", _P),
         ("row_ptr", _P), ("col", _P), ("cost", _P), ("n_diag", ctypes.c_int64),
         ("loc_b", _P), ("loc_d", _P), ("loc_w", _P), ("loc_t", _P),
@@ -77,7 +78,8 @@ class _TrainParams(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("stack_depth", ctypes.c_int32), ("work_cap", ctypes.c_int32), ("chunk_items", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("max_points_per_launch", ctypes.c_int64),
-                ("compact_records", ctypes.c_int32)]
+                ("compact_records", ctypes.c_int32), ("stream_max_rounds", ctypes.c_int32),
+                ("stream_arena_pairs", ctypes.c_int64)]
 
 
 class _NNParams(ctypes.Structure):
@@ -214,6 +216,8 @@ class Result:
     flow_cost: int
     pivots: int
     t_ms: dict
+    n_pairs_streamed: int = 0
+    pair_checksum: tuple = (0, 0)
     network: dict = field(default_factory=dict)
     stages: dict = field(default_factory=dict)
 
@@ -230,7 +234,8 @@ def _convert(r: _Result) -> Result:
         status=r.status, w1=r.w1, w1_paper=r.w1_paper, lower_bound=r.lower_bound, grid=r.grid,
         grid_exp=r.grid_exp, s=r.s, flow_solved=bool(r.flow_solved), n_points=r.n_points, n_a=r.n_a,
         n_b=r.n_b, n_locations=r.n_locations, n_cells=r.n_cells, n_pairs=r.n_pairs, n_arcs=r.n_arcs,
-        flow_cost=r.flow_cost, pivots=r.pivots, t_ms={k: r.t_ms[i] for i, k in enumerate(T_NAMES)})
+        flow_cost=r.flow_cost, pivots=r.pivots, t_ms={k: r.t_ms[i] for i, k in enumerate(T_NAMES)},
+        n_pairs_streamed=r.n_pairs_streamed, pair_checksum=(int(r.pair_checksum[0]), int(r.pair_checksum[1])))
     if r.row_ptr:
         nc = r.n_cells
         out.network = dict(
@@ -399,7 +404,7 @@ class Context:
         if rc != 0:
             raise W1Error(rc, "w1_ctx_set_tuning")
 
-    KERNEL_TIMES = ("worklist_ms", "count_ms", "emit_ms", "pairs", "unused_ms", "bucket_scatter_ms",
+    KERNEL_TIMES = ("worklist_ms", "count_ms", "emit_ms", "pairs", "stream_emit_ms", "bucket_scatter_ms",
                     "row_hist_ms", "row_scatter_ms", "row_sort_ms")
 
     def kernel_times(self) -> dict:

@@ -50,6 +50,8 @@ struct Ctx {
   uint64_t* hpin = nullptr;  // pinned host scratch for read-backs
   WspdTuning tun{16, 1024, 512, 5, 1};
   int64_t max_points = int64_t(1) << 22;  // points per launch group of a batch
+  int64_t stream_arena = 0;                // streamed emission: arena capacity in pair records (0 = off)
+  int32_t stream_rounds = 0;               // streamed emission: arena fills at most (0 = all)
   int64_t K_base = 0;                      // first pair of the last launch group
   std::vector<DBuf*> all;
   // points
@@ -66,6 +68,8 @@ struct Ctx {
   // the unsorted row heads; l1 the bucket-major arc entries and later the
   // sorted heads (col); costb the arc costs; rp the per-pair row pointers
   DBuf pu, l1, costb, rp, supply, rstart, bcnt, bstart, tfirst, bcur, rowcnt, rowcur, bflag, bpos, deg, off, parc;
+  // streamed emission: per-chunk pair checksums
+  DBuf csum;
   // per pair
   DBuf pairs;
   PairArrays P{};
@@ -91,7 +95,7 @@ struct Ctx {
                     &ndepth, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &cid, &pcap,
                     &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &l1, &costb, &rp,
                     &supply, &rstart, &bcnt, &bstart, &tfirst, &bcur, &rowcnt, &rowcur, &bflag, &bpos, &deg, &off,
-                    &parc, &pairs};
+                    &parc, &csum, &pairs};
     all.assign(std::begin(list), std::end(list));
     saved.resize(all.size());
   }

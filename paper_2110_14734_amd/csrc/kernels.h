@@ -129,6 +129,14 @@ struct BucketHist {
   uint64_t* count = nullptr;
 };
 
+// Emit pass output placement: records of chunk k start at word
+// 3 (chunk_off[k] - base) of the output; with chunk_sum set, the pass also
+// writes each chunk's record checksum (sum h, sum h^2) to chunk_sum[2k..].
+struct StreamOut {
+  int64_t base = 0;
+  uint64_t* chunk_sum = nullptr;
+};
+
 struct WspdTuning {
   int stack_depth;  // per-lane DFS stack entries (LDS), items need height sum < this
   int work_cap;     // items need |U| * |V| <= cap to skip the expansion rounds; this is the
@@ -169,8 +177,8 @@ void launch_chunks(const int32_t* cstart, int64_t K, const int64_t* item_start, 
 void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
-                      uint32_t* out, int32_t* err, bool prune, const BucketHist& bh, int num_cus,
-                      hipStream_t st);
+                      uint32_t* out, int32_t* err, bool prune, const BucketHist& bh, const StreamOut& so,
+                      int num_cus, hipStream_t st);
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,
                         hipStream_t st);

@@ -408,6 +408,9 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
 
   // ---------------------------------------------------------------- a4 --
   int64_t Ptot = 0;
+  double stream_ms = 0;                 // streamed emission (count-only calls)
+  std::vector<int64_t> stream_n;        // per pair: pairs streamed
+  std::vector<uint64_t> stream_chk;     // per pair: checksum of the streamed records
   bool timed = false, emitted = false;
   int32_t* derr = need<int32_t>(c, c.err, 64);
   fill_u32((uint32_t*)derr, 0, 1, st);
@@ -506,7 +509,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       fill_u32(xc, 0, 8, st);
       check(c, hipEventRecord(c.kev[1], st));
       launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr, prune,
-                       BucketHist{}, c.num_cus, st);
+                       BucketHist{}, StreamOut{}, c.num_cus, st);
       check(c, hipGetLastError());
       check(c, hipEventRecord(c.kev[2], st));
       scan_u64(ccnt, coff, nch, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(nch, 8)), st);
@@ -516,6 +519,49 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       trace(c, "wspd pairs", Ptot);
       fill_u64((uint64_t*)P.seg_hi, 0, K, st);
       launch_pair_totals(ccnt, coff, cp, nch, P.pair_start, (uint64_t*)P.seg_hi, P.npairs, K, st);
+      if ((o.flags & W1_COUNT_ONLY) && c.stream_arena > 0 && Ptot > 0) {
+        // streamed emission: runs of consecutive chunks whose pairs fit the
+        // arena, each run written over the previous one, with per-chunk
+        // checksums of the records
+        std::vector<uint64_t> hoff((size_t)nch), hcnt((size_t)nch);
+        readback(c, coff, hoff.data(), nch);
+        readback(c, ccnt, hcnt.data(), nch);
+        uint32_t* arena = need<uint32_t>(c, c.pu, 3 * c.stream_arena);
+        uint64_t* csum = need<uint64_t>(c, c.csum, 2 * nch);
+        fill_u64(csum, 0, 2 * nch, st);
+        int64_t c0 = 0;
+        for (int round = 0; c0 < nch && (c.stream_rounds == 0 || round < c.stream_rounds); ++round) {
+          int64_t c1 = c0;
+          while (c1 < nch && hoff[(size_t)c1] + hcnt[(size_t)c1] - hoff[(size_t)c0] <= (uint64_t)c.stream_arena) ++c1;
+          if (c1 == c0) throw StageError{W1_EOVERFLOW};  // one chunk holds more pairs than the arena
+          int32_t hr2[9];
+          for (int x = 0; x <= 8; ++x) hr2[x] = (int32_t)(c0 + ((c1 - c0) * x) / 8);
+          upload(c, xr, hr2, sizeof(hr2));
+          fill_u32(xc, 0, 8, st);
+          check(c, hipEventRecord(c.kev[3], st));
+          launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, arena, derr, prune,
+                           BucketHist{}, StreamOut{(int64_t)hoff[(size_t)c0], csum}, c.num_cus, st);
+          check(c, hipGetLastError());
+          check(c, hipEventRecord(c.kev[4], st));
+          check(c, hipEventSynchronize(c.kev[4]));
+          float ms = 0;
+          (void)hipEventElapsedTime(&ms, c.kev[3], c.kev[4]);
+          stream_ms += ms;
+          c0 = c1;
+        }
+        std::vector<uint64_t> hsum((size_t)(2 * c0));
+        std::vector<int32_t> hcp((size_t)c0);
+        readback(c, csum, hsum.data(), 2 * c0);
+        readback(c, cp, hcp.data(), c0);
+        stream_n.assign((size_t)K, 0);
+        stream_chk.assign((size_t)(2 * K), 0);
+        for (int64_t k = 0; k < c0; ++k) {
+          const size_t p = (size_t)hcp[(size_t)k];
+          stream_n[p] += (int64_t)hcnt[(size_t)k];
+          stream_chk[2 * p] += hsum[(size_t)(2 * k)];
+          stream_chk[2 * p + 1] += hsum[(size_t)(2 * k + 1)];
+        }
+      }
       if (!(o.flags & W1_COUNT_ONLY) && Ptot > 0) {
         // the records' buffer later holds the rows' unsorted heads, which
         // are placed by final arc number (2 Ptot WSPD arcs plus at most
@@ -536,7 +582,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         fill_u32(xc, 0, 8, st);
         check(c, hipEventRecord(c.kev[3], st));
         launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr, prune, bh,
-                         c.num_cus, st);
+                         StreamOut{}, c.num_cus, st);
         check(c, hipGetLastError());
         emitted = true;
       }
@@ -545,6 +591,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
   record(c, 5);
   for (double& x : c.kms) x = 0;
   c.kms[3] = (double)Ptot;
+  c.kms[4] = stream_ms;
 
   // ---------------------------------------------------------------- a5 --
   // The network in compressed sparse row form, sorted by (tail, head)
@@ -661,7 +708,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     (void)hipEventElapsedTime(&t[2], c.kev[7], c.kev[8]);
     (void)hipEventElapsedTime(&t[3], c.kev[8], c.kev[9]);
     (void)hipEventElapsedTime(&t[4], c.kev[9], c.kev[10]);
-    for (int i = 0; i < 5; ++i) c.kms[4 + i] = t[i];
+    for (int i = 1; i < 5; ++i) c.kms[4 + i] = t[i];
   }
   if (herr) throw StageError{W1_EOVERFLOW};
 
@@ -710,6 +757,11 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     r.rwmd_sum_b = (int64_t)h_sB[(size_t)p];
     r.rwmd_shift_a = h_FA[(size_t)p];
     r.rwmd_shift_b = h_FB[(size_t)p];
+    if (!stream_n.empty()) {
+      r.n_pairs_streamed = stream_n[(size_t)p];
+      r.pair_checksum[0] = stream_chk[2 * (size_t)p];
+      r.pair_checksum[1] = stream_chk[2 * (size_t)p + 1];
+    }
     for (int i = 0; i < 6; ++i) r.t_ms[i] = tms[i];
     if (r.status == 0 && r.n_points == 0) {
       r.w1 = r.w1_paper = 0.0;
@@ -1091,6 +1143,8 @@ int w1_ctx_get_tuning(const w1_ctx* c, w1_tuning* out) {
   out->blocks_per_cu = c->tun.blocks_per_cu;
   out->max_points_per_launch = c->max_points;
   out->compact_records = c->tun.compact;
+  out->stream_max_rounds = c->stream_rounds;
+  out->stream_arena_pairs = c->stream_arena;
   return W1_OK;
 }
 
@@ -1098,10 +1152,13 @@ int w1_ctx_set_tuning(w1_ctx* c, const w1_tuning* t) {
   if (!c || !t) return W1_EINVAL;
   if (t->stack_depth < 8 || t->stack_depth > 32 || t->work_cap < 1 || t->work_cap > (1 << 20) ||
       t->chunk_items < 1 || t->chunk_items > (1 << 20) || t->blocks_per_cu < 1 || t->blocks_per_cu > 16 ||
-      t->max_points_per_launch < 1 || (t->compact_records != 0 && t->compact_records != 1))
+      t->max_points_per_launch < 1 || (t->compact_records != 0 && t->compact_records != 1) ||
+      t->stream_max_rounds < 0 || t->stream_arena_pairs < 0 || t->stream_arena_pairs > (int64_t(1) << 36))
     return W1_EINVAL;
   c->tun = WspdTuning{t->stack_depth, t->work_cap, t->chunk_items, t->blocks_per_cu, t->compact_records};
   c->max_points = t->max_points_per_launch;
+  c->stream_rounds = t->stream_max_rounds;
+  c->stream_arena = t->stream_arena_pairs;
   return W1_OK;
 }
 

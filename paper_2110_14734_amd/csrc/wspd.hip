@@ -304,6 +304,12 @@ __device__ inline u32x3 make_emit(int4 c, int4 o, bool orient) {
   return u32x3{(uint32_t)(orient ? c.y : o.y), (uint32_t)(orient ? o.y : c.y), 2u * max(di, dj)};
 }
 
+// Checksum term of a pair record (u, v, cost) (see w1_result.pair_checksum).
+__device__ inline uint64_t record_hash(u32x3 m) {
+  const uint64_t x = ((uint64_t)m.x + 1) * 0x9E3779B97F4A7C15ull + ((uint64_t)m.y + 1);
+  return (x * 0xC2B2AE3D27D4EB4Full + (uint64_t)m.z) * 0x165667B19E3779F9ull;
+}
+
 // Lanes below this one whose bit is set in m, plus add.
 __device__ inline uint32_t lanes_set_below(uint64_t m, uint32_t add) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, add));
@@ -333,7 +339,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
                                               const int32_t* __restrict__ xcd_range, uint32_t* __restrict__ xcd_ctr, int s,
                                               int stack_depth, int64_t step_cap, uint64_t* __restrict__ chunk_cnt,
                                               const uint64_t* __restrict__ chunk_off, uint32_t* __restrict__ out,
-                                              int32_t* __restrict__ err, BucketHist bh) {
+                                              int32_t* __restrict__ err, BucketHist bh, StreamOut so) {
   static_assert(!(EMIT && COMPACT), "packed split records carry no representatives");
   extern __shared__ int2 s_stack[];
   const int wave = threadIdx.x / WAVE, lane = lane_id();
@@ -357,7 +363,8 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       if (k >= r1) break;
       int next = __builtin_amdgcn_readfirstlane(chunk_first[k]);
       const int end = __builtin_amdgcn_readfirstlane(chunk_end[k]);
-      uint32_t* obase = EMIT ? out + 3 * chunk_off[k] : nullptr;
+      uint32_t* obase = EMIT ? out + 3 * (chunk_off[k] - (uint64_t)so.base) : nullptr;
+      uint64_t h1 = 0, h2 = 0;  // streamed emission: the lane's checksum terms
       const uint64_t cs = EMIT && bh.NB > 0 ? (uint64_t)bh.cell_start[bh.chunk_pair[k]] : 0;
       uint64_t cursor = 0;
       bool has = false, overflow = false, runaway = false, orient = false;
@@ -474,6 +481,18 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
           if (e1) __builtin_nontemporal_store(m1, (u32x3_w*)(obase + 3 * lanes_set_below(b1, 0u)));
           if (e2) __builtin_nontemporal_store(m2, (u32x3_w*)(obase + 3 * lanes_set_below(b2, n1)));
           obase += 3 * (n1 + n2);
+          if (so.chunk_sum) {
+            if (e1) {
+              const uint64_t h = record_hash(m1);
+              h1 += h;
+              h2 += h * h;
+            }
+            if (e2) {
+              const uint64_t h = record_hash(m2);
+              h1 += h;
+              h2 += h * h;
+            }
+          }
           if (bh.NB > 0) {
             if (e1) {
               atomicAdd(&s_hist[(uint32_t)((cs + m1.x) >> bh.RB)], 1u);
@@ -490,6 +509,16 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       const bool bad = runaway || __ballot(overflow) != 0;
       if (bad) atomicOr(err, 1);
       if (!EMIT) chunk_cnt[k] = cursor;  // same value from every lane
+      if (EMIT && so.chunk_sum) {
+        for (int d = WAVE / 2; d > 0; d >>= 1) {
+          h1 += __shfl_xor(h1, d);
+          h2 += __shfl_xor(h2, d);
+        }
+        if (lane == 0) {
+          so.chunk_sum[2 * k] = h1;
+          so.chunk_sum[2 * k + 1] = h2;
+        }
+      }
     }
   }
   if (EMIT && bh.NB > 0) {
@@ -561,7 +590,8 @@ void launch_chunks(const int32_t* cstart, int64_t K, const int64_t* item_start, 
 void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
-                      uint32_t* out, int32_t* err, bool prune, const BucketHist& bh, int num_cus, hipStream_t st) {
+                      uint32_t* out, int32_t* err, bool prune, const BucketHist& bh, const StreamOut& so,
+                      int num_cus, hipStream_t st) {
   if (nchunks <= 0) return;
   int64_t grid = (int64_t)num_cus * tun.blocks_per_cu;
   grid = ((grid + 7) / 8) * 8;
@@ -576,7 +606,7 @@ void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, con
                          : (split_recs ? k_wspd<false, true, false> : k_wspd<false, false, false>));
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds, st, T.inode, split_recs, items, chunk_first, chunk_end,
                      xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, out, err,
-                     emit ? bh : BucketHist{});
+                     emit ? bh : BucketHist{}, emit ? so : StreamOut{});
 }
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,

@@ -9,6 +9,7 @@ import sys
 import numpy as np
 import pytest
 
+import cases
 import pdsynth
 
 pytestmark = pytest.mark.gpu
@@ -57,12 +58,27 @@ def same_network(a, b):
     return all(np.array_equal(a.network.get(f, np.zeros(0)), b.network.get(f, np.zeros(0))) for f in NET_KEYS)
 
 
-def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True, prune=False):
+def _stored_flows():
+    import json
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_flows.json")) as f:
+        return json.load(f)
+
+
+STORED = _stored_flows()
+
+
+def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True, prune=False, stored=None):
+    """Stage-by-stage parity with the oracle.  `stored` names the oracle's
+    optimal flow written by tests/golden/make_oracle_flows.py; the oracle
+    then runs without its (slow) flow solve.  Pruning leaves F* unchanged,
+    so a pruned case compares with the unpruned stored optimum."""
     import paper_2110_14734_amd as w1
 
     flags = w1.KEEP_NETWORK | w1.KEEP_STAGES | (0 if flow else w1.NO_FLOW) | (w1.PRUNE if prune else 0)
     g = ctx.approx(A, B, eps=eps, s_override=s_override, flags=flags)
-    oflags = (0 if flow else orc.ORC_NO_FLOW) | (orc.ORC_PRUNE if prune else 0)
+    oflow = flow and stored is None
+    oflags = (0 if oflow else orc.ORC_NO_FLOW) | (orc.ORC_PRUNE if prune else 0)
     r = orc.run(A, B, eps=eps, s_override=s_override, flags=oflags)
     assert r.status == 0 and g.status == 0
     # a0: net 0-condensation
@@ -94,27 +110,24 @@ def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True, prune=F
     assert g.n_pairs == r.n_pairs
     check_csr(net, orc.csr(A, B, eps=eps, s_override=s_override, prune=prune))
     # flow and W1
-    if flow:
+    if flow and stored is None:
         assert g.flow_cost == r.flow
         assert g.w1 == r.W1 and g.w1_paper == r.W1_paper
+    elif flow:
+        ref = STORED[stored]
+        assert g.flow_cost == ref["flow"]
+        assert g.w1 == float.fromhex(ref["W1"]) and g.w1_paper == float.fromhex(ref["W1_paper"])
     return g, r
 
 
-CASES = [
-    ("exp400_eps0.1", lambda: (pdsynth.exp_pd(400, 0), pdsynth.exp_pd(400, 1)), 0.1),
-    ("exp250_eps0.2", lambda: (pdsynth.exp_pd(250, 2), pdsynth.exp_pd(233, 3)), 0.2),
-    ("mix_f32_3000_eps0.2", lambda: (pdsynth.mixture_pd(3000, 4), pdsynth.mixture_pd(2777, 5)), 0.2),
-    ("pareto_dup_2000_eps0.5", lambda: (pdsynth.pareto_pd(2000, 6), pdsynth.pareto_pd(1500, 7)), 0.5),
-    ("int_overlap_eps0.3", lambda: (pdsynth.integer_pd(300, 8, hi=12), pdsynth.integer_pd(280, 9, hi=12)), 0.3),
-    ("exp_f32_odd_eps0.05", lambda: (pdsynth.exp_pd(129, 10, dtype=np.float32), pdsynth.exp_pd(65, 11, dtype=np.float32)), 0.05),
-]
+CASES = cases.STAGE_CASES
 
 
 @pytest.mark.parametrize("name,make,eps", CASES, ids=[c[0] for c in CASES])
 def test_stage_parity(orc, ctx, name, make, eps):
     _say(f"[gpu] stage parity {name}")
     A, B = make()
-    compare(orc, ctx, A, B, eps=eps)
+    compare(orc, ctx, A, B, eps=eps, stored=name)
 
 
 @pytest.mark.parametrize("name,make,eps", CASES, ids=[c[0] for c in CASES])
@@ -124,7 +137,7 @@ def test_prune_parity(orc, ctx, name, make, eps):
     unpruned optimum."""
     _say(f"[gpu] prune parity {name}")
     A, B = make()
-    g, r = compare(orc, ctx, A, B, eps=eps, prune=True)
+    g, r = compare(orc, ctx, A, B, eps=eps, prune=True, stored=name)
     full = ctx.approx(A, B, eps=eps)
     assert g.flow_cost == full.flow_cost and g.w1 == full.w1 and g.n_pairs <= full.n_pairs
 
@@ -154,8 +167,8 @@ def test_prune_batch_and_count_only(orc, ctx):
 @pytest.mark.parametrize("s_override", [1, 2, 3, 6, 12])
 def test_paper_mode_small_s(orc, ctx, s_override):
     _say(f"[gpu] s_override {s_override}")
-    A, B = pdsynth.exp_pd(500, 12), pdsynth.exp_pd(480, 13)
-    compare(orc, ctx, A, B, eps=0.1, s_override=s_override)
+    A, B = cases.small_s_pair()
+    compare(orc, ctx, A, B, eps=0.1, s_override=s_override, stored=f"small_s{s_override}")
 
 
 def test_edge_cases(orc, ctx):
@@ -230,18 +243,15 @@ def test_batch_equals_single_and_oracle(orc, ctx):
     _say("[gpu] batch vs single")
     import paper_2110_14734_amd as w1
 
-    sizes = pdsynth.batch_sizes(24, 99, lo=20, hi=3000)
-    As = [pdsynth.exp_pd(int(sizes[i]), 1000 + 2 * i, dtype=np.float32) for i in range(12)]
-    Bs = [pdsynth.exp_pd(int(sizes[12 + i]), 1001 + 2 * i, dtype=np.float32) for i in range(12)]
-    As[3] = np.zeros((0, 2), np.float32)
-    Bs[5] = As[5].copy()
+    As, Bs = cases.batch_pairs()
     flags = w1.KEEP_NETWORK
     batch = ctx.approx_batch(As, Bs, eps=0.2, flags=flags)
     for i in range(12):
         single = ctx.approx(As[i], Bs[i], eps=0.2, flags=flags)
-        r = orc.run(As[i], Bs[i], eps=0.2)
+        r = orc.run(As[i], Bs[i], eps=0.2, flags=orc.ORC_NO_FLOW)
+        ref = STORED[f"batch{i}"]
         for x in (batch[i], single):
-            assert x.w1 == r.W1 and x.flow_cost == (r.flow if r.n else 0) and x.n_pairs == r.n_pairs
+            assert x.w1 == float.fromhex(ref["W1"]) and x.flow_cost == ref["flow"] and x.n_pairs == r.n_pairs
             assert x.lower_bound == r.L
         assert same_network(batch[i], single)
         if r.n:
@@ -478,3 +488,87 @@ def test_rwmd_dense_cluster(orc, ctx):
     A, B = cluster(3000, 0), cluster(3000, 1)
     g, _ = compare(orc, ctx, A, B, eps=0.2, flow=False)
     assert g.n_locations > 6000
+
+
+def _stream_gold():
+    import json
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "stream_checksums.json")) as f:
+        return json.load(f)
+
+
+def test_stream_emission_small(orc, ctx):
+    """Streamed emission through a small arena (many runs of chunks, each
+    overwriting the last): every pair's records are written once, the
+    streamed count equals the oracle's pair count and the record checksum
+    equals the oracle's; a cap on the runs writes a prefix; an arena smaller
+    than one chunk is an error."""
+    import paper_2110_14734_amd as w1
+
+    _say("[gpu] streamed emission, small arena")
+    t0 = ctx.tuning
+    try:
+        for name, make, eps in cases.STAGE_CASES:
+            A, B = make()
+            r = orc.run(A, B, eps=eps, flags=orc.ORC_COUNT_ONLY, fetch=False)
+            ctx.tuning = dict(t0, stream_arena_pairs=max(20_000, r.n_pairs // 7))
+            g = ctx.approx(A, B, eps=eps, flags=w1.COUNT_ONLY)
+            assert g.n_pairs == r.n_pairs == g.n_pairs_streamed, name
+            assert g.pair_checksum == tuple(r.checksum), name
+            assert ctx.kernel_times()["stream_emit_ms"] > 0
+        A, B = cases.STAGE_CASES[2][1]()
+        n = orc.run(A, B, eps=0.2, flags=orc.ORC_COUNT_ONLY, fetch=False).n_pairs
+        ctx.tuning = dict(t0, stream_arena_pairs=n // 5, stream_max_rounds=1)
+        g = ctx.approx(A, B, eps=0.2, flags=w1.COUNT_ONLY)
+        assert g.n_pairs == n and 0 < g.n_pairs_streamed <= n // 5
+        ctx.tuning = dict(t0, stream_arena_pairs=1)
+        with pytest.raises(w1.W1Error) as e:
+            ctx.approx(A, B, eps=0.2, flags=w1.COUNT_ONLY)
+        assert e.value.code == w1.W1_EOVERFLOW
+    finally:
+        ctx.tuning = t0
+
+
+def test_stream_emission_batched_sample(ctx):
+    """Every 16th pair of the 4096-pair batched workload (256 pairs, eps 0.1)
+    streamed in one batch call: per-pair counts and record checksums equal
+    the oracle's (stored by tests/golden/make_stream_checksums.py)."""
+    import paper_2110_14734_amd as w1
+
+    _say("[gpu] streamed emission, batched workload sample")
+    gold = _stream_gold()["batch"]
+    sizes = pdsynth.batch_sizes(2 * 4096, 3)
+    idx = gold["index"]
+    As = [pdsynth.exp_pd(int(sizes[2 * i]), 10 + 2 * i, dtype=np.float32) for i in idx]
+    Bs = [pdsynth.exp_pd(int(sizes[2 * i + 1]), 11 + 2 * i, dtype=np.float32) for i in idx]
+    t0 = ctx.tuning
+    try:
+        ctx.tuning = dict(t0, stream_arena_pairs=1 << 28)
+        res = ctx.approx_batch(As, Bs, eps=0.1, flags=w1.COUNT_ONLY)
+    finally:
+        ctx.tuning = t0
+    for i, g, ref in zip(idx, res, gold["pairs"]):
+        assert g.n_pairs == ref["n_pairs"] == g.n_pairs_streamed, i
+        assert list(g.pair_checksum) == ref["checksum"], i
+
+
+def test_stream_emission_stress_subsample(ctx):
+    """A 200k + 200k subsample of the stress workload (Pareto persistence,
+    30% exact duplicates) at eps 0.01 (s = 503) with the large-item tuning
+    of the stress run: the pair count and the checksum of every record,
+    streamed through a 2^30-record arena, equal the oracle's."""
+    import paper_2110_14734_amd as w1
+
+    _say("[gpu] streamed emission, stress subsample eps 0.01")
+    ref = _stream_gold()["stress"]
+    A, B = pdsynth.pareto_pd(200_000, 0), pdsynth.pareto_pd(200_000, 1)
+    t0 = ctx.tuning
+    try:
+        ctx.tuning = dict(t0, stack_depth=32, work_cap=65536, chunk_items=64, blocks_per_cu=2,
+                          stream_arena_pairs=1 << 30)
+        g = ctx.approx(A, B, eps=0.01, flags=w1.COUNT_ONLY)
+    finally:
+        ctx.tuning = t0
+    assert g.s == ref["s"] == 503
+    assert g.n_pairs == ref["n_pairs"] == g.n_pairs_streamed
+    assert list(g.pair_checksum) == ref["checksum"]
