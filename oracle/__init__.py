@@ -34,11 +34,12 @@ ORC_NO_FLOW = 4
 ORC_KEEP_PAIR_NODES = 8
 ORC_SKIP_RWMD = 16
 ORC_PRUNE = 32
+ORC_L2 = 64
 
 STAGE_NAMES = ("O0-O1 condense", "O2 RWMD", "O3-O5 grid + Morton", "O6 tree", "O7 WSPD", "O8 network",
                "O9 flow")
 _K = dict(STATUS=0, NA=1, NB=2, N=3, NLOC=4, S=5, E=6, M0=7, NCELLS=8, NNODES=9, ROOT=10,
-          NPAIRS=11, FLOW=12, SA=13, SB=14, FA=15, FB=16, CHK1=17, CHK2=18)
+          NPAIRS=11, FLOW=12, SA=13, SB=14, FA=15, FB=16, CHK1=17, CHK2=18, COSTK=19)
 _D = dict(L=0, LA=1, LB=2, W1=3, W1P=4, G=5, EPSC=6)
 
 
@@ -84,7 +85,7 @@ def lib():
         L.orc_stage_seconds.restype = None
         L.orc_choose_s.argtypes = [f64, f64]
         L.orc_choose_s.restype = ip
-        L.orc_grid_exponent.argtypes = [f64, f64, i64]
+        L.orc_grid_exponent.argtypes = [f64, f64, i64, ip]
         L.orc_grid_exponent.restype = ip
         _lib = L
     return _lib
@@ -130,6 +131,7 @@ class Result:
     root: int = -1
     pairs: dict = field(default_factory=dict)
     stage_s: dict = field(default_factory=dict)
+    K: int = 0
 
 
 def run(A, B, eps: float = 0.1, kappa: float = 0.1, s_override: int = 0, flags: int = 0,
@@ -152,6 +154,7 @@ def run(A, B, eps: float = 0.1, kappa: float = 0.1, s_override: int = 0, flags: 
         r.W1, r.W1_paper, r.flow, r.n_pairs = gd("W1"), gd("W1P"), gi("FLOW"), gi("NPAIRS")
         r.checksum = (gi("CHK1") & (2**64 - 1), gi("CHK2") & (2**64 - 1))
         r.root = gi("ROOT")
+        r.K = gi("COSTK")
         st = np.zeros(7)
         L_.orc_stage_seconds(h, _ptr(st))
         r.stage_s = dict(zip(STAGE_NAMES, st.tolist()))
@@ -187,7 +190,7 @@ def run(A, B, eps: float = 0.1, kappa: float = 0.1, s_override: int = 0, flags: 
         L_.orc_free(h)
 
 
-def network(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False):
+def network(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False, l2=False):
     """Sparse transshipment network of the oracle: (src, dst, cost, supply).
     prune: leave out the diagonal-dominated WSPD pairs (O7')."""
     L_ = lib()
@@ -195,7 +198,8 @@ def network(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False):
     h = L_.orc_new()
     try:
         st = L_.orc_run(h, _ptr(A64), A64.shape[0], _ptr(B64), B64.shape[0], float(eps), float(kappa),
-                        int(s_override), ORC_NO_FLOW | (ORC_PRUNE if prune else 0), 0.0)
+                        int(s_override), ORC_NO_FLOW | (ORC_PRUNE if prune else 0) | (ORC_L2 if l2 else 0),
+                        0.0)
         if st != 0:
             raise RuntimeError(f"oracle status {st}")
         m = int(L_.orc_network(h, None, None, None, None))
@@ -208,7 +212,7 @@ def network(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False):
         L_.orc_free(h)
 
 
-def csr(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False):
+def csr(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False, l2=False):
     """The oracle's network in compressed sparse row form (O8): arcs sorted by
     (tail, head).  Returns dict(row_ptr, col, cost, supply, n_cells).
     prune: leave out the diagonal-dominated WSPD pairs (O7')."""
@@ -217,7 +221,8 @@ def csr(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False):
     h = L_.orc_new()
     try:
         st = L_.orc_run(h, _ptr(A64), A64.shape[0], _ptr(B64), B64.shape[0], float(eps), float(kappa),
-                        int(s_override), ORC_NO_FLOW | (ORC_PRUNE if prune else 0), 0.0)
+                        int(s_override), ORC_NO_FLOW | (ORC_PRUNE if prune else 0) | (ORC_L2 if l2 else 0),
+                        0.0)
         if st != 0:
             raise RuntimeError(f"oracle status {st}")
         N = int(L_.orc_i64(h, _K["NCELLS"]))
@@ -255,8 +260,8 @@ def choose_s(eps: float, kappa: float = 0.1) -> int:
     return int(lib().orc_choose_s(float(eps), float(kappa)))
 
 
-def grid_exponent(eps_c: float, L: float, n: int) -> int:
-    return int(lib().orc_grid_exponent(float(eps_c), float(L), int(n)))
+def grid_exponent(eps_c: float, L: float, n: int, l2: bool = False) -> int:
+    return int(lib().orc_grid_exponent(float(eps_c), float(L), int(n), int(bool(l2))))
 
 
 # ------------------------------------------------------------- exact W1 --
@@ -265,14 +270,27 @@ def _clean(X):
     return X[X[:, 1] != X[:, 0]]
 
 
-def exact_w1(A, B) -> float:
-    """Exact W1 (L-infinity) by a min-weight perfect matching on Bi(A, B).
+def _ground(P, Q, l2):
+    """Ground distances between point sets (rows (birth, death))."""
+    db = P[:, None, 0] - Q[None, :, 0]
+    dd = P[:, None, 1] - Q[None, :, 1]
+    return np.hypot(db, dd) if l2 else np.maximum(np.abs(db), np.abs(dd))
+
+
+def _to_diag(P, l2):
+    """Distance to the diagonal: (d - b)/sqrt(2) (Euclidean), (d - b)/2 (L-infinity)."""
+    return (P[:, 1] - P[:, 0]) / np.sqrt(2.0) if l2 else 0.5 * (P[:, 1] - P[:, 0])
+
+
+def exact_w1(A, B, l2=False) -> float:
+    """Exact W1 by a min-weight perfect matching on Bi(A, B), L-infinity or
+    (l2=True) Euclidean ground metric.
 
     Rows are the points of A followed by the diagonal projections of B's
     points; columns are B's points followed by A's projections (Sec. 4.3):
-    A-B edges cost the L-infinity distance, a point and its own projection
-    cost the distance to the diagonal (d - b)/2, projection-projection edges
-    cost 0, every other edge is forbidden.
+    A-B edges cost the ground distance, a point and its own projection cost
+    the distance to the diagonal, projection-projection edges cost 0, every
+    other edge is forbidden.
     """
     from scipy.optimize import linear_sum_assignment
 
@@ -280,12 +298,12 @@ def exact_w1(A, B) -> float:
     na, nb = A.shape[0], B.shape[0]
     if na + nb == 0:
         return 0.0
-    dA = 0.5 * (A[:, 1] - A[:, 0])
-    dB = 0.5 * (B[:, 1] - B[:, 0])
+    dA = _to_diag(A, l2)
+    dB = _to_diag(B, l2)
     big = 4.0 * (float(dA.sum() + dB.sum()) + 1.0) + 4.0 * float(np.abs(np.concatenate([A, B])).max(initial=0.0)) * (na + nb)
     C = np.full((na + nb, nb + na), big)
     if na and nb:
-        C[:na, :nb] = np.maximum(np.abs(A[:, None, 0] - B[None, :, 0]), np.abs(A[:, None, 1] - B[None, :, 1]))
+        C[:na, :nb] = _ground(A, B, l2)
     C[:na, nb:] = np.where(np.eye(na, dtype=bool), dA[:, None], big) if na else C[:na, nb:]
     C[na:, :nb] = np.where(np.eye(nb, dtype=bool), dB[None, :], big) if nb else C[na:, :nb]
     C[na:, nb:] = 0.0
@@ -293,19 +311,20 @@ def exact_w1(A, B) -> float:
     return float(C[r, c].sum())
 
 
-def brute_w1(A, B) -> float:
+def brute_w1(A, B, l2=False) -> float:
     """Exact W1 by enumerating every partial matching (tiny inputs only)."""
     A, B = _clean(A), _clean(B)
     na, nb = A.shape[0], B.shape[0]
-    dA = [0.5 * (a[1] - a[0]) for a in A]
-    dB = [0.5 * (b[1] - b[0]) for b in B]
+    dA = list(_to_diag(A, l2))
+    dB = list(_to_diag(B, l2))
     best = float("inf")
     for k in range(min(na, nb) + 1):
         for ia in itertools.combinations(range(na), k):
             for ib in itertools.permutations(range(nb), k):
                 cost = 0.0
                 for x, y in zip(ia, ib):
-                    cost += max(abs(A[x, 0] - B[y, 0]), abs(A[x, 1] - B[y, 1]))
+                    cost += (float(np.hypot(A[x, 0] - B[y, 0], A[x, 1] - B[y, 1])) if l2
+                             else max(abs(A[x, 0] - B[y, 0]), abs(A[x, 1] - B[y, 1])))
                 cost += sum(dA[x] for x in range(na) if x not in ia)
                 cost += sum(dB[y] for y in range(nb) if y not in ib)
                 best = min(best, cost)
@@ -313,10 +332,12 @@ def brute_w1(A, B) -> float:
 
 
 # ------------------------------------------------------ brute-force checks --
-def wspd_coverage(res: Result) -> None:
+def wspd_coverage(res: Result, l2: bool = False) -> None:
     """Assert every unordered pair of distinct cells is covered by exactly one
-    output pair and every output pair is s-well-separated (L-infinity boxes
-    recomputed from the member cells).  Needs ORC_KEEP_PAIR_NODES."""
+    output pair and every output pair is s-well-separated (boxes recomputed
+    from the member cells; L-infinity: gap >= s * longest side; Euclidean:
+    gap >= s * longest diagonal, on exact integer squares).  Needs
+    ORC_KEEP_PAIR_NODES."""
     N = res.cells["i"].shape[0]
     ci, cj = res.cells["i"], res.cells["j"]
     nodes = res.nodes
@@ -327,9 +348,16 @@ def wspd_coverage(res: Result) -> None:
         cover[lu:hu + 1, lv:hv + 1] += 1
         iu, ju = ci[lu:hu + 1], cj[lu:hu + 1]
         iv, jv = ci[lv:hv + 1], cj[lv:hv + 1]
-        diam = max(iu.max() - iu.min(), ju.max() - ju.min(), iv.max() - iv.min(), jv.max() - jv.min())
-        gap = max(0, iu.min() - iv.max(), iv.min() - iu.max(), ju.min() - jv.max(), jv.min() - ju.max())
-        assert gap >= res.s * diam, (U, V, gap, diam)
+        if l2:
+            gi = max(0, int(iu.min() - iv.max()), int(iv.min() - iu.max()))
+            gj = max(0, int(ju.min() - jv.max()), int(jv.min() - ju.max()))
+            d2 = max(int(iu.max() - iu.min()) ** 2 + int(ju.max() - ju.min()) ** 2,
+                     int(iv.max() - iv.min()) ** 2 + int(jv.max() - jv.min()) ** 2)
+            assert gi * gi + gj * gj >= res.s ** 2 * d2, (U, V, gi, gj, d2)
+        else:
+            diam = max(iu.max() - iu.min(), ju.max() - ju.min(), iv.max() - iv.min(), jv.max() - jv.min())
+            gap = max(0, iu.min() - iv.max(), iv.min() - iu.max(), ju.min() - jv.max(), jv.min() - ju.max())
+            assert gap >= res.s * diam, (U, V, gap, diam)
     sym = cover + cover.T
     off = ~np.eye(N, dtype=bool)
     assert np.all(sym[off] == 1), "pair of cells not covered exactly once"

@@ -10,8 +10,9 @@
 //
 // Everything is single-threaded FP64 / int64 with the steps in the paper's
 // order.  The ground metric is L-infinity (the integer-grid reading of the
-// method); where the paper is silent or ambiguous the reading taken is stated
-// next to the step.  Every function with a pin in the test suite says so in
+// method, costs in units of g/2) or, with ORC_L2, the paper's own Euclidean
+// metric (costs rounded up to integers in units of g 2^-K); where the paper
+// is silent or ambiguous the reading taken is stated next to the step.  Every function with a pin in the test suite says so in
 // its comment; nothing here is "parity unpinned".
 //
 // Steps
@@ -92,6 +93,8 @@ struct Oracle {
   bool count_only = false;
   bool keep_nodes = false;
   bool prune = false;       // diagonal-dominance pruning (O7')
+  bool l2 = false;          // Euclidean ground metric (the paper's own)
+  int K = 0;                // l2: costs are integers in units of g 2^-K
   int64_t n_pairs = 0;
   uint64_t chk1 = 0, chk2 = 0;
   std::vector<int64_t> pu, pv, pc, pnu, pnv;
@@ -230,6 +233,34 @@ double cheapest_arc(const std::vector<Loc>& other, double b, double d) {
   return best;
 }
 
+// Euclidean ground metric (the paper's own, Sec. 4.2 problem statement):
+// the distance of (b, d) to the diagonal is (d - b)/sqrt(2), here
+// (d - b) * R with R the double nearest to 1/sqrt(2) (just above it).  The
+// nearest location of the other diagram minimises
+// q = (b - bv)^2 + (d - dv)^2 (each operation one IEEE double operation, in
+// this order), and t = min(sqrt(q_min), (d - b) R) with the correctly rounded
+// square root.  The scan in birth order stops once the squared birth gap
+// exceeds the smallest q found: q is at least that square (every operation
+// is monotone), so no later location can lower q_min.
+const double R_SQRT1_2 = 0x1.6a09e667f3bcdp-1;
+
+double cheapest_arc_l2(const std::vector<Loc>& other, double b, double d) {
+  double q = std::numeric_limits<double>::infinity();
+  size_t k = (size_t)(std::lower_bound(other.begin(), other.end(), b,
+                                       [](const Loc& l, double x) { return l.b < x; }) - other.begin());
+  for (size_t r = k; r < other.size(); ++r) {
+    const double gb = b - other[r].b, gd = d - other[r].d;
+    if (gb * gb > q) break;
+    q = std::min(q, gb * gb + gd * gd);
+  }
+  for (size_t r = k; r-- > 0;) {
+    const double gb = b - other[r].b, gd = d - other[r].d;
+    if (gb * gb > q) break;
+    q = std::min(q, gb * gb + gd * gd);
+  }
+  return std::min(std::sqrt(q), (d - b) * R_SQRT1_2);
+}
+
 void rwmd(Oracle& o) {
   const size_t m = o.locs.size();
   o.t.assign(m, 0.0);
@@ -239,7 +270,8 @@ void rwmd(Oracle& o) {
   std::vector<double> termA, termB;
   for (size_t u = 0; u < m; ++u) {
     const Loc& a = o.locs[u];
-    const double best = cheapest_arc(a.w > 0 ? sideB : sideA, a.b, a.d);
+    const double best = o.l2 ? cheapest_arc_l2(a.w > 0 ? sideB : sideA, a.b, a.d)
+                             : cheapest_arc(a.w > 0 ? sideB : sideA, a.b, a.d);
     o.t[u] = best;
     o.term[u] = (double)(a.w > 0 ? a.w : -a.w) * best;
     if (a.w > 0) termA.push_back(o.term[u]);
@@ -275,8 +307,13 @@ int choose_s(double eps, double eps_c) {
   return s;
 }
 
-int grid_exponent(double eps_c, double L, int64_t n) {
+// Euclidean metric: a point moves by at most half a cell diagonal, g/sqrt(2),
+// and the distance to the diagonal is 1-Lipschitz, so W1 of the snapped
+// diagrams is within n g/sqrt(2) of W1; g <= sqrt(2) eps_c L / n keeps that
+// below eps_c W1 (Prop. delta-condensation's sqrt(2)).
+int grid_exponent(double eps_c, double L, int64_t n, bool l2) {
   double gmax = ((2.0 * eps_c) * L) / (double)n;
+  if (l2) gmax = gmax * R_SQRT1_2;
   double gsafe = gmax * (1.0 - 0x1p-40);
   int E = 0;
   std::frexp(gsafe, &E);  // 2^(E-1) <= gsafe < 2^E
@@ -390,11 +427,26 @@ void tree(Oracle& o) {
 // diameter.  Pins: brute-force coverage (every pair of distinct cells in
 // exactly one output pair), separation of every pair, spanner stretch by
 // all-pairs shortest paths.
+// Euclidean costs (O8 with the l2 metric), integers in units of g 2^-K: the
+// distance of two cell centres, ceil(sqrt(di^2 + dj^2) 2^K), and of a cell
+// centre to the diagonal, ceil((j - i) R 2^K), each from IEEE double
+// operations in this order (the integer sum converted to double, correctly
+// rounded square root, exact scaling by 2^K).  Rounding up keeps every cost
+// at least the exact distance (up to one rounding of the square root), so
+// the network's optimum still bounds W1 of the condensed diagrams from above.
+int64_t cost_l2(int64_t di, int64_t dj, int K) {
+  return (int64_t)std::ceil(std::ldexp(std::sqrt((double)(di * di + dj * dj)), K));
+}
+int64_t diag_cost_l2(int64_t di_dj, int K) {
+  return (int64_t)std::ceil(std::ldexp((double)di_dj * R_SQRT1_2, K));
+}
+
 void emit(Oracle& o, int64_t U, int64_t V) {
   const Node& a = o.nodes[U];
   const Node& b = o.nodes[V];
   int64_t u = a.lo, v = b.lo;
-  int64_t c = 2 * std::max(std::llabs(o.cells[u].i - o.cells[v].i), std::llabs(o.cells[u].j - o.cells[v].j));
+  int64_t c = o.l2 ? cost_l2(o.cells[u].i - o.cells[v].i, o.cells[u].j - o.cells[v].j, o.K)
+                   : 2 * std::max(std::llabs(o.cells[u].i - o.cells[v].i), std::llabs(o.cells[u].j - o.cells[v].j));
   ++o.n_pairs;
   uint64_t h = pair_mix((uint64_t)u, (uint64_t)v, (uint64_t)c);
   o.chk1 += h;
@@ -435,7 +487,38 @@ bool dominated(const Node& a, const Node& b) {
   return 2 * dist >= (a.maxj - a.mini) + (b.maxj - b.mini);
 }
 
+// Euclidean reading of the separation (Sec. 5.3: balls of the larger
+// diameter at distance at least s times that diameter): the boxes' Euclidean
+// gap is at least s times the larger box diagonal, tested exactly on squares
+// in 128-bit integers; the node with the longer diagonal is split (ties
+// split the second node).  The spanner stretch (s+2)/(s-2) holds with
+// Euclidean diameters by the same induction.
+void visit_l2(Oracle& o, int64_t U, int64_t V) {
+  const Node& a = o.nodes[U];
+  const Node& b = o.nodes[V];
+  const int64_t gi = std::max<int64_t>(0, std::max(a.mini - b.maxi, b.mini - a.maxi));
+  const int64_t gj = std::max<int64_t>(0, std::max(a.minj - b.maxj, b.minj - a.maxj));
+  const int64_t da = (a.maxi - a.mini) * (a.maxi - a.mini) + (a.maxj - a.minj) * (a.maxj - a.minj);
+  const int64_t db = (b.maxi - b.mini) * (b.maxi - b.mini) + (b.maxj - b.minj) * (b.maxj - b.minj);
+  const __int128 dist2 = (__int128)gi * gi + (__int128)gj * gj;
+  if (dist2 >= (__int128)o.s * o.s * std::max(da, db)) {
+    emit(o, U, V);
+    return;
+  }
+  if (da > db) {
+    visit_l2(o, a.left, V);
+    visit_l2(o, a.right, V);
+  } else {
+    visit_l2(o, U, b.left);
+    visit_l2(o, U, b.right);
+  }
+}
+
 void visit(Oracle& o, int64_t U, int64_t V) {
+  if (o.l2) {
+    visit_l2(o, U, V);
+    return;
+  }
   const Node& a = o.nodes[U];
   const Node& b = o.nodes[V];
   if (o.prune && dominated(a, b)) return;
@@ -586,6 +669,7 @@ void network(const Oracle& o, std::vector<Arc>* arcs, std::vector<int64_t>* supp
   }
   for (int64_t c = 0; c < N; ++c) {
     int64_t dd = o.cells[(size_t)c].j - o.cells[(size_t)c].i;
+    if (o.l2) dd = diag_cost_l2(dd, o.K);
     if (o.cells[(size_t)c].cA > 0) arcs->push_back({c, N, dd});
     if (o.cells[(size_t)c].cB > 0) arcs->push_back({N + 1, c, dd});
   }
@@ -629,6 +713,7 @@ enum {
   ORC_KEEP_PAIR_NODES = 8,
   ORC_SKIP_RWMD = 16,   // take L from the caller (for timing later stages alone)
   ORC_PRUNE = 32,       // diagonal-dominance pruning of the WSPD pairs (O7')
+  ORC_L2 = 64,          // Euclidean ground metric
 };
 
 void* orc_new(void) { return new Oracle(); }
@@ -642,6 +727,8 @@ int orc_run(void* p, const double* A, int64_t nA, const double* B, int64_t nB, d
   o.count_only = (flags & ORC_COUNT_ONLY) != 0;
   o.keep_nodes = (flags & ORC_KEEP_PAIR_NODES) != 0;
   o.prune = (flags & ORC_PRUNE) != 0;
+  o.l2 = (flags & ORC_L2) != 0;
+  if (o.l2 && o.prune) return o.status = ORC_EINVAL;  // pruning is exact for integer L-infinity costs only
   auto t0 = std::chrono::steady_clock::now();
   int st = condense0(o, A, nA, B, nB);
   o.stage_s[0] = lap(t0);
@@ -660,10 +747,19 @@ int orc_run(void* p, const double* A, int64_t nA, const double* B, int64_t nB, d
   }
   o.stage_s[1] = lap(t0);
   if (!(o.L > 0.0)) return o.status = ORC_ERANGE;
-  o.e = grid_exponent(o.eps_c, o.L, o.n);
+  o.e = grid_exponent(o.eps_c, o.L, o.n, o.l2);
   st = grid_condense(o);
   o.stage_s[2] = lap(t0);
   if (st) return o.status = st;
+  if (o.l2) {
+    // cost scale 2^K: every cost is at most about bitlen(X) + K bits and F*
+    // at most n times the largest diagonal cost, so K = 61 - bitlen(n) -
+    // bitlen(X) keeps F* below 2^62 (X: the largest shifted coordinate)
+    int64_t X = 1;
+    for (const Cell& c : o.cells) X = std::max(X, std::max(c.i, c.j));
+    o.K = std::min(30, 61 - bitlen((uint64_t)o.n) - bitlen((uint64_t)X));
+    if (o.K < 0) return o.status = ORC_ERANGE;
+  }
   tree(o);
   o.stage_s[3] = lap(t0);
   if (flags & ORC_STOP_AFTER_TREE) return o.status = ORC_OK;
@@ -678,15 +774,20 @@ int orc_run(void* p, const double* A, int64_t nA, const double* B, int64_t nB, d
   o.flow_cost = ssp((int64_t)o.cells.size() + 2, arcs, supply, nullptr, nullptr, &fst);
   o.stage_s[6] = lap(t0);
   if (fst) return o.status = fst;
-  o.W1 = std::ldexp((double)(o.flow_cost + o.n), o.e - 1);
-  o.W1_paper = std::ldexp((double)o.flow_cost, o.e - 1);
+  if (o.l2) {  // W1 = g (F* 2^-K + n / sqrt(2)): the condensation's n g / sqrt(2) added back
+    o.W1_paper = std::ldexp((double)o.flow_cost, o.e - o.K);
+    o.W1 = o.W1_paper + (double)o.n * std::ldexp(R_SQRT1_2, o.e);
+  } else {
+    o.W1 = std::ldexp((double)(o.flow_cost + o.n), o.e - 1);
+    o.W1_paper = std::ldexp((double)o.flow_cost, o.e - 1);
+  }
   return o.status = ORC_OK;
 }
 
 // Scalars ------------------------------------------------------------------
 enum {
   K_STATUS, K_NA, K_NB, K_N, K_NLOC, K_S, K_E, K_M0, K_NCELLS, K_NNODES, K_ROOT, K_NPAIRS, K_FLOW,
-  K_SA, K_SB, K_FA, K_FB, K_CHK1, K_CHK2
+  K_SA, K_SB, K_FA, K_FB, K_CHK1, K_CHK2, K_COSTK
 };
 int64_t orc_i64(void* p, int key) {
   Oracle& o = *(Oracle*)p;
@@ -710,6 +811,7 @@ int64_t orc_i64(void* p, int key) {
     case K_FB: return o.FB;
     case K_CHK1: return (int64_t)o.chk1;
     case K_CHK2: return (int64_t)o.chk2;
+    case K_COSTK: return o.K;
   }
   return 0;
 }
@@ -831,6 +933,6 @@ int64_t orc_mcf(int64_t nn, int64_t m, const int64_t* src, const int64_t* dst, c
 }
 
 int orc_choose_s(double eps, double kappa) { return choose_s(eps, kappa * eps); }
-int orc_grid_exponent(double eps_c, double L, int64_t n) { return grid_exponent(eps_c, L, n); }
+int orc_grid_exponent(double eps_c, double L, int64_t n, int l2) { return grid_exponent(eps_c, L, n, l2 != 0); }
 
 }  // extern "C"

@@ -559,3 +559,209 @@ def test_prune_closed_forms(orc):
         assert pr.W1 == full.W1
         ex = orc.exact_w1(p, q)
         assert full.L <= ex <= pr.W1 <= 1.1 * ex
+
+
+# ------------------------------------------------------ Euclidean metric --
+R_SQRT1_2 = float.fromhex("0x1.6a09e667f3bcdp-1")
+
+
+def test_l2_exact_w1_pins(orc):
+    # closed forms: one point, (d - b)/sqrt(2); one point each, the cheaper
+    # of matching them and sending both to the diagonal
+    p, q = np.array([[0.25, 1.75]]), np.array([[0.5, 1.5]])
+    assert orc.exact_w1(p, np.zeros((0, 2)), l2=True) == pytest.approx(1.5 / np.sqrt(2), rel=1e-15)
+    assert orc.exact_w1(p, q, l2=True) == pytest.approx(min(np.hypot(0.25, 0.25), (1.5 + 1.0) / np.sqrt(2)), rel=1e-15)
+    far = np.array([[10.0, 10.5]])
+    assert orc.exact_w1(p, far, l2=True) == pytest.approx((1.5 + 0.5) / np.sqrt(2), rel=1e-15)
+    rng = np.random.default_rng(15)
+    for trial in range(30):
+        na, nb = rng.integers(0, 4, 2)
+        A = pdsynth.exp_pd(int(na), 3000 + trial, mean_pers=0.3)
+        B = pdsynth.exp_pd(int(nb), 4000 + trial, mean_pers=0.3)
+        assert orc.exact_w1(A, B, l2=True) == pytest.approx(orc.brute_w1(A, B, l2=True), rel=1e-12, abs=1e-12)
+    # L-infinity <= Euclidean <= sqrt(2) L-infinity for the ground costs, and
+    # the diagonal costs differ by the factor sqrt(2)/2 ... 1: W1 keeps order
+    A, B = pdsynth.exp_pd(40, 5), pdsynth.exp_pd(35, 6)
+    assert orc.exact_w1(A, B) <= orc.exact_w1(A, B, l2=True) * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("case", ["exp", "cluster", "ties"])
+def test_l2_rwmd_nearest_neighbour_bruteforce(orc, case):
+    # every location's cost t = min(sqrt(q_min), (d - b) R) against an
+    # exhaustive scan with the same IEEE operations, bit for bit
+    if case == "exp":
+        A, B = pdsynth.exp_pd(700, 31), pdsynth.exp_pd(650, 32)
+    elif case == "cluster":
+        rng = np.random.default_rng(4)
+        b = 0.5 + 1e-3 * rng.random(600)
+        A = np.stack([b[:300], b[:300] + 0.2 + 1e-3 * rng.random(300)], 1)
+        B = np.stack([b[300:], b[300:] + 0.2 + 1e-3 * rng.random(300)], 1)
+    else:
+        g = np.arange(12) * 0.25
+        P = np.array([(x, y) for x in g for y in g if y > x])
+        A, B = P[::2], P[1::2] + np.array([0.0, 0.125])
+    r = orc.run(A, B, eps=0.1, flags=orc.ORC_L2 | orc.ORC_NO_FLOW)
+    lb, ld, lw = r.locs["b"], r.locs["d"], r.locs["w"]
+    for side in (1, -1):
+        me, other = np.flatnonzero(np.sign(lw) == side), np.flatnonzero(np.sign(lw) == -side)
+        gb = lb[me][:, None] - lb[other][None, :]
+        gd = ld[me][:, None] - ld[other][None, :]
+        q = gb * gb + gd * gd
+        qmin = q.min(axis=1) if other.size else np.full(me.size, np.inf)
+        t = np.minimum(np.sqrt(qmin), (ld[me] - lb[me]) * R_SQRT1_2)
+        assert np.array_equal(t, r.locs["t"][me])
+
+
+@pytest.mark.parametrize("eps", [0.2, 0.1, 0.05])
+def test_l2_bracket(orc, eps):
+    # RWMD <= exact <= W1 <= (1 + eps) exact with the Euclidean metric; the
+    # paper's value within [(1 - eps_c), (1 + eps)] of exact
+    for seed in range(10):
+        A = pdsynth.exp_pd(45, 100 + 2 * seed)
+        B = pdsynth.exp_pd(40, 101 + 2 * seed)
+        r = orc.run(A, B, eps=eps, flags=orc.ORC_L2)
+        ex = orc.exact_w1(A, B, l2=True)
+        assert r.status == 0
+        assert r.L <= ex * (1 + 1e-12) and ex <= r.W1 <= (1 + eps) * ex
+        assert (1 - r.eps_c) * ex <= r.W1_paper <= (1 + eps) * ex
+    A, B = pdsynth.exp_pd(400, 0), pdsynth.exp_pd(400, 1)
+    r = orc.run(A, B, eps=eps, flags=orc.ORC_L2)
+    ex = orc.exact_w1(A, B, l2=True)
+    assert r.L <= ex <= r.W1 <= (1 + eps) * ex
+
+
+@pytest.mark.parametrize("s_override", [1, 3, 12, 53])
+def test_l2_wspd_coverage(orc, s_override):
+    for seed in range(2):
+        A = pdsynth.exp_pd(24, 150 + seed, mean_pers=0.3)
+        B = pdsynth.exp_pd(22, 160 + seed, mean_pers=0.3)
+        r = orc.run(A, B, eps=0.2, s_override=s_override,
+                    flags=orc.ORC_L2 | orc.ORC_KEEP_PAIR_NODES | orc.ORC_NO_FLOW)
+        assert r.cells["i"].shape[0] >= 30
+        orc.wspd_coverage(r, l2=True)
+
+
+@pytest.mark.parametrize("s_override", [4, 9, 28])
+def test_l2_spanner_stretch(orc, s_override):
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import shortest_path
+
+    A = pdsynth.exp_pd(80, 170, mean_pers=0.2)
+    B = pdsynth.exp_pd(70, 171, mean_pers=0.2)
+    r = orc.run(A, B, eps=0.2, s_override=s_override, flags=orc.ORC_L2 | orc.ORC_NO_FLOW)
+    N = r.cells["i"].shape[0]
+    ci, cj = r.cells["i"].astype(float), r.cells["j"].astype(float)
+    u, v = r.pairs["u"], r.pairs["v"]
+    G = coo_matrix((np.hypot(ci[u] - ci[v], cj[u] - cj[v]), (u, v)), shape=(N, N)).tocsr()
+    D = shortest_path(G, directed=False)
+    direct = np.hypot(ci[:, None] - ci[None, :], cj[:, None] - cj[None, :])
+    t = (s_override + 2) / (s_override - 2)
+    off = ~np.eye(N, dtype=bool)
+    assert (D[off] <= t * direct[off] * (1 + 1e-12)).all()
+
+
+def test_l2_costs_rounded_up(orc):
+    # every cost is ceil(2^K x distance) computed in doubles: not below the
+    # exact distance by more than a rounding of the square root, and less
+    # than one unit above it (50-digit decimal arithmetic as the judge)
+    from decimal import Decimal, getcontext
+
+    getcontext().prec = 50
+    A, B = pdsynth.mixture_pd(300, 180), pdsynth.mixture_pd(280, 181)
+    r = orc.run(A, B, eps=0.1, flags=orc.ORC_L2 | orc.ORC_NO_FLOW)
+    net = orc.csr(A, B, eps=0.1, l2=True)
+    K = r.K
+    assert 0 <= K <= 30
+    N = r.cells["i"].shape[0]
+    ci, cj = r.cells["i"], r.cells["j"]
+    rp, col, cost = net["row_ptr"], net["col"], net["cost"]
+    tail = np.repeat(np.arange(N + 2), np.diff(rp))
+    scale = Decimal(2) ** K
+    lo, hi = Decimal(1) - Decimal(2) ** -50, Decimal(1) + Decimal(2) ** -50
+    for t, h, c in zip(tail.tolist(), col.tolist(), cost.tolist()):
+        if t < N and h < N:
+            x = Decimal(int(ci[t] - ci[h]) ** 2 + int(cj[t] - cj[h]) ** 2).sqrt() * scale
+        elif t < N:
+            x = Decimal(int(cj[t] - ci[t])) / Decimal(2).sqrt() * scale
+        elif h < N:
+            x = Decimal(int(cj[h] - ci[h])) / Decimal(2).sqrt() * scale
+        else:
+            x = Decimal(0)
+        assert Decimal(c) >= x * lo and Decimal(c) - 1 < x * hi, (t, h, c, x)
+
+
+def test_l2_invariances(orc):
+    A, B = pdsynth.exp_pd(60, 190), pdsynth.exp_pd(55, 191)
+    r = orc.run(A, B, eps=0.2, flags=orc.ORC_L2)
+    rs = orc.run(B, A, eps=0.2, flags=orc.ORC_L2)
+    assert rs.W1 == r.W1 and rs.flow == r.flow and rs.L == r.L
+    r2 = orc.run(2 * A, 2 * B, eps=0.2, flags=orc.ORC_L2)
+    assert r2.flow == r.flow and r2.K == r.K and r2.W1 == 2 * r.W1 and r2.L == 2 * r.L
+    # pruning is defined for the L-infinity network only
+    assert orc.run(A, B, eps=0.2, flags=orc.ORC_L2 | orc.ORC_PRUNE).status == -1
+
+
+def test_l2_sparse_network_theorem(orc):
+    # f* of the dense condensed network <= f* of the sparse one <= t f*(dense),
+    # costs rounded up alike (units of g 2^-K, so the rounding adds under one
+    # unit per arc: a relative 1e-6 allowance)
+    for seed, s in ((0, 4), (1, 12)):
+        A = pdsynth.exp_pd(60, 520 + seed, mean_pers=0.2)
+        B = pdsynth.exp_pd(50, 620 + seed, mean_pers=0.2)
+        r = orc.run(A, B, eps=0.2, s_override=s, flags=orc.ORC_L2)
+        K = r.K
+        ci, cj, ca, cb = r.cells["i"], r.cells["j"], r.cells["cA"], r.cells["cB"]
+        ia, ib = np.nonzero(ca)[0], np.nonzero(cb)[0]
+        na, nb = ia.shape[0], ib.shape[0]
+        X, Y = np.meshgrid(np.arange(na), np.arange(nb), indexing="ij")
+        d = np.sqrt(((ci[ia][X] - ci[ib][Y]) ** 2 + (cj[ia][X] - cj[ib][Y]) ** 2).astype(np.float64))
+        cAB = np.ceil(np.ldexp(d, K)).astype(np.int64).ravel()
+        dd = lambda k: np.ceil(np.ldexp((cj[k] - ci[k]).astype(np.float64) * R_SQRT1_2, K)).astype(np.int64)
+        src = np.concatenate([X.ravel(), np.arange(na), np.full(nb, na + nb + 1), [na + nb + 1]])
+        dst = np.concatenate([na + Y.ravel(), np.full(na, na + nb), na + np.arange(nb), [na + nb]])
+        cost = np.concatenate([cAB, dd(ia), dd(ib), [0]])
+        supply = np.concatenate([ca[ia], -cb[ib], [-ca.sum(), cb.sum()]])
+        fd = orc.mcf(na + nb + 2, src, dst, cost, supply)
+        t = (s + 2) / (s - 2)
+        assert fd <= r.flow <= t * fd * (1 + 1e-6)
+
+
+def test_l2_grid_exponent(orc):
+    # g = 2^e with e = floor(log2(sqrt(2) eps_c L / n)) (the condensation moves
+    # a point by at most half a cell diagonal, g / sqrt(2)), computed here in
+    # 50-digit decimal arithmetic away from powers of two
+    from decimal import Decimal, getcontext
+
+    getcontext().prec = 50
+    rng = np.random.default_rng(3)
+    two = Decimal(2)
+    seen_diff = 0
+    for _ in range(200):
+        eps_c = float(rng.choice([0.02, 0.01, 0.005, 0.001]))
+        L = float(np.exp(rng.uniform(np.log(1e-3), np.log(1e4))))
+        n = int(rng.integers(1, 10**6))
+        x = two * Decimal(eps_c) * Decimal(L) / Decimal(n) / two.sqrt()
+        e = int(np.floor(float(x.ln() / two.ln())))
+        frac = x / two ** e
+        if not (Decimal("1.000001") < frac < Decimal("1.999999")):
+            continue
+        assert orc.grid_exponent(eps_c, L, n, l2=True) == e
+        seen_diff += orc.grid_exponent(eps_c, L, n) != e
+    assert seen_diff > 20  # the sqrt(2) moves the exponent for a good share of the cases
+
+
+def test_l2_condensation_corner(orc):
+    # One point at the far corner of its cell (birth at the low edge, death
+    # at the high edge): snapping it to the cell centre lowers its distance
+    # to the diagonal by almost the full g / sqrt(2), so W1 >= exact needs
+    # the whole n g / sqrt(2) added back after the flow.
+    g = 2.0**-10
+    tiny = g / 1024
+    p = np.array([[7 * g + tiny, 148 * g - tiny]])
+    r = orc.run(p, np.zeros((0, 2)), eps=0.1, flags=orc.ORC_L2)
+    assert r.status == 0 and r.g == g and r.n_pairs == 0
+    ex = orc.exact_w1(p, np.zeros((0, 2)), l2=True)
+    # L is (d - b) R, R the double nearest 1/sqrt(2): equal to exact up to
+    # the rounding of that product
+    assert r.L <= ex * (1 + 2.0**-50) and ex <= r.W1 <= 1.1 * ex
+    assert ex - r.W1_paper > 0.7 * g  # most of the half diagonal
