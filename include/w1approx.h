@@ -18,10 +18,26 @@
  * and then solves the uncapacitated min-cost flow of that network on the host
  * with an integer network simplex (Sec. 5.4), timed separately.
  *
- * Ground metric: L-infinity.  Distance to the diagonal of (b, d): (d - b)/2.
- * Costs of the network are integers in units of g/2, g = 2^grid_exp.
+ * Ground metric: L-infinity by default.  Distance to the diagonal of (b, d):
+ * (d - b)/2.  Costs of the network are integers in units of g/2,
+ * g = 2^grid_exp.  w1 = (g/2)(F* + n), w1_paper = (g/2) F*.
  * Guarantee: exact_W1 <= w1 <= (1 + eps) * exact_W1 and
  *            lower_bound <= exact_W1.
+ *
+ * Euclidean metric (W1_METRIC_L2, the paper's own, Sec. 4.2): distance to
+ * the diagonal (d - b)/sqrt(2), computed as (d - b) R with R the double
+ * nearest to 1/sqrt(2).  The RWMD cost of a location is min(sqrt(q), (d - b)
+ * R) with q the smallest (b - b')^2 + (d - d')^2 over the other diagram, in
+ * IEEE doubles.  The grid satisfies g <= sqrt(2) eps_c L / n (a point moves by
+ * at most half a cell diagonal).  Two nodes are separated when their
+ * Euclidean box gap is at least s times the larger box diagonal (exact on
+ * integer squares); the longer diagonal is split.  Network costs are 64-bit
+ * integers in units of g 2^-K (K = cost_shift = min(30, 59 - bitlen(n) -
+ * bitlen(X)), X the largest shifted cell coordinate): between cells
+ * ceil(sqrt(di^2 + dj^2) 2^K), to the diagonal ceil((j - i) R 2^K), each from
+ * IEEE doubles.  w1 = g (F* 2^-K + n R), w1_paper = g F* 2^-K.  The same
+ * guarantee holds up to the rounding of one square root per cost and of R
+ * (relative 2^-52).  The pair records' cost word is 0 with this metric.
  *
  * Conventions for every entry point
  *   - returns W1_OK (0) or a negative W1_E* code; never aborts, never throws;
@@ -89,7 +105,11 @@ extern "C" {
                            /* Sec. 4.3: the distance to the diagonal is     */
                            /* 1-Lipschitz, and the zero-cost diagonal arc   */
                            /* carries at least the cell-to-cell flow).      */
-                           /* n_pairs then counts the pairs kept.           */
+                           /* n_pairs then counts the pairs kept.  Not with */
+                           /* W1_METRIC_L2 (W1_EINVAL).                     */
+#define W1_METRIC_L2 64u   /* Euclidean ground metric, the paper's own      */
+                           /* (Sec. 4.2), instead of L-infinity: see the    */
+                           /* Euclidean notes at the top of this file       */
 
 typedef struct w1_ctx w1_ctx;
 
@@ -173,8 +193,11 @@ typedef struct {
   int64_t *supply;            /* n_cells + 2 */
   int64_t *row_ptr;           /* n_cells + 3 */
   uint32_t *col;              /* n_arcs: head of each arc */
-  int32_t *cost;              /* n_arcs */
+  int32_t *cost;              /* n_arcs (L-infinity; NULL with W1_METRIC_L2) */
+  int64_t *cost64;            /* n_arcs (W1_METRIC_L2; NULL otherwise), see below */
   int64_t n_diag;             /* arcs at a diagonal node: #A cells + #B cells + 1 */
+  int32_t metric_l2;          /* 1 if computed with W1_METRIC_L2 */
+  int32_t cost_shift;         /* W1_METRIC_L2: costs are in units of g 2^-cost_shift */
 
   /* Stage intermediates (W1_KEEP_STAGES). */
   double *loc_b, *loc_d; /* n_locations, sorted by (birth, death) */
@@ -201,7 +224,8 @@ typedef struct {
   const int64_t *supply;  /* n_cells + 2 */
   const int64_t *row_ptr; /* n_cells + 3 */
   const uint32_t *col;    /* n_arcs */
-  const int32_t *cost;    /* n_arcs */
+  const int32_t *cost;    /* n_arcs (L-infinity; NULL with W1_METRIC_L2) */
+  const int64_t *cost64;  /* n_arcs (W1_METRIC_L2; NULL otherwise) */
 } w1_device_network;
 
 /* Create a context on HIP device `device` (must be gfx950). */
@@ -221,13 +245,14 @@ int w1_approx(w1_ctx *ctx, const w1_pd *a, const w1_pd *b, const w1_params *para
 int w1_approx_batch(w1_ctx *ctx, const w1_pd *a, const w1_pd *b, int64_t k, const w1_params *params,
                     void *stream, w1_result *out);
 
-/* RWMD lower bound L (Alg. 1) of each of k pairs, without the rest. */
+/* RWMD lower bound L (Alg. 1) of each of k pairs, without the rest
+ * (flags: W1_INPUT_DEVICE, W1_METRIC_L2). */
 int w1_rwmd(w1_ctx *ctx, const w1_pd *a, const w1_pd *b, int64_t k, uint32_t flags, void *stream,
             double *L_out);
 
 /* w1_rwmd for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
- * arguments and results as w1_rwmd (flags: only W1_INPUT_DEVICE), but the
+ * arguments and results as w1_rwmd (flags: W1_INPUT_DEVICE, W1_METRIC_L2), but the
  * call makes no device allocation (no hipMalloc, hipFree or allocating
  * library routine) and no host allocation: every device buffer it needs is a
  * slice of one fixed scratch array of 128 MiB per GPU, which the library
@@ -418,7 +443,8 @@ typedef struct w1_nn_index w1_nn_index;
  *                     (Kantorovich duality).  Its per-diagram sums are FP64,
  *                     and a margin of 1e-8 (sum_A f_c + sum_B f_c) covers
  *                     their rounding.
- *   W1_NN_EXHAUSTIVE  verify every database diagram. */
+ *   W1_NN_EXHAUSTIVE  verify every database diagram.
+ * Verifications run w1_approx with W1_PRUNE (the same w1, a smaller flow). */
 #define W1_NN_RWMD 0
 #define W1_NN_SURROGATE 1
 #define W1_NN_EXHAUSTIVE 2

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libw1approx.so")
 W1_OK, W1_EINVAL, W1_ERANGE, W1_ENOMEM, W1_EHIP, W1_EOVERFLOW, W1_ENODEV = 0, -1, -2, -3, -4, -5, -6
 W1_OPTIMAL, W1_STALLED = 0, 1
 W1_F32, W1_F64 = 0, 1
-INPUT_DEVICE, COUNT_ONLY, NO_FLOW, KEEP_NETWORK, KEEP_STAGES, PRUNE = 1, 2, 4, 8, 16, 32
+INPUT_DEVICE, COUNT_ONLY, NO_FLOW, KEEP_NETWORK, KEEP_STAGES, PRUNE, METRIC_L2 = 1, 2, 4, 8, 16, 32, 64
 T_NAMES = ("condense0", "rwmd", "grid", "tree", "wspd", "arcs", "d2h", "flow")
 
 
@@ -54,7 +54,8 @@ class _Result(ctypes.Structure):
         ("flow_cost", ctypes.c_int64), ("pivots", ctypes.c_int64),
         ("n_pairs_streamed", ctypes.c_int64), ("pair_checksum", ctypes.c_uint64 * 2),
         ("cell_i", _P), ("cell_j", _P), ("cell_ca", _P), ("cell_cb", _P), ("supply", _P),
-        ("row_ptr", _P), ("col", _P), ("cost", _P), ("n_diag", ctypes.c_int64),
+        ("row_ptr", _P), ("col", _P), ("cost", _P), ("cost64", _P), ("n_diag", ctypes.c_int64),
+        ("metric_l2", ctypes.c_int32), ("cost_shift", ctypes.c_int32),
         ("loc_b", _P), ("loc_d", _P), ("loc_w", _P), ("loc_t", _P),
         ("rwmd_sum_a", ctypes.c_int64), ("rwmd_sum_b", ctypes.c_int64),
         ("rwmd_shift_a", ctypes.c_int32), ("rwmd_shift_b", ctypes.c_int32),
@@ -66,7 +67,7 @@ class _Result(ctypes.Structure):
 class _DevNet(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_arcs", ctypes.c_int64),
                 ("cell_ij", _P), ("cell_ca", _P), ("cell_cb", _P), ("supply", _P), ("row_ptr", _P),
-                ("col", _P), ("cost", _P)]
+                ("col", _P), ("cost", _P), ("cost64", _P)]
 
 
 class _TrainParams(ctypes.Structure):
@@ -217,6 +218,8 @@ class Result:
     pivots: int
     t_ms: dict
     n_pairs_streamed: int = 0
+    metric_l2: bool = False
+    cost_shift: int = 0
     pair_checksum: tuple = (0, 0)
     network: dict = field(default_factory=dict)
     stages: dict = field(default_factory=dict)
@@ -235,14 +238,15 @@ def _convert(r: _Result) -> Result:
         grid_exp=r.grid_exp, s=r.s, flow_solved=bool(r.flow_solved), n_points=r.n_points, n_a=r.n_a,
         n_b=r.n_b, n_locations=r.n_locations, n_cells=r.n_cells, n_pairs=r.n_pairs, n_arcs=r.n_arcs,
         flow_cost=r.flow_cost, pivots=r.pivots, t_ms={k: r.t_ms[i] for i, k in enumerate(T_NAMES)},
-        n_pairs_streamed=r.n_pairs_streamed, pair_checksum=(int(r.pair_checksum[0]), int(r.pair_checksum[1])))
+        n_pairs_streamed=r.n_pairs_streamed, metric_l2=bool(r.metric_l2), cost_shift=r.cost_shift, pair_checksum=(int(r.pair_checksum[0]), int(r.pair_checksum[1])))
     if r.row_ptr:
         nc = r.n_cells
         out.network = dict(
             cell_i=_arr(r.cell_i, nc, np.int32), cell_j=_arr(r.cell_j, nc, np.int32),
             cell_ca=_arr(r.cell_ca, nc, np.int32), cell_cb=_arr(r.cell_cb, nc, np.int32),
             supply=_arr(r.supply, nc + 2, np.int64), row_ptr=_arr(r.row_ptr, nc + 3, np.int64),
-            col=_arr(r.col, r.n_arcs, np.uint32), cost=_arr(r.cost, r.n_arcs, np.int32))
+            col=_arr(r.col, r.n_arcs, np.uint32),
+            cost=_arr(r.cost64, r.n_arcs, np.int64) if r.cost64 else _arr(r.cost, r.n_arcs, np.int32))
     if r.loc_b:
         nl = r.n_locations
         out.stages = dict(loc_b=_arr(r.loc_b, nl, np.float64), loc_d=_arr(r.loc_d, nl, np.float64),
@@ -365,10 +369,11 @@ class Context:
                     raise W1Error(r.status, "pair")
         return out
 
-    def rwmd(self, As, Bs, noalloc=False) -> np.ndarray:
+    def rwmd(self, As, Bs, noalloc=False, flags=0) -> np.ndarray:
         """RWMD lower bounds of k pairs (Alg. 1); NaN marks an invalid pair.
         noalloc: through w1_rwmd_noalloc (no device allocation; at most 2^19
-        points in all pairs and 1024 pairs)."""
+        points in all pairs and 1024 pairs).  flags: METRIC_L2 for the
+        Euclidean metric."""
         k = len(As)
         keep = []
         pa, pb = (_PD * k)(), (_PD * k)()
@@ -380,7 +385,7 @@ class Context:
         dev = devs.pop()
         out = np.zeros(k)
         fn = lib().w1_rwmd_noalloc if noalloc else lib().w1_rwmd
-        rc = fn(self._h, pa, pb, k, INPUT_DEVICE if dev else 0, _stream_of(dev),
+        rc = fn(self._h, pa, pb, k, (INPUT_DEVICE if dev else 0) | int(flags), _stream_of(dev),
                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         if rc != 0:
             raise W1Error(rc, "w1_rwmd_noalloc" if noalloc else "w1_rwmd")

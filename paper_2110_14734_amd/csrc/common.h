@@ -46,6 +46,7 @@ struct PairArrays {
   int64_t* item_start;   // first WSPD work item of the pair
   uint64_t* npairs;      // WSPD pairs of the pair
   uint64_t* pair_start;  // first output pair of the pair
+  int32_t* costK;        // Euclidean network: costs in units of g 2^-costK
 };
 
 // ---------------------------------------------------------------- helpers --

@@ -303,11 +303,41 @@ __device__ inline uint32_t wave_excl_prefix_small(uint32_t v) {
   return ex;
 }
 
+// Arc costs.  L-infinity (int32, units of g/2): 2 max(|di|, |dj|) between
+// cells, j - i to the diagonal.  Euclidean (int64, units of g 2^-K): the
+// distances of the cell centres rounded up, ceil(sqrt(di^2 + dj^2) 2^K) and
+// ceil((j - i) R 2^K), each from IEEE double operations in this order (the
+// integer sum converted to double, correctly rounded square root, exact
+// scaling by 2^K).
+template <bool L2>
+struct ArcCost;
+
+template <>
+struct ArcCost<false> {
+  typedef int32_t T;
+  __device__ static T cell(int2 a, int2 b, int) { return 2 * max(abs(a.x - b.x), abs(a.y - b.y)); }
+  __device__ static T diag(int2 a, int) { return a.y - a.x; }
+};
+
+template <>
+struct ArcCost<true> {
+  typedef int64_t T;
+  __device__ static T cell(int2 a, int2 b, int K) {
+    const int64_t di = (int64_t)a.x - b.x, dj = (int64_t)a.y - b.y;
+    return (int64_t)ceil(ldexp(sqrt((double)(di * di + dj * dj)), K));
+  }
+  __device__ static T diag(int2 a, int K) {
+    return (int64_t)ceil(ldexp((double)(a.y - a.x) * 0x1.6a09e667f3bcdp-1, K));
+  }
+};
+
 // Writes a wave's staged heads (in order) as arcs k0, k0 + 1, ... of the row
-// of cell `me`: head and cost 2 max(|di|, |dj|).  Four heads per lane are in
-// flight at once, so their cell-coordinate gathers overlap.
+// of cell `me`: head and cost.  Four heads per lane are in flight at once, so
+// their cell-coordinate gathers overlap.
+template <bool L2>
 __device__ inline void flush_staged(const uint32_t* st, uint32_t n, int64_t k0, int2 me, const int2* __restrict__ cij,
-                                    int64_t cs, uint32_t* __restrict__ col, int32_t* __restrict__ cost) {
+                                    int64_t cs, int K, uint32_t* __restrict__ col,
+                                    typename ArcCost<L2>::T* __restrict__ cost) {
   const uint32_t lane = (uint32_t)lane_id();
   for (uint32_t x = lane; x < n; x += 4 * WAVE) {
     uint32_t d[4];
@@ -322,7 +352,7 @@ __device__ inline void flush_staged(const uint32_t* st, uint32_t n, int64_t k0, 
       if (x + u * WAVE < n) {
         const int64_t k = k0 + x + u * WAVE;
         col[k] = d[u];
-        cost[k] = 2 * max(abs(me.x - o[u].x), abs(me.y - o[u].y));
+        cost[k] = ArcCost<L2>::cell(me, o[u], K);
       }
   }
 }
@@ -342,13 +372,15 @@ __device__ inline void flush_staged(const uint32_t* st, uint32_t n, int64_t k0, 
 //      the set bits into its LDS staging area (a group denser than the
 //      staging area goes through in slices of 8 words, one 4-bit nibble per
 //      lane), and writes the staged heads with their costs coalesced.
+template <bool L2>
 __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict__ cpair,
                                                      const int64_t* __restrict__ cell_start,
                                                      const int32_t* __restrict__ ncells, const int2* __restrict__ cij,
                                                      const int32_t* __restrict__ ca, const uint32_t* __restrict__ rowcnt,
                                                      const uint64_t* __restrict__ off,
                                                      const uint32_t* __restrict__ heads, int64_t N, int win_words,
-                                                     uint32_t* __restrict__ col, int32_t* __restrict__ cost) {
+                                                     const int32_t* __restrict__ costK, uint32_t* __restrict__ col,
+                                                     typename ArcCost<L2>::T* __restrict__ cost) {
   extern __shared__ uint32_t s_mem[];
   __shared__ uint32_t s_gpre[SORT_MAXG + 1];
   __shared__ int s_wg[SORT_WAVES + 1];
@@ -363,6 +395,7 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
     const int64_t start = (int64_t)off[g + 2 * (int64_t)p];
     const uint32_t cnt = rowcnt[g];
     const int2 me = cij[g];
+    const int K = L2 ? costK[p] : 0;
     uint32_t written = 0;  // heads written by earlier windows (block-uniform)
     for (uint32_t w0 = 0; cnt > 0 && w0 < np; w0 += 32u * (uint32_t)win_words) {
       const uint32_t nbits = min(np - w0, 32u * (uint32_t)win_words);
@@ -415,7 +448,7 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
         const uint32_t word = i < nw ? s_bm[i] : 0u;
         if (staged + tot > SORT_STAGE) {
           __builtin_amdgcn_wave_barrier();
-          flush_staged(s_st, staged, k0, me, cij, cs, col, cost);
+          flush_staged<L2>(s_st, staged, k0, me, cij, cs, K, col, cost);
           k0 += staged;
           staged = 0;
           __builtin_amdgcn_wave_barrier();
@@ -444,7 +477,7 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
               s_st[pos++] = at + (uint32_t)bit;
             }
             __builtin_amdgcn_wave_barrier();
-            flush_staged(s_st, ts, k0, me, cij, cs, col, cost);
+            flush_staged<L2>(s_st, ts, k0, me, cij, cs, K, col, cost);
             k0 += ts;
             __builtin_amdgcn_wave_barrier();
           }
@@ -452,13 +485,13 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
         if (i < nw) s_bm[i] = 0;  // zero again for the next row
       }
       __builtin_amdgcn_wave_barrier();
-      flush_staged(s_st, staged, k0, me, cij, cs, col, cost);
+      flush_staged<L2>(s_st, staged, k0, me, cij, cs, K, col, cost);
       written += s_gpre[ng];
       __syncthreads();
     }
     if (threadIdx.x == 0 && ca[g] > 0) {  // arc to the A-diagonal node, last in the row
       col[start + cnt] = np;
-      cost[start + cnt] = me.y - me.x;
+      cost[start + cnt] = ArcCost<L2>::diag(me, K);
     }
   }
 }
@@ -491,12 +524,13 @@ __global__ void k_bflags(const int32_t* __restrict__ cb, int64_t N, uint32_t* __
 
 // The B-diagonal row and the supplies (cell: A mass minus B mass; A-diagonal
 // node: minus the A mass; B-diagonal node: the B mass).
+template <bool L2>
 __global__ void k_bdiag_rows(const uint32_t* __restrict__ cpair, const int64_t* __restrict__ cell_start,
                              const int32_t* __restrict__ ncells, const int2* __restrict__ cij,
                              const int32_t* __restrict__ ca, const int32_t* __restrict__ cb,
                              const uint32_t* __restrict__ bpos, const uint64_t* __restrict__ off, PairArrays P,
-                             int64_t N, uint32_t* __restrict__ col, int32_t* __restrict__ cost,
-                             int64_t* __restrict__ supply) {
+                             int64_t N, const int32_t* __restrict__ costK, uint32_t* __restrict__ col,
+                             typename ArcCost<L2>::T* __restrict__ cost, int64_t* __restrict__ supply) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
   const uint32_t p = cpair[g];
@@ -508,7 +542,7 @@ __global__ void k_bdiag_rows(const uint32_t* __restrict__ cpair, const int64_t* 
   const int2 v = cij[g];
   if (cb[g] > 0) {
     col[at] = local;
-    cost[at] = v.y - v.x;
+    cost[at] = ArcCost<L2>::diag(v, L2 ? costK[p] : 0);
   }
   const int64_t sb = cs + 2 * (int64_t)p;
   supply[sb + local] = (int64_t)ca[g] - (int64_t)cb[g];
@@ -583,8 +617,8 @@ void launch_csr_row_scatter(const uint32_t* ent, const int64_t* tfirst, int64_t 
 }
 void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
                          const int32_t* ca, const uint32_t* rowcnt, const uint64_t* off, const uint32_t* heads,
-                         int64_t N, int64_t max_pair_cells, int num_cus, uint32_t* col, int32_t* cost,
-                         hipStream_t st) {
+                         int64_t N, int64_t max_pair_cells, int num_cus, const int32_t* costK, uint32_t* col,
+                         void* cost, hipStream_t st) {
   if (N <= 0) return;
   // the bitmap covers the largest pair's cells at once when they fit
   const int win = (int)std::min<int64_t>(WIN_WORDS, std::max<int64_t>(1, (max_pair_cells + 31) / 32));
@@ -592,8 +626,12 @@ void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const
   // persistent: two blocks per compute unit when their LDS fits (a bitmap
   // of up to 50 KiB, i.e. pairs of up to 400k cells), else one
   const int64_t grid = std::min<int64_t>(N, (int64_t)num_cus * (lds <= 80 * 1024 ? 2 : 1));
-  hipLaunchKernelGGL(k_row_sort, dim3((unsigned)grid), dim3(SORT_B), lds, st, cpair, cell_start, ncells, cij, ca,
-                     rowcnt, off, heads, N, win, col, cost);
+  if (costK)
+    hipLaunchKernelGGL(k_row_sort<true>, dim3((unsigned)grid), dim3(SORT_B), lds, st, cpair, cell_start, ncells, cij, ca,
+                       rowcnt, off, heads, N, win, costK, col, (int64_t*)cost);
+  else
+    hipLaunchKernelGGL(k_row_sort<false>, dim3((unsigned)grid), dim3(SORT_B), lds, st, cpair, cell_start, ncells, cij,
+                       ca, rowcnt, off, heads, N, win, costK, col, (int32_t*)cost);
 }
 #define LAUNCH(kern, n, ...) \
   do { if ((n) > 0) hipLaunchKernelGGL(kern, dim3(blocks(n)), dim3(256), 0, st, __VA_ARGS__); } while (0)
@@ -605,8 +643,38 @@ void launch_csr_row_deg(const uint32_t* cpair, const int64_t* cell_start, const 
 }
 void launch_csr_bdiag(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
                       const int32_t* ca, const int32_t* cb, const uint32_t* bpos, const uint64_t* off,
-                      const PairArrays& P, int64_t N, uint32_t* col, int32_t* cost, int64_t* supply, hipStream_t st) {
-  LAUNCH(k_bdiag_rows, N, cpair, cell_start, ncells, cij, ca, cb, bpos, off, P, N, col, cost, supply);
+                      const PairArrays& P, int64_t N, const int32_t* costK, uint32_t* col, void* cost,
+                      int64_t* supply, hipStream_t st) {
+  if (costK) {
+    LAUNCH(k_bdiag_rows<true>, N, cpair, cell_start, ncells, cij, ca, cb, bpos, off, P, N, costK, col, (int64_t*)cost,
+           supply);
+  } else {
+    LAUNCH(k_bdiag_rows<false>, N, cpair, cell_start, ncells, cij, ca, cb, bpos, off, P, N, costK, col,
+           (int32_t*)cost, supply);
+  }
+}
+
+// Largest shifted cell coordinate of each diagram pair (the Euclidean cost
+// scale): per-pair maxima over the cells.
+__global__ void k_pair_xmax(const uint32_t* __restrict__ cpair, const int2* __restrict__ cij, int64_t N,
+                            unsigned long long* __restrict__ xmax) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int2 v = cij[g];
+  const uint32_t p = cpair[g];
+  const unsigned long long x = (unsigned long long)max(v.x, v.y);
+  // one atomic per run of a pair inside the wave
+  const uint32_t prev = __shfl_up(p, 1);
+  unsigned long long m = x;
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const unsigned long long o = __shfl_down(m, d);
+    const uint32_t po = __shfl_down(p, d);
+    if (lane_id() + d < WAVE && po == p && g + d < N && o > m) m = o;
+  }
+  if (lane_id() == 0 || prev != p) atomicMax(&xmax[p], m);
+}
+void launch_pair_xmax(const uint32_t* cpair, const int2* cij, int64_t N, uint64_t* xmax, hipStream_t st) {
+  LAUNCH(k_pair_xmax, N, cpair, cij, N, (unsigned long long*)xmax);
 }
 void launch_csr_local_rowptr(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells,
                              const uint64_t* off, int64_t N, int64_t* rp, hipStream_t st) {

@@ -68,14 +68,15 @@ struct Ctx {
   // the unsorted row heads; l1 the bucket-major arc entries and later the
   // sorted heads (col); costb the arc costs; rp the per-pair row pointers
   DBuf pu, l1, costb, rp, supply, rstart, bcnt, bstart, tfirst, bcur, rowcnt, rowcur, bflag, bpos, deg, off, parc;
-  // streamed emission: per-chunk pair checksums
-  DBuf csum;
+  // streamed emission: per-chunk pair checksums; Euclidean cost scale
+  DBuf csum, pxmax;
   // per pair
   DBuf pairs;
   PairArrays P{};
   int64_t K = 0;
   std::vector<int64_t> h_cell_start, h_ncells, h_npairs, h_arc_start, h_narcs;
   bool network_valid = false;
+  bool network_l2 = false;  // the last network has 64-bit (Euclidean) costs
   hipEvent_t ev[8];
   hipEvent_t kev[11];  // WSPD work list, count, emit; network passes
   double kms[kNumKernelTimes] = {0};
@@ -95,7 +96,7 @@ struct Ctx {
                     &ndepth, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &cid, &pcap,
                     &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &l1, &costb, &rp,
                     &supply, &rstart, &bcnt, &bstart, &tfirst, &bcur, &rowcnt, &rowcur, &bflag, &bpos, &deg, &off,
-                    &parc, &csum, &pairs};
+                    &parc, &csum, &pxmax, &pairs};
     all.assign(std::begin(list), std::end(list));
     saved.resize(all.size());
   }

@@ -48,7 +48,8 @@ namespace {
 // *enter take the value and the first arc that reaches it.  Two running
 // minima (even and odd offsets) halve the dependent chain; they merge by
 // value, then by the earlier arc, so the pick is the one of a single scan.
-void price_run(const int32_t* h, const int32_t* c, const int64_t* pi, int64_t pit, int64_t a, int64_t end,
+template <typename C>
+void price_run(const int32_t* h, const C* c, const int64_t* pi, int64_t pit, int64_t a, int64_t end,
                int64_t* best, int64_t* enter) {
   int64_t sv = *best, si = -1, sv1 = *best, si1 = -1;
   int64_t b = a;
@@ -83,7 +84,8 @@ int32_t row_of(const int64_t* row_ptr, int32_t n, int64_t a) {
 }
 
 // Prices the arcs [a, end) row by row, starting in row *r (which holds a).
-void price_range(const int64_t* row_ptr, const int32_t* h, const int32_t* c, const int64_t* pi, int32_t* r,
+template <typename C>
+void price_range(const int64_t* row_ptr, const int32_t* h, const C* c, const int64_t* pi, int32_t* r,
                  int64_t a, int64_t end, int64_t* best, int64_t* enter) {
   while (a < end) {
     while (row_ptr[*r + 1] <= a) ++*r;
@@ -125,10 +127,13 @@ struct Simplex {
   }
 };
 
-}  // namespace
-
-int network_simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int32_t* cost,
-                    const int64_t* supply, int64_t pivot_cap, FlowResult* out) {
+// The solver for either cost width: int32 (L-infinity costs in units of
+// g/2) or int64 (Euclidean costs in units of g 2^-K, scaled so that the
+// artificial cost (max cost + 1)(n + 1) stays below 2^60 and every reduced
+// cost fits int64).
+template <typename C>
+int simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const C* cost, const int64_t* supply,
+            int64_t pivot_cap, FlowResult* out) {
   out->cost = -1;
   out->pivots = 0;
   out->status = 0;
@@ -146,8 +151,9 @@ int network_simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col
   int64_t maxc = 0;
   for (int64_t a = 0; a < m; ++a) {
     if (cost[a] < 0 || col[a] >= (uint64_t)n_nodes) return -1;
-    maxc = std::max<int64_t>(maxc, cost[a]);
+    maxc = std::max<int64_t>(maxc, (int64_t)cost[a]);
   }
+  if (maxc >= ((int64_t)1 << 60) / ((int64_t)n + 1)) return -1;  // the artificial cost must stay below 2^60
   Simplex S;
   S.n = n;
   S.root = n;
@@ -325,6 +331,18 @@ int network_simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col
   }
   if (out->pot) std::copy(S.pi.begin(), S.pi.begin() + n, out->pot);
   return 0;
+}
+
+}  // namespace
+
+int network_simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int32_t* cost,
+                    const int64_t* supply, int64_t pivot_cap, FlowResult* out) {
+  return simplex<int32_t>(n_nodes, row_ptr, col, cost, supply, pivot_cap, out);
+}
+
+int network_simplex64(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int64_t* cost,
+                      const int64_t* supply, int64_t pivot_cap, FlowResult* out) {
+  return simplex<int64_t>(n_nodes, row_ptr, col, cost, supply, pivot_cap, out);
 }
 
 int network_simplex_arcs(int64_t n_nodes, int64_t m, const uint32_t* src, const uint32_t* dst, const int32_t* cost,

@@ -20,6 +20,11 @@ struct FlowResult {
 int network_simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int32_t* cost,
                     const int64_t* supply, int64_t pivot_cap, FlowResult* out);
 
+// The same with 64-bit costs (the Euclidean network); the largest cost times
+// (n_nodes + 1) must be below 2^60.
+int network_simplex64(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int64_t* cost,
+                      const int64_t* supply, int64_t pivot_cap, FlowResult* out);
+
 // The same for an arc list (src, dst, cost); flow entries follow the list.
 int network_simplex_arcs(int64_t n_nodes, int64_t m, const uint32_t* src, const uint32_t* dst, const int32_t* cost,
                          const int64_t* supply, int64_t pivot_cap, FlowResult* out);

@@ -42,13 +42,13 @@ void launch_bucket_fill(const double* lb, const double* ld, const int64_t* lbin,
 // one wave per bin (nbins = 2 * buckets + 1 bounds) searches the other side.
 void launch_nn(const double* lb, const double* ld, const int32_t* lw, const uint32_t* lpair, int64_t M,
                const PairArrays& P, const uint32_t* binstart, const double2* ent, const uint32_t* entl, int64_t nbins,
-               double* lt, double* lterm, hipStream_t st);
+               double* lt, double* lterm, bool l2, hipStream_t st);
 void launch_term_max(const double* lterm, const int32_t* lw, const uint32_t* lpair, int64_t M, const PairArrays& P,
                      hipStream_t st);
 void launch_rwmd_shift(const PairArrays& P, int64_t K, hipStream_t st);
 void launch_term_sum(const double* lterm, const int32_t* lw, const uint32_t* lpair, int64_t M, const PairArrays& P,
                      hipStream_t st);
-void launch_params(const PairArrays& P, int64_t K, double eps_c, hipStream_t st);
+void launch_params(const PairArrays& P, int64_t K, double eps_c, bool l2, hipStream_t st);
 // a2
 void launch_snap(const double* lb, const double* ld, const uint32_t* lpair, int64_t M, const PairArrays& P, int64_t* li,
                  int64_t* lj, hipStream_t st);
@@ -92,11 +92,15 @@ void launch_csr_row_scatter(const uint32_t* ent, const int64_t* tfirst, int64_t 
                             const uint64_t* off, uint32_t* rowcur, uint32_t* heads, hipStream_t st);
 void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
                          const int32_t* ca, const uint32_t* rowcnt, const uint64_t* off, const uint32_t* heads,
-                         int64_t N, int64_t max_pair_cells, int num_cus, uint32_t* col, int32_t* cost,
-                         hipStream_t st);
+                         int64_t N, int64_t max_pair_cells, int num_cus, const int32_t* costK, uint32_t* col,
+                         void* cost, hipStream_t st);
 void launch_csr_bdiag(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
                       const int32_t* ca, const int32_t* cb, const uint32_t* bpos, const uint64_t* off,
-                      const PairArrays& P, int64_t N, uint32_t* col, int32_t* cost, int64_t* supply, hipStream_t st);
+                      const PairArrays& P, int64_t N, const int32_t* costK, uint32_t* col, void* cost,
+                      int64_t* supply, hipStream_t st);
+// Euclidean network: costs int64 in units of g 2^-costK[pair] (costK NULL:
+// L-infinity int32 costs).  Largest shifted cell coordinate per pair:
+void launch_pair_xmax(const uint32_t* cpair, const int2* cij, int64_t N, uint64_t* xmax, hipStream_t st);
 void launch_csr_local_rowptr(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells,
                              const uint64_t* off, int64_t N, int64_t* rp, hipStream_t st);
 // out[p] = off[cell_start[p] + 2p] for p < K, out[K] = off[nrows]: each pair's
@@ -153,15 +157,15 @@ void launch_pack_nodes(const TreeView& T, const int64_t* cell_start, int4* rec, 
 // must be below 2^28.
 void launch_pack_split(const TreeView& T, uint4* out, hipStream_t st);
 // Final work items (node references) -> work entries of the passes.
-void launch_item_prep(const TreeView& T, const int2* items, const uint32_t* perm, int64_t m, int s, const int32_t* rmap,
+void launch_item_prep(const TreeView& T, const int2* items, const uint32_t* perm, int64_t m, int s, const int32_t* rmap, bool l2,
                       int2* out, hipStream_t st);
 void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st);
 void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st);
 // pair_cap[p]: the work cap of diagram pair p (at most tun.work_cap).
 void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s, const WspdTuning& tun,
-                          const int32_t* pair_cap, bool prune, uint64_t* cnt, hipStream_t st);
+                          const int32_t* pair_cap, bool prune, bool l2, uint64_t* cnt, hipStream_t st);
 void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const uint64_t* cnt, const uint64_t* pos,
-                         int2* out_items, int64_t out_base, int2* next, hipStream_t st);
+                         int2* out_items, int64_t out_base, bool l2, int2* next, hipStream_t st);
 void launch_item_keys(const TreeView& T, const int2* items, int64_t m, bool both, uint64_t* keys, hipStream_t st);
 void launch_gather_items(const int2* src, const uint32_t* perm, int2* dst, int64_t m, hipStream_t st);
 // Per-pair item runs of the sorted work list (keys: first representative
@@ -177,7 +181,7 @@ void launch_chunks(const int32_t* cstart, int64_t K, const int64_t* item_start, 
 void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
-                      uint32_t* out, int32_t* err, bool prune, const BucketHist& bh, const StreamOut& so,
+                      uint32_t* out, int32_t* err, bool prune, bool l2, const BucketHist& bh, const StreamOut& so,
                       int num_cus, hipStream_t st);
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,

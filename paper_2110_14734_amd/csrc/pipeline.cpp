@@ -32,6 +32,7 @@ namespace w1 {
 namespace {
 
 inline int clz64(uint64_t x) { return x ? __builtin_clzll(x) : 64; }
+inline int bitlen_u64(uint64_t x) { return 64 - clz64(x); }
 inline int ctz64(uint64_t x) { return x ? __builtin_ctzll(x) : 64; }
 
 // Stable sort of n elements by the words (least significant first); returns
@@ -117,7 +118,7 @@ void setup_pairs(Ctx& c, int64_t K) {
   off += K8 * 8;  // spare
   P.err = (int32_t*)take4(); P.locA = (int32_t*)take4(); P.locB = (int32_t*)take4(); P.beh = (int32_t*)take4();
   P.bnx = (int32_t*)take4(); P.bny = (int32_t*)take4(); P.FA = (int32_t*)take4(); P.FB = (int32_t*)take4();
-  P.e = (int32_t*)take4(); P.ncells = (int32_t*)take4(); off += K8 * 4;  // spare
+  P.e = (int32_t*)take4(); P.ncells = (int32_t*)take4(); P.costK = (int32_t*)take4();
   fill_u64((uint64_t*)base, 0, zero8_end / 8, c.st);
   fill_u64((uint64_t*)P.bmin, ~0ull, K8 * 2, c.st);
   fill_u64((uint64_t*)P.m0, (uint64_t)INT64_MAX, K8, c.st);
@@ -184,6 +185,8 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
   if (total >= (int64_t(1) << 31) || K >= (int64_t(1) << 30)) return W1_EINVAL;
   const int s = o.s > 0 ? o.s : separation(o.eps, o.kappa);
   const bool prune = (o.flags & W1_PRUNE) != 0;
+  const bool l2 = (o.flags & W1_METRIC_L2) != 0;
+  if (l2 && prune) return W1_EINVAL;  // pruning is exact for the integer L-infinity costs only
   const double eps_c = o.kappa * o.eps;
   for (int i = 0; i < 8; ++i) record(c, i);
   record(c, 0);
@@ -288,11 +291,11 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     launch_bucket_fill(lb, ld, lbin, M, binstart, bincnt, ent, entl, st);
     double* lt = need<double>(c, c.lt, M);
     double* lterm = need<double>(c, c.lterm, M);
-    launch_nn(lb, ld, lw, lpair, M, P, binstart, ent, entl, nbins, lt, lterm, st);
+    launch_nn(lb, ld, lw, lpair, M, P, binstart, ent, entl, nbins, lt, lterm, l2, st);
     launch_term_max(lterm, lw, lpair, M, P, st);
     launch_rwmd_shift(P, K, st);
     launch_term_sum(lterm, lw, lpair, M, P, st);
-    launch_params(P, K, eps_c, st);
+    launch_params(P, K, eps_c, l2, st);
     check(c, hipGetLastError());
   }
   record(c, 2);
@@ -443,7 +446,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       if (!worklist_round_fits(f)) throw StageError{W1_EOVERFLOW};
       uint64_t* cnt = need<uint64_t>(c, c.icnt, f);
       uint64_t* pos = need<uint64_t>(c, c.ipos, f);
-      launch_wspd_classify(T, F, f, s, tun, (const int32_t*)c.pcap.p, prune, cnt, st);
+      launch_wspd_classify(T, F, f, s, tun, (const int32_t*)c.pcap.p, prune, l2, cnt, st);
       scan_u64(cnt, pos, f, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(f, 8)), st);
       uint64_t* slot = need<uint64_t>(c, c.small, 64);
       launch_count_total64(cnt, pos, f, slot, st);
@@ -453,7 +456,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       I = grow_keep<int2>(c, c.itemsI, isz + kept, isz);
       int2* Nx = need<int2>(c, c.itemsB, std::max<int64_t>(grown, 1));
       F = (int2*)c.itemsA.p;
-      launch_wspd_scatter(T, F, f, cnt, pos, I, isz, Nx, st);
+      launch_wspd_scatter(T, F, f, cnt, pos, I, isz, l2, Nx, st);
       check(c, hipGetLastError());
       std::swap(c.itemsA, c.itemsB);
       F = (int2*)c.itemsA.p;
@@ -477,7 +480,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       launch_item_bounds(T.cpair, top, m, P.seg_lo, P.seg_hi, st);
       launch_bounds_count32(P.seg_lo, P.seg_hi, K, ipp, st);
       int2* S = need<int2>(c, c.itemsS, m);  // work entries in sorted order
-      launch_item_prep(T, I, perm, m, s, (const int32_t*)c.rmap.p, S, st);
+      launch_item_prep(T, I, perm, m, s, (const int32_t*)c.rmap.p, l2, S, st);
       timed = true;
       std::vector<int32_t> hipp = fetch_pairs(c, ipp, K);
       std::vector<int64_t> ist((size_t)K);
@@ -508,7 +511,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       uint64_t* coff = need<uint64_t>(c, c.coff, nch);
       fill_u32(xc, 0, 8, st);
       check(c, hipEventRecord(c.kev[1], st));
-      launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr, prune,
+      launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr, prune, l2,
                        BucketHist{}, StreamOut{}, c.num_cus, st);
       check(c, hipGetLastError());
       check(c, hipEventRecord(c.kev[2], st));
@@ -539,7 +542,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
           upload(c, xr, hr2, sizeof(hr2));
           fill_u32(xc, 0, 8, st);
           check(c, hipEventRecord(c.kev[3], st));
-          launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, arena, derr, prune,
+          launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, arena, derr, prune, l2,
                            BucketHist{}, StreamOut{(int64_t)hoff[(size_t)c0], csum}, c.num_cus, st);
           check(c, hipGetLastError());
           check(c, hipEventRecord(c.kev[4], st));
@@ -581,7 +584,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         bh.count = bcnt;
         fill_u32(xc, 0, 8, st);
         check(c, hipEventRecord(c.kev[3], st));
-        launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr, prune, bh,
+        launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr, prune, l2, bh,
                          StreamOut{}, c.num_cus, st);
         check(c, hipGetLastError());
         emitted = true;
@@ -598,6 +601,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
   // (Appendix, network representation); see csr.hip for the passes.
   bool csr_timed = false;
   int64_t Mtot = 0;
+  std::vector<int32_t> h_costK;  // Euclidean cost scale per pair
   std::vector<uint64_t> h_parc;  // first arc of each pair, then the total
   if (N > 0 && !(o.flags & W1_COUNT_ONLY)) {
     const uint32_t* cp = (const uint32_t*)c.cpair.p;
@@ -673,9 +677,32 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       launch_csr_row_scatter(col, tfirst, ntiles, (int)NB, bstart, RB, DB, N, cp, off, rowcur, heads, st);
       check(c, hipEventRecord(c.kev[9], st));
     }
-    int32_t* cost = need<int32_t>(c, c.costb, 2 * Ptot + 2 * N + K);
-    launch_csr_row_sort(cp, P.cell_start, ncl, cij, ca, rowcnt, off, heads, N, maxnp, c.num_cus, col, cost, st);
-    launch_csr_bdiag(cp, P.cell_start, ncl, cij, ca, cb, bpos, off, P, N, col, cost, sup, st);
+    // Euclidean costs: 64-bit, in units of g 2^-K with K per pair from the
+    // pair's point count n and largest shifted coordinate X:
+    // K = min(30, 59 - bitlen(n) - bitlen(X)), so F* and the flow solver's
+    // artificial costs stay below 2^60
+    const int32_t* costK = nullptr;
+    if (l2) {
+      uint64_t* xm = need<uint64_t>(c, c.pxmax, K);
+      fill_u64(xm, 0, K, st);
+      launch_pair_xmax(cp, cij, N, xm, st);
+      std::vector<uint64_t> hx = fetch_pairs(c, xm, K);
+      std::vector<int64_t> hna = fetch_pairs(c, P.nA, K), hnb = fetch_pairs(c, P.nB, K);
+      std::vector<int32_t> hk((size_t)K);
+      for (int64_t p = 0; p < K; ++p) {
+        const int64_t k = std::min<int64_t>(
+            30, 59 - bitlen_u64((uint64_t)(hna[(size_t)p] + hnb[(size_t)p])) - bitlen_u64(std::max<uint64_t>(hx[(size_t)p], 1)));
+        if (k < 0) throw StageError{W1_ERANGE};
+        hk[(size_t)p] = (int32_t)k;
+      }
+      upload(c, P.costK, hk.data(), (size_t)K * 4);
+      costK = P.costK;
+      h_costK = hk;
+    }
+    void* cost = l2 ? (void*)need<int64_t>(c, c.costb, 2 * Ptot + 2 * N + K)
+                    : (void*)need<int32_t>(c, c.costb, 2 * Ptot + 2 * N + K);
+    launch_csr_row_sort(cp, P.cell_start, ncl, cij, ca, rowcnt, off, heads, N, maxnp, c.num_cus, costK, col, cost, st);
+    launch_csr_bdiag(cp, P.cell_start, ncl, cij, ca, cb, bpos, off, P, N, costK, col, cost, sup, st);
     int64_t* rp = need<int64_t>(c, c.rp, N + 3 * K);
     fill_u64((uint64_t*)rp, 0, N + 3 * K, st);
     launch_csr_local_rowptr(cp, P.cell_start, ncl, off, N, rp, st);
@@ -735,6 +762,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       c.h_narcs[(size_t)p] = (int64_t)(h_parc[(size_t)p + 1] - h_parc[(size_t)p]);
     }
   c.network_valid = !(o.flags & W1_COUNT_ONLY);
+  c.network_l2 = l2;
   int64_t loc_off = 0;
   for (int64_t p = 0; p < K; ++p) {
     w1_result& r = res[p];
@@ -757,6 +785,8 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     r.rwmd_sum_b = (int64_t)h_sB[(size_t)p];
     r.rwmd_shift_a = h_FA[(size_t)p];
     r.rwmd_shift_b = h_FB[(size_t)p];
+    r.metric_l2 = l2 ? 1 : 0;
+    r.cost_shift = h_costK.empty() ? 0 : h_costK[(size_t)p];
     if (!stream_n.empty()) {
       r.n_pairs_streamed = stream_n[(size_t)p];
       r.pair_checksum[0] = stream_chk[2 * (size_t)p];
@@ -819,8 +849,9 @@ void copy_network(Ctx& c, int64_t p, w1_result& r) {
   r.supply = (int64_t*)std::malloc((size_t)(nc + 2) * 8);
   r.row_ptr = (int64_t*)std::malloc((size_t)(nc + 3) * 8);
   r.col = (uint32_t*)std::malloc((size_t)std::max<int64_t>(m, 1) * 4);
-  r.cost = (int32_t*)std::malloc((size_t)std::max<int64_t>(m, 1) * 4);
-  if (!r.cell_i || !r.cell_j || !r.cell_ca || !r.cell_cb || !r.supply || !r.row_ptr || !r.col || !r.cost)
+  if (r.metric_l2) r.cost64 = (int64_t*)std::malloc((size_t)std::max<int64_t>(m, 1) * 8);
+  else r.cost = (int32_t*)std::malloc((size_t)std::max<int64_t>(m, 1) * 4);
+  if (!r.cell_i || !r.cell_j || !r.cell_ca || !r.cell_cb || !r.supply || !r.row_ptr || !r.col || !(r.cost || r.cost64))
     throw StageError{W1_ENOMEM};
   if (nc > 0) {
     std::vector<int2> ij((size_t)nc);
@@ -839,18 +870,20 @@ void copy_network(Ctx& c, int64_t p, w1_result& r) {
   }
   if (m > 0) {
     readback(c, (const uint32_t*)c.l1.p + as, r.col, m);
-    readback(c, (const int32_t*)c.costb.p + as, r.cost, m);
+    if (r.metric_l2) readback(c, (const int64_t*)c.costb.p + as, r.cost64, m);
+    else readback(c, (const int32_t*)c.costb.p + as, r.cost, m);
   }
 }
 
 void free_network(w1_result& r) {
-  void* ptrs[] = {r.cell_i, r.cell_j, r.cell_ca, r.cell_cb, r.supply, r.row_ptr, r.col, r.cost};
+  void* ptrs[] = {r.cell_i, r.cell_j, r.cell_ca, r.cell_cb, r.supply, r.row_ptr, r.col, r.cost, r.cost64};
   for (void* q : ptrs) std::free(q);
   r.cell_i = r.cell_j = r.cell_ca = r.cell_cb = nullptr;
   r.supply = nullptr;
   r.row_ptr = nullptr;
   r.col = nullptr;
   r.cost = nullptr;
+  r.cost64 = nullptr;
 }
 
 // Flow outcome into the result.  An optimal flow gives the certified w1.  A
@@ -869,15 +902,21 @@ void finish_flow(w1_result& r, const FlowResult& fr) {
   }
   r.flow_cost = fr.cost;
   r.flow_solved = 1;
-  r.w1 = std::ldexp((double)(fr.cost + r.n_points), r.grid_exp - 1);
-  r.w1_paper = std::ldexp((double)fr.cost, r.grid_exp - 1);
+  if (r.metric_l2) {  // g (F* 2^-K + n R): the condensation's n g / sqrt(2) added back
+    r.w1_paper = std::ldexp((double)fr.cost, r.grid_exp - r.cost_shift);
+    r.w1 = r.w1_paper + (double)r.n_points * std::ldexp(0x1.6a09e667f3bcdp-1, r.grid_exp);
+  } else {
+    r.w1 = std::ldexp((double)(fr.cost + r.n_points), r.grid_exp - 1);
+    r.w1_paper = std::ldexp((double)fr.cost, r.grid_exp - 1);
+  }
 }
 
 // Host flow of one pair from its host network copy (the sorted rows are
 // the solver's own input form).
 void solve_flow(w1_result& r, int64_t pivot_cap) {
   FlowResult fr{};
-  const int rc = network_simplex(r.n_cells + 2, r.row_ptr, r.col, r.cost, r.supply, pivot_cap, &fr);
+  const int rc = r.metric_l2 ? network_simplex64(r.n_cells + 2, r.row_ptr, r.col, r.cost64, r.supply, pivot_cap, &fr)
+                             : network_simplex(r.n_cells + 2, r.row_ptr, r.col, r.cost, r.supply, pivot_cap, &fr);
   if (rc != 0) {
     r.status = rc == -3 ? W1_ENOMEM : W1_EINVAL;
     return;
@@ -1081,7 +1120,7 @@ int w1_rwmd(w1_ctx* c, const w1_pd* a, const w1_pd* b, int64_t k, uint32_t flags
 
 int w1_rwmd_noalloc(w1_ctx* c, const w1_pd* a, const w1_pd* b, int64_t k, uint32_t flags, void* stream,
                     double* L_out) {
-  if (!c || !a || !b || k <= 0 || !L_out || (flags & ~W1_INPUT_DEVICE)) return W1_EINVAL;
+  if (!c || !a || !b || k <= 0 || !L_out || (flags & ~(W1_INPUT_DEVICE | W1_METRIC_L2))) return W1_EINVAL;
   if (k > kNoAllocMaxPairs) return W1_ERANGE;
   int64_t total = 0;
   for (int64_t p = 0; p < k; ++p) {
@@ -1131,7 +1170,8 @@ int w1_device_network_get(w1_ctx* c, int64_t k, w1_device_network* out) {
   out->supply = (const int64_t*)c->supply.p + cs + 2 * k;
   out->row_ptr = (const int64_t*)c->rp.p + cs + 3 * k;
   out->col = (const uint32_t*)c->l1.p + as;
-  out->cost = (const int32_t*)c->costb.p + as;
+  out->cost = c->network_l2 ? nullptr : (const int32_t*)c->costb.p + as;
+  out->cost64 = c->network_l2 ? (const int64_t*)c->costb.p + as : nullptr;
   return W1_OK;
 }
 

@@ -281,11 +281,54 @@ __global__ void k_bucket_fill(const double* __restrict__ lb, const double* __res
   entl[pos] = (uint32_t)l;
 }
 
-// Nearest location of the other diagram in L-infinity, capped by the cost
-// to the diagonal.  Buckets are visited in square rings around the query's
-// bucket; a location in ring r is at least (r - 1) h away (bucket indices are
-// exact floors of power-of-two scalings), so after ring r nothing closer
-// than r h remains and the search stops once best <= r h.
+// Nearest location of the other diagram, capped by the cost to the diagonal.
+// Metric of the nearest-neighbour search.  L-infinity: the running value is
+// the distance itself, max(|db|, |dd|).  Euclidean: the running value is the
+// squared distance q = db*db + dd*dd (each one IEEE double operation, in this
+// order), and the cost is min(sqrt(q_min), (d - b) R) at the end, R the
+// double nearest to 1/sqrt(2).  A location in ring r or beyond is at least
+// r h away in L-infinity, hence in Euclidean distance too, and because r h
+// is a double (h a power of two) its computed square and squared
+// differences are at least (r h)^2: once q_min <= (r h)^2 no later location
+// lowers it; once the diagonal cost is <= r h no later location can undercut
+// it, its square root being at least r h.
+constexpr double kRSqrt1_2 = 0x1.6a09e667f3bcdp-1;
+
+template <bool L2>
+struct NnMetric;
+
+template <>
+struct NnMetric<false> {
+  __device__ static double start(double b, double d) { return 0.5 * (d - b); }
+  __device__ static double eval(double b, double d, double qb, double qd) {
+    const double dist = fabs(b - qb), dy = fabs(d - qd);
+    return dy > dist ? dy : dist;
+  }
+  __device__ static bool done(double best, double diag, double rh) { return best <= rh; }
+  __device__ static double finish(double best, double diag) { return best; }
+  __device__ static double diag(double b, double d) { return 0.5 * (d - b); }
+};
+
+template <>
+struct NnMetric<true> {
+  __device__ static double start(double, double) { return __builtin_inf(); }
+  __device__ static double eval(double b, double d, double qb, double qd) {
+    const double gb = b - qb, gd = d - qd;
+    return gb * gb + gd * gd;
+  }
+  __device__ static bool done(double best, double diag, double rh) { return best <= rh * rh || diag <= rh; }
+  __device__ static double finish(double best, double diag) {
+    const double t = sqrt(best);
+    return t < diag ? t : diag;
+  }
+  __device__ static double diag(double b, double d) { return (d - b) * kRSqrt1_2; }
+};
+
+// Ring search over the other diagram's buckets: ring r holds the buckets at
+// Chebyshev index distance r from the query's bucket; a location in ring r
+// is at least (r - 1) h away (bucket indices are exact floors of
+// power-of-two scalings), so after ring r nothing closer than r h remains.
+template <bool L2>
 struct RingSearch {
   const uint32_t* binstart;
   const double2* ent;
@@ -296,14 +339,13 @@ struct RingSearch {
     const uint32_t e0 = binstart[bin], e1 = binstart[bin + 1];
     for (uint32_t e = e0; e < e1; ++e) {
       const double2 q = ent[e];
-      double dist = fabs(b - q.x);
-      const double dy = fabs(d - q.y);
-      if (dy > dist) dist = dy;
-      if (dist < best) best = dist;
+      const double v = NnMetric<L2>::eval(b, d, q.x, q.y);
+      if (v < best) best = v;
     }
   }
   // rings r0, r0 + 1, ... until certified or past the grid
-  __device__ void run(int64_t ix, int64_t iy, int64_t r0, int64_t rmax, double h, double b, double d, double& best) const {
+  __device__ void run(int64_t ix, int64_t iy, int64_t r0, int64_t rmax, double h, double b, double d, double diag,
+                      double& best) const {
     for (int64_t r = r0;; ++r) {
       if (r == 0) {
         visit(ix, iy, b, d, best);
@@ -319,18 +361,19 @@ struct RingSearch {
         if (ix + r < nx)
           for (int64_t y = y0; y <= y1; ++y) visit(ix + r, y, b, d, best);
       }
-      if (best <= (double)r * h || r >= rmax) break;
+      if (NnMetric<L2>::done(best, diag, (double)r * h) || r >= rmax) break;
     }
   }
 };
 
 // Every location starts at its cost to the diagonal (locations of a pair
 // with an error keep it).
+template <bool L2>
 __global__ void k_nn_init(const double* __restrict__ lb, const double* __restrict__ ld, const int32_t* __restrict__ lw,
                           int64_t M, double* __restrict__ lt, double* __restrict__ lterm) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= M) return;
-  const double best = 0.5 * (ld[l] - lb[l]);
+  const double best = NnMetric<L2>::diag(lb[l], ld[l]);
   const int32_t w = lw[l];
   lt[l] = best;
   lterm[l] = (double)(w > 0 ? w : -w) * best;
@@ -339,12 +382,13 @@ __global__ void k_nn_init(const double* __restrict__ lb, const double* __restric
 // One wave per bucket side: the other diagram's locations in the 3x3 block
 // of buckets around it (rings 0 and 1) are staged in LDS once and scanned by
 // every query of the bucket.  Every location closer than h lies in that
-// block, so a query whose best is <= h is done; the others continue with
+// block, so a query certified at radius h is done; the others continue with
 // ring 2 onwards.  A block with more candidates than fit runs the ring
 // search from ring 0.  The minimum is over the same locations as the plain
 // ring search, so the result is identical.
 constexpr int kNnCand = 1024;
 
+template <bool L2>
 __global__ void __launch_bounds__(64) k_nn_bins(const int32_t* __restrict__ lw, const uint32_t* __restrict__ lpair,
                                                 PairArrays P, const uint32_t* __restrict__ binstart,
                                                 const double2* __restrict__ ent, const uint32_t* __restrict__ entl,
@@ -355,7 +399,7 @@ __global__ void __launch_bounds__(64) k_nn_bins(const int32_t* __restrict__ lw, 
   if (e0 == e1) return;
   const int lane = lane_id();
   const uint32_t p = lpair[entl[e0]];  // every location of a bin belongs to one pair
-  RingSearch rs{binstart, ent, P.bbase[p], P.bnx[p], P.bny[p], (int)(qb & 1) ^ 1};
+  RingSearch<L2> rs{binstart, ent, P.bbase[p], P.bnx[p], P.bny[p], (int)(qb & 1) ^ 1};
   const int64_t cell = (qb >> 1) - rs.base;
   const int64_t ix = cell % rs.nx, iy = cell / rs.nx;
   int nc = 0;
@@ -381,23 +425,23 @@ __global__ void __launch_bounds__(64) k_nn_bins(const int32_t* __restrict__ lw, 
   for (uint32_t e = e0 + lane; e < e1; e += WAVE) {
     const double2 me = ent[e];
     const double b = me.x, d = me.y;
-    double best = 0.5 * (d - b);
+    const double diag = NnMetric<L2>::diag(b, d);
+    double best = NnMetric<L2>::start(b, d);
     if (spill) {
-      rs.run(ix, iy, 0, rmax, h, b, d, best);
+      rs.run(ix, iy, 0, rmax, h, b, d, diag, best);
     } else {
       for (int c = 0; c < nc; ++c) {
         const double2 q = cand[c];
-        double dist = fabs(b - q.x);
-        const double dy = fabs(d - q.y);
-        if (dy > dist) dist = dy;
-        if (dist < best) best = dist;
+        const double v = NnMetric<L2>::eval(b, d, q.x, q.y);
+        if (v < best) best = v;
       }
-      if (!(best <= h) && rmax >= 2) rs.run(ix, iy, 2, rmax, h, b, d, best);
+      if (!NnMetric<L2>::done(best, diag, h) && rmax >= 2) rs.run(ix, iy, 2, rmax, h, b, d, diag, best);
     }
+    const double t = NnMetric<L2>::finish(best, diag);
     const uint32_t l = entl[e];
     const int32_t w = lw[l];
-    lt[l] = best;
-    lterm[l] = (double)(w > 0 ? w : -w) * best;
+    lt[l] = t;
+    lterm[l] = (double)(w > 0 ? w : -w) * t;
   }
 }
 
@@ -469,8 +513,9 @@ __global__ void k_term_sum(const double* __restrict__ lterm, const int32_t* __re
 
 // L = max(L_A, L_B), each the fixed-point sum converted toward zero; grid
 // exponent e with 2^e <= (1 - 2^-40) * 2 eps_c L / n (Prop. delta-
-// condensation, L-infinity form).
-__global__ void k_params(PairArrays P, int64_t K, double eps_c) {
+// condensation, L-infinity form: a point moves by at most g/2), times R for
+// the Euclidean metric (a point moves by half a cell diagonal, g/sqrt(2)).
+__global__ void k_params(PairArrays P, int64_t K, double eps_c, int l2) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= K) return;
   const int64_t n = P.nA[p] + P.nB[p];
@@ -485,7 +530,8 @@ __global__ void k_params(PairArrays P, int64_t K, double eps_c) {
     set_err(&P.err[p], -2);
     return;
   }
-  const double gmax = ((2.0 * eps_c) * L) / (double)n;
+  double gmax = ((2.0 * eps_c) * L) / (double)n;
+  if (l2) gmax = gmax * kRSqrt1_2;
   const double gsafe = gmax * (1.0 - 0x1p-40);
   int E = 0;
   frexp(gsafe, &E);
@@ -738,11 +784,15 @@ void launch_bucket_fill(const double* lb, const double* ld, const int64_t* lbin,
 }
 void launch_nn(const double* lb, const double* ld, const int32_t* lw, const uint32_t* lpair, int64_t M,
                const PairArrays& P, const uint32_t* binstart, const double2* ent, const uint32_t* entl, int64_t nbins,
-               double* lt, double* lterm, hipStream_t st) {
-  LAUNCH(k_nn_init, M, lb, ld, lw, M, lt, lterm);
+               double* lt, double* lterm, bool l2, hipStream_t st) {
+  if (l2) {
+    LAUNCH(k_nn_init<true>, M, lb, ld, lw, M, lt, lterm);
+  } else {
+    LAUNCH(k_nn_init<false>, M, lb, ld, lw, M, lt, lterm);
+  }
   if (nbins > 1)
-    hipLaunchKernelGGL(k_nn_bins, dim3((unsigned)(nbins - 1)), dim3(WAVE), 0, st, lw, lpair, P, binstart, ent, entl, lt,
-                       lterm);
+    hipLaunchKernelGGL(l2 ? k_nn_bins<true> : k_nn_bins<false>, dim3((unsigned)(nbins - 1)), dim3(WAVE), 0, st, lw,
+                       lpair, P, binstart, ent, entl, lt, lterm);
 }
 void launch_term_max(const double* lterm, const int32_t* lw, const uint32_t* lpair, int64_t M, const PairArrays& P,
                      hipStream_t st) {
@@ -753,7 +803,9 @@ void launch_term_sum(const double* lterm, const int32_t* lw, const uint32_t* lpa
                      hipStream_t st) {
   LAUNCH(k_term_sum, M, lterm, lw, lpair, M, P);
 }
-void launch_params(const PairArrays& P, int64_t K, double eps_c, hipStream_t st) { LAUNCH(k_params, K, P, K, eps_c); }
+void launch_params(const PairArrays& P, int64_t K, double eps_c, bool l2, hipStream_t st) {
+  LAUNCH(k_params, K, P, K, eps_c, l2 ? 1 : 0);
+}
 void launch_snap(const double* lb, const double* ld, const uint32_t* lpair, int64_t M, const PairArrays& P, int64_t* li,
                  int64_t* lj, hipStream_t st) {
   LAUNCH(k_snap, M, lb, ld, lpair, M, P, li, lj);

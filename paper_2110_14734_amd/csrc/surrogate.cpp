@@ -618,7 +618,9 @@ int w1_nn_query(w1_ctx* c, w1_nn_index* x, w1_surrogate* s, const w1_pd* q, int6
     const auto t0 = clk::now();
     std::vector<int64_t> cur((size_t)nq, 0);
     std::vector<char> live((size_t)nq, 1);
-    w1_params wp{p->eps, 0.1, 0, W1_INPUT_DEVICE, 0};
+    // verifications solve the network without its diagonal-dominated pairs:
+    // the same optimum, hence the same w1, with a smaller flow problem
+    w1_params wp{p->eps, 0.1, 0, W1_INPUT_DEVICE | W1_PRUNE, 0};
     int r = W1_OK;
     for (;;) {
       std::vector<int64_t> who, cand;

@@ -40,13 +40,6 @@ __device__ inline int64_t node_size(const TreeView& T, int32_t r) {
   const int4 a = T.iaux[r];
   return (int64_t)a.w - a.z + 1;
 }
-__device__ inline int32_t box_diam(int4 b) { return max(b.z - b.x, b.w - b.y); }
-__device__ inline bool separated(int4 a, int4 b, int s) {
-  const int gi = max(a.x - b.z, b.x - a.z);
-  const int gj = max(a.y - b.w, b.y - a.w);
-  const int dist = max(0, max(gi, gj));
-  return (int64_t)dist >= (int64_t)s * (int64_t)max(box_diam(a), box_diam(b));
-}
 // Diagonal dominance of a node pair (optional pruning, not in the paper).
 // Costs in units of g/2: an arc between cells p and q costs 2 max(|di|,|dj|)
 // >= 2 dist(box U, box V), and a cell's arc to the diagonal costs j - i <=
@@ -65,6 +58,49 @@ __device__ inline bool dominated(int4 a, int4 b) {
   const int gj = max(a.y - b.w, b.y - a.w);
   const uint32_t dist = (uint32_t)max(0, max(gi, gj));
   return 2u * dist >= (uint32_t)(a.w - a.x) + (uint32_t)(b.w - b.x);
+}
+
+// Metric of the separation test.  L-infinity: a node's diameter is its
+// longest box side and (U, V) is separated when the box gap is at least s
+// times the larger diameter.  Euclidean (the paper's balls): the diameter
+// is the squared box diagonal and (U, V) is separated when the squared
+// Euclidean box gap is at least s^2 times the larger one, in exact 128-bit
+// integers.  The node with the larger diameter is split.
+template <bool L2>
+struct WMet;
+
+template <>
+struct WMet<false> {
+  typedef int32_t D;
+  __device__ static D diam(int4 b) { return max(b.z - b.x, b.w - b.y); }
+  __device__ static bool sep(int4 a, D da, int4 b, D db, int s) {
+    const int dist = max(max(max(a.x - b.z, b.x - a.z), max(a.y - b.w, b.y - a.w)), 0);
+    return (int64_t)dist >= (int64_t)s * (int64_t)max(da, db);
+  }
+};
+
+template <>
+struct WMet<true> {
+  typedef int64_t D;
+  __device__ static D diam(int4 b) {
+    const int64_t w = b.z - b.x, h = b.w - b.y;
+    return w * w + h * h;
+  }
+  __device__ static bool sep(int4 a, D da, int4 b, D db, int s) {
+    const int64_t gi = max(max(a.x - b.z, b.x - a.z), 0), gj = max(max(a.y - b.w, b.y - a.w), 0);
+    const unsigned __int128 d2 = (unsigned __int128)(uint64_t)(gi * gi + gj * gj);
+    return d2 >= (unsigned __int128)(uint64_t)((int64_t)s * s) * (uint64_t)(da > db ? da : db);
+  }
+};
+
+template <bool L2>
+__device__ inline bool separated_m(int4 a, int4 b, int s) {
+  return WMet<L2>::sep(a, WMet<L2>::diam(a), b, WMet<L2>::diam(b), s);
+}
+// the first node is split (rather than the second) when its diameter is larger
+template <bool L2>
+__device__ inline bool split_first(int4 a, int4 b) {
+  return WMet<L2>::diam(a) > WMet<L2>::diam(b);
 }
 
 __global__ void k_roots_flags(TreeView T, uint32_t* __restrict__ flag) {
@@ -86,7 +122,7 @@ __global__ void k_roots_fill(TreeView T, const uint32_t* __restrict__ flag, cons
 // count 1; expanded -> high word count 2; dropped (diagonal-dominated, with
 // pruning on) -> 0.
 __global__ void k_classify(TreeView T, const int2* __restrict__ items, int64_t f, int s, int stack_depth,
-                           const int32_t* __restrict__ pair_cap, int prune, uint64_t* __restrict__ cnt) {
+                           const int32_t* __restrict__ pair_cap, int prune, int l2, uint64_t* __restrict__ cnt) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= f) return;
   const int2 it = items[x];
@@ -98,13 +134,13 @@ __global__ void k_classify(TreeView T, const int2* __restrict__ items, int64_t f
   const int64_t work_cap = pair_cap[T.cpair[node_rep(T, it.x)]];
   const bool small = node_height(T, it.x) + node_height(T, it.y) <= stack_depth - 1 &&
                      node_size(T, it.x) * node_size(T, it.y) <= work_cap;
-  const bool keep = small || separated(bu, bv, s);
+  const bool keep = small || (l2 ? separated_m<true>(bu, bv, s) : separated_m<false>(bu, bv, s));
   cnt[x] = keep ? 1ull : (2ull << 32);
 }
 
 __global__ void k_scatter(TreeView T, const int2* __restrict__ items, int64_t f, const uint64_t* __restrict__ cnt,
                           const uint64_t* __restrict__ pos, int2* __restrict__ out_items, int64_t out_base,
-                          int2* __restrict__ next) {
+                          int l2, int2* __restrict__ next) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= f) return;
   const int2 it = items[x];
@@ -116,7 +152,7 @@ __global__ void k_scatter(TreeView T, const int2* __restrict__ items, int64_t f,
   }
   const int64_t q = (int64_t)(p >> 32);
   const int4 bu = node_box(T, it.x), bv = node_box(T, it.y);
-  if (box_diam(bu) > box_diam(bv)) {
+  if (l2 ? split_first<true>(bu, bv) : split_first<false>(bu, bv)) {
     const int4 a = T.iaux[it.x];
     next[q] = make_int2(a.x, it.y);
     next[q + 1] = make_int2(a.y, it.y);
@@ -228,16 +264,16 @@ __global__ void k_pack_nodes(TreeView T, const int64_t* __restrict__ cell_start,
 // separated entry (fresh items only) is output as it is, U = P.
 // Gathers the sorted work list (items[perm[x]]) and writes the entries.
 __global__ void k_item_prep(TreeView T, const int2* __restrict__ items, const uint32_t* __restrict__ perm, int64_t m,
-                            int s, const int32_t* __restrict__ rmap, int2* __restrict__ out) {
+                            int s, const int32_t* __restrict__ rmap, int l2, int2* __restrict__ out) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= m) return;
   const int2 it = items[perm[x]];
   const int4 bu = node_box(T, it.x), bv = node_box(T, it.y);
   const int32_t ru = rmap[ref_index(T, it.x)], rv = rmap[ref_index(T, it.y)];
   int2 e;
-  if (separated(bu, bv, s))
+  if (l2 ? separated_m<true>(bu, bv, s) : separated_m<false>(bu, bv, s))
     e = make_int2(ru | INT32_MIN, rv | INT32_MIN);
-  else if (box_diam(bu) > box_diam(bv))
+  else if (l2 ? split_first<true>(bu, bv) : split_first<false>(bu, bv))
     e = make_int2(ru | INT32_MIN, rv);
   else
     e = make_int2(rv, ru);
@@ -284,12 +320,6 @@ __device__ inline void unpack_boxes(uint4 w0, uint4 w1, int4& b1, int4& b2) {
   b2.w = (int)(w1.z >> 4);
 }
 
-// Separation with the diameters already known.
-__device__ inline bool separated_d(int4 a, int da, int4 b, int db, int s) {
-  const int dist = max(max(max(a.x - b.z, b.x - a.z), max(a.y - b.w, b.y - a.w)), 0);
-  return (int64_t)dist >= (int64_t)s * (int64_t)max(da, db);
-}
-
 // Three-word pair record.  The vector type is 16 bytes in size (its store is
 // 12), so records are addressed in 32-bit words, never by u32x3 arithmetic.
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
@@ -298,10 +328,13 @@ typedef u32x3 u32x3_w __attribute__((aligned(4)));
 // Output pair (rep U, rep V, cost) of child / node aux c and the other node's
 // aux o; orient = 1 when c is on the U side.  Cost = 2 * L-infinity distance
 // of the representatives in grid units.
+// (The Euclidean network's costs need more than 32 bits and are formed when
+// the network's rows are sorted; its records carry 0 in the cost word.)
+template <bool L2>
 __device__ inline u32x3 make_emit(int4 c, int4 o, bool orient) {
   const uint32_t ci = (uint32_t)c.z, oi = (uint32_t)o.z, cj = (uint32_t)c.w, oj = (uint32_t)o.w;
   const uint32_t di = ci > oi ? ci - oi : oi - ci, dj = cj > oj ? cj - oj : oj - cj;
-  return u32x3{(uint32_t)(orient ? c.y : o.y), (uint32_t)(orient ? o.y : c.y), 2u * max(di, dj)};
+  return u32x3{(uint32_t)(orient ? c.y : o.y), (uint32_t)(orient ? o.y : c.y), L2 ? 0u : 2u * max(di, dj)};
 }
 
 // Checksum term of a pair record (u, v, cost) (see w1_result.pair_checksum).
@@ -332,7 +365,7 @@ __device__ inline uint32_t lanes_set_below(uint64_t m, uint32_t add) {
 // written as 12-byte records at the wave cursor in (slot, lane) order, so the
 // order depends only on the chunk.  Loop control lives in wave-uniform
 // scalars.
-template <bool EMIT, bool COMPACT, bool PRUNE>
+template <bool EMIT, bool COMPACT, bool PRUNE, bool L2>
 __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const uint4* __restrict__ SR,
                                               const int2* __restrict__ items,
                                               const int32_t* __restrict__ chunk_first, const int32_t* __restrict__ chunk_end,
@@ -367,8 +400,10 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       uint64_t h1 = 0, h2 = 0;  // streamed emission: the lane's checksum terms
       const uint64_t cs = EMIT && bh.NB > 0 ? (uint64_t)bh.cell_start[bh.chunk_pair[k]] : 0;
       uint64_t cursor = 0;
+      typedef typename WMet<L2>::D Diam;
       bool has = false, overflow = false, runaway = false, orient = false;
-      int sp = 0, oid = 0, od = 0;
+      int sp = 0, oid = 0;
+      Diam od = 0;
       int4 ob = make_int4(0, 0, 0, 0), oa = ob, pa = ob;
       for (int64_t step = 0;; ++step) {
         if (step > step_cap) {  // beyond any chunk's possible work: give up, report
@@ -410,10 +445,10 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
         if (got) {
           if (q.y < 0) {
             e1 = true;
-            if (EMIT) m1 = make_emit(pa, oa, orient);
+            if (EMIT) m1 = make_emit<L2>(pa, oa, orient);
           } else {
             has = true;
-            od = box_diam(ob);
+            od = WMet<L2>::diam(ob);
           }
         }
         if (has) {
@@ -431,11 +466,11 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
             C1 = Rec{pc[0], pc[1]};
             C2 = Rec{pc[2], pc[3]};
           }
-          const int d1 = box_diam(C1.box), d2 = box_diam(C2.box);
-          const bool s1 = separated_d(C1.box, d1, ob, od, s), s2 = separated_d(C2.box, d2, ob, od, s);
+          const Diam d1 = WMet<L2>::diam(C1.box), d2 = WMet<L2>::diam(C2.box);
+          const bool s1 = WMet<L2>::sep(C1.box, d1, ob, od, s), s2 = WMet<L2>::sep(C2.box, d2, ob, od, s);
           if (EMIT) {
-            m1 = make_emit(C1.aux, oa, orient);
-            m2 = make_emit(C2.aux, oa, orient);
+            m1 = make_emit<L2>(C1.aux, oa, orient);
+            m2 = make_emit<L2>(C2.aux, oa, orient);
           }
           // a child pair is done when separated (output unless dominated) or
           // dominated (pruning: no output, nothing below it)
@@ -457,7 +492,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
           }
           if (!r1 || !r2) {  // the lane's next pair: (first child not done, O)
             const bool first = !r1;
-            const int dn = first ? d1 : d2;
+            const Diam dn = first ? d1 : d2;
             const int4 na = first ? C1.aux : C2.aux;
             if (orient ? dn > od : dn >= od) {
               pa = na;
@@ -558,20 +593,20 @@ void launch_pack_nodes(const TreeView& T, const int64_t* cell_start, int4* rec, 
 }
 void launch_pack_split(const TreeView& T, uint4* out, hipStream_t st) { LAUNCH(k_pack_split, T.N - 1, T, out); }
 void launch_item_prep(const TreeView& T, const int2* items, const uint32_t* perm, int64_t m, int s, const int32_t* rmap,
-                      int2* out, hipStream_t st) {
-  LAUNCH(k_item_prep, m, T, items, perm, m, s, rmap, out);
+                      bool l2, int2* out, hipStream_t st) {
+  LAUNCH(k_item_prep, m, T, items, perm, m, s, rmap, l2 ? 1 : 0, out);
 }
 void launch_wspd_roots_flags(const TreeView& T, uint32_t* flag, hipStream_t st) { LAUNCH(k_roots_flags, T.N - 1, T, flag); }
 void launch_wspd_roots_fill(const TreeView& T, const uint32_t* flag, const uint32_t* pos, int2* items, hipStream_t st) {
   LAUNCH(k_roots_fill, T.N - 1, T, flag, pos, items);
 }
 void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s, const WspdTuning& tun,
-                          const int32_t* pair_cap, bool prune, uint64_t* cnt, hipStream_t st) {
-  LAUNCH(k_classify, f, T, items, f, s, tun.stack_depth, pair_cap, prune ? 1 : 0, cnt);
+                          const int32_t* pair_cap, bool prune, bool l2, uint64_t* cnt, hipStream_t st) {
+  LAUNCH(k_classify, f, T, items, f, s, tun.stack_depth, pair_cap, prune ? 1 : 0, l2 ? 1 : 0, cnt);
 }
 void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const uint64_t* cnt, const uint64_t* pos,
-                         int2* out_items, int64_t out_base, int2* next, hipStream_t st) {
-  LAUNCH(k_scatter, f, T, items, f, cnt, pos, out_items, out_base, next);
+                         int2* out_items, int64_t out_base, bool l2, int2* next, hipStream_t st) {
+  LAUNCH(k_scatter, f, T, items, f, cnt, pos, out_items, out_base, l2 ? 1 : 0, next);
 }
 void launch_item_keys(const TreeView& T, const int2* items, int64_t m, bool both, uint64_t* keys, hipStream_t st) {
   LAUNCH(k_item_keys, m, T, items, m, both ? 1 : 0, keys);
@@ -590,7 +625,7 @@ void launch_chunks(const int32_t* cstart, int64_t K, const int64_t* item_start, 
 void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
-                      uint32_t* out, int32_t* err, bool prune, const BucketHist& bh, const StreamOut& so,
+                      uint32_t* out, int32_t* err, bool prune, bool l2, const BucketHist& bh, const StreamOut& so,
                       int num_cus, hipStream_t st) {
   if (nchunks <= 0) return;
   int64_t grid = (int64_t)num_cus * tun.blocks_per_cu;
@@ -601,9 +636,12 @@ void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, con
   const int64_t step_cap = (int64_t)tun.chunk_items * (2 * (int64_t)tun.work_cap + 2) + 1024;
   // the emit pass always reads the children's records (the packed split
   // records serve the count pass)
-  auto k = prune ? (emit ? k_wspd<true, false, true> : (split_recs ? k_wspd<false, true, true> : k_wspd<false, false, true>))
-                 : (emit ? k_wspd<true, false, false>
-                         : (split_recs ? k_wspd<false, true, false> : k_wspd<false, false, false>));
+  auto k = l2 ? (emit ? k_wspd<true, false, false, true>
+                      : (split_recs ? k_wspd<false, true, false, true> : k_wspd<false, false, false, true>))
+         : prune ? (emit ? k_wspd<true, false, true, false>
+                         : (split_recs ? k_wspd<false, true, true, false> : k_wspd<false, false, true, false>))
+                 : (emit ? k_wspd<true, false, false, false>
+                         : (split_recs ? k_wspd<false, true, false, false> : k_wspd<false, false, false, false>));
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds, st, T.inode, split_recs, items, chunk_first, chunk_end,
                      xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, out, err,
                      emit ? bh : BucketHist{}, emit ? so : StreamOut{});

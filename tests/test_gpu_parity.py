@@ -68,7 +68,7 @@ def _stored_flows():
 STORED = _stored_flows()
 
 
-def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True, prune=False, stored=None):
+def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True, prune=False, stored=None, l2=False):
     """Stage-by-stage parity with the oracle.  `stored` names the oracle's
     optimal flow written by tests/golden/make_oracle_flows.py; the oracle
     then runs without its (slow) flow solve.  Pruning leaves F* unchanged,
@@ -76,9 +76,10 @@ def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True, prune=F
     import paper_2110_14734_amd as w1
 
     flags = w1.KEEP_NETWORK | w1.KEEP_STAGES | (0 if flow else w1.NO_FLOW) | (w1.PRUNE if prune else 0)
+    flags |= w1.METRIC_L2 if l2 else 0
     g = ctx.approx(A, B, eps=eps, s_override=s_override, flags=flags)
     oflow = flow and stored is None
-    oflags = (0 if oflow else orc.ORC_NO_FLOW) | (orc.ORC_PRUNE if prune else 0)
+    oflags = (0 if oflow else orc.ORC_NO_FLOW) | (orc.ORC_PRUNE if prune else 0) | (orc.ORC_L2 if l2 else 0)
     r = orc.run(A, B, eps=eps, s_override=s_override, flags=oflags)
     assert r.status == 0 and g.status == 0
     # a0: net 0-condensation
@@ -108,7 +109,9 @@ def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True, prune=F
     # a4 + a5: the WSPD pairs and the network, compared as the sorted rows
     # element by element (no host-side sorting of the library's output)
     assert g.n_pairs == r.n_pairs
-    check_csr(net, orc.csr(A, B, eps=eps, s_override=s_override, prune=prune))
+    if l2:
+        assert g.metric_l2 and g.cost_shift == r.K
+    check_csr(net, orc.csr(A, B, eps=eps, s_override=s_override, prune=prune, l2=l2))
     # flow and W1
     if flow and stored is None:
         assert g.flow_cost == r.flow
@@ -140,6 +143,59 @@ def test_prune_parity(orc, ctx, name, make, eps):
     g, r = compare(orc, ctx, A, B, eps=eps, prune=True, stored=name)
     full = ctx.approx(A, B, eps=eps)
     assert g.flow_cost == full.flow_cost and g.w1 == full.w1 and g.n_pairs <= full.n_pairs
+
+
+@pytest.mark.parametrize("name,make,eps", CASES, ids=[c[0] for c in CASES])
+def test_l2_parity(orc, ctx, name, make, eps):
+    """Euclidean ground metric: every stage bit for bit with the oracle --
+    RWMD costs and L, grid, cells, tree, the sorted network with its 64-bit
+    costs -- and F* and W1 equal to the oracle's stored optimum."""
+    _say(f"[gpu] Euclidean parity {name}")
+    A, B = make()
+    compare(orc, ctx, A, B, eps=eps, stored=name + "_l2", l2=True)
+
+
+def test_l2_batch_small_s_and_errors(orc, ctx):
+    """Euclidean metric in the batched form and at small s: per-pair counts,
+    networks and W1 equal the single calls and the oracle; pruning is
+    rejected."""
+    import paper_2110_14734_amd as w1
+
+    _say("[gpu] Euclidean batch")
+    As, Bs = cases.batch_pairs()
+    batch = ctx.approx_batch(As, Bs, eps=0.2, flags=w1.KEEP_NETWORK | w1.METRIC_L2)
+    for i in range(len(As)):
+        single = ctx.approx(As[i], Bs[i], eps=0.2, flags=w1.KEEP_NETWORK | w1.METRIC_L2)
+        assert same_network(batch[i], single) and batch[i].w1 == single.w1
+        r = orc.run(As[i], Bs[i], eps=0.2, flags=orc.ORC_L2 | orc.ORC_NO_FLOW)
+        assert batch[i].n_pairs == r.n_pairs and batch[i].lower_bound == r.L
+        if r.n:
+            check_csr(batch[i].network, orc.csr(As[i], Bs[i], eps=0.2, l2=True))
+    A, B = cases.small_s_pair()
+    for s in (1, 3):
+        compare(orc, ctx, A, B, eps=0.1, s_override=s, flow=False, l2=True)
+    with pytest.raises(w1.W1Error) as e:
+        ctx.approx(A, B, eps=0.1, flags=w1.METRIC_L2 | w1.PRUNE)
+    assert e.value.code == w1.W1_EINVAL
+    # the RWMD bound alone in the Euclidean metric
+    L = ctx.rwmd(As[:4], Bs[:4], flags=w1.METRIC_L2)
+    for i in range(4):
+        assert L[i] == orc.run(As[i], Bs[i], eps=0.2, flags=orc.ORC_L2 | orc.ORC_NO_FLOW).L
+
+
+def test_l2_bracket_against_exact(orc, ctx):
+    """Euclidean (1 + eps) bracket against Hungarian matching with Euclidean
+    costs, end to end, on 20 pairs of 120 + 110 points (exact W1 computed
+    here: 230 x 230 assignments)."""
+    _say("[gpu] Euclidean bracket")
+    As = [pdsynth.exp_pd(120, 7000 + 2 * k) for k in range(20)]
+    Bs = [pdsynth.exp_pd(110, 7001 + 2 * k) for k in range(20)]
+    import paper_2110_14734_amd as w1
+
+    res = ctx.approx_batch(As, Bs, eps=0.1, flags=w1.METRIC_L2)
+    for A, B, g in zip(As, Bs, res):
+        ex = orc.exact_w1(A, B, l2=True)
+        assert g.lower_bound <= ex * (1 + 2.0**-50) and ex <= g.w1 <= 1.1 * ex
 
 
 def test_prune_batch_and_count_only(orc, ctx):
