@@ -752,12 +752,13 @@ int orc_run(void* p, const double* A, int64_t nA, const double* B, int64_t nB, d
   o.stage_s[2] = lap(t0);
   if (st) return o.status = st;
   if (o.l2) {
-    // cost scale 2^K: every cost is at most about bitlen(X) + K bits and F*
-    // at most n times the largest diagonal cost, so K = 61 - bitlen(n) -
-    // bitlen(X) keeps F* below 2^62 (X: the largest shifted coordinate)
+    // cost scale 2^K: every cost is below 2^(bitlen(X) + 1 + K) and F* at
+    // most n times the largest diagonal cost (X: the largest shifted
+    // coordinate), so K = 59 - bitlen(n) - bitlen(X) keeps F* and any
+    // big-M cost of (max cost + 1)(node count + 1) below 2^60
     int64_t X = 1;
     for (const Cell& c : o.cells) X = std::max(X, std::max(c.i, c.j));
-    o.K = std::min(30, 61 - bitlen((uint64_t)o.n) - bitlen((uint64_t)X));
+    o.K = std::min(30, 59 - bitlen((uint64_t)o.n) - bitlen((uint64_t)X));
     if (o.K < 0) return o.status = ORC_ERANGE;
   }
   tree(o);
