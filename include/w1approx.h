@@ -166,7 +166,8 @@ typedef struct {
    * the pairs written through the arena, and an order-independent checksum
    * of them (test bookkeeping): with h(u, v, c) = (((u + 1) K1 + (v + 1)) K2
    * + c) K3 mod 2^64 over the pair records (u = representative of the
-   * pair's first node, v of its second, c the cost, local cell ids),
+   * pair's first node, v of its second, c the cost, local cell ids; under
+   * W1_METRIC_L2 the records carry no cost and c = 0),
    * K1 = 0x9E3779B97F4A7C15, K2 = 0xC2B2AE3D27D4EB4F,
    * K3 = 0x165667B19E3779F9: pair_checksum = (sum h, sum h^2) mod 2^64.
    * The checksum covers all of the pair's n_pairs when n_pairs_streamed

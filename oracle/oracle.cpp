@@ -448,7 +448,9 @@ void emit(Oracle& o, int64_t U, int64_t V) {
   int64_t c = o.l2 ? cost_l2(o.cells[u].i - o.cells[v].i, o.cells[u].j - o.cells[v].j, o.K)
                    : 2 * std::max(std::llabs(o.cells[u].i - o.cells[v].i), std::llabs(o.cells[u].j - o.cells[v].j));
   ++o.n_pairs;
-  uint64_t h = pair_mix((uint64_t)u, (uint64_t)v, (uint64_t)c);
+  // record checksum: a Euclidean pair record carries no cost (its costs come
+  // from the cells when the network rows are built), so c = 0 enters it
+  uint64_t h = pair_mix((uint64_t)u, (uint64_t)v, o.l2 ? 0 : (uint64_t)c);
   o.chk1 += h;
   o.chk2 += h * h;
   if (o.count_only) return;

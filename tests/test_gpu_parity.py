@@ -585,6 +585,25 @@ def test_stream_emission_small(orc, ctx):
         ctx.tuning = t0
 
 
+def test_stream_emission_l2(orc, ctx):
+    """Streamed emission under the Euclidean metric: the streamed count and
+    the record checksum (records carry no cost there) equal the oracle's."""
+    import paper_2110_14734_amd as w1
+
+    _say("[gpu] streamed emission, Euclidean")
+    t0 = ctx.tuning
+    try:
+        for name, make, eps in cases.STAGE_CASES[:3]:
+            A, B = make()
+            r = orc.run(A, B, eps=eps, flags=orc.ORC_COUNT_ONLY | orc.ORC_L2, fetch=False)
+            ctx.tuning = dict(t0, stream_arena_pairs=max(20_000, r.n_pairs // 5))
+            g = ctx.approx(A, B, eps=eps, flags=w1.COUNT_ONLY | w1.METRIC_L2)
+            assert g.n_pairs == r.n_pairs == g.n_pairs_streamed, name
+            assert g.pair_checksum == tuple(r.checksum), name
+    finally:
+        ctx.tuning = t0
+
+
 def test_stream_emission_batched_sample(ctx):
     """Every 16th pair of the 4096-pair batched workload (256 pairs, eps 0.1)
     streamed in one batch call: per-pair counts and record checksums equal

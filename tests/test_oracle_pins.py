@@ -765,3 +765,30 @@ def test_l2_condensation_corner(orc):
     # the rounding of that product
     assert r.L <= ex * (1 + 2.0**-50) and ex <= r.W1 <= 1.1 * ex
     assert ex - r.W1_paper > 0.7 * g  # most of the half diagonal
+
+
+# ------------------------------------------------------- record checksum --
+def _mix(u, v, c):
+    # the record hash as the library header defines it, in Python integers
+    M = 2**64
+    x = (((u + 1) * 0x9E3779B97F4A7C15 + (v + 1)) * 0xC2B2AE3D27D4EB4F + c) % M
+    return (x * 0x165667B19E3779F9) % M
+
+
+@pytest.mark.parametrize("l2", [False, True])
+def test_pair_checksum_definition(orc, l2):
+    # The count-only checksum equals the definition summed over the pair list
+    # the oracle emits (whose coverage and separation other pins fix); a
+    # Euclidean record carries no cost, so c = 0 there.
+    A = pdsynth.exp_pd(70, 1201)
+    B = pdsynth.exp_pd(60, 1202)
+    fl = orc.ORC_L2 if l2 else 0
+    full = orc.run(A, B, eps=0.2, flags=fl | orc.ORC_NO_FLOW)
+    cnt = orc.run(A, B, eps=0.2, flags=fl | orc.ORC_COUNT_ONLY, fetch=False)
+    assert cnt.n_pairs == full.n_pairs > 100
+    h1 = h2 = 0
+    for u, v, c in zip(full.pairs["u"].tolist(), full.pairs["v"].tolist(), full.pairs["c"].tolist()):
+        h = _mix(u, v, 0 if l2 else c)
+        h1 = (h1 + h) % 2**64
+        h2 = (h2 + h * h) % 2**64
+    assert cnt.checksum == full.checksum == (h1, h2)
