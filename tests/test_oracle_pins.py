@@ -170,6 +170,13 @@ def test_rwmd_fixed_point_rounds_down(orc):
         k = int(side.sum())
         assert Fraction(Lx) <= exact
         assert exact - Fraction(Lx) <= Fraction(k + 1, 2 ** F) + exact * Fraction(1, 2 ** 52)
+    # A sum whose fixed-point total is exactly representable, so the final
+    # conversion cannot hide a term rounded the wrong way: one unit diagonal
+    # term and 200 terms of 2^-60 (each far below one fixed-point unit of
+    # 2^-53).  Every small term drops, and L_A = 1 exactly, below the real sum.
+    tiny = [[j * 2.0 ** -50, j * 2.0 ** -50 + 2.0 ** -59] for j in range(1, 201)]
+    r = orc.run(np.array([[0.0, 2.0]] + tiny), np.zeros((0, 2)), eps=0.1, flags=orc.ORC_STOP_AFTER_TREE)
+    assert r.FA == 53 and r.LA == 1.0 and Fraction(r.LA) < 1 + Fraction(200, 2 ** 60)
 
 
 def test_rwmd_lower_bound_and_net(orc):
