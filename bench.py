@@ -48,7 +48,14 @@ KERNEL_NAMES = {"emit_ms": "k_wspd<emit> (WSPD pair records)",
 # counter runs on the benchmark workload (each scaled by a copy-kernel
 # calibration), valid only for the kernel source they were measured on:
 # {kernel key: (source file, sha256 prefix of that file, bytes per launch)}.
-MEASURED_TRAFFIC = {}
+# (profiles/a4_a5_kernels_c2_200k_eps0.1_hbm_counters.md)
+MEASURED_TRAFFIC = {
+    "emit_ms": ("paper_2110_14734_amd/csrc/wspd.hip", "c4a546a641e7185b", 26_329_373_020),
+    "bucket_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "4d0f6f070d9a4e10", 36_947_765_805),
+    "row_hist_ms": ("paper_2110_14734_amd/csrc/csr.hip", "4d0f6f070d9a4e10", 15_307_268_594),
+    "row_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "4d0f6f070d9a4e10", 31_690_121_048),
+    "row_sort_ms": ("paper_2110_14734_amd/csrc/csr.hip", "4d0f6f070d9a4e10", 49_755_861_571),
+}
 
 
 def measured_traffic(key, n_points, eps):
@@ -396,7 +403,8 @@ def main():
         nbytes = bp * P + bn * N
         ach = nbytes / (kern[k] * 1e-3) / 1e9 if kern[k] > 0 else 0.0
         kernels[k] = {"kernel": KERNEL_NAMES[k], "avg_launch_ms": round(kern[k], 4), "algorithmic_bytes": nbytes,
-                      "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)}
+                      "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                      "traffic": measured_traffic(k, n, args.eps)}
     dom = max(KERNEL_BYTES, key=lambda k: kern[k])
     traffic = measured_traffic(dom, n, args.eps)
     d = kernels[dom]
