@@ -35,6 +35,7 @@ ORC_KEEP_PAIR_NODES = 8
 ORC_SKIP_RWMD = 16
 ORC_PRUNE = 32
 ORC_L2 = 64
+ORC_PAPER_GRID = 128
 
 STAGE_NAMES = ("O0-O1 condense", "O2 RWMD", "O3-O5 grid + Morton", "O6 tree", "O7 WSPD", "O8 network",
                "O9 flow")
@@ -190,16 +191,17 @@ def run(A, B, eps: float = 0.1, kappa: float = 0.1, s_override: int = 0, flags: 
         L_.orc_free(h)
 
 
-def network(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False, l2=False):
+def network(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False, l2=False, paper_grid=False):
     """Sparse transshipment network of the oracle: (src, dst, cost, supply).
-    prune: leave out the diagonal-dominated WSPD pairs (O7')."""
+    prune: leave out the diagonal-dominated WSPD pairs (O7'); paper_grid: the
+    grid of Alg. 2 / Alg. 3 for the given s_override."""
     L_ = lib()
     A64, B64 = _as_f64(A), _as_f64(B)
     h = L_.orc_new()
     try:
         st = L_.orc_run(h, _ptr(A64), A64.shape[0], _ptr(B64), B64.shape[0], float(eps), float(kappa),
-                        int(s_override), ORC_NO_FLOW | (ORC_PRUNE if prune else 0) | (ORC_L2 if l2 else 0),
-                        0.0)
+                        int(s_override), ORC_NO_FLOW | (ORC_PRUNE if prune else 0) | (ORC_L2 if l2 else 0)
+                        | (ORC_PAPER_GRID if paper_grid else 0), 0.0)
         if st != 0:
             raise RuntimeError(f"oracle status {st}")
         m = int(L_.orc_network(h, None, None, None, None))
@@ -212,17 +214,18 @@ def network(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False, l2=False):
         L_.orc_free(h)
 
 
-def csr(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False, l2=False):
+def csr(A, B, eps=0.1, kappa=0.1, s_override=0, prune=False, l2=False, paper_grid=False):
     """The oracle's network in compressed sparse row form (O8): arcs sorted by
     (tail, head).  Returns dict(row_ptr, col, cost, supply, n_cells).
-    prune: leave out the diagonal-dominated WSPD pairs (O7')."""
+    prune: leave out the diagonal-dominated WSPD pairs (O7'); paper_grid: the
+    grid of Alg. 2 / Alg. 3 for the given s_override."""
     L_ = lib()
     A64, B64 = _as_f64(A), _as_f64(B)
     h = L_.orc_new()
     try:
         st = L_.orc_run(h, _ptr(A64), A64.shape[0], _ptr(B64), B64.shape[0], float(eps), float(kappa),
-                        int(s_override), ORC_NO_FLOW | (ORC_PRUNE if prune else 0) | (ORC_L2 if l2 else 0),
-                        0.0)
+                        int(s_override), ORC_NO_FLOW | (ORC_PRUNE if prune else 0) | (ORC_L2 if l2 else 0)
+                        | (ORC_PAPER_GRID if paper_grid else 0), 0.0)
         if st != 0:
             raise RuntimeError(f"oracle status {st}")
         N = int(L_.orc_i64(h, _K["NCELLS"]))

@@ -716,6 +716,7 @@ enum {
   ORC_SKIP_RWMD = 16,   // take L from the caller (for timing later stages alone)
   ORC_PRUNE = 32,       // diagonal-dominance pruning of the WSPD pairs (O7')
   ORC_L2 = 64,          // Euclidean ground metric
+  ORC_PAPER_GRID = 128, // with s_override: the grid of Alg. 2 / Alg. 3 (eps_c from s)
 };
 
 void* orc_new(void) { return new Oracle(); }
@@ -737,6 +738,13 @@ int orc_run(void* p, const double* A, int64_t nA, const double* B, int64_t nB, d
   if (st) return o.status = st;
   o.eps = eps;
   o.eps_c = kappa * eps;
+  if (flags & ORC_PAPER_GRID) {
+    // the paper's own parameter choice for a given sparsity s (Alg. 2, Alg. 3):
+    // the condensation error is 8/(s - 4) for s >= 12 and 1 below that, and
+    // it sets the grid through the same bound g <= 2 eps_c L / n as above
+    if (s_override <= 0) return o.status = ORC_EINVAL;
+    o.eps_c = s_override >= 12 ? 8.0 / (double)(s_override - 4) : 1.0;
+  }
   o.s = s_override > 0 ? s_override : choose_s(eps, o.eps_c);
   if (o.n == 0) {  // identical diagrams (up to diagonal points): W1 = 0
     o.flow_cost = 0;

@@ -44,6 +44,8 @@ MUTANTS = [
     # so the mistake that matters is a start above it)
     ("s_from_a_different_stretch", CPP, "int s = (int)std::ceil(2.0 + 4.0 / tau);",
      "int s = (int)std::ceil(4.0 + 8.0 / tau);", PINS),
+    ("paper_grid_from_s_minus_2", CPP, "o.eps_c = s_override >= 12 ? 8.0 / (double)(s_override - 4) : 1.0;",
+     "o.eps_c = s_override >= 12 ? 8.0 / (double)(s_override - 2) : 1.0;", PINS),
     # O6 / O7: tree and WSPD
     ("tree_box_from_left_child", CPP, "nd.maxj = std::max(o.nodes[l].maxj, o.nodes[r].maxj);",
      "nd.maxj = o.nodes[l].maxj;", PINS),

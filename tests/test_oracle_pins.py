@@ -799,3 +799,39 @@ def test_pair_checksum_definition(orc, l2):
         h1 = (h1 + h) % 2**64
         h2 = (h2 + h * h) % 2**64
     assert cnt.checksum == full.checksum == (h1, h2)
+
+
+# ------------------------------------------------- the paper's own grid --
+def test_paper_grid_closed_forms(orc):
+    # Alg. 2 / Alg. 3 take eps_c = 8/(s - 4) for s >= 12 and 1 below.  One
+    # point (0.5, 2) against the empty diagram: L = 0.75 and n = 1, so the
+    # grid side is the largest power of two not above 1.5 eps_c (L-infinity)
+    # or 1.5 eps_c / sqrt(2) (Euclidean).  Values worked out by hand:
+    # s = 12 -> eps_c 1 -> 1.5 -> g = 1;  s = 20 -> 0.5 -> 0.75 -> 1/2;
+    # s = 53 -> 8/49 -> 0.2449 -> 1/8;  s = 5 and s = 1 -> 1 -> g = 1.
+    # Euclidean: 1.06 -> 1, 0.53 -> 1/2, 0.173 -> 1/8, 1.06 -> 1.
+    A, E = np.array([[0.5, 2.0]]), np.zeros((0, 2))
+    for s, e_inf, e_l2, ec in ((12, 0, 0, 1.0), (20, -1, -1, 0.5), (53, -3, -3, 8 / 49), (5, 0, 0, 1.0),
+                               (1, 0, 0, 1.0)):
+        r = orc.run(A, E, eps=0.1, s_override=s, flags=orc.ORC_PAPER_GRID)
+        assert r.status == 0 and r.L == 0.75 and r.s == s
+        assert r.e == e_inf and r.eps_c == ec
+        r2 = orc.run(A, E, eps=0.1, s_override=s, flags=orc.ORC_PAPER_GRID | orc.ORC_L2)
+        assert r2.status == 0 and r2.e == e_l2
+    # the flag needs a sparsity parameter
+    assert orc.run(A, E, eps=0.1, flags=orc.ORC_PAPER_GRID).status != 0
+
+
+@pytest.mark.parametrize("s", [12, 20, 5])
+def test_paper_grid_bracket(orc, s):
+    # exact W1 <= w1 <= (t + (t + 1) eps_c) exact W1 with t = (s + 2)/(s - 2),
+    # the L-infinity stretch, and the paper's eps_c for this s
+    ec = 8 / (s - 4) if s >= 12 else 1.0
+    t = (s + 2) / (s - 2)
+    for seed in range(8):
+        A = pdsynth.exp_pd(60, 1300 + 2 * seed)
+        B = pdsynth.exp_pd(55, 1301 + 2 * seed)
+        r = orc.run(A, B, eps=0.1, s_override=s, flags=orc.ORC_PAPER_GRID)
+        ex = orc.exact_w1(A, B)
+        assert r.status == 0 and r.eps_c == ec
+        assert ex * (1 - 1e-12) <= r.W1 <= (t + (t + 1) * ec) * ex * (1 + 1e-12)
