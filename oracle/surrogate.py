@@ -153,6 +153,23 @@ def dual_bound(A, B) -> float:
     return float(np.abs(dual_stats(A) - dual_stats(B)).max())
 
 
+def wcd_half(A, B, l2=False) -> float:
+    """Half the word centroid distance of the diagonal-augmented diagrams
+    (appendix, WCD): with A~ and B~ the diagonal projections of A's and B's
+    points, the classical transport distance between A u B~ and B u A~ is at
+    most 2 W1(A, B), and the distance of the two sums (total masses equal)
+    is at most that transport distance, so half of it is a lower bound.
+    Computed as written: the augmented sets, their coordinate sums, the norm
+    of the difference (L-infinity, or Euclidean with l2)."""
+    A = np.asarray(A, np.float64).reshape(-1, 2)
+    B = np.asarray(B, np.float64).reshape(-1, 2)
+    proj = lambda X: np.repeat(((X[:, 0] + X[:, 1]) * 0.5)[:, None], 2, axis=1)
+    left = np.concatenate([A, proj(B)])
+    right = np.concatenate([B, proj(A)])
+    d = left.sum(axis=0) - right.sum(axis=0)
+    return 0.5 * float(np.hypot(d[0], d[1]) if l2 else np.abs(d).max())
+
+
 def nn_exhaustive(db, queries, eps=0.1):
     """Problem NN (Sec. 6) by exhaustive search over the oracle's certified
     W1 at eps; ties go to the lowest index.  Returns (index, W1) per query."""

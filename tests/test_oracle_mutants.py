@@ -88,6 +88,11 @@ MUTANTS = [
     ("surrogate_grad_sign_of_second", SPY, "demb[pb[j]] -= g", "demb[pb[j]] += g", SURR),
     ("surrogate_backward_W2_transposed", SPY, "dh1 = dz2 @ W2", "dh1 = dz2 @ W2.T", SURR),
     ("surrogate_backward_no_relu_mask", SPY, "dz1 = dh1 * (h1 > 0.0)", "dz1 = dh1", SURR),
+    # the WCD lower bound
+    ("wcd_not_halved", SPY, "return 0.5 * float(np.hypot(d[0], d[1]) if l2 else np.abs(d).max())",
+     "return float(np.hypot(d[0], d[1]) if l2 else np.abs(d).max())", SURR),
+    ("wcd_projection_to_birth", SPY, "proj = lambda X: np.repeat(((X[:, 0] + X[:, 1]) * 0.5)[:, None], 2, axis=1)",
+     "proj = lambda X: np.repeat(X[:, :1], 2, axis=1)", SURR),
 ]
 
 

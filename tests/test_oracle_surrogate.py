@@ -163,3 +163,34 @@ def test_nn_exhaustive_self_and_ties():
     out = S.nn_exhaustive(db, [db[1], db[4]], eps=0.2)
     assert out[0] == (1, 0.0)    # itself, lowest of the two copies
     assert out[1][0] == 4 and out[1][1] == 0.0
+
+
+# ----------------------------------------------------------------- WCD --
+@pytest.mark.parametrize("l2", [False, True])
+def test_wcd_half_is_a_lower_bound(l2):
+    # half the word centroid distance of the augmented diagrams stays below
+    # the exact W1 (Hungarian), and the dual bound's c = 0 test function
+    # (the distance to the diagonal) gives twice as much
+    for seed in range(12):
+        A = pdsynth.exp_pd(40, 500 + 2 * seed, mean_pers=0.1)
+        B = pdsynth.exp_pd(30 + seed, 501 + 2 * seed, mean_pers=0.1)
+        w = S.wcd_half(A, B, l2=l2)
+        ex = oracle.exact_w1(A, B, l2=l2)
+        assert w <= ex * (1 + 1e-12)
+        if not l2:
+            assert w <= S.dual_bound(A, B) * (1 + 1e-12)
+
+
+def test_wcd_half_closed_forms():
+    # a point minus its projection is (-p/2, p/2) for persistence p, so the
+    # difference of the sums is (P_B - P_A)/2 * (1, -1) and half its norm is
+    # |P_A - P_B| / 4 (L-infinity) or |P_A - P_B| / (2 sqrt 2) (Euclidean)
+    A = np.array([[0.0, 1.0], [0.5, 0.75]])
+    B = np.array([[0.25, 0.5]])
+    PA, PB = 1.25, 0.25
+    assert S.wcd_half(A, B) == pytest.approx(abs(PA - PB) / 4)
+    assert S.wcd_half(A, B, l2=True) == pytest.approx(abs(PA - PB) / (2 * np.sqrt(2)))
+    assert S.wcd_half(A, A) == 0.0
+    # one point against nothing: W1 is its distance to the diagonal, p/2,
+    # and the bound gives half of that
+    assert S.wcd_half(A[:1], np.zeros((0, 2))) == pytest.approx(0.25)
