@@ -48,6 +48,8 @@ constexpr int SORT_STAGE = 512;  // staged heads per wave of the row sort
 constexpr int WIN_WORDS = 24576;  // largest bitmap window (96 KiB; with the staging 112 KiB of LDS)
 constexpr int SORT_MAXG = WIN_WORDS / WAVE;  // groups of 64 words in a window
 constexpr int SORT_FILL = 4;                 // head loads per thread in flight in the row sort
+constexpr int SORT_TASKS = 64;               // runs of groups per row window, taken by the waves in turn
+constexpr uint32_t SORT_GROUP_W = 32;        // weight of visiting a non-empty group, in heads
 
 // Last p in [0, K) with rstart[p] <= x (the pair holding record x: pairs
 // without records share their start with the next pair, which wins).
@@ -362,16 +364,18 @@ __device__ inline void flush_staged(const uint32_t* st, uint32_t n, int64_t k0, 
 // col / cost: the sorted row.  Per row (and per window of `win_words`
 // bitmap words over the pair's cells):
 //   1. each head sets its bit in an LDS bitmap and counts towards its group
-//      of 64 words;
-//   2. the group counts are scanned, and each wave takes a run of whole
-//      groups holding about an eighth of the heads (a row's heads crowd
-//      around its own cell, so equal runs of words would leave most of them
-//      to one wave);
-//   3. each wave reads its non-empty groups in order (clearing the words
-//      behind it, so the bitmap is zero again for the next row), expands
-//      the set bits into its LDS staging area (a group denser than the
-//      staging area goes through in slices of 8 words, one 4-bit nibble per
-//      lane), and writes the staged heads with their costs coalesced.
+//      of 64 words (the first SORT_FILL * SORT_B heads were loaded while the
+//      previous row was being written);
+//   2. the group counts are scanned, and the groups are cut into SORT_TASKS
+//      runs of about equal weight, a group weighing its heads plus
+//      SORT_GROUP_W (the fixed cost of visiting it): a row's heads crowd
+//      around its own cell, so equal runs of words would be very uneven;
+//   3. the waves take the runs in turn as they finish the previous one, read
+//      the run's non-empty groups in order (clearing the words behind them,
+//      so the bitmap is zero again for the next row), expand the set bits
+//      into their LDS staging areas (a group denser than the staging area
+//      goes through in slices of 8 words, one 4-bit nibble per lane), and
+//      write the staged heads with their costs coalesced.
 template <bool L2>
 __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict__ cpair,
                                                      const int64_t* __restrict__ cell_start,
@@ -382,12 +386,27 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
                                                      const int32_t* __restrict__ costK, uint32_t* __restrict__ col,
                                                      typename ArcCost<L2>::T* __restrict__ cost) {
   extern __shared__ uint32_t s_mem[];
-  __shared__ uint32_t s_gpre[SORT_MAXG + 1];
-  __shared__ int s_wg[SORT_WAVES + 1];
+  __shared__ uint32_t s_gpre[SORT_MAXG + 1];  // heads per group, then their exclusive prefix
+  __shared__ uint32_t s_wpre[SORT_MAXG];      // exclusive prefix of the group weights
+  __shared__ int s_task[SORT_TASKS + 1];      // first group of each run
+  __shared__ int s_next;                      // next run to take
   const int lane = lane_id(), wave = threadIdx.x / WAVE;
   uint32_t* s_bm = s_mem;
   uint32_t* s_st = s_mem + win_words + wave * SORT_STAGE;
   for (int i = threadIdx.x; i < win_words; i += SORT_B) s_bm[i] = 0;
+  // the first SORT_FILL * SORT_B heads of a row, loaded ahead (~0: none)
+  uint32_t pre[SORT_FILL];
+  auto load_ahead = [&](int64_t r) {
+#pragma unroll
+    for (int u = 0; u < SORT_FILL; ++u) pre[u] = ~0u;
+    if (r >= N) return;
+    const uint32_t n = rowcnt[r];
+    const int64_t st = (int64_t)off[r + 2 * (int64_t)cpair[r]];
+#pragma unroll
+    for (int u = 0; u < SORT_FILL; ++u)
+      if (threadIdx.x + u * SORT_B < n) pre[u] = heads[st + threadIdx.x + u * SORT_B];
+  };
+  load_ahead(blockIdx.x);
   for (int64_t g = blockIdx.x; g < N; g += gridDim.x) {
     const uint32_t p = cpair[g];
     const int64_t cs = cell_start[p];
@@ -397,6 +416,7 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
     const int2 me = cij[g];
     const int K = L2 ? costK[p] : 0;
     uint32_t written = 0;  // heads written by earlier windows (block-uniform)
+    bool ahead = true;     // pre[] still holds this row's first heads
     for (uint32_t w0 = 0; cnt > 0 && w0 < np; w0 += 32u * (uint32_t)win_words) {
       const uint32_t nbits = min(np - w0, 32u * (uint32_t)win_words);
       const int nw = (int)((nbits + 31) / 32);
@@ -405,9 +425,14 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
       __syncthreads();  // also orders the previous row's last reads before this row's bits
       for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += SORT_FILL * SORT_B) {
         uint32_t h[SORT_FILL];  // all loads in flight before the first bit is set
+        if (i0 == threadIdx.x && w0 == 0) {
 #pragma unroll
-        for (int u = 0; u < SORT_FILL; ++u)
-          h[u] = i0 + u * SORT_B < cnt ? heads[start + i0 + u * SORT_B] - w0 : ~0u;
+          for (int u = 0; u < SORT_FILL; ++u) h[u] = pre[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < SORT_FILL; ++u)
+            h[u] = i0 + u * SORT_B < cnt ? heads[start + i0 + u * SORT_B] - w0 : ~0u;
+        }
 #pragma unroll
         for (int u = 0; u < SORT_FILL; ++u)
           if (h[u] < nbits) {
@@ -416,79 +441,103 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
           }
       }
       __syncthreads();
-      if (wave == 0) {  // exclusive scan of the group counts, then the wave runs
-        uint32_t carry = 0;
+      if (ahead) {  // the next row's first heads arrive while this one is written
+        load_ahead(g + gridDim.x);
+        ahead = false;
+      }
+      if (wave == 0) {  // exclusive scans of the heads and weights per group, then the runs
+        uint32_t carry = 0, wcarry = 0;
         for (int c0 = 0; c0 < ng; c0 += WAVE) {
           const int q = c0 + lane;
+          const uint32_t v = q < ng ? s_gpre[q] : 0u;
           uint32_t t;
-          const uint32_t ex = wave_excl_prefix<12>(q < ng ? s_gpre[q] : 0u, t);
-          if (q < ng) s_gpre[q] = carry + ex;
-          carry += t;
-        }
-        if (lane == 0) s_gpre[ng] = carry;
-        if (lane <= SORT_WAVES) {  // first group whose prefix reaches lane/8 of the heads
-          const uint32_t target = (uint32_t)(((uint64_t)carry * (uint32_t)lane) / SORT_WAVES);
-          int lo = 0, hi = ng;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_gpre[mid] >= target) hi = mid;
-            else lo = mid + 1;
+          const uint32_t ex = wave_excl_prefix<12>(v, t);
+          const uint64_t ne = __ballot(v > 0);
+          const uint32_t nex = __builtin_amdgcn_mbcnt_hi((uint32_t)(ne >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ne, 0u));
+          if (q < ng) {
+            s_gpre[q] = carry + ex;
+            s_wpre[q] = wcarry + ex + SORT_GROUP_W * nex;
           }
-          s_wg[lane] = lane == SORT_WAVES ? ng : lo;
+          carry += t;
+          wcarry += t + SORT_GROUP_W * (uint32_t)__popcll(ne);
         }
+        if (lane == 0) {
+          s_gpre[ng] = carry;
+          s_task[SORT_TASKS] = ng;
+          s_next = 0;
+        }
+        // run `lane` starts at the first group whose weight prefix reaches
+        // lane / SORT_TASKS of the total
+        const uint32_t target = (uint32_t)(((uint64_t)wcarry * (uint32_t)lane) / SORT_TASKS);
+        int lo = 0, hi = ng;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (s_wpre[mid] >= target) hi = mid;
+          else lo = mid + 1;
+        }
+        s_task[lane] = lo;
       }
       __syncthreads();
-      const int qa = s_wg[wave], qb = s_wg[wave + 1];
-      int64_t k0 = start + written + s_gpre[qa];  // next arc of this wave
-      uint32_t staged = 0;                         // wave-uniform
-      for (int q = qa; q < qb; ++q) {
-        const uint32_t tot = s_gpre[q + 1] - s_gpre[q];
-        if (tot == 0) continue;
-        const int i = q * WAVE + lane;
-        const uint32_t word = i < nw ? s_bm[i] : 0u;
-        if (staged + tot > SORT_STAGE) {
-          __builtin_amdgcn_wave_barrier();
-          flush_staged<L2>(s_st, staged, k0, me, cij, cs, K, col, cost);
-          k0 += staged;
-          staged = 0;
-          __builtin_amdgcn_wave_barrier();
-        }
-        if (tot <= SORT_STAGE) {  // each lane expands its word into the staging area
-          uint32_t bits = word, pos = staged + wave_excl_prefix_small((uint32_t)__popc(word));
-          while (bits) {
-            const int bit = __ffs(bits) - 1;
-            bits &= bits - 1;
-            s_st[pos++] = w0 + (uint32_t)i * 32u + (uint32_t)bit;
+      for (;;) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(&s_next, 1);
+        t = __shfl(t, 0);
+        if (t >= SORT_TASKS) break;
+        const int qa = s_task[t], qb = s_task[t + 1];
+        if (qa >= qb) continue;
+        int64_t k0 = start + written + s_gpre[qa];  // next arc of this run
+        uint32_t staged = 0;                         // wave-uniform
+        for (int q = qa; q < qb; ++q) {
+          const uint32_t tot = s_gpre[q + 1] - s_gpre[q];
+          if (tot == 0) continue;
+          const int i = q * WAVE + lane;
+          const uint32_t word = i < nw ? s_bm[i] : 0u;
+          if (staged + tot > SORT_STAGE) {
+            __builtin_amdgcn_wave_barrier();
+            flush_staged<L2>(s_st, staged, k0, me, cij, cs, K, col, cost);
+            k0 += staged;
+            staged = 0;
+            __builtin_amdgcn_wave_barrier();
           }
-          staged += tot;
-        } else {
-          // denser than the staging area: slices of 8 words (at most 256
-          // heads), lane l expanding nibble l % 8 of word l / 8 of the slice,
-          // which is bit order
-          for (int sl = 0; sl < 8; ++sl) {
-            const uint32_t w = __shfl(word, sl * 8 + (lane >> 3));
-            const int sh = 4 * (lane & 7);
-            uint32_t nib = (w >> sh) & 0xfu, ts;
-            uint32_t pos = wave_excl_prefix<3>((uint32_t)__popc(nib), ts);
-            const uint32_t at = w0 + (uint32_t)(q * WAVE + sl * 8 + (lane >> 3)) * 32u + (uint32_t)sh;
-            while (nib) {
-              const int bit = __ffs(nib) - 1;
-              nib &= nib - 1;
-              s_st[pos++] = at + (uint32_t)bit;
+          if (tot <= SORT_STAGE) {  // each lane expands its word into the staging area
+            uint32_t bits = word, pos = staged + wave_excl_prefix_small((uint32_t)__popc(word));
+            while (bits) {
+              const int bit = __ffs(bits) - 1;
+              bits &= bits - 1;
+              s_st[pos++] = w0 + (uint32_t)i * 32u + (uint32_t)bit;
             }
-            __builtin_amdgcn_wave_barrier();
-            flush_staged<L2>(s_st, ts, k0, me, cij, cs, K, col, cost);
-            k0 += ts;
-            __builtin_amdgcn_wave_barrier();
+            staged += tot;
+          } else {
+            // denser than the staging area: slices of 8 words (at most 256
+            // heads), lane l expanding nibble l % 8 of word l / 8 of the slice,
+            // which is bit order
+            for (int sl = 0; sl < 8; ++sl) {
+              const uint32_t w = __shfl(word, sl * 8 + (lane >> 3));
+              const int sh = 4 * (lane & 7);
+              uint32_t nib = (w >> sh) & 0xfu, ts;
+              uint32_t pos = wave_excl_prefix<3>((uint32_t)__popc(nib), ts);
+              const uint32_t at = w0 + (uint32_t)(q * WAVE + sl * 8 + (lane >> 3)) * 32u + (uint32_t)sh;
+              while (nib) {
+                const int bit = __ffs(nib) - 1;
+                nib &= nib - 1;
+                s_st[pos++] = at + (uint32_t)bit;
+              }
+              __builtin_amdgcn_wave_barrier();
+              flush_staged<L2>(s_st, ts, k0, me, cij, cs, K, col, cost);
+              k0 += ts;
+              __builtin_amdgcn_wave_barrier();
+            }
           }
+          if (i < nw) s_bm[i] = 0;  // zero again for the next row
         }
-        if (i < nw) s_bm[i] = 0;  // zero again for the next row
+        __builtin_amdgcn_wave_barrier();
+        flush_staged<L2>(s_st, staged, k0, me, cij, cs, K, col, cost);
+        __builtin_amdgcn_wave_barrier();
       }
-      __builtin_amdgcn_wave_barrier();
-      flush_staged<L2>(s_st, staged, k0, me, cij, cs, K, col, cost);
       written += s_gpre[ng];
       __syncthreads();
     }
+    if (ahead) load_ahead(g + gridDim.x);  // a row without heads
     if (threadIdx.x == 0 && ca[g] > 0) {  // arc to the A-diagonal node, last in the row
       col[start + cnt] = np;
       cost[start + cnt] = ArcCost<L2>::diag(me, K);
@@ -625,7 +674,7 @@ void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const
   const size_t lds = (size_t)win * 4 + (size_t)SORT_WAVES * SORT_STAGE * 4;
   // persistent: two blocks per compute unit when their LDS fits (a bitmap
   // of up to 50 KiB, i.e. pairs of up to 400k cells), else one
-  const int64_t grid = std::min<int64_t>(N, (int64_t)num_cus * (lds <= 80 * 1024 ? 2 : 1));
+  const int64_t grid = std::min<int64_t>(N, (int64_t)num_cus * (lds <= 76 * 1024 ? 2 : 1));
   if (costK)
     hipLaunchKernelGGL(k_row_sort<true>, dim3((unsigned)grid), dim3(SORT_B), lds, st, cpair, cell_start, ncells, cij, ca,
                        rowcnt, off, heads, N, win, costK, col, (int64_t*)cost);
