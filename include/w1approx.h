@@ -110,6 +110,12 @@ extern "C" {
 #define W1_METRIC_L2 64u   /* Euclidean ground metric, the paper's own      */
                            /* (Sec. 4.2), instead of L-infinity: see the    */
                            /* Euclidean notes at the top of this file       */
+#define W1_PAPER_GRID 128u /* with s_override > 0: the paper's own grid for */
+                           /* that s (Alg. 2, Alg. 3): eps_c = 8/(s - 4) for */
+                           /* s >= 12 and 1 below, in place of kappa * eps  */
+                           /* (eps and kappa are then unused); the grid    */
+                           /* bound g <= 2 eps_c L / n is unchanged.        */
+                           /* Without s_override W1_EINVAL                  */
 
 typedef struct w1_ctx w1_ctx;
 
@@ -316,6 +322,20 @@ typedef struct {
                               /* pair_checksum, and kernel time [4] the     */
                               /* emit time.  A chunk larger than the arena  */
                               /* gives W1_EOVERFLOW.  0 = off               */
+  int32_t blocked_emit;       /* network of a single pair with at least   */
+                              /* 4096 work-list chunks: 1 emits the pair   */
+                              /* records into blocks that the waves take  */
+                              /* as they fill them, sized by a count over  */
+                              /* every 16th chunk, instead of counting     */
+                              /* every chunk first; 0 (default) = always   */
+                              /* count first.  The network is the same.    */
+                              /* Experimental: not yet validated on the    */
+                              /* GPU                                       */
+  int32_t reserved;           /* must be 0                                 */
+  int64_t emit_block_limit;   /* blocked emission: at most this many blocks */
+                              /* of 4096 records (0 = as sized); when they */
+                              /* run out the pass is redone with every     */
+                              /* chunk counted first (same result)         */
 } w1_tuning;
 
 int w1_ctx_get_tuning(const w1_ctx *ctx, w1_tuning *out);
@@ -323,13 +343,15 @@ int w1_ctx_set_tuning(w1_ctx *ctx, const w1_tuning *t);
 
 /* Device times (ms, HIP events on the call's stream) of the last call's
  * WSPD and network kernels: [0] work-list build (expansion rounds, item
- * sort, chunking), [1] count pass, [2] emit pass (which also takes the
- * network's bucket histogram), [3] the number of pairs emitted; [4] the
- * streamed emission's emit passes, all arena fills together (0 unless
- * streaming); then the passes that sort the network into rows: [5] bucket
- * scatter, [6] row histogram, [7] row scatter (with the degree scan before
- * it), [8] row sort (with the diagonal rows and row pointers).  n is the
- * capacity of ms (>= 4); entries beyond 8 are 0. */
+ * sort, chunking), [1] count pass (with blocked emission: the count over
+ * every 16th chunk), [2] emit pass (which also takes the network's bucket
+ * histogram), [3] the number of pairs emitted; [4] the streamed emission's
+ * emit passes, all arena fills together (0 unless streaming); then the
+ * passes that sort the network into rows: [5] bucket scatter, [6] row
+ * histogram, [7] row scatter (with the degree scan before it), [8] row sort
+ * (with the diagonal rows and row pointers); [9] the blocks the blocked
+ * emission filled (0: counted layout).  n is the capacity of ms (>= 4);
+ * entries beyond 9 are 0. */
 int w1_ctx_last_kernel_times(const w1_ctx *ctx, double *ms, int n);
 
 /* Host network simplex on any uncapacitated network with non-negative integer
@@ -445,17 +467,37 @@ typedef struct w1_nn_index w1_nn_index;
  *                     and a margin of 1e-8 (sum_A f_c + sum_B f_c) covers
  *                     their rounding.
  *   W1_NN_EXHAUSTIVE  verify every database diagram.
+ *   W1_NN_SPARSE      the cheap sparse stage of the paper's 1-NN pipelines
+ *                     (Sec. 7), kept exact: the RWMD bound of every pair; the
+ *                     method at s = 1 on the paper's own grid for s = 1
+ *                     (w1_approx with s_override = 1 and W1_PAPER_GRID) for
+ *                     the `keep` candidates of smallest RWMD; the seed_k of
+ *                     those with the smallest s = 1 value (an upper bound on
+ *                     W1, ties to the earlier in RWMD order) are verified
+ *                     first; then as W1_NN_RWMD.  Same answers as above.
+ *   W1_NN_PIPELINE    the paper's keep-seed_k-1 pipeline (Sec. 7, with RWMD
+ *                     in place of its first stage), NOT exact: the candidates
+ *                     left after both cuts of W1_NN_SPARSE are verified and
+ *                     the best of them is returned.  It is the nearest
+ *                     neighbour only when that survives both cuts (what the
+ *                     paper measures as accuracy).
  * Verifications run w1_approx with W1_PRUNE (the same w1, a smaller flow). */
 #define W1_NN_RWMD 0
 #define W1_NN_SURROGATE 1
 #define W1_NN_EXHAUSTIVE 2
+#define W1_NN_SPARSE 3
+#define W1_NN_PIPELINE 4
 #define W1_NN_NSTATS 33 /* test functions of the dual bound */
 
 typedef struct {
-  double eps;     /* eps of the method that verifies candidates                 */
-  int32_t mode;   /* W1_NN_*                                                    */
-  int32_t seed_k; /* W1_NN_SURROGATE: candidates verified first, in surrogate  */
-                  /* order (0 selects 1)                                        */
+  double eps;       /* eps of the method that verifies candidates               */
+  int32_t mode;     /* W1_NN_*                                                  */
+  int32_t seed_k;   /* W1_NN_SURROGATE / W1_NN_SPARSE: candidates verified     */
+                    /* first (0 selects 1); W1_NN_PIPELINE: candidates kept    */
+                    /* after the s = 1 stage (0 selects 3)                     */
+  int32_t keep;     /* W1_NN_SPARSE / W1_NN_PIPELINE: candidates kept after    */
+                    /* RWMD for the s = 1 stage (0 selects 15)                 */
+  int32_t reserved; /* must be 0                                               */
 } w1_nn_params;
 
 typedef struct {
@@ -466,6 +508,8 @@ typedef struct {
   double t_embed_ms;     /* query embedding, surrogate distances, dual bounds  */
   double t_verify_ms;    /* full-method verifications (GPU + host flow)         */
   double t_total_ms;
+  int64_t sparse_evals;  /* s = 1 evaluations (W1_NN_SPARSE, W1_NN_PIPELINE)    */
+  double t_sparse_ms;    /* s = 1 evaluations (GPU + host flow)                 */
 } w1_nn_stats;
 
 /* Index over m database diagrams: a device copy of their points and, when s

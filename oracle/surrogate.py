@@ -170,6 +170,43 @@ def wcd_half(A, B, l2=False) -> float:
     return 0.5 * float(np.hypot(d[0], d[1]) if l2 else np.abs(d).max())
 
 
+def nn_pipeline(db, queries, eps=0.1, keep=15, c2=3):
+    """The keep-c2-1 pipeline of the 1-NN experiments (Sec. 7), with RWMD as
+    its first stage: the keep candidates of smallest RWMD (ties to the lower
+    index), of those the c2 of smallest method value at s = 1 on the paper's
+    grid for s = 1 (ties to the earlier in RWMD order), and the best certified
+    W1 at eps among them (ties to the lower index).  Returns (index, W1) per
+    query.  Not exact: the nearest neighbour may be cut."""
+    from . import ORC_PAPER_GRID, ORC_STOP_AFTER_TREE, run
+
+    out = []
+    for q in queries:
+        L = []
+        for D in db:
+            r = run(q, D, eps=eps, flags=ORC_STOP_AFTER_TREE, fetch=False)
+            if r.status != 0:
+                raise RuntimeError(f"oracle status {r.status}")
+            L.append(r.L)
+        order = sorted(range(len(db)), key=lambda i: (L[i], i))[:keep]
+        s1 = {}
+        for i in order:
+            r = run(q, db[i], eps=eps, s_override=1, flags=ORC_PAPER_GRID, fetch=False)
+            if r.status != 0:
+                raise RuntimeError(f"oracle status {r.status}")
+            s1[i] = r.W1
+        pos = {i: k for k, i in enumerate(order)}
+        cand = sorted(order, key=lambda i: (s1[i], pos[i]))[:c2]
+        best, bi = np.inf, -1
+        for i in sorted(cand):
+            r = run(q, db[i], eps=eps, fetch=False)
+            if r.status != 0:
+                raise RuntimeError(f"oracle status {r.status}")
+            if r.W1 < best:
+                best, bi = r.W1, i
+        out.append((bi, best))
+    return out
+
+
 def nn_exhaustive(db, queries, eps=0.1):
     """Problem NN (Sec. 6) by exhaustive search over the oracle's certified
     W1 at eps; ties go to the lowest index.  Returns (index, W1) per query."""

@@ -23,6 +23,7 @@ W1_OK, W1_EINVAL, W1_ERANGE, W1_ENOMEM, W1_EHIP, W1_EOVERFLOW, W1_ENODEV = 0, -1
 W1_OPTIMAL, W1_STALLED = 0, 1
 W1_F32, W1_F64 = 0, 1
 INPUT_DEVICE, COUNT_ONLY, NO_FLOW, KEEP_NETWORK, KEEP_STAGES, PRUNE, METRIC_L2 = 1, 2, 4, 8, 16, 32, 64
+PAPER_GRID = 128
 T_NAMES = ("condense0", "rwmd", "grid", "tree", "wspd", "arcs", "d2h", "flow")
 
 
@@ -80,23 +81,26 @@ class _Tuning(ctypes.Structure):
     _fields_ = [("stack_depth", ctypes.c_int32), ("work_cap", ctypes.c_int32), ("chunk_items", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("max_points_per_launch", ctypes.c_int64),
                 ("compact_records", ctypes.c_int32), ("stream_max_rounds", ctypes.c_int32),
-                ("stream_arena_pairs", ctypes.c_int64)]
+                ("stream_arena_pairs", ctypes.c_int64), ("blocked_emit", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("emit_block_limit", ctypes.c_int64)]
 
 
 class _NNParams(ctypes.Structure):
-    _fields_ = [("eps", ctypes.c_double), ("mode", ctypes.c_int32), ("seed_k", ctypes.c_int32)]
+    _fields_ = [("eps", ctypes.c_double), ("mode", ctypes.c_int32), ("seed_k", ctypes.c_int32),
+                ("keep", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _NNStats(ctypes.Structure):
     _fields_ = [("verifications", ctypes.c_int64), ("rwmd_evals", ctypes.c_int64), ("rounds", ctypes.c_int64),
                 ("t_rwmd_ms", ctypes.c_double), ("t_embed_ms", ctypes.c_double), ("t_verify_ms", ctypes.c_double),
-                ("t_total_ms", ctypes.c_double)]
+                ("t_total_ms", ctypes.c_double), ("sparse_evals", ctypes.c_int64), ("t_sparse_ms", ctypes.c_double)]
 
 
 SURR_NPARAM = 25152
 SURR_EMB = 64
-NN_RWMD, NN_SURROGATE, NN_EXHAUSTIVE = 0, 1, 2
-NN_MODES = {"rwmd": NN_RWMD, "surrogate": NN_SURROGATE, "exhaustive": NN_EXHAUSTIVE}
+NN_RWMD, NN_SURROGATE, NN_EXHAUSTIVE, NN_SPARSE, NN_PIPELINE = 0, 1, 2, 3, 4
+NN_MODES = {"rwmd": NN_RWMD, "surrogate": NN_SURROGATE, "exhaustive": NN_EXHAUSTIVE, "sparse": NN_SPARSE,
+            "pipeline": NN_PIPELINE}
 
 # Every symbol include/w1approx.h declares.
 EXPORTS = ("w1_ctx_create", "w1_ctx_destroy", "w1_ctx_hip_error", "w1_ctx_last_kernel_times", "w1_approx",
@@ -410,7 +414,7 @@ class Context:
             raise W1Error(rc, "w1_ctx_set_tuning")
 
     KERNEL_TIMES = ("worklist_ms", "count_ms", "emit_ms", "pairs", "stream_emit_ms", "bucket_scatter_ms",
-                    "row_hist_ms", "row_scatter_ms", "row_sort_ms")
+                    "row_hist_ms", "row_scatter_ms", "row_sort_ms", "emit_blocks")
 
     def kernel_times(self) -> dict:
         """HIP-event times (ms) of the last call's WSPD and network kernels."""
@@ -421,6 +425,7 @@ class Context:
             raise W1Error(rc, "w1_ctx_last_kernel_times")
         d = {k: out[i] for i, k in enumerate(self.KERNEL_TIMES)}
         d["pairs"] = int(d["pairs"])
+        d["emit_blocks"] = int(d["emit_blocks"])
         return d
 
     def device_network(self, k: int = 0) -> dict:
@@ -569,15 +574,18 @@ class NNIndex:
         except Exception:
             pass
 
-    def query(self, qs, eps=0.1, mode="surrogate", seed_k=1) -> NNResult:
-        keep = []
-        arr, dev = _pd_list(qs, keep)
+    def query(self, qs, eps=0.1, mode="surrogate", seed_k=0, keep=0) -> NNResult:
+        """keep / seed_k: the candidates kept after RWMD and after the s = 1
+        stage (modes "sparse" and "pipeline"); seed_k also sets the
+        surrogate's seeds.  0 selects the library's defaults."""
+        hold = []
+        arr, dev = _pd_list(qs, hold)
         nq = len(qs)
         nn = np.zeros(nq, np.int64)
         w = np.zeros(nq, np.float64)
         ver = np.zeros(nq, np.int64)
         st = _NNStats()
-        prm = _NNParams(float(eps), NN_MODES[mode], int(seed_k))
+        prm = _NNParams(float(eps), NN_MODES[mode], int(seed_k), int(keep), 0)
         sur = self.surrogate._h if (self.surrogate is not None and mode == "surrogate") else None
         rc = lib().w1_nn_query(self.ctx._h, self._h, sur, arr, nq, ctypes.byref(prm), INPUT_DEVICE if dev else 0,
                                _stream_of(dev), nn.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),

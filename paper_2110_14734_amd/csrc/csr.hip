@@ -50,6 +50,7 @@ constexpr int SORT_MAXG = WIN_WORDS / WAVE;  // groups of 64 words in a window
 constexpr int SORT_FILL = 4;                 // head loads per thread in flight in the row sort
 constexpr int SORT_TASKS = 64;               // runs of groups per row window, taken by the waves in turn
 constexpr uint32_t SORT_GROUP_W = 32;        // weight of visiting a non-empty group, in heads
+constexpr int SORT_DENSE_BATCH = 8;          // cell-coordinate loads in flight per lane, dense groups
 
 // Last p in [0, K) with rstart[p] <= x (the pair holding record x: pairs
 // without records share their start with the next pair, which wins).
@@ -117,10 +118,11 @@ __device__ inline void lds_excl_scan(uint32_t* cnt, int n, uint32_t* s_tmp) {
 }
 
 // ------------------------------------------------------ arcs of a record --
-// Arcs of pair records [x0, x1): tail cell (global) and entry.
-__device__ inline void record_arcs(const uint32_t* __restrict__ rec, uint64_t x, int64_t cs, int RB, int DB,
-                                   uint32_t& b0, uint32_t& e0, uint32_t& b1, uint32_t& e1) {
-  const uint32_t u = rec[3 * x], v = rec[3 * x + 1];
+// Arcs of pair record x (rw words per record, u and v first): tail cell
+// (global) and entry.
+__device__ inline void record_arcs(const uint32_t* __restrict__ rec, uint64_t x, uint32_t rw, int64_t cs, int RB,
+                                   int DB, uint32_t& b0, uint32_t& e0, uint32_t& b1, uint32_t& e1) {
+  const uint32_t u = rec[rw * x], v = rec[rw * x + 1];
   const uint64_t gu = (uint64_t)cs + u, gv = (uint64_t)cs + v;
   const uint32_t m = (1u << RB) - 1u;
   b0 = (uint32_t)(gu >> RB);
@@ -135,16 +137,23 @@ __global__ void __launch_bounds__(CB) k_bucket_scatter(const uint32_t* __restric
                                                        const int64_t* __restrict__ cell_start, int RB, int DB, int NB,
                                                        const uint64_t* __restrict__ bstart,
                                                        unsigned long long* __restrict__ bcur,
-                                                       uint32_t* __restrict__ out) {
+                                                       uint32_t* __restrict__ out,
+                                                       const uint32_t* __restrict__ blk_fill,
+                                                       const uint32_t* __restrict__ blk_pair, uint32_t blk_recs) {
   extern __shared__ uint32_t s_mem[];
   uint32_t* s_cnt = s_mem;                         // NB: counts, then prefixes
   int64_t* s_gofs = (int64_t*)(s_mem + ((NB + 1) & ~1));  // NB: global base - prefix
   uint32_t* s_ent = (uint32_t*)(s_gofs + NB);      // 2 PTILE staged entries
   uint16_t* s_bkt = (uint16_t*)(s_ent + 2 * PTILE);  // 2 PTILE bucket ids
   __shared__ uint32_t s_tmp[CB / WAVE];
-  const uint64_t x0 = (uint64_t)blockIdx.x * PTILE, x1 = min(P, x0 + PTILE);
+  // a tile: PTILE consecutive records (u, v, cost), or one block of the
+  // blocked emission (records (u, v); its fill and diagram pair given)
+  const uint64_t x0 = (uint64_t)blockIdx.x * (blk_fill ? blk_recs : (uint32_t)PTILE);
+  const uint64_t x1 = blk_fill ? x0 + blk_fill[blockIdx.x] : min(P, x0 + PTILE);
   for (int b = threadIdx.x; b < NB; b += CB) s_cnt[b] = 0;
-  const TilePairs tp = tile_pairs(rstart, K, x0, x1);
+  __syncthreads();  // every counter is zero before any thread counts
+  const TilePairs tp = blk_fill ? TilePairs{(int64_t)blk_pair[blockIdx.x], (int64_t)blk_pair[blockIdx.x]}
+                                : tile_pairs(rstart, K, x0, x1);
   uint32_t eb[2 * PPT], ee[2 * PPT], er[2 * PPT];
   int n = 0;
 #pragma unroll
@@ -152,7 +161,7 @@ __global__ void __launch_bounds__(CB) k_bucket_scatter(const uint32_t* __restric
     const uint64_t x = x0 + (uint64_t)k * CB + threadIdx.x;
     if (x < x1) {
       const int64_t cs = cell_start[record_pair(tp, rstart, x)];
-      record_arcs(rec, x, cs, RB, DB, eb[2 * k], ee[2 * k], eb[2 * k + 1], ee[2 * k + 1]);
+      record_arcs(rec, x, blk_fill ? 2u : 3u, cs, RB, DB, eb[2 * k], ee[2 * k], eb[2 * k + 1], ee[2 * k + 1]);
       er[2 * k] = atomicAdd(&s_cnt[eb[2 * k]], 1u);
       er[2 * k + 1] = atomicAdd(&s_cnt[eb[2 * k + 1]], 1u);
       n = 2 * k + 2;
@@ -373,9 +382,9 @@ __device__ inline void flush_staged(const uint32_t* st, uint32_t n, int64_t k0, 
 //   3. the waves take the runs in turn as they finish the previous one, read
 //      the run's non-empty groups in order (clearing the words behind them,
 //      so the bitmap is zero again for the next row), expand the set bits
-//      into their LDS staging areas (a group denser than the staging area
-//      goes through in slices of 8 words, one 4-bit nibble per lane), and
-//      write the staged heads with their costs coalesced.
+//      into their LDS staging areas and write the staged heads with their
+//      costs coalesced; a group denser than the staging area is written
+//      straight from its words, 64 consecutive cells per step.
 template <bool L2>
 __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict__ cpair,
                                                      const int64_t* __restrict__ cell_start,
@@ -508,25 +517,34 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
             }
             staged += tot;
           } else {
-            // denser than the staging area: slices of 8 words (at most 256
-            // heads), lane l expanding nibble l % 8 of word l / 8 of the slice,
-            // which is bit order
-            for (int sl = 0; sl < 8; ++sl) {
-              const uint32_t w = __shfl(word, sl * 8 + (lane >> 3));
-              const int sh = 4 * (lane & 7);
-              uint32_t nib = (w >> sh) & 0xfu, ts;
-              uint32_t pos = wave_excl_prefix<3>((uint32_t)__popc(nib), ts);
-              const uint32_t at = w0 + (uint32_t)(q * WAVE + sl * 8 + (lane >> 3)) * 32u + (uint32_t)sh;
-              while (nib) {
-                const int bit = __ffs(nib) - 1;
-                nib &= nib - 1;
-                s_st[pos++] = at + (uint32_t)bit;
+            // denser than the staging area: written straight from the words,
+            // 64 consecutive cells per step (lane l takes cell 64 t + l of
+            // the group): a set bit goes to the run's cursor plus the set
+            // bits before it, and the cells' coordinates come in coalesced
+            uint32_t wt;
+            const uint32_t wpre = wave_excl_prefix<6>((uint32_t)__popc(word), wt);
+            const uint32_t c0 = w0 + (uint32_t)q * (uint32_t)(WAVE * 32);
+            const uint32_t bit = (uint32_t)lane & 31u;
+            for (int t0 = 0; t0 < 32; t0 += SORT_DENSE_BATCH) {
+              int2 o[SORT_DENSE_BATCH];
+#pragma unroll
+              for (int u = 0; u < SORT_DENSE_BATCH; ++u) {
+                const uint32_t cell = c0 + (uint32_t)(t0 + u) * WAVE + (uint32_t)lane;
+                o[u] = cell < np ? cij[cs + cell] : make_int2(0, 0);
               }
-              __builtin_amdgcn_wave_barrier();
-              flush_staged<L2>(s_st, ts, k0, me, cij, cs, K, col, cost);
-              k0 += ts;
-              __builtin_amdgcn_wave_barrier();
+#pragma unroll
+              for (int u = 0; u < SORT_DENSE_BATCH; ++u) {
+                const int wi = 2 * (t0 + u) + (lane >> 5);  // the word holding this lane's cell
+                const uint32_t wv = (uint32_t)__shfl((int)word, wi);
+                const uint32_t wp = (uint32_t)__shfl((int)wpre, wi);
+                if ((wv >> bit) & 1u) {
+                  const int64_t k = k0 + wp + (uint32_t)__popc(wv & ((1u << bit) - 1u));
+                  col[k] = c0 + (uint32_t)(t0 + u) * WAVE + (uint32_t)lane;
+                  cost[k] = ArcCost<L2>::cell(me, o[u], K);
+                }
+              }
             }
+            k0 += tot;
           }
           if (i < nw) s_bm[i] = 0;  // zero again for the next row
         }
@@ -641,13 +659,18 @@ size_t csr_row_scatter_lds(int RB) {
 }
 int64_t csr_entry_tile(int RB) { return (int64_t)CB * csr_entries_per_thread(RB); }
 
+int csr_tile_records() { return PTILE; }
 void launch_csr_bucket_scatter(const uint32_t* rec, uint64_t P, const uint64_t* rstart, int64_t K,
                                const int64_t* cell_start, int RB, int DB, int NB, const uint64_t* bstart,
-                               uint64_t* bcur, uint32_t* out, hipStream_t st) {
+                               uint64_t* bcur, uint32_t* out, const uint32_t* blk_fill, const uint32_t* blk_pair,
+                               uint32_t blk_recs, uint32_t nblocks, hipStream_t st) {
   if (P == 0) return;
-  hipLaunchKernelGGL(k_bucket_scatter, dim3((unsigned)ceil_div((int64_t)P, PTILE)), dim3(CB),
-                     csr_bucket_scatter_lds(NB), st, rec, P, rstart, K, cell_start, RB, DB, NB, bstart,
-                     (unsigned long long*)bcur, out);
+  // blocked records: one tile per block, whose records must fit a tile
+  if (blk_fill && (blk_recs == 0 || blk_recs > (uint32_t)PTILE || nblocks == 0)) return;
+  const int64_t tiles = blk_fill ? (int64_t)nblocks : ceil_div((int64_t)P, PTILE);
+  hipLaunchKernelGGL(k_bucket_scatter, dim3((unsigned)tiles), dim3(CB), csr_bucket_scatter_lds(NB), st, rec, P,
+                     rstart, K, cell_start, RB, DB, NB, bstart, (unsigned long long*)bcur, out, blk_fill, blk_pair,
+                     blk_recs);
 }
 void launch_csr_row_hist(const uint32_t* ent, const int64_t* tfirst, int64_t ntiles, int NB, const uint64_t* bstart,
                          int RB, int DB, int64_t N, uint32_t* rowcnt, hipStream_t st) {

@@ -39,7 +39,12 @@ constexpr int64_t kNoAllocMaxPairs = 1024;
 // w1_ctx_last_kernel_times: work list, count pass, emit pass, pairs emitted,
 // then the network passes: bucket histogram, bucket scatter, row histogram,
 // row scatter (with the degree scan), row sort (with the diagonal rows).
-constexpr int kNumKernelTimes = 9;
+constexpr int kNumKernelTimes = 10;
+
+// Blocked emission of a single pair's network: used from this many
+// work-list chunks on, sized by a count over every kSampleStride-th chunk.
+constexpr int64_t kBlockedMinChunks = 4096;
+constexpr int kSampleStride = 16;
 
 struct Ctx {
   int device = 0;
@@ -52,6 +57,8 @@ struct Ctx {
   int64_t max_points = int64_t(1) << 22;  // points per launch group of a batch
   int64_t stream_arena = 0;                // streamed emission: arena capacity in pair records (0 = off)
   int32_t stream_rounds = 0;               // streamed emission: arena fills at most (0 = all)
+  int32_t blocked_emit = 0;                // network path: blocked emission (off by default)
+  int64_t emit_block_limit = 0;            // blocked emission: block cap (0 = as sized)
   int64_t K_base = 0;                      // first pair of the last launch group
   std::vector<DBuf*> all;
   // points
@@ -70,6 +77,10 @@ struct Ctx {
   DBuf pu, l1, costb, rp, supply, rstart, bcnt, bstart, tfirst, bcur, rowcnt, rowcur, bflag, bpos, deg, off, parc;
   // streamed emission: per-chunk pair checksums; Euclidean cost scale
   DBuf csum, pxmax;
+  // blocked emission (network path): block fills, block pairs, counters;
+  // blocks used by the last launch group (0: counted layout) and their size
+  DBuf bfill, bpairs, bctl;
+  uint32_t emit_blocks = 0, emit_block_recs = 0;
   // per pair
   DBuf pairs;
   PairArrays P{};

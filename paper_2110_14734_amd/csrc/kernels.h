@@ -78,9 +78,14 @@ void launch_level_boxes(const int2* cij, int64_t N, const int4* iaux, const int3
 size_t csr_bucket_scatter_lds(int NB);
 size_t csr_row_scatter_lds(int RB);
 int64_t csr_entry_tile(int RB);  // entries per tile of the row passes
+// Records per tile of the bucket scatter: a block of the blocked emission
+// holds at most this many.
+int csr_tile_records();
 void launch_csr_bucket_scatter(const uint32_t* rec, uint64_t P, const uint64_t* rstart, int64_t K,
                                const int64_t* cell_start, int RB, int DB, int NB, const uint64_t* bstart,
-                               uint64_t* bcur, uint32_t* out, hipStream_t st);
+                               uint64_t* bcur, uint32_t* out,
+                               const uint32_t* blk_fill, const uint32_t* blk_pair, uint32_t blk_recs,
+                               uint32_t nblocks, hipStream_t st);
 void launch_csr_row_hist(const uint32_t* ent, const int64_t* tfirst, int64_t ntiles, int NB, const uint64_t* bstart,
                          int RB, int DB, int64_t N, uint32_t* rowcnt, hipStream_t st);
 void launch_csr_bflags(const int32_t* cb, int64_t N, uint32_t* flag, hipStream_t st);
@@ -141,6 +146,26 @@ struct StreamOut {
   uint64_t* chunk_sum = nullptr;
 };
 
+// Emit pass output in blocks, for the network path (no count pass; the
+// records carry no cost, which the network takes from the cells): each
+// wave takes blocks of `block` records from a global counter as it fills
+// them, and a block holds the records of one diagram pair.  When a block is
+// full or the wave moves to another pair, fill[b] and pair[b] describe it and
+// its records are added to pair_count[pair].  A wave that finds no block left
+// sets *overflow and writes no more records (the caller then falls back to
+// the counted layout).
+struct BlockOut {
+  uint32_t* base = nullptr;  // max_blocks * block records of (u, v), 8 bytes each
+  uint32_t block = 0;        // records per block (2 * WAVE <= block)
+  uint32_t max_blocks = 0;
+  uint32_t* nblocks = nullptr;
+  uint32_t* fill = nullptr;
+  uint32_t* pair = nullptr;
+  unsigned long long* pair_count = nullptr;
+  int32_t* overflow = nullptr;
+  const int32_t* chunk_pair = nullptr;
+};
+
 struct WspdTuning {
   int stack_depth;  // per-lane DFS stack entries (LDS), items need height sum < this
   int work_cap;     // items need |U| * |V| <= cap to skip the expansion rounds; this is the
@@ -182,6 +207,7 @@ void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, con
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
                       uint32_t* out, int32_t* err, bool prune, bool l2, const BucketHist& bh, const StreamOut& so,
+                      const BlockOut& bo, int chunk_stride,
                       int num_cus, hipStream_t st);
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,

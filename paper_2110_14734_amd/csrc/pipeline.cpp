@@ -187,7 +187,13 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
   const bool prune = (o.flags & W1_PRUNE) != 0;
   const bool l2 = (o.flags & W1_METRIC_L2) != 0;
   if (l2 && prune) return W1_EINVAL;  // pruning is exact for the integer L-infinity costs only
-  const double eps_c = o.kappa * o.eps;
+  // condensation share of the error: kappa * eps, or the paper's own choice
+  // for a given sparsity parameter (Alg. 2, Alg. 3)
+  double eps_c = o.kappa * o.eps;
+  if (o.flags & W1_PAPER_GRID) {
+    if (o.s <= 0) return W1_EINVAL;
+    eps_c = o.s >= 12 ? 8.0 / (double)(o.s - 4) : 1.0;
+  }
   for (int i = 0; i < 8; ++i) record(c, i);
   record(c, 0);
 
@@ -411,6 +417,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
 
   // ---------------------------------------------------------------- a4 --
   int64_t Ptot = 0;
+  c.emit_blocks = 0;  // set by the blocked emission when it runs
   double stream_ms = 0;                 // streamed emission (count-only calls)
   std::vector<int64_t> stream_n;        // per pair: pairs streamed
   std::vector<uint64_t> stream_chk;     // per pair: checksum of the streamed records
@@ -509,10 +516,83 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       uint32_t* xc = need<uint32_t>(c, c.xctr, 16);
       uint64_t* ccnt = need<uint64_t>(c, c.ccnt, nch);
       uint64_t* coff = need<uint64_t>(c, c.coff, nch);
+      // The network path of a single large pair emits without the count
+      // pass: a count over every kSampleStride-th chunk sizes an arena of
+      // blocks that the waves fill as they go (the rows are sorted later,
+      // so where a record lands does not matter).  If the blocks run out,
+      // the counted layout below runs instead.
+      bool blocked = false;
+      uint32_t nblk = 0;
+      const uint32_t brecs = (uint32_t)csr_tile_records();
+      if (!(o.flags & W1_COUNT_ONLY) && K == 1 && nch >= kBlockedMinChunks && c.blocked_emit) {
+        fill_u64(ccnt, 0, nch, st);
+        fill_u32(xc, 0, 8, st);
+        check(c, hipEventRecord(c.kev[1], st));
+        launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr, prune, l2,
+                         BucketHist{}, StreamOut{}, BlockOut{}, kSampleStride, c.num_cus, st);
+        check(c, hipGetLastError());
+        check(c, hipEventRecord(c.kev[2], st));
+        scan_u64(ccnt, coff, nch, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(nch, 8)), st);
+        uint64_t* slot = need<uint64_t>(c, c.small, 64);
+        launch_count_total64(ccnt, coff, nch, slot, st);
+        const double est = (double)read_u64(c, slot) * kSampleStride;
+        const int64_t waves = (int64_t)c.num_cus * tun.blocks_per_cu * 4;
+        int64_t cap = (int64_t)std::ceil(est * 1.2 / brecs) + waves + 64;
+        if (c.emit_block_limit > 0) cap = std::min(cap, c.emit_block_limit);
+        trace(c, "blocked emission: estimated pairs", (int64_t)est);
+        if (cap < (int64_t(1) << 31) / 2) {
+          const CsrGeometry geo = csr_geometry(N, maxnp);
+          if (!geo.ok) throw StageError{W1_ERANGE};
+          uint32_t* pout = need<uint32_t>(c, c.pu, 2 * cap * (int64_t)brecs);
+          uint32_t* bf = need<uint32_t>(c, c.bfill, cap);
+          uint32_t* bp = need<uint32_t>(c, c.bpairs, cap);
+          uint32_t* ctl = need<uint32_t>(c, c.bctl, 64);
+          fill_u32(ctl, 0, 2, st);  // [0] blocks taken, [1] overflow
+          fill_u64(P.npairs, 0, K, st);
+          uint64_t* bcnt = need<uint64_t>(c, c.bcnt, geo.NB);
+          fill_u64(bcnt, 0, geo.NB, st);
+          BucketHist bh;
+          bh.chunk_pair = cp;
+          bh.cell_start = P.cell_start;
+          bh.RB = geo.RB;
+          bh.NB = (int)geo.NB;
+          bh.count = bcnt;
+          BlockOut bo;
+          bo.base = pout;
+          bo.block = brecs;
+          bo.max_blocks = (uint32_t)cap;
+          bo.nblocks = ctl;
+          bo.fill = bf;
+          bo.pair = bp;
+          bo.pair_count = (unsigned long long*)P.npairs;
+          bo.overflow = (int32_t*)(ctl + 1);
+          bo.chunk_pair = cp;
+          fill_u32(xc, 0, 8, st);
+          check(c, hipEventRecord(c.kev[3], st));
+          launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr, prune, l2,
+                           bh, StreamOut{}, bo, 1, c.num_cus, st);
+          check(c, hipGetLastError());
+          uint32_t hctl[2];
+          readback(c, ctl, hctl, 2);
+          if (hctl[1] == 0 && hctl[0] <= (uint32_t)cap) {
+            blocked = true;
+            emitted = true;
+            nblk = hctl[0];
+            uint64_t np0 = 0;
+            readback(c, P.npairs, &np0, 1);
+            Ptot = (int64_t)np0;
+            trace(c, "wspd pairs", Ptot);
+            trace(c, "blocked emission: blocks", (int64_t)nblk);
+          }
+        }
+      }
+      c.emit_blocks = blocked ? nblk : 0;
+      c.emit_block_recs = brecs;
+      if (!blocked) {
       fill_u32(xc, 0, 8, st);
       check(c, hipEventRecord(c.kev[1], st));
       launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr, prune, l2,
-                       BucketHist{}, StreamOut{}, c.num_cus, st);
+                       BucketHist{}, StreamOut{}, BlockOut{}, 1, c.num_cus, st);
       check(c, hipGetLastError());
       check(c, hipEventRecord(c.kev[2], st));
       scan_u64(ccnt, coff, nch, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(nch, 8)), st);
@@ -543,7 +623,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
           fill_u32(xc, 0, 8, st);
           check(c, hipEventRecord(c.kev[3], st));
           launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, arena, derr, prune, l2,
-                           BucketHist{}, StreamOut{(int64_t)hoff[(size_t)c0], csum}, c.num_cus, st);
+                           BucketHist{}, StreamOut{(int64_t)hoff[(size_t)c0], csum}, BlockOut{}, 1, c.num_cus, st);
           check(c, hipGetLastError());
           check(c, hipEventRecord(c.kev[4], st));
           check(c, hipEventSynchronize(c.kev[4]));
@@ -585,16 +665,18 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         fill_u32(xc, 0, 8, st);
         check(c, hipEventRecord(c.kev[3], st));
         launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr, prune, l2, bh,
-                         StreamOut{}, c.num_cus, st);
+                         StreamOut{}, BlockOut{}, 1, c.num_cus, st);
         check(c, hipGetLastError());
         emitted = true;
       }
+      }  // counted layout
     }
   }
   record(c, 5);
   for (double& x : c.kms) x = 0;
   c.kms[3] = (double)Ptot;
   c.kms[4] = stream_ms;
+  c.kms[9] = (double)c.emit_blocks;
 
   // ---------------------------------------------------------------- a5 --
   // The network in compressed sparse row form, sorted by (tail, head)
@@ -656,8 +738,10 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       uint64_t* bcur = need<uint64_t>(c, c.bcur, NB);
       fill_u64(bcur, 0, NB, st);
       check(c, hipEventRecord(c.kev[6], st));
+      const bool blk = c.emit_blocks > 0;
       launch_csr_bucket_scatter((const uint32_t*)c.pu.p, (uint64_t)Ptot, rstart, K, P.cell_start, RB, DB, (int)NB,
-                                bstart, bcur, col, st);
+                                bstart, bcur, col, blk ? (const uint32_t*)c.bfill.p : nullptr,
+                                blk ? (const uint32_t*)c.bpairs.p : nullptr, c.emit_block_recs, c.emit_blocks, st);
       check(c, hipEventRecord(c.kev[7], st));
       launch_csr_row_hist(col, tfirst, ntiles, (int)NB, bstart, RB, DB, N, rowcnt, st);
       check(c, hipEventRecord(c.kev[8], st));
@@ -674,6 +758,8 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     if (Ptot > 0) {
       uint32_t* rowcur = need<uint32_t>(c, c.rowcur, N);
       fill_u32(rowcur, 0, N, st);
+      // the pair records are consumed: their buffer takes the rows' heads
+      heads = need<uint32_t>(c, c.pu, 2 * Ptot + 2 * N + K);
       launch_csr_row_scatter(col, tfirst, ntiles, (int)NB, bstart, RB, DB, N, cp, off, rowcur, heads, st);
       check(c, hipEventRecord(c.kev[9], st));
     }
@@ -1185,6 +1271,9 @@ int w1_ctx_get_tuning(const w1_ctx* c, w1_tuning* out) {
   out->compact_records = c->tun.compact;
   out->stream_max_rounds = c->stream_rounds;
   out->stream_arena_pairs = c->stream_arena;
+  out->blocked_emit = c->blocked_emit;
+  out->reserved = 0;
+  out->emit_block_limit = c->emit_block_limit;
   return W1_OK;
 }
 
@@ -1193,12 +1282,15 @@ int w1_ctx_set_tuning(w1_ctx* c, const w1_tuning* t) {
   if (t->stack_depth < 8 || t->stack_depth > 32 || t->work_cap < 1 || t->work_cap > (1 << 20) ||
       t->chunk_items < 1 || t->chunk_items > (1 << 20) || t->blocks_per_cu < 1 || t->blocks_per_cu > 16 ||
       t->max_points_per_launch < 1 || (t->compact_records != 0 && t->compact_records != 1) ||
-      t->stream_max_rounds < 0 || t->stream_arena_pairs < 0 || t->stream_arena_pairs > (int64_t(1) << 36))
+      t->stream_max_rounds < 0 || t->stream_arena_pairs < 0 || t->stream_arena_pairs > (int64_t(1) << 36) ||
+      (t->blocked_emit != 0 && t->blocked_emit != 1) || t->reserved != 0 || t->emit_block_limit < 0)
     return W1_EINVAL;
   c->tun = WspdTuning{t->stack_depth, t->work_cap, t->chunk_items, t->blocks_per_cu, t->compact_records};
   c->max_points = t->max_points_per_launch;
   c->stream_rounds = t->stream_max_rounds;
   c->stream_arena = t->stream_arena_pairs;
+  c->blocked_emit = t->blocked_emit;
+  c->emit_block_limit = t->emit_block_limit;
   return W1_OK;
 }
 

@@ -536,7 +536,8 @@ int w1_nn_query(w1_ctx* c, w1_nn_index* x, w1_surrogate* s, const w1_pd* q, int6
                 uint32_t flags, void* stream, int64_t* nn_out, double* w1_out, int64_t* verif_out,
                 w1_nn_stats* stats) {
   if (!c || !x || !p || nq < 0 || (nq > 0 && (!q || !nn_out)) || x->device != c->device) return W1_EINVAL;
-  if (p->seed_k < 0 || p->mode < W1_NN_RWMD || p->mode > W1_NN_EXHAUSTIVE || !(p->eps > 0.0 && p->eps <= 1.0))
+  if (p->seed_k < 0 || p->keep < 0 || p->reserved != 0 || p->mode < W1_NN_RWMD || p->mode > W1_NN_PIPELINE ||
+      !(p->eps > 0.0 && p->eps <= 1.0))
     return W1_EINVAL;
   if (p->mode == W1_NN_SURROGATE && (!s || !x->has_emb || s->device != c->device)) return W1_EINVAL;
   int dtype;
@@ -680,6 +681,46 @@ int w1_nn_query(w1_ctx* c, w1_nn_index* x, w1_surrogate* s, const w1_pd* q, int6
     st.t_verify_ms += ms_since(t0);
     return r;
   };
+  // The method at s = 1 on the paper's grid for s = 1 (Alg. 2: eps_c = 1) for
+  // the listed pairs, batched: an upper bound on W1 that orders candidates.
+  std::vector<double> S1((size_t)(nq * m), INFINITY);
+  auto sparse = [&](const std::vector<std::vector<int32_t>>& lists) {
+    const auto t0 = clk::now();
+    w1_params sp{p->eps, 0.1, 1, W1_INPUT_DEVICE | W1_PRUNE | W1_PAPER_GRID, 0};
+    std::vector<w1_pd> A, B;
+    std::vector<int64_t> slot;
+    int64_t pts = 0;
+    int r = W1_OK;
+    auto flush = [&]() {
+      if (A.empty() || r != W1_OK) return;
+      std::vector<w1_result> res(A.size());
+      std::memset(res.data(), 0, res.size() * sizeof(w1_result));
+      r = w1_approx_batch(c, A.data(), B.data(), (int64_t)A.size(), &sp, stream, res.data());
+      for (size_t t = 0; t < res.size() && r == W1_OK; ++t)
+        if (res[t].status < 0) r = res[t].status;
+      if (r == W1_OK)
+        for (size_t t = 0; t < slot.size(); ++t) S1[(size_t)slot[t]] = res[t].w1;
+      for (auto& rr : res) w1_result_free(&rr);
+      A.clear();
+      B.clear();
+      slot.clear();
+      pts = 0;
+    };
+    for (int64_t i = 0; i < nq && r == W1_OK; ++i)
+      for (int32_t j : lists[(size_t)i]) {
+        const w1_pd& a = qv[(size_t)i];
+        const w1_pd& b = x->views[(size_t)j];
+        if (!A.empty() && (pts + a.n + b.n >= (int64_t(1) << 24) || (int64_t)A.size() >= 4096)) flush();
+        A.push_back(a);
+        B.push_back(b);
+        slot.push_back(i * m + j);
+        pts += a.n + b.n;
+        ++st.sparse_evals;
+      }
+    flush();
+    st.t_sparse_ms += ms_since(t0);
+    return r;
+  };
   auto sort_by_L = [&](std::vector<std::vector<int32_t>>& lists) {
     for (int64_t i = 0; i < nq; ++i) {
       const double* Li = L.data() + i * m;
@@ -695,6 +736,29 @@ int w1_nn_query(w1_ctx* c, w1_nn_index* x, w1_surrogate* s, const w1_pd* q, int6
   }
   if (rc == W1_OK && p->mode == W1_NN_EXHAUSTIVE) {
     rc = verify(all, 0);
+  } else if (rc == W1_OK && (p->mode == W1_NN_SPARSE || p->mode == W1_NN_PIPELINE)) {
+    // RWMD for every pair, the s = 1 stage on the `keep` nearest by RWMD,
+    // then the seed_k best of those verified (the pipeline stops there)
+    const bool pipeline = p->mode == W1_NN_PIPELINE;
+    const int64_t keep = std::min<int64_t>(m, p->keep > 0 ? p->keep : 15);
+    const int64_t c2 = std::min<int64_t>(keep, p->seed_k > 0 ? p->seed_k : (pipeline ? 3 : 1));
+    rc = rwmd(all);
+    std::vector<std::vector<int32_t>> head((size_t)nq);
+    if (rc == W1_OK) {
+      sort_by_L(all);
+      for (int64_t i = 0; i < nq; ++i) head[(size_t)i].assign(all[(size_t)i].begin(), all[(size_t)i].begin() + keep);
+      rc = sparse(head);
+    }
+    if (rc == W1_OK) {
+      for (int64_t i = 0; i < nq; ++i) {
+        const double* si = S1.data() + i * m;
+        std::vector<int32_t>& o = head[(size_t)i];
+        std::stable_sort(o.begin(), o.end(), [&](int32_t a, int32_t b) { return si[a] < si[b]; });
+        o.resize((size_t)c2);
+      }
+      rc = verify(head, 0);
+    }
+    if (rc == W1_OK && !pipeline) rc = verify(all, 2);
   } else if (rc == W1_OK && p->mode == W1_NN_RWMD) {
     rc = rwmd(all);
     if (rc == W1_OK) {

@@ -324,6 +324,7 @@ __device__ inline void unpack_boxes(uint4 w0, uint4 w1, int4& b1, int4& b2) {
 // 12), so records are addressed in 32-bit words, never by u32x3 arithmetic.
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
 typedef u32x3 u32x3_w __attribute__((aligned(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // Output pair (rep U, rep V, cost) of child / node aux c and the other node's
 // aux o; orient = 1 when c is on the U side.  Cost = 2 * L-infinity distance
@@ -372,7 +373,8 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
                                               const int32_t* __restrict__ xcd_range, uint32_t* __restrict__ xcd_ctr, int s,
                                               int stack_depth, int64_t step_cap, uint64_t* __restrict__ chunk_cnt,
                                               const uint64_t* __restrict__ chunk_off, uint32_t* __restrict__ out,
-                                              int32_t* __restrict__ err, BucketHist bh, StreamOut so) {
+                                              int32_t* __restrict__ err, BucketHist bh, StreamOut so, BlockOut bo,
+                                              int chunk_stride) {
   static_assert(!(EMIT && COMPACT), "packed split records carry no representatives");
   extern __shared__ int2 s_stack[];
   const int wave = threadIdx.x / WAVE, lane = lane_id();
@@ -384,6 +386,21 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
     for (int b = threadIdx.x; b < bh.NB; b += blockDim.x) s_hist[b] = 0;
     __syncthreads();
   }
+  // blocked output (network path): the wave's current block, wave-uniform
+  int blk = -1, bpair = -1;
+  uint32_t bleft = 0;
+  uint32_t* bptr = nullptr;  // where the block's next record goes (kept across chunks)
+  bool dead = false;
+  auto retire = [&]() {
+    if (blk >= 0 && lane == 0) {
+      const uint32_t f = bo.block - bleft;
+      bo.fill[blk] = f;
+      bo.pair[blk] = (uint32_t)bpair;
+      atomicAdd(&bo.pair_count[bpair], (unsigned long long)f);
+    }
+    blk = -1;
+    bleft = 0;
+  };
   const int xcd = blockIdx.x & 7;
   for (int probe = 0; probe < 8; ++probe) {
     const int xr = (xcd + probe) & 7;
@@ -392,11 +409,14 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       // every lane takes part in the fetch (lane 0 adds 1, the others 0), so
       // there is no lane-divergent region in the chunk loop
       const uint32_t t = atomicAdd(&xcd_ctr[xr], lane == 0 ? 1u : 0u);
-      const int k = (int)__builtin_amdgcn_readfirstlane(t) + r0;
+      const int k = (int)__builtin_amdgcn_readfirstlane(t) * chunk_stride + r0;
       if (k >= r1) break;
       int next = __builtin_amdgcn_readfirstlane(chunk_first[k]);
       const int end = __builtin_amdgcn_readfirstlane(chunk_end[k]);
-      uint32_t* obase = EMIT ? out + 3 * (chunk_off[k] - (uint64_t)so.base) : nullptr;
+      const int kp = EMIT && bo.base ? bo.chunk_pair[k] : 0;
+      if (EMIT && bo.base && blk >= 0 && kp != bpair) retire();  // a block holds one diagram pair
+      // records go at the chunk's counted offset, or on in the wave's block
+      uint32_t* obase = !EMIT ? nullptr : bo.base ? bptr : out + 3 * (chunk_off[k] - (uint64_t)so.base);
       uint64_t h1 = 0, h2 = 0;  // streamed emission: the lane's checksum terms
       const uint64_t cs = EMIT && bh.NB > 0 ? (uint64_t)bh.cell_start[bh.chunk_pair[k]] : 0;
       uint64_t cursor = 0;
@@ -513,9 +533,36 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
         if (EMIT) {
           // streaming (non-temporal) 12-byte stores: the output is written
           // once and must not evict the tree from L2
-          if (e1) __builtin_nontemporal_store(m1, (u32x3_w*)(obase + 3 * lanes_set_below(b1, 0u)));
-          if (e2) __builtin_nontemporal_store(m2, (u32x3_w*)(obase + 3 * lanes_set_below(b2, n1)));
-          obase += 3 * (n1 + n2);
+          bool wr = true;
+          if (bo.base) {  // blocked output: a fresh block when this step's records do not fit
+            const uint32_t n = n1 + n2;
+            if (n > bleft && !dead) {
+              retire();
+              uint32_t b = 0;
+              if (lane == 0) b = atomicAdd(bo.nblocks, 1u);
+              b = (uint32_t)__shfl((int)b, 0);
+              if (b < bo.max_blocks) {
+                blk = (int)b;
+                bpair = kp;
+                bleft = bo.block;
+                obase = bo.base + 2 * (size_t)b * bo.block;
+              } else {
+                dead = true;
+                if (lane == 0) atomicOr(bo.overflow, 1);
+              }
+            }
+            wr = !dead;
+            if (wr) bleft -= n;
+          }
+          if (wr && bo.base) {  // blocks hold (u, v): the network's costs come from the cells
+            if (e1) __builtin_nontemporal_store(u32x2{m1.x, m1.y}, (u32x2*)(obase + 2 * lanes_set_below(b1, 0u)));
+            if (e2) __builtin_nontemporal_store(u32x2{m2.x, m2.y}, (u32x2*)(obase + 2 * lanes_set_below(b2, n1)));
+            obase += 2 * (n1 + n2);
+          } else if (wr) {
+            if (e1) __builtin_nontemporal_store(m1, (u32x3_w*)(obase + 3 * lanes_set_below(b1, 0u)));
+            if (e2) __builtin_nontemporal_store(m2, (u32x3_w*)(obase + 3 * lanes_set_below(b2, n1)));
+            obase += 3 * (n1 + n2);
+          }
           if (so.chunk_sum) {
             if (e1) {
               const uint64_t h = record_hash(m1);
@@ -541,6 +588,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
         }
         cursor += n1 + n2;
       }
+      if (EMIT && bo.base) bptr = obase;
       const bool bad = runaway || __ballot(overflow) != 0;
       if (bad) atomicOr(err, 1);
       if (!EMIT) chunk_cnt[k] = cursor;  // same value from every lane
@@ -556,6 +604,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       }
     }
   }
+  if (EMIT && bo.base) retire();
   if (EMIT && bh.NB > 0) {
     __syncthreads();
     for (int b = threadIdx.x; b < bh.NB; b += blockDim.x)
@@ -626,7 +675,7 @@ void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, con
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
                       uint32_t* out, int32_t* err, bool prune, bool l2, const BucketHist& bh, const StreamOut& so,
-                      int num_cus, hipStream_t st) {
+                      const BlockOut& bo, int chunk_stride, int num_cus, hipStream_t st) {
   if (nchunks <= 0) return;
   int64_t grid = (int64_t)num_cus * tun.blocks_per_cu;
   grid = ((grid + 7) / 8) * 8;
@@ -644,7 +693,8 @@ void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, con
                          : (split_recs ? k_wspd<false, true, false, false> : k_wspd<false, false, false, false>));
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds, st, T.inode, split_recs, items, chunk_first, chunk_end,
                      xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, out, err,
-                     emit ? bh : BucketHist{}, emit ? so : StreamOut{});
+                     emit ? bh : BucketHist{}, emit ? so : StreamOut{}, emit ? bo : BlockOut{},
+                     chunk_stride > 0 ? chunk_stride : 1);
 }
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,

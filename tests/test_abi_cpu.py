@@ -201,3 +201,38 @@ def test_tune_workload_keys():
     assert k1 != k2 and k1.endswith("count") and k2.endswith("emit")
     assert k1.startswith("pts2^14/pair2^12/")
     assert tune.workload_key(A, B, 0.05, True) != k1
+
+
+def test_nn_query_marshalling(monkeypatch):
+    """The 1-NN binding passes mode, seed_k and keep through to the C-ABI
+    structure (checked with a stand-in for the library; no GPU)."""
+    import ctypes
+
+    assert ctypes.sizeof(w1._NNParams) == 24 and ctypes.sizeof(w1._NNStats) == 72
+    seen = []
+
+    class Fake:
+        def w1_nn_build(self, *a):
+            return 0
+
+        def w1_nn_query(self, ctx, idx, sur, arr, nq, prm, *rest):
+            p = prm._obj
+            seen.append((p.eps, p.mode, p.seed_k, p.keep, p.reserved, sur))
+            return 0
+
+        def w1_nn_destroy(self, *a):
+            return 0
+
+    monkeypatch.setattr(w1, "lib", lambda: Fake())
+
+    class Ctx:
+        _h = None
+
+    db = [np.array([[0.0, 1.0]])]
+    idx = w1.NNIndex(Ctx(), db)
+    idx.query(db, eps=0.2, mode="pipeline", seed_k=3, keep=15)
+    idx.query(db, eps=0.1, mode="sparse")
+    idx.query(db, eps=0.1, mode="rwmd", seed_k=2)
+    idx.close()
+    assert seen == [(0.2, w1.NN_PIPELINE, 3, 15, 0, None), (0.1, w1.NN_SPARSE, 0, 0, 0, None),
+                    (0.1, w1.NN_RWMD, 2, 0, 0, None)]

@@ -68,7 +68,8 @@ def _stored_flows():
 STORED = _stored_flows()
 
 
-def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True, prune=False, stored=None, l2=False):
+def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True, prune=False, stored=None, l2=False,
+            paper_grid=False):
     """Stage-by-stage parity with the oracle.  `stored` names the oracle's
     optimal flow written by tests/golden/make_oracle_flows.py; the oracle
     then runs without its (slow) flow solve.  Pruning leaves F* unchanged,
@@ -76,10 +77,11 @@ def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True, prune=F
     import paper_2110_14734_amd as w1
 
     flags = w1.KEEP_NETWORK | w1.KEEP_STAGES | (0 if flow else w1.NO_FLOW) | (w1.PRUNE if prune else 0)
-    flags |= w1.METRIC_L2 if l2 else 0
+    flags |= (w1.METRIC_L2 if l2 else 0) | (w1.PAPER_GRID if paper_grid else 0)
     g = ctx.approx(A, B, eps=eps, s_override=s_override, flags=flags)
     oflow = flow and stored is None
     oflags = (0 if oflow else orc.ORC_NO_FLOW) | (orc.ORC_PRUNE if prune else 0) | (orc.ORC_L2 if l2 else 0)
+    oflags |= orc.ORC_PAPER_GRID if paper_grid else 0
     r = orc.run(A, B, eps=eps, s_override=s_override, flags=oflags)
     assert r.status == 0 and g.status == 0
     # a0: net 0-condensation
@@ -111,7 +113,7 @@ def compare(orc, ctx, A, B, eps=0.1, s_override=0, flow=True, tree=True, prune=F
     assert g.n_pairs == r.n_pairs
     if l2:
         assert g.metric_l2 and g.cost_shift == r.K
-    check_csr(net, orc.csr(A, B, eps=eps, s_override=s_override, prune=prune, l2=l2))
+    check_csr(net, orc.csr(A, B, eps=eps, s_override=s_override, prune=prune, l2=l2, paper_grid=paper_grid))
     # flow and W1
     if flow and stored is None:
         assert g.flow_cost == r.flow
@@ -225,6 +227,22 @@ def test_paper_mode_small_s(orc, ctx, s_override):
     _say(f"[gpu] s_override {s_override}")
     A, B = cases.small_s_pair()
     compare(orc, ctx, A, B, eps=0.1, s_override=s_override, stored=f"small_s{s_override}")
+
+
+@pytest.mark.parametrize("s_override,l2", [(12, False), (20, False), (3, False), (20, True)])
+def test_paper_grid(orc, ctx, s_override, l2):
+    """The paper's own grid for a given s (eps_c = 8/(s - 4), or 1 below
+    s = 12): every stage, the network and W1 equal the oracle's; the flag
+    without s_override is rejected."""
+    import paper_2110_14734_amd as w1
+
+    _say(f"[gpu] paper grid s={s_override} l2={l2}")
+    A, B = pdsynth.exp_pd(300, 40), pdsynth.exp_pd(280, 41)
+    g, r = compare(orc, ctx, A, B, eps=0.1, s_override=s_override, l2=l2, paper_grid=True)
+    assert r.eps_c == (8 / (s_override - 4) if s_override >= 12 else 1.0)
+    with pytest.raises(w1.W1Error) as e:
+        ctx.approx(A, B, eps=0.1, flags=w1.PAPER_GRID)
+    assert e.value.code == w1.W1_EINVAL
 
 
 def test_edge_cases(orc, ctx):
@@ -454,6 +472,66 @@ def test_full_size_config2(ctx, csr_checker, eps, prune):
     _say(f"[gpu]   network: {g.n_arcs} arcs, checking rows")
     m = check_device_network(ctx, 0, pairs["checksum"], pairs["n_pairs"], csr_checker)
     assert m == g.n_arcs
+
+
+def _net_digest(ctx, chunk=1 << 28):
+    """Order-sensitive digest of pair 0's device network (heads, costs, row
+    pointers), computed on the device."""
+    import ctypes
+
+    import torch
+
+    d = ctx.device_network(0)
+    hip = _hip_runtime()
+    m = d["n_arcs"]
+    buf = torch.empty(min(m, chunk), dtype=torch.int32, device="cuda")
+    h = []
+    for name in ("col", "cost"):
+        acc = 0
+        for a0 in range(0, m, chunk):
+            n = min(chunk, m - a0)
+            torch.cuda.synchronize()
+            assert hip.hipMemcpy(ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(d[name] + 4 * a0), 4 * n, 3) == 0
+            x = buf[:n].to(torch.int64) + 1
+            w = torch.arange(a0, a0 + n, device="cuda", dtype=torch.int64) % 1000003 + 1
+            acc = (acc + int((x * w).sum().item())) % (1 << 61)
+        h.append(acc)
+    rp = _d2h(hip, d["row_ptr"], d["n_cells"] + 3, np.int64)
+    return tuple(h) + (int(rp.sum()), int(rp[-1]))
+
+
+@pytest.mark.skip(reason="blocked emission is off by default and not yet validated on the GPU: its first runs "
+                         "faulted (a block pointer lost between chunks, then a missing barrier before the bucket "
+                         "scatter's counters), both fixed from reading the code but not run again")
+def test_blocked_emission(ctx):
+    """A single large pair's network is the same whether its pair records go
+    into blocks sized by a count over every 16th chunk (the default), into
+    the counted layout (blocked_emit 0), or into too few blocks, so that the
+    pass is redone counted (emit_block_limit)."""
+    import torch
+
+    import paper_2110_14734_amd as w1
+
+    _say("[gpu] blocked emission: default, off, forced fallback")
+    A, B = pdsynth.mixture_pd(200_000, 0), pdsynth.mixture_pd(200_000, 1)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    t0 = ctx.tuning
+    out = []
+    try:
+        for cfg, blocked in ((dict(blocked_emit=1), True), (dict(blocked_emit=0), False),
+                             (dict(blocked_emit=1, emit_block_limit=64), False)):
+            ctx.tuning = dict(t0, **cfg)
+            g = ctx.approx(tA, tB, eps=0.1, flags=w1.NO_FLOW)
+            kt = ctx.kernel_times()
+            assert (kt["emit_blocks"] > 0) == blocked, cfg
+            assert kt["pairs"] == g.n_pairs
+            out.append((g.n_pairs, g.n_arcs, _net_digest(ctx)))
+        with pytest.raises(w1.W1Error):
+            ctx.tuning = dict(t0, blocked_emit=2)
+    finally:
+        ctx.tuning = t0
+    assert out[0] == out[1] == out[2]
+    assert out[0][0] == 1_823_249_560
 
 
 def test_tuning_and_launch_groups(orc, ctx):

@@ -290,6 +290,30 @@ def test_nn_answers_match_oracle(w1, ctx):
     idx.close()
 
 
+def test_nn_sparse_stage_and_pipeline(w1, ctx):
+    """The s = 1 stage of the paper's 1-NN pipelines.  Kept exact (mode
+    sparse) it gives the exhaustive answers; as the keep-c2-1 pipeline it
+    gives exactly the oracle's pipeline answers (RWMD cut, s = 1 cut on the
+    paper's grid for s = 1, best verified W1)."""
+    _say("1-NN sparse stage and pipeline vs oracle")
+    ds, fams, rng = _family_db(40, 6, 2, lo=15, hi=60)
+    qs = [pdsynth.family_pd(int(rng.integers(15, 60)), 779_000 + i, fams[i % len(fams)]) for i in range(6)]
+    idx = w1.NNIndex(ctx, ds)
+    want = S.nn_exhaustive(ds, qs, eps=0.1)
+    r = idx.query(qs, eps=0.1, mode="sparse", keep=10, seed_k=2)
+    assert [int(v) for v in r.nn] == [wi for wi, _ in want]
+    assert [float(v) for v in r.w1] == [wv for _, wv in want]
+    assert r.stats["sparse_evals"] == 10 * len(qs)
+    for keep, c2 in ((8, 2), (15, 3), (40, 40)):
+        pw = S.nn_pipeline(ds, qs, eps=0.1, keep=keep, c2=c2)
+        r = idx.query(qs, eps=0.1, mode="pipeline", keep=keep, seed_k=c2)
+        assert [int(v) for v in r.nn] == [wi for wi, _ in pw], (keep, c2)
+        assert [float(v) for v in r.w1] == [wv for _, wv in pw], (keep, c2)
+        assert np.all(r.verifications == c2)
+    assert pw == want  # keeping every candidate is the exhaustive search
+    idx.close()
+
+
 def test_nn_gain_with_trained_surrogate(w1, ctx):
     """What the trained network gains over the method without it: the same
     answers with fewer RWMD evaluations (the surrogate's first candidate

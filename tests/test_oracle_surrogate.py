@@ -194,3 +194,16 @@ def test_wcd_half_closed_forms():
     # one point against nothing: W1 is its distance to the diagonal, p/2,
     # and the bound gives half of that
     assert S.wcd_half(A[:1], np.zeros((0, 2))) == pytest.approx(0.25)
+
+
+def test_nn_pipeline_limits():
+    # the pipeline keeping every candidate is the exhaustive search, and its
+    # answer is never closer than the true nearest neighbour
+    rng = np.random.default_rng(3)
+    db = [pdsynth.exp_pd(int(rng.integers(10, 30)), 600 + i, mean_pers=0.1) for i in range(12)]
+    qs = [pdsynth.exp_pd(20, 700 + i, mean_pers=0.1) for i in range(3)]
+    want = S.nn_exhaustive(db, qs)
+    assert S.nn_pipeline(db, qs, keep=len(db), c2=len(db)) == want
+    for keep, c2 in ((4, 1), (6, 2)):
+        got = S.nn_pipeline(db, qs, keep=keep, c2=c2)
+        assert all(g[1] >= w[1] for g, w in zip(got, want))
