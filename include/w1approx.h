@@ -331,7 +331,11 @@ typedef struct {
                               /* count first.  The network is the same.    */
                               /* Experimental: not yet validated on the    */
                               /* GPU                                       */
-  int32_t reserved;           /* must be 0                                 */
+  int32_t sort_window_words;  /* row sort: bitmap window in 32-bit words   */
+                              /* (0 = as large as the largest pair needs,  */
+                              /* up to 24576); rows of pairs with more     */
+                              /* cells are sorted window by window.  The   */
+                              /* network does not depend on it             */
   int64_t emit_block_limit;   /* blocked emission: at most this many blocks */
                               /* of 4096 records (0 = as sized); when they */
                               /* run out the pass is redone with every     */

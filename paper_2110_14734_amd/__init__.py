@@ -82,7 +82,7 @@ class _Tuning(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("max_points_per_launch", ctypes.c_int64),
                 ("compact_records", ctypes.c_int32), ("stream_max_rounds", ctypes.c_int32),
                 ("stream_arena_pairs", ctypes.c_int64), ("blocked_emit", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("emit_block_limit", ctypes.c_int64)]
+                ("sort_window_words", ctypes.c_int32), ("emit_block_limit", ctypes.c_int64)]
 
 
 class _NNParams(ctypes.Structure):

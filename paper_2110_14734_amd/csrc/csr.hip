@@ -689,11 +689,12 @@ void launch_csr_row_scatter(const uint32_t* ent, const int64_t* tfirst, int64_t 
 }
 void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
                          const int32_t* ca, const uint32_t* rowcnt, const uint64_t* off, const uint32_t* heads,
-                         int64_t N, int64_t max_pair_cells, int num_cus, const int32_t* costK, uint32_t* col,
+                         int64_t N, int64_t max_pair_cells, int window_words, int num_cus, const int32_t* costK, uint32_t* col,
                          void* cost, hipStream_t st) {
   if (N <= 0) return;
   // the bitmap covers the largest pair's cells at once when they fit
-  const int win = (int)std::min<int64_t>(WIN_WORDS, std::max<int64_t>(1, (max_pair_cells + 31) / 32));
+  int win = (int)std::min<int64_t>(WIN_WORDS, std::max<int64_t>(1, (max_pair_cells + 31) / 32));
+  if (window_words > 0) win = std::min(win, window_words);
   const size_t lds = (size_t)win * 4 + (size_t)SORT_WAVES * SORT_STAGE * 4;
   // persistent: two blocks per compute unit when their LDS fits (a bitmap
   // of up to 50 KiB, i.e. pairs of up to 400k cells), else one

@@ -59,6 +59,7 @@ struct Ctx {
   int32_t stream_rounds = 0;               // streamed emission: arena fills at most (0 = all)
   int32_t blocked_emit = 0;                // network path: blocked emission (off by default)
   int64_t emit_block_limit = 0;            // blocked emission: block cap (0 = as sized)
+  int32_t sort_window = 0;                 // row sort bitmap window in words (0 = automatic)
   int64_t K_base = 0;                      // first pair of the last launch group
   std::vector<DBuf*> all;
   // points

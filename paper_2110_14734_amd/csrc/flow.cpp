@@ -131,9 +131,23 @@ struct Simplex {
 // g/2) or int64 (Euclidean costs in units of g 2^-K, scaled so that the
 // artificial cost (max cost + 1)(n + 1) stays below 2^60 and every reduced
 // cost fits int64).
+// Arc u -> w of a row sorted by head, or -1.
+int64_t find_arc(const int64_t* row_ptr, const int32_t* col, int32_t u, int32_t w) {
+  const int32_t* b = col + row_ptr[u];
+  const int32_t* e = col + row_ptr[u + 1];
+  const int32_t* f = std::lower_bound(b, e, w);
+  return f != e && *f == w ? (int64_t)(f - col) : -1;
+}
+
+// diag_a / diag_b >= 0: the network is a transshipment network whose nodes
+// diag_a and diag_b are the diagonal nodes of A and B, with rows sorted by
+// head.  The start tree is then the flow that sends every node's surplus
+// to diag_a and takes every deficit from diag_b (the diagonal arcs), with
+// diag_b -> diag_a carrying the rest, instead of artificial arcs only; if
+// an arc it needs is missing, the artificial start is used.
 template <typename C>
 int simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const C* cost, const int64_t* supply,
-            int64_t pivot_cap, FlowResult* out) {
+            int64_t pivot_cap, FlowResult* out, int32_t diag_a = -1, int32_t diag_b = -1) {
   out->cost = -1;
   out->pivots = 0;
   out->status = 0;
@@ -177,7 +191,80 @@ int simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const 
     return -3;
   }
   const int64_t ART = (maxc + 1) * ((int64_t)n + 1);
-  for (int32_t v = 0; v < n; ++v) {
+  // warm start from the diagonal flow (see above): the arcs each node needs
+  std::vector<int64_t> warm;
+  int64_t x_ba = 0, e_ba = -1;
+  if (diag_a >= 0 && diag_b >= 0 && diag_a < n && diag_b < n && diag_a != diag_b && supply[diag_a] <= 0 &&
+      supply[diag_b] >= 0) {
+    try {
+      warm.assign((size_t)n, -1);
+    } catch (...) {
+      return -3;
+    }
+    bool ok = true;
+    x_ba = supply[diag_b];
+    for (int32_t v = 0; v < n && ok; ++v) {
+      if (v == diag_a || v == diag_b) continue;
+      if (supply[v] > 0) {
+        warm[(size_t)v] = find_arc(row_ptr, S.col, v, diag_a);
+        ok = warm[(size_t)v] >= 0;
+      } else {
+        warm[(size_t)v] = find_arc(row_ptr, S.col, diag_b, v);  // may be absent for a node without supply
+        ok = supply[v] == 0 || warm[(size_t)v] >= 0;
+        x_ba += supply[v];
+      }
+    }
+    if (ok && x_ba > 0) {
+      e_ba = find_arc(row_ptr, S.col, diag_b, diag_a);
+      ok = e_ba >= 0;
+    }
+    if (!ok || x_ba < 0) warm.clear();
+  }
+  if (!warm.empty()) {
+    // strongly feasible: every zero-flow tree arc leaves the root's side
+    auto art_down = [&](int32_t v) {  // artificial root -> v, no flow
+      S.art_out[v] = 0;
+      S.pred[v] = m + v;
+      S.tflow[v] = 0;
+      S.up[v] = 0;
+      S.pi[v] = ART;
+      S.depth[v] = 1;
+      S.link(v, S.root);
+    };
+    art_down(diag_a);
+    if (x_ba > 0) {
+      S.pred[diag_b] = e_ba;
+      S.tflow[diag_b] = x_ba;
+      S.up[diag_b] = 1;
+      S.pi[diag_b] = S.pi[diag_a] - (int64_t)cost[e_ba];
+      S.depth[diag_b] = 2;
+      S.link(diag_b, diag_a);
+    } else {
+      art_down(diag_b);
+    }
+    for (int32_t v = 0; v < n; ++v) {
+      if (v == diag_a || v == diag_b) continue;
+      const int64_t e = warm[(size_t)v];
+      if (supply[v] > 0) {  // v -> diag_a carries the surplus
+        S.pred[v] = e;
+        S.tflow[v] = supply[v];
+        S.up[v] = 1;
+        S.pi[v] = S.pi[diag_a] - (int64_t)cost[e];
+        S.depth[v] = S.depth[diag_a] + 1;
+        S.link(v, diag_a);
+      } else if (e >= 0) {  // diag_b -> v carries the deficit (or nothing)
+        S.pred[v] = e;
+        S.tflow[v] = -supply[v];
+        S.up[v] = 0;
+        S.pi[v] = S.pi[diag_b] + (int64_t)cost[e];
+        S.depth[v] = S.depth[diag_b] + 1;
+        S.link(v, diag_b);
+      } else {
+        art_down(v);
+      }
+    }
+  }
+  for (int32_t v = 0; v < n && warm.empty(); ++v) {
     if (supply[v] > 0) {
       S.art_out[v] = 1;
       S.tflow[v] = supply[v];
@@ -338,6 +425,20 @@ int simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const 
 int network_simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int32_t* cost,
                     const int64_t* supply, int64_t pivot_cap, FlowResult* out) {
   return simplex<int32_t>(n_nodes, row_ptr, col, cost, supply, pivot_cap, out);
+}
+
+int network_simplex_diag(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int32_t* cost,
+                         const int64_t* supply, int64_t pivot_cap, FlowResult* out) {
+  if (n_nodes < 2) return simplex<int32_t>(n_nodes, row_ptr, col, cost, supply, pivot_cap, out);
+  return simplex<int32_t>(n_nodes, row_ptr, col, cost, supply, pivot_cap, out, (int32_t)(n_nodes - 2),
+                          (int32_t)(n_nodes - 1));
+}
+
+int network_simplex64_diag(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int64_t* cost,
+                           const int64_t* supply, int64_t pivot_cap, FlowResult* out) {
+  if (n_nodes < 2) return simplex<int64_t>(n_nodes, row_ptr, col, cost, supply, pivot_cap, out);
+  return simplex<int64_t>(n_nodes, row_ptr, col, cost, supply, pivot_cap, out, (int32_t)(n_nodes - 2),
+                          (int32_t)(n_nodes - 1));
 }
 
 int network_simplex64(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int64_t* cost,

@@ -25,6 +25,16 @@ int network_simplex(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col
 int network_simplex64(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int64_t* cost,
                       const int64_t* supply, int64_t pivot_cap, FlowResult* out);
 
+// The same for the method's transshipment networks (nodes n_nodes - 2 and
+// n_nodes - 1 the diagonal nodes of A and B, rows sorted by head): the
+// start tree is the flow through the diagonal (every surplus to A's
+// diagonal node, every deficit from B's), so the solve starts feasible.
+// The optimum is the same as network_simplex's.
+int network_simplex_diag(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int32_t* cost,
+                         const int64_t* supply, int64_t pivot_cap, FlowResult* out);
+int network_simplex64_diag(int64_t n_nodes, const int64_t* row_ptr, const uint32_t* col, const int64_t* cost,
+                           const int64_t* supply, int64_t pivot_cap, FlowResult* out);
+
 // The same for an arc list (src, dst, cost); flow entries follow the list.
 int network_simplex_arcs(int64_t n_nodes, int64_t m, const uint32_t* src, const uint32_t* dst, const int32_t* cost,
                          const int64_t* supply, int64_t pivot_cap, FlowResult* out);

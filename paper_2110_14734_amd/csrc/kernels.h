@@ -97,7 +97,7 @@ void launch_csr_row_scatter(const uint32_t* ent, const int64_t* tfirst, int64_t 
                             const uint64_t* off, uint32_t* rowcur, uint32_t* heads, hipStream_t st);
 void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
                          const int32_t* ca, const uint32_t* rowcnt, const uint64_t* off, const uint32_t* heads,
-                         int64_t N, int64_t max_pair_cells, int num_cus, const int32_t* costK, uint32_t* col,
+                         int64_t N, int64_t max_pair_cells, int window_words, int num_cus, const int32_t* costK, uint32_t* col,
                          void* cost, hipStream_t st);
 void launch_csr_bdiag(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
                       const int32_t* ca, const int32_t* cb, const uint32_t* bpos, const uint64_t* off,

@@ -787,7 +787,8 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     }
     void* cost = l2 ? (void*)need<int64_t>(c, c.costb, 2 * Ptot + 2 * N + K)
                     : (void*)need<int32_t>(c, c.costb, 2 * Ptot + 2 * N + K);
-    launch_csr_row_sort(cp, P.cell_start, ncl, cij, ca, rowcnt, off, heads, N, maxnp, c.num_cus, costK, col, cost, st);
+    launch_csr_row_sort(cp, P.cell_start, ncl, cij, ca, rowcnt, off, heads, N, maxnp, c.sort_window, c.num_cus, costK,
+                        col, cost, st);
     launch_csr_bdiag(cp, P.cell_start, ncl, cij, ca, cb, bpos, off, P, N, costK, col, cost, sup, st);
     int64_t* rp = need<int64_t>(c, c.rp, N + 3 * K);
     fill_u64((uint64_t*)rp, 0, N + 3 * K, st);
@@ -1001,8 +1002,11 @@ void finish_flow(w1_result& r, const FlowResult& fr) {
 // the solver's own input form).
 void solve_flow(w1_result& r, int64_t pivot_cap) {
   FlowResult fr{};
-  const int rc = r.metric_l2 ? network_simplex64(r.n_cells + 2, r.row_ptr, r.col, r.cost64, r.supply, pivot_cap, &fr)
-                             : network_simplex(r.n_cells + 2, r.row_ptr, r.col, r.cost, r.supply, pivot_cap, &fr);
+  // the rows are sorted by head and the diagonal nodes come last: the solve
+  // starts from the flow through the diagonal
+  const int rc = r.metric_l2
+                     ? network_simplex64_diag(r.n_cells + 2, r.row_ptr, r.col, r.cost64, r.supply, pivot_cap, &fr)
+                     : network_simplex_diag(r.n_cells + 2, r.row_ptr, r.col, r.cost, r.supply, pivot_cap, &fr);
   if (rc != 0) {
     r.status = rc == -3 ? W1_ENOMEM : W1_EINVAL;
     return;
@@ -1272,7 +1276,7 @@ int w1_ctx_get_tuning(const w1_ctx* c, w1_tuning* out) {
   out->stream_max_rounds = c->stream_rounds;
   out->stream_arena_pairs = c->stream_arena;
   out->blocked_emit = c->blocked_emit;
-  out->reserved = 0;
+  out->sort_window_words = c->sort_window;
   out->emit_block_limit = c->emit_block_limit;
   return W1_OK;
 }
@@ -1283,7 +1287,7 @@ int w1_ctx_set_tuning(w1_ctx* c, const w1_tuning* t) {
       t->chunk_items < 1 || t->chunk_items > (1 << 20) || t->blocks_per_cu < 1 || t->blocks_per_cu > 16 ||
       t->max_points_per_launch < 1 || (t->compact_records != 0 && t->compact_records != 1) ||
       t->stream_max_rounds < 0 || t->stream_arena_pairs < 0 || t->stream_arena_pairs > (int64_t(1) << 36) ||
-      (t->blocked_emit != 0 && t->blocked_emit != 1) || t->reserved != 0 || t->emit_block_limit < 0)
+      (t->blocked_emit != 0 && t->blocked_emit != 1) || t->sort_window_words < 0 || t->emit_block_limit < 0)
     return W1_EINVAL;
   c->tun = WspdTuning{t->stack_depth, t->work_cap, t->chunk_items, t->blocks_per_cu, t->compact_records};
   c->max_points = t->max_points_per_launch;
@@ -1291,6 +1295,7 @@ int w1_ctx_set_tuning(w1_ctx* c, const w1_tuning* t) {
   c->stream_arena = t->stream_arena_pairs;
   c->blocked_emit = t->blocked_emit;
   c->emit_block_limit = t->emit_block_limit;
+  c->sort_window = t->sort_window_words;
   return W1_OK;
 }
 

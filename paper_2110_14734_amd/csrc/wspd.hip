@@ -366,7 +366,7 @@ __device__ inline uint32_t lanes_set_below(uint64_t m, uint32_t add) {
 // written as 12-byte records at the wave cursor in (slot, lane) order, so the
 // order depends only on the chunk.  Loop control lives in wave-uniform
 // scalars.
-template <bool EMIT, bool COMPACT, bool PRUNE, bool L2>
+template <bool EMIT, bool COMPACT, bool PRUNE, bool L2, bool BLOCKS>
 __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const uint4* __restrict__ SR,
                                               const int2* __restrict__ items,
                                               const int32_t* __restrict__ chunk_first, const int32_t* __restrict__ chunk_end,
@@ -376,6 +376,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
                                               int32_t* __restrict__ err, BucketHist bh, StreamOut so, BlockOut bo,
                                               int chunk_stride) {
   static_assert(!(EMIT && COMPACT), "packed split records carry no representatives");
+  static_assert(EMIT || !BLOCKS, "blocked output is an emit-pass mode");
   extern __shared__ int2 s_stack[];
   const int wave = threadIdx.x / WAVE, lane = lane_id();
   int2* stk = s_stack + (size_t)wave * stack_depth * WAVE + lane;  // entry e at stk[e * WAVE]
@@ -413,10 +414,10 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       if (k >= r1) break;
       int next = __builtin_amdgcn_readfirstlane(chunk_first[k]);
       const int end = __builtin_amdgcn_readfirstlane(chunk_end[k]);
-      const int kp = EMIT && bo.base ? bo.chunk_pair[k] : 0;
-      if (EMIT && bo.base && blk >= 0 && kp != bpair) retire();  // a block holds one diagram pair
+      const int kp = BLOCKS ? bo.chunk_pair[k] : 0;
+      if (BLOCKS && blk >= 0 && kp != bpair) retire();  // a block holds one diagram pair
       // records go at the chunk's counted offset, or on in the wave's block
-      uint32_t* obase = !EMIT ? nullptr : bo.base ? bptr : out + 3 * (chunk_off[k] - (uint64_t)so.base);
+      uint32_t* obase = !EMIT ? nullptr : BLOCKS ? bptr : out + 3 * (chunk_off[k] - (uint64_t)so.base);
       uint64_t h1 = 0, h2 = 0;  // streamed emission: the lane's checksum terms
       const uint64_t cs = EMIT && bh.NB > 0 ? (uint64_t)bh.cell_start[bh.chunk_pair[k]] : 0;
       uint64_t cursor = 0;
@@ -534,7 +535,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
           // streaming (non-temporal) 12-byte stores: the output is written
           // once and must not evict the tree from L2
           bool wr = true;
-          if (bo.base) {  // blocked output: a fresh block when this step's records do not fit
+          if (BLOCKS) {  // blocked output: a fresh block when this step's records do not fit
             const uint32_t n = n1 + n2;
             if (n > bleft && !dead) {
               retire();
@@ -554,11 +555,11 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
             wr = !dead;
             if (wr) bleft -= n;
           }
-          if (wr && bo.base) {  // blocks hold (u, v): the network's costs come from the cells
+          if (BLOCKS && wr) {  // blocks hold (u, v): the network's costs come from the cells
             if (e1) __builtin_nontemporal_store(u32x2{m1.x, m1.y}, (u32x2*)(obase + 2 * lanes_set_below(b1, 0u)));
             if (e2) __builtin_nontemporal_store(u32x2{m2.x, m2.y}, (u32x2*)(obase + 2 * lanes_set_below(b2, n1)));
             obase += 2 * (n1 + n2);
-          } else if (wr) {
+          } else if (!BLOCKS) {
             if (e1) __builtin_nontemporal_store(m1, (u32x3_w*)(obase + 3 * lanes_set_below(b1, 0u)));
             if (e2) __builtin_nontemporal_store(m2, (u32x3_w*)(obase + 3 * lanes_set_below(b2, n1)));
             obase += 3 * (n1 + n2);
@@ -588,7 +589,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
         }
         cursor += n1 + n2;
       }
-      if (EMIT && bo.base) bptr = obase;
+      if (BLOCKS) bptr = obase;
       const bool bad = runaway || __ballot(overflow) != 0;
       if (bad) atomicOr(err, 1);
       if (!EMIT) chunk_cnt[k] = cursor;  // same value from every lane
@@ -604,7 +605,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       }
     }
   }
-  if (EMIT && bo.base) retire();
+  if (BLOCKS) retire();
   if (EMIT && bh.NB > 0) {
     __syncthreads();
     for (int b = threadIdx.x; b < bh.NB; b += blockDim.x)
@@ -685,12 +686,18 @@ void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, con
   const int64_t step_cap = (int64_t)tun.chunk_items * (2 * (int64_t)tun.work_cap + 2) + 1024;
   // the emit pass always reads the children's records (the packed split
   // records serve the count pass)
-  auto k = l2 ? (emit ? k_wspd<true, false, false, true>
-                      : (split_recs ? k_wspd<false, true, false, true> : k_wspd<false, false, false, true>))
-         : prune ? (emit ? k_wspd<true, false, true, false>
-                         : (split_recs ? k_wspd<false, true, true, false> : k_wspd<false, false, true, false>))
-                 : (emit ? k_wspd<true, false, false, false>
-                         : (split_recs ? k_wspd<false, true, false, false> : k_wspd<false, false, false, false>));
+  const bool blocks = emit && bo.base;
+  auto k = l2 ? (blocks ? k_wspd<true, false, false, true, true>
+                 : emit ? k_wspd<true, false, false, true, false>
+                        : (split_recs ? k_wspd<false, true, false, true, false> : k_wspd<false, false, false, true, false>))
+         : prune ? (blocks ? k_wspd<true, false, true, false, true>
+                    : emit ? k_wspd<true, false, true, false, false>
+                           : (split_recs ? k_wspd<false, true, true, false, false>
+                                         : k_wspd<false, false, true, false, false>))
+                 : (blocks ? k_wspd<true, false, false, false, true>
+                    : emit ? k_wspd<true, false, false, false, false>
+                           : (split_recs ? k_wspd<false, true, false, false, false>
+                                         : k_wspd<false, false, false, false, false>));
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds, st, T.inode, split_recs, items, chunk_first, chunk_end,
                      xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, out, err,
                      emit ? bh : BucketHist{}, emit ? so : StreamOut{}, emit ? bo : BlockOut{},

@@ -474,6 +474,22 @@ def test_full_size_config2(ctx, csr_checker, eps, prune):
     assert m == g.n_arcs
 
 
+@pytest.mark.parametrize("win", [64, 100])
+def test_row_sort_windows(orc, ctx, win):
+    """Rows sorted window by window (a bitmap window of 2048 or 3200 cells,
+    far smaller than the pairs; a window of 100 words ends inside a group)
+    give the oracle's network, row by row."""
+    _say(f"[gpu] row sort in windows of {win} words")
+    t0 = ctx.tuning
+    try:
+        ctx.tuning = dict(t0, sort_window_words=win)
+        for name, make, eps in cases.STAGE_CASES[:4]:
+            A, B = make()
+            compare(orc, ctx, A, B, eps=eps, flow=False)
+    finally:
+        ctx.tuning = t0
+
+
 def _net_digest(ctx, chunk=1 << 28):
     """Order-sensitive digest of pair 0's device network (heads, costs, row
     pointers), computed on the device."""
