@@ -178,9 +178,27 @@ def run_batch(ctx, args):
               "seconds": t_stream, "pd_pairs_per_s": K / t_stream, "pairs_written": streamed,
               "all_written": bool(streamed == wspd and all(r.n_pairs_streamed == r.n_pairs for r in rst)),
               "record_GBs": 12 * streamed / t_stream / 1e9}
+    # end to end (network and exact flow, W1 certified) on every pair of the
+    # batch with n_A + n_B <= 3000, in one batch call: the host flows run in
+    # parallel threads
+    small = [i for i in range(K) if sizes[2 * i] + sizes[2 * i + 1] <= 3000]
+    e2e = {}
+    if small:
+        sa, sb = [dA[i] for i in small], [dB[i] for i in small]
+        ctx.approx_batch(sa[:64], sb[:64], eps=args.eps)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        re2e = ctx.approx_batch(sa, sb, eps=args.eps)
+        t_e2e = time.perf_counter() - t0
+        e2e = {"what": "W1 end to end (GPU network, host flow from the diagonal start) for every pair with "
+                       "n_A + n_B <= 3000, one batch call",
+               "pairs": len(small), "seconds": t_e2e, "pd_pairs_per_s": len(small) / t_e2e,
+               "all_solved": bool(all(r.status == 0 and r.flow_solved == 1 for r in re2e)),
+               "flow_ms_last_group": float(re2e[-1].t_ms["flow"])}
     return {
         "workload": f"{K} pairs, points per diagram log-uniform in [100, 50k] (birth U[0,1), persistence "
                     f"Exponential(mean 0.05), FP32), eps={args.eps}, a0-a4 with WSPD pairs counted",
+        "end_to_end_small": e2e,
         "points": npts, "wspd_pairs": wspd,
         "batch_s": t_batch, "pd_pairs_per_s": K / t_batch, "points_per_s": npts / t_batch,
         "wspd_pairs_per_s": wspd / t_batch,
