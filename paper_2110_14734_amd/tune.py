@@ -8,7 +8,7 @@ the current setting, and keeps the fastest.  The choice is cached in a JSON
 file keyed by device architecture, compute-unit count, workload size class and
 mode.
 
-    python -m paper_2110_14734_amd.tune [--cache FILE] [--workload c2|c3]
+    python -m paper_2110_14734_amd.tune [--cache FILE] [--workload c2|c3|c3full]
 """
 from __future__ import annotations
 
@@ -101,13 +101,34 @@ def save(cache: str, key: str, result: dict) -> None:
     os.replace(tmp, cache)
 
 
+def lookup(data: dict, dev: str, key: str) -> dict | None:
+    """The cached entry for this device and workload class; failing that,
+    the entry of the same device, points per pair, eps and mode whose total
+    size is closest (the tunables follow the pair sizes more than their
+    number)."""
+    if dev + "/" + key in data:
+        return data[dev + "/" + key]
+    tot, rest = key.split("/", 1)
+    best, dist = None, None
+    for k, v in data.items():
+        if not k.startswith(dev + "/"):
+            continue
+        kt, kr = k[len(dev) + 1:].split("/", 1)
+        if kr != rest:
+            continue
+        d = abs(int(kt[len("pts2^"):]) - int(tot[len("pts2^"):]))
+        if dist is None or d < dist:
+            best, dist = v, d
+    return best
+
+
 def apply_cached(ctx, As, Bs, eps=0.1, count_only=False, cache: str = DEFAULT_CACHE) -> dict | None:
     """Apply the cached tuning of this device and workload class, if any."""
     if not os.path.exists(cache):
         return None
     with open(cache) as f:
         data = json.load(f)
-    hit = data.get(device_key() + "/" + workload_key(As, Bs, eps, count_only))
+    hit = lookup(data, device_key(), workload_key(As, Bs, eps, count_only))
     if hit:
         ctx.tuning = {k: v for k, v in hit.items() if k in ctx.tuning}
     return hit
@@ -120,7 +141,7 @@ def _workload(name: str):
 
     if name == "c2":
         return [pdsynth.mixture_pd(200_000, 0)], [pdsynth.mixture_pd(200_000, 1)], 0
-    sizes = pdsynth.batch_sizes(2 * 512, 3)
+    sizes = pdsynth.batch_sizes(2 * (4096 if name == "c3full" else 512), 3)
     As = [pdsynth.exp_pd(int(n), 10 + 2 * i, dtype=np.float32) for i, n in enumerate(sizes[0::2])]
     Bs = [pdsynth.exp_pd(int(n), 11 + 2 * i, dtype=np.float32) for i, n in enumerate(sizes[1::2])]
     return As, Bs, 2  # COUNT_ONLY
@@ -133,7 +154,7 @@ def main():
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--cache", default=DEFAULT_CACHE)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c3full"])
     ap.add_argument("--eps", type=float, default=0.1)
     a = ap.parse_args()
     As, Bs, flags = _workload(a.workload)

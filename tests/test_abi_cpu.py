@@ -236,3 +236,17 @@ def test_nn_query_marshalling(monkeypatch):
     idx.close()
     assert seen == [(0.2, w1.NN_PIPELINE, 3, 15, 0, None), (0.1, w1.NN_SPARSE, 0, 0, 0, None),
                     (0.1, w1.NN_RWMD, 2, 0, 0, None)]
+
+
+def test_tune_cache_lookup():
+    """The tuning cache: the exact key first, else the same device, points
+    per pair, eps and mode with the closest total size."""
+    from paper_2110_14734_amd import tune
+
+    data = {"dev/pts2^23/pair2^14/eps0.1/count": {"v": 1}, "dev/pts2^19/pair2^14/eps0.1/count": {"v": 2},
+            "dev/pts2^26/pair2^14/eps0.1/emit": {"v": 3}, "other/pts2^26/pair2^14/eps0.1/count": {"v": 4}}
+    assert tune.lookup(data, "dev", "pts2^23/pair2^14/eps0.1/count") == {"v": 1}
+    assert tune.lookup(data, "dev", "pts2^26/pair2^14/eps0.1/count") == {"v": 1}
+    assert tune.lookup(data, "dev", "pts2^20/pair2^14/eps0.1/count") == {"v": 2}
+    assert tune.lookup(data, "dev", "pts2^26/pair2^15/eps0.1/count") is None
+    assert tune.lookup(data, "dev", "pts2^26/pair2^14/eps0.2/count") is None
