@@ -304,12 +304,13 @@ def test_nn_sparse_stage_and_pipeline(w1, ctx):
     assert [int(v) for v in r.nn] == [wi for wi, _ in want]
     assert [float(v) for v in r.w1] == [wv for _, wv in want]
     assert r.stats["sparse_evals"] == 10 * len(qs)
-    for keep, c2 in ((8, 2), (15, 3), (40, 40)):
+    for keep, c2 in ((8, 2), (15, 3), (40, 40), (1, 1), (100, 60), (5, 9)):
         pw = S.nn_pipeline(ds, qs, eps=0.1, keep=keep, c2=c2)
         r = idx.query(qs, eps=0.1, mode="pipeline", keep=keep, seed_k=c2)
         assert [int(v) for v in r.nn] == [wi for wi, _ in pw], (keep, c2)
         assert [float(v) for v in r.w1] == [wv for _, wv in pw], (keep, c2)
-        assert np.all(r.verifications == c2)
+        # keep and c2 are clamped to the database and to keep
+        assert np.all(r.verifications == min(c2, keep, len(ds)))
     assert pw == want  # keeping every candidate is the exhaustive search
     idx.close()
 
