@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <initializer_list>
 #include <vector>
 
 #include "../../include/w1approx.h"
@@ -84,6 +85,7 @@ struct Ctx {
   uint32_t emit_blocks = 0, emit_block_recs = 0;
   // per pair
   DBuf pairs;
+  int64_t pair_bytes = 0;  // bytes of the per-pair arrays in `pairs`
   PairArrays P{};
   int64_t K = 0;
   std::vector<int64_t> h_cell_start, h_ncells, h_npairs, h_arc_start, h_narcs;
@@ -182,6 +184,22 @@ inline void upload(Ctx& c, void* dev, const void* host, size_t bytes) {
   if (!bytes) return;
   check(c, hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c.st));
   check(c, hipStreamSynchronize(c.st));
+}
+
+// Several small host -> device copies with one wait for all of them.
+struct HostCopy {
+  void* dev;
+  const void* host;
+  size_t bytes;
+};
+inline void upload_all(Ctx& c, std::initializer_list<HostCopy> copies) {
+  bool any = false;
+  for (const HostCopy& x : copies)
+    if (x.bytes) {
+      check(c, hipMemcpyAsync(x.dev, x.host, x.bytes, hipMemcpyHostToDevice, c.st));
+      any = true;
+    }
+  if (any) check(c, hipStreamSynchronize(c.st));
 }
 
 inline uint64_t read_u64(Ctx& c, const void* dev) {

@@ -35,6 +35,8 @@ inline int clz64(uint64_t x) { return x ? __builtin_clzll(x) : 64; }
 inline int bitlen_u64(uint64_t x) { return 64 - clz64(x); }
 inline int ctz64(uint64_t x) { return x ? __builtin_ctzll(x) : 64; }
 
+constexpr int kSortMaxWords = 3;
+
 // Stable sort of n elements by the words (least significant first); returns
 // the permutation in *perm and the sorted most significant word in *top.
 void sort_words(Ctx& c, const uint64_t* const* words, int nw, int64_t n, uint32_t** perm, uint64_t** top) {
@@ -43,16 +45,22 @@ void sort_words(Ctx& c, const uint64_t* const* words, int nw, int64_t n, uint32_
   uint32_t* vA = need<uint32_t>(c, c.vA, n);
   uint32_t* vB = need<uint32_t>(c, c.vB, n);
   void* tmp = need<char>(c, c.sorttmp, (int64_t)radix_tmp_bytes(n));
+  // the bits that vary in each word (OR ^ AND over its elements): reordering
+  // a word does not change them, so one read-back serves every word
+  if (nw > kSortMaxWords) throw StageError{W1_EINVAL};
   uint64_t* orand = need<uint64_t>(c, c.small, 64) + 8;
+  uint64_t* part = need<uint64_t>(c, c.orpart, 2 * kOrAndBlocks);
+  for (int w = 0; w < nw; ++w) key_or_and(words[w], n, orand + 2 * w, part, c.st);
+  readback(c, orand, c.hpin, 2 * nw);
+  uint64_t vary[kSortMaxWords];
+  for (int w = 0; w < nw; ++w) vary[w] = c.hpin[2 * w] ^ c.hpin[2 * w + 1];
   iota_u32(vA, n, c.st);
   for (int w = 0; w < nw; ++w) {
+    if (!vary[w] && w + 1 < nw) continue;  // the last word is returned sorted, so always taken
     if (w == 0) check(c, hipMemcpyAsync(kA, words[0], (size_t)n * 8, hipMemcpyDeviceToDevice, c.st));
     else gather_u64(words[w], vA, kA, n, c.st);
-    key_or_and(kA, n, orand, need<uint64_t>(c, c.orpart, 2 * kOrAndBlocks), c.st);
-    readback(c, orand, c.hpin, 2);
-    const uint64_t vary = c.hpin[0] ^ c.hpin[1];
-    if (!vary) continue;
-    const int lo = ctz64(vary), hi = 64 - clz64(vary);
+    if (!vary[w]) continue;
+    const int lo = ctz64(vary[w]), hi = 64 - clz64(vary[w]);
     if (radix_sort(kA, vA, kB, vB, n, lo, hi, tmp, c.st)) {
       std::swap(kA, kB);
       std::swap(vA, vB);
@@ -98,9 +106,11 @@ int separation(double eps, double kappa) {
 }
 
 void setup_pairs(Ctx& c, int64_t K) {
-  // 24 int64-sized arrays and 12 int32-sized arrays per pair
+  // 26 int64-sized and 14 int32-sized slots per pair (some spare), all in
+  // one allocation, so the results come back in one transfer
   const int64_t K8 = ((K + 31) / 32) * 32;
-  char* base = need<char>(c, c.pairs, K8 * 8 * 26 + K8 * 4 * 14);
+  c.pair_bytes = K8 * 8 * 26 + K8 * 4 * 14;
+  char* base = need<char>(c, c.pairs, c.pair_bytes);
   int64_t off = 0;
   auto take8 = [&](void) { void* p = base + off; off += K8 * 8; return p; };
   auto take4 = [&](void) { void* p = base + off; off += K8 * 4; return p; };
@@ -131,6 +141,13 @@ std::vector<T> fetch_pairs(Ctx& c, const T* dev, int64_t K) {
   std::vector<T> h((size_t)K);
   readback(c, dev, h.data(), K);
   return h;
+}
+
+// The per-pair array `dev` out of a host copy of the whole per-pair block.
+template <typename T>
+std::vector<T> from_pair_block(const Ctx& c, const std::vector<char>& block, const T* dev, int64_t K) {
+  const T* x = (const T*)(block.data() + ((const char*)dev - (const char*)c.pairs.p));
+  return std::vector<T>(x, x + K);
 }
 
 void record(Ctx& c, int i) {
@@ -278,10 +295,11 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     int64_t* nbk = need<int64_t>(c, c.nbuck, K + 1);
     launch_bucket_setup(P, K, nbk, st);
     scan_i64(nbk, P.bbase, K, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(K, 8)), st);
-    int64_t lastb[2];
-    readback(c, P.bbase + (K - 1), &lastb[0], 1);
-    readback(c, nbk + (K - 1), &lastb[1], 1);
-    const int64_t Btot = lastb[0] + lastb[1];
+    // the last pair's first bucket and bucket count, one wait for both
+    check(c, hipMemcpyAsync(c.hpin, P.bbase + (K - 1), 8, hipMemcpyDeviceToHost, st));
+    check(c, hipMemcpyAsync(c.hpin + 1, nbk + (K - 1), 8, hipMemcpyDeviceToHost, st));
+    check(c, hipStreamSynchronize(st));
+    const int64_t Btot = (int64_t)c.hpin[0] + (int64_t)c.hpin[1];
     trace(c, "rwmd buckets", Btot);
     const int64_t nbins = 2 * Btot + 1;
     if (nbins >= (int64_t(1) << 31)) throw StageError{W1_ERANGE};  // one workgroup per bin in the NN search
@@ -312,8 +330,9 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       er_vec.resize((size_t)K);
       er = er_vec.data();
     }
-    readback(c, P.L, L_only, K);
-    readback(c, P.err, er, K);
+    check(c, hipMemcpyAsync(L_only, P.L, (size_t)K * 8, hipMemcpyDeviceToHost, st));
+    check(c, hipMemcpyAsync(er, P.err, (size_t)K * 4, hipMemcpyDeviceToHost, st));
+    check(c, hipStreamSynchronize(st));
     for (int64_t p = 0; p < K; ++p)
       if (er[p] == -1) L_only[p] = NAN;
     return W1_OK;
@@ -362,10 +381,9 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       acc += nc[(size_t)p];
       maxnp = std::max<int64_t>(maxnp, nc[(size_t)p]);
     }
-    upload(c, P.cell_start, cs.data(), (size_t)K * 8);
     std::vector<int32_t> cap((size_t)K);
     for (int64_t p = 0; p < K; ++p) cap[(size_t)p] = pair_work_cap(nc[(size_t)p], c.tun.work_cap);
-    upload(c, need<int32_t>(c, c.pcap, K), cap.data(), (size_t)K * 4);
+    upload_all(c, {{P.cell_start, cs.data(), (size_t)K * 8}, {need<int32_t>(c, c.pcap, K), cap.data(), (size_t)K * 4}});
     check(c, hipGetLastError());
   }
   record(c, 3);
@@ -501,18 +519,18 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       }
       cst[(size_t)K] = (int32_t)nch;
       if (!worklist_chunks_fit(nch)) throw StageError{W1_EOVERFLOW};
-      upload(c, P.item_start, ist.data(), (size_t)K * 8);
       int32_t* cstd = need<int32_t>(c, c.cid, K + 1);
-      upload(c, cstd, cst.data(), (size_t)(K + 1) * 4);
+      int32_t hr[9];
+      for (int x = 0; x <= 8; ++x) hr[x] = (int32_t)((nch * x) / 8);
+      int32_t* xr = need<int32_t>(c, c.xrange, 16);
+      upload_all(c, {{P.item_start, ist.data(), (size_t)K * 8},
+                     {cstd, cst.data(), (size_t)(K + 1) * 4},
+                     {xr, hr, sizeof(hr)}});
       trace(c, "chunks", nch);
       int32_t* cf = need<int32_t>(c, c.cfirst, nch);
       int32_t* ce = need<int32_t>(c, c.cend, nch);
       int32_t* cp = need<int32_t>(c, c.cpairs, nch);
       launch_chunks(cstd, K, P.item_start, ipp, nch, tun.chunk_items, cf, ce, cp, st);
-      int32_t hr[9];
-      for (int x = 0; x <= 8; ++x) hr[x] = (int32_t)((nch * x) / 8);
-      int32_t* xr = need<int32_t>(c, c.xrange, 16);
-      upload(c, xr, hr, sizeof(hr));
       uint32_t* xc = need<uint32_t>(c, c.xctr, 16);
       uint64_t* ccnt = need<uint64_t>(c, c.ccnt, nch);
       uint64_t* coff = need<uint64_t>(c, c.coff, nch);
@@ -731,8 +749,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       if (acc != 2 * (uint64_t)Ptot || ntiles >= (int64_t(1) << 31)) throw StageError{W1_EOVERFLOW};
       uint64_t* dbs = need<uint64_t>(c, c.bstart, NB + 1);
       int64_t* dtf = need<int64_t>(c, c.tfirst, NB + 1);
-      upload(c, dbs, hbs.data(), (size_t)(NB + 1) * 8);
-      upload(c, dtf, htf.data(), (size_t)(NB + 1) * 8);
+      upload_all(c, {{dbs, hbs.data(), (size_t)(NB + 1) * 8}, {dtf, htf.data(), (size_t)(NB + 1) * 8}});
       bstart = dbs;
       tfirst = dtf;
       uint64_t* bcur = need<uint64_t>(c, c.bcur, NB);
@@ -772,8 +789,11 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       uint64_t* xm = need<uint64_t>(c, c.pxmax, K);
       fill_u64(xm, 0, K, st);
       launch_pair_xmax(cp, cij, N, xm, st);
-      std::vector<uint64_t> hx = fetch_pairs(c, xm, K);
-      std::vector<int64_t> hna = fetch_pairs(c, P.nA, K), hnb = fetch_pairs(c, P.nB, K);
+      std::vector<uint64_t> hx((size_t)K);
+      std::vector<int64_t> hna((size_t)K), hnb((size_t)K);
+      check(c, hipMemcpyAsync(hna.data(), P.nA, (size_t)K * 8, hipMemcpyDeviceToHost, st));
+      check(c, hipMemcpyAsync(hnb.data(), P.nB, (size_t)K * 8, hipMemcpyDeviceToHost, st));
+      readback(c, xm, hx.data(), K);
       std::vector<int32_t> hk((size_t)K);
       for (int64_t p = 0; p < K; ++p) {
         const int64_t k = std::min<int64_t>(
@@ -797,15 +817,21 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     launch_csr_pair_arcs(P.cell_start, off, K, NR, parc, st);
     check(c, hipEventRecord(c.kev[10], st));
     check(c, hipGetLastError());
-    h_parc.resize((size_t)K + 1);
-    readback(c, parc, h_parc.data(), K + 1);
+    h_parc.resize((size_t)K + 1);  // read with the per-pair arrays below
+    check(c, hipMemcpyAsync(h_parc.data(), parc, (size_t)(K + 1) * 8, hipMemcpyDeviceToHost, st));
+  }
+  record(c, 6);
+  // the arcs per pair, the traversal's overflow flag and every per-pair
+  // array: one wait
+  std::vector<char> hpb((size_t)c.pair_bytes);
+  check(c, hipMemcpyAsync(c.hpin, derr, 4, hipMemcpyDeviceToHost, st));
+  readback(c, (const char*)c.pairs.p, hpb.data(), c.pair_bytes);
+  int32_t herr = 0;
+  std::memcpy(&herr, c.hpin, 4);
+  if (!h_parc.empty()) {
     Mtot = (int64_t)h_parc[(size_t)K];
     trace(c, "network arcs", Mtot);
   }
-  record(c, 6);
-  check(c, hipStreamSynchronize(st));
-  int32_t herr = 0;
-  readback(c, derr, &herr, 1);
   if (timed) {
     float a = 0, b2 = 0, d = 0;
     (void)hipEventElapsedTime(&a, c.kev[0], c.kev[1]);
@@ -827,15 +853,12 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
   if (herr) throw StageError{W1_EOVERFLOW};
 
   // ------------------------------------------------------------ results --
-  std::vector<int32_t> h_err = fetch_pairs(c, P.err, K), h_locA = fetch_pairs(c, P.locA, K),
-                       h_locB = fetch_pairs(c, P.locB, K), h_e = fetch_pairs(c, P.e, K),
-                       h_nc = fetch_pairs(c, P.ncells, K), h_FA = fetch_pairs(c, P.FA, K),
-                       h_FB = fetch_pairs(c, P.FB, K);
-  std::vector<int64_t> h_nA = fetch_pairs(c, P.nA, K), h_nB = fetch_pairs(c, P.nB, K),
-                       h_cs = fetch_pairs(c, P.cell_start, K);
-  std::vector<uint64_t> h_sA = fetch_pairs(c, P.sumA, K), h_sB = fetch_pairs(c, P.sumB, K),
-                        h_np = fetch_pairs(c, P.npairs, K);
-  std::vector<double> h_L = fetch_pairs(c, P.L, K);
+  auto host = [&](const auto* dev) { return from_pair_block(c, hpb, dev, K); };
+  std::vector<int32_t> h_err = host(P.err), h_locA = host(P.locA), h_locB = host(P.locB), h_e = host(P.e),
+                       h_nc = host(P.ncells), h_FA = host(P.FA), h_FB = host(P.FB);
+  std::vector<int64_t> h_nA = host(P.nA), h_nB = host(P.nB), h_cs = host(P.cell_start);
+  std::vector<uint64_t> h_sA = host(P.sumA), h_sB = host(P.sumB), h_np = host(P.npairs);
+  std::vector<double> h_L = host(P.L);
   float tms[8] = {0};
   for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&tms[i], c.ev[i], c.ev[i + 1]);
   c.h_cell_start.assign(h_cs.begin(), h_cs.end());
