@@ -340,6 +340,16 @@ typedef struct {
                               /* of 4096 records (0 = as sized); when they */
                               /* run out the pass is redone with every     */
                               /* chunk counted first (same result)         */
+  int32_t fused_expand_cells; /* launch groups of at most this many cells  */
+                              /* (0..65536) expand their WSPD work list in */
+                              /* one workgroup, with no host wait between  */
+                              /* rounds; 0 = always round by round.  The   */
+                              /* work list is the same either way.         */
+                              /* Default 4096                              */
+  int32_t fused_expand_items; /* room of that expansion, in work-list items */
+                              /* kept and per frontier (0 = 64 n_cells +   */
+                              /* 4096 kept, 16 n_cells + 4096 frontier);   */
+                              /* out of room, the rounds run one by one    */
 } w1_tuning;
 
 int w1_ctx_get_tuning(const w1_ctx *ctx, w1_tuning *out);
@@ -354,8 +364,10 @@ int w1_ctx_set_tuning(w1_ctx *ctx, const w1_tuning *t);
  * passes that sort the network into rows: [5] bucket scatter, [6] row
  * histogram, [7] row scatter (with the degree scan before it), [8] row sort
  * (with the diagonal rows and row pointers); [9] the blocks the blocked
- * emission filled (0: counted layout).  n is the capacity of ms (>= 4);
- * entries beyond 9 are 0. */
+ * emission filled (0: counted layout); [10] how the work list was expanded:
+ * 1 in one workgroup, -1 tried so but out of room (then round by round),
+ * 0 round by round.  n is the capacity of ms (>= 4); entries beyond 10
+ * are 0. */
 int w1_ctx_last_kernel_times(const w1_ctx *ctx, double *ms, int n);
 
 /* Host network simplex on any uncapacitated network with non-negative integer

@@ -82,7 +82,8 @@ class _Tuning(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("max_points_per_launch", ctypes.c_int64),
                 ("compact_records", ctypes.c_int32), ("stream_max_rounds", ctypes.c_int32),
                 ("stream_arena_pairs", ctypes.c_int64), ("blocked_emit", ctypes.c_int32),
-                ("sort_window_words", ctypes.c_int32), ("emit_block_limit", ctypes.c_int64)]
+                ("sort_window_words", ctypes.c_int32), ("emit_block_limit", ctypes.c_int64),
+                ("fused_expand_cells", ctypes.c_int32), ("fused_expand_items", ctypes.c_int32)]
 
 
 class _NNParams(ctypes.Structure):
@@ -414,7 +415,7 @@ class Context:
             raise W1Error(rc, "w1_ctx_set_tuning")
 
     KERNEL_TIMES = ("worklist_ms", "count_ms", "emit_ms", "pairs", "stream_emit_ms", "bucket_scatter_ms",
-                    "row_hist_ms", "row_scatter_ms", "row_sort_ms", "emit_blocks")
+                    "row_hist_ms", "row_scatter_ms", "row_sort_ms", "emit_blocks", "fused_expand")
 
     def kernel_times(self) -> dict:
         """HIP-event times (ms) of the last call's WSPD and network kernels."""

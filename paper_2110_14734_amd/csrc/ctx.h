@@ -40,7 +40,7 @@ constexpr int64_t kNoAllocMaxPairs = 1024;
 // w1_ctx_last_kernel_times: work list, count pass, emit pass, pairs emitted,
 // then the network passes: bucket histogram, bucket scatter, row histogram,
 // row scatter (with the degree scan), row sort (with the diagonal rows).
-constexpr int kNumKernelTimes = 10;
+constexpr int kNumKernelTimes = 11;
 
 // Blocked emission of a single pair's network: used from this many
 // work-list chunks on, sized by a count over every kSampleStride-th chunk.
@@ -58,6 +58,8 @@ struct Ctx {
   int64_t max_points = int64_t(1) << 22;  // points per launch group of a batch
   int64_t stream_arena = 0;                // streamed emission: arena capacity in pair records (0 = off)
   int32_t stream_rounds = 0;               // streamed emission: arena fills at most (0 = all)
+  int32_t fused_expand_cells = 4096;       // work-list expansion in one workgroup up to this many cells
+  int32_t fused_expand_items = 0;          // its room in items (0: from the cell count)
   int32_t blocked_emit = 0;                // network path: blocked emission (off by default)
   int64_t emit_block_limit = 0;            // blocked emission: block cap (0 = as sized)
   int32_t sort_window = 0;                 // row sort bitmap window in words (0 = automatic)
@@ -72,7 +74,7 @@ struct Ctx {
   // cells / tree
   DBuf ckey, cpair, cij, ca, cb, iaux, ibox, iheight, iparent, ndepth, inode, rmap, isplit;
   // wspd
-  DBuf itemsA, itemsB, itemsI, itemsS, icnt, ipos, ipp, cid, pcap, cfirst, cend, cpairs, ccnt, coff, xrange, xctr, err;
+  DBuf itemsA, itemsB, itemsX, itemsI, itemsS, icnt, ipos, ipp, cid, pcap, cfirst, cend, cpairs, ccnt, coff, xrange, xctr, err;
   // network: pu holds the 12-byte WSPD pair records (u, v, cost) and later
   // the unsorted row heads; l1 the bucket-major arc entries and later the
   // sorted heads (col); costb the arc costs; rp the per-pair row pointers
@@ -107,7 +109,7 @@ struct Ctx {
     DBuf* list[] = {&stage, &orpart, &segs, &pb, &pd, &psd, &kw0, &kw1, &kw2, &kA, &kB, &vA, &vB, &head, &idx, &scantmp, &sorttmp,
                     &small, &gb, &gd, &gpair, &gw, &lb, &ld, &lw, &lpair, &lt, &lterm, &lbin, &li, &lj, &nbuck,
                     &bincnt, &binstart, &ent, &entl, &ckey, &cpair, &cij, &ca, &cb, &iaux, &ibox, &iheight, &iparent,
-                    &ndepth, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsI, &itemsS, &icnt, &ipos, &ipp, &cid, &pcap,
+                    &ndepth, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsX, &itemsI, &itemsS, &icnt, &ipos, &ipp, &cid, &pcap,
                     &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &l1, &costb, &rp,
                     &supply, &rstart, &bcnt, &bstart, &tfirst, &bcur, &rowcnt, &rowcur, &bflag, &bpos, &deg, &off,
                     &parc, &csum, &pxmax, &pairs};

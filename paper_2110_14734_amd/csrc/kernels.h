@@ -191,6 +191,14 @@ void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s
                           const int32_t* pair_cap, bool prune, bool l2, uint64_t* cnt, hipStream_t st);
 void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const uint64_t* cnt, const uint64_t* pos,
                          int2* out_items, int64_t out_base, bool l2, int2* next, hipStream_t st);
+// All expansion rounds of a small work list in one workgroup, starting from
+// the f0 items at `roots` (left unchanged): kept items go to kept[0, ctl[0]),
+// the frontiers alternate between fa and fb (cap_front items each).
+// ctl[1] = 0 done, 1 out of room (nothing usable), 2 more than max_rounds
+// rounds.  The work list equals the round-by-round one.
+void launch_wspd_expand_small(const TreeView& T, const int2* roots, int64_t f0, int s, const WspdTuning& tun,
+                              const int32_t* pair_cap, bool prune, bool l2, int max_rounds, int2* kept,
+                              int64_t cap_kept, int2* fa, int2* fb, int64_t cap_front, int64_t* ctl, hipStream_t st);
 void launch_item_keys(const TreeView& T, const int2* items, int64_t m, bool both, uint64_t* keys, hipStream_t st);
 void launch_gather_items(const int2* src, const uint32_t* perm, int2* dst, int64_t m, hipStream_t st);
 // Per-pair item runs of the sorted work list (keys: first representative

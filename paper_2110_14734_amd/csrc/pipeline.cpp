@@ -36,6 +36,9 @@ inline int bitlen_u64(uint64_t x) { return 64 - clz64(x); }
 inline int ctz64(uint64_t x) { return x ? __builtin_ctzll(x) : 64; }
 
 constexpr int kSortMaxWords = 3;
+// Largest launch group (in cells) whose work list may be expanded in one
+// workgroup (k_expand_small) rather than round by round.
+constexpr int32_t kFusedExpandMaxCells = 65536;
 
 // Stable sort of n elements by the words (least significant first); returns
 // the permutation in *perm and the sorted most significant word in *top.
@@ -440,6 +443,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
   std::vector<int64_t> stream_n;        // per pair: pairs streamed
   std::vector<uint64_t> stream_chk;     // per pair: checksum of the streamed records
   bool timed = false, emitted = false;
+  int fused = 0;  // work list: 0 round by round, 1 in one workgroup, -1 out of room there
   int32_t* derr = need<int32_t>(c, c.err, 64);
   fill_u32((uint32_t*)derr, 0, 1, st);
   if (N >= 2) {
@@ -466,8 +470,34 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     int2* I = need<int2>(c, c.itemsI, std::max<int64_t>(f, 1024));
     check(c, hipEventRecord(c.kev[0], st));
     trace(c, "root items", f);
+    constexpr int kMaxRounds = 4 * 64 + 8;  // deeper than two 64-bit key trees
+    if (f > 0 && N <= c.fused_expand_cells) {
+      fused = -1;
+      // a small launch group: every round in one workgroup, one wait; if its
+      // buffers run out, the rounds below run one by one from the roots
+      const int64_t capk = c.fused_expand_items > 0 ? c.fused_expand_items : 64 * N + 4096;
+      const int64_t capf = c.fused_expand_items > 0 ? c.fused_expand_items : 16 * N + 4096;
+      int2* kept = need<int2>(c, c.itemsI, capk);
+      int2* fa = need<int2>(c, c.itemsB, capf);
+      int2* fb = need<int2>(c, c.itemsX, capf);
+      int64_t* ctl = (int64_t*)need<uint64_t>(c, c.small, 64) + 16;
+      launch_wspd_expand_small(T, F, f, s, tun, (const int32_t*)c.pcap.p, prune, l2, kMaxRounds, kept, capk, fa, fb,
+                               capf, ctl, st);
+      check(c, hipGetLastError());
+      readback(c, ctl, (int64_t*)c.hpin, 2);
+      const int64_t got = (int64_t)c.hpin[0], status = (int64_t)c.hpin[1];
+      if (status == 2) throw StageError{W1_EOVERFLOW};
+      trace(c, "fused expansion (0 done, 1 out of room)", status);
+      I = kept;  // the same buffer the rounds below fill on a fallback
+      if (status == 0) {
+        fused = 1;
+        isz = got;
+        f = 0;
+        trace(c, "  kept items", isz);
+      }
+    }
     for (int round = 0; f > 0; ++round) {
-      if (round > 4 * 64 + 8) throw StageError{W1_EOVERFLOW};  // deeper than two 64-bit key trees
+      if (round > kMaxRounds) throw StageError{W1_EOVERFLOW};
       if (!worklist_round_fits(f)) throw StageError{W1_EOVERFLOW};
       uint64_t* cnt = need<uint64_t>(c, c.icnt, f);
       uint64_t* pos = need<uint64_t>(c, c.ipos, f);
@@ -695,6 +725,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
   c.kms[3] = (double)Ptot;
   c.kms[4] = stream_ms;
   c.kms[9] = (double)c.emit_blocks;
+  c.kms[10] = (double)fused;
 
   // ---------------------------------------------------------------- a5 --
   // The network in compressed sparse row form, sorted by (tail, head)
@@ -1301,6 +1332,8 @@ int w1_ctx_get_tuning(const w1_ctx* c, w1_tuning* out) {
   out->blocked_emit = c->blocked_emit;
   out->sort_window_words = c->sort_window;
   out->emit_block_limit = c->emit_block_limit;
+  out->fused_expand_cells = c->fused_expand_cells;
+  out->fused_expand_items = c->fused_expand_items;
   return W1_OK;
 }
 
@@ -1310,7 +1343,8 @@ int w1_ctx_set_tuning(w1_ctx* c, const w1_tuning* t) {
       t->chunk_items < 1 || t->chunk_items > (1 << 20) || t->blocks_per_cu < 1 || t->blocks_per_cu > 16 ||
       t->max_points_per_launch < 1 || (t->compact_records != 0 && t->compact_records != 1) ||
       t->stream_max_rounds < 0 || t->stream_arena_pairs < 0 || t->stream_arena_pairs > (int64_t(1) << 36) ||
-      (t->blocked_emit != 0 && t->blocked_emit != 1) || t->sort_window_words < 0 || t->emit_block_limit < 0)
+      (t->blocked_emit != 0 && t->blocked_emit != 1) || t->sort_window_words < 0 || t->emit_block_limit < 0 ||
+      t->fused_expand_cells < 0 || t->fused_expand_cells > kFusedExpandMaxCells || t->fused_expand_items < 0)
     return W1_EINVAL;
   c->tun = WspdTuning{t->stack_depth, t->work_cap, t->chunk_items, t->blocks_per_cu, t->compact_records};
   c->max_points = t->max_points_per_launch;
@@ -1319,6 +1353,8 @@ int w1_ctx_set_tuning(w1_ctx* c, const w1_tuning* t) {
   c->blocked_emit = t->blocked_emit;
   c->emit_block_limit = t->emit_block_limit;
   c->sort_window = t->sort_window_words;
+  c->fused_expand_cells = t->fused_expand_cells;
+  c->fused_expand_items = t->fused_expand_items;
   return W1_OK;
 }
 

@@ -118,24 +118,43 @@ __global__ void k_roots_fill(TreeView T, const uint32_t* __restrict__ flag, cons
   items[pos[w]] = make_int2(a.x, a.y);
 }
 
-// Item kinds of an expansion round: kept (final or separated) -> low word
-// count 1; expanded -> high word count 2; dropped (diagonal-dominated, with
-// pruning on) -> 0.
+// Item kinds of an expansion round: 0 dropped (diagonal-dominated, with
+// pruning on), 1 kept (final: separated, or small enough for the traversal),
+// 2 expanded (the node with the larger diameter is split in two).
+__device__ inline uint32_t item_kind(const TreeView& T, int2 it, int4 bu, int4 bv, int s, int stack_depth,
+                                     const int32_t* __restrict__ pair_cap, int prune, int l2) {
+  if (prune && dominated(bu, bv)) return 0;
+  const int64_t work_cap = pair_cap[T.cpair[node_rep(T, it.x)]];
+  const bool small = node_height(T, it.x) + node_height(T, it.y) <= stack_depth - 1 &&
+                     node_size(T, it.x) * node_size(T, it.y) <= work_cap;
+  const bool keep = small || (l2 ? separated_m<true>(bu, bv, s) : separated_m<false>(bu, bv, s));
+  return keep ? 1u : 2u;
+}
+
+// The two children of an expanded item, at next[q] and next[q + 1].
+__device__ inline void expand_item(const TreeView& T, int2 it, int4 bu, int4 bv, int l2, int2* __restrict__ next,
+                                   int64_t q) {
+  if (l2 ? split_first<true>(bu, bv) : split_first<false>(bu, bv)) {
+    const int4 a = T.iaux[it.x];
+    next[q] = make_int2(a.x, it.y);
+    next[q + 1] = make_int2(a.y, it.y);
+  } else {
+    const int4 a = T.iaux[it.y];
+    next[q] = make_int2(it.x, a.x);
+    next[q + 1] = make_int2(it.x, a.y);
+  }
+}
+
+// One expansion round, counted: kept -> low word 1; expanded -> high word 2
+// (its children); dropped -> 0.  The exclusive scan of these counts places
+// every kept item and every child (k_scatter).
 __global__ void k_classify(TreeView T, const int2* __restrict__ items, int64_t f, int s, int stack_depth,
                            const int32_t* __restrict__ pair_cap, int prune, int l2, uint64_t* __restrict__ cnt) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= f) return;
   const int2 it = items[x];
-  const int4 bu = node_box(T, it.x), bv = node_box(T, it.y);
-  if (prune && dominated(bu, bv)) {
-    cnt[x] = 0;
-    return;
-  }
-  const int64_t work_cap = pair_cap[T.cpair[node_rep(T, it.x)]];
-  const bool small = node_height(T, it.x) + node_height(T, it.y) <= stack_depth - 1 &&
-                     node_size(T, it.x) * node_size(T, it.y) <= work_cap;
-  const bool keep = small || (l2 ? separated_m<true>(bu, bv, s) : separated_m<false>(bu, bv, s));
-  cnt[x] = keep ? 1ull : (2ull << 32);
+  const uint32_t kind = item_kind(T, it, node_box(T, it.x), node_box(T, it.y), s, stack_depth, pair_cap, prune, l2);
+  cnt[x] = kind == 1 ? 1ull : kind == 2 ? (2ull << 32) : 0ull;
 }
 
 __global__ void k_scatter(TreeView T, const int2* __restrict__ items, int64_t f, const uint64_t* __restrict__ cnt,
@@ -150,16 +169,82 @@ __global__ void k_scatter(TreeView T, const int2* __restrict__ items, int64_t f,
     out_items[out_base + (int64_t)(uint32_t)p] = it;
     return;
   }
-  const int64_t q = (int64_t)(p >> 32);
-  const int4 bu = node_box(T, it.x), bv = node_box(T, it.y);
-  if (l2 ? split_first<true>(bu, bv) : split_first<false>(bu, bv)) {
-    const int4 a = T.iaux[it.x];
-    next[q] = make_int2(a.x, it.y);
-    next[q + 1] = make_int2(a.y, it.y);
-  } else {
-    const int4 a = T.iaux[it.y];
-    next[q] = make_int2(it.x, a.x);
-    next[q + 1] = make_int2(it.x, a.y);
+  expand_item(T, it, node_box(T, it.x), node_box(T, it.y), l2, next, (int64_t)(p >> 32));
+}
+
+// Every expansion round of a small work list in one workgroup, so the host
+// does not wait between rounds.  Tile by tile of XB items, in item order, the
+// same exclusive scan of the same counts as k_classify / k_scatter places
+// the kept items (appended to `kept`) and the children (the next frontier),
+// so the work list is identical to the round-by-round one.  The frontiers
+// alternate between fa and fb; the roots are only read, so the caller can
+// run the rounds one by one from them when this kernel runs out of room.
+// ctl[0]: items kept; ctl[1]: 0 done, 1 out of room, 2 more rounds than
+// max_rounds.
+constexpr int XB = 1024;
+__global__ void __launch_bounds__(XB) k_expand_small(TreeView T, const int2* __restrict__ roots, int64_t f0, int s,
+                                                     int stack_depth, const int32_t* __restrict__ pair_cap, int prune,
+                                                     int l2, int max_rounds, int2* __restrict__ kept_out,
+                                                     int64_t cap_kept, int2* fa, int2* fb, int64_t cap_front,
+                                                     int64_t* __restrict__ ctl) {
+  __shared__ uint64_t s_w[XB / WAVE];
+  const int lane = lane_id(), wave = threadIdx.x / WAVE;
+  const int2* src = roots;
+  int2* dst = fa;
+  int64_t f = f0, kept = 0;
+  int status = 0;  // block-uniform
+  for (int round = 0; f > 0 && status == 0; ++round) {
+    if (round > max_rounds) {
+      status = 2;
+      break;
+    }
+    int64_t grown = 0;
+    for (int64_t b0 = 0; b0 < f; b0 += XB) {
+      const int64_t x = b0 + threadIdx.x;
+      int2 it = make_int2(0, 0);
+      int4 bu = make_int4(0, 0, 0, 0), bv = bu;
+      uint32_t kind = 0;
+      if (x < f) {
+        it = src[x];
+        bu = node_box(T, it.x);
+        bv = node_box(T, it.y);
+        kind = item_kind(T, it, bu, bv, s, stack_depth, pair_cap, prune, l2);
+      }
+      const uint64_t v = kind == 1 ? 1ull : kind == 2 ? (2ull << 32) : 0ull;
+      uint64_t inc = v;
+#pragma unroll
+      for (int d = 1; d < WAVE; d <<= 1) {
+        const uint64_t o = __shfl_up(inc, d);
+        if (lane >= d) inc += o;
+      }
+      if (lane == WAVE - 1) s_w[wave] = inc;
+      __syncthreads();
+      uint64_t pre = 0, tot = 0;
+      for (int w = 0; w < XB / WAVE; ++w) {
+        const uint64_t t = s_w[w];
+        if (w < wave) pre += t;
+        tot += t;
+      }
+      __syncthreads();  // s_w is rewritten by the next tile
+      const int64_t tk = (int64_t)(uint32_t)tot, tg = (int64_t)(tot >> 32);
+      if (kept + tk > cap_kept || grown + tg > cap_front) {
+        status = 1;
+        break;
+      }
+      const uint64_t ex = pre + inc - v;
+      if (kind == 1) kept_out[kept + (int64_t)(uint32_t)ex] = it;
+      else if (kind == 2) expand_item(T, it, bu, bv, l2, dst, grown + (int64_t)(ex >> 32));
+      kept += tk;
+      grown += tg;
+    }
+    __syncthreads();  // the children written this round are read by other threads next round
+    src = dst;
+    dst = dst == fa ? fb : fa;
+    f = grown;
+  }
+  if (threadIdx.x == 0) {
+    ctl[0] = kept;
+    ctl[1] = status;
   }
 }
 
@@ -657,6 +742,12 @@ void launch_wspd_classify(const TreeView& T, const int2* items, int64_t f, int s
 void launch_wspd_scatter(const TreeView& T, const int2* items, int64_t f, const uint64_t* cnt, const uint64_t* pos,
                          int2* out_items, int64_t out_base, bool l2, int2* next, hipStream_t st) {
   LAUNCH(k_scatter, f, T, items, f, cnt, pos, out_items, out_base, l2 ? 1 : 0, next);
+}
+void launch_wspd_expand_small(const TreeView& T, const int2* roots, int64_t f0, int s, const WspdTuning& tun,
+                              const int32_t* pair_cap, bool prune, bool l2, int max_rounds, int2* kept,
+                              int64_t cap_kept, int2* fa, int2* fb, int64_t cap_front, int64_t* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_expand_small, dim3(1), dim3(XB), 0, st, T, roots, f0, s, tun.stack_depth, pair_cap,
+                     prune ? 1 : 0, l2 ? 1 : 0, max_rounds, kept, cap_kept, fa, fb, cap_front, ctl);
 }
 void launch_item_keys(const TreeView& T, const int2* items, int64_t m, bool both, uint64_t* keys, hipStream_t st) {
   LAUNCH(k_item_keys, m, T, items, m, both ? 1 : 0, keys);

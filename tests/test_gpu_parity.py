@@ -245,6 +245,60 @@ def test_paper_grid(orc, ctx, s_override, l2):
     assert e.value.code == w1.W1_EINVAL
 
 
+def test_fused_expansion(orc, ctx):
+    """The work list expanded in one workgroup, round by round, and in one
+    workgroup that runs out of room (then round by round from the roots)
+    gives the same WSPD pairs, network and W1, for single pairs (also at
+    s = 1 and 3, Euclidean, pruned, on the paper's grid) and for a batch
+    expanded in one workgroup; one fused case against the oracle too."""
+    import paper_2110_14734_amd as w1
+
+    _say("[gpu] fused work-list expansion")
+    t0 = ctx.tuning
+    configs = ((dict(fused_expand_cells=0), 0), (dict(fused_expand_cells=65536), 1),
+               (dict(fused_expand_cells=65536, fused_expand_items=64), -1))
+    A, B = pdsynth.exp_pd(300, 40), pdsynth.exp_pd(280, 41)
+    single = [(A, B, dict(eps=0.1)), (A, B, dict(eps=0.1, s_override=1)), (A, B, dict(eps=0.1, s_override=3)),
+              (A, B, dict(eps=0.1, flags=w1.METRIC_L2)), (A, B, dict(eps=0.1, flags=w1.PRUNE)),
+              (A, B, dict(eps=0.1, s_override=20, flags=w1.PAPER_GRID))]
+    for name, make, eps in cases.STAGE_CASES:
+        X, Y = make()
+        single.append((X, Y, dict(eps=eps)))
+    try:
+        for case, (X, Y, kw) in enumerate(single):
+            kw = dict(kw)
+            fl = kw.pop("flags", 0) | w1.KEEP_NETWORK | w1.NO_FLOW
+            out = []
+            for cfg, want in configs:
+                ctx.tuning = dict(t0, **cfg)
+                g = ctx.approx(X, Y, flags=fl, **kw)
+                if g.n_cells >= 2:
+                    got = ctx.kernel_times()["fused_expand"]
+                    # the default room may run out on the larger stage cases
+                    assert got == want or (want == 1 and case >= 6 and got == -1)
+                out.append(g)
+            for g in out[1:]:
+                assert (g.n_pairs, g.lower_bound, g.n_arcs) == (out[0].n_pairs, out[0].lower_bound, out[0].n_arcs)
+                assert same_network(g, out[0])
+        As, Bs = cases.batch_pairs()
+        res = []
+        for cfg, want in ((dict(fused_expand_cells=0), 0),
+                          (dict(fused_expand_cells=65536, fused_expand_items=1 << 23), 1)):
+            ctx.tuning = dict(t0, **cfg)
+            res.append(ctx.approx_batch(As, Bs, eps=0.2, flags=w1.KEEP_NETWORK | w1.NO_FLOW))
+            assert ctx.kernel_times()["fused_expand"] == want
+        for a, b in zip(*res):
+            assert a.n_pairs == b.n_pairs and same_network(a, b)
+        ctx.tuning = dict(t0, fused_expand_cells=65536)
+        compare(orc, ctx, *cases.STAGE_CASES[2][1](), eps=cases.STAGE_CASES[2][2], flow=False)
+        assert ctx.kernel_times()["fused_expand"] == 1
+        for bad in (dict(fused_expand_cells=-1), dict(fused_expand_cells=65537), dict(fused_expand_items=-1)):
+            with pytest.raises(w1.W1Error):
+                ctx.tuning = dict(t0, **bad)
+    finally:
+        ctx.tuning = t0
+
+
 def test_edge_cases(orc, ctx):
     _say("[gpu] edge cases")
     import paper_2110_14734_amd as w1
