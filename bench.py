@@ -28,17 +28,22 @@ if ROOT not in sys.path:
 METRIC = "PD pairs/sec (approx W1 at eps) + sparsify pts/s & HBM GB/s frac; 1-NN q/s"
 HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes of the WSPD and network kernels, per WSPD pair (both
-# arcs of a pair) and per cell:
-#   emit          writes the 12-byte pair record (u32 u, u32 v, i32 cost) and
-#                 counts both arcs per tail bucket in LDS;
+# arcs of a pair) and per cell, for pair records of w words (w = 2: u32 u,
+# u32 v; w = 3: also i32 cost):
+#   emit          writes the 4w-byte pair record and counts both arcs per
+#                 tail bucket in LDS;
 #   bucket_scatter reads the record, writes two 4-byte bucket entries;
 #   row_hist      reads the two entries;
 #   row_scatter   reads the two entries, writes two 4-byte row heads;
 #   row_sort      reads the two heads, writes two (u32 head, i32 cost) arcs
 #                 of the final rows and an int64 row pointer per cell.
 # The final network alone is 16 B per pair and 8 B per cell.
-KERNEL_BYTES = {"emit_ms": (12, 0), "bucket_scatter_ms": (20, 0),
-                "row_hist_ms": (8, 0), "row_scatter_ms": (16, 0), "row_sort_ms": (24, 8)}
+def kernel_bytes(w):
+    return {"emit_ms": (4 * w, 0), "bucket_scatter_ms": (4 * w + 8, 0),
+            "row_hist_ms": (8, 0), "row_scatter_ms": (16, 0), "row_sort_ms": (24, 8)}
+
+
+KERNEL_BYTES = kernel_bytes(2)
 NETWORK_BYTES = (16, 8)
 KERNEL_NAMES = {"emit_ms": "k_wspd<emit> (WSPD pair records)",
                 "bucket_scatter_ms": "k_bucket_scatter", "row_hist_ms": "k_row_hist",
@@ -434,7 +439,7 @@ def main():
         ctx.approx(tA, tB, eps=args.eps, flags=flags)
     torch.cuda.synchronize()
     stage = {k: 0.0 for k in w1.T_NAMES[:6]}
-    kern = {k: 0.0 for k in w1.Context.KERNEL_TIMES if k not in ("pairs", "stream_emit_ms")}
+    kern = {k: 0.0 for k in w1.Context.KERNEL_TIMES if k not in ("pairs", "stream_emit_ms", "record_words")}
     r = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -450,7 +455,8 @@ def main():
     n = A.shape[0] + B.shape[0]
     P, N = r.n_pairs, r.n_cells
     kernels = {}
-    for k, (bp, bn) in KERNEL_BYTES.items():
+    rec_words = ctx.kernel_times()["record_words"]
+    for k, (bp, bn) in kernel_bytes(rec_words).items():
         nbytes = bp * P + bn * N
         ach = nbytes / (kern[k] * 1e-3) / 1e9 if kern[k] > 0 else 0.0
         kernels[k] = {"kernel": KERNEL_NAMES[k], "avg_launch_ms": round(kern[k], 4), "algorithmic_bytes": nbytes,
@@ -498,6 +504,7 @@ def main():
             "avg_launch_ms": d["avg_launch_ms"],
         },
         "kernels": kernels,
+        "pair_record_bytes": 4 * rec_words,
         "network_roofline": {
             "what": "a4+a5 stage time against the final network's bytes (16 B per WSPD pair, 8 B per cell)",
             "bytes": net_bytes, "ms": round(a45_ms, 3),

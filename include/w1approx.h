@@ -366,8 +366,9 @@ int w1_ctx_set_tuning(w1_ctx *ctx, const w1_tuning *t);
  * (with the diagonal rows and row pointers); [9] the blocks the blocked
  * emission filled (0: counted layout); [10] how the work list was expanded:
  * 1 in one workgroup, -1 tried so but out of room (then round by round),
- * 0 round by round.  n is the capacity of ms (>= 4); entries beyond 10
- * are 0. */
+ * 0 round by round; [11] the words per pair record the emit pass wrote
+ * for the network: 2 (u, v), 3 (u, v, cost), 0 when nothing was emitted.
+ * n is the capacity of ms (>= 4); entries beyond 11 are 0. */
 int w1_ctx_last_kernel_times(const w1_ctx *ctx, double *ms, int n);
 
 /* Host network simplex on any uncapacitated network with non-negative integer

@@ -415,7 +415,7 @@ class Context:
             raise W1Error(rc, "w1_ctx_set_tuning")
 
     KERNEL_TIMES = ("worklist_ms", "count_ms", "emit_ms", "pairs", "stream_emit_ms", "bucket_scatter_ms",
-                    "row_hist_ms", "row_scatter_ms", "row_sort_ms", "emit_blocks", "fused_expand")
+                    "row_hist_ms", "row_scatter_ms", "row_sort_ms", "emit_blocks", "fused_expand", "record_words")
 
     def kernel_times(self) -> dict:
         """HIP-event times (ms) of the last call's WSPD and network kernels."""
@@ -427,6 +427,7 @@ class Context:
         d = {k: out[i] for i, k in enumerate(self.KERNEL_TIMES)}
         d["pairs"] = int(d["pairs"])
         d["emit_blocks"] = int(d["emit_blocks"])
+        d["record_words"] = int(d["record_words"])
         return d
 
     def device_network(self, k: int = 0) -> dict:

@@ -122,7 +122,15 @@ __device__ inline void lds_excl_scan(uint32_t* cnt, int n, uint32_t* s_tmp) {
 // (global) and entry.
 __device__ inline void record_arcs(const uint32_t* __restrict__ rec, uint64_t x, uint32_t rw, int64_t cs, int RB,
                                    int DB, uint32_t& b0, uint32_t& e0, uint32_t& b1, uint32_t& e1) {
-  const uint32_t u = rec[rw * x], v = rec[rw * x + 1];
+  uint32_t u, v;
+  if (rw == 2) {  // one 8-byte load
+    const uint2 r = ((const uint2*)rec)[x];
+    u = r.x;
+    v = r.y;
+  } else {
+    u = rec[rw * x];
+    v = rec[rw * x + 1];
+  }
   const uint64_t gu = (uint64_t)cs + u, gv = (uint64_t)cs + v;
   const uint32_t m = (1u << RB) - 1u;
   b0 = (uint32_t)(gu >> RB);
@@ -139,15 +147,17 @@ __global__ void __launch_bounds__(CB) k_bucket_scatter(const uint32_t* __restric
                                                        unsigned long long* __restrict__ bcur,
                                                        uint32_t* __restrict__ out,
                                                        const uint32_t* __restrict__ blk_fill,
-                                                       const uint32_t* __restrict__ blk_pair, uint32_t blk_recs) {
+                                                       const uint32_t* __restrict__ blk_pair, uint32_t blk_recs,
+                                                       uint32_t rw) {
   extern __shared__ uint32_t s_mem[];
   uint32_t* s_cnt = s_mem;                         // NB: counts, then prefixes
   int64_t* s_gofs = (int64_t*)(s_mem + ((NB + 1) & ~1));  // NB: global base - prefix
   uint32_t* s_ent = (uint32_t*)(s_gofs + NB);      // 2 PTILE staged entries
   uint16_t* s_bkt = (uint16_t*)(s_ent + 2 * PTILE);  // 2 PTILE bucket ids
   __shared__ uint32_t s_tmp[CB / WAVE];
-  // a tile: PTILE consecutive records (u, v, cost), or one block of the
-  // blocked emission (records (u, v); its fill and diagram pair given)
+  // a tile: PTILE consecutive records of rw words ((u, v) or (u, v, cost)),
+  // or one block of the blocked emission (records (u, v); its fill and
+  // diagram pair given)
   const uint64_t x0 = (uint64_t)blockIdx.x * (blk_fill ? blk_recs : (uint32_t)PTILE);
   const uint64_t x1 = blk_fill ? x0 + blk_fill[blockIdx.x] : min(P, x0 + PTILE);
   for (int b = threadIdx.x; b < NB; b += CB) s_cnt[b] = 0;
@@ -161,7 +171,7 @@ __global__ void __launch_bounds__(CB) k_bucket_scatter(const uint32_t* __restric
     const uint64_t x = x0 + (uint64_t)k * CB + threadIdx.x;
     if (x < x1) {
       const int64_t cs = cell_start[record_pair(tp, rstart, x)];
-      record_arcs(rec, x, blk_fill ? 2u : 3u, cs, RB, DB, eb[2 * k], ee[2 * k], eb[2 * k + 1], ee[2 * k + 1]);
+      record_arcs(rec, x, rw, cs, RB, DB, eb[2 * k], ee[2 * k], eb[2 * k + 1], ee[2 * k + 1]);
       er[2 * k] = atomicAdd(&s_cnt[eb[2 * k]], 1u);
       er[2 * k + 1] = atomicAdd(&s_cnt[eb[2 * k + 1]], 1u);
       n = 2 * k + 2;
@@ -660,17 +670,17 @@ size_t csr_row_scatter_lds(int RB) {
 int64_t csr_entry_tile(int RB) { return (int64_t)CB * csr_entries_per_thread(RB); }
 
 int csr_tile_records() { return PTILE; }
-void launch_csr_bucket_scatter(const uint32_t* rec, uint64_t P, const uint64_t* rstart, int64_t K,
+void launch_csr_bucket_scatter(const uint32_t* rec, int rec_words, uint64_t P, const uint64_t* rstart, int64_t K,
                                const int64_t* cell_start, int RB, int DB, int NB, const uint64_t* bstart,
                                uint64_t* bcur, uint32_t* out, const uint32_t* blk_fill, const uint32_t* blk_pair,
                                uint32_t blk_recs, uint32_t nblocks, hipStream_t st) {
-  if (P == 0) return;
+  if (P == 0 || (rec_words != 2 && rec_words != 3)) return;
   // blocked records: one tile per block, whose records must fit a tile
   if (blk_fill && (blk_recs == 0 || blk_recs > (uint32_t)PTILE || nblocks == 0)) return;
   const int64_t tiles = blk_fill ? (int64_t)nblocks : ceil_div((int64_t)P, PTILE);
   hipLaunchKernelGGL(k_bucket_scatter, dim3((unsigned)tiles), dim3(CB), csr_bucket_scatter_lds(NB), st, rec, P,
                      rstart, K, cell_start, RB, DB, NB, bstart, (unsigned long long*)bcur, out, blk_fill, blk_pair,
-                     blk_recs);
+                     blk_recs, blk_fill ? 2u : (uint32_t)rec_words);
 }
 void launch_csr_row_hist(const uint32_t* ent, const int64_t* tfirst, int64_t ntiles, int NB, const uint64_t* bstart,
                          int RB, int DB, int64_t N, uint32_t* rowcnt, hipStream_t st) {

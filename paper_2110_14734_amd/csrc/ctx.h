@@ -40,7 +40,7 @@ constexpr int64_t kNoAllocMaxPairs = 1024;
 // w1_ctx_last_kernel_times: work list, count pass, emit pass, pairs emitted,
 // then the network passes: bucket histogram, bucket scatter, row histogram,
 // row scatter (with the degree scan), row sort (with the diagonal rows).
-constexpr int kNumKernelTimes = 11;
+constexpr int kNumKernelTimes = 12;
 
 // Blocked emission of a single pair's network: used from this many
 // work-list chunks on, sized by a count over every kSampleStride-th chunk.
@@ -85,6 +85,7 @@ struct Ctx {
   // blocks used by the last launch group (0: counted layout) and their size
   DBuf bfill, bpairs, bctl;
   uint32_t emit_blocks = 0, emit_block_recs = 0;
+  int rec_words = 3;  // words per pair record of the last emit pass: (u, v) or (u, v, cost)
   // per pair
   DBuf pairs;
   int64_t pair_bytes = 0;  // bytes of the per-pair arrays in `pairs`

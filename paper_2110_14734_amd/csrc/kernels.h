@@ -81,7 +81,7 @@ int64_t csr_entry_tile(int RB);  // entries per tile of the row passes
 // Records per tile of the bucket scatter: a block of the blocked emission
 // holds at most this many.
 int csr_tile_records();
-void launch_csr_bucket_scatter(const uint32_t* rec, uint64_t P, const uint64_t* rstart, int64_t K,
+void launch_csr_bucket_scatter(const uint32_t* rec, int rec_words, uint64_t P, const uint64_t* rstart, int64_t K,
                                const int64_t* cell_start, int RB, int DB, int NB, const uint64_t* bstart,
                                uint64_t* bcur, uint32_t* out,
                                const uint32_t* blk_fill, const uint32_t* blk_pair, uint32_t blk_recs,
@@ -208,10 +208,12 @@ void launch_item_bounds(const uint32_t* cpair, const uint64_t* keys, int64_t m, 
                         hipStream_t st);
 void launch_chunks(const int32_t* cstart, int64_t K, const int64_t* item_start, const int32_t* ipp, int64_t nch,
                    int chunk, int32_t* chunk_first, int32_t* chunk_end, int32_t* chunk_pair, hipStream_t st);
-// Count (emit = false) or emit pass; split_recs = packed split records for
-// the count pass, or nullptr to read the children's records (the emit pass
-// always does).
-void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
+// Count (emit = false) or emit pass; split_recs = packed split records, or
+// nullptr to read the children's records.  An emit pass uses the packed
+// records only for the network's records (a bucket histogram, no checksums,
+// no blocks), which are then (u, v) pairs.  Returns the words per record
+// written: 0 (count pass), 2 (u, v) or 3 (u, v, cost).
+int launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
                       uint32_t* out, int32_t* err, bool prune, bool l2, const BucketHist& bh, const StreamOut& so,

@@ -696,8 +696,9 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       if (!(o.flags & W1_COUNT_ONLY) && Ptot > 0) {
         // the records' buffer later holds the rows' unsorted heads, which
         // are placed by final arc number (2 Ptot WSPD arcs plus at most
-        // 2 N + K diagonal arcs)
-        uint32_t* pout = need<uint32_t>(c, c.pu, std::max<int64_t>(3 * Ptot, 2 * Ptot + 2 * N + K));
+        // 2 N + K diagonal arcs); records are (u, v) when the packed split
+        // records exist, else (u, v, cost)
+        uint32_t* pout = need<uint32_t>(c, c.pu, std::max<int64_t>((split ? 2 : 3) * Ptot, 2 * Ptot + 2 * N + K));
         // the emit pass also counts the arcs per tail bucket of the
         // network's row partition (a5)
         const CsrGeometry geo = csr_geometry(N, maxnp);
@@ -712,8 +713,8 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         bh.count = bcnt;
         fill_u32(xc, 0, 8, st);
         check(c, hipEventRecord(c.kev[3], st));
-        launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr, prune, l2, bh,
-                         StreamOut{}, BlockOut{}, 1, c.num_cus, st);
+        c.rec_words = launch_wspd_pass(true, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr, prune,
+                                       l2, bh, StreamOut{}, BlockOut{}, 1, c.num_cus, st);
         check(c, hipGetLastError());
         emitted = true;
       }
@@ -726,6 +727,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
   c.kms[4] = stream_ms;
   c.kms[9] = (double)c.emit_blocks;
   c.kms[10] = (double)fused;
+  c.kms[11] = emitted ? (double)(c.emit_blocks > 0 ? 2 : c.rec_words) : 0.0;
 
   // ---------------------------------------------------------------- a5 --
   // The network in compressed sparse row form, sorted by (tail, head)
@@ -787,8 +789,8 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       fill_u64(bcur, 0, NB, st);
       check(c, hipEventRecord(c.kev[6], st));
       const bool blk = c.emit_blocks > 0;
-      launch_csr_bucket_scatter((const uint32_t*)c.pu.p, (uint64_t)Ptot, rstart, K, P.cell_start, RB, DB, (int)NB,
-                                bstart, bcur, col, blk ? (const uint32_t*)c.bfill.p : nullptr,
+      launch_csr_bucket_scatter((const uint32_t*)c.pu.p, c.rec_words, (uint64_t)Ptot, rstart, K, P.cell_start, RB, DB,
+                                (int)NB, bstart, bcur, col, blk ? (const uint32_t*)c.bfill.p : nullptr,
                                 blk ? (const uint32_t*)c.bpairs.p : nullptr, c.emit_block_recs, c.emit_blocks, st);
       check(c, hipEventRecord(c.kev[7], st));
       launch_csr_row_hist(col, tfirst, ntiles, (int)NB, bstart, RB, DB, N, rowcnt, st);

@@ -439,9 +439,13 @@ __device__ inline uint32_t lanes_set_below(uint64_t m, uint32_t add) {
 // separated, held as (P, O, orient): the aux of P, the node to split (its
 // child base, and its representative, which is also its left child's), and
 // O's record.  A split of P reads both children's records (one aligned
-// 64-byte pair, four loads); COMPACT (count pass only) reads P's packed
-// 32-byte split record instead (two loads).  Both hold the same boxes and
-// child bases, so the counts are the same.  A step first lets every lane without a pair acquire an
+// 64-byte pair, four loads); COMPACT reads P's packed 32-byte split record
+// instead (two loads).  Both hold the same boxes and child bases, so the
+// pairs are the same.  The representatives a COMPACT emit pass needs follow
+// from the split index gamma: the left child starts where P starts (P's
+// representative), the right child at cell gamma + 1.  Its records are
+// (u, v) without the cost (the network's costs come from the cells when its
+// rows are sorted), 8 bytes each.  A step first lets every lane without a pair acquire an
 // entry (pop its LDS stack, else take a fresh item from the chunk); a
 // separated fresh item is output at once.  Then each lane with a pair loads
 // both children of P (adjacent records), tests both child pairs against O
@@ -460,7 +464,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
                                               const uint64_t* __restrict__ chunk_off, uint32_t* __restrict__ out,
                                               int32_t* __restrict__ err, BucketHist bh, StreamOut so, BlockOut bo,
                                               int chunk_stride) {
-  static_assert(!(EMIT && COMPACT), "packed split records carry no representatives");
+  static_assert(!(COMPACT && BLOCKS), "blocked output reads the full records");
   static_assert(EMIT || !BLOCKS, "blocked output is an emit-pass mode");
   extern __shared__ int2 s_stack[];
   const int wave = threadIdx.x / WAVE, lane = lane_id();
@@ -502,9 +506,12 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       const int kp = BLOCKS ? bo.chunk_pair[k] : 0;
       if (BLOCKS && blk >= 0 && kp != bpair) retire();  // a block holds one diagram pair
       // records go at the chunk's counted offset, or on in the wave's block
-      uint32_t* obase = !EMIT ? nullptr : BLOCKS ? bptr : out + 3 * (chunk_off[k] - (uint64_t)so.base);
+      uint32_t* obase = !EMIT    ? nullptr
+                        : BLOCKS  ? bptr
+                        : COMPACT ? out + 2 * (chunk_off[k] - (uint64_t)so.base)
+                                  : out + 3 * (chunk_off[k] - (uint64_t)so.base);
       uint64_t h1 = 0, h2 = 0;  // streamed emission: the lane's checksum terms
-      const uint64_t cs = EMIT && bh.NB > 0 ? (uint64_t)bh.cell_start[bh.chunk_pair[k]] : 0;
+      const uint64_t cs = EMIT && (COMPACT || bh.NB > 0) ? (uint64_t)bh.cell_start[bh.chunk_pair[k]] : 0;
       uint64_t cursor = 0;
       typedef typename WMet<L2>::D Diam;
       bool has = false, overflow = false, runaway = false, orient = false;
@@ -565,8 +572,8 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
             const uint4 w0 = ps[0], w1 = ps[1];
             unpack_boxes(w0, w1, C1.box, C2.box);
             const int gamma = (int)w1.w;
-            C1.aux = make_int4(gamma, 0, 0, 0);
-            C2.aux = make_int4(gamma + 1, 0, 0, 0);
+            C1.aux = make_int4(gamma, EMIT ? pa.y : 0, 0, 0);
+            C2.aux = make_int4(gamma + 1, EMIT ? (int)((int64_t)gamma + 1 - (int64_t)cs) : 0, 0, 0);
           } else {
             const int4* pc = R + 2 * (size_t)c1;  // both children: 64 contiguous, aligned bytes
             C1 = Rec{pc[0], pc[1]};
@@ -640,16 +647,16 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
             wr = !dead;
             if (wr) bleft -= n;
           }
-          if (BLOCKS && wr) {  // blocks hold (u, v): the network's costs come from the cells
+          if ((BLOCKS && wr) || COMPACT) {  // (u, v): the network's costs come from the cells
             if (e1) __builtin_nontemporal_store(u32x2{m1.x, m1.y}, (u32x2*)(obase + 2 * lanes_set_below(b1, 0u)));
             if (e2) __builtin_nontemporal_store(u32x2{m2.x, m2.y}, (u32x2*)(obase + 2 * lanes_set_below(b2, n1)));
             obase += 2 * (n1 + n2);
-          } else if (!BLOCKS) {
+          } else if (!BLOCKS && !COMPACT) {
             if (e1) __builtin_nontemporal_store(m1, (u32x3_w*)(obase + 3 * lanes_set_below(b1, 0u)));
             if (e2) __builtin_nontemporal_store(m2, (u32x3_w*)(obase + 3 * lanes_set_below(b2, n1)));
             obase += 3 * (n1 + n2);
           }
-          if (so.chunk_sum) {
+          if (!COMPACT && so.chunk_sum) {
             if (e1) {
               const uint64_t h = record_hash(m1);
               h1 += h;
@@ -763,36 +770,40 @@ void launch_chunks(const int32_t* cstart, int64_t K, const int64_t* item_start, 
                    int chunk, int32_t* chunk_first, int32_t* chunk_end, int32_t* chunk_pair, hipStream_t st) {
   LAUNCH(k_chunks, nch, cstart, K, item_start, ipp, nch, chunk, chunk_first, chunk_end, chunk_pair);
 }
-void launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
+int launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, const int2* items,
                       const int32_t* chunk_first, const int32_t* chunk_end, int64_t nchunks, const int32_t* xcd_range,
                       uint32_t* xcd_ctr, int s, const WspdTuning& tun, uint64_t* chunk_cnt, const uint64_t* chunk_off,
                       uint32_t* out, int32_t* err, bool prune, bool l2, const BucketHist& bh, const StreamOut& so,
                       const BlockOut& bo, int chunk_stride, int num_cus, hipStream_t st) {
-  if (nchunks <= 0) return;
+  if (nchunks <= 0) return 0;
   int64_t grid = (int64_t)num_cus * tun.blocks_per_cu;
   grid = ((grid + 7) / 8) * 8;
   const size_t lds = (size_t)4 * tun.stack_depth * WAVE * sizeof(int2) + (emit ? (size_t)bh.NB * 4 : 0);
   // A chunk's items each have at most work_cap leaf pairs, hence fewer than
   // 2 work_cap recursion nodes; every wave step resolves at least one.
   const int64_t step_cap = (int64_t)tun.chunk_items * (2 * (int64_t)tun.work_cap + 2) + 1024;
-  // the emit pass always reads the children's records (the packed split
-  // records serve the count pass)
+  // the emit pass reads the packed split records only when it writes
+  // (u, v) records for the network (it needs the chunks' first cells, which
+  // come with the bucket histogram); with checksums or blocks it reads the
+  // children's full records
   const bool blocks = emit && bo.base;
+  const bool packed = split_recs && (!emit || (!blocks && !so.chunk_sum && bh.NB > 0));
   auto k = l2 ? (blocks ? k_wspd<true, false, false, true, true>
-                 : emit ? k_wspd<true, false, false, true, false>
-                        : (split_recs ? k_wspd<false, true, false, true, false> : k_wspd<false, false, false, true, false>))
+                 : emit ? (packed ? k_wspd<true, true, false, true, false> : k_wspd<true, false, false, true, false>)
+                        : (packed ? k_wspd<false, true, false, true, false> : k_wspd<false, false, false, true, false>))
          : prune ? (blocks ? k_wspd<true, false, true, false, true>
-                    : emit ? k_wspd<true, false, true, false, false>
-                           : (split_recs ? k_wspd<false, true, true, false, false>
-                                         : k_wspd<false, false, true, false, false>))
+                    : emit ? (packed ? k_wspd<true, true, true, false, false> : k_wspd<true, false, true, false, false>)
+                           : (packed ? k_wspd<false, true, true, false, false>
+                                     : k_wspd<false, false, true, false, false>))
                  : (blocks ? k_wspd<true, false, false, false, true>
-                    : emit ? k_wspd<true, false, false, false, false>
-                           : (split_recs ? k_wspd<false, true, false, false, false>
-                                         : k_wspd<false, false, false, false, false>));
+                    : emit ? (packed ? k_wspd<true, true, false, false, false> : k_wspd<true, false, false, false, false>)
+                           : (packed ? k_wspd<false, true, false, false, false>
+                                     : k_wspd<false, false, false, false, false>));
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds, st, T.inode, split_recs, items, chunk_first, chunk_end,
                      xcd_range, xcd_ctr, s, tun.stack_depth, step_cap, chunk_cnt, chunk_off, out, err,
                      emit ? bh : BucketHist{}, emit ? so : StreamOut{}, emit ? bo : BlockOut{},
                      chunk_stride > 0 ? chunk_stride : 1);
+  return !emit ? 0 : (blocks || packed) ? 2 : 3;
 }
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,
