@@ -40,8 +40,19 @@ namespace w1 {
 namespace {
 
 constexpr int CB = 512;        // threads per block of the partition passes
-constexpr int PPT = 8;         // pair records per thread in the bucket passes
+// Tile sizes of the partition passes.  Each is one tile per block with three
+// barriers, so occupancy hides more latency than longer output runs save:
+// on the 200k + 200k pair (782 buckets) the bucket scatter took 12.9 ms with
+// 8 records per thread, 11.7 ms with 4 (2: 14.3 ms); the row scatter 14.7 ms
+// with 16 entries per thread, 11.1 ms with 8 (4: 13.8 ms).  The row
+// histogram's cost per tile is one atomic per row, so it takes large tiles.
+constexpr int PPT = 4;         // pair records per thread in the bucket scatter
 constexpr int PTILE = CB * PPT;
+constexpr int HIST_EPT = 64;   // entries per thread in the row histogram
+// The bucket cursors sit one per 128-byte line: every tile of the bucket
+// scatter reserves a run in most buckets, and cursors sharing a line
+// serialise those atomics (with 2 records per thread, 17.4 -> 14.3 ms).
+constexpr int BCUR_STRIDE = 16;
 constexpr int SORT_B = 512;    // threads per block of the row sort
 constexpr int SORT_WAVES = SORT_B / WAVE;
 constexpr int SORT_STAGE = 512;  // staged heads per wave of the row sort
@@ -148,7 +159,7 @@ __global__ void __launch_bounds__(CB) k_bucket_scatter(const uint32_t* __restric
                                                        uint32_t* __restrict__ out,
                                                        const uint32_t* __restrict__ blk_fill,
                                                        const uint32_t* __restrict__ blk_pair, uint32_t blk_recs,
-                                                       uint32_t rw) {
+                                                       uint32_t rw, int cstride) {
   extern __shared__ uint32_t s_mem[];
   uint32_t* s_cnt = s_mem;                         // NB: counts, then prefixes
   int64_t* s_gofs = (int64_t*)(s_mem + ((NB + 1) & ~1));  // NB: global base - prefix
@@ -182,7 +193,7 @@ __global__ void __launch_bounds__(CB) k_bucket_scatter(const uint32_t* __restric
   // block-local prefixes
   for (int b = threadIdx.x; b < NB; b += CB) {
     const uint32_t c = s_cnt[b];
-    s_gofs[b] = c ? (int64_t)(bstart[b] + atomicAdd(&bcur[b], (unsigned long long)c)) : 0;
+    s_gofs[b] = c ? (int64_t)(bstart[b] + atomicAdd(&bcur[(int64_t)b * cstride], (unsigned long long)c)) : 0;
   }
   __syncthreads();
   lds_excl_scan(s_cnt, NB, s_tmp);
@@ -239,7 +250,7 @@ __global__ void __launch_bounds__(CB) k_row_hist(const uint32_t* __restrict__ en
 }
 
 // EPT entries per thread: the tile of CB * EPT entries and the 2^RB row
-// counters share the LDS (EPT = 16 up to 2^10 rows per bucket).
+// counters share the LDS (EPT = 8 up to 2^11 rows per bucket).
 template <int EPT>
 __global__ void __launch_bounds__(CB) k_row_scatter(const uint32_t* __restrict__ ent, const int64_t* __restrict__ tfirst,
                                                     int NB, const uint64_t* __restrict__ bstart, int RB, int DB,
@@ -660,14 +671,16 @@ inline unsigned blocks(int64_t n, int bs = 256) { return (unsigned)(n > 0 ? ceil
 
 }  // namespace
 
+int csr_bucket_stride() { return BCUR_STRIDE; }
 size_t csr_bucket_scatter_lds(int NB) {
   return (size_t)((NB + 1) & ~1) * 4 + (size_t)NB * 8 + (size_t)2 * PTILE * (4 + 2);
 }
-int csr_entries_per_thread(int RB) { return RB <= 10 ? 16 : (RB == 11 ? 8 : 4); }
+int csr_entries_per_thread(int RB) { return RB <= 11 ? 8 : 4; }
 size_t csr_row_scatter_lds(int RB) {
   return (size_t)(1 << RB) * 12 + (size_t)CB * csr_entries_per_thread(RB) * (4 + 2);
 }
 int64_t csr_entry_tile(int RB) { return (int64_t)CB * csr_entries_per_thread(RB); }
+int64_t csr_hist_tile(int) { return (int64_t)CB * HIST_EPT; }
 
 int csr_tile_records() { return PTILE; }
 void launch_csr_bucket_scatter(const uint32_t* rec, int rec_words, uint64_t P, const uint64_t* rstart, int64_t K,
@@ -676,24 +689,25 @@ void launch_csr_bucket_scatter(const uint32_t* rec, int rec_words, uint64_t P, c
                                uint32_t blk_recs, uint32_t nblocks, hipStream_t st) {
   if (P == 0 || (rec_words != 2 && rec_words != 3)) return;
   // blocked records: one tile per block, whose records must fit a tile
-  if (blk_fill && (blk_recs == 0 || blk_recs > (uint32_t)PTILE || nblocks == 0)) return;
-  const int64_t tiles = blk_fill ? (int64_t)nblocks : ceil_div((int64_t)P, PTILE);
+  const int ptile = csr_tile_records();
+  if (blk_fill && (blk_recs == 0 || blk_recs > (uint32_t)ptile || nblocks == 0)) return;
+  const int64_t tiles = blk_fill ? (int64_t)nblocks : ceil_div((int64_t)P, ptile);
   hipLaunchKernelGGL(k_bucket_scatter, dim3((unsigned)tiles), dim3(CB), csr_bucket_scatter_lds(NB), st, rec, P,
                      rstart, K, cell_start, RB, DB, NB, bstart, (unsigned long long*)bcur, out, blk_fill, blk_pair,
-                     blk_recs, blk_fill ? 2u : (uint32_t)rec_words);
+                     blk_recs, blk_fill ? 2u : (uint32_t)rec_words, csr_bucket_stride());
 }
 void launch_csr_row_hist(const uint32_t* ent, const int64_t* tfirst, int64_t ntiles, int NB, const uint64_t* bstart,
                          int RB, int DB, int64_t N, uint32_t* rowcnt, hipStream_t st) {
   if (ntiles <= 0) return;
   hipLaunchKernelGGL(k_row_hist, dim3((unsigned)ntiles), dim3(CB), (size_t)(1 << RB) * 4, st, ent, tfirst, NB, bstart,
-                     RB, DB, N, (int)csr_entry_tile(RB), rowcnt);
+                     RB, DB, N, (int)csr_hist_tile(RB), rowcnt);
 }
 void launch_csr_row_scatter(const uint32_t* ent, const int64_t* tfirst, int64_t ntiles, int NB,
                             const uint64_t* bstart, int RB, int DB, int64_t N, const uint32_t* cpair,
                             const uint64_t* off, uint32_t* rowcur, uint32_t* heads, hipStream_t st) {
   if (ntiles <= 0) return;
   const int ept = csr_entries_per_thread(RB);
-  auto k = ept == 16 ? k_row_scatter<16> : (ept == 8 ? k_row_scatter<8> : k_row_scatter<4>);
+  auto k = ept == 8 ? k_row_scatter<8> : k_row_scatter<4>;
   hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(CB), csr_row_scatter_lds(RB), st, ent, tfirst, NB, bstart, RB, DB,
                      N, cpair, off, rowcur, heads);
 }

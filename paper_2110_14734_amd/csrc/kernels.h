@@ -75,9 +75,11 @@ void launch_level_boxes(const int2* cij, int64_t N, const int4* iaux, const int3
 // a5: the network in compressed sparse row form (csr.hip).  Geometry
 // (csr_geometry in limits.h): a bucket is 2^RB consecutive cells, heads take
 // DB bits, RB + DB <= 32, at most 1024 buckets.
+int csr_bucket_stride();
 size_t csr_bucket_scatter_lds(int NB);
 size_t csr_row_scatter_lds(int RB);
-int64_t csr_entry_tile(int RB);  // entries per tile of the row passes
+int64_t csr_entry_tile(int RB);  // entries per tile of the row scatter
+int64_t csr_hist_tile(int RB);   // entries per tile of the row histogram
 // Records per tile of the bucket scatter: a block of the blocked emission
 // holds at most this many.
 int csr_tile_records();

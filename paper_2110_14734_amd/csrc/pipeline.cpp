@@ -754,7 +754,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     uint32_t* rowcnt = need<uint32_t>(c, c.rowcnt, N);
     fill_u32(rowcnt, 0, N, st);
     int64_t* sup = need<int64_t>(c, c.supply, NR);
-    int64_t ntiles = 0;
+    int64_t ntiles = 0, ntiles_h = 0;  // tiles of the row scatter and of the row histogram
     const uint64_t* bstart = nullptr;
     const int64_t* tfirst = nullptr;
     if (Ptot > 0) {
@@ -767,33 +767,38 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       // bucket starts and the tiles of the row passes (host: NB is small)
       std::vector<uint64_t> hb((size_t)NB);
       readback(c, bcnt, hb.data(), NB);
-      const int64_t et = csr_entry_tile(RB);
+      // (the row histogram takes larger tiles than the row scatter: its only
+      // per-tile cost is one atomic per row of the bucket)
+      const int64_t et = csr_entry_tile(RB), eth = csr_hist_tile(RB);
       std::vector<uint64_t> hbs((size_t)NB + 1);
-      std::vector<int64_t> htf((size_t)NB + 1);
+      std::vector<int64_t> htf((size_t)(2 * (NB + 1)));
       uint64_t acc = 0;
       for (int64_t b = 0; b < NB; ++b) {
         hbs[(size_t)b] = acc;
         htf[(size_t)b] = ntiles;
+        htf[(size_t)(NB + 1 + b)] = ntiles_h;
         acc += hb[(size_t)b];
         ntiles += ceil_div((int64_t)hb[(size_t)b], et);
+        ntiles_h += ceil_div((int64_t)hb[(size_t)b], eth);
       }
       hbs[(size_t)NB] = acc;
       htf[(size_t)NB] = ntiles;
+      htf[(size_t)(2 * NB + 1)] = ntiles_h;
       if (acc != 2 * (uint64_t)Ptot || ntiles >= (int64_t(1) << 31)) throw StageError{W1_EOVERFLOW};
       uint64_t* dbs = need<uint64_t>(c, c.bstart, NB + 1);
-      int64_t* dtf = need<int64_t>(c, c.tfirst, NB + 1);
-      upload_all(c, {{dbs, hbs.data(), (size_t)(NB + 1) * 8}, {dtf, htf.data(), (size_t)(NB + 1) * 8}});
+      int64_t* dtf = need<int64_t>(c, c.tfirst, 2 * (NB + 1));
+      upload_all(c, {{dbs, hbs.data(), (size_t)(NB + 1) * 8}, {dtf, htf.data(), (size_t)(2 * (NB + 1)) * 8}});
       bstart = dbs;
       tfirst = dtf;
-      uint64_t* bcur = need<uint64_t>(c, c.bcur, NB);
-      fill_u64(bcur, 0, NB, st);
+      uint64_t* bcur = need<uint64_t>(c, c.bcur, NB * csr_bucket_stride());
+      fill_u64(bcur, 0, NB * csr_bucket_stride(), st);
       check(c, hipEventRecord(c.kev[6], st));
       const bool blk = c.emit_blocks > 0;
       launch_csr_bucket_scatter((const uint32_t*)c.pu.p, c.rec_words, (uint64_t)Ptot, rstart, K, P.cell_start, RB, DB,
                                 (int)NB, bstart, bcur, col, blk ? (const uint32_t*)c.bfill.p : nullptr,
                                 blk ? (const uint32_t*)c.bpairs.p : nullptr, c.emit_block_recs, c.emit_blocks, st);
       check(c, hipEventRecord(c.kev[7], st));
-      launch_csr_row_hist(col, tfirst, ntiles, (int)NB, bstart, RB, DB, N, rowcnt, st);
+      launch_csr_row_hist(col, tfirst + NB + 1, ntiles_h, (int)NB, bstart, RB, DB, N, rowcnt, st);
       check(c, hipEventRecord(c.kev[8], st));
     }
     // degrees, row offsets
