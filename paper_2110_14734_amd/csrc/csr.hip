@@ -393,9 +393,9 @@ __device__ inline void flush_staged(const uint32_t* st, uint32_t n, int64_t k0, 
 // heads: a row's heads in arbitrary order (rowcnt[g] of them at off[row]);
 // col / cost: the sorted row.  Per row (and per window of `win_words`
 // bitmap words over the pair's cells):
-//   1. each head sets its bit in an LDS bitmap and counts towards its group
-//      of 64 words (the first SORT_FILL * SORT_B heads were loaded while the
-//      previous row was being written);
+//   1. each head sets its bit in an LDS bitmap (the first SORT_FILL * SORT_B
+//      heads were loaded while the previous row was being written); the set
+//      bits are then counted per group of 64 words by popcount;
 //   2. the group counts are scanned, and the groups are cut into SORT_TASKS
 //      runs of about equal weight, a group weighing its heads plus
 //      SORT_GROUP_W (the fixed cost of visiting it): a row's heads crowd
@@ -465,10 +465,22 @@ __global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict_
         }
 #pragma unroll
         for (int u = 0; u < SORT_FILL; ++u)
-          if (h[u] < nbits) {
-            atomicOr(&s_bm[h[u] >> 5], 1u << (h[u] & 31));
-            atomicAdd(&s_gpre[h[u] >> 11], 1u);
-          }
+          if (h[u] < nbits) atomicOr(&s_bm[h[u] >> 5], 1u << (h[u] & 31));
+      }
+      __syncthreads();
+      // heads per group: each thread counts eight words by popcount and adds
+      // them with one LDS atomic (an atomic per head on the group counters
+      // serialised the dense groups' heads)
+      for (int i0 = threadIdx.x * 8; i0 < nw; i0 += SORT_B * 8) {
+        uint32_t v = 0;
+        if (i0 + 8 <= nw) {
+          const uint4 a = *(const uint4*)(s_bm + i0), b = *(const uint4*)(s_bm + i0 + 4);
+          v = __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w) + __popc(b.x) + __popc(b.y) + __popc(b.z) +
+              __popc(b.w);
+        } else {
+          for (int k = i0; k < nw; ++k) v += __popc(s_bm[k]);
+        }
+        if (v) atomicAdd(&s_gpre[i0 >> 6], v);
       }
       __syncthreads();
       if (ahead) {  // the next row's first heads arrive while this one is written

@@ -125,99 +125,13 @@ def test_gradient_parity(w1, ctx):
         assert err <= 1e-3 * np.linalg.norm(b) + 1e-6 * gscale, (name, err, np.linalg.norm(b))
 
 
-def _dyadic_case(seed=11):
-    """Parameters and points on coarse dyadic grids (W1, b1 in steps of 2^-3,
-    W2 and W3 of 2^-2, all within [-1/2, 1/2]; b2 in steps of 2^-9, b3 of
-    2^-11; births and persistences in steps of 2^-4 below 1/2; at most 8
-    points per diagram), so that every product of the forward pass is exact
-    in FP32, every h1 is a BF16 number, and every sum is exact in any order
-    (checked below through the magnitude sums).  The only rounding left is
-    in the per-pair loss coefficients and in the backward sums."""
-    rng = np.random.default_rng(seed)
-    p = np.zeros(S.NPARAM)
-    q = lambda n, step: rng.integers(-int(0.5 / step), int(0.5 / step) + 1, n) * step
-    p[S.OFF_W1:S.OFF_B1], p[S.OFF_B1:S.OFF_W2] = q(256, 2.0**-3), q(128, 2.0**-3)
-    p[S.OFF_W2:S.OFF_B2], p[S.OFF_B2:S.OFF_W3] = q(128 * 128, 2.0**-2), q(128, 2.0**-9)
-    p[S.OFF_W3:S.OFF_B3], p[S.OFF_B3:] = q(64 * 128, 2.0**-2), q(64, 2.0**-11)
-    ds = []
-    for _ in range(8):
-        n = int(rng.integers(1, 9))
-        b, pe = rng.integers(0, 8, n) * 2.0**-4, rng.integers(1, 8, n) * 2.0**-4
-        ds.append(np.stack([b, b + pe], 1).astype(np.float32))
-    pa = np.array([0, 1, 2, 3, 4, 5, 6, 0, 2, 7, 7, 3])
-    pb = np.array([1, 2, 3, 4, 5, 6, 7, 7, 5, 1, 2, 0])
-    return p.astype(np.float32), ds, pa, pb, rng.uniform(0.5, 5.0, len(pa))
-
-
-def _exact_forward(p, ds):
-    """Every forward sum is a multiple of its grid step and its magnitude sum
-    is below 2^24 steps, so FP32 adds it exactly in any order."""
-    P = S.unpack(p)
-    for A in ds:
-        x = S.features(A)
-        h1 = np.maximum(x @ P["W1"].T + P["b1"], 0.0)
-        if not (np.array_equal(h1, S.bf16(h1)) and (np.abs(x) @ np.abs(P["W1"]).T + np.abs(P["b1"])).max() < 2.0**17):
-            return False
-        if (h1 @ np.abs(P["W2"]).T + np.abs(P["b2"])).max() >= 2.0**15:
-            return False
-        pool = np.maximum(h1 @ P["W2"].T + P["b2"], 0.0).sum(axis=0)
-        if pool.max() >= 2.0**15 or (np.abs(P["W3"]) @ pool + np.abs(P["b3"])).max() >= 2.0**13:
-            return False
-    return True
-
-
-def _gradient_tolerance(p, ds, pa, pb, w, gam=2.0**-16):
-    """Element-wise bound on |g_gpu - g_oracle| when the forward pass is exact.
-
-    The GPU's per-pair coefficients c_j = 2 (pred - w) / (w^2 P pred) differ
-    from the FP64 ones by a few FP32 ulps and its backward sums round in
-    FP32; both are covered by gam = 2^-16 (256 terms of 2^-24) times the
-    magnitude of each gradient entry, i.e. the backward pass run on absolute
-    values with demb replaced by sum_j |c_j| |diff_j|.  dpool is rounded to
-    BF16 before it enters dW2 and dH1; where dpool +- gam * its magnitude
-    straddles a BF16 rounding boundary, the full BF16 step is added and
-    carried through dW2, dH1, dW1 and db1."""
-    P = S.unpack(p)
-    W2b = S.bf16(P["W2"])
-    emb, cache = S.forward(p, ds, emulate=True)
-    nP = len(w)
-    demb, mag = np.zeros_like(emb), np.zeros_like(emb)
-    for j in range(nP):
-        diff = emb[pa[j]] - emb[pb[j]]
-        pred = np.sqrt(diff @ diff)
-        if pred > 0:
-            g = 2.0 * (pred - w[j]) / (w[j] ** 2 * nP * pred) * diff
-            demb[pa[j]] += g
-            demb[pb[j]] -= g
-            mag[pa[j]] += np.abs(g)
-            mag[pb[j]] += np.abs(g)
-    A3 = np.abs(P["W3"])
-    t = dict(W1=np.zeros((128, 2)), b1=np.zeros(128), W2=np.zeros((128, 128)), b2=np.zeros(128),
-             W3=np.zeros((64, 128)), b3=gam * mag.sum(axis=0))
-    for d, (x, h1, z2, pool) in enumerate(cache):
-        t["W3"] += gam * np.outer(mag[d], np.abs(pool))
-        if not len(x):
-            continue
-        dpool, mpool = P["W3"].T @ demb[d], A3.T @ mag[d]
-        m2 = (z2 > 0.0).astype(np.float64)
-        t["b2"] += gam * (m2 * mpool).sum(axis=0)
-        rb = S.bf16(dpool)
-        flip = np.maximum(np.abs(S.bf16(dpool + gam * mpool) - rb), np.abs(rb - S.bf16(dpool - gam * mpool)))
-        e_dz2 = m2 * flip + gam * m2 * (np.abs(rb) + flip)
-        t["W2"] += e_dz2.T @ np.abs(h1)
-        e_dz1 = (e_dz2 @ np.abs(W2b)) * (h1 > 0.0)
-        t["W1"] += e_dz1.T @ np.abs(x)
-        t["b1"] += e_dz1.sum(axis=0)
-    return np.concatenate([t["W1"].ravel(), t["b1"], t["W2"].ravel(), t["b2"], t["W3"].ravel(), t["b3"]])
-
-
 def test_gradient_parity_elementwise(w1, ctx):
     """Every gradient entry within its own derived bound, on inputs whose
     forward pass is exact (so the only differences are the backward's FP32
     roundings)."""
     _say("surrogate gradient, element-wise")
-    p, ds, pa, pb, w = _dyadic_case()
-    assert _exact_forward(p, ds)
+    p, ds, pa, pb, w = S.dyadic_case()
+    assert S.exact_forward(p, ds)
     sur = w1.Surrogate(ctx, seed=5)
     sur.params = p
     e_orc, _ = S.forward(p, ds, emulate=True)
@@ -225,7 +139,7 @@ def test_gradient_parity_elementwise(w1, ctx):
     loss_g, g_gpu = sur.grad(ds, pa, pb, w)
     loss_o, g_orc = S.loss_grad(p, ds, pa, pb, w, emulate=True)
     assert abs(loss_g - loss_o) <= 1e-6 * abs(loss_o)
-    tol = _gradient_tolerance(p, ds, pa, pb, w)
+    tol = S.gradient_tolerance(p, ds, pa, pb, w)
     err = np.abs(g_gpu.astype(np.float64) - g_orc)
     bad = np.flatnonzero(err > tol)
     assert bad.size == 0, (bad[:10], err[bad[:10]], tol[bad[:10]], g_orc[bad[:10]])
