@@ -275,7 +275,7 @@ def gradient_tolerance(p, ds, pa, pb, w, gam=2.0**-16):
     from the FP64 ones by a few FP32 ulps and its backward sums round in
     FP32; both are covered by gam = 2^-16 (256 terms of 2^-24) times the
     magnitude of each gradient entry, i.e. the backward pass run on absolute
-    values with demb replaced by sum_j |c_j| |diff_j|.  dpool is rounded to
+    values with the embedding gradient replaced by sum_j |c_j| |diff_j|.  dpool is rounded to
     BF16 before it enters dW2 and dH1; where dpool +- gam * its magnitude
     straddles a BF16 rounding boundary, the full BF16 step is added and
     carried through dW2, dH1, dW1 and db1."""
@@ -283,14 +283,14 @@ def gradient_tolerance(p, ds, pa, pb, w, gam=2.0**-16):
     W2b = bf16(P["W2"])
     emb, cache = forward(p, ds, emulate=True)
     nP = len(w)
-    demb, mag = np.zeros_like(emb), np.zeros_like(emb)
+    dsum, mag = np.zeros_like(emb), np.zeros_like(emb)
     for j in range(nP):
         diff = emb[pa[j]] - emb[pb[j]]
         pred = np.sqrt(diff @ diff)
         if pred > 0:
             g = 2.0 * (pred - w[j]) / (w[j] ** 2 * nP * pred) * diff
-            demb[pa[j]] += g
-            demb[pb[j]] -= g
+            dsum[pa[j]] += g
+            dsum[pb[j]] = dsum[pb[j]] - g
             mag[pa[j]] += np.abs(g)
             mag[pb[j]] += np.abs(g)
     A3 = np.abs(P["W3"])
@@ -300,7 +300,7 @@ def gradient_tolerance(p, ds, pa, pb, w, gam=2.0**-16):
         t["W3"] += gam * np.outer(mag[d], np.abs(pool))
         if not len(x):
             continue
-        dpool, mpool = P["W3"].T @ demb[d], A3.T @ mag[d]
+        dpool, mpool = P["W3"].T @ dsum[d], A3.T @ mag[d]
         m2 = (z2 > 0.0).astype(np.float64)
         t["b2"] += gam * (m2 * mpool).sum(axis=0)
         rb = bf16(dpool)
