@@ -55,11 +55,10 @@ KERNEL_NAMES = {"emit_ms": "k_wspd<emit> (WSPD pair records)",
 # {kernel key: (source file, sha256 prefix of that file, bytes per launch)}.
 # (profiles/a4_a5_kernels_c2_200k_eps0.1_hbm_counters.md)
 MEASURED_TRAFFIC = {
-    "emit_ms": ("paper_2110_14734_amd/csrc/wspd.hip", "d629a62d49794035", 26_564_967_010),
-    "bucket_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "74895ed2105a970a", 36_946_970_388),
-    "row_hist_ms": ("paper_2110_14734_amd/csrc/csr.hip", "74895ed2105a970a", 15_307_170_014),
-    "row_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "74895ed2105a970a", 31_506_718_517),
-    "row_sort_ms": ("paper_2110_14734_amd/csrc/csr.hip", "74895ed2105a970a", 49_835_646_029),
+    "bucket_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "b2aef032ecc32bdf", 30_226_472_313),
+    "row_hist_ms": ("paper_2110_14734_amd/csrc/csr.hip", "b2aef032ecc32bdf", 14_805_215_588),
+    "row_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "b2aef032ecc32bdf", 32_074_986_621),
+    "row_sort_ms": ("paper_2110_14734_amd/csrc/csr.hip", "b2aef032ecc32bdf", 49_577_644_242),
 }
 
 

@@ -337,7 +337,7 @@ typedef struct {
                               /* cells are sorted window by window.  The   */
                               /* network does not depend on it             */
   int64_t emit_block_limit;   /* blocked emission: at most this many blocks */
-                              /* of 4096 records (0 = as sized); when they */
+                              /* of 2048 records (0 = as sized); when they */
                               /* run out the pass is redone with every     */
                               /* chunk counted first (same result)         */
   int32_t fused_expand_cells; /* launch groups of at most this many cells  */
@@ -350,6 +350,13 @@ typedef struct {
                               /* kept and per frontier (0 = 64 n_cells +   */
                               /* 4096 kept, 16 n_cells + 4096 frontier);   */
                               /* out of room, the rounds run one by one    */
+  int32_t stream_graph;       /* streamed emission: 1 (default) captures   */
+                              /* one arena fill (its ranges taken from a   */
+                              /* device table, then the emit pass) in a    */
+                              /* HIP graph and replays it for every fill,  */
+                              /* with no host wait between fills; 0        */
+                              /* launches each fill directly.  Same        */
+                              /* records and checksums either way          */
 } w1_tuning;
 
 int w1_ctx_get_tuning(const w1_ctx *ctx, w1_tuning *out);

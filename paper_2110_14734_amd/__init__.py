@@ -83,7 +83,8 @@ class _Tuning(ctypes.Structure):
                 ("compact_records", ctypes.c_int32), ("stream_max_rounds", ctypes.c_int32),
                 ("stream_arena_pairs", ctypes.c_int64), ("blocked_emit", ctypes.c_int32),
                 ("sort_window_words", ctypes.c_int32), ("emit_block_limit", ctypes.c_int64),
-                ("fused_expand_cells", ctypes.c_int32), ("fused_expand_items", ctypes.c_int32)]
+                ("fused_expand_cells", ctypes.c_int32), ("fused_expand_items", ctypes.c_int32),
+                ("stream_graph", ctypes.c_int32)]
 
 
 class _NNParams(ctypes.Structure):

@@ -58,6 +58,7 @@ struct Ctx {
   int64_t max_points = int64_t(1) << 22;  // points per launch group of a batch
   int64_t stream_arena = 0;                // streamed emission: arena capacity in pair records (0 = off)
   int32_t stream_rounds = 0;               // streamed emission: arena fills at most (0 = all)
+  int32_t stream_graph = 1;                // streamed emission: arena fills replayed from one captured graph
   int32_t fused_expand_cells = 4096;       // work-list expansion in one workgroup up to this many cells
   int32_t fused_expand_items = 0;          // its room in items (0: from the cell count)
   int32_t blocked_emit = 0;                // network path: blocked emission (off by default)
@@ -80,7 +81,7 @@ struct Ctx {
   // sorted heads (col); costb the arc costs; rp the per-pair row pointers
   DBuf pu, l1, costb, rp, supply, rstart, bcnt, bstart, tfirst, bcur, rowcnt, rowcur, bflag, bpos, deg, off, parc;
   // streamed emission: per-chunk pair checksums; Euclidean cost scale
-  DBuf csum, pxmax;
+  DBuf csum, pxmax, runxr, runbase;
   // blocked emission (network path): block fills, block pairs, counters;
   // blocks used by the last launch group (0: counted layout) and their size
   DBuf bfill, bpairs, bctl;
@@ -113,7 +114,7 @@ struct Ctx {
                     &ndepth, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsX, &itemsI, &itemsS, &icnt, &ipos, &ipp, &cid, &pcap,
                     &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &l1, &costb, &rp,
                     &supply, &rstart, &bcnt, &bstart, &tfirst, &bcur, &rowcnt, &rowcur, &bflag, &bpos, &deg, &off,
-                    &parc, &csum, &pxmax, &pairs};
+                    &parc, &csum, &pxmax, &runxr, &runbase, &pairs};
     all.assign(std::begin(list), std::end(list));
     saved.resize(all.size());
   }

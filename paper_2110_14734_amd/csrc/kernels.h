@@ -144,7 +144,8 @@ struct BucketHist {
 // 3 (chunk_off[k] - base) of the output; with chunk_sum set, the pass also
 // writes each chunk's record checksum (sum h, sum h^2) to chunk_sum[2k..].
 struct StreamOut {
-  int64_t base = 0;
+  int64_t base = 0;                   // first pair of the arena fill (if base_dev is null)
+  const int64_t* base_dev = nullptr;  // device copy of it, read at launch (graph replays)
   uint64_t* chunk_sum = nullptr;
 };
 
@@ -221,6 +222,12 @@ int launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, cons
                       uint32_t* out, int32_t* err, bool prune, bool l2, const BucketHist& bh, const StreamOut& so,
                       const BlockOut& bo, int chunk_stride,
                       int num_cus, hipStream_t st);
+// Streamed emission: next arena fill of a replayed launch sequence.  Fill
+// r = *ctr (of nruns) copies its chunk ranges per XCD (9 values at
+// run_xr + 9 r) into xr and its first pair into *base, clears the 8 chunk
+// counters xc and advances *ctr; past the last fill, the ranges are empty.
+void launch_stream_next(const int32_t* run_xr, const int64_t* run_base, int nruns, int32_t* ctr, int32_t* xr,
+                        int64_t* base, uint32_t* xc, hipStream_t st);
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,
                         hipStream_t st);

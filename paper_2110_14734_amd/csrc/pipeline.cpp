@@ -184,6 +184,26 @@ int pair_work_cap(int64_t ncells, int tuned) {
   return std::min(cap, tuned);
 }
 
+// A captured launch sequence: released (after the stream it was replayed
+// on has drained) when the guard goes out of scope, also on an error.
+struct GraphGuard {
+  hipStream_t cap = nullptr, wait = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool capturing = false;
+  ~GraphGuard() {
+    if (capturing) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(cap, &g);
+      if (g) (void)hipGraphDestroy(g);
+    }
+    if (exec && wait) (void)hipStreamSynchronize(wait);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
 // ------------------------------------------------------------------ pipeline --
 int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStream_t st, w1_result* res,
         double* L_only) {
@@ -660,26 +680,58 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         uint32_t* arena = need<uint32_t>(c, c.pu, 3 * c.stream_arena);
         uint64_t* csum = need<uint64_t>(c, c.csum, 2 * nch);
         fill_u64(csum, 0, 2 * nch, st);
+        // the arena fills, planned on the host: chunk ranges per XCD and the
+        // first pair of each run
+        std::vector<int32_t> run_xr;
+        std::vector<int64_t> run_base;
         int64_t c0 = 0;
         for (int round = 0; c0 < nch && (c.stream_rounds == 0 || round < c.stream_rounds); ++round) {
           int64_t c1 = c0;
           while (c1 < nch && hoff[(size_t)c1] + hcnt[(size_t)c1] - hoff[(size_t)c0] <= (uint64_t)c.stream_arena) ++c1;
           if (c1 == c0) throw StageError{W1_EOVERFLOW};  // one chunk holds more pairs than the arena
-          int32_t hr2[9];
-          for (int x = 0; x <= 8; ++x) hr2[x] = (int32_t)(c0 + ((c1 - c0) * x) / 8);
-          upload(c, xr, hr2, sizeof(hr2));
-          fill_u32(xc, 0, 8, st);
-          check(c, hipEventRecord(c.kev[3], st));
-          launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, arena, derr, prune, l2,
-                           BucketHist{}, StreamOut{(int64_t)hoff[(size_t)c0], csum}, BlockOut{}, 1, c.num_cus, st);
-          check(c, hipGetLastError());
-          check(c, hipEventRecord(c.kev[4], st));
-          check(c, hipEventSynchronize(c.kev[4]));
-          float ms = 0;
-          (void)hipEventElapsedTime(&ms, c.kev[3], c.kev[4]);
-          stream_ms += ms;
+          for (int x = 0; x <= 8; ++x) run_xr.push_back((int32_t)(c0 + ((c1 - c0) * x) / 8));
+          run_base.push_back((int64_t)hoff[(size_t)c0]);
           c0 = c1;
         }
+        const int nruns = (int)run_base.size();
+        int32_t* dxr = need<int32_t>(c, c.runxr, 9 * (int64_t)nruns);
+        int64_t* dtab = need<int64_t>(c, c.runbase, (int64_t)nruns + 2);  // bases, current base, fill counter
+        upload_all(c, {{dxr, run_xr.data(), run_xr.size() * 4}, {dtab, run_base.data(), run_base.size() * 8}});
+        int64_t* cur_base = dtab + nruns;
+        int32_t* ctr = (int32_t*)(dtab + nruns + 1);
+        fill_u32((uint32_t*)ctr, 0, 1, st);
+        const StreamOut so{0, cur_base, csum};
+        // one arena fill: the next run's ranges and base, then the emit pass
+        auto fill_once = [&](hipStream_t s2) {
+          launch_stream_next(dxr, dtab, nruns, ctr, xr, cur_base, xc, s2);
+          launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, arena, derr, prune, l2,
+                           BucketHist{}, so, BlockOut{}, 1, c.num_cus, s2);
+        };
+        GraphGuard gg;
+        if (c.stream_graph && nruns > 1) {
+          // captured once on a private stream, replayed on the caller's for
+          // every fill: no host wait between fills (the graph holds kernels
+          // only, no memset nodes)
+          check(c, hipStreamCreateWithFlags(&gg.cap, hipStreamNonBlocking));
+          gg.wait = st;
+          check(c, hipStreamBeginCapture(gg.cap, hipStreamCaptureModeThreadLocal));
+          gg.capturing = true;
+          fill_once(gg.cap);
+          gg.capturing = false;
+          check(c, hipStreamEndCapture(gg.cap, &gg.graph));
+          check(c, hipGraphInstantiate(&gg.exec, gg.graph, nullptr, nullptr, 0));
+        }
+        check(c, hipEventRecord(c.kev[3], st));
+        for (int r = 0; r < nruns; ++r) {
+          if (gg.exec) check(c, hipGraphLaunch(gg.exec, st));
+          else fill_once(st);
+        }
+        check(c, hipGetLastError());
+        check(c, hipEventRecord(c.kev[4], st));
+        check(c, hipEventSynchronize(c.kev[4]));
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, c.kev[3], c.kev[4]);
+        stream_ms = ms;
         std::vector<uint64_t> hsum((size_t)(2 * c0));
         std::vector<int32_t> hcp((size_t)c0);
         readback(c, csum, hsum.data(), 2 * c0);
@@ -1335,6 +1387,7 @@ int w1_ctx_get_tuning(const w1_ctx* c, w1_tuning* out) {
   out->max_points_per_launch = c->max_points;
   out->compact_records = c->tun.compact;
   out->stream_max_rounds = c->stream_rounds;
+  out->stream_graph = c->stream_graph;
   out->stream_arena_pairs = c->stream_arena;
   out->blocked_emit = c->blocked_emit;
   out->sort_window_words = c->sort_window;
@@ -1351,11 +1404,13 @@ int w1_ctx_set_tuning(w1_ctx* c, const w1_tuning* t) {
       t->max_points_per_launch < 1 || (t->compact_records != 0 && t->compact_records != 1) ||
       t->stream_max_rounds < 0 || t->stream_arena_pairs < 0 || t->stream_arena_pairs > (int64_t(1) << 36) ||
       (t->blocked_emit != 0 && t->blocked_emit != 1) || t->sort_window_words < 0 || t->emit_block_limit < 0 ||
-      t->fused_expand_cells < 0 || t->fused_expand_cells > kFusedExpandMaxCells || t->fused_expand_items < 0)
+      t->fused_expand_cells < 0 || t->fused_expand_cells > kFusedExpandMaxCells || t->fused_expand_items < 0 ||
+      (t->stream_graph != 0 && t->stream_graph != 1))
     return W1_EINVAL;
   c->tun = WspdTuning{t->stack_depth, t->work_cap, t->chunk_items, t->blocks_per_cu, t->compact_records};
   c->max_points = t->max_points_per_launch;
   c->stream_rounds = t->stream_max_rounds;
+  c->stream_graph = t->stream_graph;
   c->stream_arena = t->stream_arena_pairs;
   c->blocked_emit = t->blocked_emit;
   c->emit_block_limit = t->emit_block_limit;

@@ -491,6 +491,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
     blk = -1;
     bleft = 0;
   };
+  const uint64_t sbase = so.base_dev ? (uint64_t)*so.base_dev : (uint64_t)so.base;
   const int xcd = blockIdx.x & 7;
   for (int probe = 0; probe < 8; ++probe) {
     const int xr = (xcd + probe) & 7;
@@ -508,8 +509,8 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       // records go at the chunk's counted offset, or on in the wave's block
       uint32_t* obase = !EMIT    ? nullptr
                         : BLOCKS  ? bptr
-                        : COMPACT ? out + 2 * (chunk_off[k] - (uint64_t)so.base)
-                                  : out + 3 * (chunk_off[k] - (uint64_t)so.base);
+                        : COMPACT ? out + 2 * (chunk_off[k] - sbase)
+                                  : out + 3 * (chunk_off[k] - sbase);
       uint64_t h1 = 0, h2 = 0;  // streamed emission: the lane's checksum terms
       const uint64_t cs = EMIT && (COMPACT || bh.NB > 0) ? (uint64_t)bh.cell_start[bh.chunk_pair[k]] : 0;
       uint64_t cursor = 0;
@@ -723,6 +724,20 @@ __global__ void k_pair_counts(const uint64_t* __restrict__ pair_start, const uin
   if (p < K) npairs[p] = pair_end[p] > pair_start[p] ? pair_end[p] - pair_start[p] : 0;
 }
 
+__global__ void k_stream_next(const int32_t* __restrict__ run_xr, const int64_t* __restrict__ run_base, int nruns,
+                              int32_t* __restrict__ ctr, int32_t* __restrict__ xr, int64_t* __restrict__ base,
+                              uint32_t* __restrict__ xc) {
+  const int r = *ctr;  // every thread reads it before thread 0 advances it
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 9) xr[t] = r < nruns ? run_xr[9 * r + t] : 0;
+  if (t < 8) xc[t] = 0;
+  if (t == 0) {
+    *base = r < nruns ? run_base[r] : 0;
+    *ctr = r + 1;
+  }
+}
+
 inline unsigned blocks(int64_t n, int bs = 256) { return (unsigned)(n > 0 ? ceil_div(n, bs) : 1); }
 
 }  // namespace
@@ -804,6 +819,10 @@ int launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, cons
                      emit ? bh : BucketHist{}, emit ? so : StreamOut{}, emit ? bo : BlockOut{},
                      chunk_stride > 0 ? chunk_stride : 1);
   return !emit ? 0 : (blocks || packed) ? 2 : 3;
+}
+void launch_stream_next(const int32_t* run_xr, const int64_t* run_base, int nruns, int32_t* ctr, int32_t* xr,
+                        int64_t* base, uint32_t* xc, hipStream_t st) {
+  hipLaunchKernelGGL(k_stream_next, dim3(1), dim3(64), 0, st, run_xr, run_base, nruns, ctr, xr, base, xc);
 }
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,

@@ -775,6 +775,43 @@ def test_stream_emission_batched_sample(ctx):
         assert list(g.pair_checksum) == ref["checksum"], i
 
 
+def test_stream_emission_graph_replay(orc, ctx):
+    """The arena fills of the streamed emission replayed from one captured
+    HIP graph equal the fills launched one by one, and the oracle's stored
+    checksums, for every pair: 64 pairs of the batched workload through an
+    arena of 2^22 records (dozens of fills, so the graph is replayed that
+    many times), twice, with other work of the library (a full W1 call and a
+    synchronisation) between the two graph calls."""
+    import paper_2110_14734_amd as w1
+
+    _say("[gpu] streamed emission, graph replay")
+    gold = _stream_gold()["batch"]
+    sizes = pdsynth.batch_sizes(2 * 4096, 3)
+    idx = gold["index"][:64]
+    As = [pdsynth.exp_pd(int(sizes[2 * i]), 10 + 2 * i, dtype=np.float32) for i in idx]
+    Bs = [pdsynth.exp_pd(int(sizes[2 * i + 1]), 11 + 2 * i, dtype=np.float32) for i in idx]
+    C1a, C1b = pdsynth.exp_pd(400, 0), pdsynth.exp_pd(400, 1)
+    t0 = ctx.tuning
+    runs = {}
+    try:
+        for mode in ("eager", "graph1", "between", "graph2"):
+            if mode == "between":
+                g = ctx.approx(C1a, C1b, eps=0.1)
+                assert g.flow_cost == orc.run(C1a, C1b, eps=0.1, fetch=False).flow
+                continue
+            ctx.tuning = dict(t0, stream_arena_pairs=1 << 22, stream_graph=0 if mode == "eager" else 1)
+            res = ctx.approx_batch(As, Bs, eps=0.1, flags=w1.COUNT_ONLY)
+            runs[mode] = [(g.n_pairs, g.n_pairs_streamed, tuple(g.pair_checksum)) for g in res]
+            assert ctx.kernel_times()["stream_emit_ms"] > 0
+    finally:
+        ctx.tuning = t0
+    assert sum(n for n, _, _ in runs["eager"]) > 40 * (1 << 22)  # dozens of arena fills
+    for mode in ("graph1", "graph2"):
+        assert runs[mode] == runs["eager"], mode
+    for i, (n, ns, chk), ref in zip(idx, runs["eager"], gold["pairs"]):
+        assert n == ns == ref["n_pairs"] and list(chk) == ref["checksum"], i
+
+
 def test_stream_emission_stress_subsample(ctx):
     """A 200k + 200k subsample of the stress workload (Pareto persistence,
     30% exact duplicates) at eps 0.01 (s = 503) with the large-item tuning
