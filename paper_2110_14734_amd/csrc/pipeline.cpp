@@ -542,6 +542,18 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     }
     const int64_t m = isz;
     if (m > 0) {
+      // A short work list is cut into shorter chunks, so that every wave of
+      // the passes gets some: a chunk is walked by one wave, and with fewer
+      // chunks than waves the passes last as long as the longest chunk (on a
+      // 400 + 400-point pair ~0.5 ms each for ~40 chunks of 512 items).  The
+      // pairs are the same for any chunk size; only the order of the records
+      // changes, which the sorted network rows and the order-free checksums
+      // do not see.
+      WspdTuning tg = tun;
+      {
+        const int64_t waves = (int64_t)c.num_cus * tun.blocks_per_cu * 4;
+        while (tg.chunk_items > 16 && m / tg.chunk_items < 2 * waves) tg.chunk_items /= 2;
+      }
       // sort items by (rep U, rep V): Morton order, pair-major, canonical
       uint64_t* keys = need<uint64_t>(c, c.kw0, m);
       launch_item_keys(T, I, m, false, keys, st);
@@ -565,7 +577,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         ist[(size_t)p] = acc;
         cst[(size_t)p] = (int32_t)nch;
         acc += hipp[(size_t)p];
-        nch += (hipp[(size_t)p] + tun.chunk_items - 1) / tun.chunk_items;
+        nch += (hipp[(size_t)p] + tg.chunk_items - 1) / tg.chunk_items;
       }
       cst[(size_t)K] = (int32_t)nch;
       if (!worklist_chunks_fit(nch)) throw StageError{W1_EOVERFLOW};
@@ -580,7 +592,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       int32_t* cf = need<int32_t>(c, c.cfirst, nch);
       int32_t* ce = need<int32_t>(c, c.cend, nch);
       int32_t* cp = need<int32_t>(c, c.cpairs, nch);
-      launch_chunks(cstd, K, P.item_start, ipp, nch, tun.chunk_items, cf, ce, cp, st);
+      launch_chunks(cstd, K, P.item_start, ipp, nch, tg.chunk_items, cf, ce, cp, st);
       uint32_t* xc = need<uint32_t>(c, c.xctr, 16);
       uint64_t* ccnt = need<uint64_t>(c, c.ccnt, nch);
       uint64_t* coff = need<uint64_t>(c, c.coff, nch);
@@ -596,7 +608,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         fill_u64(ccnt, 0, nch, st);
         fill_u32(xc, 0, 8, st);
         check(c, hipEventRecord(c.kev[1], st));
-        launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr, prune, l2,
+        launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tg, ccnt, coff, nullptr, derr, prune, l2,
                          BucketHist{}, StreamOut{}, BlockOut{}, kSampleStride, c.num_cus, st);
         check(c, hipGetLastError());
         check(c, hipEventRecord(c.kev[2], st));
@@ -637,7 +649,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
           bo.chunk_pair = cp;
           fill_u32(xc, 0, 8, st);
           check(c, hipEventRecord(c.kev[3], st));
-          launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr, prune, l2,
+          launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tg, ccnt, coff, nullptr, derr, prune, l2,
                            bh, StreamOut{}, bo, 1, c.num_cus, st);
           check(c, hipGetLastError());
           uint32_t hctl[2];
@@ -659,7 +671,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       if (!blocked) {
       fill_u32(xc, 0, 8, st);
       check(c, hipEventRecord(c.kev[1], st));
-      launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, nullptr, derr, prune, l2,
+      launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tg, ccnt, coff, nullptr, derr, prune, l2,
                        BucketHist{}, StreamOut{}, BlockOut{}, 1, c.num_cus, st);
       check(c, hipGetLastError());
       check(c, hipEventRecord(c.kev[2], st));
@@ -704,7 +716,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         // one arena fill: the next run's ranges and base, then the emit pass
         auto fill_once = [&](hipStream_t s2) {
           launch_stream_next(dxr, dtab, nruns, ctr, xr, cur_base, xc, s2);
-          launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, arena, derr, prune, l2,
+          launch_wspd_pass(true, T, nullptr, S, cf, ce, nch, xr, xc, s, tg, ccnt, coff, arena, derr, prune, l2,
                            BucketHist{}, so, BlockOut{}, 1, c.num_cus, s2);
         };
         GraphGuard gg;
@@ -765,7 +777,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
         bh.count = bcnt;
         fill_u32(xc, 0, 8, st);
         check(c, hipEventRecord(c.kev[3], st));
-        c.rec_words = launch_wspd_pass(true, T, split, S, cf, ce, nch, xr, xc, s, tun, ccnt, coff, pout, derr, prune,
+        c.rec_words = launch_wspd_pass(true, T, split, S, cf, ce, nch, xr, xc, s, tg, ccnt, coff, pout, derr, prune,
                                        l2, bh, StreamOut{}, BlockOut{}, 1, c.num_cus, st);
         check(c, hipGetLastError());
         emitted = true;

@@ -791,8 +791,13 @@ int launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, cons
                       uint32_t* out, int32_t* err, bool prune, bool l2, const BucketHist& bh, const StreamOut& so,
                       const BlockOut& bo, int chunk_stride, int num_cus, hipStream_t st) {
   if (nchunks <= 0) return 0;
+  // persistent blocks of 4 waves, but no more than the chunks need: every
+  // wave starts by probing the 8 shared chunk counters, and thousands of
+  // idle waves doing so cost a short work list ~0.4 ms per pass
   int64_t grid = (int64_t)num_cus * tun.blocks_per_cu;
-  grid = ((grid + 7) / 8) * 8;
+  const int64_t cstride = chunk_stride > 0 ? chunk_stride : 1;
+  grid = std::min(grid, ceil_div(ceil_div(nchunks, cstride), (int64_t)4));
+  grid = std::max<int64_t>(8, ((grid + 7) / 8) * 8);
   const size_t lds = (size_t)4 * tun.stack_depth * WAVE * sizeof(int2) + (emit ? (size_t)bh.NB * 4 : 0);
   // A chunk's items each have at most work_cap leaf pairs, hence fewer than
   // 2 work_cap recursion nodes; every wave step resolves at least one.
