@@ -1123,15 +1123,58 @@ void finish_flow(w1_result& r, const FlowResult& fr) {
   }
 }
 
+// The L-infinity network's rows without the cell arcs u -> v that cost at
+// least both cells' diagonal arcs together (cost(u, v) >= d(u) + d(v), with
+// d = j - i the diagonal cost in the same units).  Leaving them out keeps the
+// optimal cost (the argument of diagonal-dominance pruning, arc by arc):
+// some optimal flow sends everything from B's diagonal node to A's directly
+// over the zero-cost arc, so that arc carries as much as all paths from A
+// mass to B mass together; a path through a dropped arc is replaced by its
+// source's arc to A's diagonal node and its sink's arc from B's (both exist,
+// the source holding A mass and the sink B mass), taking as much off the
+// zero-cost arc, and d is 1-Lipschitz along cell arcs (|d(u) - d(v)| <=
+// |di| + |dj| <= cost), so the replacement costs no more.  Paths from B's
+// diagonal node, or into A's, are shortened the same way.  Rows stay sorted.
+struct SolveRows {
+  std::vector<int64_t> row_ptr;
+  std::vector<uint32_t> col;
+  std::vector<int32_t> cost;
+};
+void drop_dominated_arcs(const w1_result& r, SolveRows& out) {
+  const int64_t nc = r.n_cells, nrow = nc + 2;
+  out.row_ptr.resize((size_t)nrow + 1);
+  out.col.reserve((size_t)r.row_ptr[nc] + (size_t)(r.row_ptr[nrow] - r.row_ptr[nc]));
+  out.cost.reserve(out.col.capacity());
+  std::vector<int64_t> d((size_t)nc);
+  for (int64_t u = 0; u < nc; ++u) d[(size_t)u] = (int64_t)r.cell_j[u] - (int64_t)r.cell_i[u];
+  out.row_ptr[0] = 0;
+  for (int64_t u = 0; u < nrow; ++u) {
+    for (int64_t a = r.row_ptr[u]; a < r.row_ptr[u + 1]; ++a) {
+      const uint32_t v = r.col[a];
+      if (u < nc && (int64_t)v < nc && (int64_t)r.cost[a] >= d[(size_t)u] + d[(size_t)v]) continue;
+      out.col.push_back(v);
+      out.cost.push_back(r.cost[a]);
+    }
+    out.row_ptr[(size_t)u + 1] = (int64_t)out.col.size();
+  }
+}
+
 // Host flow of one pair from its host network copy (the sorted rows are
-// the solver's own input form).
+// the solver's own input form; on the L-infinity network, without the
+// dominated cell arcs).
 void solve_flow(w1_result& r, int64_t pivot_cap) {
   FlowResult fr{};
   // the rows are sorted by head and the diagonal nodes come last: the solve
   // starts from the flow through the diagonal
-  const int rc = r.metric_l2
-                     ? network_simplex64_diag(r.n_cells + 2, r.row_ptr, r.col, r.cost64, r.supply, pivot_cap, &fr)
-                     : network_simplex_diag(r.n_cells + 2, r.row_ptr, r.col, r.cost, r.supply, pivot_cap, &fr);
+  int rc;
+  if (r.metric_l2) {
+    rc = network_simplex64_diag(r.n_cells + 2, r.row_ptr, r.col, r.cost64, r.supply, pivot_cap, &fr);
+  } else {
+    SolveRows sr;
+    drop_dominated_arcs(r, sr);
+    rc = network_simplex_diag(r.n_cells + 2, sr.row_ptr.data(), sr.col.data(), sr.cost.data(), r.supply, pivot_cap,
+                              &fr);
+  }
   if (rc != 0) {
     r.status = rc == -3 ? W1_ENOMEM : W1_EINVAL;
     return;

@@ -532,6 +532,44 @@ def test_prune_keeps_optimum(orc, kind):
             assert pr.n_pairs <= full.n_pairs
 
 
+@pytest.mark.parametrize("kind", ["exp", "mixture", "pareto", "integer", "one_sided"])
+def test_arc_dominance_keeps_optimum(orc, kind):
+    # Arc by arc: a cell arc u -> v with cost >= d(u) + d(v) (d = j - i, the
+    # diagonal arc's cost) is never needed -- some optimal flow sends all of
+    # B's diagonal node's surplus to A's directly, and a path through such an
+    # arc is rerouted over its ends' diagonal arcs at no extra cost.  The
+    # library's host flow solves the L-infinity network without these arcs;
+    # here the oracle's own flow solves both networks and F* must agree.
+    dropped = 0
+    for seed in range(4):
+        if kind == "exp":
+            A, B = pdsynth.exp_pd(60 + 9 * seed, 1100 + seed), pdsynth.exp_pd(55 + 6 * seed, 1150 + seed)
+        elif kind == "mixture":
+            A, B = pdsynth.mixture_pd(250, 1110 + seed), pdsynth.mixture_pd(230, 1160 + seed)
+        elif kind == "pareto":
+            A, B = pdsynth.pareto_pd(180, 1120 + seed), pdsynth.pareto_pd(200, 1170 + seed)
+        elif kind == "integer":
+            A, B = pdsynth.integer_pd(40, 1130 + seed), pdsynth.integer_pd(35, 1180 + seed)
+        else:
+            A, B = pdsynth.exp_pd(70, 1140 + seed), np.zeros((0, 2))
+        for eps, s, prune in ((0.1, 0, False), (0.2, 3, False), (0.2, 0, True)):
+            r = orc.run(A, B, eps=eps, s_override=s, flags=orc.ORC_PRUNE if prune else 0)
+            src, dst, cost, sup = orc.network(A, B, eps=eps, s_override=s, prune=prune)
+            N = sup.shape[0] - 2
+            d = (r.cells["j"] - r.cells["i"]).astype(np.int64)
+            assert d.shape[0] == N
+            cell = (src < N) & (dst < N)
+            dom = np.zeros(src.shape[0], bool)
+            dom[cell] = cost[cell] >= d[src[cell]] + d[dst[cell]]
+            keep = ~dom
+            f_full = orc.mcf(N + 2, src, dst, cost, sup)
+            f_kept = orc.mcf(N + 2, src[keep], dst[keep], cost[keep], sup)
+            assert f_full == f_kept == r.flow, (kind, seed, eps, s, prune)
+            dropped += int(dom.sum())
+    if kind != "one_sided":
+        assert dropped > 0
+
+
 def test_prune_pair_set_is_filtered_wspd(orc):
     # The recursion below a dominated pair is cut, and the test is monotone,
     # so the pruned pairs are exactly the s-WSPD pairs whose own boxes pass.
