@@ -544,20 +544,19 @@ def main():
     if not args.no_c1:
         # end to end incl. host network simplex, 400 + 400 points, eps 0.1
         C1a, C1b = pdsynth.exp_pd(400, 0), pdsynth.exp_pd(400, 1)
-        ctx.approx(C1a, C1b, eps=0.1)
-        t1 = time.perf_counter()
-        reps = 5
-        for _ in range(reps):
-            g = ctx.approx(C1a, C1b, eps=0.1)
-        e2e = (time.perf_counter() - t1) / reps
-        t1 = time.perf_counter()
-        for _ in range(reps):
-            gp = ctx.approx(C1a, C1b, eps=0.1, flags=w1.PRUNE)
-        e2p = (time.perf_counter() - t1) / reps
-        t1 = time.perf_counter()
-        for _ in range(reps):
-            gl = ctx.approx(C1a, C1b, eps=0.1, flags=w1.METRIC_L2)
-        e2l = (time.perf_counter() - t1) / reps
+        reps = 20
+
+        def per_call(flags):
+            for _ in range(3):
+                ctx.approx(C1a, C1b, eps=0.1, flags=flags)
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                r = ctx.approx(C1a, C1b, eps=0.1, flags=flags)
+            return r, (time.perf_counter() - t1) / reps
+
+        g, e2e = per_call(0)
+        gp, e2p = per_call(w1.PRUNE)
+        gl, e2l = per_call(w1.METRIC_L2)
         out["c1_l2_end_to_end"] = {"pd_pairs_per_s": 1.0 / e2l, "ms": 1e3 * e2l, "w1": gl.w1,
                                    "flow_ms": gl.t_ms["flow"], "wspd_pairs": gl.n_pairs}
         out["c1_end_to_end"] = {"pd_pairs_per_s": 1.0 / e2e, "ms": 1e3 * e2e, "w1": g.w1,

@@ -147,6 +147,7 @@ struct StreamOut {
   int64_t base = 0;                   // first pair of the arena fill (if base_dev is null)
   const int64_t* base_dev = nullptr;  // device copy of it, read at launch (graph replays)
   uint64_t* chunk_sum = nullptr;
+  int64_t slot = 0;  // > 0: chunk k writes its records at k * slot (and its count), no count pass needed
 };
 
 // Emit pass output in blocks, for the network path (no count pass; the
@@ -228,6 +229,10 @@ int launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, cons
 // counters xc and advances *ctr; past the last fill, the ranges are empty.
 void launch_stream_next(const int32_t* run_xr, const int64_t* run_base, int nruns, int32_t* ctr, int32_t* xr,
                         int64_t* base, uint32_t* xc, hipStream_t st);
+// Records of slotted chunks (cnt[k] records of w words at k * slot) moved
+// to their scanned offsets off[k].
+void launch_compact_slots(const uint32_t* src, const uint64_t* cnt, const uint64_t* off, int64_t nch, int64_t slot,
+                          int w, uint32_t* dst, hipStream_t st);
 void launch_pair_totals(const uint64_t* chunk_cnt, const uint64_t* chunk_off, const int32_t* chunk_pair,
                         int64_t nchunks, uint64_t* pair_start, uint64_t* pair_end, uint64_t* npairs, int64_t K,
                         hipStream_t st);

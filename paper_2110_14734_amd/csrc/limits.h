@@ -20,6 +20,10 @@ inline bool worklist_items_fit(int64_t items) { return items >= 0 && items < (in
 // Chunks of the persistent passes are numbered by int32.
 inline bool worklist_chunks_fit(int64_t chunks) { return chunks >= 0 && chunks < (int64_t(1) << 31); }
 
+// Slotted emission (short work lists on the network path, no count pass):
+// at most this many record slots over all chunks (12 bytes each at most).
+constexpr int64_t kSlottedMaxRecords = int64_t(1) << 25;
+
 // Geometry of the partition passes that sort the network into rows: buckets
 // of 2^RB consecutive cells (RB in 9..12, the smallest giving at most 1024
 // buckets over the launch group's n_cells), entries of 32 bits holding the

@@ -363,6 +363,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
 
   // ---------------------------------------------------------------- a2 --
   int64_t maxnp = 0;  // most cells of one diagram pair
+  int32_t maxcap = 0;  // largest per-pair work cap of the launch group
   if (M > 0) {
     const double* lb = (const double*)c.lb.p;
     const double* ld = (const double*)c.ld.p;
@@ -405,7 +406,10 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       maxnp = std::max<int64_t>(maxnp, nc[(size_t)p]);
     }
     std::vector<int32_t> cap((size_t)K);
-    for (int64_t p = 0; p < K; ++p) cap[(size_t)p] = pair_work_cap(nc[(size_t)p], c.tun.work_cap);
+    for (int64_t p = 0; p < K; ++p) {
+      cap[(size_t)p] = pair_work_cap(nc[(size_t)p], c.tun.work_cap);
+      maxcap = std::max(maxcap, cap[(size_t)p]);
+    }
     upload_all(c, {{P.cell_start, cs.data(), (size_t)K * 8}, {need<int32_t>(c, c.pcap, K), cap.data(), (size_t)K * 4}});
     check(c, hipGetLastError());
   }
@@ -668,7 +672,50 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       }
       c.emit_blocks = blocked ? nblk : 0;
       c.emit_block_recs = brecs;
-      if (!blocked) {
+      // A short work list on the network path skips the count pass: each
+      // chunk writes into a slot of chunk_items * (largest work cap) records
+      // (an item covers at most its work cap of leaf pairs, so no chunk can
+      // fill more), counting as it goes; the records are then moved to
+      // their scanned offsets.  Same records as the counted layout.
+      const int64_t slot_recs = (int64_t)tg.chunk_items * maxcap;
+      const bool slotted = !blocked && !(o.flags & W1_COUNT_ONLY) && slot_recs > 0 &&
+                           nch * slot_recs <= kSlottedMaxRecords;
+      if (slotted) {
+        const CsrGeometry geo = csr_geometry(N, maxnp);
+        if (!geo.ok) throw StageError{W1_ERANGE};
+        uint64_t* bcnt = need<uint64_t>(c, c.bcnt, geo.NB);
+        fill_u64(bcnt, 0, geo.NB, st);
+        BucketHist bh;
+        bh.chunk_pair = cp;
+        bh.cell_start = P.cell_start;
+        bh.RB = geo.RB;
+        bh.NB = (int)geo.NB;
+        bh.count = bcnt;
+        uint32_t* sl = need<uint32_t>(c, c.pslot, 3 * nch * slot_recs);
+        StreamOut so;
+        so.slot = slot_recs;
+        fill_u32(xc, 0, 8, st);
+        check(c, hipEventRecord(c.kev[1], st));
+        check(c, hipEventRecord(c.kev[2], st));  // no count pass
+        check(c, hipEventRecord(c.kev[3], st));
+        c.rec_words = launch_wspd_pass(true, T, split, S, cf, ce, nch, xr, xc, s, tg, ccnt, coff, sl, derr, prune, l2,
+                                       bh, so, BlockOut{}, 1, c.num_cus, st);
+        check(c, hipGetLastError());
+        scan_u64(ccnt, coff, nch, need<char>(c, c.scantmp, (int64_t)scan_tmp_bytes(nch, 8)), st);
+        uint64_t* slot = need<uint64_t>(c, c.small, 64);
+        launch_count_total64(ccnt, coff, nch, slot, st);
+        Ptot = (int64_t)read_u64(c, slot);
+        trace(c, "wspd pairs (slotted emission)", Ptot);
+        fill_u64((uint64_t*)P.seg_hi, 0, K, st);
+        launch_pair_totals(ccnt, coff, cp, nch, P.pair_start, (uint64_t*)P.seg_hi, P.npairs, K, st);
+        if (Ptot > 0) {
+          uint32_t* pout = need<uint32_t>(c, c.pu, std::max<int64_t>(c.rec_words * Ptot, 2 * Ptot + 2 * N + K));
+          launch_compact_slots(sl, ccnt, coff, nch, slot_recs, c.rec_words, pout, st);
+          check(c, hipGetLastError());
+          emitted = true;
+        }
+      }
+      if (!blocked && !slotted) {
       fill_u32(xc, 0, 8, st);
       check(c, hipEventRecord(c.kev[1], st));
       launch_wspd_pass(false, T, split, S, cf, ce, nch, xr, xc, s, tg, ccnt, coff, nullptr, derr, prune, l2,

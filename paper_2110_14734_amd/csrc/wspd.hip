@@ -509,6 +509,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       // records go at the chunk's counted offset, or on in the wave's block
       uint32_t* obase = !EMIT    ? nullptr
                         : BLOCKS  ? bptr
+                        : so.slot ? out + (COMPACT ? 2 : 3) * ((uint64_t)k * (uint64_t)so.slot)
                         : COMPACT ? out + 2 * (chunk_off[k] - sbase)
                                   : out + 3 * (chunk_off[k] - sbase);
       uint64_t h1 = 0, h2 = 0;  // streamed emission: the lane's checksum terms
@@ -648,11 +649,15 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
             wr = !dead;
             if (wr) bleft -= n;
           }
-          if ((BLOCKS && wr) || COMPACT) {  // (u, v): the network's costs come from the cells
+          if (!BLOCKS && so.slot && cursor + n1 + n2 > (uint64_t)so.slot) {  // beyond the chunk's slot
+            wr = false;
+            overflow = true;
+          }
+          if (wr && (BLOCKS || COMPACT)) {  // (u, v): the network's costs come from the cells
             if (e1) __builtin_nontemporal_store(u32x2{m1.x, m1.y}, (u32x2*)(obase + 2 * lanes_set_below(b1, 0u)));
             if (e2) __builtin_nontemporal_store(u32x2{m2.x, m2.y}, (u32x2*)(obase + 2 * lanes_set_below(b2, n1)));
             obase += 2 * (n1 + n2);
-          } else if (!BLOCKS && !COMPACT) {
+          } else if (wr && !BLOCKS && !COMPACT) {
             if (e1) __builtin_nontemporal_store(m1, (u32x3_w*)(obase + 3 * lanes_set_below(b1, 0u)));
             if (e2) __builtin_nontemporal_store(m2, (u32x3_w*)(obase + 3 * lanes_set_below(b2, n1)));
             obase += 3 * (n1 + n2);
@@ -685,7 +690,7 @@ __global__ void __launch_bounds__(256) k_wspd(const int4* __restrict__ R, const 
       if (BLOCKS) bptr = obase;
       const bool bad = runaway || __ballot(overflow) != 0;
       if (bad) atomicOr(err, 1);
-      if (!EMIT) chunk_cnt[k] = cursor;  // same value from every lane
+      if (!EMIT || so.slot) chunk_cnt[k] = cursor;  // same value from every lane
       if (EMIT && so.chunk_sum) {
         for (int d = WAVE / 2; d > 0; d >>= 1) {
           h1 += __shfl_xor(h1, d);
@@ -722,6 +727,15 @@ __global__ void k_pair_counts(const uint64_t* __restrict__ pair_start, const uin
                               uint64_t* __restrict__ npairs) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < K) npairs[p] = pair_end[p] > pair_start[p] ? pair_end[p] - pair_start[p] : 0;
+}
+
+__global__ void k_compact_slots(const uint32_t* __restrict__ src, const uint64_t* __restrict__ cnt,
+                                const uint64_t* __restrict__ off, int64_t slot, int w, uint32_t* __restrict__ dst) {
+  const int64_t k = blockIdx.x;
+  const int64_t n = (int64_t)cnt[k] * w;
+  const uint32_t* s = src + (uint64_t)k * (uint64_t)slot * (uint64_t)w;
+  uint32_t* d = dst + off[k] * (uint64_t)w;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
 }
 
 __global__ void k_stream_next(const int32_t* __restrict__ run_xr, const int64_t* __restrict__ run_base, int nruns,
@@ -824,6 +838,10 @@ int launch_wspd_pass(bool emit, const TreeView& T, const uint4* split_recs, cons
                      emit ? bh : BucketHist{}, emit ? so : StreamOut{}, emit ? bo : BlockOut{},
                      chunk_stride > 0 ? chunk_stride : 1);
   return !emit ? 0 : (blocks || packed) ? 2 : 3;
+}
+void launch_compact_slots(const uint32_t* src, const uint64_t* cnt, const uint64_t* off, int64_t nch, int64_t slot,
+                          int w, uint32_t* dst, hipStream_t st) {
+  if (nch > 0) hipLaunchKernelGGL(k_compact_slots, dim3((unsigned)nch), dim3(256), 0, st, src, cnt, off, slot, w, dst);
 }
 void launch_stream_next(const int32_t* run_xr, const int64_t* run_base, int nruns, int32_t* ctr, int32_t* xr,
                         int64_t* base, uint32_t* xc, hipStream_t st) {

@@ -701,6 +701,25 @@ def _stream_gold():
         return json.load(f)
 
 
+def test_slotted_and_counted_layouts(orc, ctx):
+    """Short work lists are emitted into per-chunk slots without a count
+    pass (long ones are counted first: the full-size tests).  A 400 +
+    400-point pair takes the slotted layout (no count-pass time), and its
+    sorted rows and F* equal the oracle's, with and without pruning."""
+    _say("[gpu] slotted emission")
+    A, B = pdsynth.exp_pd(400, 0), pdsynth.exp_pd(400, 1)
+    import paper_2110_14734_amd as w1
+
+    for prune in (False, True):
+        g = ctx.approx(A, B, eps=0.1, flags=w1.KEEP_NETWORK | (w1.PRUNE if prune else 0))
+        assert ctx.kernel_times()["count_ms"] < 0.005  # no count pass
+        net = orc.csr(A, B, eps=0.1, prune=prune)
+        assert np.array_equal(g.network["row_ptr"], net["row_ptr"])
+        assert np.array_equal(g.network["col"].astype(np.int64), net["col"])
+        assert np.array_equal(g.network["cost"].astype(np.int64), net["cost"])
+        assert g.flow_cost == orc.run(A, B, eps=0.1, flags=orc.ORC_PRUNE if prune else 0, fetch=False).flow
+
+
 def test_stream_emission_small(orc, ctx):
     """Streamed emission through a small arena (many runs of chunks, each
     overwriting the last): every pair's records are written once, the
