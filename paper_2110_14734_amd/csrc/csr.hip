@@ -406,8 +406,11 @@ __device__ inline void flush_staged(const uint32_t* st, uint32_t n, int64_t k0, 
 //      into their LDS staging areas and write the staged heads with their
 //      costs coalesced; a group denser than the staging area is written
 //      straight from its words, 64 consecutive cells per step.
+// At most 128 VGPRs (4 waves per SIMD), so that two blocks share a compute
+// unit: the Euclidean variant compiled to 129 on its own, which halved the
+// blocks per compute unit and took its pass from 36.6 to 55.8 ms.
 template <bool L2>
-__global__ void __launch_bounds__(SORT_B) k_row_sort(const uint32_t* __restrict__ cpair,
+__global__ void __launch_bounds__(SORT_B) __attribute__((amdgpu_waves_per_eu(4))) k_row_sort(const uint32_t* __restrict__ cpair,
                                                      const int64_t* __restrict__ cell_start,
                                                      const int32_t* __restrict__ ncells, const int2* __restrict__ cij,
                                                      const int32_t* __restrict__ ca, const uint32_t* __restrict__ rowcnt,
