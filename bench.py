@@ -55,10 +55,11 @@ KERNEL_NAMES = {"emit_ms": "k_wspd<emit> (WSPD pair records)",
 # {kernel key: (source file, sha256 prefix of that file, bytes per launch)}.
 # (profiles/a4_a5_kernels_c2_200k_eps0.1_hbm_counters.md)
 MEASURED_TRAFFIC = {
-    "bucket_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "b2aef032ecc32bdf", 30_226_472_313),
-    "row_hist_ms": ("paper_2110_14734_amd/csrc/csr.hip", "b2aef032ecc32bdf", 14_805_215_588),
-    "row_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "b2aef032ecc32bdf", 32_074_986_621),
-    "row_sort_ms": ("paper_2110_14734_amd/csrc/csr.hip", "b2aef032ecc32bdf", 49_577_644_242),
+    "emit_ms": ("paper_2110_14734_amd/csrc/wspd.hip", "d28e6267955300df", 24_063_365_084),
+    "bucket_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "81b090edf509503c", 30_222_318_211),
+    "row_hist_ms": ("paper_2110_14734_amd/csrc/csr.hip", "81b090edf509503c", 14_809_854_161),
+    "row_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "81b090edf509503c", 32_338_512_695),
+    "row_sort_ms": ("paper_2110_14734_amd/csrc/csr.hip", "81b090edf509503c", 49_625_016_583),
 }
 
 
