@@ -97,6 +97,10 @@ def parse():
                     help="pairs of the batch also run one call each (the per-pair loop)")
     ap.add_argument("--nn-db", type=int, default=2000, help="1-NN database size")
     ap.add_argument("--nn-queries", type=int, default=64)
+    ap.add_argument("--nn-c4", type=int, default=0,
+                    help="also run 1-NN search at the configured database (10k diagrams of 1k-20k points) with "
+                         "this many queries (minutes per query pair; off by default)")
+    ap.add_argument("--nn-c4-labels", type=int, default=400, help="method labels for that search's surrogate")
     ap.add_argument("--embed-db", type=int, default=10_000,
                     help="diagrams in the embedding (MFMA) workload, sizes log-uniform in [1k, 20k]")
     return ap.parse_args()
@@ -374,6 +378,75 @@ def run_nn(ctx, args):
     return out
 
 
+def run_nn_c4(ctx, args):
+    """1-NN search at the configured database size: 10k diagrams of 1k-20k
+    points from the latent-family generator (the embedding workload's
+    database), args.nn_c4 queries from the same generator, the method alone
+    (RWMD order) against the surrogate-seeded search.  The surrogate is
+    trained on args.nn_c4_labels method labels from that database (half on
+    random pairs, half on each anchor's RWMD-nearest of 8 random candidates):
+    the configured 200k labels would take ~9 hours of labelling."""
+    import numpy as np
+
+    import paper_2110_14734_amd as w1
+    import pdsynth
+
+    say = lambda msg: print(f"[bench] c4 1-NN: {msg}", file=sys.stderr, flush=True)
+    db, fams, rng = family_db(10_000, 200, 9, 1000, 20_000)
+    m, nl = len(db), args.nn_c4_labels
+    rand = [(int(i), int(j)) for i, j in rng.integers(0, m, (nl // 2, 2)) if i != j]
+    anchors = rng.integers(0, m, nl - nl // 2)
+    cand = rng.integers(0, m, (anchors.shape[0], 8))
+    Lr = ctx.rwmd([db[a] for a in anchors for _ in range(8)], [db[c] for c in cand.ravel()]).reshape(-1, 8)
+    near = [(int(a), int(cand[k][np.argmin(Lr[k])])) for k, a in enumerate(anchors)]
+    pairs = [p for p in rand + near if p[0] != p[1]]
+    t0 = time.perf_counter()
+    labels = []
+    for k in range(0, len(pairs), 32):
+        part = pairs[k:k + 32]
+        labels += [r.w1 for r in ctx.approx_batch([db[i] for i, _ in part], [db[j] for _, j in part], eps=args.eps,
+                                                 flags=w1.PRUNE)]
+        say(f"{len(labels)} of {len(pairs)} labels")
+    label_s = time.perf_counter() - t0
+    labels = np.array(labels)
+    keep = labels > 0
+    sur = w1.Surrogate(ctx, seed=7)
+    t0 = time.perf_counter()
+    losses = sur.train(db, np.array([p[0] for p in pairs])[keep], np.array([p[1] for p in pairs])[keep],
+                       labels[keep], epochs=40, batch_pairs=64, lr=3e-3, seed=5)
+    train_s = time.perf_counter() - t0
+    qs = [pdsynth.family_pd(int(np.rint(np.exp(rng.uniform(np.log(1000), np.log(20_000))))), 8_000_000 + i,
+                            fams[int(rng.integers(0, 200))]) for i in range(args.nn_c4)]
+    idx = w1.NNIndex(ctx, db, sur)
+    out, ans = {}, {}
+    for mode in ("rwmd", "surrogate"):
+        dt, st, nn, w = 0.0, {}, [], []
+        for k, q in enumerate(qs):
+            t0 = time.perf_counter()
+            r = idx.query([q], eps=args.eps, mode=mode)
+            dt += time.perf_counter() - t0
+            for key, v in r.stats.items():
+                st[key] = st.get(key, 0) + v
+            nn.append(int(r.nn[0]))
+            w.append(float(r.w1[0]))
+            say(f"{mode} query {k + 1} of {len(qs)}: {dt:.1f} s so far")
+        ans[mode] = (nn, w)
+        out[f"nn_{mode}"] = {"queries_per_s": len(qs) / dt, "seconds_per_query": dt / len(qs),
+                             "verifications_per_query": st["verifications"] / len(qs),
+                             "rwmd_evals_per_query": st["rwmd_evals"] / len(qs),
+                             "t_rwmd_ms": st["t_rwmd_ms"], "t_verify_ms": st["t_verify_ms"]}
+    idx.close()
+    sur.close()
+    out["identical_answers"] = ans["rwmd"] == ans["surrogate"]
+    out["speedup"] = out["nn_surrogate"]["queries_per_s"] / out["nn_rwmd"]["queries_per_s"]
+    out["workload"] = (f"database 10000 diagrams (latent-family generator, sizes log-uniform [1k, 20k], "
+                       f"{sum(len(d) for d in db)} points), {len(qs)} queries from the same generator, "
+                       f"eps={args.eps}; surrogate trained on {int(keep.sum())} W1 labels from the method "
+                       f"({label_s:.1f} s to label, {train_s:.1f} s to train, loss {losses[0]:.3f} -> "
+                       f"{losses[-1]:.3f})")
+    return out
+
+
 def _cpu_model():
     try:
         for ln in open("/proc/cpuinfo"):
@@ -572,6 +645,8 @@ def main():
         out["stress"] = run_stress(ctx, args)
     if not args.no_nn:
         out["learned"] = run_nn(ctx, args)
+    if args.nn_c4 > 0:
+        out["learned_c4"] = run_nn_c4(ctx, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, args.eps)
     ctx.close()
