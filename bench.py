@@ -99,7 +99,7 @@ def parse():
     ap.add_argument("--nn-queries", type=int, default=64)
     ap.add_argument("--nn-c4", type=int, default=0,
                     help="also run 1-NN search at the configured database (10k diagrams of 1k-20k points) with "
-                         "this many queries (minutes per query pair; off by default)")
+                         "this many queries (off by default: a query in RWMD order can take many minutes)")
     ap.add_argument("--nn-c4-labels", type=int, default=400, help="method labels for that search's surrogate")
     ap.add_argument("--embed-db", type=int, default=10_000,
                     help="diagrams in the embedding (MFMA) workload, sizes log-uniform in [1k, 20k]")

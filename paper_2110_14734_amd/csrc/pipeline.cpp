@@ -727,6 +727,18 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
       launch_count_total64(ccnt, coff, nch, slot, st);
       Ptot = (int64_t)read_u64(c, slot);
       trace(c, "wspd pairs", Ptot);
+      if (c.trace && nch > 0) {  // the spread of the pairs over the chunks
+        std::vector<uint64_t> hc((size_t)nch);
+        readback(c, ccnt, hc.data(), nch);
+        std::vector<uint64_t> sorted_c(hc);
+        std::sort(sorted_c.begin(), sorted_c.end());
+        trace(c, "  pairs per chunk: max", (int64_t)sorted_c.back());
+        trace(c, "  pairs per chunk: 99.9th percentile", (int64_t)sorted_c[(size_t)((nch - 1) * 999 / 1000)]);
+        trace(c, "  pairs per chunk: median", (int64_t)sorted_c[(size_t)(nch / 2)]);
+        uint64_t smax = 0;
+        for (int64_t k = 0; k < nch; k += kSampleStride) smax = std::max(smax, hc[(size_t)k]);
+        trace(c, "  pairs per chunk: max over every 16th chunk", (int64_t)smax);
+      }
       fill_u64((uint64_t*)P.seg_hi, 0, K, st);
       launch_pair_totals(ccnt, coff, cp, nch, P.pair_start, (uint64_t*)P.seg_hi, P.npairs, K, st);
       if ((o.flags & W1_COUNT_ONLY) && c.stream_arena > 0 && Ptot > 0) {
