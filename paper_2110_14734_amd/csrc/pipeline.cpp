@@ -1194,43 +1194,67 @@ void finish_flow(w1_result& r, const FlowResult& fr) {
 // zero-cost arc, and d is 1-Lipschitz along cell arcs (|d(u) - d(v)| <=
 // |di| + |dj| <= cost), so the replacement costs no more.  Paths from B's
 // diagonal node, or into A's, are shortened the same way.  Rows stay sorted.
+//
+// The Euclidean network's costs are the real distances rounded up to
+// integers through double arithmetic (relative error eta <= 2^-52 before the
+// rounding up), so each rounded cost exceeds the real one by less than
+// 1 + eta * cost and may fall short of it by eta * cost.  Carried through the
+// argument above (a path between cells has fewer than n_cells arcs, and every
+// cell's diagonal cost is the cost of one of its arcs, so all of them are at
+// most the largest cost), a dropped arc must then cost at least
+// d(u) + d(v) + M with M = 3 + 2^-50 * (n_cells + 3) * (largest cost); d is
+// the rounded cost of the arc to the diagonal, formed as the network forms it.
+template <typename C>
 struct SolveRows {
   std::vector<int64_t> row_ptr;
   std::vector<uint32_t> col;
-  std::vector<int32_t> cost;
+  std::vector<C> cost;
 };
-void drop_dominated_arcs(const w1_result& r, SolveRows& out) {
-  const int64_t nc = r.n_cells, nrow = nc + 2;
+template <typename C>
+void drop_dominated_arcs(const w1_result& r, const C* cost, SolveRows<C>& out) {
+  const int64_t nc = r.n_cells, nrow = nc + 2, m = r.row_ptr[nrow];
   out.row_ptr.resize((size_t)nrow + 1);
-  out.col.reserve((size_t)r.row_ptr[nc] + (size_t)(r.row_ptr[nrow] - r.row_ptr[nc]));
-  out.cost.reserve(out.col.capacity());
+  out.col.reserve((size_t)m);
+  out.cost.reserve((size_t)m);
   std::vector<int64_t> d((size_t)nc);
-  for (int64_t u = 0; u < nc; ++u) d[(size_t)u] = (int64_t)r.cell_j[u] - (int64_t)r.cell_i[u];
+  int64_t margin = 0;
+  if (r.metric_l2) {
+    int64_t cmax = 0;
+    for (int64_t a = 0; a < m; ++a) cmax = std::max<int64_t>(cmax, (int64_t)cost[a]);
+    margin = 3 + (int64_t)std::ceil(std::ldexp((double)(nc + 3) * (double)cmax, -50));
+    for (int64_t u = 0; u < nc; ++u)
+      d[(size_t)u] = (int64_t)std::ceil(
+          std::ldexp((double)((int64_t)r.cell_j[u] - (int64_t)r.cell_i[u]) * 0x1.6a09e667f3bcdp-1, r.cost_shift));
+  } else {
+    for (int64_t u = 0; u < nc; ++u) d[(size_t)u] = (int64_t)r.cell_j[u] - (int64_t)r.cell_i[u];
+  }
   out.row_ptr[0] = 0;
   for (int64_t u = 0; u < nrow; ++u) {
     for (int64_t a = r.row_ptr[u]; a < r.row_ptr[u + 1]; ++a) {
       const uint32_t v = r.col[a];
-      if (u < nc && (int64_t)v < nc && (int64_t)r.cost[a] >= d[(size_t)u] + d[(size_t)v]) continue;
+      if (u < nc && (int64_t)v < nc && (int64_t)cost[a] >= d[(size_t)u] + d[(size_t)v] + margin) continue;
       out.col.push_back(v);
-      out.cost.push_back(r.cost[a]);
+      out.cost.push_back(cost[a]);
     }
     out.row_ptr[(size_t)u + 1] = (int64_t)out.col.size();
   }
 }
 
 // Host flow of one pair from its host network copy (the sorted rows are
-// the solver's own input form; on the L-infinity network, without the
-// dominated cell arcs).
+// the solver's own input form), without the dominated cell arcs.
 void solve_flow(w1_result& r, int64_t pivot_cap) {
   FlowResult fr{};
   // the rows are sorted by head and the diagonal nodes come last: the solve
   // starts from the flow through the diagonal
   int rc;
   if (r.metric_l2) {
-    rc = network_simplex64_diag(r.n_cells + 2, r.row_ptr, r.col, r.cost64, r.supply, pivot_cap, &fr);
+    SolveRows<int64_t> sr;
+    drop_dominated_arcs(r, r.cost64, sr);
+    rc = network_simplex64_diag(r.n_cells + 2, sr.row_ptr.data(), sr.col.data(), sr.cost.data(), r.supply, pivot_cap,
+                                &fr);
   } else {
-    SolveRows sr;
-    drop_dominated_arcs(r, sr);
+    SolveRows<int32_t> sr;
+    drop_dominated_arcs(r, r.cost, sr);
     rc = network_simplex_diag(r.n_cells + 2, sr.row_ptr.data(), sr.col.data(), sr.cost.data(), r.supply, pivot_cap,
                               &fr);
   }

@@ -712,7 +712,9 @@ def test_slotted_and_counted_layouts(orc, ctx):
 
     for prune in (False, True):
         g = ctx.approx(A, B, eps=0.1, flags=w1.KEEP_NETWORK | (w1.PRUNE if prune else 0))
-        assert ctx.kernel_times()["count_ms"] < 0.005  # no count pass
+        # no count pass: the two events around where it would run are a few
+        # microseconds apart (a count pass over this work list takes ~0.2 ms)
+        assert ctx.kernel_times()["count_ms"] < 0.05
         net = orc.csr(A, B, eps=0.1, prune=prune)
         assert np.array_equal(g.network["row_ptr"], net["row_ptr"])
         assert np.array_equal(g.network["col"].astype(np.int64), net["col"])

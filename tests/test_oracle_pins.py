@@ -570,6 +570,40 @@ def test_arc_dominance_keeps_optimum(orc, kind):
         assert dropped > 0
 
 
+@pytest.mark.parametrize("kind", ["exp", "mixture", "pareto"])
+def test_arc_dominance_keeps_optimum_l2(orc, kind):
+    # The same on the Euclidean network, whose costs are real distances
+    # rounded up through double arithmetic: an arc is dropped when it costs at
+    # least d(u) + d(v) + M, M = 3 + 2^-50 (n_cells + 3) max cost, d the
+    # diagonal arc's rounded cost (the rounding slack carried through the
+    # rerouting argument).  F* from the oracle's own flow must not change.
+    import math
+
+    dropped = 0
+    for seed in range(3):
+        if kind == "exp":
+            A, B = pdsynth.exp_pd(60 + 9 * seed, 1200 + seed), pdsynth.exp_pd(55 + 6 * seed, 1250 + seed)
+        elif kind == "mixture":
+            A, B = pdsynth.mixture_pd(200, 1210 + seed), pdsynth.mixture_pd(190, 1260 + seed)
+        else:
+            A, B = pdsynth.pareto_pd(150, 1220 + seed), pdsynth.pareto_pd(160, 1270 + seed)
+        for eps, s in ((0.1, 0), (0.2, 3)):
+            r = orc.run(A, B, eps=eps, s_override=s, flags=orc.ORC_L2)
+            src, dst, cost, sup = orc.network(A, B, eps=eps, s_override=s, l2=True)
+            N = sup.shape[0] - 2
+            K, R = r.K, float.fromhex("0x1.6a09e667f3bcdp-1")
+            d = np.array([math.ceil(math.ldexp(float(int(j) - int(i)) * R, K))
+                          for i, j in zip(r.cells["i"], r.cells["j"])], np.int64)
+            M = 3 + math.ceil(math.ldexp(float(N + 3) * float(cost.max()), -50))
+            cell = (src < N) & (dst < N)
+            dom = np.zeros(src.shape[0], bool)
+            dom[cell] = cost[cell] >= d[src[cell]] + d[dst[cell]] + M
+            keep = ~dom
+            assert orc.mcf(N + 2, src[keep], dst[keep], cost[keep], sup) == orc.mcf(N + 2, src, dst, cost, sup) == r.flow
+            dropped += int(dom.sum())
+    assert dropped > 0
+
+
 def test_prune_pair_set_is_filtered_wspd(orc):
     # The recursion below a dominated pair is cut, and the test is monotone,
     # so the pruned pairs are exactly the s-WSPD pairs whose own boxes pass.
