@@ -101,6 +101,8 @@ def parse():
                     help="also run 1-NN search at the configured database (10k diagrams of 1k-20k points) with "
                          "this many queries (off by default: a query in RWMD order can take many minutes)")
     ap.add_argument("--nn-c4-labels", type=int, default=400, help="method labels for that search's surrogate")
+    ap.add_argument("--nn-c4-extra", type=int, default=0,
+                    help="further queries of that search run in the surrogate-seeded mode only")
     ap.add_argument("--embed-db", type=int, default=10_000,
                     help="diagrams in the embedding (MFMA) workload, sizes log-uniform in [1k, 20k]")
     return ap.parse_args()
@@ -416,31 +418,34 @@ def run_nn_c4(ctx, args):
                        labels[keep], epochs=40, batch_pairs=64, lr=3e-3, seed=5)
     train_s = time.perf_counter() - t0
     qs = [pdsynth.family_pd(int(np.rint(np.exp(rng.uniform(np.log(1000), np.log(20_000))))), 8_000_000 + i,
-                            fams[int(rng.integers(0, 200))]) for i in range(args.nn_c4)]
+                            fams[int(rng.integers(0, 200))]) for i in range(args.nn_c4 + args.nn_c4_extra)]
     idx = w1.NNIndex(ctx, db, sur)
     out, ans = {}, {}
-    for mode in ("rwmd", "surrogate"):
+    for mode, qm in (("rwmd", qs[:args.nn_c4]), ("surrogate", qs[:args.nn_c4]), ("surrogate_extra", qs[args.nn_c4:])):
+        if not qm:
+            continue
         dt, st, nn, w = 0.0, {}, [], []
-        for k, q in enumerate(qs):
+        for k, q in enumerate(qm):
             t0 = time.perf_counter()
-            r = idx.query([q], eps=args.eps, mode=mode)
+            r = idx.query([q], eps=args.eps, mode=mode.split("_")[0])
             dt += time.perf_counter() - t0
             for key, v in r.stats.items():
                 st[key] = st.get(key, 0) + v
             nn.append(int(r.nn[0]))
             w.append(float(r.w1[0]))
-            say(f"{mode} query {k + 1} of {len(qs)}: {dt:.1f} s so far")
+            say(f"{mode} query {k + 1} of {len(qm)}: {dt:.1f} s so far")
         ans[mode] = (nn, w)
-        out[f"nn_{mode}"] = {"queries_per_s": len(qs) / dt, "seconds_per_query": dt / len(qs),
-                             "verifications_per_query": st["verifications"] / len(qs),
-                             "rwmd_evals_per_query": st["rwmd_evals"] / len(qs),
+        out[f"nn_{mode}"] = {"queries": len(qm), "queries_per_s": len(qm) / dt, "seconds_per_query": dt / len(qm),
+                             "verifications_per_query": st["verifications"] / len(qm),
+                             "rwmd_evals_per_query": st["rwmd_evals"] / len(qm),
                              "t_rwmd_ms": st["t_rwmd_ms"], "t_verify_ms": st["t_verify_ms"]}
     idx.close()
     sur.close()
     out["identical_answers"] = ans["rwmd"] == ans["surrogate"]
     out["speedup"] = out["nn_surrogate"]["queries_per_s"] / out["nn_rwmd"]["queries_per_s"]
     out["workload"] = (f"database 10000 diagrams (latent-family generator, sizes log-uniform [1k, 20k], "
-                       f"{sum(len(d) for d in db)} points), {len(qs)} queries from the same generator, "
+                       f"{sum(len(d) for d in db)} points), {args.nn_c4} queries from the same generator in both "
+                       f"modes and {args.nn_c4_extra} more in the surrogate-seeded mode, "
                        f"eps={args.eps}; surrogate trained on {int(keep.sum())} W1 labels from the method "
                        f"({label_s:.1f} s to label, {train_s:.1f} s to train, loss {losses[0]:.3f} -> "
                        f"{losses[-1]:.3f})")
