@@ -16,7 +16,11 @@
  *       supplies, as compressed sparse rows with the arcs sorted by tail,
  *       then head (Appendix, representation of the transshipment network),
  * and then solves the uncapacitated min-cost flow of that network on the host
- * with an integer network simplex (Sec. 5.4), timed separately.
+ * with an integer network simplex (Sec. 5.4), timed separately.  The solve
+ * leaves out the cell arcs that cost at least both ends' diagonal arcs
+ * together (on the Euclidean network, plus a margin for its rounded costs):
+ * some optimal flow never uses them, so F* is that of the whole network,
+ * which is still what the result holds; pivots count the reduced solve.
  *
  * Ground metric: L-infinity by default.  Distance to the diagonal of (b, d):
  * (d - b)/2.  Costs of the network are integers in units of g/2,
