@@ -732,7 +732,9 @@ __global__ void k_pair_counts(const uint64_t* __restrict__ pair_start, const uin
 __global__ void k_compact_slots(const uint32_t* __restrict__ src, const uint64_t* __restrict__ cnt,
                                 const uint64_t* __restrict__ off, int64_t slot, int w, uint32_t* __restrict__ dst) {
   const int64_t k = blockIdx.x;
-  const int64_t n = (int64_t)cnt[k] * w;
+  // a chunk never outgrows its slot (the emit pass reports one that would,
+  // and the call fails); the clamp keeps the reads inside the slot anyway
+  const int64_t n = (int64_t)min(cnt[k], (uint64_t)slot) * w;
   const uint32_t* s = src + (uint64_t)k * (uint64_t)slot * (uint64_t)w;
   uint32_t* d = dst + off[k] * (uint64_t)w;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
