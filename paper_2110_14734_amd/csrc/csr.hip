@@ -417,8 +417,10 @@ __global__ void __launch_bounds__(SORT_B) __attribute__((amdgpu_waves_per_eu(4))
                                                      const uint64_t* __restrict__ off,
                                                      const uint32_t* __restrict__ heads, int64_t N, int win_words,
                                                      const int32_t* __restrict__ costK, uint32_t* __restrict__ col,
-                                                     typename ArcCost<L2>::T* __restrict__ cost) {
+                                                     typename ArcCost<L2>::T* __restrict__ cost,
+                                                     unsigned long long* __restrict__ rowq) {
   extern __shared__ uint32_t s_mem[];
+  __shared__ int64_t s_nextg;                 // the block's next row, from the row queue
   __shared__ uint32_t s_gpre[SORT_MAXG + 1];  // heads per group, then their exclusive prefix
   __shared__ uint32_t s_wpre[SORT_MAXG];      // exclusive prefix of the group weights
   __shared__ int s_task[SORT_TASKS + 1];      // first group of each run
@@ -440,7 +442,11 @@ __global__ void __launch_bounds__(SORT_B) __attribute__((amdgpu_waves_per_eu(4))
       if (threadIdx.x + u * SORT_B < n) pre[u] = heads[st + threadIdx.x + u * SORT_B];
   };
   load_ahead(blockIdx.x);
-  for (int64_t g = blockIdx.x; g < N; g += gridDim.x) {
+  // rows: blockIdx.x first, then from a queue (rows gridDim.x, gridDim.x + 1,
+  // ... in the order blocks ask), so that blocks with shorter rows take more
+  // of them; thread 0 takes the next row during the fill
+  int64_t nextg = N;
+  for (int64_t g = blockIdx.x; g < N; g = nextg) {
     const uint32_t p = cpair[g];
     const int64_t cs = cell_start[p];
     const uint32_t np = (uint32_t)ncells[p];
@@ -456,6 +462,7 @@ __global__ void __launch_bounds__(SORT_B) __attribute__((amdgpu_waves_per_eu(4))
       const int ng = (nw + WAVE - 1) / WAVE;
       for (int q = threadIdx.x; q <= ng; q += SORT_B) s_gpre[q] = 0;
       __syncthreads();  // also orders the previous row's last reads before this row's bits
+      if (ahead && threadIdx.x == 0) s_nextg = (int64_t)gridDim.x + (int64_t)atomicAdd(rowq, 1ull);
       for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += SORT_FILL * SORT_B) {
         uint32_t h[SORT_FILL];  // all loads in flight before the first bit is set
         if (i0 == threadIdx.x && w0 == 0) {
@@ -487,7 +494,8 @@ __global__ void __launch_bounds__(SORT_B) __attribute__((amdgpu_waves_per_eu(4))
       }
       __syncthreads();
       if (ahead) {  // the next row's first heads arrive while this one is written
-        load_ahead(g + gridDim.x);
+        nextg = s_nextg;
+        load_ahead(nextg);
         ahead = false;
       }
       if (wave == 0) {  // exclusive scans of the heads and weights per group, then the runs
@@ -591,7 +599,13 @@ __global__ void __launch_bounds__(SORT_B) __attribute__((amdgpu_waves_per_eu(4))
       written += s_gpre[ng];
       __syncthreads();
     }
-    if (ahead) load_ahead(g + gridDim.x);  // a row without heads
+    if (ahead) {  // a row without heads
+      __syncthreads();  // every thread has read the previous row's s_nextg
+      if (threadIdx.x == 0) s_nextg = (int64_t)gridDim.x + (int64_t)atomicAdd(rowq, 1ull);
+      __syncthreads();
+      nextg = s_nextg;
+      load_ahead(nextg);
+    }
     if (threadIdx.x == 0 && ca[g] > 0) {  // arc to the A-diagonal node, last in the row
       col[start + cnt] = np;
       cost[start + cnt] = ArcCost<L2>::diag(me, K);
@@ -729,7 +743,7 @@ void launch_csr_row_scatter(const uint32_t* ent, const int64_t* tfirst, int64_t 
 void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
                          const int32_t* ca, const uint32_t* rowcnt, const uint64_t* off, const uint32_t* heads,
                          int64_t N, int64_t max_pair_cells, int window_words, int num_cus, const int32_t* costK, uint32_t* col,
-                         void* cost, hipStream_t st) {
+                         void* cost, uint64_t* rowq, hipStream_t st) {
   if (N <= 0) return;
   // the bitmap covers the largest pair's cells at once when they fit
   int win = (int)std::min<int64_t>(WIN_WORDS, std::max<int64_t>(1, (max_pair_cells + 31) / 32));
@@ -740,10 +754,12 @@ void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const
   const int64_t grid = std::min<int64_t>(N, (int64_t)num_cus * (lds <= 76 * 1024 ? 2 : 1));
   if (costK)
     hipLaunchKernelGGL(k_row_sort<true>, dim3((unsigned)grid), dim3(SORT_B), lds, st, cpair, cell_start, ncells, cij, ca,
-                       rowcnt, off, heads, N, win, costK, col, (int64_t*)cost);
+                       rowcnt, off, heads, N, win, costK, col, (int64_t*)cost,
+                       (unsigned long long*)rowq);
   else
     hipLaunchKernelGGL(k_row_sort<false>, dim3((unsigned)grid), dim3(SORT_B), lds, st, cpair, cell_start, ncells, cij,
-                       ca, rowcnt, off, heads, N, win, costK, col, (int32_t*)cost);
+                       ca, rowcnt, off, heads, N, win, costK, col, (int32_t*)cost,
+                       (unsigned long long*)rowq);
 }
 #define LAUNCH(kern, n, ...) \
   do { if ((n) > 0) hipLaunchKernelGGL(kern, dim3(blocks(n)), dim3(256), 0, st, __VA_ARGS__); } while (0)

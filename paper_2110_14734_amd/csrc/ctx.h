@@ -81,7 +81,7 @@ struct Ctx {
   // sorted heads (col); costb the arc costs; rp the per-pair row pointers
   DBuf pu, l1, costb, rp, supply, rstart, bcnt, bstart, tfirst, bcur, rowcnt, rowcur, bflag, bpos, deg, off, parc;
   // streamed emission: per-chunk pair checksums; Euclidean cost scale
-  DBuf csum, pxmax, runxr, runbase, pslot;
+  DBuf csum, pxmax, runxr, runbase, pslot, rowq;
   // blocked emission (network path): block fills, block pairs, counters;
   // blocks used by the last launch group (0: counted layout) and their size
   DBuf bfill, bpairs, bctl;
@@ -114,7 +114,7 @@ struct Ctx {
                     &ndepth, &inode, &rmap, &isplit, &itemsA, &itemsB, &itemsX, &itemsI, &itemsS, &icnt, &ipos, &ipp, &cid, &pcap,
                     &cfirst, &cend, &cpairs, &ccnt, &coff, &xrange, &xctr, &err, &pu, &l1, &costb, &rp,
                     &supply, &rstart, &bcnt, &bstart, &tfirst, &bcur, &rowcnt, &rowcur, &bflag, &bpos, &deg, &off,
-                    &parc, &csum, &pxmax, &runxr, &runbase, &pslot, &pairs};
+                    &parc, &csum, &pxmax, &runxr, &runbase, &pslot, &rowq, &pairs};
     all.assign(std::begin(list), std::end(list));
     saved.resize(all.size());
   }

@@ -100,7 +100,7 @@ void launch_csr_row_scatter(const uint32_t* ent, const int64_t* tfirst, int64_t 
 void launch_csr_row_sort(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
                          const int32_t* ca, const uint32_t* rowcnt, const uint64_t* off, const uint32_t* heads,
                          int64_t N, int64_t max_pair_cells, int window_words, int num_cus, const int32_t* costK, uint32_t* col,
-                         void* cost, hipStream_t st);
+                         void* cost, uint64_t* rowq /* row queue counter, zero at launch */, hipStream_t st);
 void launch_csr_bdiag(const uint32_t* cpair, const int64_t* cell_start, const int32_t* ncells, const int2* cij,
                       const int32_t* ca, const int32_t* cb, const uint32_t* bpos, const uint64_t* off,
                       const PairArrays& P, int64_t N, const int32_t* costK, uint32_t* col, void* cost,

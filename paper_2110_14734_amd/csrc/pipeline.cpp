@@ -968,8 +968,10 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
     }
     void* cost = l2 ? (void*)need<int64_t>(c, c.costb, 2 * Ptot + 2 * N + K)
                     : (void*)need<int32_t>(c, c.costb, 2 * Ptot + 2 * N + K);
+    uint64_t* rowq = need<uint64_t>(c, c.rowq, 1);
+    fill_u64(rowq, 0, 1, st);
     launch_csr_row_sort(cp, P.cell_start, ncl, cij, ca, rowcnt, off, heads, N, maxnp, c.sort_window, c.num_cus, costK,
-                        col, cost, st);
+                        col, cost, rowq, st);
     launch_csr_bdiag(cp, P.cell_start, ncl, cij, ca, cb, bpos, off, P, N, costK, col, cost, sup, st);
     int64_t* rp = need<int64_t>(c, c.rp, N + 3 * K);
     fill_u64((uint64_t*)rp, 0, N + 3 * K, st);
