@@ -55,11 +55,11 @@ KERNEL_NAMES = {"emit_ms": "k_wspd<emit> (WSPD pair records)",
 # {kernel key: (source file, sha256 prefix of that file, bytes per launch)}.
 # (profiles/a4_a5_kernels_c2_200k_eps0.1_hbm_counters.md)
 MEASURED_TRAFFIC = {
-    "emit_ms": ("paper_2110_14734_amd/csrc/wspd.hip", "29711b414e76cfa6", 24_000_460_072),
-    "bucket_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "81b090edf509503c", 30_227_414_804),
-    "row_hist_ms": ("paper_2110_14734_amd/csrc/csr.hip", "81b090edf509503c", 14_805_825_053),
-    "row_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "81b090edf509503c", 32_105_531_831),
-    "row_sort_ms": ("paper_2110_14734_amd/csrc/csr.hip", "81b090edf509503c", 49_532_090_948),
+    "emit_ms": ("paper_2110_14734_amd/csrc/wspd.hip", "29711b414e76cfa6", 23_838_175_396),
+    "bucket_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "fa11260a58425148", 30_224_031_670),
+    "row_hist_ms": ("paper_2110_14734_amd/csrc/csr.hip", "fa11260a58425148", 14_810_458_574),
+    "row_scatter_ms": ("paper_2110_14734_amd/csrc/csr.hip", "fa11260a58425148", 31_811_291_743),
+    "row_sort_ms": ("paper_2110_14734_amd/csrc/csr.hip", "fa11260a58425148", 47_948_840_548),
 }
 
 
