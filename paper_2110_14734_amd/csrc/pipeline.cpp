@@ -1112,7 +1112,7 @@ int run(Ctx& c, const w1_pd* a, const w1_pd* b, int64_t K, const Opts& o, hipStr
 // Copy one pair's network to the host (arrays owned by the result): cells,
 // supplies and the sorted rows (row pointers local to the pair, local node
 // ids as heads).
-void copy_network(Ctx& c, int64_t p, w1_result& r) {
+void copy_network(Ctx& c, int64_t p, w1_result& r, std::vector<int2>& ij) {
   const int64_t nc = c.h_ncells[(size_t)p], m = c.h_narcs[(size_t)p];
   const int64_t cs = c.h_cell_start[(size_t)p], as = c.h_arc_start[(size_t)p];
   r.cell_i = (int32_t*)std::malloc((size_t)std::max<int64_t>(nc, 1) * 4);
@@ -1126,25 +1126,33 @@ void copy_network(Ctx& c, int64_t p, w1_result& r) {
   else r.cost = (int32_t*)std::malloc((size_t)std::max<int64_t>(m, 1) * 4);
   if (!r.cell_i || !r.cell_j || !r.cell_ca || !r.cell_cb || !r.supply || !r.row_ptr || !r.col || !(r.cost || r.cost64))
     throw StageError{W1_ENOMEM};
+  // the copies are only queued here: the caller waits once for every pair
+  // of the launch group, then finish_network() splits the cell coordinates
+  auto get = [&](void* host, const void* dev, size_t bytes) {
+    if (bytes) check(c, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c.st));
+  };
+  ij.assign((size_t)std::max<int64_t>(nc, 0), int2{0, 0});
   if (nc > 0) {
-    std::vector<int2> ij((size_t)nc);
-    readback(c, (const int2*)c.cij.p + cs, ij.data(), nc);
-    for (int64_t q = 0; q < nc; ++q) {
-      r.cell_i[q] = ij[(size_t)q].x;
-      r.cell_j[q] = ij[(size_t)q].y;
-    }
-    readback(c, (const int32_t*)c.ca.p + cs, r.cell_ca, nc);
-    readback(c, (const int32_t*)c.cb.p + cs, r.cell_cb, nc);
-    readback(c, (const int64_t*)c.supply.p + cs + 2 * p, r.supply, nc + 2);
-    readback(c, (const int64_t*)c.rp.p + cs + 3 * p, r.row_ptr, nc + 3);
+    get(ij.data(), (const int2*)c.cij.p + cs, (size_t)nc * 8);
+    get(r.cell_ca, (const int32_t*)c.ca.p + cs, (size_t)nc * 4);
+    get(r.cell_cb, (const int32_t*)c.cb.p + cs, (size_t)nc * 4);
+    get(r.supply, (const int64_t*)c.supply.p + cs + 2 * p, (size_t)(nc + 2) * 8);
+    get(r.row_ptr, (const int64_t*)c.rp.p + cs + 3 * p, (size_t)(nc + 3) * 8);
   } else {
     r.supply[0] = r.supply[1] = 0;
     r.row_ptr[0] = r.row_ptr[1] = r.row_ptr[2] = 0;
   }
   if (m > 0) {
-    readback(c, (const uint32_t*)c.l1.p + as, r.col, m);
-    if (r.metric_l2) readback(c, (const int64_t*)c.costb.p + as, r.cost64, m);
-    else readback(c, (const int32_t*)c.costb.p + as, r.cost, m);
+    get(r.col, (const uint32_t*)c.l1.p + as, (size_t)m * 4);
+    if (r.metric_l2) get(r.cost64, (const int64_t*)c.costb.p + as, (size_t)m * 8);
+    else get(r.cost, (const int32_t*)c.costb.p + as, (size_t)m * 4);
+  }
+}
+
+void finish_network(w1_result& r, const std::vector<int2>& ij) {
+  for (int64_t q = 0; q < r.n_cells; ++q) {
+    r.cell_i[q] = ij[(size_t)q].x;
+    r.cell_j[q] = ij[(size_t)q].y;
   }
 }
 
@@ -1308,8 +1316,12 @@ int entry(Ctx* c, const w1_pd* a, const w1_pd* b, int64_t K, const w1_params* pa
       const bool keep = (o.flags & W1_KEEP_NETWORK) != 0;
       if (!(want_flow || keep)) continue;
       auto t0 = std::chrono::steady_clock::now();
+      std::vector<std::vector<int2>> ijs((size_t)Kg);
       for (int64_t p = 0; p < Kg; ++p)
-        if (og[p].status == 0 && og[p].n_points > 0) copy_network(*c, p, og[p]);
+        if (og[p].status == 0 && og[p].n_points > 0) copy_network(*c, p, og[p], ijs[(size_t)p]);
+      check(*c, hipStreamSynchronize(c->st));
+      for (int64_t p = 0; p < Kg; ++p)
+        if (og[p].status == 0 && og[p].n_points > 0) finish_network(og[p], ijs[(size_t)p]);
       auto t1 = std::chrono::steady_clock::now();
       double d2h = std::chrono::duration<double, std::milli>(t1 - t0).count();
       if (want_flow) {
