@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <vector>
 
 namespace w1 {
 
@@ -38,5 +39,21 @@ int network_simplex64_diag(int64_t n_nodes, const int64_t* row_ptr, const uint32
 // The same for an arc list (src, dst, cost); flow entries follow the list.
 int network_simplex_arcs(int64_t n_nodes, int64_t m, const uint32_t* src, const uint32_t* dst, const int32_t* cost,
                          const int64_t* supply, int64_t pivot_cap, FlowResult* out);
+
+// Rows of one of the method's networks (cells 0 .. n_cells - 1 with grid
+// coordinates (ci, cj), then the A- and B-diagonal nodes) without the cell
+// arcs that some optimal flow never uses; the optimum is the whole network's.
+// cost_shift = -1 marks integer L-infinity costs (units g/2); >= 0 the
+// Euclidean costs in units of g 2^-cost_shift.
+template <typename C>
+struct SolveRows {
+  std::vector<int64_t> row_ptr;
+  std::vector<uint32_t> col;
+  std::vector<C> cost;
+};
+void drop_dominated_arcs(int64_t n_cells, const int64_t* row_ptr, const uint32_t* col, const int32_t* cost,
+                         const int32_t* ci, const int32_t* cj, int cost_shift, SolveRows<int32_t>& out);
+void drop_dominated_arcs(int64_t n_cells, const int64_t* row_ptr, const uint32_t* col, const int64_t* cost,
+                         const int32_t* ci, const int32_t* cj, int cost_shift, SolveRows<int64_t>& out);
 
 }  // namespace w1

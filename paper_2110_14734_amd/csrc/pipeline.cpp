@@ -1192,66 +1192,8 @@ void finish_flow(w1_result& r, const FlowResult& fr) {
   }
 }
 
-// The L-infinity network's rows without the cell arcs u -> v that cost at
-// least both cells' diagonal arcs together (cost(u, v) >= d(u) + d(v), with
-// d = j - i the diagonal cost in the same units).  Leaving them out keeps the
-// optimal cost (the argument of diagonal-dominance pruning, arc by arc):
-// some optimal flow sends everything from B's diagonal node to A's directly
-// over the zero-cost arc, so that arc carries as much as all paths from A
-// mass to B mass together; a path through a dropped arc is replaced by its
-// source's arc to A's diagonal node and its sink's arc from B's (both exist,
-// the source holding A mass and the sink B mass), taking as much off the
-// zero-cost arc, and d is 1-Lipschitz along cell arcs (|d(u) - d(v)| <=
-// |di| + |dj| <= cost), so the replacement costs no more.  Paths from B's
-// diagonal node, or into A's, are shortened the same way.  Rows stay sorted.
-//
-// The Euclidean network's costs are the real distances rounded up to
-// integers through double arithmetic (relative error eta <= 2^-52 before the
-// rounding up), so each rounded cost exceeds the real one by less than
-// 1 + eta * cost and may fall short of it by eta * cost.  Carried through the
-// argument above (a path between cells has fewer than n_cells arcs, and every
-// cell's diagonal cost is the cost of one of its arcs, so all of them are at
-// most the largest cost), a dropped arc must then cost at least
-// d(u) + d(v) + M with M = 3 + 2^-50 * (n_cells + 3) * (largest cost); d is
-// the rounded cost of the arc to the diagonal, formed as the network forms it.
-template <typename C>
-struct SolveRows {
-  std::vector<int64_t> row_ptr;
-  std::vector<uint32_t> col;
-  std::vector<C> cost;
-};
-template <typename C>
-void drop_dominated_arcs(const w1_result& r, const C* cost, SolveRows<C>& out) {
-  const int64_t nc = r.n_cells, nrow = nc + 2, m = r.row_ptr[nrow];
-  out.row_ptr.resize((size_t)nrow + 1);
-  // most cell arcs go (all but 8% of a 400 + 400-point pair's); the vectors
-  // grow if more stay
-  out.col.reserve((size_t)(m / 8 + 4 * nrow));
-  out.cost.reserve((size_t)(m / 8 + 4 * nrow));
-  std::vector<int64_t> d((size_t)nc);
-  int64_t margin = 0;
-  if (r.metric_l2) {
-    int64_t cmax = 0;
-    for (int64_t a = 0; a < m; ++a) cmax = std::max<int64_t>(cmax, (int64_t)cost[a]);
-    margin = 3 + (int64_t)std::ceil(std::ldexp((double)(nc + 3) * (double)cmax, -50));
-    for (int64_t u = 0; u < nc; ++u)
-      d[(size_t)u] = (int64_t)std::ceil(
-          std::ldexp((double)((int64_t)r.cell_j[u] - (int64_t)r.cell_i[u]) * 0x1.6a09e667f3bcdp-1, r.cost_shift));
-  } else {
-    for (int64_t u = 0; u < nc; ++u) d[(size_t)u] = (int64_t)r.cell_j[u] - (int64_t)r.cell_i[u];
-  }
-  out.row_ptr[0] = 0;
-  for (int64_t u = 0; u < nrow; ++u) {
-    for (int64_t a = r.row_ptr[u]; a < r.row_ptr[u + 1]; ++a) {
-      const uint32_t v = r.col[a];
-      if (u < nc && (int64_t)v < nc && (int64_t)cost[a] >= d[(size_t)u] + d[(size_t)v] + margin) continue;
-      out.col.push_back(v);
-      out.cost.push_back(cost[a]);
-    }
-    out.row_ptr[(size_t)u + 1] = (int64_t)out.col.size();
-  }
-}
-
+// The host flow leaves out the dominated cell arcs (drop_dominated_arcs in
+// flow.cpp states when and why that keeps the optimum).
 // Host flow of one pair from its host network copy (the sorted rows are
 // the solver's own input form), without the dominated cell arcs.
 void solve_flow(w1_result& r, int64_t pivot_cap) {
@@ -1261,12 +1203,12 @@ void solve_flow(w1_result& r, int64_t pivot_cap) {
   int rc;
   if (r.metric_l2) {
     SolveRows<int64_t> sr;
-    drop_dominated_arcs(r, r.cost64, sr);
+    drop_dominated_arcs(r.n_cells, r.row_ptr, r.col, r.cost64, r.cell_i, r.cell_j, r.cost_shift, sr);
     rc = network_simplex64_diag(r.n_cells + 2, sr.row_ptr.data(), sr.col.data(), sr.cost.data(), r.supply, pivot_cap,
                                 &fr);
   } else {
     SolveRows<int32_t> sr;
-    drop_dominated_arcs(r, r.cost, sr);
+    drop_dominated_arcs(r.n_cells, r.row_ptr, r.col, r.cost, r.cell_i, r.cell_j, -1, sr);
     rc = network_simplex_diag(r.n_cells + 2, sr.row_ptr.data(), sr.col.data(), sr.cost.data(), r.supply, pivot_cap,
                               &fr);
   }

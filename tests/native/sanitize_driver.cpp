@@ -43,6 +43,7 @@ static int fails = 0;
 
 // keys of orc_i64
 enum { K_STATUS, K_NA, K_NB, K_N, K_NLOC, K_S, K_E, K_M0, K_NCELLS, K_NNODES, K_ROOT, K_NPAIRS, K_FLOW };
+constexpr int K_COSTK = 19;  // the Euclidean cost shift
 
 static void flows(std::mt19937_64& rng) {
   for (int trial = 0; trial < 60; ++trial) {
@@ -185,7 +186,7 @@ static void oracle_modes(std::mt19937_64& rng) {
 static void warm_starts(std::mt19937_64& rng) {
   std::uniform_real_distribution<double> U(0.0, 1.0);
   std::exponential_distribution<double> E(15.0);
-  int64_t piv_cold = 0, piv_warm = 0;
+  int64_t piv_cold = 0, piv_warm = 0, arcs_all = 0, arcs_kept = 0;
   const int flags_list[] = {4, 4 | 32, 4 | 64};
   for (int trial = 0; trial < 24; ++trial) {
     const int64_t nA = 1 + (int64_t)(rng() % 120), nB = (int64_t)(rng() % 100);
@@ -233,6 +234,30 @@ static void warm_starts(std::mt19937_64& rng) {
           EXPECT(cap.feasible == 1 && cap.cost >= cold.cost);
         }
         EXPECT(warm.status == 0 && cold.status == 0 && warm.cost == cold.cost);
+        // the library's solve without the dominated cell arcs: the same optimum
+        std::vector<int64_t> ci64((size_t)nc), cj64((size_t)nc), ca64((size_t)nc), cb64((size_t)nc);
+        std::vector<uint64_t> key((size_t)nc);
+        orc_cells(o, ci64.data(), cj64.data(), ca64.data(), cb64.data(), key.data());
+        std::vector<int32_t> ci(ci64.begin(), ci64.end()), cj(cj64.begin(), cj64.end());
+        w1::FlowResult red{};
+        int64_t kept = 0;
+        if (flags & 64) {
+          w1::SolveRows<int64_t> sr;
+          w1::drop_dominated_arcs(nc, rp.data(), col.data(), cc.data(), ci.data(), cj.data(), (int)orc_i64(o, K_COSTK),
+                                  sr);
+          EXPECT(w1::network_simplex64_diag(nn, sr.row_ptr.data(), sr.col.data(), sr.cost.data(), sup.data(), 0, &red) ==
+                 0);
+          kept = (int64_t)sr.col.size();
+        } else {
+          std::vector<int32_t> c32(cc.begin(), cc.end());
+          w1::SolveRows<int32_t> sr;
+          w1::drop_dominated_arcs(nc, rp.data(), col.data(), c32.data(), ci.data(), cj.data(), -1, sr);
+          EXPECT(w1::network_simplex_diag(nn, sr.row_ptr.data(), sr.col.data(), sr.cost.data(), sup.data(), 0, &red) == 0);
+          kept = (int64_t)sr.col.size();
+        }
+        EXPECT(red.status == 0 && red.cost == cold.cost && kept <= m);
+        arcs_all += m;
+        arcs_kept += kept;
         std::vector<int64_t> bal((size_t)nn, 0);
         for (int64_t v = 0; v < nn; ++v)
           for (int64_t a = rp[(size_t)v]; a < rp[(size_t)v + 1]; ++a) {
@@ -250,6 +275,8 @@ static void warm_starts(std::mt19937_64& rng) {
     }
   }
   std::printf("pivots: artificial start %lld, diagonal start %lld\n", (long long)piv_cold, (long long)piv_warm);
+  std::printf("arcs: %lld, kept without the dominated cell arcs %lld\n", (long long)arcs_all, (long long)arcs_kept);
+  EXPECT(arcs_kept < arcs_all);
 }
 
 int main() {
