@@ -277,6 +277,24 @@ static void warm_starts(std::mt19937_64& rng) {
   std::printf("pivots: artificial start %lld, diagonal start %lld\n", (long long)piv_cold, (long long)piv_warm);
   std::printf("arcs: %lld, kept without the dominated cell arcs %lld\n", (long long)arcs_all, (long long)arcs_kept);
   EXPECT(arcs_kept < arcs_all);
+  {
+    // edge cases of the filter: no cells (only the two diagonal nodes), and
+    // a hand network where one cell arc costs exactly d(u) + d(v) (dropped),
+    // one less (kept), and arcs touching a diagonal node (always kept)
+    const int64_t rp0[3] = {0, 0, 0};
+    w1::SolveRows<int32_t> e;
+    w1::drop_dominated_arcs(0, rp0, nullptr, (const int32_t*)nullptr, nullptr, nullptr, -1, e);
+    EXPECT(e.row_ptr.size() == 3 && e.row_ptr[2] == 0 && e.col.empty() && e.cost.empty());
+    const int64_t rp[5] = {0, 2, 3, 3, 4};
+    const uint32_t cl[4] = {1, 2, 0, 0};
+    const int32_t cs[4] = {6, 4, 5, 4};
+    const int32_t ci[2] = {0, 1}, cj[2] = {4, 3};  // d = 4 and 2
+    w1::SolveRows<int32_t> h;
+    w1::drop_dominated_arcs(2, rp, cl, cs, ci, cj, -1, h);
+    EXPECT(h.row_ptr.size() == 5 && h.row_ptr[1] == 1 && h.row_ptr[2] == 2 && h.row_ptr[3] == 2 && h.row_ptr[4] == 3);
+    EXPECT(h.col.size() == 3 && h.col[0] == 2 && h.col[1] == 0 && h.col[2] == 0);
+    EXPECT(h.cost[0] == 4 && h.cost[1] == 5 && h.cost[2] == 4);
+  }
 }
 
 int main() {
